@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the FP64 SBDF2 Rayleigh-Benard step on one MI355X.
+
+Workload: 2-D Rayleigh-Benard, Fourier x (Nx=1024, Lx=4) x Chebyshev z
+(Nz=256), Ra=1e8, Pr=1, dt=1e-5, seeded noise on b (workload seed 1001): 513
+pencils of 7*256 unknowns.  A step is one pass of the whole hot path: the
+backward z transform, the x pass with the grid products, the forward z
+transform with the SBDF2 right-hand side, and the banded pencil solve.  The
+two start-up factorisations (SBDF1, then SBDF2) happen in the warm-up steps,
+as in any run of the scheme.
+
+Prints one JSON line: metric, value (DOF-updates/s = 7*Nx*Nz per step per
+second), roofline of the dominant kernel (HIP-event timing on the launch
+stream) and the CPU-oracle baseline on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+WORKLOAD = dict(Nx=1024, Nz=256, Lx=4.0, Ra=1e8, Pr=1.0, dt=1e-5, seed_workload=1)
+
+
+def b_grid(Nx, Nz, xi, amp=1e-3):
+    """b = 1 - z + amp z (1 - z) xi on the scale-1 grid (Gauss-Chebyshev z)."""
+    import numpy as np
+
+    j = np.arange(Nz)
+    z = 0.5 * (1.0 - np.cos(np.pi * (j + 0.5) / Nz))
+    return (1.0 - z)[None, :] + amp * (z * (1.0 - z))[None, :] * xi
+
+
+def algorithmic_bytes(info):
+    """Minimum HBM bytes per launch of each kernel (FP64)."""
+    P, Pa, N, M, S, ne = info["P"], info["P_active"], info["Nz"], info["Ngz"], info["S"], info["ne"]
+    n, kl, ku = info["n"], info["kl"], info["ku"]
+    c16 = 16
+    zb = 6 * P * N * c16 + 8 * M * P * c16
+    xp = 8 * M * Pa * c16 + 3 * M * P * c16
+    zf = 3 * M * P * c16 + 3 * P * N * c16 + 2 * (2 * ne * P * N * c16) + ne * P * N * c16
+    solve = Pa * n * ((2 * kl + ku + 1) * 8 + 1) + Pa * ne * N * c16 + P * S * N * c16
+    return {"z_backward": zb, "x_pass": xp, "z_forward_rhs": zf, "pencil_solve": solve}
+
+
+def cpu_baseline(w, sample_pencils=128, reps=3):
+    """The oracle's SBDF2 step on a bounded sample: the explicit term on the
+    full grid, then right-hand side + LU solve of `sample_pencils` pencils
+    (factorisations done beforehand, untimed), scaled to all pencils."""
+    import numpy as np
+
+    import seeded_inputs as si
+    from oracle import RBOracle, RBParams, sbdf_coefficients
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    Nx, Nz = w["Nx"], w["Nz"]
+    o = RBOracle(Nx, Nz, w["Lx"], RBParams(w["Ra"], w["Pr"]))
+    X = o.initial_state(si.workload_noise((Nx, Nz), w["seed_workload"]))
+    dt = w["dt"]
+    a0, a1, a2, b0, c1, c2 = sbdf_coefficients(1, dt, dt)
+    act = [p for p in o.pencils() if p[4]]
+    stride = max(1, len(act) // sample_pencils)
+    sample = act[::stride][:sample_pencils]
+    solvers = {}
+    for key, kx, ky, mean, _ in sample:
+        solvers[key] = (o._ML_cached(key, kx, ky, mean), o.solver_for(key, kx, ky, mean, a0, b0))
+    t_nl, t_pen = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        F = o.nonlinear(X)
+        t1 = time.perf_counter()
+        for key, kx, ky, mean, _ in sample:
+            (M, L), solve = solvers[key]
+            Ft = o.precondition_rhs(F[key], mean)
+            MX = M @ X[key].reshape(-1)
+            B = c1 * Ft - a1 * MX + c2 * Ft - a2 * MX
+            for r, val in o.bc_values(mean).items():
+                B[r] = val
+            solve(B)
+        t2 = time.perf_counter()
+        t_nl.append(t1 - t0)
+        t_pen.append(t2 - t1)
+    t_step = float(np.median(t_nl)) + float(np.median(t_pen)) * len(act) / len(sample)
+    dof = 7 * Nx * Nz
+    return {
+        "value": dof / t_step, "unit": "DOF-updates/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"explicit term on the full 1536x384 grid + RHS and LU solves of "
+                   f"{len(sample)}/{len(act)} pencils (factorisations untimed), median of "
+                   f"{reps}, solve time scaled by {len(act)}/{len(sample)}; "
+                   f"{os.cpu_count()} host cores, {threads} BLAS threads"),
+        "seconds_per_step": t_step,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timing-steps", type=int, default=100,
+                    help="steps of the per-kernel HIP-event pass after the timed region")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run one device-to-device copy of this many bytes (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_1905_10388_amd import RBSolver
+
+    w = WORKLOAD
+    Nx, Nz, dt = w["Nx"], w["Nz"], w["dt"]
+    g = RBSolver(Nx, Nz, w["Lx"], w["Ra"], w["Pr"])
+    xi = si.workload_noise((Nx, Nz), w["seed_workload"])
+    g.initial_state(torch.from_numpy(b_grid(Nx, Nz, xi)))
+    for _ in range(max(2, args.warmup)):
+        g.step(dt)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        g.step(dt)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_wall = (t1 - t0) * 1e3 / args.steps
+    ms_ev = ev0.elapsed_time(ev1) / args.steps
+    ms_per_step = max(ms_wall, ms_ev)
+    g.check()
+    dof = 7 * Nx * Nz
+    value = dof / (ms_per_step * 1e-3)
+
+    # per-kernel HIP-event timing on the launch stream (separate pass)
+    g.set_kernel_timing(True)
+    for _ in range(args.timing_steps):
+        g.step(dt)
+    kt = g.read_kernel_timing()
+    g.set_kernel_timing(False)
+    nbytes = algorithmic_bytes(g.info)
+    kernels = {}
+    for k, (ms, cnt) in kt.items():
+        if cnt:
+            avg_us = ms * 1e3 / cnt
+            entry = {"avg_us": round(avg_us, 3), "launches": int(cnt)}
+            if k in nbytes:
+                entry["bytes"] = nbytes[k]
+                entry["GBps"] = round(nbytes[k] / (avg_us * 1e-6) / 1e9, 1)
+            kernels[k] = entry
+    roofline = None
+    timed_kernels = [k for k in kernels if k in nbytes]
+    if timed_kernels:
+        dom = max(timed_kernels, key=lambda k: kernels[k]["avg_us"])
+        ach = kernels[dom]["GBps"]
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None}
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": "DOF-updates/s per SBDF2 step (FP64)",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": max(2, args.warmup),
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "rb2d_1024x256_Ra1e8_dt1e-5", "Nx": Nx, "Nz": Nz, "Lx": w["Lx"],
+                   "Ra": w["Ra"], "Pr": w["Pr"], "dt": dt, "pencils": g.info["P_active"],
+                   "unknowns_per_pencil": g.info["n"], "kl": g.info["kl"], "ku": g.info["ku"]},
+        "kernels": kernels,
+        "roofline": roofline,
+        "mode_updates_per_s": Nx * Nz / (ms_per_step * 1e-3),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

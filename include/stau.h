@@ -1,0 +1,202 @@
+/*
+ * stau -- sparse generalized-tau IMEX stepper for Fourier x Chebyshev
+ * Rayleigh-Benard convection on one gfx950 GPU.  C ABI.
+ *
+ * The operation is one implicit-explicit multistep step (SBDF1 on the first
+ * step, SBDF2 afterwards) of the first-order sparse tau discretisation of
+ * Burns et al., "Dedalus: A flexible framework for numerical simulations
+ * with spectral methods" (2020):
+ *   Sec. II   -- T-to-U differentiation/conversion, tau rows, Dirichlet
+ *                recombination, interleaved (mode-major) banded systems;
+ *   Sec. IV   -- Fourier / Chebyshev transforms, 3/2 dealiasing;
+ *   Sec. IX   -- pencil matrix construction, IVP form M dX/dt + L X = F,
+ *                multistep IMEX update (a0 M + b0 L) X^n = B^n, factor reuse.
+ *
+ * Conventions common to every call
+ * --------------------------------
+ * - Every function returns an int status (STAU_OK = 0, else an STAU_E* code);
+ *   the message of the last failure on the calling thread is returned by
+ *   stau_last_error().  No C++ exception crosses this boundary.
+ * - Pointers documented as "device" are HIP device pointers on the domain's
+ *   device; the caller owns them and must keep them alive for the call (and
+ *   for the enqueued work, when the call is asynchronous).  The library never
+ *   frees caller memory.  Handles (stau_domain, stau_pencils) are library
+ *   owned and released by the matching destroy call.
+ * - `stream` is a hipStream_t (NULL = the default stream).  All device work of
+ *   a call is enqueued on it.  Only stau_factor, stau_check and the destroy
+ *   calls synchronise the host with the device.
+ * - Complex arrays are interleaved (re, im) float64 pairs (C99 double complex).
+ *
+ * State layout (the FieldSystem of Sec. VI, pencil-major, variable-major inside)
+ * ---------------------------------------------------------------------------
+ *   2-D: X[kx][var][n],  kx = 0..Nx/2 (slot Nx/2 is the Nyquist mode, kept 0),
+ *        var in (p, b, u, w, bz, uz, wz), n = 0..Nz-1 Chebyshev T coefficients
+ *        of z in [0, 1] (native [-1, 1] by z = (zeta + 1) / 2).
+ *   3-D: X[ky][kx][var][n], ky in FFT order (0..Ny/2-1, Nyquist, -Ny/2+1..-1),
+ *        var in (p, b, u, v, w, bz, uz, vz, wz).
+ *   Fourier coefficients are mode amplitudes: f(x) = sum_k f_k e^{i k 2 pi x/Lx}.
+ */
+#ifndef STAU_H
+#define STAU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STAU_OK 0
+#define STAU_EINVAL 1        /* bad argument: null pointer, shape, dt <= 0 ... */
+#define STAU_ENOMEM 2        /* device or host allocation failed */
+#define STAU_EHIP 3          /* a HIP runtime call failed (message in last_error) */
+#define STAU_ESINGULAR 4     /* zero or non-finite pivot in a pencil factorisation */
+#define STAU_ESTATE 5        /* call not valid in the current state */
+#define STAU_EUNSUPPORTED 6  /* size or option not supported */
+#define STAU_ENONFINITE 7    /* non-finite value detected by stau_check */
+
+#define STAU_FP64 0
+#define STAU_MIXED 1
+
+typedef struct stau_domain stau_domain;
+typedef struct stau_pencils stau_pencils;
+
+/* Domain: direct product of Fourier (x[, y]) and Chebyshev (z) bases (Sec. V).
+ * dim      2 or 3.
+ * Nx, Ny   Fourier modes (even, Nx >= 4; Ny ignored in 2-D).  The dealiased
+ *          grid size 3N/2 must be of the form 2^a 3^b (a >= 1) and <= 8192.
+ * Nz       Chebyshev modes (even, 4 <= Nz <= 1024; 3Nz/2 of the form 2^a 3^b).
+ * Lx, Ly   periods of x, y (> 0).
+ * dealias  transform scale; must be 1.5 (the 3/2 rule, Sec. IV).
+ * precision STAU_FP64 (everything FP64) or STAU_MIXED (FP32 transforms and
+ *          products, FP32 solve plus one FP64 refinement sweep, FP64 factors
+ *          and boundary rows).
+ * device   HIP device ordinal. */
+typedef struct stau_domain_desc {
+  int32_t dim;
+  int32_t precision;
+  int64_t Nx, Ny, Nz;
+  double Lx, Ly;
+  double dealias;
+  int32_t device;
+  int32_t reserved;
+} stau_domain_desc;
+
+/* Rayleigh-Benard parameters in free-fall units: kappa = (Ra Pr)^(-1/2),
+ * nu = (Ra / Pr)^(-1/2).  buoyancy multiplies the -b term of the w equation
+ * (1 for convection, 0 for pure diffusion checks).  b_bottom / b_top are the
+ * Dirichlet values of b at z = 0 / z = 1; u = (v =) w = 0 on both walls. */
+typedef struct stau_rb_params {
+  double Ra, Pr, buoyancy, b_bottom, b_top;
+} stau_rb_params;
+
+/* Multistep state, caller owned.
+ * X     device, complex128, state layout above (read as X^{n-1}, overwritten
+ *       with X^n by stau_step).
+ * hist  device, complex128, [2][P][2][ne][Nz]: for the two latest steps, the
+ *       left-preconditioned explicit term F~ = P^L F and M~X (evolved equation
+ *       U-rows only; ne = 3 in 2-D, 4 in 3-D; P = number of pencil slots).
+ * iteration  number of steps taken so far (0 selects SBDF1).
+ * dt_prev    previous timestep (ignored when iteration == 0).
+ * head       slot of hist holding step n-1 (updated by stau_step). */
+typedef struct stau_state {
+  void* X;
+  void* hist;
+  int64_t iteration;
+  double dt_prev;
+  int32_t head;
+  int32_t reserved;
+} stau_state;
+
+/* Sizes derived from a domain (filled by stau_query). */
+typedef struct stau_info {
+  int64_t Nx, Ny, Nz, Ngx, Ngy, Ngz;
+  int64_t Px;          /* Nx/2 + 1 rfft slots along x */
+  int64_t P;           /* pencil slots: Px (2-D) or Ny*Px (3-D) */
+  int64_t P_active;    /* pencils solved: Nx/2 (2-D) or (Nx/2)(Ny-1) (3-D) */
+  int64_t S;           /* variables per pencil: 7 or 9 */
+  int64_t ne;          /* evolved fields: 3 or 4 */
+  int64_t n;           /* unknowns per pencil S*Nz */
+  int64_t kl, ku;      /* band widths of the interleaved pencil matrix */
+  int64_t state_elems; /* complex elements of X */
+  int64_t hist_elems;  /* complex elements of hist */
+  int64_t workspace_bytes; /* device bytes held by the pencils object */
+} stau_info;
+
+/* Create a domain (validates sizes, builds FP64 twiddle and Chebyshev tables
+ * on the host and uploads them).  Sec. IV, V. */
+int stau_create_domain(const stau_domain_desc* desc, stau_domain** out);
+int stau_destroy_domain(stau_domain* dom);
+
+/* Build the pencil system of the Rayleigh-Benard problem on a domain:
+ * operator templates of Appendix A (T-to-U conversion P^L, derivative
+ * dT_n = n U_{n-1}, boundary rows T_n(+-1) = (+-1)^n, Dirichlet recombination
+ * P^R), row processing of Sec. IX "Matrix construction", interleaved mode-major
+ * ordering, and the device workspaces.  The pencils object keeps a pointer to
+ * the domain, which must outlive it. */
+int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils** out);
+int stau_destroy_pencils(stau_pencils* pen);
+int stau_query(const stau_pencils* pen, stau_info* info);
+
+/* Assemble a0 M~ + b0 L~ for every pencil on the device and factor it by
+ * banded LU with partial pivoting (Sec. IX: factorisations are stored and
+ * reused while a0, b0 are unchanged).  Synchronises `stream`.  Returns
+ * STAU_ESINGULAR if a pivot is zero or non-finite; the first such pencil index
+ * is then returned by stau_last_singular_pencil(). */
+int stau_factor(stau_pencils* pen, double a0, double b0, void* stream);
+int64_t stau_last_singular_pencil(const stau_pencils* pen);
+
+/* One IMEX step (Sec. IX "Multistep IMEX integrators"): SBDF1 when
+ * st->iteration == 0, else variable-step SBDF2 with w = dt / st->dt_prev.
+ * Evaluates the explicit term on the dealiased grid, forms
+ * B = sum_j c_j F~^{n-j} - a_j M~X^{n-j}, solves (a0 M~ + b0 L~) X~ = B per
+ * pencil and recovers X = P^R X~.  Refactors (synchronously) when (a0, b0)
+ * differ from the stored factorisation.  Updates st->X, st->hist and the
+ * host fields iteration, dt_prev, head.  Asynchronous otherwise. */
+int stau_step(stau_pencils* pen, stau_state* st, double dt, void* stream);
+
+/* Initial state from real scale-1 grid values of b (2-D b[ix][jz], 3-D
+ * b[ix][ly][jz]; device, float64; Chebyshev Gauss grid in z ascending,
+ * x_i = Lx i / Nx): forward transforms, bz = d_z b by the Chebyshev derivative
+ * recursion, every other variable zero.  X is written entirely. */
+int stau_initial_state(stau_pencils* pen, const double* b_grid, void* X, void* stream);
+
+/* Explicit term alone: F = coefficients of -(u.grad) q for q in the evolved
+ * fields, evaluated on the 3/2 grid (Sec. IV) from the state X.  F is device
+ * complex128 [P][ne][Nz] (2-D) / [Ny][Px][ne][Nz] (3-D); inactive slots are
+ * written as zero. */
+int stau_nonlinear(stau_pencils* pen, const void* X, void* F, void* stream);
+
+/* Pencil solve alone with the stored factors: B_ev is device complex128
+ * [P][ne][Nz] holding the right-hand sides of the evolved-equation U-rows
+ * n = 0..Nz-2 (entry Nz-1 ignored); the z-derivative and continuity rows are
+ * zero and the boundary rows take the problem's Dirichlet values.  Writes X
+ * (state layout).  Sec. IX "Linear boundary value solver". */
+int stau_solve(stau_pencils* pen, const void* B_ev, void* X, void* stream);
+
+/* Synchronise and check the device error flag and the state for non-finite
+ * values.  Returns STAU_ENONFINITE if X holds a NaN/Inf. */
+int stau_check(stau_pencils* pen, const void* X, void* stream);
+
+/* Kinetic-energy functional J = (1/V) int |u|^2 / 2 evaluated on the 3/2 grid
+ * with truncated forward transforms and the Chebyshev integration vector
+ * (Sec. VII "Integration"); result written to *out (host) after a sync. */
+int stau_kinetic_energy(stau_pencils* pen, const void* X, double* out, void* stream);
+
+/* Measurement hook: when enabled, every kernel launched by stau_step and
+ * stau_factor is bracketed by two HIP events recorded on the call's stream.
+ * stau_read_kernel_timing synchronises on those events, writes the summed
+ * elapsed milliseconds and launch counts per kernel kind (0 backward z
+ * transform, 1 x pass with products, 2 forward z transform with right-hand
+ * side assembly, 3 pencil solve, 4 pencil factorisation) into ms[] and
+ * launches[] (caller-owned host arrays of nkinds entries) and clears the
+ * record. */
+int stau_set_kernel_timing(stau_pencils* pen, int enable);
+int stau_read_kernel_timing(stau_pencils* pen, double* ms, int64_t* launches, int nkinds);
+
+const char* stau_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STAU_H */

@@ -1,0 +1,162 @@
+"""MI355X (gfx950) sparse-tau SBDF2 stepper for Fourier x Chebyshev
+Rayleigh-Benard convection.
+
+Every step of the path runs in the HIP kernels of libstau.so; this module only
+marshals torch device tensors and the current HIP stream into the C ABI of
+include/stau.h.  Importing it does not load the library; constructing an
+`RBSolver` does, and fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+
+__all__ = ["RBSolver", "StauError"]
+
+StauError = _lib.StauError
+
+
+def _stream_ptr(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class RBSolver:
+    """One domain + pencil system + caller-owned state tensors.
+
+    Attributes after construction: `X` (complex128 state, layout of the C ABI),
+    `hist` (complex128 history), `info` (sizes), `iteration`, `dt_prev`.
+    """
+
+    def __init__(self, Nx: int, Nz: int, Lx: float, Ra: float, Pr: float, *, dim: int = 2,
+                 Ny: int = 1, Ly: float = 1.0, precision: str = "fp64", buoyancy: float = 1.0,
+                 b_bottom: float = 1.0, b_top: float = 0.0, device: int = 0):
+        import torch
+
+        self._torch = torch
+        lib = _lib.load()
+        self.lib = lib
+        desc = _lib.DomainDesc(dim=dim, precision={"fp64": _lib.STAU_FP64, "mixed": _lib.STAU_MIXED}[precision],
+                               Nx=Nx, Ny=Ny, Nz=Nz, Lx=Lx, Ly=Ly, dealias=1.5, device=device)
+        self._dom = C.c_void_p()
+        _lib.check(lib.stau_create_domain(C.byref(desc), C.byref(self._dom)))
+        par = _lib.RBParamsC(Ra=Ra, Pr=Pr, buoyancy=buoyancy, b_bottom=b_bottom, b_top=b_top)
+        self._pen = C.c_void_p()
+        rc = lib.stau_build_pencils(self._dom, C.byref(par), C.byref(self._pen))
+        if rc:
+            lib.stau_destroy_domain(self._dom)
+            _lib.check(rc)
+        info = _lib.InfoC()
+        _lib.check(lib.stau_query(self._pen, C.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _lib.InfoC._fields_}
+        self.dim = dim
+        self.device = torch.device("cuda", device)
+        i = self.info
+        if dim == 2:
+            self.state_shape = (i["Px"], i["S"], i["Nz"])
+            self.ev_shape = (i["Px"], i["ne"], i["Nz"])
+        else:
+            self.state_shape = (i["Ny"], i["Px"], i["S"], i["Nz"])
+            self.ev_shape = (i["Ny"], i["Px"], i["ne"], i["Nz"])
+        self.X = torch.zeros(self.state_shape, dtype=torch.complex128, device=self.device)
+        self.hist = torch.zeros((2, i["P"], 2, i["ne"], i["Nz"]), dtype=torch.complex128,
+                                device=self.device)
+        self._st = _lib.StateC(X=self.X.data_ptr(), hist=self.hist.data_ptr(), iteration=0,
+                               dt_prev=0.0, head=0)
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_pen", None):
+            self.lib.stau_destroy_pencils(self._pen)
+            self._pen = None
+        if getattr(self, "_dom", None):
+            self.lib.stau_destroy_domain(self._dom)
+            self._dom = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state ------------------------------------------------------------
+    @property
+    def iteration(self) -> int:
+        return int(self._st.iteration)
+
+    @property
+    def dt_prev(self) -> float:
+        return float(self._st.dt_prev)
+
+    def reset(self):
+        self._st.iteration = 0
+        self._st.dt_prev = 0.0
+        self._st.head = 0
+
+    def set_state(self, X):
+        """Copy a complex128 state (state layout) into the solver and restart at SBDF1."""
+        self.X.copy_(X)
+        self.reset()
+
+    def initial_state(self, b_grid):
+        """Initial state from scale-1 grid values of b (float64 device tensor)."""
+        t = self._torch
+        b = b_grid.to(device=self.device, dtype=t.float64).contiguous()
+        _lib.check(self.lib.stau_initial_state(self._pen, _ptr(b), _ptr(self.X), _stream_ptr()))
+        self.reset()
+        return self.X
+
+    # -- the hot path -----------------------------------------------------
+    def step(self, dt: float):
+        self._st.X = self.X.data_ptr()
+        self._st.hist = self.hist.data_ptr()
+        _lib.check(self.lib.stau_step(self._pen, C.byref(self._st), float(dt), _stream_ptr()))
+
+    def factor(self, a0: float, b0: float = 1.0):
+        _lib.check(self.lib.stau_factor(self._pen, float(a0), float(b0), _stream_ptr()))
+
+    def last_singular_pencil(self) -> int:
+        return int(self.lib.stau_last_singular_pencil(self._pen))
+
+    # -- components -------------------------------------------------------
+    def nonlinear(self, X=None):
+        t = self._torch
+        Xs = (self.X if X is None else X).contiguous()
+        F = t.empty(self.ev_shape, dtype=t.complex128, device=self.device)
+        _lib.check(self.lib.stau_nonlinear(self._pen, _ptr(Xs), _ptr(F), _stream_ptr()))
+        return F
+
+    def solve(self, Bev):
+        t = self._torch
+        B = Bev.to(device=self.device, dtype=t.complex128).contiguous()
+        X = t.empty(self.state_shape, dtype=t.complex128, device=self.device)
+        _lib.check(self.lib.stau_solve(self._pen, _ptr(B), _ptr(X), _stream_ptr()))
+        return X
+
+    def set_kernel_timing(self, enable: bool):
+        _lib.check(self.lib.stau_set_kernel_timing(self._pen, 1 if enable else 0))
+
+    def read_kernel_timing(self):
+        """{kernel kind: (total ms, launches)} since timing was enabled (synchronises)."""
+        n = len(_lib.KERNEL_KINDS)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        _lib.check(self.lib.stau_read_kernel_timing(self._pen, ms, cnt, n))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KERNEL_KINDS)}
+
+    def check(self, X=None):
+        Xs = self.X if X is None else X
+        _lib.check(self.lib.stau_check(self._pen, _ptr(Xs), _stream_ptr()))
+
+    def kinetic_energy(self, X=None) -> float:
+        Xs = (self.X if X is None else X).contiguous()
+        out = C.c_double()
+        _lib.check(self.lib.stau_kinetic_energy(self._pen, _ptr(Xs), C.byref(out), _stream_ptr()))
+        return out.value

@@ -1,0 +1,309 @@
+// Shared device helpers: complex arithmetic, the in-LDS mixed-radix FFT and
+// the pencil-system description.  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stau {
+
+template <typename T>
+struct cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T x, T y) {
+  cpx<T> r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {  // a * conj(b)
+  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> conj(cpx<T> a) { return mk(a.x, -a.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return mk(a.x * s, a.y * s); }
+// multiply by i (DIR=+1) or -i (DIR=-1)
+template <int DIR, typename T>
+__device__ __forceinline__ cpx<T> mul_pi(cpx<T> a) {
+  return DIR > 0 ? mk(-a.y, a.x) : mk(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs.  DIR = -1: forward kernel e^{-2 pi i n k / R}; DIR = +1: inverse.
+// ---------------------------------------------------------------------------
+template <int DIR, typename T>
+__device__ __forceinline__ void dft2(cpx<T>* v) {
+  cpx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft3(cpx<T>* v) {
+  // w = e^{DIR 2 pi i / 3} = -1/2 + DIR i sqrt(3)/2
+  const T c = T(-0.5);
+  const T s = T(DIR) * T(0.86602540378443864676372317075294);
+  cpx<T> sum = v[1] + v[2], dif = v[1] - v[2];
+  cpx<T> m = mk(v[0].x + c * sum.x, v[0].y + c * sum.y);
+  cpx<T> is = mk(-s * dif.y, s * dif.x);  // i s (v1 - v2)
+  v[0] = v[0] + sum;
+  v[1] = m + is;
+  v[2] = m - is;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cpx<T>* v) {
+  cpx<T> t0 = v[0] + v[2], t1 = v[0] - v[2];
+  cpx<T> t2 = v[1] + v[3], t3 = v[1] - v[3];
+  cpx<T> r3 = mul_pi<DIR>(t3);  // DIR i t3
+  v[0] = t0 + t2;
+  v[2] = t0 - t2;
+  v[1] = t1 + r3;
+  v[3] = t1 - r3;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft8(cpx<T>* v) {
+  cpx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<DIR>(e);
+  dft4<DIR>(o);
+  const T h = T(0.70710678118654752440084436210485);
+  // w^k = e^{DIR 2 pi i k / 8}
+  cpx<T> w1o = cmul(o[1], mk(h, T(DIR) * h));
+  cpx<T> w2o = mul_pi<DIR>(o[2]);
+  cpx<T> w3o = cmul(o[3], mk(-h, T(DIR) * h));
+  v[0] = e[0] + o[0];
+  v[4] = e[0] - o[0];
+  v[1] = e[1] + w1o;
+  v[5] = e[1] - w1o;
+  v[2] = e[2] + w2o;
+  v[6] = e[2] - w2o;
+  v[3] = e[3] + w3o;
+  v[7] = e[3] - w3o;
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dftR(cpx<T>* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  if constexpr (R == 3) dft3<DIR>(v);
+  if constexpr (R == 4) dft4<DIR>(v);
+  if constexpr (R == 8) dft8<DIR>(v);
+}
+
+// ---------------------------------------------------------------------------
+// In-place Stockham autosort FFT of `batch` contiguous sequences of length M
+// held in LDS.  Radix plan: one radix-3 pass if 3 | M, one radix-8 pass if the
+// power of two is odd, radix-4 passes otherwise (M = 2^a 3^b, b <= 1).
+// tw[t] = e^{-2 pi i t / M}, t < M (FP64 host table, global memory).
+// Each pass stages its butterflies in registers between two barriers, so the
+// transform is in place.  MAXBF bounds the butterflies per thread per pass;
+// the caller guarantees batch*M/4 <= MAXBF*nthreads.
+// ---------------------------------------------------------------------------
+template <int R, int DIR, int MAXBF, typename T>
+__device__ __forceinline__ void stockham_pass(cpx<T>* buf, int M, int batch, int Ns,
+                                              const cpx<T>* __restrict__ tw, int tid, int nt) {
+  const int MR = M / R;
+  const int nbf = batch * MR;
+  const int tstride = M / (Ns * R);
+  cpx<T> v[MAXBF][R];
+#pragma unroll
+  for (int b = 0; b < MAXBF; ++b) {
+    const int bf = tid + b * nt;
+    if (bf < nbf) {
+      const int s = bf / MR, j = bf - s * MR;
+      const cpx<T>* src = buf + s * M + j;
+      const int jm = j % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = src[r * MR];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cpx<T> w = tw[jm * r * tstride];
+        v[b][r] = DIR < 0 ? cmul(v[b][r], w) : cmulc(v[b][r], w);
+      }
+      dftR<R, DIR>(v[b]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXBF; ++b) {
+    const int bf = tid + b * nt;
+    if (bf < nbf) {
+      const int s = bf / MR, j = bf - s * MR;
+      const int jm = j % Ns;
+      cpx<T>* dst = buf + s * M + (j / Ns) * Ns * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIR, int MAXBF, typename T>
+__device__ void fft_lds(cpx<T>* buf, int M, int batch, const cpx<T>* __restrict__ tw, int tid,
+                        int nt) {
+  int Ns = 1;
+  int m2 = M;
+  if (m2 % 3 == 0) {
+    stockham_pass<3, DIR, (MAXBF * 4 + 2) / 3>(buf, M, batch, Ns, tw, tid, nt);
+    Ns *= 3;
+    m2 /= 3;
+  }
+  int lg = 31 - __clz(m2);
+  if (lg & 1) {
+    if (lg >= 3) {
+      stockham_pass<8, DIR, (MAXBF + 1) / 2>(buf, M, batch, Ns, tw, tid, nt);
+      Ns *= 8;
+      lg -= 3;
+    } else {  // lg == 1
+      stockham_pass<2, DIR, MAXBF * 2>(buf, M, batch, Ns, tw, tid, nt);
+      Ns *= 2;
+      lg -= 1;
+    }
+  }
+  for (; lg > 0; lg -= 2) {
+    stockham_pass<4, DIR, MAXBF>(buf, M, batch, Ns, tw, tid, nt);
+    Ns *= 4;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pencil system layout (2-D: S = 7, 3-D: S = 9).
+//  variables per mode (column order):  2-D (w, b, u, p, bz, uz, wz)
+//                                      3-D (w, b, u, v, p, bz, uz, vz, wz)
+//  equations per mode (row order):     2-D (w, b, u, c, uz, bz, wz)
+//                                      3-D (w, b, u, v, c, uz, vz, bz, wz)
+//  boundary rows first: q(z=0) for q in evolved, then q(z=1) (gauge p(z=1)
+//  in place of w(z=1) at the mean pencil).
+// State arrays use the variable order of the C ABI: 2-D (p,b,u,w,bz,uz,wz),
+// 3-D (p,b,u,v,w,bz,uz,vz,wz).
+// ---------------------------------------------------------------------------
+enum Var { VW = 0, VB, VU, VV, VP, VBZ, VUZ, VVZ, VWZ };
+enum Eq { EW = 0, EB, EU, EV, EC, EUZ, EVZ, EBZ, EWZ };
+
+struct SysDesc {
+  int dim, S, ne, N, kb;
+  int var_at[9];      // column position in mode -> Var
+  int eq_at[9];       // row position in mode -> Eq
+  int var_pos[9];     // Var -> column position in mode (-1 if absent)
+  int eq_pos[9];      // Eq -> row position in mode
+  int abi_index[9];   // Var -> variable index in the C-ABI state layout
+  int bc_var[8];      // boundary row -> Var  (rows 0..kb-1)
+  int bc_side[8];     // 0: z = 0, 1: z = 1
+  int evolved[4];     // evolved Var in ABI evolved order (b, u, [v], w)
+};
+
+struct PencilCoef {
+  double a0, b0, kappa, nu, buoy, kx, ky;
+  int mean;
+};
+
+// Entry (r, c) of a0 M~ + b0 L~ in the interleaved, Dirichlet-recombined,
+// real-scaled system of one pencil.  Rows: kb boundary rows, then modes
+// n = 0..N-1 with S equation rows each (only continuity at n = N-1).
+// Columns: mode-major, S variables per mode.
+__host__ __device__ inline int sys_row_mode(const SysDesc& d, int r, int* epos) {
+  if (r < d.kb) {
+    *epos = -1;
+    return -1;
+  }
+  int q = r - d.kb;
+  int n = q / d.S;
+  *epos = q - n * d.S;
+  if (n == d.N - 1) *epos = d.eq_pos[EC];  // last mode: the continuity row only
+  return n;
+}
+
+__host__ __device__ inline double cheb_C(int n, int m) {  // P^L (n, m)
+  if (m == n) return n == 0 ? 1.0 : 0.5;
+  if (m == n + 2) return -0.5;
+  return 0.0;
+}
+__host__ __device__ inline double cheb_D(int n, int m) {  // d/dz (z in [0,1]) T->U
+  return m == n + 1 ? 2.0 * m : 0.0;
+}
+
+// T-basis entry (row (n, eq), column (m, var)); real-scaled.
+__host__ __device__ inline double entry_T(const SysDesc& d, const PencilCoef& pc, int n, int eq,
+                                          int m, int var) {
+  const double k2 = pc.kx * pc.kx + pc.ky * pc.ky;
+  switch (eq) {
+    case EB:
+      if (var == VB) return (pc.a0 + pc.b0 * pc.kappa * k2) * cheb_C(n, m);
+      if (var == VBZ) return -pc.b0 * pc.kappa * cheb_D(n, m);
+      return 0.0;
+    case EU:
+      if (var == VU) return (pc.a0 + pc.b0 * pc.nu * k2) * cheb_C(n, m);
+      if (var == VUZ) return -pc.b0 * pc.nu * cheb_D(n, m);
+      if (var == VP) return -pc.b0 * pc.kx * cheb_C(n, m);
+      return 0.0;
+    case EV:
+      if (var == VV) return (pc.a0 + pc.b0 * pc.nu * k2) * cheb_C(n, m);
+      if (var == VVZ) return -pc.b0 * pc.nu * cheb_D(n, m);
+      if (var == VP) return -pc.b0 * pc.ky * cheb_C(n, m);
+      return 0.0;
+    case EW:
+      if (var == VW) return (pc.a0 + pc.b0 * pc.nu * k2) * cheb_C(n, m);
+      if (var == VWZ) return -pc.b0 * pc.nu * cheb_D(n, m);
+      if (var == VP) return pc.b0 * cheb_D(n, m);
+      if (var == VB) return -pc.b0 * pc.buoy * cheb_C(n, m);
+      return 0.0;
+    case EBZ:
+      if (var == VBZ) return pc.b0 * cheb_C(n, m);
+      if (var == VB) return -pc.b0 * cheb_D(n, m);
+      return 0.0;
+    case EUZ:
+      if (var == VUZ) return pc.b0 * cheb_C(n, m);
+      if (var == VU) return -pc.b0 * cheb_D(n, m);
+      return 0.0;
+    case EVZ:
+      if (var == VVZ) return pc.b0 * cheb_C(n, m);
+      if (var == VV) return -pc.b0 * cheb_D(n, m);
+      return 0.0;
+    case EWZ:
+      if (var == VWZ) return pc.b0 * cheb_C(n, m);
+      if (var == VW) return -pc.b0 * cheb_D(n, m);
+      return 0.0;
+    case EC:
+      if (m != n) return 0.0;
+      if (var == VU) return pc.b0 * pc.kx;
+      if (var == VV) return pc.b0 * pc.ky;
+      if (var == VWZ) return pc.b0;
+      return 0.0;
+  }
+  return 0.0;
+}
+
+__host__ __device__ inline double sys_entry(const SysDesc& d, const PencilCoef& pc, int r, int c) {
+  const int m = c / d.S;
+  const int var = d.var_at[c - m * d.S];
+  if (r < d.kb) {
+    // boundary row: T_m(-1) = (-1)^m, T_m(1) = 1, recombined D_0, D_1 only
+    int bv = d.bc_var[r];
+    if (pc.mean && bv == VW && d.bc_side[r] == 1) bv = VP;  // gauge p(z=1) = 0
+    if (var != bv || m > 1) return 0.0;
+    const double val = (d.bc_side[r] == 0 && m == 1) ? -1.0 : 1.0;
+    return pc.b0 * val;
+  }
+  int epos;
+  const int n = sys_row_mode(d, r, &epos);
+  const int eq = d.eq_at[epos];
+  double v = entry_T(d, pc, n, eq, m, var);
+  if (m >= 2) v -= entry_T(d, pc, n, eq, m - 2, var);  // right-multiply by P^R
+  return v;
+}
+
+}  // namespace stau

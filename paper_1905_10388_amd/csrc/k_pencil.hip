@@ -1,0 +1,335 @@
+// Pencil kernels: device-side assembly of a0 M~ + b0 L~ from the operator
+// templates, banded LU with partial pivoting (one wavefront per pencil), and
+// the batched banded solve (one wavefront per pencil, register windows).
+//
+// Factor storage per pencil p and column j (n = S*N columns):
+//   Lf[p][j][FW]  multipliers of column j routed to the physical slot that
+//                 holds each pending row in the solve's forward window
+//                 (FW = kl + 1 slots; zero for the pivot's slot);
+//   sl[p][j]      physical slot holding the pivot row of column j;
+//   Uf[p][j][BW]  column j of U rotated into the backward window: lane l
+//                 holds U(r, j) for the row r = j - ((j - l) mod BW) it
+//                 carries, 1 / U(j, j) on lane j mod BW, zero elsewhere.
+// The interchanges are LAPACK's (row j <-> pivot row, applied column by
+// column), so the forward sweep follows the same order as the factorisation.
+#include "common.h"
+#include "kernels.h"
+
+namespace stau {
+
+constexpr int kWave = 64;
+constexpr int kCW = 64;  // factor column window (>= kv + 1)
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ PencilCoef pencil_coef(const PencilArgs& a, int p, double a0, double b0) {
+  PencilCoef pc;
+  pc.a0 = a0;
+  pc.b0 = b0;
+  pc.kappa = a.kappa;
+  pc.nu = a.nu;
+  pc.buoy = a.buoyancy;
+  int ix, iy;
+  if (a.desc.dim == 2) {
+    ix = p;
+    iy = 0;
+    pc.ky = 0.0;
+  } else {
+    iy = p / a.Px;
+    ix = p - iy * a.Px;
+    int kyi = iy < (a.Ny + 1) / 2 ? iy : iy - a.Ny;
+    pc.ky = a.two_pi_over_Ly * (double)kyi;
+  }
+  pc.kx = a.two_pi_over_Lx * (double)ix;
+  pc.mean = (ix == 0 && iy == 0);
+  return pc;
+}
+
+__device__ __forceinline__ bool pencil_active(const PencilArgs& a, int p) {
+  if (a.desc.dim == 2) return p < a.Px - 1;
+  int iy = p / a.Px;
+  int ix = p - iy * a.Px;
+  return ix < a.Px - 1 && iy != a.Ny / 2;
+}
+
+// ---------------------------------------------------------------------------
+// Factor: one wavefront per pencil.  Band held in an LDS window of kCW
+// columns, LAPACK layout (row i of column c at kv + i - c).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, double b0,
+                                                       double* __restrict__ Lf,
+                                                       uint8_t* __restrict__ sl,
+                                                       double* __restrict__ Uf,
+                                                       int* __restrict__ sing) {
+  extern __shared__ double lds[];
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int n = a.n, kl = a.kl, ku = a.ku, kv = kl + ku, ld = kv + kl + 1;
+  const int FW = a.FW, BW = a.BW;
+  double* win = lds;                                  // kCW * ld
+  __shared__ int phys[64];
+  __shared__ int spiv;
+  if (!pencil_active(a, p)) return;
+  const PencilCoef pc = pencil_coef(a, p, a0, b0);
+  const SysDesc d = a.desc;
+
+  auto assemble = [&](int c) {
+    double* col = win + (c % kCW) * ld;
+    for (int q = lane; q < ld; q += kWave) {
+      const int r = c - kv + q;
+      double v = 0.0;
+      if (r >= 0 && r < n && r >= c - ku) v = sys_entry(d, pc, r, c);
+      col[q] = v;
+    }
+  };
+  for (int c = 0; c <= kv && c < n; ++c) assemble(c);
+  if (lane < FW) phys[lane] = lane;
+  __syncthreads();
+
+  double* Lp = Lf + (size_t)p * n * FW;
+  double* Up = Uf + (size_t)p * n * BW;
+  uint8_t* sp = sl + (size_t)p * n;
+
+  for (int j = 0; j < n; ++j) {
+    double* cj = win + (j % kCW) * ld;
+    const int hi = min(n - 1, j + kl);
+    // --- pivot search: first index of the largest |a_ij|, i = j..hi
+    double mag = -1.0;
+    int idx = j;
+    if (lane <= hi - j) {
+      mag = fabs(cj[kv + lane]);
+      idx = j + lane;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      double om = __shfl_xor(mag, off);
+      int oi = __shfl_xor(idx, off);
+      if (om > mag || (om == mag && oi < idx)) {
+        mag = om;
+        idx = oi;
+      }
+    }
+    const int pr = idx;
+    // --- swap rows j and pr over columns j..j+kv
+    const int cmax = min(n - 1, j + kv);
+    if (pr != j) {
+      for (int c = j + lane; c <= cmax; c += kWave) {
+        double* cc = win + (c % kCW) * ld;
+        double t = cc[kv + j - c];
+        cc[kv + j - c] = cc[kv + pr - c];
+        cc[kv + pr - c] = t;
+      }
+    }
+    __syncthreads();
+    double piv = cj[kv];
+    if (!(fabs(piv) > 0.0) || !isfinite(piv)) {
+      if (lane == 0) atomicMin(sing, p);
+      piv = 1.0;
+    }
+    const double rinv = 1.0 / piv;
+    // --- multipliers
+    if (lane >= 1 && lane <= hi - j) cj[kv + lane] *= rinv;
+    __syncthreads();
+    // --- rank-1 update of rows j+1..hi, columns j+1..cmax
+    const int nr = hi - j, nc = cmax - j;
+    for (int t = lane; t < nr * nc; t += kWave) {
+      const int i = 1 + t / nc, cc = 1 + t % nc;
+      double* col = win + ((j + cc) % kCW) * ld;
+      col[kv + (j + i) - (j + cc)] -= cj[kv + i] * col[kv + j - (j + cc)];
+    }
+    // --- emit column j: U rotated into the backward window
+    for (int l = lane; l < BW; l += kWave) {
+      const int r = j - ((j - l) % BW + BW) % BW;
+      double v = 0.0;
+      if (r == j)
+        v = rinv;
+      else if (r >= 0 && j - r <= kv)
+        v = cj[kv + r - j];
+      Up[(size_t)j * BW + l] = v;
+    }
+    // --- emit column j: multipliers routed to physical forward slots
+    if (lane == 0) spiv = pr;
+    __syncthreads();
+    {
+      const int dd = spiv - j;
+      const int s = phys[dd];
+      const int t0 = phys[0];
+      __syncthreads();
+      if (lane == 0) {
+        phys[dd] = t0;
+        phys[0] = s;
+        sp[j] = (uint8_t)s;
+      }
+      __syncthreads();
+      double lv = 0.0;
+      int slot = -1;
+      if (lane >= 1 && lane < FW) {
+        slot = phys[lane];
+        lv = (lane <= hi - j) ? cj[kv + lane] : 0.0;
+      }
+      if (lane < FW) Lp[(size_t)j * FW + (lane == 0 ? s : slot)] = (lane == 0 ? 0.0 : lv);
+      __syncthreads();
+      int nxt = (lane < FW - 1) ? phys[lane + 1] : s;
+      __syncthreads();
+      if (lane < FW) phys[lane] = nxt;
+    }
+    __syncthreads();
+    if (j + kv + 1 < n) assemble(j + kv + 1);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solve: one wavefront per pencil.  Right-hand side of the real-scaled system
+// built in LDS (two real vectors: the real and imaginary parts), overwritten
+// by y = L^{-1} P b and then by x~ = U^{-1} y; finally X = P^R x~ is written in
+// the state layout with the real scaling undone.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kWave) solve_kernel(PencilArgs a, const double2* __restrict__ Bev,
+                                                      const double* __restrict__ Lf,
+                                                      const uint8_t* __restrict__ sl,
+                                                      const double* __restrict__ Uf,
+                                                      double2* __restrict__ X) {
+  extern __shared__ double lds[];
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int n = a.n, N = a.desc.N, S = a.desc.S, kb = a.desc.kb, ne = a.desc.ne;
+  const int FW = a.FW, BW = a.BW;
+  const SysDesc& d = a.desc;
+  double2* Xp = X + (size_t)p * S * N;
+  if (!pencil_active(a, p)) {
+    for (int i = lane; i < S * N; i += kWave) Xp[i] = make_double2(0.0, 0.0);
+    return;
+  }
+  const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
+  double* br = lds;
+  double* bi = lds + n;
+  const double2* Bp = Bev + (size_t)p * ne * N;
+  // --- right-hand side
+  for (int r = lane; r < n; r += kWave) {
+    double vr = 0.0, vi = 0.0;
+    if (r < kb) {
+      if (pc.mean && d.bc_var[r] == VB) vr = d.bc_side[r] == 0 ? a.b_bottom : a.b_top;
+    } else {
+      int epos;
+      const int m = sys_row_mode(d, r, &epos);
+      const int eq = d.eq_at[epos];
+      int e = -1;
+      if (eq == EB) e = 0;
+      if (eq == EU) e = 1;
+      if (eq == EV) e = 2;
+      if (eq == EW) e = ne - 1;
+      if (e >= 0 && m <= N - 2) {
+        double2 v = Bp[e * N + m];
+        if (eq == EU || eq == EV) {  // row scaled by i
+          vr = -v.y;
+          vi = v.x;
+        } else {
+          vr = v.x;
+          vi = v.y;
+        }
+      }
+    }
+    br[r] = vr;
+    bi[r] = vi;
+  }
+  __syncthreads();
+  const double* Lp = Lf + (size_t)p * n * FW;
+  const uint8_t* sp = sl + (size_t)p * n;
+  const double* Up = Uf + (size_t)p * n * BW;
+  // --- forward sweep: window of FW pending rows in lanes 0..FW-1
+  double wr = 0.0, wi = 0.0;
+  if (lane < FW && lane < n) {
+    wr = br[lane];
+    wi = bi[lane];
+  }
+  for (int j = 0; j < n; ++j) {
+    const int s = __builtin_amdgcn_readfirstlane((int)sp[j]);
+    const double lj = lane < FW ? Lp[(size_t)j * FW + lane] : 0.0;
+    const double yr = readlane_d(wr, s);
+    const double yi = readlane_d(wi, s);
+    if (lane == s) {
+      br[j] = yr;
+      bi[j] = yi;
+    }
+    wr = fma(-lj, yr, wr);
+    wi = fma(-lj, yi, wi);
+    if (lane == s) {
+      const int r = j + FW;
+      wr = r < n ? br[r] : 0.0;
+      wi = r < n ? bi[r] : 0.0;
+    }
+  }
+  __syncthreads();
+  // --- backward sweep: lane l carries the row r = l (mod BW) of [j-BW+1, j]
+  wr = 0.0;
+  wi = 0.0;
+  if (lane < BW) {
+    const int r = (n - 1) - (((n - 1 - lane) % BW) + BW) % BW;
+    if (r >= 0) {
+      wr = br[r];
+      wi = bi[r];
+    }
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    const int sj = j % BW;
+    const double u = lane < BW ? Up[(size_t)j * BW + lane] : 0.0;
+    const double xr = readlane_d(wr * u, sj);
+    const double xi = readlane_d(wi * u, sj);
+    if (lane == sj) {
+      br[j] = xr;
+      bi[j] = xi;
+    }
+    wr = fma(-u, xr, wr);
+    wi = fma(-u, xi, wi);
+    if (lane == sj) {
+      const int r = j - BW;
+      wr = r >= 0 ? br[r] : 0.0;
+      wi = r >= 0 ? bi[r] : 0.0;
+    }
+  }
+  __syncthreads();
+  // --- X = P^R x~, undo the real scaling, state layout
+  for (int i = lane; i < S * N; i += kWave) {
+    const int vabi = i / N, m = i - vabi * N;
+    const int var = a.var_of_abi[vabi];
+    const int pos = d.var_pos[var];
+    double xr = br[m * S + pos], xi = bi[m * S + pos];
+    if (m + 2 < N) {
+      xr -= br[(m + 2) * S + pos];
+      xi -= bi[(m + 2) * S + pos];
+    }
+    if (var == VU || var == VUZ || var == VV || var == VVZ)
+      Xp[i] = make_double2(xi, -xr);  // u = -i u~
+    else
+      Xp[i] = make_double2(xr, xi);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, uint8_t* sl,
+                         double* Uf, int* sing, hipStream_t st) {
+  const int ld = a.kl + a.ku + a.kl + 1;
+  size_t lds = (size_t)kCW * ld * sizeof(double);
+  hipLaunchKernelGGL(factor_kernel, dim3(a.P), dim3(kWave), lds, st, a, a0, b0, Lf, sl, Uf, sing);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
+                        const double* Uf, void* X, hipStream_t st) {
+  size_t lds = (size_t)2 * a.n * sizeof(double);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  hipLaunchKernelGGL(solve_kernel, dim3(a.P), dim3(kWave), lds, st, a,
+                     (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+  return hipGetLastError();
+}
+
+}  // namespace stau

@@ -1,0 +1,76 @@
+// Internal launcher interface between the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace stau {
+
+constexpr int kMaxFields = 16;
+
+struct PencilArgs {
+  SysDesc desc;
+  int n, kl, ku, FW, BW;
+  int P, Px, Ny;
+  double kappa, nu, buoyancy, b_bottom, b_top;
+  double two_pi_over_Lx, two_pi_over_Ly;
+  int var_of_abi[9];
+};
+
+struct XformArgs {
+  int dim;
+  int N, M;          // Chebyshev modes, dealiased z grid
+  int Nx, L;         // Fourier x modes, dealiased x grid
+  int Pa, Px;        // active kx (Nx/2), kx slots (Nx/2 + 1)
+  int Ny, Ngy;       // 3-D only
+  int P;             // pencil slots = row length of the z-transform outputs
+  int S, ne;
+  double two_pi_over_Lx, two_pi_over_Ly;
+  const double2* twz;   // e^{-2 pi i t / M}
+  const double2* dctz;  // e^{+i pi n / (2 M)}
+  const double2* twx;   // e^{-2 pi i t / L}
+  const double2* twy;   // e^{-2 pi i t / Ngy}
+};
+
+// Field list for the backward z transform: state variable (ABI index) and
+// derivative flag (0: none, 1: multiply by i kx, 2: multiply by i ky).
+struct FieldList {
+  int nf;
+  int var[kMaxFields];
+  int deriv[kMaxFields];
+};
+
+// pencil kernels
+hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, uint8_t* sl,
+                         double* Uf, int* sing, hipStream_t st);
+hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
+                        const double* Uf, void* X, hipStream_t st);
+
+// transforms (2-D)
+hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, void* G,
+                     hipStream_t st);
+hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st);
+// forward z; mode 0 writes F[P][ne][N]; mode 1 assembles the SBDF right-hand
+// side and the history (see k_transform.hip)
+struct RhsArgs {
+  int mode;
+  double c1, c2, a1, a2;
+  int has_hist;
+  const double2* Xprev;  // state X^{n-1}
+  double2* hist_cur;     // [P][2][ne][N]
+  const double2* hist_old;
+};
+hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
+                     hipStream_t st);
+
+// initial state from scale-1 grid values of b
+hipError_t launch_initial_state(const XformArgs& a1, const double* bgrid, void* X, void* work,
+                                hipStream_t st);
+
+// kinetic energy: mean over x of |u|^2/2 per z row, then Chebyshev integral
+hipError_t launch_ke(const XformArgs& a, const void* X, void* G, double* rowmean, double* out,
+                     hipStream_t st);
+
+}  // namespace stau

@@ -1,0 +1,600 @@
+// Host runtime behind the C ABI of include/stau.h: domain validation, FP64
+// twiddle / DCT tables (host libm, integer argument reduction), pencil system
+// description, device workspaces and the step sequence.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/stau.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace stau;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(STAU_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// exp(-2 pi i t / n) with t reduced modulo n in integers and the angle formed
+// in long double.
+void fft_table(int64_t n, std::vector<double2>& out) {
+  out.resize(n);
+  for (int64_t t = 0; t < n; ++t) {
+    const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)(t % n) /
+                            (long double)n;
+    out[t] = make_double2((double)cosl(ang), (double)sinl(ang));
+  }
+}
+// exp(+i pi n / (2 m)), n < m
+void dct_table(int64_t m, std::vector<double2>& out) {
+  out.resize(m);
+  for (int64_t t = 0; t < m; ++t) {
+    const long double ang =
+        3.14159265358979323846264338327950288L * (long double)t / (2.0L * (long double)m);
+    out[t] = make_double2((double)cosl(ang), (double)sinl(ang));
+  }
+}
+
+template <typename T>
+int upload(const std::vector<T>& h, T** d) {
+  HIP_TRY(hipMalloc((void**)d, h.size() * sizeof(T)));
+  HIP_TRY(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return STAU_OK;
+}
+
+}  // namespace
+
+struct stau_domain {
+  stau_domain_desc d{};
+  int64_t Ngx = 0, Ngy = 1, Ngz = 0, Px = 0, P = 0, Pa = 0;
+  double2 *twz = nullptr, *dctz = nullptr, *twx = nullptr, *twy = nullptr;
+  double2 *twz1 = nullptr, *dctz1 = nullptr, *twx1 = nullptr;
+};
+
+struct stau_pencils {
+  stau_domain* dom = nullptr;
+  stau_rb_params par{};
+  PencilArgs pa{};
+  XformArgs xa{};   // dealiased transforms
+  XformArgs xa1{};  // scale-1 transforms
+  FieldList fl{};
+  int64_t n = 0;
+  // workspaces
+  double2* G = nullptr;    // [NF][M][P]
+  double2* H = nullptr;    // [ne][M][P]
+  double2* Bev = nullptr;  // [P][ne][N]
+  double* Lf = nullptr;
+  uint8_t* sl = nullptr;
+  double* Uf = nullptr;
+  int* sing = nullptr;     // device: first singular pencil (INT_MAX if none)
+  int* flag = nullptr;     // device: non-finite flag
+  double* scratch = nullptr;
+  int64_t ws_bytes = 0;
+  bool factored = false;
+  double fa0 = 0.0, fb0 = 0.0;
+  int64_t last_sing = -1;
+  // per-kernel event timing (instrumentation)
+  bool timing = false;
+  struct Ev {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Ev> events;
+};
+
+namespace {
+enum Kind { K_ZB = 0, K_XPASS, K_ZF, K_SOLVE, K_FACTOR, K_NKINDS };
+
+template <typename F>
+hipError_t timed(stau_pencils* pen, int kind, hipStream_t st, F&& launch) {
+  if (!pen->timing) return launch();
+  stau_pencils::Ev ev{kind, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev.a);
+  if (e == hipSuccess) e = hipEventCreate(&ev.b);
+  if (e == hipSuccess) e = hipEventRecord(ev.a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ev.b, st);
+  pen->events.push_back(ev);
+  return e;
+}
+}  // namespace
+
+namespace {
+
+void build_sysdesc(int dim, int N, SysDesc& d, int* var_of_abi) {
+  std::memset(&d, 0, sizeof(d));
+  d.dim = dim;
+  d.N = N;
+  for (int i = 0; i < 9; ++i) {
+    d.var_pos[i] = -1;
+    d.eq_pos[i] = -1;
+    d.abi_index[i] = -1;
+  }
+  if (dim == 2) {
+    const int va[7] = {VW, VB, VU, VP, VBZ, VUZ, VWZ};
+    const int ea[7] = {EW, EB, EU, EC, EUZ, EBZ, EWZ};
+    const int abi[7] = {VP, VB, VU, VW, VBZ, VUZ, VWZ};
+    d.S = 7;
+    d.ne = 3;
+    d.kb = 6;
+    for (int i = 0; i < 7; ++i) {
+      d.var_at[i] = va[i];
+      d.eq_at[i] = ea[i];
+      var_of_abi[i] = abi[i];
+    }
+    const int bv[6] = {VB, VU, VW, VB, VU, VW};
+    for (int i = 0; i < 6; ++i) {
+      d.bc_var[i] = bv[i];
+      d.bc_side[i] = i < 3 ? 0 : 1;
+    }
+    d.evolved[0] = VB;
+    d.evolved[1] = VU;
+    d.evolved[2] = VW;
+  } else {
+    const int va[9] = {VW, VB, VU, VV, VP, VBZ, VUZ, VVZ, VWZ};
+    const int ea[9] = {EW, EB, EU, EV, EC, EUZ, EVZ, EBZ, EWZ};
+    const int abi[9] = {VP, VB, VU, VV, VW, VBZ, VUZ, VVZ, VWZ};
+    d.S = 9;
+    d.ne = 4;
+    d.kb = 8;
+    for (int i = 0; i < 9; ++i) {
+      d.var_at[i] = va[i];
+      d.eq_at[i] = ea[i];
+      var_of_abi[i] = abi[i];
+    }
+    const int bv[8] = {VB, VU, VV, VW, VB, VU, VV, VW};
+    for (int i = 0; i < 8; ++i) {
+      d.bc_var[i] = bv[i];
+      d.bc_side[i] = i < 4 ? 0 : 1;
+    }
+    d.evolved[0] = VB;
+    d.evolved[1] = VU;
+    d.evolved[2] = VV;
+    d.evolved[3] = VW;
+  }
+  for (int i = 0; i < d.S; ++i) {
+    d.var_pos[d.var_at[i]] = i;
+    d.eq_pos[d.eq_at[i]] = i;
+    d.abi_index[var_of_abi[i]] = i;
+  }
+}
+
+// Band widths of the interleaved system from its structure (generic
+// coefficients, plus the mean pencil for the gauge row).
+void band_widths(const SysDesc& d, int64_t n, int* kl, int* ku) {
+  int l = 0, u = 0;
+  for (int mean = 0; mean < 2; ++mean) {
+    PencilCoef pc{1.7, 1.3, 0.31, 0.67, 1.1, mean ? 0.0 : 0.93, (mean || d.dim == 2) ? 0.0 : 0.61,
+                  mean};
+    for (int64_t r = 0; r < n; ++r) {
+      const int64_t c0 = r - 6 * d.S < 0 ? 0 : r - 6 * d.S;
+      const int64_t c1 = r + 7 * d.S > n ? n : r + 7 * d.S;
+      for (int64_t c = c0; c < c1; ++c) {
+        if (sys_entry(d, pc, (int)r, (int)c) != 0.0) {
+          if (r - c > l) l = (int)(r - c);
+          if (c - r > u) u = (int)(c - r);
+        }
+      }
+    }
+  }
+  *kl = l;
+  *ku = u;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stau_last_error(void) { return g_err.c_str(); }
+
+int stau_set_kernel_timing(stau_pencils* pen, int enable) {
+  if (!pen) return fail(STAU_EINVAL, "null argument");
+  pen->timing = enable != 0;
+  return STAU_OK;
+}
+
+int stau_read_kernel_timing(stau_pencils* pen, double* ms, int64_t* launches, int nkinds) {
+  if (!pen || !ms || !launches || nkinds < 0) return fail(STAU_EINVAL, "bad argument");
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  for (int k = 0; k < nkinds; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  int rc = STAU_OK;
+  for (auto& ev : pen->events) {
+    if (rc == STAU_OK) {
+      hipError_t e = hipEventSynchronize(ev.b);
+      float t = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, ev.a, ev.b);
+      if (e != hipSuccess)
+        rc = fail(STAU_EHIP, "event timing failed: %s", hipGetErrorString(e));
+      else if (ev.kind < nkinds) {
+        ms[ev.kind] += t;
+        launches[ev.kind] += 1;
+      }
+    }
+    hipEventDestroy(ev.a);
+    hipEventDestroy(ev.b);
+  }
+  pen->events.clear();
+  return rc;
+}
+
+int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
+  if (!desc || !out) return fail(STAU_EINVAL, "null argument");
+  *out = nullptr;
+  const stau_domain_desc& d = *desc;
+  if (d.dim != 2) return fail(STAU_EUNSUPPORTED, "dim=%d: only 2-D domains are built", d.dim);
+  if (d.precision != STAU_FP64) return fail(STAU_EUNSUPPORTED, "precision %d not built", d.precision);
+  if (std::fabs(d.dealias - 1.5) > 1e-15) return fail(STAU_EUNSUPPORTED, "dealias must be 1.5");
+  if (!is_pow2(d.Nx) || d.Nx < 4 || d.Nx > 4096)
+    return fail(STAU_EUNSUPPORTED, "Nx=%lld must be a power of two in [4, 4096]", (long long)d.Nx);
+  if (!is_pow2(d.Nz) || d.Nz < 4 || d.Nz > 512)
+    return fail(STAU_EUNSUPPORTED, "Nz=%lld must be a power of two in [4, 512]", (long long)d.Nz);
+  if (!(d.Lx > 0.0)) return fail(STAU_EINVAL, "Lx must be positive");
+  HIP_TRY(hipSetDevice(d.device));
+  stau_domain* dom = new (std::nothrow) stau_domain();
+  if (!dom) return fail(STAU_ENOMEM, "host allocation failed");
+  dom->d = d;
+  dom->Ngx = 3 * d.Nx / 2;
+  dom->Ngz = 3 * d.Nz / 2;
+  dom->Px = d.Nx / 2 + 1;
+  dom->P = dom->Px;
+  dom->Pa = d.Nx / 2;
+  std::vector<double2> t;
+  int rc;
+  fft_table(dom->Ngz, t);
+  if ((rc = upload(t, &dom->twz))) goto bad;
+  dct_table(dom->Ngz, t);
+  if ((rc = upload(t, &dom->dctz))) goto bad;
+  fft_table(dom->Ngx, t);
+  if ((rc = upload(t, &dom->twx))) goto bad;
+  fft_table(d.Nz, t);
+  if ((rc = upload(t, &dom->twz1))) goto bad;
+  dct_table(d.Nz, t);
+  if ((rc = upload(t, &dom->dctz1))) goto bad;
+  fft_table(d.Nx, t);
+  if ((rc = upload(t, &dom->twx1))) goto bad;
+  *out = dom;
+  return STAU_OK;
+bad:
+  stau_destroy_domain(dom);
+  return rc;
+}
+
+int stau_destroy_domain(stau_domain* dom) {
+  if (!dom) return STAU_OK;
+  hipSetDevice(dom->d.device);
+  hipFree(dom->twz);
+  hipFree(dom->dctz);
+  hipFree(dom->twx);
+  hipFree(dom->twy);
+  hipFree(dom->twz1);
+  hipFree(dom->dctz1);
+  hipFree(dom->twx1);
+  delete dom;
+  return STAU_OK;
+}
+
+static void free_pencils(stau_pencils* p) {
+  for (auto& ev : p->events) {
+    hipEventDestroy(ev.a);
+    hipEventDestroy(ev.b);
+  }
+  p->events.clear();
+  hipFree(p->G);
+  hipFree(p->H);
+  hipFree(p->Bev);
+  hipFree(p->Lf);
+  hipFree(p->sl);
+  hipFree(p->Uf);
+  hipFree(p->sing);
+  hipFree(p->flag);
+  hipFree(p->scratch);
+}
+
+int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils** out) {
+  if (!dom || !par || !out) return fail(STAU_EINVAL, "null argument");
+  *out = nullptr;
+  if (!(par->Ra > 0.0) || !(par->Pr > 0.0)) return fail(STAU_EINVAL, "Ra and Pr must be positive");
+  HIP_TRY(hipSetDevice(dom->d.device));
+  stau_pencils* pen = new (std::nothrow) stau_pencils();
+  if (!pen) return fail(STAU_ENOMEM, "host allocation failed");
+  pen->dom = dom;
+  pen->par = *par;
+  const stau_domain_desc& d = dom->d;
+  const int N = (int)d.Nz;
+  PencilArgs& pa = pen->pa;
+  build_sysdesc(d.dim, N, pa.desc, pa.var_of_abi);
+  pen->n = (int64_t)pa.desc.S * N;
+  pa.n = (int)pen->n;
+  band_widths(pa.desc, pen->n, &pa.kl, &pa.ku);
+  pa.FW = pa.kl + 1;
+  pa.BW = (pa.kl + pa.ku + 1 <= 32) ? 32 : 64;
+  if (pa.FW > 64 || pa.kl + pa.ku + 1 > 64) {
+    free_pencils(pen);
+    delete pen;
+    return fail(STAU_EUNSUPPORTED, "band too wide (kl=%d, ku=%d)", pa.kl, pa.ku);
+  }
+  pa.P = (int)dom->P;
+  pa.Px = (int)dom->Px;
+  pa.Ny = (int)d.Ny;
+  pa.kappa = std::pow(par->Ra * par->Pr, -0.5);
+  pa.nu = std::pow(par->Ra / par->Pr, -0.5);
+  pa.buoyancy = par->buoyancy;
+  pa.b_bottom = par->b_bottom;
+  pa.b_top = par->b_top;
+  pa.two_pi_over_Lx = 2.0 * M_PI / d.Lx;
+  pa.two_pi_over_Ly = d.dim == 3 ? 2.0 * M_PI / d.Ly : 0.0;
+
+  XformArgs& xa = pen->xa;
+  xa.dim = d.dim;
+  xa.N = N;
+  xa.M = (int)dom->Ngz;
+  xa.Nx = (int)d.Nx;
+  xa.L = (int)dom->Ngx;
+  xa.Pa = (int)dom->Pa;
+  xa.Px = (int)dom->Px;
+  xa.Ny = (int)d.Ny;
+  xa.Ngy = (int)dom->Ngy;
+  xa.P = (int)dom->P;
+  xa.S = pa.desc.S;
+  xa.ne = pa.desc.ne;
+  xa.two_pi_over_Lx = pa.two_pi_over_Lx;
+  xa.two_pi_over_Ly = pa.two_pi_over_Ly;
+  xa.twz = dom->twz;
+  xa.dctz = dom->dctz;
+  xa.twx = dom->twx;
+  xa.twy = dom->twy;
+  pen->xa1 = xa;
+  pen->xa1.M = N;
+  pen->xa1.L = (int)d.Nx;
+  pen->xa1.twz = dom->twz1;
+  pen->xa1.dctz = dom->dctz1;
+  pen->xa1.twx = dom->twx1;
+
+  FieldList& fl = pen->fl;  // u, w, b_x, b_z, u_x, u_z, w_x, w_z
+  const int fv[8] = {2, 3, 1, 4, 2, 5, 3, 6};
+  const int fd[8] = {0, 0, 1, 0, 1, 0, 1, 0};
+  fl.nf = 8;
+  for (int i = 0; i < 8; ++i) {
+    fl.var[i] = fv[i];
+    fl.deriv[i] = fd[i];
+  }
+
+  const size_t P = dom->P, M = dom->Ngz, ne = pa.desc.ne, n = pen->n;
+  const size_t szG = (size_t)fl.nf * M * P * sizeof(double2);
+  const size_t szH = ne * M * P * sizeof(double2);
+  const size_t szB = P * ne * N * sizeof(double2);
+  const size_t szL = P * n * pa.FW * sizeof(double);
+  const size_t szU = P * n * pa.BW * sizeof(double);
+  const size_t szS = P * n;
+  const size_t szScratch = (size_t)(N * P + P * N + 4 * M + 64) * sizeof(double2);
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->G, szG);
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->H, szH);
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->Bev, szB);
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->Lf, szL);
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->sl, szS);
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->Uf, szU);
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->sing, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->flag, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->scratch, szScratch);
+  if (e != hipSuccess) {
+    free_pencils(pen);
+    delete pen;
+    return fail(STAU_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  pen->ws_bytes = (int64_t)(szG + szH + szB + szL + szU + szS + szScratch);
+  *out = pen;
+  return STAU_OK;
+}
+
+int stau_destroy_pencils(stau_pencils* pen) {
+  if (!pen) return STAU_OK;
+  hipSetDevice(pen->dom->d.device);
+  hipDeviceSynchronize();
+  free_pencils(pen);
+  delete pen;
+  return STAU_OK;
+}
+
+int stau_query(const stau_pencils* pen, stau_info* info) {
+  if (!pen || !info) return fail(STAU_EINVAL, "null argument");
+  const stau_domain* dom = pen->dom;
+  info->Nx = dom->d.Nx;
+  info->Ny = dom->d.dim == 3 ? dom->d.Ny : 1;
+  info->Nz = dom->d.Nz;
+  info->Ngx = dom->Ngx;
+  info->Ngy = dom->Ngy;
+  info->Ngz = dom->Ngz;
+  info->Px = dom->Px;
+  info->P = dom->P;
+  info->P_active = dom->d.dim == 2 ? dom->Pa : dom->Pa * (dom->d.Ny - 1);
+  info->S = pen->pa.desc.S;
+  info->ne = pen->pa.desc.ne;
+  info->n = pen->n;
+  info->kl = pen->pa.kl;
+  info->ku = pen->pa.ku;
+  info->state_elems = dom->P * info->S * info->Nz;
+  info->hist_elems = 2 * dom->P * 2 * info->ne * info->Nz;
+  info->workspace_bytes = pen->ws_bytes;
+  return STAU_OK;
+}
+
+int stau_factor(stau_pencils* pen, double a0, double b0, void* stream) {
+  if (!pen) return fail(STAU_EINVAL, "null argument");
+  if (!std::isfinite(a0) || !std::isfinite(b0)) return fail(STAU_EINVAL, "non-finite a0/b0");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  const int big = 0x7fffffff;
+  HIP_TRY(hipMemcpyAsync(pen->sing, &big, sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(timed(pen, K_FACTOR, st, [&] {
+    return launch_factor(pen->pa, a0, b0, pen->Lf, pen->sl, pen->Uf, pen->sing, st);
+  }));
+  int h = big;
+  HIP_TRY(hipMemcpyAsync(&h, pen->sing, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h != big) {
+    pen->factored = false;
+    pen->last_sing = h;
+    return fail(STAU_ESINGULAR, "zero or non-finite pivot in pencil %d", h);
+  }
+  pen->factored = true;
+  pen->fa0 = a0;
+  pen->fb0 = b0;
+  pen->last_sing = -1;
+  return STAU_OK;
+}
+
+int64_t stau_last_singular_pencil(const stau_pencils* pen) { return pen ? pen->last_sing : -1; }
+
+static void sbdf(int64_t it, double dt, double dtp, double* a0, double* a1, double* a2, double* b0,
+                 double* c1, double* c2) {
+  if (it == 0) {
+    *a0 = 1.0 / dt;
+    *a1 = -1.0 / dt;
+    *a2 = 0.0;
+    *b0 = 1.0;
+    *c1 = 1.0;
+    *c2 = 0.0;
+    return;
+  }
+  const double w = dt / dtp;
+  *a0 = (1.0 + 2.0 * w) / ((1.0 + w) * dt);
+  *a1 = -(1.0 + w) / dt;
+  *a2 = w * w / ((1.0 + w) * dt);
+  *b0 = 1.0;
+  *c1 = 1.0 + w;
+  *c2 = -w;
+}
+
+int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
+  if (!pen || !s || !s->X || !s->hist) return fail(STAU_EINVAL, "null argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(STAU_EINVAL, "dt must be positive");
+  if (s->iteration > 0 && !(s->dt_prev > 0.0)) return fail(STAU_ESTATE, "dt_prev not set");
+  if (s->head != 0 && s->head != 1) return fail(STAU_EINVAL, "head must be 0 or 1");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  double a0, a1, a2, b0, c1, c2;
+  sbdf(s->iteration, dt, s->dt_prev, &a0, &a1, &a2, &b0, &c1, &c2);
+  if (!pen->factored || a0 != pen->fa0 || b0 != pen->fb0) {
+    int rc = stau_factor(pen, a0, b0, stream);
+    if (rc) return rc;
+  }
+  const int cur = s->head ^ 1;
+  const size_t hslot = (size_t)pen->dom->P * 2 * pen->pa.desc.ne * pen->dom->d.Nz;
+  double2* hist = (double2*)s->hist;
+  RhsArgs r{};
+  r.mode = 1;
+  r.c1 = c1;
+  r.c2 = c2;
+  r.a1 = a1;
+  r.a2 = a2;
+  r.has_hist = s->iteration > 0;
+  r.Xprev = (const double2*)s->X;
+  r.hist_cur = hist + cur * hslot;
+  r.hist_old = hist + (cur ^ 1) * hslot;
+  HIP_TRY(timed(pen, K_ZB, st, [&] { return launch_zb(pen->xa, pen->fl, s->X, pen->G, st); }));
+  HIP_TRY(timed(pen, K_XPASS, st, [&] { return launch_xpass(pen->xa, pen->G, pen->H, st); }));
+  HIP_TRY(timed(pen, K_ZF, st, [&] { return launch_zf(pen->xa, pen->H, pen->Bev, r, st); }));
+  HIP_TRY(timed(pen, K_SOLVE, st, [&] {
+    return launch_solve(pen->pa, pen->Bev, pen->Lf, pen->sl, pen->Uf, s->X, st);
+  }));
+  s->head = cur;
+  s->iteration += 1;
+  s->dt_prev = dt;
+  return STAU_OK;
+}
+
+int stau_initial_state(stau_pencils* pen, const double* b_grid, void* X, void* stream) {
+  if (!pen || !b_grid || !X) return fail(STAU_EINVAL, "null argument");
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  HIP_TRY(launch_initial_state(pen->xa1, b_grid, X, pen->scratch, (hipStream_t)stream));
+  return STAU_OK;
+}
+
+int stau_nonlinear(stau_pencils* pen, const void* X, void* F, void* stream) {
+  if (!pen || !X || !F) return fail(STAU_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  RhsArgs r{};
+  r.mode = 0;
+  HIP_TRY(launch_zb(pen->xa, pen->fl, X, pen->G, st));
+  HIP_TRY(launch_xpass(pen->xa, pen->G, pen->H, st));
+  HIP_TRY(launch_zf(pen->xa, pen->H, F, r, st));
+  return STAU_OK;
+}
+
+int stau_solve(stau_pencils* pen, const void* B_ev, void* X, void* stream) {
+  if (!pen || !B_ev || !X) return fail(STAU_EINVAL, "null argument");
+  if (!pen->factored) return fail(STAU_ESTATE, "stau_solve before stau_factor");
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  HIP_TRY(launch_solve(pen->pa, B_ev, pen->Lf, pen->sl, pen->Uf, X, (hipStream_t)stream));
+  return STAU_OK;
+}
+
+__global__ void nonfinite_kernel(const double* x, size_t n, int* flag) {
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) {
+      atomicOr(flag, 1);
+      return;
+    }
+}
+
+int stau_check(stau_pencils* pen, const void* X, void* stream) {
+  if (!pen || !X) return fail(STAU_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  const int zero = 0;
+  HIP_TRY(hipMemcpyAsync(pen->flag, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  const size_t nd = (size_t)pen->dom->P * pen->pa.desc.S * pen->dom->d.Nz * 2;
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(1024), dim3(256), 0, st, (const double*)X, nd,
+                     pen->flag);
+  HIP_TRY(hipGetLastError());
+  int h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, pen->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h) return fail(STAU_ENONFINITE, "state holds non-finite values");
+  return STAU_OK;
+}
+
+int stau_kinetic_energy(stau_pencils* pen, const void* X, double* out, void* stream) {
+  if (!pen || !X || !out) return fail(STAU_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  double* rowmean = (double*)pen->scratch;
+  double* dout = rowmean + pen->xa.M;
+  HIP_TRY(launch_ke(pen->xa, X, pen->G, rowmean, dout, st));
+  HIP_TRY(hipMemcpyAsync(out, dout, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return STAU_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,195 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+FP64 bar: the workload statement asks for 1e-10 relative per field after 100
+steps; component tolerances below are set from the arithmetic (FFT rounding
+~ eps log2 L, banded LU backward error ~ eps * cond).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import RBOracle, RBParams
+from gpu_helpers import field_errors, oracle_solve_from_ev, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1905_10388_amd import RBSolver, StauError  # noqa: E402
+
+# (Nx, Nz, Lx, Ra, Pr, dt)
+C1 = (64, 32, 4.0, 1e4, 1.0, 1e-3)
+SMALL = [C1, (16, 8, 3.0, 2e5, 0.7, 2e-3), (128, 64, 4.0, 1e6, 1.0, 1e-4), (32, 128, 2.0, 1e7, 7.0, 2e-5)]
+
+
+def _pair(cfg, **kw):
+    Nx, Nz, Lx, Ra, Pr, dt = cfg
+    g = RBSolver(Nx, Nz, Lx, Ra, Pr, **kw)
+    o = RBOracle(Nx, Nz, Lx, RBParams(Ra, Pr, **{k: v for k, v in kw.items()
+                                                 if k in ("buoyancy", "b_bottom", "b_top")}))
+    return g, o
+
+
+def _random_state(o, seed, amp=1.0):
+    X = si.complex_noise(o.state_shape, seed) * amp
+    X[0] = X[0].real
+    X[o.Px - 1] = 0
+    decay = np.exp(-np.arange(o.Nz) / (o.Nz / 6.0))
+    return X * decay
+
+
+def _to_dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X)).to("cuda")
+
+
+def _to_np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("cfg", SMALL, ids=lambda c: f"{c[0]}x{c[1]}")
+def test_nonlinear_term_matches_oracle(cfg):
+    g, o = _pair(cfg)
+    X = _random_state(o, 11)
+    Fg = _to_np(g.nonlinear(_to_dev(X)))
+    Fo = o.nonlinear(X)
+    assert rel_err(Fg, Fo) < 1e-13
+    assert np.all(Fg[o.Px - 1] == 0)
+
+
+@pytest.mark.parametrize("cfg", SMALL, ids=lambda c: f"{c[0]}x{c[1]}")
+@pytest.mark.parametrize("sbdf", [1, 2])
+def test_pencil_solve_matches_oracle(cfg, sbdf):
+    g, o = _pair(cfg)
+    dt = cfg[5]
+    a0 = 1.0 / dt if sbdf == 1 else 1.5 / dt
+    g.factor(a0, 1.0)
+    Bev = si.complex_noise(g.ev_shape, 12)
+    Bev[0] = Bev[0].real
+    Xg = _to_np(g.solve(_to_dev(Bev)))
+    Xo = oracle_solve_from_ev(o, Bev, a0, 1.0)
+    errs = field_errors(o, Xg, Xo)
+    assert max(errs.values()) < 1e-11, errs
+    assert np.all(Xg[o.Px - 1] == 0)
+
+
+def test_initial_state_matches_oracle():
+    Nx, Nz, Lx, Ra, Pr, dt = C1
+    g, o = _pair(C1)
+    xi = si.workload_noise((Nx, Nz), 0)
+    bgrid = o.initial_b_grid(xi)
+    Xg = _to_np(g.initial_state(torch.from_numpy(bgrid)))
+    Xo = o.initial_state(xi)
+    _check_initial_state(o, Xg, Xo)
+
+
+def _check_initial_state(o, Xg, Xo):
+    # b: FFT/DCT rounding against direct sums.  bz = d_z b amplifies the
+    # ~eps differences of the high b modes by the norm of the Chebyshev
+    # derivative (~ N^2), so its bound is 20 N^2 eps.
+    eps = np.finfo(float).eps
+    assert rel_err(Xg[..., o.vi["b"], :], Xo[..., o.vi["b"], :]) < 1e-14
+    assert rel_err(Xg[..., o.vi["bz"], :], Xo[..., o.vi["bz"], :]) < 20 * o.Nz ** 2 * eps
+    others = [i for v, i in o.vi.items() if v not in ("b", "bz")]
+    assert np.all(Xg[..., others, :] == 0)
+
+
+@pytest.mark.parametrize("cfg", [C1, (128, 64, 4.0, 1e6, 1.0, 1e-4)], ids=["C1", "128x64"])
+def test_step_trajectory_matches_oracle(cfg):
+    Nx, Nz, Lx, Ra, Pr, dt = cfg
+    steps = 100 if cfg is C1 else 20
+    g, o = _pair(cfg)
+    xi = si.workload_noise((Nx, Nz), 0)
+    Xo = o.initial_state(xi)
+    g.initial_state(torch.from_numpy(o.initial_b_grid(xi)))
+    for _ in range(steps):
+        Xo = o.step(Xo, dt)
+        g.step(dt)
+    Xg = _to_np(g.X)
+    errs = field_errors(o, Xg, Xo)
+    assert max(errs.values()) < 1e-10, errs
+    assert g.iteration == steps
+
+
+def test_variable_timestep_sbdf2():
+    cfg = (32, 16, 4.0, 5e4, 1.0, 1e-3)
+    g, o = _pair(cfg)
+    xi = si.workload_noise((32, 16), 3)
+    Xo = o.initial_state(xi, amp=1e-2)
+    g.initial_state(torch.from_numpy(o.initial_b_grid(xi, amp=1e-2)))
+    for dt in (1e-3, 1e-3, 1.5e-3, 1.5e-3, 0.7e-3, 1e-3):
+        Xo = o.step(Xo, dt)
+        g.step(dt)
+    errs = field_errors(o, _to_np(g.X), Xo)
+    assert max(errs.values()) < 1e-11, errs
+
+
+def test_kinetic_energy_matches_oracle():
+    g, o = _pair(C1)
+    X = _random_state(o, 13, amp=0.1)
+    Jg = g.kinetic_energy(_to_dev(X))
+    Jo = o.kinetic_energy(X)
+    assert abs(Jg - Jo) <= 1e-13 * abs(Jo)
+
+
+def test_singular_pencil_reported():
+    g, o = _pair(C1)
+    with pytest.raises(StauError) as ei:
+        g.factor(0.0, 0.0)          # every entry vanishes
+    assert "ESINGULAR" in str(ei.value)
+    assert g.last_singular_pencil() == 0
+
+
+def test_nonfinite_state_reported():
+    g, o = _pair(C1)
+    X = torch.zeros(g.state_shape, dtype=torch.complex128, device="cuda")
+    g.check(X)
+    X[3, 2, 5] = float("nan")
+    with pytest.raises(StauError) as ei:
+        g.check(X)
+    assert "ENONFINITE" in str(ei.value)
+
+
+def test_rejects_bad_arguments():
+    with pytest.raises(StauError):
+        RBSolver(48, 32, 4.0, 1e4, 1.0)      # Nx not a power of two
+    with pytest.raises(StauError):
+        RBSolver(64, 32, -1.0, 1e4, 1.0)     # negative period
+    g, o = _pair(C1)
+    with pytest.raises(StauError):
+        g.step(-1.0)
+
+
+# --------------------------------------------------------------- full size
+def test_full_size_one_step_sampled_pencils():
+    """Workload at Nx=1024, Nz=256 (Ra=1e8, dt=1e-5): one SBDF1 step from the
+    seeded initial state, compared on sampled pencils (the oracle computes the
+    explicit term everywhere and solves the sampled pencils only)."""
+    Nx, Nz, Lx, Ra, Pr, dt = 1024, 256, 4.0, 1e8, 1.0, 1e-5
+    g, o = _pair((Nx, Nz, Lx, Ra, Pr, dt))
+    xi = si.workload_noise((Nx, Nz), 1)
+    X0 = o.initial_state(xi)
+    g.initial_state(torch.from_numpy(o.initial_b_grid(xi)))
+    _check_initial_state(o, _to_np(g.X), X0)
+    g.set_state(_to_dev(X0))              # step from the oracle's own state
+    g.step(dt)
+    Xg = _to_np(g.X)
+    F = o.nonlinear(X0)
+    a0, a1 = 1.0 / dt, -1.0 / dt
+    sample = [(0,), (1,), (2,), (77,), (256,), (510,), (511,)]
+    Bev = np.zeros((o.Px, o.ne, Nz), complex)
+    for key in sample:
+        M, L = o.pencil_matrices(2 * np.pi * key[0] / Lx, 0.0, key[0] == 0)
+        Ft = o.precondition_rhs(F[key], key[0] == 0)
+        MX = M @ X0[key].reshape(-1)
+        B = Ft - a1 * MX
+        for e in range(o.ne):
+            Bev[key][e, : Nz - 1] = B[e * Nz: e * Nz + Nz - 1]
+    Xo = oracle_solve_from_ev(o, Bev, a0, 1.0, pencils=set(sample))
+    for key in sample:
+        assert rel_err(Xg[key], Xo[key]) < 1e-10, key
+    assert np.all(Xg[o.Px - 1] == 0)
