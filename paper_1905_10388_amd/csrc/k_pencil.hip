@@ -20,6 +20,10 @@ namespace stau {
 constexpr int kWave = 64;
 constexpr int kCW = 64;  // factor column window (>= kv + 1)
 
+// Materialise a loaded value in its register here: the loads it depends on
+// complete before this point and cannot be sunk past it by the scheduler.
+__device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -188,33 +192,53 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
 // built in LDS (two real vectors: the real and imaginary parts), overwritten
 // by y = L^{-1} P b and then by x~ = U^{-1} y; finally X = P^R x~ is written in
 // the state layout with the real scaling undone.
+//
+// Factor data streams through LDS in chunks of CH columns, double buffered:
+// while a chunk is swept, the next one is loaded into registers and stored to
+// the other buffer at the end of the chunk, so HBM latency hides behind the
+// sweep.  FW / BW are compile-time so that window lanes are immediates and
+// the y / x stores provably do not alias the b loads ahead of them.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kWave) solve_kernel(PencilArgs a, const double2* __restrict__ Bev,
-                                                      const double* __restrict__ Lf,
-                                                      const uint8_t* __restrict__ sl,
-                                                      const double* __restrict__ Uf,
-                                                      double2* __restrict__ X) {
+template <int FW, int BW, int CH>
+__global__ void __launch_bounds__(2 * kWave) solve_kernel(PencilArgs a,
+                                                          const double2* __restrict__ Bev,
+                                                          const double* __restrict__ Lf,
+                                                          const uint8_t* __restrict__ sl,
+                                                          const double* __restrict__ Uf,
+                                                          double2* __restrict__ X) {
+  // Two wavefronts per pencil: wave 0 solves for the real part of the
+  // right-hand side, wave 1 for the imaginary part (the real-scaled matrix is
+  // real).  Both share the factor chunks staged in LDS.
+  static_assert(CH % BW == 0 && CH == kWave && (CH * FW) % (2 * kWave) == 0 &&
+                    (CH * BW) % (2 * kWave) == 0,
+                "chunking");
   extern __shared__ double lds[];
   const int p = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // 0: real part, 1: imaginary part
   const int n = a.n, N = a.desc.N, S = a.desc.S, kb = a.desc.kb, ne = a.desc.ne;
-  const int FW = a.FW, BW = a.BW;
   const SysDesc& d = a.desc;
   double2* Xp = X + (size_t)p * S * N;
   if (!pencil_active(a, p)) {
-    for (int i = lane; i < S * N; i += kWave) Xp[i] = make_double2(0.0, 0.0);
+    for (int i = tid; i < S * N; i += 2 * kWave) Xp[i] = make_double2(0.0, 0.0);
     return;
   }
   const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
-  double* br = lds;
-  double* bi = lds + n;
+  const int nch = (n + CH - 1) / CH;
+  const int npad = nch * CH;
+  // right-hand side vectors with BW zeros in front and FW zeros behind, so the
+  // sweeps read their look-ahead / look-behind rows without bounds checks
+  const int span = BW + npad + FW;
+  double* bre = lds + BW;
+  double* bim = lds + span + BW;
+  double* fbuf = lds + 2 * span;  // [2][CH*BW] doubles (U chunks) / [2][CH*FW] (L chunks)
   const double2* Bp = Bev + (size_t)p * ne * N;
-  // --- right-hand side
-  for (int r = lane; r < n; r += kWave) {
+  for (int r = tid - BW; r < npad + FW; r += 2 * kWave) {
     double vr = 0.0, vi = 0.0;
-    if (r < kb) {
+    if (r >= 0 && r < kb) {
       if (pc.mean && d.bc_var[r] == VB) vr = d.bc_side[r] == 0 ? a.b_bottom : a.b_top;
-    } else {
+    } else if (r >= kb && r < n) {
       int epos;
       const int m = sys_row_mode(d, r, &epos);
       const int eq = d.eq_at[epos];
@@ -234,74 +258,152 @@ __global__ void __launch_bounds__(kWave) solve_kernel(PencilArgs a, const double
         }
       }
     }
-    br[r] = vr;
-    bi[r] = vi;
+    bre[r] = vr;
+    bim[r] = vi;
   }
-  __syncthreads();
+  double* b = wv == 0 ? bre : bim;
   const double* Lp = Lf + (size_t)p * n * FW;
-  const uint8_t* sp = sl + (size_t)p * n;
+  const uint32_t* sw = (const uint32_t*)(sl + (size_t)p * n);  // n % 4 == 0 (4-byte aligned)
   const double* Up = Uf + (size_t)p * n * BW;
-  // --- forward sweep: window of FW pending rows in lanes 0..FW-1
-  double wr = 0.0, wi = 0.0;
-  if (lane < FW && lane < n) {
-    wr = br[lane];
-    wi = bi[lane];
-  }
-  for (int j = 0; j < n; ++j) {
-    const int s = __builtin_amdgcn_readfirstlane((int)sp[j]);
-    const double lj = lane < FW ? Lp[(size_t)j * FW + lane] : 0.0;
-    const double yr = readlane_d(wr, s);
-    const double yi = readlane_d(wi, s);
-    if (lane == s) {
-      br[j] = yr;
-      bi[j] = yi;
+
+  // ---- forward sweep: window of FW pending rows, physical slots 0..FW-1 ----
+  constexpr int LPT = CH * FW / (2 * kWave);
+  constexpr int G = 16;  // insert values preloaded per group of columns
+  double regL[LPT];
+  uint32_t regS = 0;
+  uint32_t* sbuf = (uint32_t*)(fbuf + 2 * CH * BW);  // [2][CH/4] words
+  auto loadL = [&](int c) {
+    const int base = c * CH * FW, lim = n * FW;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const int idx = tid + k * 2 * kWave;
+      regL[k] = base + idx < lim ? Lp[base + idx] : 0.0;
     }
-    wr = fma(-lj, yr, wr);
-    wi = fma(-lj, yi, wi);
-    if (lane == s) {
-      const int r = j + FW;
-      wr = r < n ? br[r] : 0.0;
-      wi = r < n ? bi[r] : 0.0;
-    }
-  }
+    const int w4 = c * (CH / 4) + tid;
+    regS = (tid < CH / 4 && 4 * w4 < n) ? sw[w4] : 0u;
+  };
+  auto storeL = [&](int buf) {
+    double* dst = fbuf + buf * CH * BW;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) dst[tid + k * 2 * kWave] = regL[k];
+    if (tid < CH / 4) sbuf[buf * (CH / 4) + tid] = regS;
+  };
+  loadL(0);
+  storeL(0);
   __syncthreads();
-  // --- backward sweep: lane l carries the row r = l (mod BW) of [j-BW+1, j]
-  wr = 0.0;
-  wi = 0.0;
-  if (lane < BW) {
-    const int r = (n - 1) - (((n - 1 - lane) % BW) + BW) % BW;
-    if (r >= 0) {
-      wr = br[r];
-      wi = bi[r];
+  const int lf = lane & (FW - 1);
+  double w = lane < FW ? b[lane] : 0.0;
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) loadL(c + 1);
+    const int j0 = c * CH;
+    const double* Lc = fbuf + (c & 1) * CH * BW + lf;
+    const uint32_t* Sc = sbuf + (c & 1) * (CH / 4);
+    uint32_t sword[CH / 4];
+#pragma unroll
+    for (int k = 0; k < CH / 4; ++k) sword[k] = __builtin_amdgcn_readfirstlane(Sc[k]);
+    double lc[CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) lc[t] = Lc[t * FW];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) pin(lc[t]);
+    double* yo = b + j0;
+    double nv[2][G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) nv[0][k] = yo[k + FW];
+#pragma unroll
+    for (int k = 0; k < G; ++k) pin(nv[0][k]);
+#pragma unroll
+    for (int g = 0; g < CH / G; ++g) {
+      if (g + 1 < CH / G) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) nv[(g + 1) & 1][k] = yo[(g + 1) * G + k + FW];
+      }
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int t = g * G + k;
+        const int s = (sword[t >> 2] >> (8 * (t & 3))) & 0xff;
+        const double y = readlane_d(w, s);
+        yo[t] = y;  // every lane stores the same value
+        w = lane == s ? nv[g & 1][k] : fma(-lc[t], y, w);
+      }
+      if (g + 1 < CH / G) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) pin(nv[(g + 1) & 1][k]);
+      }
     }
+    if (c + 1 < nch) storeL((c + 1) & 1);
+    __syncthreads();
   }
-  for (int j = n - 1; j >= 0; --j) {
-    const int sj = j % BW;
-    const double u = lane < BW ? Up[(size_t)j * BW + lane] : 0.0;
-    const double xr = readlane_d(wr * u, sj);
-    const double xi = readlane_d(wi * u, sj);
-    if (lane == sj) {
-      br[j] = xr;
-      bi[j] = xi;
+
+  // ---- backward sweep: lane l carries the row r = l (mod BW) of [j-BW+1, j]
+  constexpr int UPT = CH * BW / (2 * kWave);
+  double regU[UPT];
+  auto loadU = [&](int c) {
+    const int base = c * CH * BW, lim = n * BW;
+#pragma unroll
+    for (int k = 0; k < UPT; ++k) {
+      const int idx = tid + k * 2 * kWave;
+      regU[k] = base + idx < lim ? Up[base + idx] : 0.0;
     }
-    wr = fma(-u, xr, wr);
-    wi = fma(-u, xi, wi);
-    if (lane == sj) {
-      const int r = j - BW;
-      wr = r >= 0 ? br[r] : 0.0;
-      wi = r >= 0 ? bi[r] : 0.0;
-    }
-  }
+  };
+  auto storeU = [&](int buf) {
+    double* dst = fbuf + buf * CH * BW;
+#pragma unroll
+    for (int k = 0; k < UPT; ++k) dst[tid + k * 2 * kWave] = regU[k];
+  };
+  loadU(nch - 1);
+  storeU((nch - 1) & 1);
   __syncthreads();
+  const int lb = lane & (BW - 1);
+  // rows npad-BW .. npad-1 (rows >= n hold finite padding; their U
+  // coefficients are zero)
+  w = b[npad - BW + lb];
+  for (int c = nch - 1; c >= 0; --c) {
+    if (c > 0) loadU(c - 1);
+    const double* Uc = fbuf + (c & 1) * CH * BW + lb;
+    double uc[CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) uc[t] = Uc[t * BW];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) pin(uc[t]);
+    double* xo = b + c * CH;
+    constexpr int NG = CH / G;
+    double nv[2][G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) nv[(NG - 1) & 1][k] = xo[(NG - 1) * G + k - BW];
+#pragma unroll
+    for (int k = 0; k < G; ++k) pin(nv[(NG - 1) & 1][k]);
+#pragma unroll
+    for (int g = NG - 1; g >= 0; --g) {
+      if (g > 0) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) nv[(g - 1) & 1][k] = xo[(g - 1) * G + k - BW];
+      }
+#pragma unroll
+      for (int k = G - 1; k >= 0; --k) {
+        const int t = g * G + k;
+        const int sj = t % BW;
+        const double x = readlane_d(w * uc[t], sj);
+        xo[t] = x;  // every lane stores the same value
+        w = lb == sj ? nv[g & 1][k] : fma(-uc[t], x, w);
+      }
+      if (g > 0) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) pin(nv[(g - 1) & 1][k]);
+      }
+    }
+    if (c > 0) storeU((c - 1) & 1);
+    __syncthreads();
+  }
   // --- X = P^R x~, undo the real scaling, state layout
-  for (int i = lane; i < S * N; i += kWave) {
+  for (int i = tid; i < S * N; i += 2 * kWave) {
     const int vabi = i / N, m = i - vabi * N;
     const int var = a.var_of_abi[vabi];
     const int pos = d.var_pos[var];
-    double xr = br[m * S + pos], xi = bi[m * S + pos];
+    double xr = bre[m * S + pos], xi = bim[m * S + pos];
     if (m + 2 < N) {
-      xr -= br[(m + 2) * S + pos];
-      xi -= bi[(m + 2) * S + pos];
+      xr -= bre[(m + 2) * S + pos];
+      xi -= bim[(m + 2) * S + pos];
     }
     if (var == VU || var == VUZ || var == VV || var == VVZ)
       Xp[i] = make_double2(xi, -xr);  // u = -i u~
@@ -321,15 +423,29 @@ hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, 
   return hipGetLastError();
 }
 
+constexpr int kCH = 64;
+
+template <int FW, int BW>
+static hipError_t launch_solve_t(const PencilArgs& a, const void* Bev, const double* Lf,
+                                 const uint8_t* sl, const double* Uf, void* X, hipStream_t st) {
+  const int npad = (a.n + kCH - 1) / kCH * kCH;
+  size_t lds = (size_t)(2 * (BW + npad + FW) + 2 * kCH * BW) * sizeof(double) + 2 * kCH;
+  auto fn = solve_kernel<FW, BW, kCH>;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(fn, dim3(a.P), dim3(2 * kWave), lds, st, a, (const double2*)Bev, Lf, sl, Uf,
+                     (double2*)X);
+  return hipGetLastError();
+}
+
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
                         const double* Uf, void* X, hipStream_t st) {
-  size_t lds = (size_t)2 * a.n * sizeof(double);
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-  hipLaunchKernelGGL(solve_kernel, dim3(a.P), dim3(kWave), lds, st, a,
-                     (const double2*)Bev, Lf, sl, Uf, (double2*)X);
-  return hipGetLastError();
+  if (a.FW == 8 && a.BW == 32) return launch_solve_t<8, 32>(a, Bev, Lf, sl, Uf, X, st);
+  if (a.FW == 8 && a.BW == 64) return launch_solve_t<8, 64>(a, Bev, Lf, sl, Uf, X, st);
+  if (a.FW == 16 && a.BW == 32) return launch_solve_t<16, 32>(a, Bev, Lf, sl, Uf, X, st);
+  if (a.FW == 16 && a.BW == 64) return launch_solve_t<16, 64>(a, Bev, Lf, sl, Uf, X, st);
+  if (a.FW == 32 && a.BW == 64) return launch_solve_t<32, 64>(a, Bev, Lf, sl, Uf, X, st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace stau

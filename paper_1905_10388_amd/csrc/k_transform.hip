@@ -182,14 +182,15 @@ __global__ void __launch_bounds__(256) zf_kernel(XformArgs a, const double2* __r
 // and two real-to-complex transforms, truncated to k < Nx/2 and scaled 1/L.
 // G field order: u, w, b_x, b_z, u_x, u_z, w_x, w_z.
 // ---------------------------------------------------------------------------
-template <int MAXBF, int PTS>
-__global__ void __launch_bounds__(1024) xpass_kernel(XformArgs a, const double2* __restrict__ G,
-                                                     double2* __restrict__ H) {
+template <int MAXBF, int PTS, int NT>
+__global__ void __launch_bounds__(NT) xpass_kernel(XformArgs a, const double2* __restrict__ G,
+                                                   double2* __restrict__ H) {
   extern __shared__ double2 smem[];
   cd* buf = (cd*)smem;
   const int jz = blockIdx.x;
   const int M = a.M, L = a.L, Pa = a.Pa, P = a.P;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nt = NT;
   const cd* tw = (const cd*)a.twx;
 
   auto c2r_pair = [&](int fa, int fb, double* ra, double* rb) {
@@ -424,13 +425,24 @@ static void allow_lds(const void* fn, size_t bytes) {
   if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st) {
-  const int nt = x_threads(a.L);
+template <int NT>
+static hipError_t launch_xpass_t(const XformArgs& a, const void* G, void* H, hipStream_t st) {
   size_t lds = (size_t)a.L * sizeof(double2);
-  allow_lds((const void*)xpass_kernel<2, 6>, lds);
-  hipLaunchKernelGGL((xpass_kernel<2, 6>), dim3(a.M), dim3(nt), lds, st, a, (const double2*)G,
+  allow_lds((const void*)xpass_kernel<2, 6, NT>, lds);
+  hipLaunchKernelGGL((xpass_kernel<2, 6, NT>), dim3(a.M), dim3(NT), lds, st, a, (const double2*)G,
                      (double2*)H);
   return hipGetLastError();
+}
+
+hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st) {
+  switch (x_threads(a.L)) {
+    case 64: return launch_xpass_t<64>(a, G, H, st);
+    case 128: return launch_xpass_t<128>(a, G, H, st);
+    case 256: return launch_xpass_t<256>(a, G, H, st);
+    case 512: return launch_xpass_t<512>(a, G, H, st);
+    case 1024: return launch_xpass_t<1024>(a, G, H, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_initial_state(const XformArgs& a1, const double* bgrid, void* X, void* work,

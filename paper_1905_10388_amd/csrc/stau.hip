@@ -334,9 +334,10 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   pen->n = (int64_t)pa.desc.S * N;
   pa.n = (int)pen->n;
   band_widths(pa.desc, pen->n, &pa.kl, &pa.ku);
-  pa.FW = pa.kl + 1;
+  // window widths of the solve (compile-time variants 8/16/32 and 32/64)
+  pa.FW = pa.kl + 1 <= 8 ? 8 : (pa.kl + 1 <= 16 ? 16 : 32);
   pa.BW = (pa.kl + pa.ku + 1 <= 32) ? 32 : 64;
-  if (pa.FW > 64 || pa.kl + pa.ku + 1 > 64) {
+  if (pa.kl + 1 > 32 || pa.kl + pa.ku + 1 > 64 || (pa.FW == 32 && pa.BW == 32)) {
     free_pencils(pen);
     delete pen;
     return fail(STAU_EUNSUPPORTED, "band too wide (kl=%d, ku=%d)", pa.kl, pa.ku);
