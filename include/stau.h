@@ -182,6 +182,46 @@ int stau_check(stau_pencils* pen, const void* X, void* stream);
  * (Sec. VII "Integration"); result written to *out (host) after a sync. */
 int stau_kinetic_energy(stau_pencils* pen, const void* X, double* out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Discrete adjoint.  The adjoint of a complex coefficient z is
+ * dJ/dRe z + i dJ/dIm z (coefficients are pairs of independent reals), so a
+ * complex-linear map y = A x has x_bar = A^H y_bar.
+ * ------------------------------------------------------------------------ */
+
+/* Adjoint state, caller owned.
+ * Xbar  device complex128, state layout: on entry the adjoint of X^n, on exit
+ *       the adjoint of X^{n-1} (overwritten in place).
+ * hbar  device complex128 [P][2][ne][Nz]: adjoints of the history entries
+ *       (F~ and M~X of step n-1) pending from the step after; zero before the
+ *       last step is reversed; on exit, those of step n-2. */
+typedef struct stau_adjstate {
+  void* Xbar;
+  void* hbar;
+} stau_adjstate;
+
+/* Reverse of one stau_step (the exact derivative of the discrete forward
+ * map): X_prev is the state X^{n-1} the forward step started from (device,
+ * state layout), iteration the forward step's st->iteration (0: SBDF1), dt
+ * and dt_prev its timesteps.  Computes, per pencil,
+ *   B_bar = A^{-H} X_bar (transposed banded solve with the stored factors),
+ *   F~_bar = c1 B_bar + pending, M~X_bar = -a1 B_bar + pending,
+ *   X_bar^{n-1} = M^H M~X_bar + N'(X^{n-1})^H (P^L)^H F~_bar
+ * where N' is the linearised explicit term (adjoint transforms and products on
+ * the 3/2 grid).  Uses cached factors of (a0, b0), refactoring synchronously
+ * if neither stored factorisation matches.  Sec. IX (IVP, multistep IMEX) is
+ * the forward operation; the adjoint is not part of the paper. */
+int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, double dt,
+                      double dt_prev, stau_adjstate* adj, void* stream);
+
+/* Xbar (device, state layout, written entirely) = dJ/dX of the kinetic-energy
+ * functional of stau_kinetic_energy at the state X. */
+int stau_kinetic_energy_adjoint(stau_pencils* pen, const void* X, void* Xbar, void* stream);
+
+/* Adjoint of stau_initial_state: b_grid_bar (device float64, layout of the b
+ * grid, written entirely) = dJ/d b_grid given Xbar = dJ/dX^0. */
+int stau_initial_state_adjoint(stau_pencils* pen, const void* Xbar, double* b_grid_bar,
+                               void* stream);
+
 /* Measurement hook: when enabled, every kernel launched by stau_step and
  * stau_factor is bracketed by two HIP events recorded on the call's stream.
  * stau_read_kernel_timing synchronises on those events, writes the summed

@@ -151,6 +151,49 @@ class RBSolver:
         _lib.check(self.lib.stau_read_kernel_timing(self._pen, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KERNEL_KINDS)}
 
+    # -- adjoint ------------------------------------------------------------
+    def snapshot(self):
+        """Checkpoint of the multistep state (device copies + step counters)."""
+        return (self.X.clone(), self.hist.clone(), int(self._st.iteration),
+                float(self._st.dt_prev), int(self._st.head))
+
+    def restore(self, snap):
+        X, hist, it, dtp, head = snap
+        self.X.copy_(X)
+        self.hist.copy_(hist)
+        self._st.iteration, self._st.dt_prev, self._st.head = it, dtp, head
+
+    def new_adjoint_state(self):
+        t = self._torch
+        Xbar = t.zeros(self.state_shape, dtype=t.complex128, device=self.device)
+        hbar = t.zeros((self.info["P"], 2, self.info["ne"], self.info["Nz"]),
+                       dtype=t.complex128, device=self.device)
+        return Xbar, hbar
+
+    def adjoint_step(self, X_prev, iteration: int, dt: float, dt_prev: float, Xbar, hbar):
+        """Reverse one forward step in place on (Xbar, hbar)."""
+        adj = _lib.AdjStateC(Xbar=Xbar.data_ptr(), hbar=hbar.data_ptr())
+        _lib.check(self.lib.stau_adjoint_step(self._pen, _ptr(X_prev.contiguous()), int(iteration),
+                                              float(dt), float(dt_prev), C.byref(adj),
+                                              _stream_ptr()))
+
+    def kinetic_energy_adjoint(self, X=None):
+        t = self._torch
+        Xs = (self.X if X is None else X).contiguous()
+        Xbar = t.empty(self.state_shape, dtype=t.complex128, device=self.device)
+        _lib.check(self.lib.stau_kinetic_energy_adjoint(self._pen, _ptr(Xs), _ptr(Xbar),
+                                                        _stream_ptr()))
+        return Xbar
+
+    def initial_state_adjoint(self, Xbar):
+        t = self._torch
+        i = self.info
+        shape = (i["Nx"], i["Nz"]) if self.dim == 2 else (i["Nx"], i["Ny"], i["Nz"])
+        g = t.empty(shape, dtype=t.float64, device=self.device)
+        _lib.check(self.lib.stau_initial_state_adjoint(self._pen, _ptr(Xbar.contiguous()), _ptr(g),
+                                                       _stream_ptr()))
+        return g
+
     def check(self, X=None):
         Xs = self.X if X is None else X
         _lib.check(self.lib.stau_check(self._pen, _ptr(Xs), _stream_ptr()))

@@ -26,7 +26,8 @@ EXPORTS = (
     "stau_create_domain", "stau_destroy_domain", "stau_build_pencils", "stau_destroy_pencils",
     "stau_query", "stau_factor", "stau_last_singular_pencil", "stau_step", "stau_initial_state",
     "stau_nonlinear", "stau_solve", "stau_check", "stau_kinetic_energy", "stau_last_error",
-    "stau_set_kernel_timing", "stau_read_kernel_timing",
+    "stau_set_kernel_timing", "stau_read_kernel_timing", "stau_adjoint_step",
+    "stau_kinetic_energy_adjoint", "stau_initial_state_adjoint",
 )
 KERNEL_KINDS = ("z_backward", "x_pass", "z_forward_rhs", "pencil_solve", "pencil_factor")
 
@@ -45,6 +46,10 @@ class RBParamsC(C.Structure):
 class StateC(C.Structure):
     _fields_ = [("X", C.c_void_p), ("hist", C.c_void_p), ("iteration", C.c_int64),
                 ("dt_prev", C.c_double), ("head", C.c_int32), ("reserved", C.c_int32)]
+
+
+class AdjStateC(C.Structure):
+    _fields_ = [("Xbar", C.c_void_p), ("hbar", C.c_void_p)]
 
 
 class InfoC(C.Structure):
@@ -88,6 +93,9 @@ def load(path: str = LIB_PATH):
         "stau_kinetic_energy": (i32, [vp, vp, C.POINTER(dbl), vp]),
         "stau_last_error": (C.c_char_p, []),
         "stau_set_kernel_timing": (i32, [vp, i32]),
+        "stau_adjoint_step": (i32, [vp, vp, i64, dbl, dbl, C.POINTER(AdjStateC), vp]),
+        "stau_kinetic_energy_adjoint": (i32, [vp, vp, vp, vp]),
+        "stau_initial_state_adjoint": (i32, [vp, vp, vp, vp]),
         "stau_read_kernel_timing": (i32, [vp, C.POINTER(dbl), C.POINTER(i64), i32]),
     }
     for name, (res, args) in sig.items():

@@ -412,6 +412,223 @@ __global__ void __launch_bounds__(2 * kWave) solve_kernel(PencilArgs a,
   }
 }
 
+// Sum over aligned groups of W lanes (W a power of two <= 64); every lane of
+// a group receives the group sum.
+template <int W>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int off = W / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Transposed solve (adjoint of solve_kernel): B_bar = S_L^H A~^{-T} S_R^H
+// (P^R)^T X_bar, where A~ is the real-scaled recombined matrix, S_R the
+// column scaling (u = -i u~) and S_L the row scaling (u rows times i).  The
+// two sweeps are the exact reverses of the forward register-window sweeps on
+// the same factor storage:
+//   U^T (columns ascending): y_bar[j-BW] = W[sj];  x_tot = x_bar_j -
+//       sum_{l != sj} U_rot[j][l] W[l];  W[sj] = rinv_j x_tot;
+//   L^T (columns descending): b_bar[j+FW] = W[s_j];  W[s_j] = y_bar_j -
+//       sum_l L_phys[j][l] W[l].
+// Epilogue (per pencil): the multistep history adjoints,
+//   F~_bar = c1 B_bar + hF,  MX_bar = -a1 B_bar + hM,  hF <- c2 B_bar,
+//   hM <- -a2 B_bar,  F_bar = (P^L)^T F~_bar,  X_bar_out = (P^L)^T MX_bar on
+//   the evolved variables, zero elsewhere.
+// ---------------------------------------------------------------------------
+template <int FW, int BW, int CH>
+__global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
+                                                           const double2* __restrict__ Xin,
+                                                           const double* __restrict__ Lf,
+                                                           const uint8_t* __restrict__ sl,
+                                                           const double* __restrict__ Uf,
+                                                           double2* Xout, AdjRhsArgs r) {
+  static_assert(CH % BW == 0 && CH == kWave && (CH * FW) % (2 * kWave) == 0 &&
+                    (CH * BW) % (2 * kWave) == 0,
+                "chunking");
+  extern __shared__ double lds[];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = a.n, N = a.desc.N, S = a.desc.S, kb = a.desc.kb, ne = a.desc.ne;
+  const SysDesc& d = a.desc;
+  const double2* Xp = Xin + (size_t)p * S * N;
+  double2* Xo = Xout + (size_t)p * S * N;
+  double2* Fb = r.Fbar + (size_t)p * ne * N;
+  double2* hb = r.hbar + (size_t)p * 2 * ne * N;
+  if (!pencil_active(a, p)) {
+    __syncthreads();
+    for (int i = tid; i < S * N; i += 2 * kWave) Xo[i] = make_double2(0.0, 0.0);
+    for (int i = tid; i < ne * N; i += 2 * kWave) Fb[i] = make_double2(0.0, 0.0);
+    for (int i = tid; i < 2 * ne * N; i += 2 * kWave) hb[i] = make_double2(0.0, 0.0);
+    return;
+  }
+  const int nch = (n + CH - 1) / CH;
+  const int npad = nch * CH;
+  const int span = BW + npad + FW;
+  double* bre = lds + BW;
+  double* bim = lds + span + BW;
+  double* fbuf = lds + 2 * span;
+  uint32_t* sbuf = (uint32_t*)(fbuf + 2 * CH * BW);
+  // x~_bar = S_R^H (P^R)^T X_bar in system column order
+  for (int c = tid - BW; c < npad + FW; c += 2 * kWave) {
+    double vr = 0.0, vi = 0.0;
+    if (c >= 0 && c < n) {
+      const int m = c / S, pos = c - m * S;
+      const int var = d.var_at[pos];
+      const int vabi = d.abi_index[var];
+      double2 v = Xp[(size_t)vabi * N + m];
+      if (m >= 2) {
+        const double2 w2 = Xp[(size_t)vabi * N + m - 2];
+        v.x -= w2.x;
+        v.y -= w2.y;
+      }
+      if (var == VU || var == VUZ || var == VV || var == VVZ) {
+        vr = -v.y;  // i v
+        vi = v.x;
+      } else {
+        vr = v.x;
+        vi = v.y;
+      }
+    }
+    bre[c] = vr;
+    bim[c] = vi;
+  }
+  double* b = wv == 0 ? bre : bim;
+  const double* Lp = Lf + (size_t)p * n * FW;
+  const uint32_t* sw = (const uint32_t*)(sl + (size_t)p * n);
+  const double* Up = Uf + (size_t)p * n * BW;
+
+  // ---- U^T sweep (ascending) ---------------------------------------------
+  constexpr int UPT = CH * BW / (2 * kWave);
+  double regU[UPT];
+  auto loadU = [&](int c) {
+    const int base = c * CH * BW, lim = n * BW;
+#pragma unroll
+    for (int k = 0; k < UPT; ++k) {
+      const int idx = tid + k * 2 * kWave;
+      regU[k] = base + idx < lim ? Up[base + idx] : 0.0;
+    }
+  };
+  auto storeU = [&](int buf) {
+    double* dst = fbuf + buf * CH * BW;
+#pragma unroll
+    for (int k = 0; k < UPT; ++k) dst[tid + k * 2 * kWave] = regU[k];
+  };
+  loadU(0);
+  storeU(0);
+  __syncthreads();
+  const int lb = lane & (BW - 1);
+  double w = 0.0;
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) loadU(c + 1);
+    const double* Uc = fbuf + (c & 1) * CH * BW + lb;
+    double* xo = b + c * CH;
+#pragma unroll 8
+    for (int t = 0; t < CH; ++t) {
+      const int sj = t % BW;
+      const double u = Uc[t * BW];
+      const double xin = xo[t];
+      const double wsj = readlane_d(w, sj);
+      xo[t - BW] = wsj;  // y_bar[j - BW]; every lane stores the same value
+      const bool mine = lb == sj;
+      const double dot = group_sum<BW>(mine ? 0.0 : u * w);
+      const double xt = xin - dot;
+      w = mine ? u * xt : w;
+    }
+    if (c + 1 < nch) storeU((c + 1) & 1);
+    __syncthreads();
+  }
+  if (lane < BW) b[npad - BW + lane] = w;
+  __syncthreads();
+
+  // ---- L^T sweep (descending) --------------------------------------------
+  constexpr int LPT = CH * FW / (2 * kWave);
+  double regL[LPT];
+  uint32_t regS = 0;
+  auto loadL = [&](int c) {
+    const int base = c * CH * FW, lim = n * FW;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const int idx = tid + k * 2 * kWave;
+      regL[k] = base + idx < lim ? Lp[base + idx] : 0.0;
+    }
+    const int w4 = c * (CH / 4) + tid;
+    regS = (tid < CH / 4 && 4 * w4 < n) ? sw[w4] : 0u;
+  };
+  auto storeL = [&](int buf) {
+    double* dst = fbuf + buf * CH * BW;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) dst[tid + k * 2 * kWave] = regL[k];
+    if (tid < CH / 4) sbuf[buf * (CH / 4) + tid] = regS;
+  };
+  loadL(nch - 1);
+  storeL((nch - 1) & 1);
+  __syncthreads();
+  const int lf = lane & (FW - 1);
+  w = 0.0;
+  for (int c = nch - 1; c >= 0; --c) {
+    if (c > 0) loadL(c - 1);
+    const double* Lc = fbuf + (c & 1) * CH * BW + lf;
+    const uint32_t* Sc = sbuf + (c & 1) * (CH / 4);
+    double* yo = b + c * CH;
+#pragma unroll 8
+    for (int t = CH - 1; t >= 0; --t) {
+      const int s = (__builtin_amdgcn_readfirstlane(Sc[t >> 2]) >> (8 * (t & 3))) & 0xff;
+      const double lj = Lc[t * FW];
+      const double yin = yo[t];
+      const double wsj = readlane_d(w, s);
+      yo[t + FW] = wsj;  // b_bar[j + FW]
+      const double dot = group_sum<FW>(lane < FW ? lj * w : 0.0);
+      w = lane == s ? yin - dot : w;
+    }
+    if (c > 0) storeL((c - 1) & 1);
+    __syncthreads();
+  }
+  if (lane < FW) b[lane] = w;
+  __syncthreads();
+
+  // ---- epilogue: history adjoints, (P^L)^T, state-layout outputs --------------
+  auto bbar = [&](int e, int m) -> double2 {
+    if (m < 0 || m > N - 2) return make_double2(0.0, 0.0);
+    const int eq = e == 0 ? EB : (e == ne - 1 ? EW : (e == 1 ? EU : EV));
+    const int row = kb + m * S + d.eq_pos[eq];
+    const double vr = bre[row], vi = bim[row];
+    if (eq == EU || eq == EV) return make_double2(vi, -vr);  // -i v
+    return make_double2(vr, vi);
+  };
+  for (int i = tid; i < ne * N; i += 2 * kWave) {
+    const int e = i / N, m = i - e * N;
+    const size_t hF = ((size_t)0 * ne + e) * N, hM = ((size_t)1 * ne + e) * N;
+    auto ft = [&](int q) -> double2 {  // F~_bar_q
+      if (q < 0 || q > N - 2) return make_double2(0.0, 0.0);
+      const double2 bb = bbar(e, q), h = hb[hF + q];
+      return make_double2(r.c1 * bb.x + h.x, r.c1 * bb.y + h.y);
+    };
+    auto mx = [&](int q) -> double2 {  // MX_bar_q
+      if (q < 0 || q > N - 2) return make_double2(0.0, 0.0);
+      const double2 bb = bbar(e, q), h = hb[hM + q];
+      return make_double2(-r.a1 * bb.x + h.x, -r.a1 * bb.y + h.y);
+    };
+    const double cm = m == 0 ? 1.0 : 0.5;
+    const double2 f0 = ft(m), f2 = ft(m - 2), x0 = mx(m), x2 = mx(m - 2);
+    Fb[(size_t)e * N + m] = make_double2(cm * f0.x - 0.5 * f2.x, cm * f0.y - 0.5 * f2.y);
+    Xo[(size_t)(e + 1) * N + m] = make_double2(cm * x0.x - 0.5 * x2.x, cm * x0.y - 0.5 * x2.y);
+  }
+  for (int i = tid; i < S * N; i += 2 * kWave) {
+    const int v = i / N;
+    if (v == 0 || v > ne) Xo[i] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int i = tid; i < ne * N; i += 2 * kWave) {
+    const int e = i / N, m = i - e * N;
+    const double2 bb = bbar(e, m);
+    hb[((size_t)0 * ne + e) * N + m] = make_double2(r.c2 * bb.x, r.c2 * bb.y);
+    hb[((size_t)1 * ne + e) * N + m] = make_double2(-r.a2 * bb.x, -r.a2 * bb.y);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -445,6 +662,30 @@ hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, 
   if (a.FW == 16 && a.BW == 32) return launch_solve_t<16, 32>(a, Bev, Lf, sl, Uf, X, st);
   if (a.FW == 16 && a.BW == 64) return launch_solve_t<16, 64>(a, Bev, Lf, sl, Uf, X, st);
   if (a.FW == 32 && a.BW == 64) return launch_solve_t<32, 64>(a, Bev, Lf, sl, Uf, X, st);
+  return hipErrorInvalidValue;
+}
+
+template <int FW, int BW>
+static hipError_t launch_solveT_t(const PencilArgs& a, const void* Xin, const double* Lf,
+                                  const uint8_t* sl, const double* Uf, void* Xout,
+                                  const AdjRhsArgs& r, hipStream_t st) {
+  const int npad = (a.n + kCH - 1) / kCH * kCH;
+  size_t lds = (size_t)(2 * (BW + npad + FW) + 2 * kCH * BW) * sizeof(double) + 2 * kCH;
+  auto fn = solveT_kernel<FW, BW, kCH>;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(fn, dim3(a.P), dim3(2 * kWave), lds, st, a, (const double2*)Xin, Lf, sl, Uf,
+                     (double2*)Xout, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_solveT(const PencilArgs& a, const void* Xin, const double* Lf, const uint8_t* sl,
+                         const double* Uf, void* Xout, const AdjRhsArgs& r, hipStream_t st) {
+  if (a.FW == 8 && a.BW == 32) return launch_solveT_t<8, 32>(a, Xin, Lf, sl, Uf, Xout, r, st);
+  if (a.FW == 8 && a.BW == 64) return launch_solveT_t<8, 64>(a, Xin, Lf, sl, Uf, Xout, r, st);
+  if (a.FW == 16 && a.BW == 32) return launch_solveT_t<16, 32>(a, Xin, Lf, sl, Uf, Xout, r, st);
+  if (a.FW == 16 && a.BW == 64) return launch_solveT_t<16, 64>(a, Xin, Lf, sl, Uf, Xout, r, st);
+  if (a.FW == 32 && a.BW == 64) return launch_solveT_t<32, 64>(a, Xin, Lf, sl, Uf, Xout, r, st);
   return hipErrorInvalidValue;
 }
 

@@ -51,8 +51,9 @@ __global__ void __launch_bounds__(256) zb_kernel(XformArgs a, FieldList fl,
   cd* buf = (cd*)smem;
   const int f = blockIdx.y;
   const int p0 = blockIdx.x * TP;
-  const int M = a.M, N = a.N, S = a.S;
+  const int M = a.M, N = a.N, S = fl.src_S ? fl.src_S : a.S;
   const int var = fl.var[f], der = fl.deriv[f];
+  const double wfac = fl.wmode ? 2.0 / (double)M : 1.0;  // (2 - delta_n0) / M, n > 0
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int idx = tid; idx < TP * M; idx += nt) {
     const int s = idx / M, nn = idx - s * M;
@@ -68,7 +69,8 @@ __global__ void __launch_bounds__(256) zb_kernel(XformArgs a, FieldList fl,
         cd c = ld2(col + m);
         if (der) c = mk(-kk * c.y, kk * c.x);  // i k c
         double s1 = (m & 1) ? -1.0 : 1.0;      // T_n on the ascending grid
-        if (m > 0) s1 *= 0.5;
+        if (m > 0) s1 *= 0.5 * wfac;
+        else if (fl.wmode) s1 = 1.0 / (double)M;
         return scale(c, s1);
       };
       cd yn = Yp(nn);
@@ -389,6 +391,324 @@ __global__ void ke_sum_kernel(const double2* __restrict__ c, int N, double* out)
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// ===========================================================================
+// Adjoint kernels.  Complex coefficients are pairs of independent reals; the
+// adjoint of z is dJ/dRe z + i dJ/dIm z.  Real-grid adjoints are real.
+// ===========================================================================
+
+// Adjoint of the backward z transform (c -> g_j = sum_n c_n T_n(z_j), with
+// c optionally multiplied by i k): c_bar_n += conj(i k) sum_j T_n(z_j) g_bar_j,
+// i.e. an unweighted DCT-II per source field, summed per target variable and
+// accumulated into Xbar[p][var][n].
+template <int MAXBF, int MAXIT>
+__global__ void __launch_bounds__(256) zadj_kernel(XformArgs a, AccList al,
+                                                   const double2* __restrict__ Gb,
+                                                   double2* __restrict__ Xb, int TP) {
+  extern __shared__ double2 smem[];
+  cd* buf = (cd*)smem;
+  const int ti = blockIdx.y;
+  const int p0 = blockIdx.x * TP;
+  const int M = a.M, N = a.N, S = a.S;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  cd acc[MAXIT];
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) acc[it] = mk(0.0, 0.0);
+  for (int q = 0; q < al.nsrc[ti]; ++q) {
+    const int f = al.src[ti][q], der = al.deriv[ti][q];
+    for (int idx = tid; idx < TP * M; idx += nt) {
+      const int jz = idx / TP, s = idx - jz * TP;
+      const int p = p0 + s;
+      cd y = mk(0.0, 0.0);
+      if (p < a.P) y = ld2(Gb + ((size_t)f * M + jz) * a.P + p);
+      const int dst = (jz & 1) ? (M - 1 - (jz >> 1)) : (jz >> 1);
+      buf[s * M + dst] = y;
+    }
+    __syncthreads();
+    fft_lds<-1, MAXBF>(buf, M, TP, (const cd*)a.twz, tid, nt);
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+      const int idx = tid + it * nt;
+      if (idx < TP * N) {
+        const int s = idx / N, nn = idx - s * N;
+        const int p = p0 + s;
+        cd V = buf[s * M + nn];
+        cd Vm = buf[s * M + (nn == 0 ? 0 : M - nn)];
+        cd w = conj(ld2(a.dctz + nn));
+        cd P = cmul(w, V), Q = cmul(w, conj(Vm));
+        cd Y = mk(0.5 * (P.x + Q.x), 0.5 * (P.y - Q.y));
+        if (nn & 1) Y = mk(-Y.x, -Y.y);
+        if (der && p < a.P) {
+          const double kk = der == 1 ? kx_of(a, p) : ky_of(a, p);
+          Y = mk(kk * Y.y, -kk * Y.x);  // conj(i k) Y = -i k Y
+        }
+        acc[it] = acc[it] + Y;
+      }
+    }
+    __syncthreads();
+  }
+  const int var = al.target[ti];
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    const int idx = tid + it * nt;
+    if (idx < TP * N) {
+      const int s = idx / N, nn = idx - s * N;
+      const int p = p0 + s;
+      if (active(a, p)) {
+        double2* o = Xb + ((size_t)p * S + var) * N + nn;
+        const double2 old = *o;
+        *o = make_double2(old.x + acc[it].x, old.y + acc[it].y);
+      }
+    }
+  }
+}
+
+// Adjoint of the fused x pass for one dealiased z row.  Recomputes the eight
+// forward grid fields from G, maps the explicit-term adjoints H_bar to the
+// grid (adjoint of the truncated real-to-complex transform:
+// g_bar_i = (1/L) [Re c_0 + Re sum_{k>=1} c_k e^{2 pi i k i / L}]), applies the
+// product rule, and maps the eight grid adjoints back to spectra (adjoint of
+// the complex-to-real synthesis: c_bar_k = w_k sum_i g_bar_i e^{-2 pi i k i/L},
+// w_0 = 1, w_k = 2).
+template <int MAXBF, int PTS, int NT>
+__global__ void __launch_bounds__(NT) xpass_adj_kernel(XformArgs a, const double2* __restrict__ G,
+                                                       const double2* __restrict__ Hb,
+                                                       double2* __restrict__ Gb) {
+  extern __shared__ double2 smem[];
+  cd* buf = (cd*)smem;
+  const int jz = blockIdx.x;
+  const int M = a.M, L = a.L, Pa = a.Pa, P = a.P;
+  const int tid = threadIdx.x;
+  constexpr int nt = NT;
+  const cd* tw = (const cd*)a.twx;
+  // complex-to-real of a packed pair; hs scales k >= 1 (1 for synthesis, 0.5
+  // for the adjoint of the truncated forward transform)
+  auto c2r_pair = [&](const double2* A, const double2* B, double hs, double* ra, double* rb) {
+    for (int k = tid; k < L; k += nt) {
+      cd z = mk(0.0, 0.0);
+      if (k < Pa) {
+        cd Ak = A ? ld2(A + k) : mk(0.0, 0.0), Bk = B ? ld2(B + k) : mk(0.0, 0.0);
+        if (k == 0) {
+          Ak.y = 0.0;
+          Bk.y = 0.0;
+        } else {
+          Ak = scale(Ak, hs);
+          Bk = scale(Bk, hs);
+        }
+        z = mk(Ak.x - Bk.y, Ak.y + Bk.x);
+      } else if (k > L - Pa) {
+        cd Ak = A ? ld2(A + (L - k)) : mk(0.0, 0.0), Bk = B ? ld2(B + (L - k)) : mk(0.0, 0.0);
+        Ak = scale(Ak, hs);
+        Bk = scale(Bk, hs);
+        z = mk(Ak.x + Bk.y, -Ak.y + Bk.x);
+      }
+      buf[k] = z;
+    }
+    __syncthreads();
+    fft_lds<+1, MAXBF>(buf, L, 1, tw, tid, nt);
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) {
+      const int i = tid + q * nt;
+      if (i < L) {
+        ra[q] = buf[i].x;
+        rb[q] = buf[i].y;
+      }
+    }
+    __syncthreads();
+  };
+  // adjoint of a synthesis pair: spectra of two real grid rows, weights w_k
+  auto r2c_adj_pair = [&](const double* ga, const double* gb, int fa, int fb) {
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) {
+      const int i = tid + q * nt;
+      if (i < L) buf[i] = mk(ga[q], gb[q]);
+    }
+    __syncthreads();
+    fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, nt);
+    double2* Oa = Gb + ((size_t)fa * M + jz) * P;
+    double2* Ob = Gb + ((size_t)fb * M + jz) * P;
+    for (int k = tid; k < P; k += nt) {
+      cd A = mk(0.0, 0.0), Bv = mk(0.0, 0.0);
+      if (k < Pa) {
+        cd Zk = buf[k], Zm = buf[k == 0 ? 0 : L - k];
+        const double wk = k == 0 ? 1.0 : 2.0;
+        A = mk(0.5 * (Zk.x + Zm.x) * wk, 0.5 * (Zk.y - Zm.y) * wk);
+        Bv = mk(0.5 * (Zk.y + Zm.y) * wk, -0.5 * (Zk.x - Zm.x) * wk);
+      }
+      st2(Oa + k, A);
+      st2(Ob + k, Bv);
+    }
+    __syncthreads();
+  };
+  auto row = [&](const double2* base, int f) { return base + ((size_t)f * M + jz) * P; };
+
+  double u[PTS], w[PTS], bx[PTS], bz[PTS], ux[PTS], uz[PTS], wx[PTS], wz[PTS];
+  double nb[PTS], nu[PTS], nw[PTS], t1[PTS], t2[PTS];
+  c2r_pair(row(G, 0), row(G, 1), 1.0, u, w);
+  c2r_pair(row(G, 2), row(G, 3), 1.0, bx, bz);
+  c2r_pair(row(G, 4), row(G, 5), 1.0, ux, uz);
+  c2r_pair(row(G, 6), row(G, 7), 1.0, wx, wz);
+  c2r_pair(row(Hb, 0), row(Hb, 1), 0.5, nb, nu);
+  c2r_pair(row(Hb, 2), nullptr, 0.5, nw, t1);
+  const double invL = 1.0 / (double)L;
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    nb[q] *= invL;
+    nu[q] *= invL;
+    nw[q] *= invL;
+  }
+  // (u, w)
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    t1[q] = -(nb[q] * bx[q] + nu[q] * ux[q] + nw[q] * wx[q]);
+    t2[q] = -(nb[q] * bz[q] + nu[q] * uz[q] + nw[q] * wz[q]);
+  }
+  r2c_adj_pair(t1, t2, 0, 1);
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    t1[q] = -nb[q] * u[q];
+    t2[q] = -nb[q] * w[q];
+  }
+  r2c_adj_pair(t1, t2, 2, 3);
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    t1[q] = -nu[q] * u[q];
+    t2[q] = -nu[q] * w[q];
+  }
+  r2c_adj_pair(t1, t2, 4, 5);
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    t1[q] = -nw[q] * u[q];
+    t2[q] = -nw[q] * w[q];
+  }
+  r2c_adj_pair(t1, t2, 6, 7);
+}
+
+// Kinetic-energy adjoint for one row: u_bar = e_bar_j u, w_bar = e_bar_j w with
+// e_bar_j = (1/L) sum_m w_m (2 - delta)/M T_m(z_j) (precomputed in ebar).
+template <int MAXBF, int PTS, int NT>
+__global__ void __launch_bounds__(NT) ke_row_adj_kernel(XformArgs a, const double2* __restrict__ G,
+                                                        const double2* __restrict__ ebar,
+                                                        double2* __restrict__ Gb) {
+  extern __shared__ double2 smem[];
+  cd* buf = (cd*)smem;
+  const int jz = blockIdx.x;
+  const int M = a.M, L = a.L, Pa = a.Pa, P = a.P;
+  const int tid = threadIdx.x;
+  constexpr int nt = NT;
+  const cd* tw = (const cd*)a.twx;
+  const double2* A = G + ((size_t)0 * M + jz) * P;
+  const double2* B = G + ((size_t)1 * M + jz) * P;
+  for (int k = tid; k < L; k += nt) {
+    cd z = mk(0.0, 0.0);
+    if (k < Pa) {
+      cd Ak = ld2(A + k), Bk = ld2(B + k);
+      if (k == 0) {
+        Ak.y = 0.0;
+        Bk.y = 0.0;
+      }
+      z = mk(Ak.x - Bk.y, Ak.y + Bk.x);
+    } else if (k > L - Pa) {
+      cd Ak = ld2(A + (L - k)), Bk = ld2(B + (L - k));
+      z = mk(Ak.x + Bk.y, -Ak.y + Bk.x);
+    }
+    buf[k] = z;
+  }
+  __syncthreads();
+  fft_lds<+1, MAXBF>(buf, L, 1, tw, tid, nt);
+  const double e = ebar[jz].x / (double)L;
+  double gu[PTS], gw[PTS];
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    const int i = tid + q * nt;
+    if (i < L) {
+      gu[q] = e * buf[i].x;
+      gw[q] = e * buf[i].y;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    const int i = tid + q * nt;
+    if (i < L) buf[i] = mk(gu[q], gw[q]);
+  }
+  __syncthreads();
+  fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, nt);
+  double2* Oa = Gb + ((size_t)0 * M + jz) * P;
+  double2* Ob = Gb + ((size_t)1 * M + jz) * P;
+  for (int k = tid; k < P; k += nt) {
+    cd Av = mk(0.0, 0.0), Bv = mk(0.0, 0.0);
+    if (k < Pa) {
+      cd Zk = buf[k], Zm = buf[k == 0 ? 0 : L - k];
+      const double wk = k == 0 ? 1.0 : 2.0;
+      Av = mk(0.5 * (Zk.x + Zm.x) * wk, 0.5 * (Zk.y - Zm.y) * wk);
+      Bv = mk(0.5 * (Zk.y + Zm.y) * wk, -0.5 * (Zk.x - Zm.x) * wk);
+    }
+    st2(Oa + k, Av);
+    st2(Ob + k, Bv);
+  }
+}
+
+// Initial-state adjoint, step 1 (per pencil): c_bar = X_bar_b + D^T X_bar_bz
+// for bz = D b, D_nm = 4 m / (1 + delta_n0) for n < m, m - n odd (d/dz on
+// [0, 1] of the T-to-T derivative).
+__global__ void ic_adj_coef_kernel(XformArgs a, const double2* __restrict__ Xb,
+                                   double2* __restrict__ C, int vb, int vbz) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.P) return;
+  const int N = a.N, S = a.S;
+  const double2* xb = Xb + ((size_t)p * S + vb) * N;
+  const double2* xz = Xb + ((size_t)p * S + vbz) * N;
+  double2* c = C + (size_t)p * N;
+  double se_r = 0.0, se_i = 0.0, so_r = 0.0, so_i = 0.0;  // running sums over even / odd n
+  for (int m = 0; m < N; ++m) {
+    double vr = xb[m].x, vi = xb[m].y;
+    if (m & 1) {
+      vr += 4.0 * m * se_r;
+      vi += 4.0 * m * se_i;
+    } else {
+      vr += 4.0 * m * so_r;
+      vi += 4.0 * m * so_i;
+    }
+    c[m] = make_double2(vr, vi);
+    const double f = m == 0 ? 0.5 : 1.0;
+    if (m & 1) {
+      so_r += xz[m].x;
+      so_i += xz[m].y;
+    } else {
+      se_r += f * xz[m].x;
+      se_i += f * xz[m].y;
+    }
+  }
+}
+
+// Initial-state adjoint, step 3 (per z level): g_bar_i = (1/Nx) [Re H_0 +
+// Re sum_{k>=1} H_k e^{2 pi i k i / Nx}] (adjoint of the truncated forward x
+// transform at scale 1), written to gbar[ix][jz].
+template <int MAXBF>
+__global__ void __launch_bounds__(256) ic_adj_x_kernel(XformArgs a, const double2* __restrict__ H1,
+                                                       double* __restrict__ gbar) {
+  extern __shared__ double2 smem[];
+  cd* buf = (cd*)smem;
+  const int jz = blockIdx.x;
+  const int Nx = a.Nx, N = a.N, Pa = a.Pa;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double2* h = H1 + (size_t)jz * a.P;
+  for (int k = tid; k < Nx; k += nt) {
+    cd z = mk(0.0, 0.0);
+    if (k == 0)
+      z = mk(h[0].x, 0.0);
+    else if (k < Pa)
+      z = scale(ld2(h + k), 0.5);
+    else if (k > Nx - Pa)
+      z = scale(conj(ld2(h + (Nx - k))), 0.5);
+    buf[k] = z;
+  }
+  __syncthreads();
+  fft_lds<+1, MAXBF>(buf, Nx, 1, (const cd*)a.twx, tid, nt);
+  const double inv = 1.0 / (double)Nx;
+  for (int i = tid; i < Nx; i += nt) gbar[(size_t)i * N + jz] = buf[i].x * inv;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -443,6 +763,108 @@ hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t 
     case 1024: return launch_xpass_t<1024>(a, G, H, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_zadj(const XformArgs& a, const AccList& al, const void* Gbar, void* Xbar,
+                       hipStream_t st) {
+  const int TP = z_tile(a.M);
+  dim3 grid((a.P + TP - 1) / TP, al.nt);
+  size_t lds = (size_t)TP * a.M * sizeof(double2);
+  hipLaunchKernelGGL((zadj_kernel<3, 12>), grid, dim3(256), lds, st, a, al, (const double2*)Gbar,
+                     (double2*)Xbar, TP);
+  return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t launch_xpass_adj_t(const XformArgs& a, const void* G, const void* Hb, void* Gb,
+                                     hipStream_t st) {
+  size_t lds = (size_t)a.L * sizeof(double2);
+  allow_lds((const void*)xpass_adj_kernel<2, 6, NT>, lds);
+  hipLaunchKernelGGL((xpass_adj_kernel<2, 6, NT>), dim3(a.M), dim3(NT), lds, st, a,
+                     (const double2*)G, (const double2*)Hb, (double2*)Gb);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpass_adj(const XformArgs& a, const void* G, const void* Hbar, void* Gbar,
+                            hipStream_t st) {
+  switch (x_threads(a.L)) {
+    case 64: return launch_xpass_adj_t<64>(a, G, Hbar, Gbar, st);
+    case 128: return launch_xpass_adj_t<128>(a, G, Hbar, Gbar, st);
+    case 256: return launch_xpass_adj_t<256>(a, G, Hbar, Gbar, st);
+    case 512: return launch_xpass_adj_t<512>(a, G, Hbar, Gbar, st);
+    case 1024: return launch_xpass_adj_t<1024>(a, G, Hbar, Gbar, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int NT>
+static hipError_t launch_ke_row_adj_t(const XformArgs& a, const void* G, const void* ebar,
+                                      void* Gb, hipStream_t st) {
+  size_t lds = (size_t)a.L * sizeof(double2);
+  allow_lds((const void*)ke_row_adj_kernel<2, 6, NT>, lds);
+  hipLaunchKernelGGL((ke_row_adj_kernel<2, 6, NT>), dim3(a.M), dim3(NT), lds, st, a,
+                     (const double2*)G, (const double2*)ebar, (double2*)Gb);
+  return hipGetLastError();
+}
+
+hipError_t launch_ke_adjoint(const XformArgs& a, const void* X, void* G, void* Gbar,
+                             const void* wvec, void* ebar, void* Xbar, hipStream_t st) {
+  // e_bar_j: weighted DCT-III of the integration weights (one "pencil")
+  XformArgs aw = a;
+  aw.P = 1;
+  aw.Pa = 1;
+  aw.dim = 2;
+  FieldList fw{};
+  fw.nf = 1;
+  fw.var[0] = 0;
+  fw.src_S = 1;
+  fw.wmode = 1;
+  launch_zb(aw, fw, wvec, ebar, st);
+  FieldList fl{};
+  fl.nf = 2;
+  fl.var[0] = 2;                   // u
+  fl.var[1] = a.dim == 2 ? 3 : 4;  // w
+  launch_zb(a, fl, X, G, st);
+  hipError_t e;
+  switch (x_threads(a.L)) {
+    case 64: e = launch_ke_row_adj_t<64>(a, G, ebar, Gbar, st); break;
+    case 128: e = launch_ke_row_adj_t<128>(a, G, ebar, Gbar, st); break;
+    case 256: e = launch_ke_row_adj_t<256>(a, G, ebar, Gbar, st); break;
+    case 512: e = launch_ke_row_adj_t<512>(a, G, ebar, Gbar, st); break;
+    case 1024: e = launch_ke_row_adj_t<1024>(a, G, ebar, Gbar, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(Xbar, 0, (size_t)a.P * a.S * a.N * sizeof(double2), st);
+  if (e != hipSuccess) return e;
+  AccList al{};
+  al.nt = 2;
+  al.target[0] = 2;
+  al.nsrc[0] = 1;
+  al.src[0][0] = 0;
+  al.target[1] = a.dim == 2 ? 3 : 4;
+  al.nsrc[1] = 1;
+  al.src[1][0] = 1;
+  return launch_zadj(a, al, Gbar, Xbar, st);
+}
+
+hipError_t launch_initial_state_adjoint(const XformArgs& a1, const void* Xbar, double* gbar,
+                                        void* work, hipStream_t st) {
+  double2* C = (double2*)work;              // [P][1][N]
+  double2* H1 = C + (size_t)a1.P * a1.N;    // [N][P]
+  const int vb = 1, vbz = a1.dim == 2 ? 4 : 5;
+  hipLaunchKernelGGL(ic_adj_coef_kernel, dim3((a1.P + 63) / 64), dim3(64), 0, st, a1,
+                     (const double2*)Xbar, C, vb, vbz);
+  FieldList fl{};
+  fl.nf = 1;
+  fl.var[0] = 0;
+  fl.src_S = 1;
+  fl.wmode = 1;
+  launch_zb(a1, fl, C, H1, st);
+  allow_lds((const void*)ic_adj_x_kernel<8>, (size_t)a1.Nx * sizeof(double2));
+  hipLaunchKernelGGL((ic_adj_x_kernel<8>), dim3(a1.N), dim3(256), (size_t)a1.Nx * sizeof(double2),
+                     st, a1, (const double2*)H1, gbar);
+  return hipGetLastError();
 }
 
 hipError_t launch_initial_state(const XformArgs& a1, const double* bgrid, void* X, void* work,

@@ -34,12 +34,27 @@ struct XformArgs {
   const double2* twy;   // e^{-2 pi i t / Ngy}
 };
 
-// Field list for the backward z transform: state variable (ABI index) and
-// derivative flag (0: none, 1: multiply by i kx, 2: multiply by i ky).
+// Field list for the backward z transform: source variable index and
+// derivative flag (0: none, 1: multiply by i kx, 2: multiply by i ky).  The
+// source array is [P][src_S][N]; wmode 1 multiplies coefficient n by the
+// forward-transform weight (2 - delta_n0) / M first (adjoint of the forward z
+// transform).
 struct FieldList {
   int nf;
   int var[kMaxFields];
   int deriv[kMaxFields];
+  int src_S;   // 0 means the state's S
+  int wmode;
+};
+
+// Adjoint of the backward z transform: for each target variable, sum over its
+// source fields of conj(i k)^deriv * T^T G_f, accumulated into Xbar[P][S][N].
+struct AccList {
+  int nt;
+  int target[9];
+  int nsrc[9];
+  int src[9][2];
+  int deriv[9][2];
 };
 
 // pencil kernels
@@ -64,6 +79,24 @@ struct RhsArgs {
 };
 hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
                      hipStream_t st);
+
+// adjoint path
+hipError_t launch_zadj(const XformArgs& a, const AccList& al, const void* Gbar, void* Xbar,
+                       hipStream_t st);
+hipError_t launch_xpass_adj(const XformArgs& a, const void* G, const void* Hbar, void* Gbar,
+                            hipStream_t st);
+struct AdjRhsArgs {
+  double c1, c2, a1, a2;
+  double2* hbar;  // [P][2][ne][N] pending adjoints (read, then overwritten)
+  double2* Fbar;  // [P][ne][N] output: (P^L)^H F~bar
+};
+hipError_t launch_solveT(const PencilArgs& a, const void* Xbar_in, const double* Lf,
+                         const uint8_t* sl, const double* Uf, void* Xbar_out,
+                         const AdjRhsArgs& r, hipStream_t st);
+hipError_t launch_ke_adjoint(const XformArgs& a, const void* X, void* G, void* Gbar,
+                             const void* wvec, void* ebar, void* Xbar, hipStream_t st);
+hipError_t launch_initial_state_adjoint(const XformArgs& a1, const void* Xbar, double* gbar,
+                                        void* work, hipStream_t st);
 
 // initial state from scale-1 grid values of b
 hipError_t launch_initial_state(const XformArgs& a1, const double* bgrid, void* X, void* work,

@@ -81,20 +81,30 @@ struct stau_pencils {
   XformArgs xa{};   // dealiased transforms
   XformArgs xa1{};  // scale-1 transforms
   FieldList fl{};
+  AccList acc{};
   int64_t n = 0;
   // workspaces
   double2* G = nullptr;    // [NF][M][P]
   double2* H = nullptr;    // [ne][M][P]
   double2* Bev = nullptr;  // [P][ne][N]
-  double* Lf = nullptr;
+  double2* Gb = nullptr;   // [NF][M][P] adjoint workspace
+  double2* wvec = nullptr; // [N] Chebyshev integration weights of the KE functional
+  struct FactorSlot {
+    double* Lf = nullptr;
+    uint8_t* sl = nullptr;
+    double* Uf = nullptr;
+    bool valid = false;
+    double a0 = 0.0, b0 = 0.0;
+    int64_t stamp = 0;
+  } slot[2];
+  int64_t clock = 0;
+  double* Lf = nullptr;     // factors of the most recent stau_factor (aliases a slot)
   uint8_t* sl = nullptr;
   double* Uf = nullptr;
   int* sing = nullptr;     // device: first singular pencil (INT_MAX if none)
   int* flag = nullptr;     // device: non-finite flag
   double* scratch = nullptr;
   int64_t ws_bytes = 0;
-  bool factored = false;
-  double fa0 = 0.0, fb0 = 0.0;
   int64_t last_sing = -1;
   // per-kernel event timing (instrumentation)
   bool timing = false;
@@ -310,9 +320,13 @@ static void free_pencils(stau_pencils* p) {
   hipFree(p->G);
   hipFree(p->H);
   hipFree(p->Bev);
-  hipFree(p->Lf);
-  hipFree(p->sl);
-  hipFree(p->Uf);
+  hipFree(p->Gb);
+  hipFree(p->wvec);
+  for (auto& f : p->slot) {
+    hipFree(f.Lf);
+    hipFree(f.sl);
+    hipFree(f.Uf);
+  }
   hipFree(p->sing);
   hipFree(p->flag);
   hipFree(p->scratch);
@@ -387,6 +401,23 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
     fl.var[i] = fv[i];
     fl.deriv[i] = fd[i];
   }
+  {
+    // adjoint of the backward z transform: target variable <- source fields
+    AccList& al = pen->acc;
+    const int tgt[6] = {2, 3, 1, 4, 5, 6};                 // u, w, b, bz, uz, wz
+    const int ns[6] = {2, 2, 1, 1, 1, 1};
+    const int sf[6][2] = {{0, 4}, {1, 6}, {2, -1}, {3, -1}, {5, -1}, {7, -1}};
+    const int sd[6][2] = {{0, 1}, {0, 1}, {1, 0}, {0, 0}, {0, 0}, {0, 0}};
+    al.nt = 6;
+    for (int i = 0; i < 6; ++i) {
+      al.target[i] = tgt[i];
+      al.nsrc[i] = ns[i];
+      for (int q = 0; q < 2; ++q) {
+        al.src[i][q] = sf[i][q];
+        al.deriv[i][q] = sd[i][q];
+      }
+    }
+  }
 
   const size_t P = dom->P, M = dom->Ngz, ne = pa.desc.ne, n = pen->n;
   const size_t szG = (size_t)fl.nf * M * P * sizeof(double2);
@@ -400,9 +431,13 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   if (e == hipSuccess) e = hipMalloc((void**)&pen->G, szG);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->H, szH);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->Bev, szB);
-  if (e == hipSuccess) e = hipMalloc((void**)&pen->Lf, szL);
-  if (e == hipSuccess) e = hipMalloc((void**)&pen->sl, szS);
-  if (e == hipSuccess) e = hipMalloc((void**)&pen->Uf, szU);
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->Gb, szG);
+  if (e == hipSuccess) e = hipMalloc((void**)&pen->wvec, (size_t)N * sizeof(double2));
+  for (auto& f : pen->slot) {
+    if (e == hipSuccess) e = hipMalloc((void**)&f.Lf, szL);
+    if (e == hipSuccess) e = hipMalloc((void**)&f.sl, szS);
+    if (e == hipSuccess) e = hipMalloc((void**)&f.Uf, szU);
+  }
   if (e == hipSuccess) e = hipMalloc((void**)&pen->sing, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->flag, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->scratch, szScratch);
@@ -411,7 +446,19 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
     delete pen;
     return fail(STAU_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
-  pen->ws_bytes = (int64_t)(szG + szH + szB + szL + szU + szS + szScratch);
+  pen->ws_bytes = (int64_t)(2 * szG + szH + szB + 2 * (szL + szU + szS) + szScratch);
+  {
+    // KE functional weights: integral over z in [0, 1] of T_m = 1 / (1 - m^2), m even
+    std::vector<double2> wv(N);
+    for (int m = 0; m < N; ++m)
+      wv[m] = make_double2((m & 1) ? 0.0 : 1.0 / (1.0 - (double)m * (double)m), 0.0);
+    hipError_t e2 = hipMemcpy(pen->wvec, wv.data(), N * sizeof(double2), hipMemcpyHostToDevice);
+    if (e2 != hipSuccess) {
+      free_pencils(pen);
+      delete pen;
+      return fail(STAU_EHIP, "upload failed: %s", hipGetErrorString(e2));
+    }
+  }
   *out = pen;
   return STAU_OK;
 }
@@ -448,29 +495,61 @@ int stau_query(const stau_pencils* pen, stau_info* info) {
   return STAU_OK;
 }
 
-int stau_factor(stau_pencils* pen, double a0, double b0, void* stream) {
-  if (!pen) return fail(STAU_EINVAL, "null argument");
-  if (!std::isfinite(a0) || !std::isfinite(b0)) return fail(STAU_EINVAL, "non-finite a0/b0");
-  hipStream_t st = (hipStream_t)stream;
-  HIP_TRY(hipSetDevice(pen->dom->d.device));
+static int factor_into(stau_pencils* pen, int k, double a0, double b0, hipStream_t st) {
+  auto& f = pen->slot[k];
+  f.valid = false;
   const int big = 0x7fffffff;
   HIP_TRY(hipMemcpyAsync(pen->sing, &big, sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(timed(pen, K_FACTOR, st, [&] {
-    return launch_factor(pen->pa, a0, b0, pen->Lf, pen->sl, pen->Uf, pen->sing, st);
+    return launch_factor(pen->pa, a0, b0, f.Lf, f.sl, f.Uf, pen->sing, st);
   }));
   int h = big;
   HIP_TRY(hipMemcpyAsync(&h, pen->sing, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (h != big) {
-    pen->factored = false;
     pen->last_sing = h;
     return fail(STAU_ESINGULAR, "zero or non-finite pivot in pencil %d", h);
   }
-  pen->factored = true;
-  pen->fa0 = a0;
-  pen->fb0 = b0;
+  f.valid = true;
+  f.a0 = a0;
+  f.b0 = b0;
+  f.stamp = ++pen->clock;
   pen->last_sing = -1;
   return STAU_OK;
+}
+
+// Factors for (a0, b0): a cached slot if one matches, else refactor the least
+// recently used slot (two slots: the SBDF1 and SBDF2 operators of a run).
+static int factors_for(stau_pencils* pen, double a0, double b0, hipStream_t st,
+                       stau_pencils::FactorSlot** out) {
+  for (auto& f : pen->slot)
+    if (f.valid && f.a0 == a0 && f.b0 == b0) {
+      f.stamp = ++pen->clock;
+      *out = &f;
+      return STAU_OK;
+    }
+  int k = pen->slot[0].stamp <= pen->slot[1].stamp ? 0 : 1;
+  if (!pen->slot[0].valid) k = 0;
+  else if (!pen->slot[1].valid) k = 1;
+  int rc = factor_into(pen, k, a0, b0, st);
+  if (rc) return rc;
+  *out = &pen->slot[k];
+  return STAU_OK;
+}
+
+int stau_factor(stau_pencils* pen, double a0, double b0, void* stream) {
+  if (!pen) return fail(STAU_EINVAL, "null argument");
+  if (!std::isfinite(a0) || !std::isfinite(b0)) return fail(STAU_EINVAL, "non-finite a0/b0");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  int k = pen->slot[0].stamp <= pen->slot[1].stamp ? 0 : 1;
+  for (int q = 0; q < 2; ++q)
+    if (pen->slot[q].valid && pen->slot[q].a0 == a0 && pen->slot[q].b0 == b0) k = q;
+  int rc = factor_into(pen, k, a0, b0, st);
+  pen->Lf = rc ? nullptr : pen->slot[k].Lf;
+  pen->sl = rc ? nullptr : pen->slot[k].sl;
+  pen->Uf = rc ? nullptr : pen->slot[k].Uf;
+  return rc;
 }
 
 int64_t stau_last_singular_pencil(const stau_pencils* pen) { return pen ? pen->last_sing : -1; }
@@ -504,8 +583,9 @@ int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
   HIP_TRY(hipSetDevice(pen->dom->d.device));
   double a0, a1, a2, b0, c1, c2;
   sbdf(s->iteration, dt, s->dt_prev, &a0, &a1, &a2, &b0, &c1, &c2);
-  if (!pen->factored || a0 != pen->fa0 || b0 != pen->fb0) {
-    int rc = stau_factor(pen, a0, b0, stream);
+  stau_pencils::FactorSlot* fs = nullptr;
+  {
+    int rc = factors_for(pen, a0, b0, st, &fs);
     if (rc) return rc;
   }
   const int cur = s->head ^ 1;
@@ -525,7 +605,7 @@ int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
   HIP_TRY(timed(pen, K_XPASS, st, [&] { return launch_xpass(pen->xa, pen->G, pen->H, st); }));
   HIP_TRY(timed(pen, K_ZF, st, [&] { return launch_zf(pen->xa, pen->H, pen->Bev, r, st); }));
   HIP_TRY(timed(pen, K_SOLVE, st, [&] {
-    return launch_solve(pen->pa, pen->Bev, pen->Lf, pen->sl, pen->Uf, s->X, st);
+    return launch_solve(pen->pa, pen->Bev, fs->Lf, fs->sl, fs->Uf, s->X, st);
   }));
   s->head = cur;
   s->iteration += 1;
@@ -554,9 +634,67 @@ int stau_nonlinear(stau_pencils* pen, const void* X, void* F, void* stream) {
 
 int stau_solve(stau_pencils* pen, const void* B_ev, void* X, void* stream) {
   if (!pen || !B_ev || !X) return fail(STAU_EINVAL, "null argument");
-  if (!pen->factored) return fail(STAU_ESTATE, "stau_solve before stau_factor");
+  if (!pen->Lf) return fail(STAU_ESTATE, "stau_solve before a successful stau_factor");
   HIP_TRY(hipSetDevice(pen->dom->d.device));
   HIP_TRY(launch_solve(pen->pa, B_ev, pen->Lf, pen->sl, pen->Uf, X, (hipStream_t)stream));
+  return STAU_OK;
+}
+
+int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, double dt,
+                      double dt_prev, stau_adjstate* adj, void* stream) {
+  if (!pen || !X_prev || !adj || !adj->Xbar || !adj->hbar) return fail(STAU_EINVAL, "null argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(STAU_EINVAL, "dt must be positive");
+  if (iteration < 0 || (iteration > 0 && !(dt_prev > 0.0)))
+    return fail(STAU_EINVAL, "iteration / dt_prev inconsistent");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  double a0, a1, a2, b0, c1, c2;
+  sbdf(iteration, dt, dt_prev, &a0, &a1, &a2, &b0, &c1, &c2);
+  stau_pencils::FactorSlot* fs = nullptr;
+  {
+    int rc = factors_for(pen, a0, b0, st, &fs);
+    if (rc) return rc;
+  }
+  AdjRhsArgs r{};
+  r.c1 = c1;
+  r.c2 = c2;
+  r.a1 = a1;
+  r.a2 = a2;
+  r.hbar = (double2*)adj->hbar;
+  r.Fbar = pen->Bev;
+  // 1. transposed pencil solve + multistep history adjoints
+  HIP_TRY(launch_solveT(pen->pa, adj->Xbar, fs->Lf, fs->sl, fs->Uf, adj->Xbar, r, st));
+  // 2. adjoint of the forward z transform: H_bar = W^T F_bar
+  FieldList fe{};
+  fe.nf = pen->pa.desc.ne;
+  for (int e = 0; e < fe.nf; ++e) fe.var[e] = e;
+  fe.src_S = pen->pa.desc.ne;
+  fe.wmode = 1;
+  HIP_TRY(launch_zb(pen->xa, fe, pen->Bev, pen->H, st));
+  // 3. forward grid fields at X^{n-1}
+  HIP_TRY(launch_zb(pen->xa, pen->fl, X_prev, pen->G, st));
+  // 4. adjoint x pass
+  HIP_TRY(launch_xpass_adj(pen->xa, pen->G, pen->H, pen->Gb, st));
+  // 5. adjoint of the backward z transform, accumulated into X_bar
+  HIP_TRY(launch_zadj(pen->xa, pen->acc, pen->Gb, adj->Xbar, st));
+  return STAU_OK;
+}
+
+int stau_kinetic_energy_adjoint(stau_pencils* pen, const void* X, void* Xbar, void* stream) {
+  if (!pen || !X || !Xbar) return fail(STAU_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  double2* ebar = (double2*)pen->scratch;
+  HIP_TRY(launch_ke_adjoint(pen->xa, X, pen->G, pen->Gb, pen->wvec, ebar, Xbar, st));
+  return STAU_OK;
+}
+
+int stau_initial_state_adjoint(stau_pencils* pen, const void* Xbar, double* b_grid_bar,
+                               void* stream) {
+  if (!pen || !Xbar || !b_grid_bar) return fail(STAU_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  HIP_TRY(launch_initial_state_adjoint(pen->xa1, Xbar, b_grid_bar, pen->scratch, st));
   return STAU_OK;
 }
 
