@@ -50,6 +50,96 @@ def algorithmic_bytes(info):
     return {"z_backward": zb, "x_pass": xp, "z_forward_rhs": zf, "pencil_solve": solve}
 
 
+ADJ_WORKLOAD = dict(Nx=512, Nz=128, Lx=4.0, Ra=1e6, Pr=1.0, dt=1e-4, steps=200, checkpoint=20,
+                    seed_workload=3)
+
+
+def adjoint_ratio(reps=3):
+    """Adjoint workload (512x128, Ra=1e6, 200 SBDF2 steps, checkpoint every 20):
+    time of the forward run vs the full gradient (forward with checkpoints +
+    recomputation + reverse steps + initial-condition adjoint)."""
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_1905_10388_amd import RBSolver
+    from paper_1905_10388_amd.adjoint import kinetic_energy_and_gradient
+
+    a = ADJ_WORKLOAD
+    g = RBSolver(a["Nx"], a["Nz"], a["Lx"], a["Ra"], a["Pr"])
+    b = torch.from_numpy(b_grid(a["Nx"], a["Nz"], si.workload_noise((a["Nx"], a["Nz"]), a["seed_workload"]))).cuda()
+
+    def fwd():
+        g.initial_state(b)
+        for _ in range(a["steps"]):
+            g.step(a["dt"])
+        return g.kinetic_energy()
+
+    fwd()
+    kinetic_energy_and_gradient(g, b, a["dt"], a["steps"], a["checkpoint"])  # warm (factor cache)
+    tf, tg = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fwd()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kinetic_energy_and_gradient(g, b, a["dt"], a["steps"], a["checkpoint"])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        tg.append(t2 - t1)
+    f, gr = float(np.median(tf)), float(np.median(tg))
+    dof = 7 * a["Nx"] * a["Nz"] * a["steps"]
+    return {"workload": "rb2d_512x128_Ra1e6_dt1e-4_200steps_ckpt20", "forward_ms": f * 1e3,
+            "gradient_ms": gr * 1e3, "adjoint_over_forward": gr / f,
+            "forward_dof_updates_per_s": dof / f, "adjoint_dof_updates_per_s": dof / (gr - f) if gr > f else None,
+            "dtype": "f64"}
+
+
+def mixed_run(w, steps, warmup, X_fp64):
+    """The mixed-precision step on the same workload and step count; per-field
+    relative L2 error of its final state against the FP64 path's final state
+    (the FP64 path agrees with the FP64 oracle to 1e-10)."""
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_1905_10388_amd import RBSolver
+
+    Nx, Nz, dt = w["Nx"], w["Nz"], w["dt"]
+    g = RBSolver(Nx, Nz, w["Lx"], w["Ra"], w["Pr"], precision="mixed")
+    g.initial_state(torch.from_numpy(b_grid(Nx, Nz, si.workload_noise((Nx, Nz), w["seed_workload"]))))
+    for _ in range(warmup):
+        g.step(dt)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        g.step(dt)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = max((time.perf_counter() - t0) * 1e3 / steps, ev0.elapsed_time(ev1) / steps)
+    g.check()
+    Xm = g.X.cpu().numpy()
+    Xd = X_fp64.cpu().numpy()
+    names = ("p", "b", "u", "w", "bz", "uz", "wz")
+    err = {}
+    for i, v in enumerate(names):
+        den = np.linalg.norm(Xd[:, i])
+        err[v] = float(np.linalg.norm(Xm[:, i] - Xd[:, i]) / den) if den > 0 else None
+    g.set_kernel_timing(True)
+    for _ in range(20):
+        g.step(dt)
+    kt = {k: round(ms_ * 1e3 / c, 3) for k, (ms_, c) in g.read_kernel_timing().items() if c}
+    g.close()
+    return {"value": 7 * Nx * Nz / (ms * 1e-3), "unit": "DOF-updates/s", "ms_per_step": ms,
+            "dtype": "f32+f64", "err_vs_fp64_per_field": err, "kernels_avg_us": kt,
+            "steps_compared": steps + warmup}
+
+
 def cpu_baseline(w, sample_pencils=128, reps=3):
     """The oracle's SBDF2 step on a bounded sample: the explicit term on the
     full grid, then right-hand side + LU solve of `sample_pencils` pencils
@@ -112,6 +202,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=100,
                     help="steps of the per-kernel HIP-event pass after the timed region")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -150,6 +242,8 @@ def main():
     g.check()
     dof = 7 * Nx * Nz
     value = dof / (ms_per_step * 1e-3)
+    X_end = g.X.clone()
+    n_steps_end = g.iteration
 
     # per-kernel HIP-event timing on the launch stream (separate pass)
     g.set_kernel_timing(True)
@@ -181,7 +275,7 @@ def main():
         torch.cuda.synchronize()
 
     out = {
-        "metric": "DOF-updates/s per SBDF2 step (FP64)",
+        "metric": "DOF-updates/s per SBDF2 step, FP64 vs mixed at stated err; adjoint/forward time",
         "value": value,
         "unit": "DOF-updates/s",
         "n_gpus": 1,
@@ -200,6 +294,11 @@ def main():
         "roofline": roofline,
         "mode_updates_per_s": Nx * Nz / (ms_per_step * 1e-3),
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_run(w, args.steps, n_steps_end - args.steps, X_end)
+        out["mixed"]["speedup_vs_fp64"] = out["mixed"]["value"] / value
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_ratio()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -67,9 +67,13 @@ typedef struct stau_pencils stau_pencils;
  * Nz       Chebyshev modes (even, 4 <= Nz <= 1024; 3Nz/2 of the form 2^a 3^b).
  * Lx, Ly   periods of x, y (> 0).
  * dealias  transform scale; must be 1.5 (the 3/2 rule, Sec. IV).
- * precision STAU_FP64 (everything FP64) or STAU_MIXED (FP32 transforms and
- *          products, FP32 solve plus one FP64 refinement sweep, FP64 factors
- *          and boundary rows).
+ * precision STAU_FP64 (everything FP64) or STAU_MIXED (stau_step only: FP32
+ *          transforms and products; FP64 factorisation rounded to FP32 for the
+ *          sweeps; FP32 solve, FP64 residual of the full system (boundary rows
+ *          included) from the operator templates, one FP32 correction sweep,
+ *          FP64 accumulation; state, history and right-hand side FP64).  The
+ *          component calls (stau_nonlinear, stau_solve) and the adjoint run in
+ *          FP64 in either mode.
  * device   HIP device ordinal. */
 typedef struct stau_domain_desc {
   int32_t dim;

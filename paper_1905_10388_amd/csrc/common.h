@@ -306,4 +306,52 @@ __host__ __device__ inline double sys_entry(const SysDesc& d, const PencilCoef& 
   return v;
 }
 
+// ---------------------------------------------------------------------------
+// Row r of (a0 M~ + b0 L~) x~ for the real-scaled recombined system, from the
+// operator templates (no stored matrix): x_T = P^R x~ per variable, then the
+// T-to-U conversion C and derivative D of each equation (the same entries as
+// entry_T).  getx(m, var) returns x~ at column (m, var).
+// ---------------------------------------------------------------------------
+template <typename GX>
+__host__ __device__ inline double apply_row(const SysDesc& d, const PencilCoef& pc, int r, GX getx) {
+  const int N = d.N;
+  auto xT = [&](int var, int m) -> double {
+    if (m >= N || d.var_pos[var] < 0) return 0.0;
+    double v = getx(m, var);
+    if (m + 2 < N) v -= getx(m + 2, var);
+    return v;
+  };
+  auto Cv = [&](int var, int q) {
+    double v = xT(var, q) * (q == 0 ? 1.0 : 0.5);
+    if (q + 2 < N) v -= 0.5 * xT(var, q + 2);
+    return v;
+  };
+  auto Dv = [&](int var, int q) { return q + 1 < N ? 2.0 * (q + 1) * xT(var, q + 1) : 0.0; };
+  if (r < d.kb) {
+    int q = d.bc_var[r];
+    if (pc.mean && q == VW && d.bc_side[r] == 1) q = VP;
+    return pc.b0 * (getx(0, q) + (d.bc_side[r] == 0 ? -1.0 : 1.0) * getx(1, q));  // T_m(-1), T_m(1)
+  }
+  int epos;
+  const int n = sys_row_mode(d, r, &epos);
+  const int eq = d.eq_at[epos];
+  const double k2 = pc.kx * pc.kx + pc.ky * pc.ky;
+  const double ak = pc.a0 + pc.b0 * pc.kappa * k2, an = pc.a0 + pc.b0 * pc.nu * k2;
+  switch (eq) {
+    case EB: return ak * Cv(VB, n) - pc.b0 * pc.kappa * Dv(VBZ, n);
+    case EU: return an * Cv(VU, n) - pc.b0 * pc.nu * Dv(VUZ, n) - pc.b0 * pc.kx * Cv(VP, n);
+    case EV: return an * Cv(VV, n) - pc.b0 * pc.nu * Dv(VVZ, n) - pc.b0 * pc.ky * Cv(VP, n);
+    case EW:
+      return an * Cv(VW, n) - pc.b0 * pc.nu * Dv(VWZ, n) + pc.b0 * Dv(VP, n) -
+             pc.b0 * pc.buoy * Cv(VB, n);
+    case EBZ: return pc.b0 * (Cv(VBZ, n) - Dv(VB, n));
+    case EUZ: return pc.b0 * (Cv(VUZ, n) - Dv(VU, n));
+    case EVZ: return pc.b0 * (Cv(VVZ, n) - Dv(VV, n));
+    case EWZ: return pc.b0 * (Cv(VWZ, n) - Dv(VW, n));
+    case EC: return pc.b0 * (pc.kx * xT(VU, n) + pc.ky * xT(VV, n) + xT(VWZ, n));
+  }
+  return 0.0;
+}
+
+
 }  // namespace stau

@@ -24,11 +24,17 @@ constexpr int kCW = 64;  // factor column window (>= kv + 1)
 // complete before this point and cannot be sunk past it by the scheduler.
 __device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
 
+__device__ __forceinline__ void pin(float& x) { asm volatile("" : "+v"(x)); }
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float readlane_t(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double readlane_t(double v, int lane) { return readlane_d(v, lane); }
 
 __device__ __forceinline__ PencilCoef pencil_coef(const PencilArgs& a, int p, double a0, double b0) {
   PencilCoef pc;
@@ -199,6 +205,149 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
 // sweep.  FW / BW are compile-time so that window lanes are immediates and
 // the y / x stores provably do not alias the b loads ahead of them.
 // ---------------------------------------------------------------------------
+// Forward (L, with the LAPACK interchanges through physical slots) and
+// backward (U, circular window) sweeps of one real right-hand side b of
+// length n (padded: BW zeros before, FW after, chunk multiple).  One
+// wavefront; the two wavefronts of a block run them on their own vectors and
+// share the factor chunks staged in fbuf.
+template <typename T, int FW, int BW, int CH>
+__device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uint32_t* __restrict__ sw,
+                                       const T* __restrict__ Up, T* fbuf, int n, int tid) {
+  const int lane = tid & (kWave - 1);
+  const int nch = (n + CH - 1) / CH;
+  const int npad = nch * CH;
+
+  // ---- forward sweep: window of FW pending rows, physical slots 0..FW-1 ----
+  constexpr int LPT = CH * FW / (2 * kWave);
+  constexpr int G = 16;  // insert values preloaded per group of columns
+  T regL[LPT];
+  uint32_t regS = 0;
+  uint32_t* sbuf = (uint32_t*)(fbuf + 2 * CH * BW);  // [2][CH/4] words
+  auto loadL = [&](int c) {
+    const int base = c * CH * FW, lim = n * FW;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const int idx = tid + k * 2 * kWave;
+      regL[k] = base + idx < lim ? Lp[base + idx] : (T)0;
+    }
+    const int w4 = c * (CH / 4) + tid;
+    regS = (tid < CH / 4 && 4 * w4 < n) ? sw[w4] : 0u;
+  };
+  auto storeL = [&](int buf) {
+    T* dst = fbuf + buf * CH * BW;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) dst[tid + k * 2 * kWave] = regL[k];
+    if (tid < CH / 4) sbuf[buf * (CH / 4) + tid] = regS;
+  };
+  loadL(0);
+  storeL(0);
+  __syncthreads();
+  const int lf = lane & (FW - 1);
+  T w = lane < FW ? b[lane] : (T)0;
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) loadL(c + 1);
+    const int j0 = c * CH;
+    const T* Lc = fbuf + (c & 1) * CH * BW + lf;
+    const uint32_t* Sc = sbuf + (c & 1) * (CH / 4);
+    uint32_t sword[CH / 4];
+#pragma unroll
+    for (int k = 0; k < CH / 4; ++k) sword[k] = __builtin_amdgcn_readfirstlane(Sc[k]);
+    T lc[CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) lc[t] = Lc[t * FW];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) pin(lc[t]);
+    T* yo = b + j0;
+    T nv[2][G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) nv[0][k] = yo[k + FW];
+#pragma unroll
+    for (int k = 0; k < G; ++k) pin(nv[0][k]);
+#pragma unroll
+    for (int g = 0; g < CH / G; ++g) {
+      if (g + 1 < CH / G) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) nv[(g + 1) & 1][k] = yo[(g + 1) * G + k + FW];
+      }
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int t = g * G + k;
+        const int s = (sword[t >> 2] >> (8 * (t & 3))) & 0xff;
+        const T y = readlane_t(w, s);
+        yo[t] = y;  // every lane stores the same value
+        w = lane == s ? nv[g & 1][k] : fma(-lc[t], y, w);
+      }
+      if (g + 1 < CH / G) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) pin(nv[(g + 1) & 1][k]);
+      }
+    }
+    if (c + 1 < nch) storeL((c + 1) & 1);
+    __syncthreads();
+  }
+
+  // ---- backward sweep: lane l carries the row r = l (mod BW) of [j-BW+1, j]
+  constexpr int UPT = CH * BW / (2 * kWave);
+  T regU[UPT];
+  auto loadU = [&](int c) {
+    const int base = c * CH * BW, lim = n * BW;
+#pragma unroll
+    for (int k = 0; k < UPT; ++k) {
+      const int idx = tid + k * 2 * kWave;
+      regU[k] = base + idx < lim ? Up[base + idx] : (T)0;
+    }
+  };
+  auto storeU = [&](int buf) {
+    T* dst = fbuf + buf * CH * BW;
+#pragma unroll
+    for (int k = 0; k < UPT; ++k) dst[tid + k * 2 * kWave] = regU[k];
+  };
+  loadU(nch - 1);
+  storeU((nch - 1) & 1);
+  __syncthreads();
+  const int lb = lane & (BW - 1);
+  // rows npad-BW .. npad-1 (rows >= n hold finite padding; their U
+  // coefficients are zero)
+  w = b[npad - BW + lb];
+  for (int c = nch - 1; c >= 0; --c) {
+    if (c > 0) loadU(c - 1);
+    const T* Uc = fbuf + (c & 1) * CH * BW + lb;
+    T uc[CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) uc[t] = Uc[t * BW];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) pin(uc[t]);
+    T* xo = b + c * CH;
+    constexpr int NG = CH / G;
+    T nv[2][G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) nv[(NG - 1) & 1][k] = xo[(NG - 1) * G + k - BW];
+#pragma unroll
+    for (int k = 0; k < G; ++k) pin(nv[(NG - 1) & 1][k]);
+#pragma unroll
+    for (int g = NG - 1; g >= 0; --g) {
+      if (g > 0) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) nv[(g - 1) & 1][k] = xo[(g - 1) * G + k - BW];
+      }
+#pragma unroll
+      for (int k = G - 1; k >= 0; --k) {
+        const int t = g * G + k;
+        const int sj = t % BW;
+        const T x = readlane_t(w * uc[t], sj);
+        xo[t] = x;  // every lane stores the same value
+        w = lb == sj ? nv[g & 1][k] : fma(-uc[t], x, w);
+      }
+      if (g > 0) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) pin(nv[(g - 1) & 1][k]);
+      }
+    }
+    if (c > 0) storeU((c - 1) & 1);
+    __syncthreads();
+  }
+}
+
 template <int FW, int BW, int CH>
 __global__ void __launch_bounds__(2 * kWave) solve_kernel(PencilArgs a,
                                                           const double2* __restrict__ Bev,
@@ -262,139 +411,8 @@ __global__ void __launch_bounds__(2 * kWave) solve_kernel(PencilArgs a,
     bim[r] = vi;
   }
   double* b = wv == 0 ? bre : bim;
-  const double* Lp = Lf + (size_t)p * n * FW;
-  const uint32_t* sw = (const uint32_t*)(sl + (size_t)p * n);  // n % 4 == 0 (4-byte aligned)
-  const double* Up = Uf + (size_t)p * n * BW;
-
-  // ---- forward sweep: window of FW pending rows, physical slots 0..FW-1 ----
-  constexpr int LPT = CH * FW / (2 * kWave);
-  constexpr int G = 16;  // insert values preloaded per group of columns
-  double regL[LPT];
-  uint32_t regS = 0;
-  uint32_t* sbuf = (uint32_t*)(fbuf + 2 * CH * BW);  // [2][CH/4] words
-  auto loadL = [&](int c) {
-    const int base = c * CH * FW, lim = n * FW;
-#pragma unroll
-    for (int k = 0; k < LPT; ++k) {
-      const int idx = tid + k * 2 * kWave;
-      regL[k] = base + idx < lim ? Lp[base + idx] : 0.0;
-    }
-    const int w4 = c * (CH / 4) + tid;
-    regS = (tid < CH / 4 && 4 * w4 < n) ? sw[w4] : 0u;
-  };
-  auto storeL = [&](int buf) {
-    double* dst = fbuf + buf * CH * BW;
-#pragma unroll
-    for (int k = 0; k < LPT; ++k) dst[tid + k * 2 * kWave] = regL[k];
-    if (tid < CH / 4) sbuf[buf * (CH / 4) + tid] = regS;
-  };
-  loadL(0);
-  storeL(0);
-  __syncthreads();
-  const int lf = lane & (FW - 1);
-  double w = lane < FW ? b[lane] : 0.0;
-  for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) loadL(c + 1);
-    const int j0 = c * CH;
-    const double* Lc = fbuf + (c & 1) * CH * BW + lf;
-    const uint32_t* Sc = sbuf + (c & 1) * (CH / 4);
-    uint32_t sword[CH / 4];
-#pragma unroll
-    for (int k = 0; k < CH / 4; ++k) sword[k] = __builtin_amdgcn_readfirstlane(Sc[k]);
-    double lc[CH];
-#pragma unroll
-    for (int t = 0; t < CH; ++t) lc[t] = Lc[t * FW];
-#pragma unroll
-    for (int t = 0; t < CH; ++t) pin(lc[t]);
-    double* yo = b + j0;
-    double nv[2][G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) nv[0][k] = yo[k + FW];
-#pragma unroll
-    for (int k = 0; k < G; ++k) pin(nv[0][k]);
-#pragma unroll
-    for (int g = 0; g < CH / G; ++g) {
-      if (g + 1 < CH / G) {
-#pragma unroll
-        for (int k = 0; k < G; ++k) nv[(g + 1) & 1][k] = yo[(g + 1) * G + k + FW];
-      }
-#pragma unroll
-      for (int k = 0; k < G; ++k) {
-        const int t = g * G + k;
-        const int s = (sword[t >> 2] >> (8 * (t & 3))) & 0xff;
-        const double y = readlane_d(w, s);
-        yo[t] = y;  // every lane stores the same value
-        w = lane == s ? nv[g & 1][k] : fma(-lc[t], y, w);
-      }
-      if (g + 1 < CH / G) {
-#pragma unroll
-        for (int k = 0; k < G; ++k) pin(nv[(g + 1) & 1][k]);
-      }
-    }
-    if (c + 1 < nch) storeL((c + 1) & 1);
-    __syncthreads();
-  }
-
-  // ---- backward sweep: lane l carries the row r = l (mod BW) of [j-BW+1, j]
-  constexpr int UPT = CH * BW / (2 * kWave);
-  double regU[UPT];
-  auto loadU = [&](int c) {
-    const int base = c * CH * BW, lim = n * BW;
-#pragma unroll
-    for (int k = 0; k < UPT; ++k) {
-      const int idx = tid + k * 2 * kWave;
-      regU[k] = base + idx < lim ? Up[base + idx] : 0.0;
-    }
-  };
-  auto storeU = [&](int buf) {
-    double* dst = fbuf + buf * CH * BW;
-#pragma unroll
-    for (int k = 0; k < UPT; ++k) dst[tid + k * 2 * kWave] = regU[k];
-  };
-  loadU(nch - 1);
-  storeU((nch - 1) & 1);
-  __syncthreads();
-  const int lb = lane & (BW - 1);
-  // rows npad-BW .. npad-1 (rows >= n hold finite padding; their U
-  // coefficients are zero)
-  w = b[npad - BW + lb];
-  for (int c = nch - 1; c >= 0; --c) {
-    if (c > 0) loadU(c - 1);
-    const double* Uc = fbuf + (c & 1) * CH * BW + lb;
-    double uc[CH];
-#pragma unroll
-    for (int t = 0; t < CH; ++t) uc[t] = Uc[t * BW];
-#pragma unroll
-    for (int t = 0; t < CH; ++t) pin(uc[t]);
-    double* xo = b + c * CH;
-    constexpr int NG = CH / G;
-    double nv[2][G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) nv[(NG - 1) & 1][k] = xo[(NG - 1) * G + k - BW];
-#pragma unroll
-    for (int k = 0; k < G; ++k) pin(nv[(NG - 1) & 1][k]);
-#pragma unroll
-    for (int g = NG - 1; g >= 0; --g) {
-      if (g > 0) {
-#pragma unroll
-        for (int k = 0; k < G; ++k) nv[(g - 1) & 1][k] = xo[(g - 1) * G + k - BW];
-      }
-#pragma unroll
-      for (int k = G - 1; k >= 0; --k) {
-        const int t = g * G + k;
-        const int sj = t % BW;
-        const double x = readlane_d(w * uc[t], sj);
-        xo[t] = x;  // every lane stores the same value
-        w = lb == sj ? nv[g & 1][k] : fma(-uc[t], x, w);
-      }
-      if (g > 0) {
-#pragma unroll
-        for (int k = 0; k < G; ++k) pin(nv[(g - 1) & 1][k]);
-      }
-    }
-    if (c > 0) storeU((c - 1) & 1);
-    __syncthreads();
-  }
+  sweeps<double, FW, BW, CH>(b, Lf + (size_t)p * n * FW, (const uint32_t*)(sl + (size_t)p * n),
+                             Uf + (size_t)p * n * BW, fbuf, n, tid);
   // --- X = P^R x~, undo the real scaling, state layout
   for (int i = tid; i < S * N; i += 2 * kWave) {
     const int vabi = i / N, m = i - vabi * N;
@@ -630,6 +648,118 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
 }
 
 // ---------------------------------------------------------------------------
+// Mixed-precision solve: FP32 sweeps with FP32 copies of the FP64 factors,
+// FP64 residual r = b - A x^ from the operator templates (boundary rows
+// included), one FP32 correction sweep, x = x^ + d accumulated in FP64.
+// The right-hand side (boundary values included) and the output stay FP64.
+// ---------------------------------------------------------------------------
+template <int FW, int BW, int CH>
+__global__ void __launch_bounds__(2 * kWave) solve_mixed_kernel(
+    PencilArgs a, double a0, double b0, const double2* __restrict__ Bev,
+    const float* __restrict__ Lf, const uint8_t* __restrict__ sl, const float* __restrict__ Uf,
+    double2* __restrict__ X) {
+  extern __shared__ double lds[];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = a.n, N = a.desc.N, S = a.desc.S, kb = a.desc.kb, ne = a.desc.ne;
+  const SysDesc& d = a.desc;
+  double2* Xp = X + (size_t)p * S * N;
+  if (!pencil_active(a, p)) {
+    for (int i = tid; i < S * N; i += 2 * kWave) Xp[i] = make_double2(0.0, 0.0);
+    return;
+  }
+  const PencilCoef pc = pencil_coef(a, p, a0, b0);
+  const int nch = (n + CH - 1) / CH;
+  const int npad = nch * CH;
+  const int span = BW + npad + FW;
+  double* b64r = lds;
+  double* b64i = lds + n;
+  float* f0 = (float*)(lds + 2 * n);
+  float* w32r = f0 + BW;
+  float* w32i = f0 + span + BW;
+  float* xhr = f0 + 2 * span;
+  float* xhi = xhr + n;
+  float* fbuf = xhi + n;  // [2][CH*BW] floats, then slot words
+  const double2* Bp = Bev + (size_t)p * ne * N;
+  for (int r = tid - BW; r < npad + FW; r += 2 * kWave) {
+    double vr = 0.0, vi = 0.0;
+    if (r >= 0 && r < kb) {
+      if (pc.mean && d.bc_var[r] == VB) vr = d.bc_side[r] == 0 ? a.b_bottom : a.b_top;
+    } else if (r >= kb && r < n) {
+      int epos;
+      const int m = sys_row_mode(d, r, &epos);
+      const int eq = d.eq_at[epos];
+      int e = -1;
+      if (eq == EB) e = 0;
+      if (eq == EU) e = 1;
+      if (eq == EV) e = 2;
+      if (eq == EW) e = ne - 1;
+      if (e >= 0 && m <= N - 2) {
+        double2 v = Bp[e * N + m];
+        if (eq == EU || eq == EV) {
+          vr = -v.y;
+          vi = v.x;
+        } else {
+          vr = v.x;
+          vi = v.y;
+        }
+      }
+    }
+    if (r >= 0 && r < n) {
+      b64r[r] = vr;
+      b64i[r] = vi;
+    }
+    w32r[r] = (float)vr;
+    w32i[r] = (float)vi;
+  }
+  float* w = wv == 0 ? w32r : w32i;
+  float* xh = wv == 0 ? xhr : xhi;
+  double* b64 = wv == 0 ? b64r : b64i;
+  const float* Lp = Lf + (size_t)p * n * FW;
+  const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * n);
+  const float* Up = Uf + (size_t)p * n * BW;
+  sweeps<float, FW, BW, CH>(w, Lp, swp, Up, fbuf, n, tid);
+  for (int r = lane; r < n; r += kWave) xh[r] = w[r];
+  __syncthreads();
+  for (int r = lane; r < npad + FW; r += kWave) {
+    if (r < n) {
+      const double ax =
+          apply_row(d, pc, r, [&](int m, int var) { return (double)xh[m * S + d.var_pos[var]]; });
+      w[r] = (float)(b64[r] - ax);
+    } else {
+      w[r] = 0.0f;
+    }
+  }
+  __syncthreads();
+  sweeps<float, FW, BW, CH>(w, Lp, swp, Up, fbuf, n, tid);
+  for (int r = lane; r < n; r += kWave) b64[r] = (double)xh[r] + (double)w[r];
+  __syncthreads();
+  for (int i = tid; i < S * N; i += 2 * kWave) {
+    const int vabi = i / N, m = i - vabi * N;
+    const int var = a.var_of_abi[vabi];
+    const int pos = d.var_pos[var];
+    double xr = b64r[m * S + pos], xi = b64i[m * S + pos];
+    if (m + 2 < N) {
+      xr -= b64r[(m + 2) * S + pos];
+      xi -= b64i[(m + 2) * S + pos];
+    }
+    if (var == VU || var == VUZ || var == VV || var == VVZ)
+      Xp[i] = make_double2(xi, -xr);
+    else
+      Xp[i] = make_double2(xr, xi);
+  }
+}
+
+__global__ void round_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
+                                    size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, uint8_t* sl,
@@ -663,6 +793,38 @@ hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, 
   if (a.FW == 16 && a.BW == 64) return launch_solve_t<16, 64>(a, Bev, Lf, sl, Uf, X, st);
   if (a.FW == 32 && a.BW == 64) return launch_solve_t<32, 64>(a, Bev, Lf, sl, Uf, X, st);
   return hipErrorInvalidValue;
+}
+
+template <int FW, int BW>
+static hipError_t launch_solve_mixed_t(const PencilArgs& a, double a0, double b0, const void* Bev,
+                                       const float* Lf, const uint8_t* sl, const float* Uf,
+                                       void* X, hipStream_t st) {
+  const int npad = (a.n + kCH - 1) / kCH * kCH;
+  const int span = BW + npad + FW;
+  size_t lds = (size_t)2 * a.n * sizeof(double) +
+               (size_t)(2 * span + 2 * a.n + 2 * kCH * BW) * sizeof(float) + 2 * kCH;
+  auto fn = solve_mixed_kernel<FW, BW, kCH>;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(fn, dim3(a.P), dim3(2 * kWave), lds, st, a, a0, b0, (const double2*)Bev, Lf,
+                     sl, Uf, (double2*)X);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_mixed(const PencilArgs& a, double a0, double b0, const void* Bev,
+                              const float* Lf, const uint8_t* sl, const float* Uf, void* X,
+                              hipStream_t st) {
+  if (a.FW == 8 && a.BW == 32) return launch_solve_mixed_t<8, 32>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
+  if (a.FW == 8 && a.BW == 64) return launch_solve_mixed_t<8, 64>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
+  if (a.FW == 16 && a.BW == 32) return launch_solve_mixed_t<16, 32>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
+  if (a.FW == 16 && a.BW == 64) return launch_solve_mixed_t<16, 64>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
+  if (a.FW == 32 && a.BW == 64) return launch_solve_mixed_t<32, 64>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_round_f32(const double* src, float* dst, size_t count, hipStream_t st) {
+  hipLaunchKernelGGL(round_to_f32_kernel, dim3(1024), dim3(256), 0, st, src, dst, count);
+  return hipGetLastError();
 }
 
 template <int FW, int BW>

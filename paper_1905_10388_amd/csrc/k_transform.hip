@@ -22,6 +22,38 @@ __device__ __forceinline__ cd ld2(const double2* p) {
 }
 __device__ __forceinline__ void st2(double2* p, cd v) { *p = make_double2(v.x, v.y); }
 
+// storage of complex T in workspaces (double2 / float2)
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+  using type = double2;
+};
+template <>
+struct V2<float> {
+  using type = float2;
+};
+template <typename T>
+__device__ __forceinline__ cpx<T> ldv(const typename V2<T>::type* p) {
+  auto v = *p;
+  return mk<T>(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void stv(typename V2<T>::type* p, cpx<T> v) {
+  typename V2<T>::type o;
+  o.x = v.x;
+  o.y = v.y;
+  *p = o;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> tw_of(const XformArgs& a, const void* t64, const void* t32, int i) {
+  if constexpr (sizeof(T) == 8) return ld2((const double2*)t64 + i);
+  else {
+    const float2 v = ((const float2*)t32)[i];
+    return mk<float>(v.x, v.y);
+  }
+}
+
 __device__ __forceinline__ double kx_of(const XformArgs& a, int p) {
   const int ix = a.dim == 2 ? p : p % a.Px;
   return a.two_pi_over_Lx * (double)ix;
@@ -43,12 +75,13 @@ __device__ __forceinline__ bool active(const XformArgs& a, int p) {
 // Backward z (DCT-III with padding N -> M): g_j = sum_{n<N} c_n T_n(z_j)
 // for every field of `fl` and TP pencils per block.
 // ---------------------------------------------------------------------------
-template <int MAXBF>
+template <int MAXBF, typename T>
 __global__ void __launch_bounds__(256) zb_kernel(XformArgs a, FieldList fl,
                                                  const double2* __restrict__ X,
-                                                 double2* __restrict__ G, int TP) {
+                                                 typename V2<T>::type* __restrict__ G, int TP) {
   extern __shared__ double2 smem[];
-  cd* buf = (cd*)smem;
+  using cT = cpx<T>;
+  cT* buf = (cT*)smem;
   const int f = blockIdx.y;
   const int p0 = blockIdx.x * TP;
   const int M = a.M, N = a.N, S = fl.src_S ? fl.src_S : a.S;
@@ -58,7 +91,7 @@ __global__ void __launch_bounds__(256) zb_kernel(XformArgs a, FieldList fl,
   for (int idx = tid; idx < TP * M; idx += nt) {
     const int s = idx / M, nn = idx - s * M;
     const int p = p0 + s;
-    cd z = mk(0.0, 0.0);
+    cT z = mk<T>(0, 0);
     if (active(a, p)) {
       const double2* col = X + ((size_t)p * S + var) * N;
       double kk = 0.0;
@@ -76,18 +109,27 @@ __global__ void __launch_bounds__(256) zb_kernel(XformArgs a, FieldList fl,
       cd yn = Yp(nn);
       cd ym = nn == 0 ? mk(0.0, 0.0) : Yp(M - nn);
       cd t = mk(yn.x + ym.y, yn.y - ym.x);  // Y_n - i Y_{M-n}
-      z = cmul(ld2(a.dctz + nn), t);
+      if constexpr (sizeof(T) == 8) {
+        cd zz = cmul(ld2(a.dctz + nn), t);
+        z = mk<T>(zz.x, zz.y);
+      } else {
+        cT tt = mk<T>((T)t.x, (T)t.y);
+        z = cmul(tw_of<T>(a, a.dctz, a.dctz32, nn), tt);
+      }
     }
     buf[idx] = z;
   }
   __syncthreads();
-  fft_lds<+1, MAXBF>(buf, M, TP, (const cd*)a.twz, tid, nt);
+  if constexpr (sizeof(T) == 8)
+    fft_lds<+1, MAXBF>(buf, M, TP, (const cT*)a.twz, tid, nt);
+  else
+    fft_lds<+1, MAXBF>(buf, M, TP, (const cT*)a.twz32, tid, nt);
   for (int idx = tid; idx < TP * M; idx += nt) {
     const int jz = idx / TP, s = idx - jz * TP;
     const int p = p0 + s;
     if (p >= a.P) continue;
     const int src = (jz & 1) ? (M - 1 - (jz >> 1)) : (jz >> 1);
-    st2(G + ((size_t)f * M + jz) * a.P + p, buf[s * M + src]);
+    stv<T>(G + ((size_t)f * M + jz) * a.P + p, buf[s * M + src]);
   }
 }
 
@@ -99,11 +141,13 @@ __global__ void __launch_bounds__(256) zb_kernel(XformArgs a, FieldList fl,
 //   B_n = c1 F~_n - a1 MX_n + [c2 F~old_n - a2 MXold_n],
 //   history hist_cur[p][0][e][n] = F~_n, hist_cur[p][1][e][n] = MX_n.
 // ---------------------------------------------------------------------------
-template <int MAXBF, int MAXIT>
-__global__ void __launch_bounds__(256) zf_kernel(XformArgs a, const double2* __restrict__ H,
+template <int MAXBF, int MAXIT, typename T>
+__global__ void __launch_bounds__(256) zf_kernel(XformArgs a,
+                                                 const typename V2<T>::type* __restrict__ H,
                                                  double2* __restrict__ out, RhsArgs r, int TP) {
   extern __shared__ double2 smem[];
-  cd* buf = (cd*)smem;
+  using cT = cpx<T>;
+  cT* buf = (cT*)smem;
   const int e = blockIdx.y;
   const int p0 = blockIdx.x * TP;
   const int M = a.M, N = a.N, ne = a.ne;
@@ -111,26 +155,29 @@ __global__ void __launch_bounds__(256) zf_kernel(XformArgs a, const double2* __r
   for (int idx = tid; idx < TP * M; idx += nt) {
     const int jz = idx / TP, s = idx - jz * TP;
     const int p = p0 + s;
-    cd y = mk(0.0, 0.0);
-    if (p < a.P) y = ld2(H + ((size_t)e * M + jz) * a.P + p);
+    cT y = mk<T>(0, 0);
+    if (p < a.P) y = ldv<T>(H + ((size_t)e * M + jz) * a.P + p);
     const int dst = (jz & 1) ? (M - 1 - (jz >> 1)) : (jz >> 1);
     buf[s * M + dst] = y;
   }
   __syncthreads();
-  fft_lds<-1, MAXBF>(buf, M, TP, (const cd*)a.twz, tid, nt);
-  cd c[MAXIT];
-  const double invM = 1.0 / (double)M;
+  if constexpr (sizeof(T) == 8)
+    fft_lds<-1, MAXBF>(buf, M, TP, (const cT*)a.twz, tid, nt);
+  else
+    fft_lds<-1, MAXBF>(buf, M, TP, (const cT*)a.twz32, tid, nt);
+  cT c[MAXIT];
+  const T invM = (T)1 / (T)M;
 #pragma unroll
   for (int it = 0; it < MAXIT; ++it) {
     const int idx = tid + it * nt;
     if (idx < TP * N) {
       const int s = idx / N, nn = idx - s * N;
-      cd V = buf[s * M + nn];
-      cd Vm = buf[s * M + (nn == 0 ? 0 : M - nn)];
-      cd w = conj(ld2(a.dctz + nn));
-      cd P = cmul(w, V), Q = cmul(w, conj(Vm));
-      cd Y = mk(0.5 * (P.x + Q.x), 0.5 * (P.y - Q.y));
-      double sc = (nn == 0 ? 1.0 : 2.0) * invM;
+      cT V = buf[s * M + nn];
+      cT Vm = buf[s * M + (nn == 0 ? 0 : M - nn)];
+      cT w = conj(tw_of<T>(a, a.dctz, a.dctz32, nn));
+      cT P = cmul(w, V), Q = cmul(w, conj(Vm));
+      cT Y = mk<T>((T)0.5 * (P.x + Q.x), (T)0.5 * (P.y - Q.y));
+      T sc = (nn == 0 ? (T)1 : (T)2) * invM;
       if (nn & 1) sc = -sc;
       c[it] = scale(Y, sc);
     }
@@ -150,15 +197,19 @@ __global__ void __launch_bounds__(256) zf_kernel(XformArgs a, const double2* __r
     const int p = p0 + s;
     if (p >= a.P) continue;
     const size_t o = ((size_t)p * ne + e) * N + nn;
+    auto cget = [&](int m) -> cd {
+      const cT v = buf[s * M + m];
+      return mk((double)v.x, (double)v.y);
+    };
     if (r.mode == 0) {
-      st2(out + o, buf[s * M + nn]);
+      st2(out + o, cget(nn));
       continue;
     }
     cd Ft = mk(0.0, 0.0), MX = mk(0.0, 0.0), B = mk(0.0, 0.0);
     if (active(a, p) && nn <= N - 2) {
       const double cnn = nn == 0 ? 1.0 : 0.5;
-      Ft = scale(buf[s * M + nn], cnn);
-      if (nn + 2 < N) Ft = Ft - scale(buf[s * M + nn + 2], 0.5);
+      Ft = scale(cget(nn), cnn);
+      if (nn + 2 < N) Ft = Ft - scale(cget(nn + 2), 0.5);
       const double2* xc = r.Xprev + ((size_t)p * a.S + (e + 1)) * N;
       MX = scale(ld2(xc + nn), cnn);
       if (nn + 2 < N) MX = MX - scale(ld2(xc + nn + 2), 0.5);
@@ -184,32 +235,35 @@ __global__ void __launch_bounds__(256) zf_kernel(XformArgs a, const double2* __r
 // and two real-to-complex transforms, truncated to k < Nx/2 and scaled 1/L.
 // G field order: u, w, b_x, b_z, u_x, u_z, w_x, w_z.
 // ---------------------------------------------------------------------------
-template <int MAXBF, int PTS, int NT>
-__global__ void __launch_bounds__(NT) xpass_kernel(XformArgs a, const double2* __restrict__ G,
-                                                   double2* __restrict__ H) {
+template <int MAXBF, int PTS, int NT, typename T>
+__global__ void __launch_bounds__(NT) xpass_kernel(XformArgs a,
+                                                   const typename V2<T>::type* __restrict__ G,
+                                                   typename V2<T>::type* __restrict__ H) {
   extern __shared__ double2 smem[];
-  cd* buf = (cd*)smem;
+  using cT = cpx<T>;
+  using S2 = typename V2<T>::type;
+  cT* buf = (cT*)smem;
   const int jz = blockIdx.x;
   const int M = a.M, L = a.L, Pa = a.Pa, P = a.P;
   const int tid = threadIdx.x;
   constexpr int nt = NT;
-  const cd* tw = (const cd*)a.twx;
+  const cT* tw = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
 
-  auto c2r_pair = [&](int fa, int fb, double* ra, double* rb) {
-    const double2* A = G + ((size_t)fa * M + jz) * P;
-    const double2* B = G + ((size_t)fb * M + jz) * P;
+  auto c2r_pair = [&](int fa, int fb, T* ra, T* rb) {
+    const S2* A = G + ((size_t)fa * M + jz) * P;
+    const S2* B = G + ((size_t)fb * M + jz) * P;
     for (int k = tid; k < L; k += nt) {
-      cd z = mk(0.0, 0.0);
+      cT z = mk<T>(0, 0);
       if (k < Pa) {
-        cd Ak = ld2(A + k), Bk = ld2(B + k);
+        cT Ak = ldv<T>(A + k), Bk = ldv<T>(B + k);
         if (k == 0) {
-          Ak.y = 0.0;
-          Bk.y = 0.0;
+          Ak.y = 0;
+          Bk.y = 0;
         }
-        z = mk(Ak.x - Bk.y, Ak.y + Bk.x);
+        z = mk<T>(Ak.x - Bk.y, Ak.y + Bk.x);
       } else if (k > L - Pa) {
-        cd Ak = ld2(A + (L - k)), Bk = ld2(B + (L - k));
-        z = mk(Ak.x + Bk.y, -Ak.y + Bk.x);
+        cT Ak = ldv<T>(A + (L - k)), Bk = ldv<T>(B + (L - k));
+        z = mk<T>(Ak.x + Bk.y, -Ak.y + Bk.x);
       }
       buf[k] = z;
     }
@@ -226,7 +280,7 @@ __global__ void __launch_bounds__(NT) xpass_kernel(XformArgs a, const double2* _
     __syncthreads();
   };
 
-  double u[PTS], w[PTS], t1[PTS], t2[PTS], nb[PTS], nu[PTS], nw[PTS];
+  T u[PTS], w[PTS], t1[PTS], t2[PTS], nb[PTS], nu[PTS], nw[PTS];
   c2r_pair(0, 1, u, w);
   c2r_pair(2, 3, t1, t2);
 #pragma unroll
@@ -238,42 +292,43 @@ __global__ void __launch_bounds__(NT) xpass_kernel(XformArgs a, const double2* _
 #pragma unroll
   for (int q = 0; q < PTS; ++q) nw[q] = -(u[q] * t1[q] + w[q] * t2[q]);
 
-  const double invL = 1.0 / (double)L;
+  const T invL = (T)1 / (T)L;
+  const T half = (T)0.5;
   // N_b + i N_u
 #pragma unroll
   for (int q = 0; q < PTS; ++q) {
     const int i = tid + q * nt;
-    if (i < L) buf[i] = mk(nb[q], nu[q]);
+    if (i < L) buf[i] = mk<T>(nb[q], nu[q]);
   }
   __syncthreads();
   fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, nt);
   {
-    double2* Ha = H + ((size_t)0 * M + jz) * P;
-    double2* Hb = H + ((size_t)1 * M + jz) * P;
+    S2* Ha = H + ((size_t)0 * M + jz) * P;
+    S2* Hb = H + ((size_t)1 * M + jz) * P;
     for (int k = tid; k < P; k += nt) {
-      cd A = mk(0.0, 0.0), Bv = mk(0.0, 0.0);
+      cT A = mk<T>(0, 0), Bv = mk<T>(0, 0);
       if (k < Pa) {
-        cd Zk = buf[k], Zm = buf[k == 0 ? 0 : L - k];
-        A = mk(0.5 * (Zk.x + Zm.x) * invL, 0.5 * (Zk.y - Zm.y) * invL);
-        Bv = mk(0.5 * (Zk.y + Zm.y) * invL, -0.5 * (Zk.x - Zm.x) * invL);
+        cT Zk = buf[k], Zm = buf[k == 0 ? 0 : L - k];
+        A = mk<T>(half * (Zk.x + Zm.x) * invL, half * (Zk.y - Zm.y) * invL);
+        Bv = mk<T>(half * (Zk.y + Zm.y) * invL, -half * (Zk.x - Zm.x) * invL);
       }
-      st2(Ha + k, A);
-      st2(Hb + k, Bv);
+      stv<T>(Ha + k, A);
+      stv<T>(Hb + k, Bv);
     }
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < PTS; ++q) {
     const int i = tid + q * nt;
-    if (i < L) buf[i] = mk(nw[q], 0.0);
+    if (i < L) buf[i] = mk<T>(nw[q], 0);
   }
   __syncthreads();
   fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, nt);
   {
-    double2* Hc = H + ((size_t)2 * M + jz) * P;
+    S2* Hc = H + ((size_t)2 * M + jz) * P;
     for (int k = tid; k < P; k += nt) {
-      cd A = k < Pa ? scale(buf[k], invL) : mk(0.0, 0.0);
-      st2(Hc + k, A);
+      cT A = k < Pa ? scale(buf[k], invL) : mk<T>(0, 0);
+      stv<T>(Hc + k, A);
     }
   }
 }
@@ -722,22 +777,34 @@ static int x_threads(int L) {
 }
 
 hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, void* G,
-                     hipStream_t st) {
+                     hipStream_t st, bool fp32) {
   const int TP = z_tile(a.M);
   dim3 grid((a.P + TP - 1) / TP, fl.nf);
-  size_t lds = (size_t)TP * a.M * sizeof(double2);
-  hipLaunchKernelGGL(zb_kernel<3>, grid, dim3(256), lds, st, a, fl, (const double2*)X,
-                     (double2*)G, TP);
+  if (fp32) {
+    size_t lds = (size_t)TP * a.M * sizeof(float2);
+    hipLaunchKernelGGL((zb_kernel<3, float>), grid, dim3(256), lds, st, a, fl, (const double2*)X,
+                       (float2*)G, TP);
+  } else {
+    size_t lds = (size_t)TP * a.M * sizeof(double2);
+    hipLaunchKernelGGL((zb_kernel<3, double>), grid, dim3(256), lds, st, a, fl, (const double2*)X,
+                       (double2*)G, TP);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
-                     hipStream_t st) {
+                     hipStream_t st, bool fp32) {
   const int TP = z_tile(a.M);
   dim3 grid((a.P + TP - 1) / TP, a.ne);
-  size_t lds = (size_t)TP * a.M * sizeof(double2);
-  hipLaunchKernelGGL((zf_kernel<3, 12>), grid, dim3(256), lds, st, a, (const double2*)H,
-                     (double2*)out, r, TP);
+  if (fp32) {
+    size_t lds = (size_t)TP * a.M * sizeof(float2);
+    hipLaunchKernelGGL((zf_kernel<3, 12, float>), grid, dim3(256), lds, st, a, (const float2*)H,
+                       (double2*)out, r, TP);
+  } else {
+    size_t lds = (size_t)TP * a.M * sizeof(double2);
+    hipLaunchKernelGGL((zf_kernel<3, 12, double>), grid, dim3(256), lds, st, a, (const double2*)H,
+                       (double2*)out, r, TP);
+  }
   return hipGetLastError();
 }
 
@@ -745,24 +812,30 @@ static void allow_lds(const void* fn, size_t bytes) {
   if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int NT>
+template <int NT, typename T>
 static hipError_t launch_xpass_t(const XformArgs& a, const void* G, void* H, hipStream_t st) {
-  size_t lds = (size_t)a.L * sizeof(double2);
-  allow_lds((const void*)xpass_kernel<2, 6, NT>, lds);
-  hipLaunchKernelGGL((xpass_kernel<2, 6, NT>), dim3(a.M), dim3(NT), lds, st, a, (const double2*)G,
-                     (double2*)H);
+  using S2 = typename V2<T>::type;
+  size_t lds = (size_t)a.L * sizeof(S2);
+  allow_lds((const void*)xpass_kernel<2, 6, NT, T>, lds);
+  hipLaunchKernelGGL((xpass_kernel<2, 6, NT, T>), dim3(a.M), dim3(NT), lds, st, a, (const S2*)G,
+                     (S2*)H);
   return hipGetLastError();
 }
 
-hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st) {
+template <typename T>
+static hipError_t launch_xpass_T(const XformArgs& a, const void* G, void* H, hipStream_t st) {
   switch (x_threads(a.L)) {
-    case 64: return launch_xpass_t<64>(a, G, H, st);
-    case 128: return launch_xpass_t<128>(a, G, H, st);
-    case 256: return launch_xpass_t<256>(a, G, H, st);
-    case 512: return launch_xpass_t<512>(a, G, H, st);
-    case 1024: return launch_xpass_t<1024>(a, G, H, st);
+    case 64: return launch_xpass_t<64, T>(a, G, H, st);
+    case 128: return launch_xpass_t<128, T>(a, G, H, st);
+    case 256: return launch_xpass_t<256, T>(a, G, H, st);
+    case 512: return launch_xpass_t<512, T>(a, G, H, st);
+    case 1024: return launch_xpass_t<1024, T>(a, G, H, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st, bool fp32) {
+  return fp32 ? launch_xpass_T<float>(a, G, H, st) : launch_xpass_T<double>(a, G, H, st);
 }
 
 hipError_t launch_zadj(const XformArgs& a, const AccList& al, const void* Gbar, void* Xbar,

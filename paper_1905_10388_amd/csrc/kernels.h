@@ -32,6 +32,10 @@ struct XformArgs {
   const double2* dctz;  // e^{+i pi n / (2 M)}
   const double2* twx;   // e^{-2 pi i t / L}
   const double2* twy;   // e^{-2 pi i t / Ngy}
+  // FP32 copies (rounded from the FP64 tables) for the mixed-precision path
+  const float2* twz32;
+  const float2* dctz32;
+  const float2* twx32;
 };
 
 // Field list for the backward z transform: source variable index and
@@ -63,10 +67,16 @@ hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, 
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
                         const double* Uf, void* X, hipStream_t st);
 
+hipError_t launch_solve_mixed(const PencilArgs& a, double a0, double b0, const void* Bev,
+                              const float* Lf, const uint8_t* sl, const float* Uf, void* X,
+                              hipStream_t st);
+hipError_t launch_round_f32(const double* src, float* dst, size_t count, hipStream_t st);
+
 // transforms (2-D)
 hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, void* G,
-                     hipStream_t st);
-hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st);
+                     hipStream_t st, bool fp32 = false);
+hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st,
+                        bool fp32 = false);
 // forward z; mode 0 writes F[P][ne][N]; mode 1 assembles the SBDF right-hand
 // side and the history (see k_transform.hip)
 struct RhsArgs {
@@ -78,7 +88,7 @@ struct RhsArgs {
   const double2* hist_old;
 };
 hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
-                     hipStream_t st);
+                     hipStream_t st, bool fp32 = false);
 
 // adjoint path
 hipError_t launch_zadj(const XformArgs& a, const AccList& al, const void* Gbar, void* Xbar,

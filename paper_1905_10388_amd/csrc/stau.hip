@@ -58,6 +58,14 @@ void dct_table(int64_t m, std::vector<double2>& out) {
   }
 }
 
+int upload32(const std::vector<double2>& h, float2** d) {
+  std::vector<float2> f(h.size());
+  for (size_t i = 0; i < h.size(); ++i) f[i] = make_float2((float)h[i].x, (float)h[i].y);
+  HIP_TRY(hipMalloc((void**)d, f.size() * sizeof(float2)));
+  HIP_TRY(hipMemcpy(*d, f.data(), f.size() * sizeof(float2), hipMemcpyHostToDevice));
+  return STAU_OK;
+}
+
 template <typename T>
 int upload(const std::vector<T>& h, T** d) {
   HIP_TRY(hipMalloc((void**)d, h.size() * sizeof(T)));
@@ -72,6 +80,7 @@ struct stau_domain {
   int64_t Ngx = 0, Ngy = 1, Ngz = 0, Px = 0, P = 0, Pa = 0;
   double2 *twz = nullptr, *dctz = nullptr, *twx = nullptr, *twy = nullptr;
   double2 *twz1 = nullptr, *dctz1 = nullptr, *twx1 = nullptr;
+  float2 *twz32 = nullptr, *dctz32 = nullptr, *twx32 = nullptr;
 };
 
 struct stau_pencils {
@@ -93,6 +102,8 @@ struct stau_pencils {
     double* Lf = nullptr;
     uint8_t* sl = nullptr;
     double* Uf = nullptr;
+    float* Lf32 = nullptr;  // mixed precision: FP32 copies of the FP64 factors
+    float* Uf32 = nullptr;
     bool valid = false;
     double a0 = 0.0, b0 = 0.0;
     int64_t stamp = 0;
@@ -260,7 +271,8 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
   *out = nullptr;
   const stau_domain_desc& d = *desc;
   if (d.dim != 2) return fail(STAU_EUNSUPPORTED, "dim=%d: only 2-D domains are built", d.dim);
-  if (d.precision != STAU_FP64) return fail(STAU_EUNSUPPORTED, "precision %d not built", d.precision);
+  if (d.precision != STAU_FP64 && d.precision != STAU_MIXED)
+    return fail(STAU_EINVAL, "precision %d unknown", d.precision);
   if (std::fabs(d.dealias - 1.5) > 1e-15) return fail(STAU_EUNSUPPORTED, "dealias must be 1.5");
   if (!is_pow2(d.Nx) || d.Nx < 4 || d.Nx > 4096)
     return fail(STAU_EUNSUPPORTED, "Nx=%lld must be a power of two in [4, 4096]", (long long)d.Nx);
@@ -280,10 +292,13 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
   int rc;
   fft_table(dom->Ngz, t);
   if ((rc = upload(t, &dom->twz))) goto bad;
+  if ((rc = upload32(t, &dom->twz32))) goto bad;
   dct_table(dom->Ngz, t);
   if ((rc = upload(t, &dom->dctz))) goto bad;
+  if ((rc = upload32(t, &dom->dctz32))) goto bad;
   fft_table(dom->Ngx, t);
   if ((rc = upload(t, &dom->twx))) goto bad;
+  if ((rc = upload32(t, &dom->twx32))) goto bad;
   fft_table(d.Nz, t);
   if ((rc = upload(t, &dom->twz1))) goto bad;
   dct_table(d.Nz, t);
@@ -307,6 +322,9 @@ int stau_destroy_domain(stau_domain* dom) {
   hipFree(dom->twz1);
   hipFree(dom->dctz1);
   hipFree(dom->twx1);
+  hipFree(dom->twz32);
+  hipFree(dom->dctz32);
+  hipFree(dom->twx32);
   delete dom;
   return STAU_OK;
 }
@@ -326,6 +344,8 @@ static void free_pencils(stau_pencils* p) {
     hipFree(f.Lf);
     hipFree(f.sl);
     hipFree(f.Uf);
+    hipFree(f.Lf32);
+    hipFree(f.Uf32);
   }
   hipFree(p->sing);
   hipFree(p->flag);
@@ -386,6 +406,9 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   xa.dctz = dom->dctz;
   xa.twx = dom->twx;
   xa.twy = dom->twy;
+  xa.twz32 = dom->twz32;
+  xa.dctz32 = dom->dctz32;
+  xa.twx32 = dom->twx32;
   pen->xa1 = xa;
   pen->xa1.M = N;
   pen->xa1.L = (int)d.Nx;
@@ -433,10 +456,13 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   if (e == hipSuccess) e = hipMalloc((void**)&pen->Bev, szB);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->Gb, szG);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->wvec, (size_t)N * sizeof(double2));
+  const bool mixed = d.precision == STAU_MIXED;
   for (auto& f : pen->slot) {
     if (e == hipSuccess) e = hipMalloc((void**)&f.Lf, szL);
     if (e == hipSuccess) e = hipMalloc((void**)&f.sl, szS);
     if (e == hipSuccess) e = hipMalloc((void**)&f.Uf, szU);
+    if (mixed && e == hipSuccess) e = hipMalloc((void**)&f.Lf32, szL / 2);
+    if (mixed && e == hipSuccess) e = hipMalloc((void**)&f.Uf32, szU / 2);
   }
   if (e == hipSuccess) e = hipMalloc((void**)&pen->sing, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->flag, sizeof(int));
@@ -446,7 +472,8 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
     delete pen;
     return fail(STAU_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
-  pen->ws_bytes = (int64_t)(2 * szG + szH + szB + 2 * (szL + szU + szS) + szScratch);
+  pen->ws_bytes = (int64_t)(2 * szG + szH + szB + 2 * (szL + szU + szS) + szScratch +
+                            (mixed ? (szL + szU) : 0));
   {
     // KE functional weights: integral over z in [0, 1] of T_m = 1 / (1 - m^2), m even
     std::vector<double2> wv(N);
@@ -509,6 +536,12 @@ static int factor_into(stau_pencils* pen, int k, double a0, double b0, hipStream
   if (h != big) {
     pen->last_sing = h;
     return fail(STAU_ESINGULAR, "zero or non-finite pivot in pencil %d", h);
+  }
+  if (f.Lf32) {
+    const size_t nl = (size_t)pen->dom->P * pen->n * pen->pa.FW;
+    const size_t nu = (size_t)pen->dom->P * pen->n * pen->pa.BW;
+    HIP_TRY(launch_round_f32(f.Lf, f.Lf32, nl, st));
+    HIP_TRY(launch_round_f32(f.Uf, f.Uf32, nu, st));
   }
   f.valid = true;
   f.a0 = a0;
@@ -601,10 +634,13 @@ int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
   r.Xprev = (const double2*)s->X;
   r.hist_cur = hist + cur * hslot;
   r.hist_old = hist + (cur ^ 1) * hslot;
-  HIP_TRY(timed(pen, K_ZB, st, [&] { return launch_zb(pen->xa, pen->fl, s->X, pen->G, st); }));
-  HIP_TRY(timed(pen, K_XPASS, st, [&] { return launch_xpass(pen->xa, pen->G, pen->H, st); }));
-  HIP_TRY(timed(pen, K_ZF, st, [&] { return launch_zf(pen->xa, pen->H, pen->Bev, r, st); }));
+  const bool mixed = pen->dom->d.precision == STAU_MIXED;
+  HIP_TRY(timed(pen, K_ZB, st, [&] { return launch_zb(pen->xa, pen->fl, s->X, pen->G, st, mixed); }));
+  HIP_TRY(timed(pen, K_XPASS, st, [&] { return launch_xpass(pen->xa, pen->G, pen->H, st, mixed); }));
+  HIP_TRY(timed(pen, K_ZF, st, [&] { return launch_zf(pen->xa, pen->H, pen->Bev, r, st, mixed); }));
   HIP_TRY(timed(pen, K_SOLVE, st, [&] {
+    if (mixed)
+      return launch_solve_mixed(pen->pa, a0, b0, pen->Bev, fs->Lf32, fs->sl, fs->Uf32, s->X, st);
     return launch_solve(pen->pa, pen->Bev, fs->Lf, fs->sl, fs->Uf, s->X, st);
   }));
   s->head = cur;
