@@ -97,6 +97,25 @@ def adjoint_ratio(reps=3):
             "dtype": "f64"}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE runs, scaled by the copy-kernel calibration),
+    or None if the kernel's sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)[kernel]
+        m = hashlib.sha256()
+        for f in rec["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                m.update(fh.read())
+        return rec["bytes"] if m.hexdigest() == rec["sha256"] else None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def mixed_run(w, steps, warmup, X_fp64):
     """The mixed-precision step on the same workload and step count; per-field
     relative L2 error of its final state against the FP64 path's final state
@@ -267,7 +286,7 @@ def main():
         dom = max(timed_kernels, key=lambda k: kernels[k]["avg_us"])
         ach = kernels[dom]["GBps"]
         roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None}
+                    "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom)}
     if args.copy_bytes > 0:
         src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
