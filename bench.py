@@ -159,6 +159,86 @@ def mixed_run(w, steps, warmup, X_fp64):
             "steps_compared": steps + warmup}
 
 
+EXTRA_WORKLOADS = {
+    # 3-D Fourier x, y x Chebyshev z: 33,024 pencil slots per launch
+    "rb3d_256x256x128_Ra1e7_dt5e-5": dict(dim=3, Nx=256, Ny=256, Nz=128, Lx=4.0, Ly=4.0, Ra=1e7,
+                                          Pr=1.0, dt=5e-5, seed_workload=2, steps=50),
+    # small-Nz regime: 2049 pencil slots of n = 448
+    "rb2d_4096x64_Lx16_Ra1e7_Pr7_dt2e-5": dict(dim=2, Nx=4096, Ny=1, Nz=64, Lx=16.0, Ly=1.0,
+                                               Ra=1e7, Pr=7.0, dt=2e-5, seed_workload=4, steps=200),
+}
+
+
+def run_workload(w, precision, steps, warmup=10):
+    """Timed steps of one workload at one precision: (ms per step, final state
+    on the host, per-kernel average us over 10 extra steps)."""
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_1905_10388_amd import RBSolver
+
+    dim, Nx, Ny, Nz, dt = w["dim"], w["Nx"], w["Ny"], w["Nz"], w["dt"]
+    g = RBSolver(Nx, Nz, w["Lx"], w["Ra"], w["Pr"], dim=dim, Ny=Ny, Ly=w["Ly"], precision=precision)
+    shape = (Nx, Nz) if dim == 2 else (Nx, Ny, Nz)
+    xi = si.workload_noise(shape, w["seed_workload"])
+    j = np.arange(Nz)
+    z = 0.5 * (1.0 - np.cos(np.pi * (j + 0.5) / Nz))
+    prof = z * (1.0 - z)
+    bg = (1.0 - z) + 1e-3 * prof * xi
+    g.initial_state(torch.from_numpy(bg))
+    for _ in range(warmup):
+        g.step(dt)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        g.step(dt)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = max((time.perf_counter() - t0) * 1e3 / steps, ev0.elapsed_time(ev1) / steps)
+    g.check()
+    X = g.X.cpu().numpy()
+    g.set_kernel_timing(True)
+    for _ in range(10):
+        g.step(dt)
+    kt = {k: round(v * 1e3 / c, 3) for k, (v, c) in g.read_kernel_timing().items() if c}
+    info = dict(g.info)
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    return ms, X, kt, info
+
+
+def extra_workloads():
+    """The 3-D and small-Nz workloads, FP64 and mixed, with the mixed path's
+    per-field error against the FP64 path after the same steps."""
+    import numpy as np
+
+    out = {}
+    for name, w in EXTRA_WORKLOADS.items():
+        steps = w["steps"]
+        ms64, X64, kt64, info = run_workload(w, "fp64", steps)
+        msmx, Xmx, ktmx, _ = run_workload(w, "mixed", steps)
+        S = info["S"]
+        names = ("p", "b", "u", "w", "bz", "uz", "wz") if S == 7 else \
+            ("p", "b", "u", "v", "w", "bz", "uz", "vz", "wz")
+        err = {}
+        for i, v in enumerate(names):
+            a, b = Xmx[..., i, :], X64[..., i, :]
+            den = np.linalg.norm(b)
+            err[v] = float(np.linalg.norm(a - b) / den) if den > 0 else None
+        dof = S * w["Nx"] * w["Ny"] * w["Nz"]
+        out[name] = {"steps": steps, "pencils": info["P_active"], "unknowns_per_pencil": info["n"],
+                     "fp64": {"value": dof / (ms64 * 1e-3), "ms_per_step": ms64, "kernels_avg_us": kt64},
+                     "mixed": {"value": dof / (msmx * 1e-3), "ms_per_step": msmx, "kernels_avg_us": ktmx,
+                               "err_vs_fp64_per_field": err, "steps_compared": steps + 10},
+                     "unit": "DOF-updates/s"}
+    return out
+
+
 def cpu_baseline(w, sample_pencils=128, reps=3):
     """The oracle's SBDF2 step on a bounded sample: the explicit term on the
     full grid, then right-hand side + LU solve of `sample_pencils` pencils
@@ -223,6 +303,8 @@ def main():
                     help="steps of the per-kernel HIP-event pass after the timed region")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 3-D and small-Nz workloads")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -318,6 +400,8 @@ def main():
         out["mixed"]["speedup_vs_fp64"] = out["mixed"]["value"] / value
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio()
+    if not args.no_extra:
+        out["workloads"] = extra_workloads()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -62,9 +62,9 @@ typedef struct stau_pencils stau_pencils;
 
 /* Domain: direct product of Fourier (x[, y]) and Chebyshev (z) bases (Sec. V).
  * dim      2 or 3.
- * Nx, Ny   Fourier modes (even, Nx >= 4; Ny ignored in 2-D).  The dealiased
- *          grid size 3N/2 must be of the form 2^a 3^b (a >= 1) and <= 8192.
- * Nz       Chebyshev modes (even, 4 <= Nz <= 1024; 3Nz/2 of the form 2^a 3^b).
+ * Nx, Ny   Fourier modes: powers of two in [4, 4096] (Ny ignored in 2-D); the
+ *          dealiased grids have 3Nx/2 and 3Ny/2 points.
+ * Nz       Chebyshev modes: a power of two in [4, 512] (3Nz/2 grid points).
  * Lx, Ly   periods of x, y (> 0).
  * dealias  transform scale; must be 1.5 (the 3/2 rule, Sec. IV).
  * precision STAU_FP64 (everything FP64) or STAU_MIXED (stau_step only: FP32
@@ -187,7 +187,8 @@ int stau_check(stau_pencils* pen, const void* X, void* stream);
 int stau_kinetic_energy(stau_pencils* pen, const void* X, double* out, void* stream);
 
 /* ------------------------------------------------------------------------
- * Discrete adjoint.  The adjoint of a complex coefficient z is
+ * Discrete adjoint (2-D domains; the three calls below return
+ * STAU_EUNSUPPORTED for dim = 3).  The adjoint of a complex coefficient z is
  * dJ/dRe z + i dJ/dIm z (coefficients are pairs of independent reals), so a
  * complex-linear map y = A x has x_bar = A^H y_bar.
  * ------------------------------------------------------------------------ */
@@ -231,7 +232,8 @@ int stau_initial_state_adjoint(stau_pencils* pen, const void* Xbar, double* b_gr
  * stau_read_kernel_timing synchronises on those events, writes the summed
  * elapsed milliseconds and launch counts per kernel kind (0 backward z
  * transform, 1 x pass with products, 2 forward z transform with right-hand
- * side assembly, 3 pencil solve, 4 pencil factorisation) into ms[] and
+ * side assembly, 3 pencil solve, 4 pencil factorisation, 5 backward and
+ * forward y transforms of 3-D domains) into ms[] and
  * launches[] (caller-owned host arrays of nkinds entries) and clears the
  * record. */
 int stau_set_kernel_timing(stau_pencils* pen, int enable);

@@ -29,7 +29,7 @@ EXPORTS = (
     "stau_set_kernel_timing", "stau_read_kernel_timing", "stau_adjoint_step",
     "stau_kinetic_energy_adjoint", "stau_initial_state_adjoint",
 )
-KERNEL_KINDS = ("z_backward", "x_pass", "z_forward_rhs", "pencil_solve", "pencil_factor")
+KERNEL_KINDS = ("z_backward", "x_pass", "z_forward_rhs", "pencil_solve", "pencil_factor", "y_pass")
 
 
 class DomainDesc(C.Structure):

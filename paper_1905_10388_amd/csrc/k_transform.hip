@@ -333,6 +333,187 @@ __global__ void __launch_bounds__(NT) xpass_kernel(XformArgs a,
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// y pass (3-D): complex transforms along y of TK consecutive kx columns per
+// block, one (field, z level) per (blockIdx.z, blockIdx.y).  Stored y slots
+// iy hold the signed wavenumbers 0..Ny/2-1, [Nyquist, held zero],
+// -Ny/2+1..-1; on the padded grid of Ngy points they sit at position k
+// (k >= 0) or Ngy + k (k < 0).
+//   dir +1 (backward): In[f][jz][iy][kx] -> Out[f][jz][l][kx] = sum_k c_k e^{+2 pi i k l / Ngy}
+//   dir -1 (forward):  In[f][jz][l][kx]  -> Out[f][jz][iy][kx] = (1/Ngy) sum_l g_l e^{-2 pi i k l / Ngy},
+//                      truncated to the stored slots; Nyquist slots (iy = Ny/2 or kx >= Pa) zero.
+// ---------------------------------------------------------------------------
+template <int DIR, int MAXBF, typename T>
+__global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
+                                                    const typename V2<T>::type* __restrict__ In,
+                                                    typename V2<T>::type* __restrict__ Out, int TK) {
+  extern __shared__ double2 smem[];
+  using cT = cpx<T>;
+  cT* buf = (cT*)smem;
+  const int f = blockIdx.z, jz = blockIdx.y, k0 = blockIdx.x * TK;
+  const int Ny = a.Ny, Ng = a.Ngy, Px = a.Px, M = a.M, half = Ny / 2;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const size_t inRows = DIR > 0 ? Ny : Ng, outRows = DIR > 0 ? Ng : Ny;
+  const typename V2<T>::type* src = In + ((size_t)f * M + jz) * inRows * Px;
+  typename V2<T>::type* dst = Out + ((size_t)f * M + jz) * outRows * Px;
+  // padded position -> stored slot (-1: padding or Nyquist)
+  auto slot_of = [&](int pos) -> int {
+    if (pos < half) return pos;
+    if (pos > Ng - half) return Ny + (pos - Ng);
+    return -1;
+  };
+  for (int idx = tid; idx < TK * Ng; idx += nt) {
+    const int pos = idx / TK, s = idx - pos * TK;  // consecutive threads: consecutive kx
+    const int kx = k0 + s;
+    cT v = mk<T>(0, 0);
+    if (kx < Px) {
+      if (DIR > 0) {
+        const int iy = slot_of(pos);
+        if (iy >= 0) v = ldv<T>(src + (size_t)iy * Px + kx);
+      } else {
+        v = ldv<T>(src + (size_t)pos * Px + kx);
+      }
+    }
+    buf[s * Ng + pos] = v;
+  }
+  __syncthreads();
+  if constexpr (sizeof(T) == 8)
+    fft_lds<DIR, MAXBF>(buf, Ng, TK, (const cT*)a.twy, tid, nt);
+  else
+    fft_lds<DIR, MAXBF>(buf, Ng, TK, (const cT*)a.twy32, tid, nt);
+  if (DIR > 0) {
+    for (int idx = tid; idx < TK * Ng; idx += nt) {
+      const int l = idx / TK, s = idx - l * TK;
+      const int kx = k0 + s;
+      if (kx < Px) stv<T>(dst + (size_t)l * Px + kx, buf[s * Ng + l]);
+    }
+  } else {
+    const T inv = (T)1 / (T)Ng;
+    for (int idx = tid; idx < TK * Ny; idx += nt) {
+      const int iy = idx / TK, s = idx - iy * TK;
+      const int kx = k0 + s;
+      if (kx >= Px) continue;
+      cT v = mk<T>(0, 0);
+      if (iy != half && kx < a.Pa) {
+        const int pos = iy < half ? iy : Ng + (iy - Ny);
+        v = scale(buf[s * Ng + pos], inv);
+      }
+      stv<T>(dst + (size_t)iy * Px + kx, v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused x pass for one dealiased (z, y) row (3-D): eight complex-to-real
+// transforms of packed field pairs, the products
+//   N_q = -(u q_x + v q_y + w q_z),  q = b, u, v, w,
+// and two real-to-complex transforms of packed output pairs, truncated to
+// k < Nx/2 and scaled 1/L.  Rows r = jz * Ngy + l of Px slots; field f at
+// G2 + (f * R + r) * Px with R = M * Ngy.
+// G2 field order: u, v, w, b_x, b_y, b_z, u_x, u_y, u_z, v_x, v_y, v_z, w_x, w_y, w_z.
+// ---------------------------------------------------------------------------
+template <int MAXBF, int PTS, int NT, typename T>
+__global__ void __launch_bounds__(NT) xpass3_kernel(XformArgs a,
+                                                    const typename V2<T>::type* __restrict__ G,
+                                                    typename V2<T>::type* __restrict__ H) {
+  extern __shared__ double2 smem[];
+  using cT = cpx<T>;
+  using S2 = typename V2<T>::type;
+  cT* buf = (cT*)smem;
+  const int r = blockIdx.x;
+  const int L = a.L, Pa = a.Pa, Px = a.Px;
+  const size_t R = (size_t)a.M * a.Ngy;
+  const int tid = threadIdx.x;
+  constexpr int nt = NT;
+  const cT* tw = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
+
+  // fb < 0: the second field of the pair is zero
+  auto c2r_pair = [&](int fa, int fb, T* ra, T* rb) {
+    const S2* A = G + ((size_t)fa * R + r) * Px;
+    const S2* B = fb >= 0 ? G + ((size_t)fb * R + r) * Px : nullptr;
+    for (int k = tid; k < L; k += nt) {
+      cT z = mk<T>(0, 0);
+      const int kk = k < Pa ? k : (k > L - Pa ? L - k : -1);
+      if (kk >= 0) {
+        cT Ak = ldv<T>(A + kk);
+        cT Bk = B ? ldv<T>(B + kk) : mk<T>(0, 0);
+        if (kk == 0) {
+          Ak.y = 0;
+          Bk.y = 0;
+        }
+        z = k < Pa ? mk<T>(Ak.x - Bk.y, Ak.y + Bk.x) : mk<T>(Ak.x + Bk.y, -Ak.y + Bk.x);
+      }
+      buf[k] = z;
+    }
+    __syncthreads();
+    fft_lds<+1, MAXBF>(buf, L, 1, tw, tid, nt);
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) {
+      const int i = tid + q * nt;
+      if (i < L) {
+        ra[q] = buf[i].x;
+        rb[q] = buf[i].y;
+      }
+    }
+    __syncthreads();
+  };
+
+  T u[PTS], v[PTS], w[PTS], t1[PTS], t2[PTS], nb[PTS], nu[PTS], nv[PTS], nw[PTS];
+  c2r_pair(0, 1, u, v);
+  c2r_pair(2, 3, w, t1);  // w, b_x
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) nb[q] = -(u[q] * t1[q]);
+  c2r_pair(4, 5, t1, t2);  // b_y, b_z
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) nb[q] -= v[q] * t1[q] + w[q] * t2[q];
+  c2r_pair(6, 7, t1, t2);  // u_x, u_y
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) nu[q] = -(u[q] * t1[q] + v[q] * t2[q]);
+  c2r_pair(8, 9, t1, t2);  // u_z, v_x
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    nu[q] -= w[q] * t1[q];
+    nv[q] = -(u[q] * t2[q]);
+  }
+  c2r_pair(10, 11, t1, t2);  // v_y, v_z
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) nv[q] -= v[q] * t1[q] + w[q] * t2[q];
+  c2r_pair(12, 13, t1, t2);  // w_x, w_y
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) nw[q] = -(u[q] * t1[q] + v[q] * t2[q]);
+  c2r_pair(14, -1, t1, t2);  // w_z
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) nw[q] -= w[q] * t1[q];
+
+  const T invL = (T)1 / (T)L;
+  const T hf = (T)0.5;
+  auto r2c_pair = [&](const T* ra, const T* rb, int ea, int eb) {
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) {
+      const int i = tid + q * nt;
+      if (i < L) buf[i] = mk<T>(ra[q], rb[q]);
+    }
+    __syncthreads();
+    fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, nt);
+    S2* Ha = H + ((size_t)ea * R + r) * Px;
+    S2* Hb = H + ((size_t)eb * R + r) * Px;
+    for (int k = tid; k < Px; k += nt) {
+      cT A = mk<T>(0, 0), Bv = mk<T>(0, 0);
+      if (k < Pa) {
+        cT Zk = buf[k], Zm = buf[k == 0 ? 0 : L - k];
+        A = mk<T>(hf * (Zk.x + Zm.x) * invL, hf * (Zk.y - Zm.y) * invL);
+        Bv = mk<T>(hf * (Zk.y + Zm.y) * invL, -hf * (Zk.x - Zm.x) * invL);
+      }
+      stv<T>(Ha + k, A);
+      stv<T>(Hb + k, Bv);
+    }
+    __syncthreads();
+  };
+  r2c_pair(nb, nu, 0, 1);
+  r2c_pair(nv, nw, 2, 3);
+}
+
 // ---------------------------------------------------------------------------
 // Initial state: scale-1 forward x transform of the b grid (one z level per
 // block), then the z forward transform (zf_kernel, mode 0) and the fill below.
@@ -340,17 +521,19 @@ __global__ void __launch_bounds__(NT) xpass_kernel(XformArgs a,
 template <int MAXBF>
 __global__ void __launch_bounds__(256) ic_x_kernel(XformArgs a, const double* __restrict__ bgrid,
                                                    double2* __restrict__ H1) {
+  // one (z level jz, y level l) row per block; b grid [ix][l][jz] (Ny = 1 in 2-D);
+  // output H1[jz][l][kx] with Px slots per row
   extern __shared__ double2 smem[];
   cd* buf = (cd*)smem;
-  const int jz = blockIdx.x;
-  const int Nx = a.Nx, N = a.N;
+  const int jz = blockIdx.x, l = blockIdx.y;
+  const int Nx = a.Nx, N = a.N, Ny = a.dim == 2 ? 1 : a.Ny;
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < Nx; i += nt) buf[i] = mk(bgrid[(size_t)i * N + jz], 0.0);
+  for (int i = tid; i < Nx; i += nt) buf[i] = mk(bgrid[((size_t)i * Ny + l) * N + jz], 0.0);
   __syncthreads();
   fft_lds<-1, MAXBF>(buf, Nx, 1, (const cd*)a.twx, tid, nt);
   const double inv = 1.0 / (double)Nx;
-  for (int k = tid; k < a.P; k += nt)
-    st2(H1 + (size_t)jz * a.P + k, k < a.Pa ? scale(buf[k], inv) : mk(0.0, 0.0));
+  double2* out = H1 + ((size_t)jz * Ny + l) * a.Px;
+  for (int k = tid; k < a.Px; k += nt) st2(out + k, k < a.Pa ? scale(buf[k], inv) : mk(0.0, 0.0));
 }
 
 // X[p][b] = c, X[p][bz] = d_z c (Chebyshev derivative recursion on [0, 1]),
@@ -384,50 +567,61 @@ __global__ void ic_fill_kernel(XformArgs a, const double2* __restrict__ C, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Kinetic energy: per z row, mean over x of (u^2 + w^2)/2 from the packed
-// complex-to-real transform (the k = 0 coefficient of the forward transform).
+// Kinetic energy: per dealiased row r (z level, and y level in 3-D), mean
+// over x of |u|^2 / 2 from complex-to-real transforms of the velocity
+// components (u, w in 2-D; u, v, w in 3-D).  Field f of row r at
+// G + (f * R + r) * Px, R = M * Ngy.
 // ---------------------------------------------------------------------------
 template <int MAXBF, int PTS>
 __global__ void __launch_bounds__(1024) ke_row_kernel(XformArgs a, const double2* __restrict__ G,
-                                                      double* __restrict__ rowmean) {
+                                                      int nf, double* __restrict__ rowmean) {
   extern __shared__ double2 smem[];
   cd* buf = (cd*)smem;
   __shared__ double red[1024];
-  const int jz = blockIdx.x;
-  const int M = a.M, L = a.L, Pa = a.Pa, P = a.P;
+  const int r = blockIdx.x;
+  const int L = a.L, Pa = a.Pa, Px = a.Px;
+  const size_t R = (size_t)a.M * a.Ngy;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const double2* A = G + ((size_t)0 * M + jz) * P;
-  const double2* B = G + ((size_t)1 * M + jz) * P;
-  for (int k = tid; k < L; k += nt) {
-    cd z = mk(0.0, 0.0);
-    if (k < Pa) {
-      cd Ak = ld2(A + k), Bk = ld2(B + k);
-      if (k == 0) {
-        Ak.y = 0.0;
-        Bk.y = 0.0;
-      }
-      z = mk(Ak.x - Bk.y, Ak.y + Bk.x);
-    } else if (k > L - Pa) {
-      cd Ak = ld2(A + (L - k)), Bk = ld2(B + (L - k));
-      z = mk(Ak.x + Bk.y, -Ak.y + Bk.x);
-    }
-    buf[k] = z;
-  }
-  __syncthreads();
-  fft_lds<+1, MAXBF>(buf, L, 1, (const cd*)a.twx, tid, nt);
   double acc = 0.0;
-  for (int i = tid; i < L; i += nt) acc += 0.5 * (buf[i].x * buf[i].x + buf[i].y * buf[i].y);
+  for (int f0 = 0; f0 < nf; f0 += 2) {
+    const double2* A = G + ((size_t)f0 * R + r) * Px;
+    const double2* B = f0 + 1 < nf ? G + ((size_t)(f0 + 1) * R + r) * Px : nullptr;
+    for (int k = tid; k < L; k += nt) {
+      cd z = mk(0.0, 0.0);
+      const int kk = k < Pa ? k : (k > L - Pa ? L - k : -1);
+      if (kk >= 0) {
+        cd Ak = ld2(A + kk), Bk = B ? ld2(B + kk) : mk(0.0, 0.0);
+        if (kk == 0) {
+          Ak.y = 0.0;
+          Bk.y = 0.0;
+        }
+        z = k < Pa ? mk(Ak.x - Bk.y, Ak.y + Bk.x) : mk(Ak.x + Bk.y, -Ak.y + Bk.x);
+      }
+      buf[k] = z;
+    }
+    __syncthreads();
+    fft_lds<+1, MAXBF>(buf, L, 1, (const cd*)a.twx, tid, nt);
+    for (int i = tid; i < L; i += nt) acc += 0.5 * (buf[i].x * buf[i].x + buf[i].y * buf[i].y);
+    __syncthreads();
+  }
   red[tid] = acc;
   __syncthreads();
   for (int s = nt / 2; s > 0; s >>= 1) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
-  if (tid == 0) rowmean[jz] = red[0] / (double)L;
+  if (tid == 0) rowmean[r] = red[0] / (double)L;
 }
 
-__global__ void real_to_complex_kernel(const double* __restrict__ r, double2* __restrict__ h, int M) {
-  for (int j = threadIdx.x; j < M; j += blockDim.x) h[j] = make_double2(r[j], 0.0);
+// mean over the Ngy y levels of each z level (3-D), as complex values for the
+// z forward transform
+__global__ void ke_ymean_kernel(const double* __restrict__ rowmean, double2* __restrict__ h, int M,
+                                int Ngy) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < M; j += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int l = 0; l < Ngy; ++l) acc += rowmean[(size_t)j * Ngy + l];
+    h[j] = make_double2(acc / (double)Ngy, 0.0);
+  }
 }
 
 // J = sum_{m even < N} c_m / (1 - m^2) from the Chebyshev coefficients c of
@@ -838,6 +1032,55 @@ hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t 
   return fp32 ? launch_xpass_T<float>(a, G, H, st) : launch_xpass_T<double>(a, G, H, st);
 }
 
+hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, void* Out,
+                        hipStream_t st, bool fp32) {
+  const int TK = a.Ngy >= 3072 ? 1 : 3072 / a.Ngy;
+  dim3 grid((a.Px + TK - 1) / TK, a.M, nf);
+  const size_t lds = (size_t)TK * a.Ngy * (fp32 ? sizeof(float2) : sizeof(double2));
+  if (fp32) {
+    if (dir > 0)
+      hipLaunchKernelGGL((ypass_kernel<+1, 3, float>), grid, dim3(256), lds, st, a,
+                         (const float2*)In, (float2*)Out, TK);
+    else
+      hipLaunchKernelGGL((ypass_kernel<-1, 3, float>), grid, dim3(256), lds, st, a,
+                         (const float2*)In, (float2*)Out, TK);
+  } else {
+    if (dir > 0)
+      hipLaunchKernelGGL((ypass_kernel<+1, 3, double>), grid, dim3(256), lds, st, a,
+                         (const double2*)In, (double2*)Out, TK);
+    else
+      hipLaunchKernelGGL((ypass_kernel<-1, 3, double>), grid, dim3(256), lds, st, a,
+                         (const double2*)In, (double2*)Out, TK);
+  }
+  return hipGetLastError();
+}
+
+template <int NT, typename T>
+static hipError_t launch_xpass3_t(const XformArgs& a, const void* G, void* H, hipStream_t st) {
+  using S2 = typename V2<T>::type;
+  size_t lds = (size_t)a.L * sizeof(S2);
+  allow_lds((const void*)xpass3_kernel<2, 6, NT, T>, lds);
+  hipLaunchKernelGGL((xpass3_kernel<2, 6, NT, T>), dim3(a.M * a.Ngy), dim3(NT), lds, st, a,
+                     (const S2*)G, (S2*)H);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_xpass3_T(const XformArgs& a, const void* G, void* H, hipStream_t st) {
+  switch (x_threads(a.L)) {
+    case 64: return launch_xpass3_t<64, T>(a, G, H, st);
+    case 128: return launch_xpass3_t<128, T>(a, G, H, st);
+    case 256: return launch_xpass3_t<256, T>(a, G, H, st);
+    case 512: return launch_xpass3_t<512, T>(a, G, H, st);
+    case 1024: return launch_xpass3_t<1024, T>(a, G, H, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_xpass3(const XformArgs& a, const void* G2, void* H2, hipStream_t st, bool fp32) {
+  return fp32 ? launch_xpass3_T<float>(a, G2, H2, st) : launch_xpass3_T<double>(a, G2, H2, st);
+}
+
 hipError_t launch_zadj(const XformArgs& a, const AccList& al, const void* Gbar, void* Xbar,
                        hipStream_t st) {
   const int TP = z_tile(a.M);
@@ -942,34 +1185,52 @@ hipError_t launch_initial_state_adjoint(const XformArgs& a1, const void* Xbar, d
 
 hipError_t launch_initial_state(const XformArgs& a1, const double* bgrid, void* X, void* work,
                                 hipStream_t st) {
-  // a1 describes the scale-1 transforms: M = N (z), twx of length Nx, L = Nx.
-  double2* H1 = (double2*)work;                    // [N][P]
-  double2* C = H1 + (size_t)a1.N * a1.P;           // [P][1][N]
+  // a1 describes the scale-1 transforms: M = N (z), twx of length Nx, L = Nx,
+  // and in 3-D Ngy = Ny with the y table of length Ny.
+  const int Ny = a1.dim == 2 ? 1 : a1.Ny;
+  double2* H1 = (double2*)work;                           // [N][Ny][Px]
+  double2* Hy = H1 + (size_t)a1.N * Ny * a1.Px;           // [N][P] (3-D)
+  double2* C = Hy + (size_t)a1.N * a1.P;                  // [P][1][N]
   allow_lds((const void*)ic_x_kernel<8>, (size_t)a1.Nx * sizeof(double2));
-  hipLaunchKernelGGL((ic_x_kernel<8>), dim3(a1.N), dim3(256), (size_t)a1.Nx * sizeof(double2),
+  hipLaunchKernelGGL((ic_x_kernel<8>), dim3(a1.N, Ny), dim3(256), (size_t)a1.Nx * sizeof(double2),
                      st, a1, bgrid, H1);
+  const double2* Hz = H1;
+  if (a1.dim == 3) {
+    hipError_t e = launch_ypass(a1, -1, 1, H1, Hy, st);
+    if (e != hipSuccess) return e;
+    Hz = Hy;
+  }
   XformArgs az = a1;
   az.ne = 1;
   RhsArgs r{};
   r.mode = 0;
-  launch_zf(az, H1, C, r, st);
+  launch_zf(az, Hz, C, r, st);
   hipLaunchKernelGGL(ic_fill_kernel, dim3(a1.P), dim3(256), 0, st, a1, (const double2*)C,
                      (double2*)X, 1, a1.dim == 2 ? 4 : 5);
   return hipGetLastError();
 }
 
-hipError_t launch_ke(const XformArgs& a, const void* X, void* G, double* rowmean, double* out,
-                     hipStream_t st) {
+hipError_t launch_ke(const XformArgs& a, const void* X, void* G, void* G2, double* rowmean,
+                     double* out, hipStream_t st) {
+  const int nf = a.dim == 2 ? 2 : 3;
   FieldList fl{};
-  fl.nf = 2;
+  fl.nf = nf;
   fl.var[0] = 2;                    // u
-  fl.var[1] = a.dim == 2 ? 3 : 4;   // w
+  fl.var[1] = 3;                    // w (2-D) / v (3-D)
+  fl.var[2] = 4;                    // w (3-D)
   launch_zb(a, fl, X, G, st);
+  const void* Gr = G;
+  if (a.dim == 3) {
+    hipError_t e = launch_ypass(a, +1, nf, G, G2, st);
+    if (e != hipSuccess) return e;
+    Gr = G2;
+  }
   const int nt = x_threads(a.L);
+  const int rows = a.M * (a.dim == 2 ? 1 : a.Ngy);
   allow_lds((const void*)ke_row_kernel<2, 6>, (size_t)a.L * sizeof(double2) + 8192);
-  hipLaunchKernelGGL((ke_row_kernel<2, 6>), dim3(a.M), dim3(nt), (size_t)a.L * sizeof(double2),
-                     st, a, (const double2*)G, rowmean);
-  // z forward of the (real) row means: treat as one pencil, one field
+  hipLaunchKernelGGL((ke_row_kernel<2, 6>), dim3(rows), dim3(nt), (size_t)a.L * sizeof(double2),
+                     st, a, (const double2*)Gr, nf, rowmean);
+  // z forward of the (real) x[y]-means: one pencil, one field
   XformArgs az = a;
   az.P = 1;
   az.ne = 1;
@@ -977,8 +1238,8 @@ hipError_t launch_ke(const XformArgs& a, const void* X, void* G, double* rowmean
   az.Pa = 1;
   double2* H = (double2*)G;            // reuse: [1][M][1]
   double2* C = H + a.M;                // [1][1][N]
-  hipLaunchKernelGGL(real_to_complex_kernel, dim3(1), dim3(256), 0, st, (const double*)rowmean, H,
-                     a.M);
+  hipLaunchKernelGGL(ke_ymean_kernel, dim3(1), dim3(256), 0, st, (const double*)rowmean, H, a.M,
+                     a.dim == 2 ? 1 : a.Ngy);
   RhsArgs r{};
   r.mode = 0;
   launch_zf(az, H, C, r, st);

@@ -36,6 +36,7 @@ struct XformArgs {
   const float2* twz32;
   const float2* dctz32;
   const float2* twx32;
+  const float2* twy32;
 };
 
 // Field list for the backward z transform: source variable index and
@@ -71,6 +72,12 @@ hipError_t launch_solve_mixed(const PencilArgs& a, double a0, double b0, const v
                               const float* Lf, const uint8_t* sl, const float* Uf, void* X,
                               hipStream_t st);
 hipError_t launch_round_f32(const double* src, float* dst, size_t count, hipStream_t st);
+
+// transforms along y and the 3-D x pass
+hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, void* Out,
+                        hipStream_t st, bool fp32 = false);
+hipError_t launch_xpass3(const XformArgs& a, const void* G2, void* H2, hipStream_t st,
+                         bool fp32 = false);
 
 // transforms (2-D)
 hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, void* G,
@@ -113,7 +120,7 @@ hipError_t launch_initial_state(const XformArgs& a1, const double* bgrid, void* 
                                 hipStream_t st);
 
 // kinetic energy: mean over x of |u|^2/2 per z row, then Chebyshev integral
-hipError_t launch_ke(const XformArgs& a, const void* X, void* G, double* rowmean, double* out,
+hipError_t launch_ke(const XformArgs& a, const void* X, void* G, void* G2, double* rowmean, double* out,
                      hipStream_t st);
 
 }  // namespace stau

@@ -79,8 +79,8 @@ struct stau_domain {
   stau_domain_desc d{};
   int64_t Ngx = 0, Ngy = 1, Ngz = 0, Px = 0, P = 0, Pa = 0;
   double2 *twz = nullptr, *dctz = nullptr, *twx = nullptr, *twy = nullptr;
-  double2 *twz1 = nullptr, *dctz1 = nullptr, *twx1 = nullptr;
-  float2 *twz32 = nullptr, *dctz32 = nullptr, *twx32 = nullptr;
+  double2 *twz1 = nullptr, *dctz1 = nullptr, *twx1 = nullptr, *twy1 = nullptr;
+  float2 *twz32 = nullptr, *dctz32 = nullptr, *twx32 = nullptr, *twy32 = nullptr;
 };
 
 struct stau_pencils {
@@ -94,6 +94,7 @@ struct stau_pencils {
   int64_t n = 0;
   // workspaces
   double2* G = nullptr;    // [NF][M][P]
+  double2* G2 = nullptr;   // 3-D: [NF][M][Ngy][Px] after the y pass
   double2* H = nullptr;    // [ne][M][P]
   double2* Bev = nullptr;  // [P][ne][N]
   double2* Gb = nullptr;   // [NF][M][P] adjoint workspace
@@ -127,7 +128,7 @@ struct stau_pencils {
 };
 
 namespace {
-enum Kind { K_ZB = 0, K_XPASS, K_ZF, K_SOLVE, K_FACTOR, K_NKINDS };
+enum Kind { K_ZB = 0, K_XPASS, K_ZF, K_SOLVE, K_FACTOR, K_YPASS, K_NKINDS };
 
 template <typename F>
 hipError_t timed(stau_pencils* pen, int kind, hipStream_t st, F&& launch) {
@@ -270,7 +271,7 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
   if (!desc || !out) return fail(STAU_EINVAL, "null argument");
   *out = nullptr;
   const stau_domain_desc& d = *desc;
-  if (d.dim != 2) return fail(STAU_EUNSUPPORTED, "dim=%d: only 2-D domains are built", d.dim);
+  if (d.dim != 2 && d.dim != 3) return fail(STAU_EINVAL, "dim=%d must be 2 or 3", d.dim);
   if (d.precision != STAU_FP64 && d.precision != STAU_MIXED)
     return fail(STAU_EINVAL, "precision %d unknown", d.precision);
   if (std::fabs(d.dealias - 1.5) > 1e-15) return fail(STAU_EUNSUPPORTED, "dealias must be 1.5");
@@ -279,6 +280,11 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
   if (!is_pow2(d.Nz) || d.Nz < 4 || d.Nz > 512)
     return fail(STAU_EUNSUPPORTED, "Nz=%lld must be a power of two in [4, 512]", (long long)d.Nz);
   if (!(d.Lx > 0.0)) return fail(STAU_EINVAL, "Lx must be positive");
+  if (d.dim == 3) {
+    if (!is_pow2(d.Ny) || d.Ny < 4 || d.Ny > 4096)
+      return fail(STAU_EUNSUPPORTED, "Ny=%lld must be a power of two in [4, 4096]", (long long)d.Ny);
+    if (!(d.Ly > 0.0)) return fail(STAU_EINVAL, "Ly must be positive");
+  }
   HIP_TRY(hipSetDevice(d.device));
   stau_domain* dom = new (std::nothrow) stau_domain();
   if (!dom) return fail(STAU_ENOMEM, "host allocation failed");
@@ -286,8 +292,9 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
   dom->Ngx = 3 * d.Nx / 2;
   dom->Ngz = 3 * d.Nz / 2;
   dom->Px = d.Nx / 2 + 1;
-  dom->P = dom->Px;
+  dom->P = d.dim == 3 ? dom->Px * d.Ny : dom->Px;
   dom->Pa = d.Nx / 2;
+  dom->Ngy = d.dim == 3 ? 3 * d.Ny / 2 : 1;
   std::vector<double2> t;
   int rc;
   fft_table(dom->Ngz, t);
@@ -305,6 +312,13 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
   if ((rc = upload(t, &dom->dctz1))) goto bad;
   fft_table(d.Nx, t);
   if ((rc = upload(t, &dom->twx1))) goto bad;
+  if (d.dim == 3) {
+    fft_table(dom->Ngy, t);
+    if ((rc = upload(t, &dom->twy))) goto bad;
+    if ((rc = upload32(t, &dom->twy32))) goto bad;
+    fft_table(d.Ny, t);
+    if ((rc = upload(t, &dom->twy1))) goto bad;
+  }
   *out = dom;
   return STAU_OK;
 bad:
@@ -325,6 +339,8 @@ int stau_destroy_domain(stau_domain* dom) {
   hipFree(dom->twz32);
   hipFree(dom->dctz32);
   hipFree(dom->twx32);
+  hipFree(dom->twy1);
+  hipFree(dom->twy32);
   delete dom;
   return STAU_OK;
 }
@@ -336,6 +352,7 @@ static void free_pencils(stau_pencils* p) {
   }
   p->events.clear();
   hipFree(p->G);
+  hipFree(p->G2);
   hipFree(p->H);
   hipFree(p->Bev);
   hipFree(p->Gb);
@@ -409,20 +426,33 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   xa.twz32 = dom->twz32;
   xa.dctz32 = dom->dctz32;
   xa.twx32 = dom->twx32;
+  xa.twy32 = dom->twy32;
   pen->xa1 = xa;
   pen->xa1.M = N;
   pen->xa1.L = (int)d.Nx;
   pen->xa1.twz = dom->twz1;
   pen->xa1.dctz = dom->dctz1;
   pen->xa1.twx = dom->twx1;
+  pen->xa1.Ngy = d.dim == 3 ? (int)d.Ny : 1;
+  pen->xa1.twy = dom->twy1;
 
-  FieldList& fl = pen->fl;  // u, w, b_x, b_z, u_x, u_z, w_x, w_z
-  const int fv[8] = {2, 3, 1, 4, 2, 5, 3, 6};
-  const int fd[8] = {0, 0, 1, 0, 1, 0, 1, 0};
-  fl.nf = 8;
-  for (int i = 0; i < 8; ++i) {
-    fl.var[i] = fv[i];
-    fl.deriv[i] = fd[i];
+  FieldList& fl = pen->fl;
+  if (d.dim == 2) {  // u, w, b_x, b_z, u_x, u_z, w_x, w_z
+    const int fv[8] = {2, 3, 1, 4, 2, 5, 3, 6};
+    const int fd[8] = {0, 0, 1, 0, 1, 0, 1, 0};
+    fl.nf = 8;
+    for (int i = 0; i < 8; ++i) {
+      fl.var[i] = fv[i];
+      fl.deriv[i] = fd[i];
+    }
+  } else {  // u, v, w, then q_x, q_y, q_z for q = b, u, v, w (ABI order p,b,u,v,w,bz,uz,vz,wz)
+    const int fv[15] = {2, 3, 4, 1, 1, 5, 2, 2, 6, 3, 3, 7, 4, 4, 8};
+    const int fd[15] = {0, 0, 0, 1, 2, 0, 1, 2, 0, 1, 2, 0, 1, 2, 0};
+    fl.nf = 15;
+    for (int i = 0; i < 15; ++i) {
+      fl.var[i] = fv[i];
+      fl.deriv[i] = fd[i];
+    }
   }
   {
     // adjoint of the backward z transform: target variable <- source fields
@@ -449,12 +479,16 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   const size_t szL = P * n * pa.FW * sizeof(double);
   const size_t szU = P * n * pa.BW * sizeof(double);
   const size_t szS = P * n;
-  const size_t szScratch = (size_t)(N * P + P * N + 4 * M + 64) * sizeof(double2);
+  const size_t Ngy = (size_t)dom->Ngy, Px = (size_t)dom->Px;
+  const size_t szG2 = d.dim == 3 ? (size_t)fl.nf * M * Ngy * Px * sizeof(double2) : 0;
+  const size_t szGb = d.dim == 2 ? szG : 0;  // the adjoint is built for 2-D
+  const size_t szScratch = (size_t)(3 * N * P + 4 * M * Ngy + 64) * sizeof(double2);
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMalloc((void**)&pen->G, szG);
+  if (e == hipSuccess && szG2) e = hipMalloc((void**)&pen->G2, szG2);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->H, szH);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->Bev, szB);
-  if (e == hipSuccess) e = hipMalloc((void**)&pen->Gb, szG);
+  if (e == hipSuccess && szGb) e = hipMalloc((void**)&pen->Gb, szGb);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->wvec, (size_t)N * sizeof(double2));
   const bool mixed = d.precision == STAU_MIXED;
   for (auto& f : pen->slot) {
@@ -472,7 +506,7 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
     delete pen;
     return fail(STAU_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
-  pen->ws_bytes = (int64_t)(2 * szG + szH + szB + 2 * (szL + szU + szS) + szScratch +
+  pen->ws_bytes = (int64_t)(szG + szG2 + szGb + szH + szB + 2 * (szL + szU + szS) + szScratch +
                             (mixed ? (szL + szU) : 0));
   {
     // KE functional weights: integral over z in [0, 1] of T_m = 1 / (1 - m^2), m even
@@ -607,6 +641,23 @@ static void sbdf(int64_t it, double dt, double dtp, double* a0, double* a1, doub
   *c2 = -w;
 }
 
+// Grid-space explicit term up to the z forward transform: H[e][jz][p].
+// 2-D: z backward, fused x pass.  3-D: z backward, y backward, fused x pass,
+// y forward (the x-pass output H2 reuses G, the y-forward output goes to H).
+static hipError_t explicit_term(stau_pencils* pen, const void* X, hipStream_t st, bool mixed) {
+  hipError_t e = timed(pen, K_ZB, st, [&] { return launch_zb(pen->xa, pen->fl, X, pen->G, st, mixed); });
+  if (e != hipSuccess) return e;
+  if (pen->dom->d.dim == 2)
+    return timed(pen, K_XPASS, st, [&] { return launch_xpass(pen->xa, pen->G, pen->H, st, mixed); });
+  e = timed(pen, K_YPASS, st,
+            [&] { return launch_ypass(pen->xa, +1, pen->fl.nf, pen->G, pen->G2, st, mixed); });
+  if (e != hipSuccess) return e;
+  e = timed(pen, K_XPASS, st, [&] { return launch_xpass3(pen->xa, pen->G2, pen->G, st, mixed); });
+  if (e != hipSuccess) return e;
+  return timed(pen, K_YPASS, st,
+               [&] { return launch_ypass(pen->xa, -1, pen->pa.desc.ne, pen->G, pen->H, st, mixed); });
+}
+
 int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
   if (!pen || !s || !s->X || !s->hist) return fail(STAU_EINVAL, "null argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(STAU_EINVAL, "dt must be positive");
@@ -635,8 +686,7 @@ int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
   r.hist_cur = hist + cur * hslot;
   r.hist_old = hist + (cur ^ 1) * hslot;
   const bool mixed = pen->dom->d.precision == STAU_MIXED;
-  HIP_TRY(timed(pen, K_ZB, st, [&] { return launch_zb(pen->xa, pen->fl, s->X, pen->G, st, mixed); }));
-  HIP_TRY(timed(pen, K_XPASS, st, [&] { return launch_xpass(pen->xa, pen->G, pen->H, st, mixed); }));
+  HIP_TRY(explicit_term(pen, s->X, st, mixed));
   HIP_TRY(timed(pen, K_ZF, st, [&] { return launch_zf(pen->xa, pen->H, pen->Bev, r, st, mixed); }));
   HIP_TRY(timed(pen, K_SOLVE, st, [&] {
     if (mixed)
@@ -662,8 +712,7 @@ int stau_nonlinear(stau_pencils* pen, const void* X, void* F, void* stream) {
   HIP_TRY(hipSetDevice(pen->dom->d.device));
   RhsArgs r{};
   r.mode = 0;
-  HIP_TRY(launch_zb(pen->xa, pen->fl, X, pen->G, st));
-  HIP_TRY(launch_xpass(pen->xa, pen->G, pen->H, st));
+  HIP_TRY(explicit_term(pen, X, st, false));
   HIP_TRY(launch_zf(pen->xa, pen->H, F, r, st));
   return STAU_OK;
 }
@@ -679,6 +728,7 @@ int stau_solve(stau_pencils* pen, const void* B_ev, void* X, void* stream) {
 int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, double dt,
                       double dt_prev, stau_adjstate* adj, void* stream) {
   if (!pen || !X_prev || !adj || !adj->Xbar || !adj->hbar) return fail(STAU_EINVAL, "null argument");
+  if (pen->dom->d.dim != 2) return fail(STAU_EUNSUPPORTED, "the adjoint is built for 2-D domains");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(STAU_EINVAL, "dt must be positive");
   if (iteration < 0 || (iteration > 0 && !(dt_prev > 0.0)))
     return fail(STAU_EINVAL, "iteration / dt_prev inconsistent");
@@ -718,6 +768,7 @@ int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, 
 
 int stau_kinetic_energy_adjoint(stau_pencils* pen, const void* X, void* Xbar, void* stream) {
   if (!pen || !X || !Xbar) return fail(STAU_EINVAL, "null argument");
+  if (pen->dom->d.dim != 2) return fail(STAU_EUNSUPPORTED, "the adjoint is built for 2-D domains");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(pen->dom->d.device));
   double2* ebar = (double2*)pen->scratch;
@@ -728,6 +779,7 @@ int stau_kinetic_energy_adjoint(stau_pencils* pen, const void* X, void* Xbar, vo
 int stau_initial_state_adjoint(stau_pencils* pen, const void* Xbar, double* b_grid_bar,
                                void* stream) {
   if (!pen || !Xbar || !b_grid_bar) return fail(STAU_EINVAL, "null argument");
+  if (pen->dom->d.dim != 2) return fail(STAU_EUNSUPPORTED, "the adjoint is built for 2-D domains");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(pen->dom->d.device));
   HIP_TRY(launch_initial_state_adjoint(pen->xa1, Xbar, b_grid_bar, pen->scratch, st));
@@ -765,8 +817,8 @@ int stau_kinetic_energy(stau_pencils* pen, const void* X, double* out, void* str
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(pen->dom->d.device));
   double* rowmean = (double*)pen->scratch;
-  double* dout = rowmean + pen->xa.M;
-  HIP_TRY(launch_ke(pen->xa, X, pen->G, rowmean, dout, st));
+  double* dout = rowmean + (size_t)pen->xa.M * pen->dom->Ngy;
+  HIP_TRY(launch_ke(pen->xa, X, pen->G, pen->G2, rowmean, dout, st));
   HIP_TRY(hipMemcpyAsync(out, dout, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return STAU_OK;
