@@ -2,7 +2,8 @@
 // templates, banded LU with partial pivoting (one wavefront per pencil), and
 // the batched banded solve (one wavefront per pencil, register windows).
 //
-// Factor storage per pencil p and column j (n = S*N columns):
+// Factor storage per pencil p and column j (n = S*N columns, nst >= n stored
+// per pencil, columns n..nst-1 zero):
 //   Lf[p][j][FW]  multipliers of column j routed to the physical slot that
 //                 holds each pending row in the solve's forward window
 //                 (FW = kl + 1 slots; zero for the pivot's slot);
@@ -19,6 +20,8 @@ namespace stau {
 
 constexpr int kWave = 64;
 constexpr int kCW = 64;  // factor column window (>= kv + 1)
+constexpr int kCH = 64;  // sweep chunk: columns per unrolled loop body
+constexpr int kRing = 32;  // look-ahead of the factor loads in the sweeps (columns)
 
 // Materialise a loaded value in its register here: the loads it depends on
 // complete before this point and cannot be sunk past it by the scheduler.
@@ -68,7 +71,9 @@ __device__ __forceinline__ bool pencil_active(const PencilArgs& a, int p) {
 
 // ---------------------------------------------------------------------------
 // Factor: one wavefront per pencil.  Band held in an LDS window of kCW
-// columns, LAPACK layout (row i of column c at kv + i - c).
+// columns, LAPACK layout (row i of column c at kv + i - c).  With a.trans the
+// transposed matrix is factored (kl and ku of `a` are then those of the
+// transpose), for the adjoint's transposed solves.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, double b0,
                                                        double* __restrict__ Lf,
@@ -92,7 +97,7 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     for (int q = lane; q < ld; q += kWave) {
       const int r = c - kv + q;
       double v = 0.0;
-      if (r >= 0 && r < n && r >= c - ku) v = sys_entry(d, pc, r, c);
+      if (r >= 0 && r < n && r >= c - ku) v = a.trans ? sys_entry(d, pc, c, r) : sys_entry(d, pc, r, c);
       col[q] = v;
     }
   };
@@ -100,9 +105,9 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
   if (lane < FW) phys[lane] = lane;
   __syncthreads();
 
-  double* Lp = Lf + (size_t)p * n * FW;
-  double* Up = Uf + (size_t)p * n * BW;
-  uint8_t* sp = sl + (size_t)p * n;
+  double* Lp = Lf + (size_t)p * a.nst * FW;
+  double* Up = Uf + (size_t)p * a.nst * BW;
+  uint8_t* sp = sl + (size_t)p * a.nst;
 
   for (int j = 0; j < n; ++j) {
     double* cj = win + (j % kCW) * ld;
@@ -194,75 +199,49 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
 }
 
 // ---------------------------------------------------------------------------
-// Solve: one wavefront per pencil.  Right-hand side of the real-scaled system
-// built in LDS (two real vectors: the real and imaginary parts), overwritten
-// by y = L^{-1} P b and then by x~ = U^{-1} y; finally X = P^R x~ is written in
-// the state layout with the real scaling undone.
-//
-// Factor data streams through LDS in chunks of CH columns, double buffered:
-// while a chunk is swept, the next one is loaded into registers and stored to
-// the other buffer at the end of the chunk, so HBM latency hides behind the
-// sweep.  FW / BW are compile-time so that window lanes are immediates and
-// the y / x stores provably do not alias the b loads ahead of them.
+// Sweeps of one real right-hand side b (this wavefront's own vector in LDS,
+// padded: BW finite values before row 0, FW after row npad - 1, npad = nch *
+// kCH) through the stored factors of one pencil:
+//   forward  y = L^{-1} P b  (window of FW pending rows in physical slots:
+//            lane s holds the row in slot s; the pivot's slot is refilled
+//            with the next row, the others take the rank-1 update);
+//   backward x = U^{-1} y    (lane l carries row r = l mod BW of the window
+//            [j - BW + 1, j]; lane j mod BW holds 1 / U(j, j)).
+// Factor coefficients stream from global memory straight into a ring of
+// kRing registers per lane, kRing columns ahead of their use: no LDS staging
+// and no barrier, so each wavefront sweeps on its own.  The factor arrays
+// hold nst = npad columns per pencil (zero beyond n) with kRing columns of
+// slack before the first pencil and after the last, so the look-ahead loads
+// never leave the allocation (their values past the sweep are not used).
 // ---------------------------------------------------------------------------
-// Forward (L, with the LAPACK interchanges through physical slots) and
-// backward (U, circular window) sweeps of one real right-hand side b of
-// length n (padded: BW zeros before, FW after, chunk multiple).  One
-// wavefront; the two wavefronts of a block run them on their own vectors and
-// share the factor chunks staged in fbuf.
-template <typename T, int FW, int BW, int CH>
+template <typename T, int FW, int BW>
 __device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uint32_t* __restrict__ sw,
-                                       const T* __restrict__ Up, T* fbuf, int n, int tid) {
-  const int lane = tid & (kWave - 1);
-  const int nch = (n + CH - 1) / CH;
+                                       const T* __restrict__ Up, int nch, int lane) {
+  constexpr int CH = kCH, D = kRing, G = 16;
+  static_assert(CH % D == 0 && D % 4 == 0 && CH % G == 0 && CH % BW == 0 && FW <= 32 && BW <= 64,
+                "sweep geometry");
   const int npad = nch * CH;
 
-  // ---- forward sweep: window of FW pending rows, physical slots 0..FW-1 ----
-  constexpr int LPT = CH * FW / (2 * kWave);
-  constexpr int G = 16;  // insert values preloaded per group of columns
-  T regL[LPT];
-  uint32_t regS = 0;
-  uint32_t* sbuf = (uint32_t*)(fbuf + 2 * CH * BW);  // [2][CH/4] words
-  auto loadL = [&](int c) {
-    const int base = c * CH * FW, lim = n * FW;
-#pragma unroll
-    for (int k = 0; k < LPT; ++k) {
-      const int idx = tid + k * 2 * kWave;
-      regL[k] = base + idx < lim ? Lp[base + idx] : (T)0;
-    }
-    const int w4 = c * (CH / 4) + tid;
-    regS = (tid < CH / 4 && 4 * w4 < n) ? sw[w4] : 0u;
-  };
-  auto storeL = [&](int buf) {
-    T* dst = fbuf + buf * CH * BW;
-#pragma unroll
-    for (int k = 0; k < LPT; ++k) dst[tid + k * 2 * kWave] = regL[k];
-    if (tid < CH / 4) sbuf[buf * (CH / 4) + tid] = regS;
-  };
-  loadL(0);
-  storeL(0);
-  __syncthreads();
+  // ---- forward sweep
   const int lf = lane & (FW - 1);
+  T ring[D];
+  uint32_t sring[D / 4];
+#pragma unroll
+  for (int k = 0; k < D; ++k) ring[k] = Lp[k * FW + lf];
+#pragma unroll
+  for (int k = 0; k < D / 4; ++k) sring[k] = sw[k];
   T w = lane < FW ? b[lane] : (T)0;
   for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) loadL(c + 1);
     const int j0 = c * CH;
-    const T* Lc = fbuf + (c & 1) * CH * BW + lf;
-    const uint32_t* Sc = sbuf + (c & 1) * (CH / 4);
-    uint32_t sword[CH / 4];
-#pragma unroll
-    for (int k = 0; k < CH / 4; ++k) sword[k] = __builtin_amdgcn_readfirstlane(Sc[k]);
-    T lc[CH];
-#pragma unroll
-    for (int t = 0; t < CH; ++t) lc[t] = Lc[t * FW];
-#pragma unroll
-    for (int t = 0; t < CH; ++t) pin(lc[t]);
+    const T* Ln = Lp + (size_t)(j0 + D) * FW + lf;  // column j0 + D + t at Ln[t * FW]
+    const uint32_t* Sn = sw + (j0 + D) / 4;
     T* yo = b + j0;
     T nv[2][G];
 #pragma unroll
     for (int k = 0; k < G; ++k) nv[0][k] = yo[k + FW];
 #pragma unroll
     for (int k = 0; k < G; ++k) pin(nv[0][k]);
+    uint32_t word = 0;
 #pragma unroll
     for (int g = 0; g < CH / G; ++g) {
       if (g + 1 < CH / G) {
@@ -272,52 +251,33 @@ __device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uin
 #pragma unroll
       for (int k = 0; k < G; ++k) {
         const int t = g * G + k;
-        const int s = (sword[t >> 2] >> (8 * (t & 3))) & 0xff;
+        if ((t & 3) == 0) word = __builtin_amdgcn_readfirstlane(sring[(t >> 2) % (D / 4)]);
+        const int s = (word >> (8 * (t & 3))) & 0xff;
         const T y = readlane_t(w, s);
         yo[t] = y;  // every lane stores the same value
-        w = lane == s ? nv[g & 1][k] : fma(-lc[t], y, w);
+        const T l = ring[t % D];
+        ring[t % D] = Ln[t * FW];
+        if ((t & 3) == 3) sring[(t >> 2) % (D / 4)] = Sn[t >> 2];
+        w = lane == s ? nv[g & 1][k] : fma(-l, y, w);
       }
       if (g + 1 < CH / G) {
 #pragma unroll
         for (int k = 0; k < G; ++k) pin(nv[(g + 1) & 1][k]);
       }
     }
-    if (c + 1 < nch) storeL((c + 1) & 1);
-    __syncthreads();
   }
 
-  // ---- backward sweep: lane l carries the row r = l (mod BW) of [j-BW+1, j]
-  constexpr int UPT = CH * BW / (2 * kWave);
-  T regU[UPT];
-  auto loadU = [&](int c) {
-    const int base = c * CH * BW, lim = n * BW;
-#pragma unroll
-    for (int k = 0; k < UPT; ++k) {
-      const int idx = tid + k * 2 * kWave;
-      regU[k] = base + idx < lim ? Up[base + idx] : (T)0;
-    }
-  };
-  auto storeU = [&](int buf) {
-    T* dst = fbuf + buf * CH * BW;
-#pragma unroll
-    for (int k = 0; k < UPT; ++k) dst[tid + k * 2 * kWave] = regU[k];
-  };
-  loadU(nch - 1);
-  storeU((nch - 1) & 1);
-  __syncthreads();
+  // ---- backward sweep (columns descending)
   const int lb = lane & (BW - 1);
+#pragma unroll
+  for (int k = 0; k < D; ++k) ring[k] = Up[(size_t)(npad - D + k) * BW + lb];  // slot j mod D
   // rows npad-BW .. npad-1 (rows >= n hold finite padding; their U
   // coefficients are zero)
   w = b[npad - BW + lb];
   for (int c = nch - 1; c >= 0; --c) {
-    if (c > 0) loadU(c - 1);
-    const T* Uc = fbuf + (c & 1) * CH * BW + lb;
-    T uc[CH];
-#pragma unroll
-    for (int t = 0; t < CH; ++t) uc[t] = Uc[t * BW];
-#pragma unroll
-    for (int t = 0; t < CH; ++t) pin(uc[t]);
-    T* xo = b + c * CH;
+    const int j0 = c * CH;
+    const T* Un = Up + ((ptrdiff_t)j0 - D) * BW + lb;  // column j0 - D + t at Un[t * BW]
+    T* xo = b + j0;
     constexpr int NG = CH / G;
     T nv[2][G];
 #pragma unroll
@@ -334,56 +294,31 @@ __device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uin
       for (int k = G - 1; k >= 0; --k) {
         const int t = g * G + k;
         const int sj = t % BW;
-        const T x = readlane_t(w * uc[t], sj);
+        const T u = ring[t % D];
+        ring[t % D] = Un[t * BW];
+        const T x = readlane_t(w * u, sj);
         xo[t] = x;  // every lane stores the same value
-        w = lb == sj ? nv[g & 1][k] : fma(-uc[t], x, w);
+        w = lb == sj ? nv[g & 1][k] : fma(-u, x, w);
       }
       if (g > 0) {
 #pragma unroll
         for (int k = 0; k < G; ++k) pin(nv[(g - 1) & 1][k]);
       }
     }
-    if (c > 0) storeU((c - 1) & 1);
-    __syncthreads();
   }
 }
 
-template <int FW, int BW, int CH>
-__global__ void __launch_bounds__(2 * kWave) solve_kernel(PencilArgs a,
-                                                          const double2* __restrict__ Bev,
-                                                          const double* __restrict__ Lf,
-                                                          const uint8_t* __restrict__ sl,
-                                                          const double* __restrict__ Uf,
-                                                          double2* __restrict__ X) {
-  // Two wavefronts per pencil: wave 0 solves for the real part of the
-  // right-hand side, wave 1 for the imaginary part (the real-scaled matrix is
-  // real).  Both share the factor chunks staged in LDS.
-  static_assert(CH % BW == 0 && CH == kWave && (CH * FW) % (2 * kWave) == 0 &&
-                    (CH * BW) % (2 * kWave) == 0,
-                "chunking");
-  extern __shared__ double lds[];
-  const int p = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // 0: real part, 1: imaginary part
-  const int n = a.n, N = a.desc.N, S = a.desc.S, kb = a.desc.kb, ne = a.desc.ne;
+// Right-hand side of the real-scaled system for one pencil, one real part
+// (part 0: real, 1: imaginary), written to b[-BW .. npad + FW): boundary rows
+// take the Dirichlet values (b at the mean pencil), the evolved-equation
+// U-rows n <= N-2 the entries of Bev (u, v rows times i), all else zero.
+template <typename T>
+__device__ __forceinline__ void build_rhs(const PencilArgs& a, const PencilCoef& pc,
+                                          const double2* __restrict__ Bp, int part, T* b, double* b64,
+                                          int BW, int FW, int npad, int lane) {
   const SysDesc& d = a.desc;
-  double2* Xp = X + (size_t)p * S * N;
-  if (!pencil_active(a, p)) {
-    for (int i = tid; i < S * N; i += 2 * kWave) Xp[i] = make_double2(0.0, 0.0);
-    return;
-  }
-  const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
-  const int nch = (n + CH - 1) / CH;
-  const int npad = nch * CH;
-  // right-hand side vectors with BW zeros in front and FW zeros behind, so the
-  // sweeps read their look-ahead / look-behind rows without bounds checks
-  const int span = BW + npad + FW;
-  double* bre = lds + BW;
-  double* bim = lds + span + BW;
-  double* fbuf = lds + 2 * span;  // [2][CH*BW] doubles (U chunks) / [2][CH*FW] (L chunks)
-  const double2* Bp = Bev + (size_t)p * ne * N;
-  for (int r = tid - BW; r < npad + FW; r += 2 * kWave) {
+  const int n = a.n, N = d.N, kb = d.kb, ne = d.ne;
+  for (int r = lane - BW; r < npad + FW; r += kWave) {
     double vr = 0.0, vi = 0.0;
     if (r >= 0 && r < kb) {
       if (pc.mean && d.bc_var[r] == VB) vr = d.bc_side[r] == 0 ? a.b_bottom : a.b_top;
@@ -397,7 +332,7 @@ __global__ void __launch_bounds__(2 * kWave) solve_kernel(PencilArgs a,
       if (eq == EV) e = 2;
       if (eq == EW) e = ne - 1;
       if (e >= 0 && m <= N - 2) {
-        double2 v = Bp[e * N + m];
+        const double2 v = Bp[e * N + m];
         if (eq == EU || eq == EV) {  // row scaled by i
           vr = -v.y;
           vi = v.x;
@@ -407,21 +342,25 @@ __global__ void __launch_bounds__(2 * kWave) solve_kernel(PencilArgs a,
         }
       }
     }
-    bre[r] = vr;
-    bim[r] = vi;
+    const double v = part == 0 ? vr : vi;
+    b[r] = (T)v;
+    if (b64 && r >= 0 && r < n) b64[r] = v;
   }
-  double* b = wv == 0 ? bre : bim;
-  sweeps<double, FW, BW, CH>(b, Lf + (size_t)p * n * FW, (const uint32_t*)(sl + (size_t)p * n),
-                             Uf + (size_t)p * n * BW, fbuf, n, tid);
-  // --- X = P^R x~, undo the real scaling, state layout
-  for (int i = tid; i < S * N; i += 2 * kWave) {
+}
+
+// X = P^R x~ with the real scaling undone, state layout (both parts in LDS).
+__device__ __forceinline__ void write_state(const PencilArgs& a, const double* xr_, const double* xi_,
+                                            double2* __restrict__ Xp, int tid, int nt) {
+  const SysDesc& d = a.desc;
+  const int N = d.N, S = d.S;
+  for (int i = tid; i < S * N; i += nt) {
     const int vabi = i / N, m = i - vabi * N;
     const int var = a.var_of_abi[vabi];
     const int pos = d.var_pos[var];
-    double xr = bre[m * S + pos], xi = bim[m * S + pos];
+    double xr = xr_[m * S + pos], xi = xi_[m * S + pos];
     if (m + 2 < N) {
-      xr -= bre[(m + 2) * S + pos];
-      xi -= bim[(m + 2) * S + pos];
+      xr -= xr_[(m + 2) * S + pos];
+      xi -= xi_[(m + 2) * S + pos];
     }
     if (var == VU || var == VUZ || var == VV || var == VVZ)
       Xp[i] = make_double2(xi, -xr);  // u = -i u~
@@ -430,40 +369,63 @@ __global__ void __launch_bounds__(2 * kWave) solve_kernel(PencilArgs a,
   }
 }
 
-// Sum over aligned groups of W lanes (W a power of two <= 64); every lane of
-// a group receives the group sum.
-template <int W>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int off = W / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+// ---------------------------------------------------------------------------
+// Solve: two wavefronts per pencil, wave 0 for the real part of the
+// right-hand side and wave 1 for the imaginary part (the real-scaled matrix
+// is real).  Each builds its vector in LDS, overwrites it by y = L^{-1} P b
+// and x~ = U^{-1} y, and after one barrier both write X = P^R x~.
+// ---------------------------------------------------------------------------
+template <int FW, int BW>
+__global__ void __launch_bounds__(2 * kWave) solve_kernel(PencilArgs a,
+                                                          const double2* __restrict__ Bev,
+                                                          const double* __restrict__ Lf,
+                                                          const uint8_t* __restrict__ sl,
+                                                          const double* __restrict__ Uf,
+                                                          double2* __restrict__ X) {
+  extern __shared__ double lds[];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const SysDesc& d = a.desc;
+  const int N = d.N, S = d.S, ne = d.ne;
+  double2* Xp = X + (size_t)p * S * N;
+  if (!pencil_active(a, p)) {
+    for (int i = tid; i < S * N; i += 2 * kWave) Xp[i] = make_double2(0.0, 0.0);
+    return;
+  }
+  const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
+  const int npad = a.nst, nch = npad / kCH;
+  const int span = BW + npad + FW;
+  double* bre = lds + BW;
+  double* bim = lds + span + BW;
+  double* b = wv == 0 ? bre : bim;
+  build_rhs<double>(a, pc, Bev + (size_t)p * ne * N, wv, b, nullptr, BW, FW, npad, lane);
+  sweeps<double, FW, BW>(b, Lf + (size_t)p * npad * FW, (const uint32_t*)(sl + (size_t)p * npad),
+                         Uf + (size_t)p * npad * BW, nch, lane);
+  __syncthreads();
+  write_state(a, bre, bim, Xp, tid, 2 * kWave);
 }
 
 // ---------------------------------------------------------------------------
 // Transposed solve (adjoint of solve_kernel): B_bar = S_L^H A~^{-T} S_R^H
 // (P^R)^T X_bar, where A~ is the real-scaled recombined matrix, S_R the
-// column scaling (u = -i u~) and S_L the row scaling (u rows times i).  The
-// two sweeps are the exact reverses of the forward register-window sweeps on
-// the same factor storage:
-//   U^T (columns ascending): y_bar[j-BW] = W[sj];  x_tot = x_bar_j -
-//       sum_{l != sj} U_rot[j][l] W[l];  W[sj] = rinv_j x_tot;
-//   L^T (columns descending): b_bar[j+FW] = W[s_j];  W[s_j] = y_bar_j -
-//       sum_l L_phys[j][l] W[l].
+// column scaling (u = -i u~) and S_L the row scaling (u rows times i).  A~^T
+// has its own banded LU with partial pivoting (factor_kernel with a.trans),
+// so A~^{-T} is the same pair of sweeps as the forward solve, on the
+// transposed factors.
 // Epilogue (per pencil): the multistep history adjoints,
 //   F~_bar = c1 B_bar + hF,  MX_bar = -a1 B_bar + hM,  hF <- c2 B_bar,
 //   hM <- -a2 B_bar,  F_bar = (P^L)^T F~_bar,  X_bar_out = (P^L)^T MX_bar on
 //   the evolved variables, zero elsewhere.
 // ---------------------------------------------------------------------------
-template <int FW, int BW, int CH>
+template <int FW, int BW>
 __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
                                                            const double2* __restrict__ Xin,
                                                            const double* __restrict__ Lf,
                                                            const uint8_t* __restrict__ sl,
                                                            const double* __restrict__ Uf,
                                                            double2* Xout, AdjRhsArgs r) {
-  static_assert(CH % BW == 0 && CH == kWave && (CH * FW) % (2 * kWave) == 0 &&
-                    (CH * BW) % (2 * kWave) == 0,
-                "chunking");
   extern __shared__ double lds[];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
@@ -482,15 +444,13 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
     for (int i = tid; i < 2 * ne * N; i += 2 * kWave) hb[i] = make_double2(0.0, 0.0);
     return;
   }
-  const int nch = (n + CH - 1) / CH;
-  const int npad = nch * CH;
+  const int npad = a.nst, nch = npad / kCH;
   const int span = BW + npad + FW;
   double* bre = lds + BW;
   double* bim = lds + span + BW;
-  double* fbuf = lds + 2 * span;
-  uint32_t* sbuf = (uint32_t*)(fbuf + 2 * CH * BW);
-  // x~_bar = S_R^H (P^R)^T X_bar in system column order
-  for (int c = tid - BW; c < npad + FW; c += 2 * kWave) {
+  double* b = wv == 0 ? bre : bim;
+  // x~_bar = S_R^H (P^R)^T X_bar in system column order (this wave's part)
+  for (int c = lane - BW; c < npad + FW; c += kWave) {
     double vr = 0.0, vi = 0.0;
     if (c >= 0 && c < n) {
       const int m = c / S, pos = c - m * S;
@@ -510,101 +470,10 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
         vi = v.y;
       }
     }
-    bre[c] = vr;
-    bim[c] = vi;
+    b[c] = wv == 0 ? vr : vi;
   }
-  double* b = wv == 0 ? bre : bim;
-  const double* Lp = Lf + (size_t)p * n * FW;
-  const uint32_t* sw = (const uint32_t*)(sl + (size_t)p * n);
-  const double* Up = Uf + (size_t)p * n * BW;
-
-  // ---- U^T sweep (ascending) ---------------------------------------------
-  constexpr int UPT = CH * BW / (2 * kWave);
-  double regU[UPT];
-  auto loadU = [&](int c) {
-    const int base = c * CH * BW, lim = n * BW;
-#pragma unroll
-    for (int k = 0; k < UPT; ++k) {
-      const int idx = tid + k * 2 * kWave;
-      regU[k] = base + idx < lim ? Up[base + idx] : 0.0;
-    }
-  };
-  auto storeU = [&](int buf) {
-    double* dst = fbuf + buf * CH * BW;
-#pragma unroll
-    for (int k = 0; k < UPT; ++k) dst[tid + k * 2 * kWave] = regU[k];
-  };
-  loadU(0);
-  storeU(0);
-  __syncthreads();
-  const int lb = lane & (BW - 1);
-  double w = 0.0;
-  for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) loadU(c + 1);
-    const double* Uc = fbuf + (c & 1) * CH * BW + lb;
-    double* xo = b + c * CH;
-#pragma unroll 8
-    for (int t = 0; t < CH; ++t) {
-      const int sj = t % BW;
-      const double u = Uc[t * BW];
-      const double xin = xo[t];
-      const double wsj = readlane_d(w, sj);
-      xo[t - BW] = wsj;  // y_bar[j - BW]; every lane stores the same value
-      const bool mine = lb == sj;
-      const double dot = group_sum<BW>(mine ? 0.0 : u * w);
-      const double xt = xin - dot;
-      w = mine ? u * xt : w;
-    }
-    if (c + 1 < nch) storeU((c + 1) & 1);
-    __syncthreads();
-  }
-  if (lane < BW) b[npad - BW + lane] = w;
-  __syncthreads();
-
-  // ---- L^T sweep (descending) --------------------------------------------
-  constexpr int LPT = CH * FW / (2 * kWave);
-  double regL[LPT];
-  uint32_t regS = 0;
-  auto loadL = [&](int c) {
-    const int base = c * CH * FW, lim = n * FW;
-#pragma unroll
-    for (int k = 0; k < LPT; ++k) {
-      const int idx = tid + k * 2 * kWave;
-      regL[k] = base + idx < lim ? Lp[base + idx] : 0.0;
-    }
-    const int w4 = c * (CH / 4) + tid;
-    regS = (tid < CH / 4 && 4 * w4 < n) ? sw[w4] : 0u;
-  };
-  auto storeL = [&](int buf) {
-    double* dst = fbuf + buf * CH * BW;
-#pragma unroll
-    for (int k = 0; k < LPT; ++k) dst[tid + k * 2 * kWave] = regL[k];
-    if (tid < CH / 4) sbuf[buf * (CH / 4) + tid] = regS;
-  };
-  loadL(nch - 1);
-  storeL((nch - 1) & 1);
-  __syncthreads();
-  const int lf = lane & (FW - 1);
-  w = 0.0;
-  for (int c = nch - 1; c >= 0; --c) {
-    if (c > 0) loadL(c - 1);
-    const double* Lc = fbuf + (c & 1) * CH * BW + lf;
-    const uint32_t* Sc = sbuf + (c & 1) * (CH / 4);
-    double* yo = b + c * CH;
-#pragma unroll 8
-    for (int t = CH - 1; t >= 0; --t) {
-      const int s = (__builtin_amdgcn_readfirstlane(Sc[t >> 2]) >> (8 * (t & 3))) & 0xff;
-      const double lj = Lc[t * FW];
-      const double yin = yo[t];
-      const double wsj = readlane_d(w, s);
-      yo[t + FW] = wsj;  // b_bar[j + FW]
-      const double dot = group_sum<FW>(lane < FW ? lj * w : 0.0);
-      w = lane == s ? yin - dot : w;
-    }
-    if (c > 0) storeL((c - 1) & 1);
-    __syncthreads();
-  }
-  if (lane < FW) b[lane] = w;
+  sweeps<double, FW, BW>(b, Lf + (size_t)p * npad * FW, (const uint32_t*)(sl + (size_t)p * npad),
+                         Uf + (size_t)p * npad * BW, nch, lane);
   __syncthreads();
 
   // ---- epilogue: history adjoints, (P^L)^T, state-layout outputs --------------
@@ -652,8 +521,10 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
 // FP64 residual r = b - A x^ from the operator templates (boundary rows
 // included), one FP32 correction sweep, x = x^ + d accumulated in FP64.
 // The right-hand side (boundary values included) and the output stay FP64.
+// Per wavefront (one real part) in LDS: b64[n] (FP64 right-hand side, then
+// the solution), w32 (padded FP32 sweep vector), xh[n] (FP32 first solution).
 // ---------------------------------------------------------------------------
-template <int FW, int BW, int CH>
+template <int FW, int BW>
 __global__ void __launch_bounds__(2 * kWave) solve_mixed_kernel(
     PencilArgs a, double a0, double b0, const double2* __restrict__ Bev,
     const float* __restrict__ Lf, const uint8_t* __restrict__ sl, const float* __restrict__ Uf,
@@ -663,7 +534,7 @@ __global__ void __launch_bounds__(2 * kWave) solve_mixed_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int n = a.n, N = a.desc.N, S = a.desc.S, kb = a.desc.kb, ne = a.desc.ne;
+  const int n = a.n, N = a.desc.N, S = a.desc.S, ne = a.desc.ne;
   const SysDesc& d = a.desc;
   double2* Xp = X + (size_t)p * S * N;
   if (!pencil_active(a, p)) {
@@ -671,58 +542,20 @@ __global__ void __launch_bounds__(2 * kWave) solve_mixed_kernel(
     return;
   }
   const PencilCoef pc = pencil_coef(a, p, a0, b0);
-  const int nch = (n + CH - 1) / CH;
-  const int npad = nch * CH;
+  const int npad = a.nst, nch = npad / kCH;
   const int span = BW + npad + FW;
   double* b64r = lds;
   double* b64i = lds + n;
-  float* f0 = (float*)(lds + 2 * n);
-  float* w32r = f0 + BW;
-  float* w32i = f0 + span + BW;
-  float* xhr = f0 + 2 * span;
-  float* xhi = xhr + n;
-  float* fbuf = xhi + n;  // [2][CH*BW] floats, then slot words
-  const double2* Bp = Bev + (size_t)p * ne * N;
-  for (int r = tid - BW; r < npad + FW; r += 2 * kWave) {
-    double vr = 0.0, vi = 0.0;
-    if (r >= 0 && r < kb) {
-      if (pc.mean && d.bc_var[r] == VB) vr = d.bc_side[r] == 0 ? a.b_bottom : a.b_top;
-    } else if (r >= kb && r < n) {
-      int epos;
-      const int m = sys_row_mode(d, r, &epos);
-      const int eq = d.eq_at[epos];
-      int e = -1;
-      if (eq == EB) e = 0;
-      if (eq == EU) e = 1;
-      if (eq == EV) e = 2;
-      if (eq == EW) e = ne - 1;
-      if (e >= 0 && m <= N - 2) {
-        double2 v = Bp[e * N + m];
-        if (eq == EU || eq == EV) {
-          vr = -v.y;
-          vi = v.x;
-        } else {
-          vr = v.x;
-          vi = v.y;
-        }
-      }
-    }
-    if (r >= 0 && r < n) {
-      b64r[r] = vr;
-      b64i[r] = vi;
-    }
-    w32r[r] = (float)vr;
-    w32i[r] = (float)vi;
-  }
-  float* w = wv == 0 ? w32r : w32i;
-  float* xh = wv == 0 ? xhr : xhi;
   double* b64 = wv == 0 ? b64r : b64i;
-  const float* Lp = Lf + (size_t)p * n * FW;
-  const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * n);
-  const float* Up = Uf + (size_t)p * n * BW;
-  sweeps<float, FW, BW, CH>(w, Lp, swp, Up, fbuf, n, tid);
+  float* f0 = (float*)(lds + 2 * n) + (size_t)wv * (span + n);
+  float* w = f0 + BW;
+  float* xh = f0 + span;
+  build_rhs<float>(a, pc, Bev + (size_t)p * ne * N, wv, w, b64, BW, FW, npad, lane);
+  const float* Lp = Lf + (size_t)p * npad * FW;
+  const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
+  const float* Up = Uf + (size_t)p * npad * BW;
+  sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
   for (int r = lane; r < n; r += kWave) xh[r] = w[r];
-  __syncthreads();
   for (int r = lane; r < npad + FW; r += kWave) {
     if (r < n) {
       const double ax =
@@ -732,24 +565,10 @@ __global__ void __launch_bounds__(2 * kWave) solve_mixed_kernel(
       w[r] = 0.0f;
     }
   }
-  __syncthreads();
-  sweeps<float, FW, BW, CH>(w, Lp, swp, Up, fbuf, n, tid);
+  sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
   for (int r = lane; r < n; r += kWave) b64[r] = (double)xh[r] + (double)w[r];
   __syncthreads();
-  for (int i = tid; i < S * N; i += 2 * kWave) {
-    const int vabi = i / N, m = i - vabi * N;
-    const int var = a.var_of_abi[vabi];
-    const int pos = d.var_pos[var];
-    double xr = b64r[m * S + pos], xi = b64i[m * S + pos];
-    if (m + 2 < N) {
-      xr -= b64r[(m + 2) * S + pos];
-      xi -= b64i[(m + 2) * S + pos];
-    }
-    if (var == VU || var == VUZ || var == VV || var == VVZ)
-      Xp[i] = make_double2(xi, -xr);
-    else
-      Xp[i] = make_double2(xr, xi);
-  }
+  write_state(a, b64r, b64i, Xp, tid, 2 * kWave);
 }
 
 __global__ void round_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
@@ -762,36 +581,39 @@ __global__ void round_to_f32_kernel(const double* __restrict__ src, float* __res
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+int factor_stride(int n) { return (n + kCH - 1) / kCH * kCH; }
+int factor_slack() { return kRing; }
+
 hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, uint8_t* sl,
                          double* Uf, int* sing, hipStream_t st) {
-  const int ld = a.kl + a.ku + a.kl + 1;
+  const int kv = a.kl + a.ku, ld = kv + a.kl + 1;
   size_t lds = (size_t)kCW * ld * sizeof(double);
   hipLaunchKernelGGL(factor_kernel, dim3(a.P), dim3(kWave), lds, st, a, a0, b0, Lf, sl, Uf, sing);
   return hipGetLastError();
 }
 
-constexpr int kCH = 64;
+static void allow_lds(const void* fn, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+#define STAU_SWEEP_VARIANTS(X) X(8, 32) X(8, 64) X(16, 32) X(16, 64) X(32, 32) X(32, 64)
 
 template <int FW, int BW>
 static hipError_t launch_solve_t(const PencilArgs& a, const void* Bev, const double* Lf,
                                  const uint8_t* sl, const double* Uf, void* X, hipStream_t st) {
-  const int npad = (a.n + kCH - 1) / kCH * kCH;
-  size_t lds = (size_t)(2 * (BW + npad + FW) + 2 * kCH * BW) * sizeof(double) + 2 * kCH;
-  auto fn = solve_kernel<FW, BW, kCH>;
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(fn, dim3(a.P), dim3(2 * kWave), lds, st, a, (const double2*)Bev, Lf, sl, Uf,
-                     (double2*)X);
+  size_t lds = (size_t)2 * (BW + a.nst + FW) * sizeof(double);
+  allow_lds((const void*)solve_kernel<FW, BW>, lds);
+  hipLaunchKernelGGL((solve_kernel<FW, BW>), dim3(a.P), dim3(2 * kWave), lds, st, a,
+                     (const double2*)Bev, Lf, sl, Uf, (double2*)X);
   return hipGetLastError();
 }
 
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
                         const double* Uf, void* X, hipStream_t st) {
-  if (a.FW == 8 && a.BW == 32) return launch_solve_t<8, 32>(a, Bev, Lf, sl, Uf, X, st);
-  if (a.FW == 8 && a.BW == 64) return launch_solve_t<8, 64>(a, Bev, Lf, sl, Uf, X, st);
-  if (a.FW == 16 && a.BW == 32) return launch_solve_t<16, 32>(a, Bev, Lf, sl, Uf, X, st);
-  if (a.FW == 16 && a.BW == 64) return launch_solve_t<16, 64>(a, Bev, Lf, sl, Uf, X, st);
-  if (a.FW == 32 && a.BW == 64) return launch_solve_t<32, 64>(a, Bev, Lf, sl, Uf, X, st);
+#define STAU_CASE(F, B) \
+  if (a.FW == F && a.BW == B) return launch_solve_t<F, B>(a, Bev, Lf, sl, Uf, X, st);
+  STAU_SWEEP_VARIANTS(STAU_CASE)
+#undef STAU_CASE
   return hipErrorInvalidValue;
 }
 
@@ -799,26 +621,21 @@ template <int FW, int BW>
 static hipError_t launch_solve_mixed_t(const PencilArgs& a, double a0, double b0, const void* Bev,
                                        const float* Lf, const uint8_t* sl, const float* Uf,
                                        void* X, hipStream_t st) {
-  const int npad = (a.n + kCH - 1) / kCH * kCH;
-  const int span = BW + npad + FW;
-  size_t lds = (size_t)2 * a.n * sizeof(double) +
-               (size_t)(2 * span + 2 * a.n + 2 * kCH * BW) * sizeof(float) + 2 * kCH;
-  auto fn = solve_mixed_kernel<FW, BW, kCH>;
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(fn, dim3(a.P), dim3(2 * kWave), lds, st, a, a0, b0, (const double2*)Bev, Lf,
-                     sl, Uf, (double2*)X);
+  const int span = BW + a.nst + FW;
+  size_t lds = (size_t)2 * a.n * sizeof(double) + (size_t)2 * (span + a.n) * sizeof(float);
+  allow_lds((const void*)solve_mixed_kernel<FW, BW>, lds);
+  hipLaunchKernelGGL((solve_mixed_kernel<FW, BW>), dim3(a.P), dim3(2 * kWave), lds, st, a, a0, b0,
+                     (const double2*)Bev, Lf, sl, Uf, (double2*)X);
   return hipGetLastError();
 }
 
 hipError_t launch_solve_mixed(const PencilArgs& a, double a0, double b0, const void* Bev,
                               const float* Lf, const uint8_t* sl, const float* Uf, void* X,
                               hipStream_t st) {
-  if (a.FW == 8 && a.BW == 32) return launch_solve_mixed_t<8, 32>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
-  if (a.FW == 8 && a.BW == 64) return launch_solve_mixed_t<8, 64>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
-  if (a.FW == 16 && a.BW == 32) return launch_solve_mixed_t<16, 32>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
-  if (a.FW == 16 && a.BW == 64) return launch_solve_mixed_t<16, 64>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
-  if (a.FW == 32 && a.BW == 64) return launch_solve_mixed_t<32, 64>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
+#define STAU_CASE(F, B) \
+  if (a.FW == F && a.BW == B) return launch_solve_mixed_t<F, B>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
+  STAU_SWEEP_VARIANTS(STAU_CASE)
+#undef STAU_CASE
   return hipErrorInvalidValue;
 }
 
@@ -831,23 +648,19 @@ template <int FW, int BW>
 static hipError_t launch_solveT_t(const PencilArgs& a, const void* Xin, const double* Lf,
                                   const uint8_t* sl, const double* Uf, void* Xout,
                                   const AdjRhsArgs& r, hipStream_t st) {
-  const int npad = (a.n + kCH - 1) / kCH * kCH;
-  size_t lds = (size_t)(2 * (BW + npad + FW) + 2 * kCH * BW) * sizeof(double) + 2 * kCH;
-  auto fn = solveT_kernel<FW, BW, kCH>;
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(fn, dim3(a.P), dim3(2 * kWave), lds, st, a, (const double2*)Xin, Lf, sl, Uf,
-                     (double2*)Xout, r);
+  size_t lds = (size_t)2 * (BW + a.nst + FW) * sizeof(double);
+  allow_lds((const void*)solveT_kernel<FW, BW>, lds);
+  hipLaunchKernelGGL((solveT_kernel<FW, BW>), dim3(a.P), dim3(2 * kWave), lds, st, a,
+                     (const double2*)Xin, Lf, sl, Uf, (double2*)Xout, r);
   return hipGetLastError();
 }
 
 hipError_t launch_solveT(const PencilArgs& a, const void* Xin, const double* Lf, const uint8_t* sl,
                          const double* Uf, void* Xout, const AdjRhsArgs& r, hipStream_t st) {
-  if (a.FW == 8 && a.BW == 32) return launch_solveT_t<8, 32>(a, Xin, Lf, sl, Uf, Xout, r, st);
-  if (a.FW == 8 && a.BW == 64) return launch_solveT_t<8, 64>(a, Xin, Lf, sl, Uf, Xout, r, st);
-  if (a.FW == 16 && a.BW == 32) return launch_solveT_t<16, 32>(a, Xin, Lf, sl, Uf, Xout, r, st);
-  if (a.FW == 16 && a.BW == 64) return launch_solveT_t<16, 64>(a, Xin, Lf, sl, Uf, Xout, r, st);
-  if (a.FW == 32 && a.BW == 64) return launch_solveT_t<32, 64>(a, Xin, Lf, sl, Uf, Xout, r, st);
+#define STAU_CASE(F, B) \
+  if (a.FW == F && a.BW == B) return launch_solveT_t<F, B>(a, Xin, Lf, sl, Uf, Xout, r, st);
+  STAU_SWEEP_VARIANTS(STAU_CASE)
+#undef STAU_CASE
   return hipErrorInvalidValue;
 }
 

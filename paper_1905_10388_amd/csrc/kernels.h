@@ -13,6 +13,9 @@ constexpr int kMaxFields = 16;
 struct PencilArgs {
   SysDesc desc;
   int n, kl, ku, FW, BW;
+  int nst;    // factor columns stored per pencil (n rounded up to the sweep chunk; zero beyond n)
+  int trans;  // 1: the factors are those of the transposed matrix
+
   int P, Px, Ny;
   double kappa, nu, buoyancy, b_bottom, b_top;
   double two_pi_over_Lx, two_pi_over_Ly;
@@ -62,7 +65,11 @@ struct AccList {
   int deriv[9][2];
 };
 
-// pencil kernels
+// pencil kernels: factor arrays hold factor_stride(n) columns per pencil with
+// factor_slack() columns of zero slack before the first and after the last
+// pencil (the solve's look-ahead loads read into them)
+int factor_stride(int n);
+int factor_slack();
 hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, uint8_t* sl,
                          double* Uf, int* sing, hipStream_t st);
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,

@@ -99,7 +99,12 @@ struct stau_pencils {
   double2* Bev = nullptr;  // [P][ne][N]
   double2* Gb = nullptr;   // [NF][M][P] adjoint workspace
   double2* wvec = nullptr; // [N] Chebyshev integration weights of the KE functional
+  // Factor storage of one (a0, b0): factor_stride(n) columns per pencil plus
+  // factor_slack() zero columns before and after (raw pointers own the memory).
   struct FactorSlot {
+    double *Lraw = nullptr, *Uraw = nullptr;
+    uint8_t* sraw = nullptr;
+    float *L32raw = nullptr, *U32raw = nullptr;
     double* Lf = nullptr;
     uint8_t* sl = nullptr;
     double* Uf = nullptr;
@@ -108,7 +113,8 @@ struct stau_pencils {
     bool valid = false;
     double a0 = 0.0, b0 = 0.0;
     int64_t stamp = 0;
-  } slot[2];
+  } slot[2], slotT[2];    // slotT: factors of the transposed matrices (adjoint)
+  PencilArgs paT{};       // band description of the transposed system
   int64_t clock = 0;
   double* Lf = nullptr;     // factors of the most recent stau_factor (aliases a slot)
   uint8_t* sl = nullptr;
@@ -357,16 +363,55 @@ static void free_pencils(stau_pencils* p) {
   hipFree(p->Bev);
   hipFree(p->Gb);
   hipFree(p->wvec);
-  for (auto& f : p->slot) {
-    hipFree(f.Lf);
-    hipFree(f.sl);
-    hipFree(f.Uf);
-    hipFree(f.Lf32);
-    hipFree(f.Uf32);
-  }
+  for (auto* set : {p->slot, p->slotT})
+    for (int k = 0; k < 2; ++k) {
+      auto& f = set[k];
+      hipFree(f.Lraw);
+      hipFree(f.sraw);
+      hipFree(f.Uraw);
+      hipFree(f.L32raw);
+      hipFree(f.U32raw);
+      f = stau_pencils::FactorSlot{};
+    }
   hipFree(p->sing);
   hipFree(p->flag);
   hipFree(p->scratch);
+}
+
+// Allocate (zeroed) factor storage for one slot of the band description pa.
+static hipError_t alloc_slot(stau_pencils::FactorSlot& f, const PencilArgs& pa, bool mixed,
+                             size_t* bytes) {
+  const size_t sk = (size_t)factor_slack();
+  const size_t cols = (size_t)pa.P * pa.nst + 2 * sk;
+  hipError_t e = hipSuccess;
+  auto get = [&](void** ptr, size_t nb) {
+    if (e == hipSuccess) e = hipMalloc(ptr, nb);
+    if (e == hipSuccess) e = hipMemset(*ptr, 0, nb);
+    *bytes += nb;
+  };
+  get((void**)&f.Lraw, cols * pa.FW * sizeof(double));
+  get((void**)&f.Uraw, cols * pa.BW * sizeof(double));
+  get((void**)&f.sraw, cols);
+  if (mixed) {
+    get((void**)&f.L32raw, cols * pa.FW * sizeof(float));
+    get((void**)&f.U32raw, cols * pa.BW * sizeof(float));
+  }
+  if (e != hipSuccess) return e;
+  f.Lf = f.Lraw + sk * pa.FW;
+  f.Uf = f.Uraw + sk * pa.BW;
+  f.sl = f.sraw + sk;
+  if (mixed) {
+    f.Lf32 = f.L32raw + sk * pa.FW;
+    f.Uf32 = f.U32raw + sk * pa.BW;
+  }
+  return hipSuccess;
+}
+
+// Solve window widths for a band: FW >= kl + 1 (8, 16, 32), BW >= kl + ku + 1 (32, 64).
+static bool window_widths(PencilArgs& pa) {
+  pa.FW = pa.kl + 1 <= 8 ? 8 : (pa.kl + 1 <= 16 ? 16 : 32);
+  pa.BW = (pa.kl + pa.ku + 1 <= 32) ? 32 : 64;
+  return pa.kl + 1 <= 32 && pa.kl + pa.ku + 1 <= 64;
 }
 
 int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils** out) {
@@ -385,11 +430,10 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   pen->n = (int64_t)pa.desc.S * N;
   pa.n = (int)pen->n;
   band_widths(pa.desc, pen->n, &pa.kl, &pa.ku);
-  // window widths of the solve (compile-time variants 8/16/32 and 32/64)
-  pa.FW = pa.kl + 1 <= 8 ? 8 : (pa.kl + 1 <= 16 ? 16 : 32);
-  pa.BW = (pa.kl + pa.ku + 1 <= 32) ? 32 : 64;
-  if (pa.kl + 1 > 32 || pa.kl + pa.ku + 1 > 64 || (pa.FW == 32 && pa.BW == 32)) {
-    free_pencils(pen);
+  pa.nst = factor_stride(pa.n);
+  pa.trans = 0;
+  PencilArgs& paT = pen->paT;  // filled below from pa
+  if (!window_widths(pa)) {
     delete pen;
     return fail(STAU_EUNSUPPORTED, "band too wide (kl=%d, ku=%d)", pa.kl, pa.ku);
   }
@@ -403,6 +447,14 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   pa.b_top = par->b_top;
   pa.two_pi_over_Lx = 2.0 * M_PI / d.Lx;
   pa.two_pi_over_Ly = d.dim == 3 ? 2.0 * M_PI / d.Ly : 0.0;
+  paT = pa;
+  paT.kl = pa.ku;
+  paT.ku = pa.kl;
+  paT.trans = 1;
+  if (!window_widths(paT)) {
+    delete pen;
+    return fail(STAU_EUNSUPPORTED, "transposed band too wide (kl=%d, ku=%d)", paT.kl, paT.ku);
+  }
 
   XformArgs& xa = pen->xa;
   xa.dim = d.dim;
@@ -476,9 +528,6 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   const size_t szG = (size_t)fl.nf * M * P * sizeof(double2);
   const size_t szH = ne * M * P * sizeof(double2);
   const size_t szB = P * ne * N * sizeof(double2);
-  const size_t szL = P * n * pa.FW * sizeof(double);
-  const size_t szU = P * n * pa.BW * sizeof(double);
-  const size_t szS = P * n;
   const size_t Ngy = (size_t)dom->Ngy, Px = (size_t)dom->Px;
   const size_t szG2 = d.dim == 3 ? (size_t)fl.nf * M * Ngy * Px * sizeof(double2) : 0;
   const size_t szGb = d.dim == 2 ? szG : 0;  // the adjoint is built for 2-D
@@ -491,13 +540,9 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   if (e == hipSuccess && szGb) e = hipMalloc((void**)&pen->Gb, szGb);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->wvec, (size_t)N * sizeof(double2));
   const bool mixed = d.precision == STAU_MIXED;
-  for (auto& f : pen->slot) {
-    if (e == hipSuccess) e = hipMalloc((void**)&f.Lf, szL);
-    if (e == hipSuccess) e = hipMalloc((void**)&f.sl, szS);
-    if (e == hipSuccess) e = hipMalloc((void**)&f.Uf, szU);
-    if (mixed && e == hipSuccess) e = hipMalloc((void**)&f.Lf32, szL / 2);
-    if (mixed && e == hipSuccess) e = hipMalloc((void**)&f.Uf32, szU / 2);
-  }
+  size_t szF = 0;
+  for (auto& f : pen->slot)
+    if (e == hipSuccess) e = alloc_slot(f, pa, mixed, &szF);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->sing, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->flag, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->scratch, szScratch);
@@ -506,8 +551,7 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
     delete pen;
     return fail(STAU_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
-  pen->ws_bytes = (int64_t)(szG + szG2 + szGb + szH + szB + 2 * (szL + szU + szS) + szScratch +
-                            (mixed ? (szL + szU) : 0));
+  pen->ws_bytes = (int64_t)(szG + szG2 + szGb + szH + szB + szF + szScratch);
   {
     // KE functional weights: integral over z in [0, 1] of T_m = 1 / (1 - m^2), m even
     std::vector<double2> wv(N);
@@ -556,13 +600,14 @@ int stau_query(const stau_pencils* pen, stau_info* info) {
   return STAU_OK;
 }
 
-static int factor_into(stau_pencils* pen, int k, double a0, double b0, hipStream_t st) {
-  auto& f = pen->slot[k];
+static int factor_into(stau_pencils* pen, stau_pencils::FactorSlot* set, const PencilArgs& pa,
+                       int k, double a0, double b0, hipStream_t st) {
+  auto& f = set[k];
   f.valid = false;
   const int big = 0x7fffffff;
   HIP_TRY(hipMemcpyAsync(pen->sing, &big, sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(timed(pen, K_FACTOR, st, [&] {
-    return launch_factor(pen->pa, a0, b0, f.Lf, f.sl, f.Uf, pen->sing, st);
+    return launch_factor(pa, a0, b0, f.Lf, f.sl, f.Uf, pen->sing, st);
   }));
   int h = big;
   HIP_TRY(hipMemcpyAsync(&h, pen->sing, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -572,10 +617,9 @@ static int factor_into(stau_pencils* pen, int k, double a0, double b0, hipStream
     return fail(STAU_ESINGULAR, "zero or non-finite pivot in pencil %d", h);
   }
   if (f.Lf32) {
-    const size_t nl = (size_t)pen->dom->P * pen->n * pen->pa.FW;
-    const size_t nu = (size_t)pen->dom->P * pen->n * pen->pa.BW;
-    HIP_TRY(launch_round_f32(f.Lf, f.Lf32, nl, st));
-    HIP_TRY(launch_round_f32(f.Uf, f.Uf32, nu, st));
+    const size_t cols = (size_t)pa.P * pa.nst;
+    HIP_TRY(launch_round_f32(f.Lf, f.Lf32, cols * pa.FW, st));
+    HIP_TRY(launch_round_f32(f.Uf, f.Uf32, cols * pa.BW, st));
   }
   f.valid = true;
   f.a0 = a0;
@@ -587,20 +631,29 @@ static int factor_into(stau_pencils* pen, int k, double a0, double b0, hipStream
 
 // Factors for (a0, b0): a cached slot if one matches, else refactor the least
 // recently used slot (two slots: the SBDF1 and SBDF2 operators of a run).
+// trans selects the factors of the transposed matrices (allocated on first use).
 static int factors_for(stau_pencils* pen, double a0, double b0, hipStream_t st,
-                       stau_pencils::FactorSlot** out) {
-  for (auto& f : pen->slot)
-    if (f.valid && f.a0 == a0 && f.b0 == b0) {
-      f.stamp = ++pen->clock;
-      *out = &f;
+                       stau_pencils::FactorSlot** out, bool trans = false) {
+  stau_pencils::FactorSlot* set = trans ? pen->slotT : pen->slot;
+  const PencilArgs& pa = trans ? pen->paT : pen->pa;
+  for (int q = 0; q < 2; ++q)
+    if (set[q].valid && set[q].a0 == a0 && set[q].b0 == b0) {
+      set[q].stamp = ++pen->clock;
+      *out = &set[q];
       return STAU_OK;
     }
-  int k = pen->slot[0].stamp <= pen->slot[1].stamp ? 0 : 1;
-  if (!pen->slot[0].valid) k = 0;
-  else if (!pen->slot[1].valid) k = 1;
-  int rc = factor_into(pen, k, a0, b0, st);
+  int k = set[0].stamp <= set[1].stamp ? 0 : 1;
+  if (!set[0].valid) k = 0;
+  else if (!set[1].valid) k = 1;
+  if (!set[k].Lraw) {
+    size_t bytes = 0;
+    hipError_t e = alloc_slot(set[k], pa, false, &bytes);
+    if (e != hipSuccess) return fail(STAU_ENOMEM, "factor allocation failed: %s", hipGetErrorString(e));
+    pen->ws_bytes += (int64_t)bytes;
+  }
+  int rc = factor_into(pen, set, pa, k, a0, b0, st);
   if (rc) return rc;
-  *out = &pen->slot[k];
+  *out = &set[k];
   return STAU_OK;
 }
 
@@ -612,7 +665,7 @@ int stau_factor(stau_pencils* pen, double a0, double b0, void* stream) {
   int k = pen->slot[0].stamp <= pen->slot[1].stamp ? 0 : 1;
   for (int q = 0; q < 2; ++q)
     if (pen->slot[q].valid && pen->slot[q].a0 == a0 && pen->slot[q].b0 == b0) k = q;
-  int rc = factor_into(pen, k, a0, b0, st);
+  int rc = factor_into(pen, pen->slot, pen->pa, k, a0, b0, st);
   pen->Lf = rc ? nullptr : pen->slot[k].Lf;
   pen->sl = rc ? nullptr : pen->slot[k].sl;
   pen->Uf = rc ? nullptr : pen->slot[k].Uf;
@@ -738,7 +791,7 @@ int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, 
   sbdf(iteration, dt, dt_prev, &a0, &a1, &a2, &b0, &c1, &c2);
   stau_pencils::FactorSlot* fs = nullptr;
   {
-    int rc = factors_for(pen, a0, b0, st, &fs);
+    int rc = factors_for(pen, a0, b0, st, &fs, true);
     if (rc) return rc;
   }
   AdjRhsArgs r{};
@@ -749,7 +802,7 @@ int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, 
   r.hbar = (double2*)adj->hbar;
   r.Fbar = pen->Bev;
   // 1. transposed pencil solve + multistep history adjoints
-  HIP_TRY(launch_solveT(pen->pa, adj->Xbar, fs->Lf, fs->sl, fs->Uf, adj->Xbar, r, st));
+  HIP_TRY(launch_solveT(pen->paT, adj->Xbar, fs->Lf, fs->sl, fs->Uf, adj->Xbar, r, st));
   // 2. adjoint of the forward z transform: H_bar = W^T F_bar
   FieldList fe{};
   fe.nf = pen->pa.desc.ne;
