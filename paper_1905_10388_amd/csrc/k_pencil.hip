@@ -13,6 +13,8 @@
 //                 carries, 1 / U(j, j) on lane j mod BW, zero elsewhere.
 // The interchanges are LAPACK's (row j <-> pivot row, applied column by
 // column), so the forward sweep follows the same order as the factorisation.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -38,6 +40,30 @@ __device__ __forceinline__ float readlane_t(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 __device__ __forceinline__ double readlane_t(double v, int lane) { return readlane_d(v, lane); }
+
+// acc[lane L] = v (v uniform, L an immediate): the sweeps collect one result
+// per column in a register this way and store a whole chunk at once, so no
+// SGPR copy of the result stays live until an LDS store.
+template <int L>
+__device__ __forceinline__ void put_lane(float& acc, float v) {
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(acc) : "s"(__float_as_int(v)), "i"(L));
+}
+template <int L>
+__device__ __forceinline__ void put_lane(double& acc, double v) {
+  int lo = __double2loint(acc), hi = __double2hiint(acc);
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(lo) : "s"(__double2loint(v)), "i"(L));
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(hi) : "s"(__double2hiint(v)), "i"(L));
+  acc = __hiloint2double(hi, lo);
+}
+
+// compile-time loop helper: f(std::integral_constant<int, I>) for I < N
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
 
 __device__ __forceinline__ PencilCoef pencil_coef(const PencilArgs& a, int p, double a0, double b0) {
   PencilCoef pc;
@@ -242,29 +268,32 @@ __device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uin
 #pragma unroll
     for (int k = 0; k < G; ++k) pin(nv[0][k]);
     uint32_t word = 0;
-#pragma unroll
-    for (int g = 0; g < CH / G; ++g) {
+    T yacc = (T)0;  // lane t: y of column j0 + t
+    static_for<0, CH / G>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
       if (g + 1 < CH / G) {
 #pragma unroll
         for (int k = 0; k < G; ++k) nv[(g + 1) & 1][k] = yo[(g + 1) * G + k + FW];
       }
-#pragma unroll
-      for (int k = 0; k < G; ++k) {
-        const int t = g * G + k;
+      static_for<0, G>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int t = g * G + k;
         if ((t & 3) == 0) word = __builtin_amdgcn_readfirstlane(sring[(t >> 2) % (D / 4)]);
         const int s = (word >> (8 * (t & 3))) & 0xff;
         const T y = readlane_t(w, s);
-        yo[t] = y;  // every lane stores the same value
+        put_lane<t>(yacc, y);
         const T l = ring[t % D];
         ring[t % D] = Ln[t * FW];
         if ((t & 3) == 3) sring[(t >> 2) % (D / 4)] = Sn[t >> 2];
-        w = lane == s ? nv[g & 1][k] : fma(-l, y, w);
-      }
+        // lane s takes the next row; the lane mask is formed on the scalar unit
+        w = __builtin_amdgcn_inverse_ballot_w64(1ull << s) ? nv[g & 1][k] : fma(-l, y, w);
+      });
       if (g + 1 < CH / G) {
 #pragma unroll
         for (int k = 0; k < G; ++k) pin(nv[(g + 1) & 1][k]);
       }
-    }
+    });
+    yo[lane] = yacc;
   }
 
   // ---- backward sweep (columns descending)
@@ -284,27 +313,30 @@ __device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uin
     for (int k = 0; k < G; ++k) nv[(NG - 1) & 1][k] = xo[(NG - 1) * G + k - BW];
 #pragma unroll
     for (int k = 0; k < G; ++k) pin(nv[(NG - 1) & 1][k]);
-#pragma unroll
-    for (int g = NG - 1; g >= 0; --g) {
+    T xacc = (T)0;  // lane t: x of column j0 + t
+    static_for<0, NG>([&](auto gc) {
+      constexpr int g = NG - 1 - decltype(gc)::value;
       if (g > 0) {
 #pragma unroll
         for (int k = 0; k < G; ++k) nv[(g - 1) & 1][k] = xo[(g - 1) * G + k - BW];
       }
-#pragma unroll
-      for (int k = G - 1; k >= 0; --k) {
-        const int t = g * G + k;
-        const int sj = t % BW;
+      static_for<0, G>([&](auto kc) {
+        constexpr int k = G - 1 - decltype(kc)::value;
+        constexpr int t = g * G + k;
+        constexpr int sj = t % BW;
+        constexpr uint64_t msj = BW == 32 ? ((1ull << sj) | (1ull << (sj + 32))) : (1ull << sj);
         const T u = ring[t % D];
         ring[t % D] = Un[t * BW];
         const T x = readlane_t(w * u, sj);
-        xo[t] = x;  // every lane stores the same value
-        w = lb == sj ? nv[g & 1][k] : fma(-u, x, w);
-      }
+        put_lane<t>(xacc, x);
+        w = __builtin_amdgcn_inverse_ballot_w64(msj) ? nv[g & 1][k] : fma(-u, x, w);  // lanes l = sj mod BW
+      });
       if (g > 0) {
 #pragma unroll
         for (int k = 0; k < G; ++k) pin(nv[(g - 1) & 1][k]);
       }
-    }
+    });
+    xo[lane] = xacc;
   }
 }
 

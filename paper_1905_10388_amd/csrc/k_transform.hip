@@ -229,112 +229,6 @@ __global__ void __launch_bounds__(256) zf_kernel(XformArgs a,
 }
 
 // ---------------------------------------------------------------------------
-// Fused x pass for one dealiased z row (2-D): four complex-to-real transforms
-// of packed field pairs, the products
-//   N_b = -(u b_x + w b_z), N_u = -(u u_x + w u_z), N_w = -(u w_x + w w_z),
-// and two real-to-complex transforms, truncated to k < Nx/2 and scaled 1/L.
-// G field order: u, w, b_x, b_z, u_x, u_z, w_x, w_z.
-// ---------------------------------------------------------------------------
-template <int MAXBF, int PTS, int NT, typename T>
-__global__ void __launch_bounds__(NT) xpass_kernel(XformArgs a,
-                                                   const typename V2<T>::type* __restrict__ G,
-                                                   typename V2<T>::type* __restrict__ H) {
-  extern __shared__ double2 smem[];
-  using cT = cpx<T>;
-  using S2 = typename V2<T>::type;
-  cT* buf = (cT*)smem;
-  const int jz = blockIdx.x;
-  const int M = a.M, L = a.L, Pa = a.Pa, P = a.P;
-  const int tid = threadIdx.x;
-  constexpr int nt = NT;
-  const cT* tw = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
-
-  auto c2r_pair = [&](int fa, int fb, T* ra, T* rb) {
-    const S2* A = G + ((size_t)fa * M + jz) * P;
-    const S2* B = G + ((size_t)fb * M + jz) * P;
-    for (int k = tid; k < L; k += nt) {
-      cT z = mk<T>(0, 0);
-      if (k < Pa) {
-        cT Ak = ldv<T>(A + k), Bk = ldv<T>(B + k);
-        if (k == 0) {
-          Ak.y = 0;
-          Bk.y = 0;
-        }
-        z = mk<T>(Ak.x - Bk.y, Ak.y + Bk.x);
-      } else if (k > L - Pa) {
-        cT Ak = ldv<T>(A + (L - k)), Bk = ldv<T>(B + (L - k));
-        z = mk<T>(Ak.x + Bk.y, -Ak.y + Bk.x);
-      }
-      buf[k] = z;
-    }
-    __syncthreads();
-    fft_lds<+1, MAXBF>(buf, L, 1, tw, tid, nt);
-#pragma unroll
-    for (int q = 0; q < PTS; ++q) {
-      const int i = tid + q * nt;
-      if (i < L) {
-        ra[q] = buf[i].x;
-        rb[q] = buf[i].y;
-      }
-    }
-    __syncthreads();
-  };
-
-  T u[PTS], w[PTS], t1[PTS], t2[PTS], nb[PTS], nu[PTS], nw[PTS];
-  c2r_pair(0, 1, u, w);
-  c2r_pair(2, 3, t1, t2);
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) nb[q] = -(u[q] * t1[q] + w[q] * t2[q]);
-  c2r_pair(4, 5, t1, t2);
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) nu[q] = -(u[q] * t1[q] + w[q] * t2[q]);
-  c2r_pair(6, 7, t1, t2);
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) nw[q] = -(u[q] * t1[q] + w[q] * t2[q]);
-
-  const T invL = (T)1 / (T)L;
-  const T half = (T)0.5;
-  // N_b + i N_u
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) {
-    const int i = tid + q * nt;
-    if (i < L) buf[i] = mk<T>(nb[q], nu[q]);
-  }
-  __syncthreads();
-  fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, nt);
-  {
-    S2* Ha = H + ((size_t)0 * M + jz) * P;
-    S2* Hb = H + ((size_t)1 * M + jz) * P;
-    for (int k = tid; k < P; k += nt) {
-      cT A = mk<T>(0, 0), Bv = mk<T>(0, 0);
-      if (k < Pa) {
-        cT Zk = buf[k], Zm = buf[k == 0 ? 0 : L - k];
-        A = mk<T>(half * (Zk.x + Zm.x) * invL, half * (Zk.y - Zm.y) * invL);
-        Bv = mk<T>(half * (Zk.y + Zm.y) * invL, -half * (Zk.x - Zm.x) * invL);
-      }
-      stv<T>(Ha + k, A);
-      stv<T>(Hb + k, Bv);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) {
-    const int i = tid + q * nt;
-    if (i < L) buf[i] = mk<T>(nw[q], 0);
-  }
-  __syncthreads();
-  fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, nt);
-  {
-    S2* Hc = H + ((size_t)2 * M + jz) * P;
-    for (int k = tid; k < P; k += nt) {
-      cT A = k < Pa ? scale(buf[k], invL) : mk<T>(0, 0);
-      stv<T>(Hc + k, A);
-    }
-  }
-}
-
-
-// ---------------------------------------------------------------------------
 // y pass (3-D): complex transforms along y of TK consecutive kx columns per
 // block, one (field, z level) per (blockIdx.z, blockIdx.y).  Stored y slots
 // iy hold the signed wavenumbers 0..Ny/2-1, [Nyquist, held zero],
@@ -405,113 +299,148 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
 }
 
 // ---------------------------------------------------------------------------
-// Fused x pass for one dealiased (z, y) row (3-D): eight complex-to-real
-// transforms of packed field pairs, the products
-//   N_q = -(u q_x + v q_y + w q_z),  q = b, u, v, w,
-// and two real-to-complex transforms of packed output pairs, truncated to
-// k < Nx/2 and scaled 1/L.  Rows r = jz * Ngy + l of Px slots; field f at
-// G2 + (f * R + r) * Px with R = M * Ngy.
-// G2 field order: u, v, w, b_x, b_y, b_z, u_x, u_y, u_z, v_x, v_y, v_z, w_x, w_y, w_z.
+// Fused x pass for one dealiased row r (a z level; in 3-D a (z, y) level):
+// packed complex-to-real transforms of field pairs, the grid products
+//   N_q = -(u q_x [+ v q_y] + w q_z),
+// and packed real-to-complex transforms truncated to k < Nx/2 and scaled 1/L.
+// Field f of row r sits at G + (f R + r) Px with R = M Ngy (Ngy = 1 in 2-D).
+//   2-D fields: u, w, b_x, b_z, u_x, u_z, w_x, w_z           -> N_b, N_u, N_w
+//   3-D fields: u, v, w, b_x, b_y, b_z, u_x, u_y, u_z, v_x, v_y, v_z, w_x,
+//               w_y, w_z                                     -> N_b, N_u, N_v, N_w
+// Each pair's half spectrum is loaded into registers one pair ahead of its
+// transform; with TWL the twiddle table is staged in LDS once per block.
+// Thread t owns grid points t + q NT, q < PTS.
 // ---------------------------------------------------------------------------
-template <int MAXBF, int PTS, int NT, typename T>
-__global__ void __launch_bounds__(NT) xpass3_kernel(XformArgs a,
-                                                    const typename V2<T>::type* __restrict__ G,
-                                                    typename V2<T>::type* __restrict__ H) {
+template <int DIM, int NT, int PTS, int MAXBF, bool TWL, typename T>
+__global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
+                                                  const typename V2<T>::type* __restrict__ G,
+                                                  typename V2<T>::type* __restrict__ H) {
   extern __shared__ double2 smem[];
   using cT = cpx<T>;
   using S2 = typename V2<T>::type;
+  constexpr int KPT = (PTS + 2) / 3;  // half-spectrum entries per thread (Pa = L / 3)
+  constexpr int NP = DIM == 2 ? 4 : 8;
   cT* buf = (cT*)smem;
   const int r = blockIdx.x;
   const int L = a.L, Pa = a.Pa, Px = a.Px;
   const size_t R = (size_t)a.M * a.Ngy;
   const int tid = threadIdx.x;
-  constexpr int nt = NT;
-  const cT* tw = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
+  const cT* twg = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
+  cT* twl = buf + L;
+  if constexpr (TWL) {
+    for (int i = tid; i < L; i += NT) twl[i] = twg[i];
+  }
+  const cT* tw = TWL ? (const cT*)twl : twg;
 
-  // fb < 0: the second field of the pair is zero
-  auto c2r_pair = [&](int fa, int fb, T* ra, T* rb) {
+  // pair k: fields (fa, fb); fb < 0 means zero
+  auto pair_fields = [](int k, int& fa, int& fb) {
+    fa = 2 * k;
+    fb = 2 * k + 1;
+    if (DIM == 3 && k == 7) fb = -1;
+  };
+  cT sa[KPT], sb[KPT];
+  auto fetch = [&](int k) {
+    int fa, fb;
+    pair_fields(k, fa, fb);
     const S2* A = G + ((size_t)fa * R + r) * Px;
-    const S2* B = fb >= 0 ? G + ((size_t)fb * R + r) * Px : nullptr;
-    for (int k = tid; k < L; k += nt) {
-      cT z = mk<T>(0, 0);
-      const int kk = k < Pa ? k : (k > L - Pa ? L - k : -1);
-      if (kk >= 0) {
-        cT Ak = ldv<T>(A + kk);
-        cT Bk = B ? ldv<T>(B + kk) : mk<T>(0, 0);
+    const S2* B = G + ((size_t)(fb < 0 ? fa : fb) * R + r) * Px;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int kk = tid + q * NT;
+      sa[q] = mk<T>(0, 0);
+      sb[q] = mk<T>(0, 0);
+      if (kk < Pa) {
+        sa[q] = ldv<T>(A + kk);
+        if (fb >= 0) sb[q] = ldv<T>(B + kk);
+      }
+    }
+  };
+  // Hermitian extension of the packed pair A + i B onto the L-point grid
+  auto scatter = [&]() {
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int kk = tid + q * NT;
+      if (kk < Pa) {
+        cT Ak = sa[q], Bk = sb[q];
         if (kk == 0) {
           Ak.y = 0;
           Bk.y = 0;
         }
-        z = k < Pa ? mk<T>(Ak.x - Bk.y, Ak.y + Bk.x) : mk<T>(Ak.x + Bk.y, -Ak.y + Bk.x);
-      }
-      buf[k] = z;
-    }
-    __syncthreads();
-    fft_lds<+1, MAXBF>(buf, L, 1, tw, tid, nt);
-#pragma unroll
-    for (int q = 0; q < PTS; ++q) {
-      const int i = tid + q * nt;
-      if (i < L) {
-        ra[q] = buf[i].x;
-        rb[q] = buf[i].y;
+        buf[kk] = mk<T>(Ak.x - Bk.y, Ak.y + Bk.x);
+        if (kk > 0) buf[L - kk] = mk<T>(Ak.x + Bk.y, -Ak.y + Bk.x);
       }
     }
-    __syncthreads();
+    for (int k = Pa + tid; k <= L - Pa; k += NT) buf[k] = mk<T>(0, 0);
   };
 
-  T u[PTS], v[PTS], w[PTS], t1[PTS], t2[PTS], nb[PTS], nu[PTS], nv[PTS], nw[PTS];
-  c2r_pair(0, 1, u, v);
-  c2r_pair(2, 3, w, t1);  // w, b_x
+  T u[PTS], v[PTS], w[PTS], nb[PTS], nu[PTS], nv[PTS], nw[PTS];
+  fetch(0);
 #pragma unroll
-  for (int q = 0; q < PTS; ++q) nb[q] = -(u[q] * t1[q]);
-  c2r_pair(4, 5, t1, t2);  // b_y, b_z
+  for (int k = 0; k < NP; ++k) {
+    scatter();
+    if (k + 1 < NP) fetch(k + 1);
+    __syncthreads();
+    fft_lds<+1, MAXBF>(buf, L, 1, tw, tid, NT);
 #pragma unroll
-  for (int q = 0; q < PTS; ++q) nb[q] -= v[q] * t1[q] + w[q] * t2[q];
-  c2r_pair(6, 7, t1, t2);  // u_x, u_y
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) nu[q] = -(u[q] * t1[q] + v[q] * t2[q]);
-  c2r_pair(8, 9, t1, t2);  // u_z, v_x
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) {
-    nu[q] -= w[q] * t1[q];
-    nv[q] = -(u[q] * t2[q]);
+    for (int q = 0; q < PTS; ++q) {
+      const int i = tid + q * NT;
+      if (i < L) {
+        const T x = buf[i].x, y = buf[i].y;  // the pair's two real fields at point i
+        if constexpr (DIM == 2) {
+          if (k == 0) { u[q] = x; w[q] = y; }
+          if (k == 1) nb[q] = -(u[q] * x + w[q] * y);
+          if (k == 2) nu[q] = -(u[q] * x + w[q] * y);
+          if (k == 3) nw[q] = -(u[q] * x + w[q] * y);
+        } else {
+          if (k == 0) { u[q] = x; v[q] = y; }
+          if (k == 1) { w[q] = x; nb[q] = -(u[q] * y); }
+          if (k == 2) nb[q] -= v[q] * x + w[q] * y;
+          if (k == 3) nu[q] = -(u[q] * x + v[q] * y);
+          if (k == 4) { nu[q] -= w[q] * x; nv[q] = -(u[q] * y); }
+          if (k == 5) nv[q] -= v[q] * x + w[q] * y;
+          if (k == 6) nw[q] = -(u[q] * x + v[q] * y);
+          if (k == 7) nw[q] -= w[q] * x;
+        }
+      }
+    }
+    __syncthreads();
   }
-  c2r_pair(10, 11, t1, t2);  // v_y, v_z
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) nv[q] -= v[q] * t1[q] + w[q] * t2[q];
-  c2r_pair(12, 13, t1, t2);  // w_x, w_y
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) nw[q] = -(u[q] * t1[q] + v[q] * t2[q]);
-  c2r_pair(14, -1, t1, t2);  // w_z
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) nw[q] -= w[q] * t1[q];
 
   const T invL = (T)1 / (T)L;
   const T hf = (T)0.5;
-  auto r2c_pair = [&](const T* ra, const T* rb, int ea, int eb) {
+  // packed real-to-complex: ra + i rb (rb null: a single real field)
+  auto r2c = [&](const T* ra, const T* rb, int ea, int eb) {
 #pragma unroll
     for (int q = 0; q < PTS; ++q) {
-      const int i = tid + q * nt;
-      if (i < L) buf[i] = mk<T>(ra[q], rb[q]);
+      const int i = tid + q * NT;
+      if (i < L) buf[i] = mk<T>(ra[q], rb ? rb[q] : (T)0);
     }
     __syncthreads();
-    fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, nt);
+    fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, NT);
     S2* Ha = H + ((size_t)ea * R + r) * Px;
-    S2* Hb = H + ((size_t)eb * R + r) * Px;
-    for (int k = tid; k < Px; k += nt) {
+    S2* Hb = H + ((size_t)(eb < 0 ? ea : eb) * R + r) * Px;
+    for (int k = tid; k < Px; k += NT) {
       cT A = mk<T>(0, 0), Bv = mk<T>(0, 0);
       if (k < Pa) {
-        cT Zk = buf[k], Zm = buf[k == 0 ? 0 : L - k];
-        A = mk<T>(hf * (Zk.x + Zm.x) * invL, hf * (Zk.y - Zm.y) * invL);
-        Bv = mk<T>(hf * (Zk.y + Zm.y) * invL, -hf * (Zk.x - Zm.x) * invL);
+        const cT Zk = buf[k];
+        if (eb < 0) {
+          A = scale(Zk, invL);
+        } else {
+          const cT Zm = buf[k == 0 ? 0 : L - k];
+          A = mk<T>(hf * (Zk.x + Zm.x) * invL, hf * (Zk.y - Zm.y) * invL);
+          Bv = mk<T>(hf * (Zk.y + Zm.y) * invL, -hf * (Zk.x - Zm.x) * invL);
+        }
       }
       stv<T>(Ha + k, A);
-      stv<T>(Hb + k, Bv);
+      if (eb >= 0) stv<T>(Hb + k, Bv);
     }
     __syncthreads();
   };
-  r2c_pair(nb, nu, 0, 1);
-  r2c_pair(nv, nw, 2, 3);
+  r2c(nb, nu, 0, 1);
+  if constexpr (DIM == 2)
+    r2c(nw, nullptr, 2, -1);
+  else
+    r2c(nv, nw, 2, 3);
 }
 
 // ---------------------------------------------------------------------------
@@ -1006,32 +935,6 @@ static void allow_lds(const void* fn, size_t bytes) {
   if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int NT, typename T>
-static hipError_t launch_xpass_t(const XformArgs& a, const void* G, void* H, hipStream_t st) {
-  using S2 = typename V2<T>::type;
-  size_t lds = (size_t)a.L * sizeof(S2);
-  allow_lds((const void*)xpass_kernel<2, 6, NT, T>, lds);
-  hipLaunchKernelGGL((xpass_kernel<2, 6, NT, T>), dim3(a.M), dim3(NT), lds, st, a, (const S2*)G,
-                     (S2*)H);
-  return hipGetLastError();
-}
-
-template <typename T>
-static hipError_t launch_xpass_T(const XformArgs& a, const void* G, void* H, hipStream_t st) {
-  switch (x_threads(a.L)) {
-    case 64: return launch_xpass_t<64, T>(a, G, H, st);
-    case 128: return launch_xpass_t<128, T>(a, G, H, st);
-    case 256: return launch_xpass_t<256, T>(a, G, H, st);
-    case 512: return launch_xpass_t<512, T>(a, G, H, st);
-    case 1024: return launch_xpass_t<1024, T>(a, G, H, st);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st, bool fp32) {
-  return fp32 ? launch_xpass_T<float>(a, G, H, st) : launch_xpass_T<double>(a, G, H, st);
-}
-
 hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, void* Out,
                         hipStream_t st, bool fp32) {
   const int TK = a.Ngy >= 3072 ? 1 : 3072 / a.Ngy;
@@ -1055,30 +958,48 @@ hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, voi
   return hipGetLastError();
 }
 
-template <int NT, typename T>
-static hipError_t launch_xpass3_t(const XformArgs& a, const void* G, void* H, hipStream_t st) {
+// x-pass launch shape for an L-point row: NT ~ L/3 threads (one radix-4
+// butterfly per thread per pass, MAXBF = 1), PTS = ceil(L / NT) points each;
+// L = 6144 uses 1024 threads, 6 points, MAXBF = 2.  The twiddle table goes
+// to LDS when it fits in 32 KB.
+template <int DIM, int NT, int PTS, int MAXBF, typename T>
+static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipStream_t st) {
   using S2 = typename V2<T>::type;
-  size_t lds = (size_t)a.L * sizeof(S2);
-  allow_lds((const void*)xpass3_kernel<2, 6, NT, T>, lds);
-  hipLaunchKernelGGL((xpass3_kernel<2, 6, NT, T>), dim3(a.M * a.Ngy), dim3(NT), lds, st, a,
-                     (const S2*)G, (S2*)H);
+  const int rows = a.M * (DIM == 2 ? 1 : a.Ngy);
+  const bool twl = (size_t)a.L * sizeof(S2) <= 32768;
+  const size_t lds = (size_t)a.L * sizeof(S2) * (twl ? 2 : 1);
+  if (twl) {
+    auto fn = xrow_kernel<DIM, NT, PTS, MAXBF, true, T>;
+    allow_lds((const void*)fn, lds);
+    hipLaunchKernelGGL(fn, dim3(rows), dim3(NT), lds, st, a, (const S2*)G, (S2*)H);
+  } else {
+    auto fn = xrow_kernel<DIM, NT, PTS, MAXBF, false, T>;
+    allow_lds((const void*)fn, lds);
+    hipLaunchKernelGGL(fn, dim3(rows), dim3(NT), lds, st, a, (const S2*)G, (S2*)H);
+  }
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_xpass3_T(const XformArgs& a, const void* G, void* H, hipStream_t st) {
-  switch (x_threads(a.L)) {
-    case 64: return launch_xpass3_t<64, T>(a, G, H, st);
-    case 128: return launch_xpass3_t<128, T>(a, G, H, st);
-    case 256: return launch_xpass3_t<256, T>(a, G, H, st);
-    case 512: return launch_xpass3_t<512, T>(a, G, H, st);
-    case 1024: return launch_xpass3_t<1024, T>(a, G, H, st);
-  }
+template <int DIM, typename T>
+static hipError_t launch_xrow_T(const XformArgs& a, const void* G, void* H, hipStream_t st) {
+  const int L = a.L;
+  if (L <= 64) return launch_xrow_t<DIM, 64, 1, 1, T>(a, G, H, st);
+  if (L <= 128) return launch_xrow_t<DIM, 64, 2, 1, T>(a, G, H, st);
+  if (L <= 192) return launch_xrow_t<DIM, 64, 3, 1, T>(a, G, H, st);
+  if (L <= 384) return launch_xrow_t<DIM, 128, 3, 1, T>(a, G, H, st);
+  if (L <= 768) return launch_xrow_t<DIM, 256, 3, 1, T>(a, G, H, st);
+  if (L <= 1536) return launch_xrow_t<DIM, 512, 3, 1, T>(a, G, H, st);
+  if (L <= 3072) return launch_xrow_t<DIM, 1024, 3, 1, T>(a, G, H, st);
+  if (L <= 6144) return launch_xrow_t<DIM, 1024, 6, 2, T>(a, G, H, st);
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st, bool fp32) {
+  return fp32 ? launch_xrow_T<2, float>(a, G, H, st) : launch_xrow_T<2, double>(a, G, H, st);
+}
+
 hipError_t launch_xpass3(const XformArgs& a, const void* G2, void* H2, hipStream_t st, bool fp32) {
-  return fp32 ? launch_xpass3_T<float>(a, G2, H2, st) : launch_xpass3_T<double>(a, G2, H2, st);
+  return fp32 ? launch_xrow_T<3, float>(a, G2, H2, st) : launch_xrow_T<3, double>(a, G2, H2, st);
 }
 
 hipError_t launch_zadj(const XformArgs& a, const AccList& al, const void* Gbar, void* Xbar,
