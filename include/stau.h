@@ -57,6 +57,10 @@ extern "C" {
 #define STAU_FP64 0
 #define STAU_MIXED 1
 
+#define STAU_DCT_AUTO 0
+#define STAU_DCT_FFT 1
+#define STAU_DCT_MATMUL 2
+
 typedef struct stau_domain stau_domain;
 typedef struct stau_pencils stau_pencils;
 
@@ -74,7 +78,12 @@ typedef struct stau_pencils stau_pencils;
  *          FP64 accumulation; state, history and right-hand side FP64).  The
  *          component calls (stau_nonlinear, stau_solve) and the adjoint run in
  *          FP64 in either mode.
- * device   HIP device ordinal. */
+ * device   HIP device ordinal.
+ * dct_method  Chebyshev z transforms of the step: STAU_DCT_AUTO (matrix
+ *          products for Nz <= 64, FFT otherwise), STAU_DCT_FFT (DCT through
+ *          one complex FFT per column), STAU_DCT_MATMUL (dense products on the
+ *          FP64 matrix cores; Nz a multiple of 32 in [32, 256], else
+ *          STAU_EUNSUPPORTED).  The mixed-precision step uses the FP32 FFT. */
 typedef struct stau_domain_desc {
   int32_t dim;
   int32_t precision;
@@ -82,7 +91,7 @@ typedef struct stau_domain_desc {
   double Lx, Ly;
   double dealias;
   int32_t device;
-  int32_t reserved;
+  int32_t dct_method;
 } stau_domain_desc;
 
 /* Rayleigh-Benard parameters in free-fall units: kappa = (Ra Pr)^(-1/2),

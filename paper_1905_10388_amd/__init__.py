@@ -37,14 +37,16 @@ class RBSolver:
 
     def __init__(self, Nx: int, Nz: int, Lx: float, Ra: float, Pr: float, *, dim: int = 2,
                  Ny: int = 1, Ly: float = 1.0, precision: str = "fp64", buoyancy: float = 1.0,
-                 b_bottom: float = 1.0, b_top: float = 0.0, device: int = 0):
+                 b_bottom: float = 1.0, b_top: float = 0.0, device: int = 0, dct: str = "auto"):
         import torch
 
         self._torch = torch
         lib = _lib.load()
         self.lib = lib
         desc = _lib.DomainDesc(dim=dim, precision={"fp64": _lib.STAU_FP64, "mixed": _lib.STAU_MIXED}[precision],
-                               Nx=Nx, Ny=Ny, Nz=Nz, Lx=Lx, Ly=Ly, dealias=1.5, device=device)
+                               Nx=Nx, Ny=Ny, Nz=Nz, Lx=Lx, Ly=Ly, dealias=1.5, device=device,
+                               dct_method={"auto": _lib.STAU_DCT_AUTO, "fft": _lib.STAU_DCT_FFT,
+                                           "matmul": _lib.STAU_DCT_MATMUL}[dct])
         self._dom = C.c_void_p()
         _lib.check(lib.stau_create_domain(C.byref(desc), C.byref(self._dom)))
         par = _lib.RBParamsC(Ra=Ra, Pr=Pr, buoyancy=buoyancy, b_bottom=b_bottom, b_top=b_top)

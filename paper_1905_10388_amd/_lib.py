@@ -17,6 +17,9 @@ STAU_EUNSUPPORTED = 6
 STAU_ENONFINITE = 7
 STAU_FP64 = 0
 STAU_MIXED = 1
+STAU_DCT_AUTO = 0
+STAU_DCT_FFT = 1
+STAU_DCT_MATMUL = 2
 
 ERRNAMES = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ESINGULAR", 5: "ESTATE",
             6: "EUNSUPPORTED", 7: "ENONFINITE"}
@@ -35,7 +38,7 @@ KERNEL_KINDS = ("z_backward", "x_pass", "z_forward_rhs", "pencil_solve", "pencil
 class DomainDesc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("Nx", C.c_int64),
                 ("Ny", C.c_int64), ("Nz", C.c_int64), ("Lx", C.c_double), ("Ly", C.c_double),
-                ("dealias", C.c_double), ("device", C.c_int32), ("reserved", C.c_int32)]
+                ("dealias", C.c_double), ("device", C.c_int32), ("dct_method", C.c_int32)]
 
 
 class RBParamsC(C.Structure):

@@ -104,6 +104,14 @@ struct RhsArgs {
 hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
                      hipStream_t st, bool fp32 = false);
 
+// z transforms as FP64 matrix-core products (k_dctmm.hip)
+bool mm_supported(int N);
+hipError_t launch_zb_mm(const XformArgs& a, const FieldList& fl, const void* X, void* G,
+                        const double* Bfrag, hipStream_t st);
+hipError_t launch_zf_mm(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
+                        const double* Ffrag, hipStream_t st);
+
+
 // adjoint path
 hipError_t launch_zadj(const XformArgs& a, const AccList& al, const void* Gbar, void* Xbar,
                        hipStream_t st);

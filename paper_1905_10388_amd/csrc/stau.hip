@@ -58,6 +58,25 @@ void dct_table(int64_t m, std::vector<double2>& out) {
   }
 }
 
+// T_n(z_j) on the ascending Gauss grid of m points: z_j = -cos(pi (j + 1/2) / m)
+// = cos(pi (2m - 2j - 1) / (2m)), so T_n(z_j) = cos(pi n (2m - 2j - 1) / (2m))
+// with the integer argument reduced modulo 4m.
+double cheb_T(int64_t n, int64_t j, int64_t m) {
+  const int64_t q = (n * (2 * m - 2 * j - 1)) % (4 * m);
+  return (double)cosl(3.14159265358979323846264338327950288L * (long double)q / (2.0L * (long double)m));
+}
+
+// rows x cols matrix A(i, k) into the 16x16x4 FP64 fragment order
+std::vector<double> to_frag(int rows, int cols, const std::vector<double>& A) {
+  const int KS = cols / 4;
+  std::vector<double> f((size_t)rows * cols);
+  for (int rb = 0; rb < rows / 16; ++rb)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int l = 0; l < 64; ++l)
+        f[((size_t)rb * KS + ks) * 64 + l] = A[(size_t)(rb * 16 + l % 16) * cols + ks * 4 + l / 16];
+  return f;
+}
+
 int upload32(const std::vector<double2>& h, float2** d) {
   std::vector<float2> f(h.size());
   for (size_t i = 0; i < h.size(); ++i) f[i] = make_float2((float)h[i].x, (float)h[i].y);
@@ -81,6 +100,9 @@ struct stau_domain {
   double2 *twz = nullptr, *dctz = nullptr, *twx = nullptr, *twy = nullptr;
   double2 *twz1 = nullptr, *dctz1 = nullptr, *twx1 = nullptr, *twy1 = nullptr;
   float2 *twz32 = nullptr, *dctz32 = nullptr, *twx32 = nullptr, *twy32 = nullptr;
+  // z transforms as matrix products (fragment order of the FP64 matrix cores)
+  bool mm = false;
+  double *Bzfrag = nullptr, *Fzfrag = nullptr, *PLFzfrag = nullptr;
 };
 
 struct stau_pencils {
@@ -280,6 +302,10 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
   if (d.dim != 2 && d.dim != 3) return fail(STAU_EINVAL, "dim=%d must be 2 or 3", d.dim);
   if (d.precision != STAU_FP64 && d.precision != STAU_MIXED)
     return fail(STAU_EINVAL, "precision %d unknown", d.precision);
+  if (d.dct_method < STAU_DCT_AUTO || d.dct_method > STAU_DCT_MATMUL)
+    return fail(STAU_EINVAL, "dct_method %d unknown", d.dct_method);
+  if (d.dct_method == STAU_DCT_MATMUL && !mm_supported((int)d.Nz))
+    return fail(STAU_EUNSUPPORTED, "matrix-product z transforms need Nz a multiple of 32 in [32, 256]");
   if (std::fabs(d.dealias - 1.5) > 1e-15) return fail(STAU_EUNSUPPORTED, "dealias must be 1.5");
   if (!is_pow2(d.Nx) || d.Nx < 4 || d.Nx > 4096)
     return fail(STAU_EUNSUPPORTED, "Nx=%lld must be a power of two in [4, 4096]", (long long)d.Nx);
@@ -318,6 +344,25 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
   if ((rc = upload(t, &dom->dctz1))) goto bad;
   fft_table(d.Nx, t);
   if ((rc = upload(t, &dom->twx1))) goto bad;
+  dom->mm = mm_supported((int)d.Nz) &&
+            (d.dct_method == STAU_DCT_MATMUL || (d.dct_method == STAU_DCT_AUTO && d.Nz <= 64));
+  if (dom->mm) {
+    const int N = (int)d.Nz, M = (int)dom->Ngz;
+    std::vector<double> Bz((size_t)M * N), Fz((size_t)N * M), PLFz((size_t)N * M);
+    for (int j = 0; j < M; ++j)
+      for (int n = 0; n < N; ++n) {
+        const double T = cheb_T(n, j, M);
+        Bz[(size_t)j * N + n] = T;
+        Fz[(size_t)n * M + j] = (n == 0 ? 1.0 : 2.0) / (double)M * T;
+      }
+    for (int n = 0; n < N; ++n)
+      for (int j = 0; j < M; ++j)
+        PLFz[(size_t)n * M + j] = (n == 0 ? 1.0 : 0.5) * Fz[(size_t)n * M + j] -
+                                  (n + 2 < N ? 0.5 * Fz[(size_t)(n + 2) * M + j] : 0.0);
+    if ((rc = upload(to_frag(M, N, Bz), &dom->Bzfrag))) goto bad;
+    if ((rc = upload(to_frag(N, M, Fz), &dom->Fzfrag))) goto bad;
+    if ((rc = upload(to_frag(N, M, PLFz), &dom->PLFzfrag))) goto bad;
+  }
   if (d.dim == 3) {
     fft_table(dom->Ngy, t);
     if ((rc = upload(t, &dom->twy))) goto bad;
@@ -347,6 +392,9 @@ int stau_destroy_domain(stau_domain* dom) {
   hipFree(dom->twx32);
   hipFree(dom->twy1);
   hipFree(dom->twy32);
+  hipFree(dom->Bzfrag);
+  hipFree(dom->Fzfrag);
+  hipFree(dom->PLFzfrag);
   delete dom;
   return STAU_OK;
 }
@@ -698,7 +746,11 @@ static void sbdf(int64_t it, double dt, double dtp, double* a0, double* a1, doub
 // 2-D: z backward, fused x pass.  3-D: z backward, y backward, fused x pass,
 // y forward (the x-pass output H2 reuses G, the y-forward output goes to H).
 static hipError_t explicit_term(stau_pencils* pen, const void* X, hipStream_t st, bool mixed) {
-  hipError_t e = timed(pen, K_ZB, st, [&] { return launch_zb(pen->xa, pen->fl, X, pen->G, st, mixed); });
+  const bool mm = pen->dom->mm && !mixed;
+  hipError_t e = timed(pen, K_ZB, st, [&] {
+    if (mm) return launch_zb_mm(pen->xa, pen->fl, X, pen->G, pen->dom->Bzfrag, st);
+    return launch_zb(pen->xa, pen->fl, X, pen->G, st, mixed);
+  });
   if (e != hipSuccess) return e;
   if (pen->dom->d.dim == 2)
     return timed(pen, K_XPASS, st, [&] { return launch_xpass(pen->xa, pen->G, pen->H, st, mixed); });
@@ -740,7 +792,10 @@ int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
   r.hist_old = hist + (cur ^ 1) * hslot;
   const bool mixed = pen->dom->d.precision == STAU_MIXED;
   HIP_TRY(explicit_term(pen, s->X, st, mixed));
-  HIP_TRY(timed(pen, K_ZF, st, [&] { return launch_zf(pen->xa, pen->H, pen->Bev, r, st, mixed); }));
+  HIP_TRY(timed(pen, K_ZF, st, [&] {
+    if (pen->dom->mm && !mixed) return launch_zf_mm(pen->xa, pen->H, pen->Bev, r, pen->dom->PLFzfrag, st);
+    return launch_zf(pen->xa, pen->H, pen->Bev, r, st, mixed);
+  }));
   HIP_TRY(timed(pen, K_SOLVE, st, [&] {
     if (mixed)
       return launch_solve_mixed(pen->pa, a0, b0, pen->Bev, fs->Lf32, fs->sl, fs->Uf32, s->X, st);
@@ -766,7 +821,10 @@ int stau_nonlinear(stau_pencils* pen, const void* X, void* F, void* stream) {
   RhsArgs r{};
   r.mode = 0;
   HIP_TRY(explicit_term(pen, X, st, false));
-  HIP_TRY(launch_zf(pen->xa, pen->H, F, r, st));
+  if (pen->dom->mm)
+    HIP_TRY(launch_zf_mm(pen->xa, pen->H, F, r, pen->dom->Fzfrag, st));
+  else
+    HIP_TRY(launch_zf(pen->xa, pen->H, F, r, st));
   return STAU_OK;
 }
 

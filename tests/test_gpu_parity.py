@@ -193,3 +193,62 @@ def test_full_size_one_step_sampled_pencils():
     for key in sample:
         assert rel_err(Xg[key], Xo[key]) < 1e-10, key
     assert np.all(Xg[o.Px - 1] == 0)
+
+
+# --------------------------------------------------------- z-transform methods
+@pytest.mark.parametrize("cfg", [(128, 64, 4.0, 1e6, 1.0, 1e-4), (32, 128, 2.0, 1e7, 7.0, 2e-5),
+                                 (16, 256, 4.0, 1e8, 1.0, 1e-5)], ids=lambda c: f"{c[0]}x{c[1]}")
+@pytest.mark.parametrize("dct", ["fft", "matmul"])
+def test_nonlinear_term_both_z_transforms(cfg, dct):
+    g, o = _pair(cfg, dct=dct)
+    X = _random_state(o, 13)
+    Fg = _to_np(g.nonlinear(_to_dev(X)))
+    assert rel_err(Fg, o.nonlinear(X)) < 1e-13
+
+
+@pytest.mark.parametrize("dct", ["fft", "matmul"])
+def test_trajectory_both_z_transforms(dct):
+    cfg = (64, 64, 4.0, 1e5, 1.0, 5e-4)
+    Nx, Nz, Lx, Ra, Pr, dt = cfg
+    g, o = _pair(cfg, dct=dct)
+    xi = si.workload_noise((Nx, Nz), 5)
+    Xo = o.initial_state(xi, amp=1e-2)
+    g.initial_state(torch.from_numpy(o.initial_b_grid(xi, amp=1e-2)))
+    for _ in range(30):
+        Xo = o.step(Xo, dt)
+        g.step(dt)
+    errs = field_errors(o, _to_np(g.X), Xo)
+    assert max(errs.values()) < 1e-10, errs
+
+
+def test_matmul_z_transform_rejects_unsupported_nz():
+    with pytest.raises(StauError):
+        RBSolver(64, 48, 4.0, 1e4, 1.0, dct="matmul")   # Nz not a multiple of 32
+
+
+def test_small_nz_full_size_one_step_sampled_pencils():
+    """Nx=4096 (Lx=16), Nz=64, Ra=1e7, Pr=7, dt=2e-5 (2048 pencils, matrix-core
+    z transforms): one SBDF1 step from the seeded state on sampled pencils."""
+    Nx, Nz, Lx, Ra, Pr, dt = 4096, 64, 16.0, 1e7, 7.0, 2e-5
+    g, o = _pair((Nx, Nz, Lx, Ra, Pr, dt))
+    xi = si.workload_noise((Nx, Nz), 4)
+    X0 = o.initial_state(xi, amp=1e-1)
+    X0[:, o.vi["u"], : Nz // 2] += 1e-2 * si.complex_noise((o.Px, Nz // 2), 41)
+    X0[0] = X0[0].real
+    X0[o.Px - 1] = 0
+    g.set_state(_to_dev(X0))
+    g.step(dt)
+    Xg = _to_np(g.X)
+    F = o.nonlinear(X0)
+    a0, a1 = 1.0 / dt, -1.0 / dt
+    sample = [(0,), (1,), (333,), (2047,)]
+    Bev = np.zeros((o.Px, o.ne, Nz), complex)
+    for key in sample:
+        M, L = o.pencil_matrices(2 * np.pi * key[0] / Lx, 0.0, key[0] == 0)
+        Ft = o.precondition_rhs(F[key], key[0] == 0)
+        B = Ft - a1 * (M @ X0[key].reshape(-1))
+        for e in range(o.ne):
+            Bev[key][e, : Nz - 1] = B[e * Nz: e * Nz + Nz - 1]
+    Xo = oracle_solve_from_ev(o, Bev, a0, 1.0, pencils=set(sample))
+    for key in sample:
+        assert rel_err(Xg[key], Xo[key]) < 1e-10, key
