@@ -106,9 +106,11 @@ __device__ __forceinline__ void dftR(cpx<T>* v) {
 
 // ---------------------------------------------------------------------------
 // In-place Stockham autosort FFT of `batch` contiguous sequences of length M
-// held in LDS.  Radix plan: one radix-3 pass if 3 | M, one radix-8 pass if the
-// power of two is odd, radix-4 passes otherwise (M = 2^a 3^b, b <= 1).
-// tw[t] = e^{-2 pi i t / M}, t < M (FP64 host table, global memory).
+// held in LDS.  Radix plan: one radix-3 pass if 3 | M, then over the power
+// of two either radix-8 passes and one radix-4 or radix-2 pass for what is
+// left (R8) or radix-4 passes with one radix-8 pass if the exponent is odd
+// (M = 2^a 3^b, b <= 1).  tw[t] = e^{-2 pi i t / M}, t < M; each butterfly
+// reads one entry and forms the other powers it needs by complex products.
 // Each pass stages its butterflies in registers between two barriers, so the
 // transform is in place.  MAXBF bounds the butterflies per thread per pass;
 // the caller guarantees batch*M/4 <= MAXBF*nthreads.
@@ -129,11 +131,19 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* buf, int M, int batch, int
       const int jm = j % Ns;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = src[r * MR];
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cpx<T> w = tw[jm * r * tstride];
-        v[b][r] = DIR < 0 ? cmul(v[b][r], w) : cmulc(v[b][r], w);
+      // twiddles w^r, r < R, from one table entry (at most three products deep)
+      cpx<T> w[R];
+      w[1] = tw[jm * tstride];
+      if constexpr (R >= 3) w[2] = cmul(w[1], w[1]);
+      if constexpr (R >= 4) w[3] = cmul(w[1], w[2]);
+      if constexpr (R == 8) {
+        w[4] = cmul(w[2], w[2]);
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
       }
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[b][r] = DIR < 0 ? cmul(v[b][r], w[r]) : cmulc(v[b][r], w[r]);
       dftR<R, DIR>(v[b]);
     }
   }
@@ -152,8 +162,8 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* buf, int M, int batch, int
   __syncthreads();
 }
 
-template <int DIR, int MAXBF, typename T>
-__device__ void fft_lds(cpx<T>* buf, int M, int batch, const cpx<T>* __restrict__ tw, int tid,
+template <int DIR, int MAXBF, typename T, bool R8 = true>
+__device__ __forceinline__ void fft_lds(cpx<T>* buf, int M, int batch, const cpx<T>* __restrict__ tw, int tid,
                         int nt) {
   int Ns = 1;
   int m2 = M;
@@ -163,20 +173,33 @@ __device__ void fft_lds(cpx<T>* buf, int M, int batch, const cpx<T>* __restrict_
     m2 /= 3;
   }
   int lg = 31 - __clz(m2);
-  if (lg & 1) {
-    if (lg >= 3) {
+  if constexpr (R8) {
+    // power of two: radix-8 passes, then one radix-4 or radix-2 pass for the
+    // rest (fewest passes; for latency-bound launches with few blocks)
+    for (; lg >= 3; lg -= 3) {
       stockham_pass<8, DIR, (MAXBF + 1) / 2>(buf, M, batch, Ns, tw, tid, nt);
       Ns *= 8;
-      lg -= 3;
-    } else {  // lg == 1
-      stockham_pass<2, DIR, MAXBF * 2>(buf, M, batch, Ns, tw, tid, nt);
-      Ns *= 2;
-      lg -= 1;
     }
-  }
-  for (; lg > 0; lg -= 2) {
-    stockham_pass<4, DIR, MAXBF>(buf, M, batch, Ns, tw, tid, nt);
-    Ns *= 4;
+    if (lg == 2) stockham_pass<4, DIR, MAXBF>(buf, M, batch, Ns, tw, tid, nt);
+    if (lg == 1) stockham_pass<2, DIR, MAXBF * 2>(buf, M, batch, Ns, tw, tid, nt);
+  } else {
+    // radix-4 passes (one radix-8 pass if the exponent is odd): more threads
+    // busy per pass, for launches with many blocks per CU
+    if (lg & 1) {
+      if (lg >= 3) {
+        stockham_pass<8, DIR, (MAXBF + 1) / 2>(buf, M, batch, Ns, tw, tid, nt);
+        Ns *= 8;
+        lg -= 3;
+      } else {
+        stockham_pass<2, DIR, MAXBF * 2>(buf, M, batch, Ns, tw, tid, nt);
+        Ns *= 2;
+        lg -= 1;
+      }
+    }
+    for (; lg > 0; lg -= 2) {
+      stockham_pass<4, DIR, MAXBF>(buf, M, batch, Ns, tw, tid, nt);
+      Ns *= 4;
+    }
   }
 }
 

@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
     scatter();
     if (k + 1 < NP) fetch(k + 1);
     __syncthreads();
-    fft_lds<+1, MAXBF>(buf, L, 1, tw, tid, NT);
+    fft_lds<+1, MAXBF, T, DIM == 2>(buf, L, 1, tw, tid, NT);
 #pragma unroll
     for (int q = 0; q < PTS; ++q) {
       const int i = tid + q * NT;
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
       if (i < L) buf[i] = mk<T>(ra[q], rb ? rb[q] : (T)0);
     }
     __syncthreads();
-    fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, NT);
+    fft_lds<-1, MAXBF, T, DIM == 2>(buf, L, 1, tw, tid, NT);
     S2* Ha = H + ((size_t)ea * R + r) * Px;
     S2* Hb = H + ((size_t)(eb < 0 ? ea : eb) * R + r) * Px;
     for (int k = tid; k < Px; k += NT) {
