@@ -83,7 +83,12 @@ typedef struct stau_pencils stau_pencils;
  *          products for Nz <= 64, FFT otherwise), STAU_DCT_FFT (DCT through
  *          one complex FFT per column), STAU_DCT_MATMUL (dense products on the
  *          FP64 matrix cores; Nz a multiple of 32 in [32, 256], else
- *          STAU_EUNSUPPORTED).  The mixed-precision step uses the FP32 FFT. */
+ *          STAU_EUNSUPPORTED).  In the mixed-precision step the products
+ *          run as split-BF16 matrix-core products with FP32 accumulation
+ *          (each operand split into three BF16 terms): STAU_DCT_MATMUL needs
+ *          Nz = 64, 128 or 256 there (else STAU_EUNSUPPORTED) and
+ *          STAU_DCT_AUTO takes them for those Nz; otherwise the mixed step
+ *          uses the FP32 FFT. */
 typedef struct stau_domain_desc {
   int32_t dim;
   int32_t precision;

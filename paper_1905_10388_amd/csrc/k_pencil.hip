@@ -15,6 +15,8 @@
 // column), so the forward sweep follows the same order as the factorisation.
 #include <type_traits>
 
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -340,43 +342,229 @@ __device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uin
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same two sweeps with the factor columns staged through LDS, for
+// launches of at most one block per compute unit (one sweeping wavefront per
+// SIMD).  There a global load per column and wavefront is what limits the
+// sweep: the load unit takes about 16 cycles for every 64-lane load of a
+// compute unit, and four wavefronts each need one per column.  Here the
+// factors move in units of kSU columns with 16-byte loads of 64 distinct
+// addresses (1 KB per instruction), two units ahead of their use, through two
+// LDS buffers per wavefront; each column is then one LDS read into a ring of
+// kSR registers.  At the start of processing unit v the data of unit v + 1 is
+// written to LDS buffer (v + 1) mod 2 and unit v + 3 is loaded into the freed
+// registers; reads of unit v + 1 begin kSR columns before it.
+// ---------------------------------------------------------------------------
+constexpr int kSU = 32;  // columns per staging unit
+constexpr int kSR = 8;   // LDS-read look-ahead (columns)
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte loads per lane that move one staging unit of W-wide columns
+template <typename T, int W>
+constexpr int stage_loads() {
+  return kSU * W * (int)sizeof(T) / 1024;
+}
+
+template <typename T, int W, int NL>
+__device__ __forceinline__ void stage_load(u32x4 (&r)[NL], const T* __restrict__ A, int unit,
+                                           int lane) {
+  const u32x4* src = (const u32x4*)(A + (size_t)unit * kSU * W);
+#pragma unroll
+  for (int i = 0; i < NL; ++i) r[i] = src[i * 64 + lane];
+}
+
+template <int NL, typename T>
+__device__ __forceinline__ void stage_store(const u32x4 (&r)[NL], T* dst, int lane) {
+#pragma unroll
+  for (int i = 0; i < NL; ++i) ((u32x4*)dst)[i * 64 + lane] = r[i];
+}
+
+// LDS bytes of the factor stage of one wavefront
+template <typename T, int FW, int BW>
+constexpr int stage_bytes() {
+  return 2 * kSU * (FW > BW ? FW : BW) * (int)sizeof(T);
+}
+
+template <typename T, int FW, int BW>
+__device__ __forceinline__ void sweeps_staged(T* b, const T* __restrict__ Lp,
+                                              const uint32_t* __restrict__ sw,
+                                              const T* __restrict__ Up, int nch, int lane, T* st) {
+  constexpr int CH = kCH, G = 16, R = kSR;
+  static_assert(CH == 2 * kSU && R <= kSU && CH % G == 0 && CH % BW == 0 &&
+                    FW <= 32 && BW <= 64,
+                "sweep geometry");
+  const int npad = nch * CH, nu = 2 * nch;
+
+  // ---- forward sweep
+  {
+    const int lf = lane & (FW - 1);
+    constexpr int NL = stage_loads<T, FW>();
+    static_assert(NL >= 1 && kSU * FW * (int)sizeof(T) % 1024 == 0, "staging unit geometry");
+    u32x4 r0[NL], r1[NL];  // units in flight (even / odd)
+    stage_load<T, FW>(r0, Lp, 0, lane);
+    stage_load<T, FW>(r1, Lp, 1, lane);
+    stage_store(r0, st, lane);
+    if (nu > 2) stage_load<T, FW>(r0, Lp, 2, lane);
+    T ring[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) ring[k] = st[k * FW + lf];
+    // slot bytes of a chunk: lane i holds word i mod 16 (columns 4i .. 4i + 3);
+    // vector loads, one chunk ahead, so that no scalar load shares the LDS
+    // wait counter with the ring reads
+    uint32_t swv = sw[lane & 15];
+    T w = lane < FW ? b[lane] : (T)0;
+    for (int c = 0; c < nch; ++c) {
+      const int j0 = c * CH;
+      const uint32_t swc = swv;
+      if (c + 1 < nch) swv = sw[(j0 + CH) / 4 + (lane & 15)];
+      T* yo = b + j0;
+      T nv[2][G];
+#pragma unroll
+      for (int k = 0; k < G; ++k) nv[0][k] = yo[k + FW];
+#pragma unroll
+      for (int k = 0; k < G; ++k) pin(nv[0][k]);
+      uint32_t word = 0;
+      T yacc = (T)0;  // lane t: y of column j0 + t
+      static_for<0, CH / G>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (g + 1 < CH / G) {
+#pragma unroll
+          for (int k = 0; k < G; ++k) nv[(g + 1) & 1][k] = yo[(g + 1) * G + k + FW];
+        }
+        static_for<0, G>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          constexpr int t = g * G + k;
+          if constexpr (t % kSU == 0) {
+            // start of unit v = 2c + t / kSU: unit v + 1 to LDS, unit v + 3 requested
+            constexpr int h = (t / kSU + 1) & 1;
+            const int v3 = 2 * c + t / kSU + 3;
+            if constexpr (h == 1) {
+              stage_store(r1, st + kSU * FW, lane);
+              if (v3 < nu) stage_load<T, FW>(r1, Lp, v3, lane);
+            } else {
+              stage_store(r0, st, lane);
+              if (v3 < nu) stage_load<T, FW>(r0, Lp, v3, lane);
+            }
+          }
+          if ((t & 3) == 0) word = __builtin_amdgcn_readlane(swc, t >> 2);
+          const int s = (word >> (8 * (t & 3))) & 0xff;
+          const T y = readlane_t(w, s);
+          put_lane<t>(yacc, y);
+          const T l = ring[t % R];
+          constexpr int tn = t + R;  // column read ahead, buffer by its unit's parity
+          ring[t % R] = st[((tn / kSU) & 1) * kSU * FW + (tn % kSU) * FW + lf];
+          w = __builtin_amdgcn_inverse_ballot_w64(1ull << s) ? nv[g & 1][k] : fma(-l, y, w);
+        });
+        if (g + 1 < CH / G) {
+#pragma unroll
+          for (int k = 0; k < G; ++k) pin(nv[(g + 1) & 1][k]);
+        }
+      });
+      yo[lane] = yacc;
+    }
+  }
+
+  // ---- backward sweep (columns descending; processing index v of unit nu - 1 - v)
+  {
+    const int lb = lane & (BW - 1);
+    constexpr int NL = stage_loads<T, BW>();
+    static_assert(NL >= 1 && kSU * BW * (int)sizeof(T) % 1024 == 0, "staging unit geometry");
+    u32x4 r0[NL], r1[NL];
+    stage_load<T, BW>(r0, Up, nu - 1, lane);
+    stage_load<T, BW>(r1, Up, nu - 2, lane);
+    stage_store(r0, st, lane);
+    if (nu > 2) stage_load<T, BW>(r0, Up, nu - 3, lane);
+    // processing unit v sits in LDS buffer v mod 2; column kSU - 1 - k of unit
+    // nu - 1 is ring entry k
+    T ring[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) ring[k] = st[(kSU - 1 - k) * BW + lb];
+    // rows npad-BW .. npad-1 (rows >= n hold finite padding; their U
+    // coefficients are zero)
+    T w = b[npad - BW + lb];
+    for (int c = nch - 1; c >= 0; --c) {
+      const int j0 = c * CH;
+      T* xo = b + j0;
+      constexpr int NG = CH / G;
+      T nv[2][G];
+#pragma unroll
+      for (int k = 0; k < G; ++k) nv[(NG - 1) & 1][k] = xo[(NG - 1) * G + k - BW];
+#pragma unroll
+      for (int k = 0; k < G; ++k) pin(nv[(NG - 1) & 1][k]);
+      T xacc = (T)0;  // lane t: x of column j0 + t
+      static_for<0, NG>([&](auto gc) {
+        constexpr int g = NG - 1 - decltype(gc)::value;
+        if (g > 0) {
+#pragma unroll
+          for (int k = 0; k < G; ++k) nv[(g - 1) & 1][k] = xo[(g - 1) * G + k - BW];
+        }
+        static_for<0, G>([&](auto kc) {
+          constexpr int k = G - 1 - decltype(kc)::value;
+          constexpr int t = g * G + k;
+          constexpr int q = CH - 1 - t;  // position in processing order within the chunk
+          if constexpr (q % kSU == 0) {
+            // unit of processing index v = 2 (nch - 1 - c) + q / kSU starts
+            constexpr int h = (q / kSU + 1) & 1;
+            const int v3 = 2 * (nch - 1 - c) + q / kSU + 3;
+            if constexpr (h == 1) {
+              stage_store(r1, st + kSU * BW, lane);
+              if (v3 < nu) stage_load<T, BW>(r1, Up, nu - 1 - v3, lane);
+            } else {
+              stage_store(r0, st, lane);
+              if (v3 < nu) stage_load<T, BW>(r0, Up, nu - 1 - v3, lane);
+            }
+          }
+          constexpr int sj = t % BW;
+          constexpr uint64_t msj = BW == 32 ? ((1ull << sj) | (1ull << (sj + 32))) : (1ull << sj);
+          const T u = ring[q % R];
+          constexpr int qn = q + R;  // processing position read ahead
+          ring[q % R] = st[((qn / kSU) & 1) * kSU * BW + (kSU - 1 - qn % kSU) * BW + lb];
+          const T x = readlane_t(w * u, sj);
+          put_lane<t>(xacc, x);
+          w = __builtin_amdgcn_inverse_ballot_w64(msj) ? nv[g & 1][k] : fma(-u, x, w);
+        });
+        if (g > 0) {
+#pragma unroll
+          for (int k = 0; k < G; ++k) pin(nv[(g - 1) & 1][k]);
+        }
+      });
+      xo[lane] = xacc;
+    }
+  }
+}
+
 // Right-hand side of the real-scaled system for one pencil, one real part
 // (part 0: real, 1: imaginary), written to b[-BW .. npad + FW): boundary rows
-// take the Dirichlet values (b at the mean pencil), the evolved-equation
-// U-rows n <= N-2 the entries of Bev (u, v rows times i), all else zero.
+// take the Dirichlet values (b at the mean pencil, real part), the evolved-
+// equation U-rows n <= N-2 the entries of Bev (u, v rows times i), all else
+// zero.  The zero fill comes first and the Bev entries are then read in
+// their own order (coalesced, independent loads) and scattered to their rows;
+// both passes belong to one wavefront, whose LDS accesses stay in order.
 template <typename T>
 __device__ __forceinline__ void build_rhs(const PencilArgs& a, const PencilCoef& pc,
                                           const double2* __restrict__ Bp, int part, T* b, double* b64,
                                           int BW, int FW, int npad, int lane) {
   const SysDesc& d = a.desc;
-  const int n = a.n, N = d.N, kb = d.kb, ne = d.ne;
+  const int n = a.n, N = d.N, S = d.S, kb = d.kb, ne = d.ne;
   for (int r = lane - BW; r < npad + FW; r += kWave) {
-    double vr = 0.0, vi = 0.0;
-    if (r >= 0 && r < kb) {
-      if (pc.mean && d.bc_var[r] == VB) vr = d.bc_side[r] == 0 ? a.b_bottom : a.b_top;
-    } else if (r >= kb && r < n) {
-      int epos;
-      const int m = sys_row_mode(d, r, &epos);
-      const int eq = d.eq_at[epos];
-      int e = -1;
-      if (eq == EB) e = 0;
-      if (eq == EU) e = 1;
-      if (eq == EV) e = 2;
-      if (eq == EW) e = ne - 1;
-      if (e >= 0 && m <= N - 2) {
-        const double2 v = Bp[e * N + m];
-        if (eq == EU || eq == EV) {  // row scaled by i
-          vr = -v.y;
-          vi = v.x;
-        } else {
-          vr = v.x;
-          vi = v.y;
-        }
-      }
-    }
-    const double v = part == 0 ? vr : vi;
+    double v = 0.0;
+    if (part == 0 && r >= 0 && r < kb && pc.mean && d.bc_var[r] == VB)
+      v = d.bc_side[r] == 0 ? a.b_bottom : a.b_top;
     b[r] = (T)v;
     if (b64 && r >= 0 && r < n) b64[r] = v;
+  }
+  const int Nm = N - 1;
+#pragma unroll 4
+  for (int i = lane; i < ne * Nm; i += kWave) {
+    const int e = i / Nm, m = i - e * Nm;
+    const int eq = e == 0 ? EB : (e == ne - 1 ? EW : (e == 1 ? EU : EV));
+    const double2 v = Bp[e * N + m];
+    const bool scaled = eq == EU || eq == EV;  // row scaled by i
+    const double val = part == 0 ? (scaled ? -v.y : v.x) : (scaled ? v.x : v.y);
+    const int r = kb + m * S + d.eq_pos[eq];
+    b[r] = (T)val;
+    if (b64) b64[r] = val;
   }
 }
 
@@ -402,41 +590,65 @@ __device__ __forceinline__ void write_state(const PencilArgs& a, const double* x
 }
 
 // ---------------------------------------------------------------------------
-// Solve: two wavefronts per pencil, wave 0 for the real part of the
-// right-hand side and wave 1 for the imaginary part (the real-scaled matrix
-// is real).  Each builds its vector in LDS, overwrites it by y = L^{-1} P b
-// and x~ = U^{-1} y, and after one barrier both write X = P^R x~.
+// Pencil blocks: two pencils per block of four wavefronts, wave 2 q + part
+// for pencil 2 blockIdx.x + q and real part `part` (the real-scaled matrix is
+// real, so the real and imaginary parts of the right-hand side are two
+// independent real solves).  Blocks cover pencils [0, plaunch); block 0 also
+// zeroes the state of the inactive pencils [plaunch, P) (in 2-D the Nyquist
+// pencil), so that a launch of plaunch / 2 <= #CU blocks can place one block
+// per compute unit and one sweeping wavefront per SIMD.
 // ---------------------------------------------------------------------------
-template <int FW, int BW>
-__global__ void __launch_bounds__(2 * kWave) solve_kernel(PencilArgs a,
+__device__ __forceinline__ void zero_pencils(double2* __restrict__ X, size_t first, size_t last,
+                                             int stride, int tid, int nt) {
+  for (size_t i = first * stride + tid; i < last * stride; i += nt) X[i] = make_double2(0.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// Solve: each wavefront builds its real vector in LDS, overwrites it by
+// y = L^{-1} P b and x~ = U^{-1} y, and after one barrier the pencil's two
+// wavefronts write X = P^R x~.
+// ---------------------------------------------------------------------------
+template <int FW, int BW, bool STG>
+__global__ void __launch_bounds__(4 * kWave) solve_kernel(PencilArgs a, int plaunch,
                                                           const double2* __restrict__ Bev,
                                                           const double* __restrict__ Lf,
                                                           const uint8_t* __restrict__ sl,
                                                           const double* __restrict__ Uf,
                                                           double2* __restrict__ X) {
   extern __shared__ double lds[];
-  const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = wv >> 1, part = wv & 1;
+  const int p = blockIdx.x * 2 + q;
   const SysDesc& d = a.desc;
   const int N = d.N, S = d.S, ne = d.ne;
-  double2* Xp = X + (size_t)p * S * N;
-  if (!pencil_active(a, p)) {
-    for (int i = tid; i < S * N; i += 2 * kWave) Xp[i] = make_double2(0.0, 0.0);
-    return;
-  }
-  const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
+  if (blockIdx.x == 0 && plaunch < a.P) zero_pencils(X, plaunch, a.P, S * N, tid, 4 * kWave);
+  const bool live = p < plaunch;
+  const bool act = live && pencil_active(a, p);
   const int npad = a.nst, nch = npad / kCH;
   const int span = BW + npad + FW;
-  double* bre = lds + BW;
-  double* bim = lds + span + BW;
-  double* b = wv == 0 ? bre : bim;
-  build_rhs<double>(a, pc, Bev + (size_t)p * ne * N, wv, b, nullptr, BW, FW, npad, lane);
-  sweeps<double, FW, BW>(b, Lf + (size_t)p * npad * FW, (const uint32_t*)(sl + (size_t)p * npad),
-                         Uf + (size_t)p * npad * BW, nch, lane);
+  double* bre = lds + (size_t)q * 2 * span + BW;
+  double* bim = bre + span;
+  if (act) {
+    const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
+    double* b = part == 0 ? bre : bim;
+    build_rhs<double>(a, pc, Bev + (size_t)p * ne * N, part, b, nullptr, BW, FW, npad, lane);
+    const double* Lp = Lf + (size_t)p * npad * FW;
+    const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
+    const double* Up = Uf + (size_t)p * npad * BW;
+    if constexpr (STG) {
+      double* stg = lds + (size_t)4 * span + (size_t)wv * (stage_bytes<double, FW, BW>() / 8);
+      sweeps_staged<double, FW, BW>(b, Lp, swp, Up, nch, lane, stg);
+    } else {
+      sweeps<double, FW, BW>(b, Lp, swp, Up, nch, lane);
+    }
+  }
   __syncthreads();
-  write_state(a, bre, bim, Xp, tid, 2 * kWave);
+  if (act)
+    write_state(a, bre, bim, X + (size_t)p * S * N, tid & (2 * kWave - 1), 2 * kWave);
+  else if (live)
+    zero_pencils(X, p, p + 1, S * N, tid & (2 * kWave - 1), 2 * kWave);
 }
 
 // ---------------------------------------------------------------------------
@@ -548,6 +760,12 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
   }
 }
 
+// LDS of one pencil in the mixed solve, in doubles (16-byte multiple):
+// b64[2 n] + 2 x (FP32 sweep vector [span] + FP32 first solution [n])
+__host__ __device__ inline size_t mixed_pencil_doubles(int n, int span) {
+  return ((size_t)2 * n + (size_t)(span + n) + 1) / 2 * 2;
+}
+
 // ---------------------------------------------------------------------------
 // Mixed-precision solve: FP32 sweeps with FP32 copies of the FP64 factors,
 // FP64 residual r = b - A x^ from the operator templates (boundary rows
@@ -556,51 +774,64 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
 // Per wavefront (one real part) in LDS: b64[n] (FP64 right-hand side, then
 // the solution), w32 (padded FP32 sweep vector), xh[n] (FP32 first solution).
 // ---------------------------------------------------------------------------
-template <int FW, int BW>
-__global__ void __launch_bounds__(2 * kWave) solve_mixed_kernel(
-    PencilArgs a, double a0, double b0, const double2* __restrict__ Bev,
+template <int FW, int BW, bool STG>
+__global__ void __launch_bounds__(4 * kWave) solve_mixed_kernel(
+    PencilArgs a, int plaunch, double a0, double b0, const double2* __restrict__ Bev,
     const float* __restrict__ Lf, const uint8_t* __restrict__ sl, const float* __restrict__ Uf,
     double2* __restrict__ X) {
   extern __shared__ double lds[];
-  const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = wv >> 1, part = wv & 1;
+  const int p = blockIdx.x * 2 + q;
   const int n = a.n, N = a.desc.N, S = a.desc.S, ne = a.desc.ne;
   const SysDesc& d = a.desc;
-  double2* Xp = X + (size_t)p * S * N;
-  if (!pencil_active(a, p)) {
-    for (int i = tid; i < S * N; i += 2 * kWave) Xp[i] = make_double2(0.0, 0.0);
-    return;
-  }
-  const PencilCoef pc = pencil_coef(a, p, a0, b0);
+  if (blockIdx.x == 0 && plaunch < a.P) zero_pencils(X, plaunch, a.P, S * N, tid, 4 * kWave);
+  const bool live = p < plaunch;
+  const bool act = live && pencil_active(a, p);
   const int npad = a.nst, nch = npad / kCH;
   const int span = BW + npad + FW;
-  double* b64r = lds;
-  double* b64i = lds + n;
-  double* b64 = wv == 0 ? b64r : b64i;
-  float* f0 = (float*)(lds + 2 * n) + (size_t)wv * (span + n);
-  float* w = f0 + BW;
-  float* xh = f0 + span;
-  build_rhs<float>(a, pc, Bev + (size_t)p * ne * N, wv, w, b64, BW, FW, npad, lane);
-  const float* Lp = Lf + (size_t)p * npad * FW;
-  const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
-  const float* Up = Uf + (size_t)p * npad * BW;
-  sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
-  for (int r = lane; r < n; r += kWave) xh[r] = w[r];
-  for (int r = lane; r < npad + FW; r += kWave) {
-    if (r < n) {
-      const double ax =
-          apply_row(d, pc, r, [&](int m, int var) { return (double)xh[m * S + d.var_pos[var]]; });
-      w[r] = (float)(b64[r] - ax);
-    } else {
-      w[r] = 0.0f;
+  // per pencil: b64 for both parts, then per part the FP32 sweep vector and x^
+  double* b64r = lds + (size_t)q * mixed_pencil_doubles(n, span);
+  double* b64i = b64r + n;
+  if (act) {
+    const PencilCoef pc = pencil_coef(a, p, a0, b0);
+    double* b64 = part == 0 ? b64r : b64i;
+    float* f0 = (float*)(b64r + 2 * n) + (size_t)part * (span + n);
+    float* w = f0 + BW;
+    float* xh = f0 + span;
+    build_rhs<float>(a, pc, Bev + (size_t)p * ne * N, part, w, b64, BW, FW, npad, lane);
+    const float* Lp = Lf + (size_t)p * npad * FW;
+    const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
+    const float* Up = Uf + (size_t)p * npad * BW;
+    float* stg = (float*)(lds + 2 * mixed_pencil_doubles(n, span)) +
+                 (size_t)wv * (stage_bytes<float, FW, BW>() / 4);
+    auto sweep = [&]() {
+      if constexpr (STG)
+        sweeps_staged<float, FW, BW>(w, Lp, swp, Up, nch, lane, stg);
+      else
+        sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
+    };
+    sweep();
+    for (int r = lane; r < n; r += kWave) xh[r] = w[r];
+    for (int r = lane; r < npad + FW; r += kWave) {
+      if (r < n) {
+        const double ax =
+            apply_row(d, pc, r, [&](int m, int var) { return (double)xh[m * S + d.var_pos[var]]; });
+        w[r] = (float)(b64[r] - ax);
+      } else {
+        w[r] = 0.0f;
+      }
     }
+    sweep();
+    for (int r = lane; r < n; r += kWave) b64[r] = (double)xh[r] + (double)w[r];
   }
-  sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
-  for (int r = lane; r < n; r += kWave) b64[r] = (double)xh[r] + (double)w[r];
   __syncthreads();
-  write_state(a, b64r, b64i, Xp, tid, 2 * kWave);
+  if (act)
+    write_state(a, b64r, b64i, X + (size_t)p * S * N, tid & (2 * kWave - 1), 2 * kWave);
+  else if (live)
+    zero_pencils(X, p, p + 1, S * N, tid & (2 * kWave - 1), 2 * kWave);
 }
 
 __global__ void round_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
@@ -630,13 +861,57 @@ static void allow_lds(const void* fn, size_t bytes) {
 
 #define STAU_SWEEP_VARIANTS(X) X(8, 32) X(8, 64) X(16, 32) X(16, 64) X(32, 32) X(32, 64)
 
+// Launch shape of the two-pencil blocks: pencils covered (the leading active
+// pencils in 2-D, all in 3-D), block count, and the LDS request.  When the
+// blocks fit one per compute unit the request is raised above half of a
+// unit's LDS, so that no unit takes two blocks (two sweeping wavefronts on
+// one SIMD) while others idle.
+// When the blocks fit one per compute unit, the factor columns are staged
+// through LDS (stage_lds more bytes per block) if that fits.
+struct PencilGrid {
+  int plaunch, blocks;
+  size_t lds;
+  bool staged;
+};
+
+static PencilGrid pencil_grid(const PencilArgs& a, size_t lds_per_pencil, size_t stage_lds) {
+  PencilGrid g;
+  g.plaunch = a.desc.dim == 2 ? a.Px - 1 : a.P;
+  g.blocks = (g.plaunch + 1) / 2;
+  g.lds = 2 * lds_per_pencil;
+  g.staged = false;
+  int dev = 0, cus = 0, lds_cu = 0, lds_blk = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess &&
+      hipDeviceGetAttribute(&lds_blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+      g.blocks <= cus) {
+    const size_t lim = std::min((size_t)lds_cu, (size_t)lds_blk);
+    if (g.lds + stage_lds <= lim) {
+      g.lds += stage_lds;
+      g.staged = true;
+    }
+    const size_t want = (size_t)lds_cu / 2 + 1024;
+    if (g.lds < want && want <= (size_t)lds_blk) g.lds = want;
+  }
+  return g;
+}
+
 template <int FW, int BW>
 static hipError_t launch_solve_t(const PencilArgs& a, const void* Bev, const double* Lf,
                                  const uint8_t* sl, const double* Uf, void* X, hipStream_t st) {
-  size_t lds = (size_t)2 * (BW + a.nst + FW) * sizeof(double);
-  allow_lds((const void*)solve_kernel<FW, BW>, lds);
-  hipLaunchKernelGGL((solve_kernel<FW, BW>), dim3(a.P), dim3(2 * kWave), lds, st, a,
-                     (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+  const PencilGrid g = pencil_grid(a, (size_t)2 * (BW + a.nst + FW) * sizeof(double),
+                                   (size_t)4 * stage_bytes<double, FW, BW>());
+  if (g.staged) {
+    allow_lds((const void*)solve_kernel<FW, BW, true>, g.lds);
+    hipLaunchKernelGGL((solve_kernel<FW, BW, true>), dim3(g.blocks), dim3(4 * kWave), g.lds, st, a,
+                       g.plaunch, (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+  } else {
+    allow_lds((const void*)solve_kernel<FW, BW, false>, g.lds);
+    hipLaunchKernelGGL((solve_kernel<FW, BW, false>), dim3(g.blocks), dim3(4 * kWave), g.lds, st, a,
+                       g.plaunch, (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+  }
   return hipGetLastError();
 }
 
@@ -654,10 +929,17 @@ static hipError_t launch_solve_mixed_t(const PencilArgs& a, double a0, double b0
                                        const float* Lf, const uint8_t* sl, const float* Uf,
                                        void* X, hipStream_t st) {
   const int span = BW + a.nst + FW;
-  size_t lds = (size_t)2 * a.n * sizeof(double) + (size_t)2 * (span + a.n) * sizeof(float);
-  allow_lds((const void*)solve_mixed_kernel<FW, BW>, lds);
-  hipLaunchKernelGGL((solve_mixed_kernel<FW, BW>), dim3(a.P), dim3(2 * kWave), lds, st, a, a0, b0,
-                     (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+  const PencilGrid g = pencil_grid(a, mixed_pencil_doubles(a.n, span) * sizeof(double),
+                                   (size_t)4 * stage_bytes<float, FW, BW>());
+  if (g.staged) {
+    allow_lds((const void*)solve_mixed_kernel<FW, BW, true>, g.lds);
+    hipLaunchKernelGGL((solve_mixed_kernel<FW, BW, true>), dim3(g.blocks), dim3(4 * kWave), g.lds,
+                       st, a, g.plaunch, a0, b0, (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+  } else {
+    allow_lds((const void*)solve_mixed_kernel<FW, BW, false>, g.lds);
+    hipLaunchKernelGGL((solve_mixed_kernel<FW, BW, false>), dim3(g.blocks), dim3(4 * kWave), g.lds,
+                       st, a, g.plaunch, a0, b0, (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+  }
   return hipGetLastError();
 }
 

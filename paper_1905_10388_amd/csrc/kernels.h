@@ -110,6 +110,13 @@ hipError_t launch_zb_mm(const XformArgs& a, const FieldList& fl, const void* X, 
                         const double* Bfrag, hipStream_t st);
 hipError_t launch_zf_mm(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
                         const double* Ffrag, hipStream_t st);
+// mixed path: split-BF16 products with FP32 accumulation; tables split into
+// three BF16 terms in fragment order (N = 64, 128 or 256)
+bool mm_bf16_supported(int N);
+hipError_t launch_zb_bf16(const XformArgs& a, const FieldList& fl, const void* X, void* G,
+                          const void* B3, hipStream_t st);
+hipError_t launch_zf_bf16(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
+                          const void* F3, hipStream_t st);
 
 
 // adjoint path

@@ -77,6 +77,41 @@ std::vector<double> to_frag(int rows, int cols, const std::vector<double>& A) {
   return f;
 }
 
+// BF16 bits of f, rounded to nearest even
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+double bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+// rows x cols matrix A(i, k) split into three BF16 terms (x = h + m + l) in
+// the 16x16x32 BF16 fragment order: lane l of (row block rb, k step ks) holds
+// A[16 rb + l mod 16][32 ks + 8 (l / 16) + e], e < 8, at
+// ((((rb * KS + ks) * 3 + term) * 64 + l) * 8 + e)
+std::vector<uint16_t> to_frag3(int rows, int cols, const std::vector<double>& A) {
+  const int KS = cols / 32;
+  std::vector<uint16_t> f((size_t)rows * cols * 3);
+  for (int rb = 0; rb < rows / 16; ++rb)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e) {
+          double x = A[(size_t)(rb * 16 + l % 16) * cols + ks * 32 + 8 * (l / 16) + e];
+          for (int term = 0; term < 3; ++term) {
+            const uint16_t h = bf16_bits((float)x);
+            f[((((size_t)rb * KS + ks) * 3 + term) * 64 + l) * 8 + e] = h;
+            x -= bf16_value(h);
+          }
+        }
+  return f;
+}
+
 int upload32(const std::vector<double2>& h, float2** d) {
   std::vector<float2> f(h.size());
   for (size_t i = 0; i < h.size(); ++i) f[i] = make_float2((float)h[i].x, (float)h[i].y);
@@ -103,6 +138,9 @@ struct stau_domain {
   // z transforms as matrix products (fragment order of the FP64 matrix cores)
   bool mm = false;
   double *Bzfrag = nullptr, *Fzfrag = nullptr, *PLFzfrag = nullptr;
+  // mixed path: the same tables split into three BF16 terms
+  bool mm16 = false;
+  uint16_t *Bz3 = nullptr, *PLFz3 = nullptr;
 };
 
 struct stau_pencils {
@@ -306,6 +344,8 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
     return fail(STAU_EINVAL, "dct_method %d unknown", d.dct_method);
   if (d.dct_method == STAU_DCT_MATMUL && !mm_supported((int)d.Nz))
     return fail(STAU_EUNSUPPORTED, "matrix-product z transforms need Nz a multiple of 32 in [32, 256]");
+  if (d.dct_method == STAU_DCT_MATMUL && d.precision == STAU_MIXED && !mm_bf16_supported((int)d.Nz))
+    return fail(STAU_EUNSUPPORTED, "mixed-precision matrix-product z transforms need Nz = 64, 128 or 256");
   if (std::fabs(d.dealias - 1.5) > 1e-15) return fail(STAU_EUNSUPPORTED, "dealias must be 1.5");
   if (!is_pow2(d.Nx) || d.Nx < 4 || d.Nx > 4096)
     return fail(STAU_EUNSUPPORTED, "Nx=%lld must be a power of two in [4, 4096]", (long long)d.Nx);
@@ -346,7 +386,9 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
   if ((rc = upload(t, &dom->twx1))) goto bad;
   dom->mm = mm_supported((int)d.Nz) &&
             (d.dct_method == STAU_DCT_MATMUL || (d.dct_method == STAU_DCT_AUTO && d.Nz <= 64));
-  if (dom->mm) {
+  dom->mm16 = d.precision == STAU_MIXED && mm_bf16_supported((int)d.Nz) &&
+              (d.dct_method == STAU_DCT_MATMUL || d.dct_method == STAU_DCT_AUTO);
+  if (dom->mm || dom->mm16) {
     const int N = (int)d.Nz, M = (int)dom->Ngz;
     std::vector<double> Bz((size_t)M * N), Fz((size_t)N * M), PLFz((size_t)N * M);
     for (int j = 0; j < M; ++j)
@@ -359,9 +401,15 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
       for (int j = 0; j < M; ++j)
         PLFz[(size_t)n * M + j] = (n == 0 ? 1.0 : 0.5) * Fz[(size_t)n * M + j] -
                                   (n + 2 < N ? 0.5 * Fz[(size_t)(n + 2) * M + j] : 0.0);
-    if ((rc = upload(to_frag(M, N, Bz), &dom->Bzfrag))) goto bad;
-    if ((rc = upload(to_frag(N, M, Fz), &dom->Fzfrag))) goto bad;
-    if ((rc = upload(to_frag(N, M, PLFz), &dom->PLFzfrag))) goto bad;
+    if (dom->mm) {
+      if ((rc = upload(to_frag(M, N, Bz), &dom->Bzfrag))) goto bad;
+      if ((rc = upload(to_frag(N, M, Fz), &dom->Fzfrag))) goto bad;
+      if ((rc = upload(to_frag(N, M, PLFz), &dom->PLFzfrag))) goto bad;
+    }
+    if (dom->mm16) {
+      if ((rc = upload(to_frag3(M, N, Bz), &dom->Bz3))) goto bad;
+      if ((rc = upload(to_frag3(N, M, PLFz), &dom->PLFz3))) goto bad;
+    }
   }
   if (d.dim == 3) {
     fft_table(dom->Ngy, t);
@@ -395,6 +443,8 @@ int stau_destroy_domain(stau_domain* dom) {
   hipFree(dom->Bzfrag);
   hipFree(dom->Fzfrag);
   hipFree(dom->PLFzfrag);
+  hipFree(dom->Bz3);
+  hipFree(dom->PLFz3);
   delete dom;
   return STAU_OK;
 }
@@ -746,9 +796,10 @@ static void sbdf(int64_t it, double dt, double dtp, double* a0, double* a1, doub
 // 2-D: z backward, fused x pass.  3-D: z backward, y backward, fused x pass,
 // y forward (the x-pass output H2 reuses G, the y-forward output goes to H).
 static hipError_t explicit_term(stau_pencils* pen, const void* X, hipStream_t st, bool mixed) {
-  const bool mm = pen->dom->mm && !mixed;
+  const bool mm = pen->dom->mm && !mixed, mm16 = pen->dom->mm16 && mixed;
   hipError_t e = timed(pen, K_ZB, st, [&] {
     if (mm) return launch_zb_mm(pen->xa, pen->fl, X, pen->G, pen->dom->Bzfrag, st);
+    if (mm16) return launch_zb_bf16(pen->xa, pen->fl, X, pen->G, pen->dom->Bz3, st);
     return launch_zb(pen->xa, pen->fl, X, pen->G, st, mixed);
   });
   if (e != hipSuccess) return e;
@@ -794,6 +845,7 @@ int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
   HIP_TRY(explicit_term(pen, s->X, st, mixed));
   HIP_TRY(timed(pen, K_ZF, st, [&] {
     if (pen->dom->mm && !mixed) return launch_zf_mm(pen->xa, pen->H, pen->Bev, r, pen->dom->PLFzfrag, st);
+    if (pen->dom->mm16 && mixed) return launch_zf_bf16(pen->xa, pen->H, pen->Bev, r, pen->dom->PLFz3, st);
     return launch_zf(pen->xa, pen->H, pen->Bev, r, st, mixed);
   }));
   HIP_TRY(timed(pen, K_SOLVE, st, [&] {

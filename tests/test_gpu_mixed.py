@@ -1,6 +1,7 @@
 """Mixed-precision step (FP32 transforms and products, FP32 sweeps with one
 FP64-residual correction, FP64 factorisation and boundary rows) against the
-FP64 oracle, per field.
+FP64 oracle, per field.  The Chebyshev transforms run either as FP32 FFTs or
+as split-BF16 matrix-core products with FP32 accumulation; both are checked.
 
 Stated bound: relative L2 error per field at most 1e-5 after the trajectories
 below.  The FP64 component calls (stau_nonlinear, stau_solve) are unaffected by
@@ -30,12 +31,16 @@ def _to_np(t):
     return t.cpu().numpy()
 
 
-@pytest.mark.parametrize("cfg,steps", [(C1, 100), ((128, 64, 4.0, 1e6, 1.0, 1e-4), 20),
-                                       ((32, 128, 2.0, 1e7, 7.0, 2e-5), 10)],
-                         ids=["C1", "128x64", "32x128"])
-def test_mixed_trajectory_within_bound(cfg, steps):
+@pytest.mark.parametrize("cfg,steps,dct", [(C1, 100, "fft"), ((128, 64, 4.0, 1e6, 1.0, 1e-4), 20, "fft"),
+                                           ((128, 64, 4.0, 1e6, 1.0, 1e-4), 20, "matmul"),
+                                           ((32, 128, 2.0, 1e7, 7.0, 2e-5), 10, "fft"),
+                                           ((32, 128, 2.0, 1e7, 7.0, 2e-5), 10, "matmul"),
+                                           ((16, 256, 2.0, 1e8, 1.0, 1e-5), 5, "matmul")],
+                         ids=["C1-fft", "128x64-fft", "128x64-bf16", "32x128-fft", "32x128-bf16",
+                              "16x256-bf16"])
+def test_mixed_trajectory_within_bound(cfg, steps, dct):
     Nx, Nz, Lx, Ra, Pr, dt = cfg
-    g = RBSolver(Nx, Nz, Lx, Ra, Pr, precision="mixed")
+    g = RBSolver(Nx, Nz, Lx, Ra, Pr, precision="mixed", dct=dct)
     o = RBOracle(Nx, Nz, Lx, RBParams(Ra, Pr))
     xi = si.workload_noise((Nx, Nz), 0)
     Xo = o.initial_state(xi)
@@ -50,11 +55,12 @@ def test_mixed_trajectory_within_bound(cfg, steps):
     assert max(errs.values()) > 1e-15
 
 
-def test_mixed_full_size_one_step_sampled_pencils():
+@pytest.mark.parametrize("dct", ["fft", "matmul"])
+def test_mixed_full_size_one_step_sampled_pencils(dct):
     """Nx=1024, Nz=256, Ra=1e8, dt=1e-5: one SBDF1 step of the mixed path from
     the oracle's seeded state, compared on sampled pencils."""
     Nx, Nz, Lx, Ra, Pr, dt = 1024, 256, 4.0, 1e8, 1.0, 1e-5
-    g = RBSolver(Nx, Nz, Lx, Ra, Pr, precision="mixed")
+    g = RBSolver(Nx, Nz, Lx, Ra, Pr, precision="mixed", dct=dct)
     o = RBOracle(Nx, Nz, Lx, RBParams(Ra, Pr))
     xi = si.workload_noise((Nx, Nz), 1)
     X0 = o.initial_state(xi)
@@ -89,3 +95,11 @@ def test_mixed_mode_leaves_fp64_components_exact():
     Xg = _to_np(g.solve(torch.from_numpy(Bev).cuda()))
     Xo = oracle_solve_from_ev(o, Bev, 1.0 / dt, 1.0)
     assert max(field_errors(o, Xg, Xo).values()) < 1e-11
+
+
+def test_mixed_matmul_rejects_unsupported_nz():
+    """The split-BF16 products cover Nz = 64, 128, 256; Nz = 32 is refused
+    for the mixed step (the FP64 products accept it)."""
+    with pytest.raises(RuntimeError, match="Nz = 64, 128 or 256"):
+        RBSolver(64, 32, 4.0, 1e4, 1.0, precision="mixed", dct="matmul")
+    RBSolver(64, 32, 4.0, 1e4, 1.0, precision="fp64", dct="matmul")
