@@ -242,15 +242,11 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
 // slack before the first pencil and after the last, so the look-ahead loads
 // never leave the allocation (their values past the sweep are not used).
 // ---------------------------------------------------------------------------
-template <typename T, int FW, int BW>
-__device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uint32_t* __restrict__ sw,
-                                       const T* __restrict__ Up, int nch, int lane) {
+template <typename T, int FW>
+__device__ __forceinline__ void sweep_forward(T* b, const T* __restrict__ Lp,
+                                              const uint32_t* __restrict__ sw, int nch, int lane) {
   constexpr int CH = kCH, D = kRing, G = 16;
-  static_assert(CH % D == 0 && D % 4 == 0 && CH % G == 0 && CH % BW == 0 && FW <= 32 && BW <= 64,
-                "sweep geometry");
-  const int npad = nch * CH;
-
-  // ---- forward sweep
+  static_assert(CH % D == 0 && D % 4 == 0 && CH % G == 0 && FW <= 32, "sweep geometry");
   const int lf = lane & (FW - 1);
   T ring[D];
   uint32_t sring[D / 4];
@@ -298,13 +294,21 @@ __device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uin
     yo[lane] = yacc;
   }
 
-  // ---- backward sweep (columns descending)
+}
+
+template <typename T, int BW>
+__device__ __forceinline__ void sweep_backward(T* b, const T* __restrict__ Up, int nch, int lane) {
+  constexpr int CH = kCH, D = kRing, G = 16;
+  static_assert(CH % D == 0 && CH % G == 0 && CH % BW == 0 && BW <= 64, "sweep geometry");
+  const int npad = nch * CH;
+  // columns descending
   const int lb = lane & (BW - 1);
+  T ring[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) ring[k] = Up[(size_t)(npad - D + k) * BW + lb];  // slot j mod D
   // rows npad-BW .. npad-1 (rows >= n hold finite padding; their U
   // coefficients are zero)
-  w = b[npad - BW + lb];
+  T w = b[npad - BW + lb];
   for (int c = nch - 1; c >= 0; --c) {
     const int j0 = c * CH;
     const T* Un = Up + ((ptrdiff_t)j0 - D) * BW + lb;  // column j0 - D + t at Un[t * BW]
@@ -339,21 +343,30 @@ __device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uin
       }
     });
     xo[lane] = xacc;
-  }
+  }}
+
+template <typename T, int FW, int BW>
+__device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uint32_t* __restrict__ sw,
+                                       const T* __restrict__ Up, int nch, int lane) {
+  sweep_forward<T, FW>(b, Lp, sw, nch, lane);
+  sweep_backward<T, BW>(b, Up, nch, lane);
 }
 
 // ---------------------------------------------------------------------------
-// The same two sweeps with the factor columns staged through LDS, for
-// launches of at most one block per compute unit (one sweeping wavefront per
-// SIMD).  There a global load per column and wavefront is what limits the
-// sweep: the load unit takes about 16 cycles for every 64-lane load of a
-// compute unit, and four wavefronts each need one per column.  Here the
-// factors move in units of kSU columns with 16-byte loads of 64 distinct
-// addresses (1 KB per instruction), two units ahead of their use, through two
-// LDS buffers per wavefront; each column is then one LDS read into a ring of
-// kSR registers.  At the start of processing unit v the data of unit v + 1 is
-// written to LDS buffer (v + 1) mod 2 and unit v + 3 is loaded into the freed
-// registers; reads of unit v + 1 begin kSR columns before it.
+// Backward sweep with the U columns staged through LDS, for launches of at
+// most one block per compute unit (one sweeping wavefront per SIMD).  A
+// 64-lane global load costs the load unit of a compute unit about 16 cycles
+// whatever the number of distinct addresses, and the backward sweep needs
+// BW values per column; here the columns move in units of kSU columns with
+// 16-byte loads of 64 distinct addresses (1 KB per instruction), two units
+// ahead of their use, through two LDS buffers per wavefront, and each column
+// is then one LDS read into a ring of kSR registers.  At the start of
+// processing unit v the data of unit v + 1 is written to LDS buffer
+// (v + 1) mod 2 and unit v + 3 is loaded into the freed registers; reads of
+// unit v + 1 begin kSR columns before it.  (The forward sweep keeps its
+// register ring of global loads: its FW-wide columns gain nothing from
+// staging, and the scalar loads of its slot bytes would share the LDS wait
+// counter.)
 // ---------------------------------------------------------------------------
 constexpr int kSU = 32;  // columns per staging unit
 constexpr int kSR = 8;   // LDS-read look-ahead (columns)
@@ -383,88 +396,16 @@ __device__ __forceinline__ void stage_store(const u32x4 (&r)[NL], T* dst, int la
 // LDS bytes of the factor stage of one wavefront
 template <typename T, int FW, int BW>
 constexpr int stage_bytes() {
-  return 2 * kSU * (FW > BW ? FW : BW) * (int)sizeof(T);
+  return 2 * kSU * BW * (int)sizeof(T);
 }
 
-template <typename T, int FW, int BW>
-__device__ __forceinline__ void sweeps_staged(T* b, const T* __restrict__ Lp,
-                                              const uint32_t* __restrict__ sw,
-                                              const T* __restrict__ Up, int nch, int lane, T* st) {
+template <typename T, int BW>
+__device__ __forceinline__ void sweep_backward_staged(T* b, const T* __restrict__ Up, int nch,
+                                                      int lane, T* st) {
   constexpr int CH = kCH, G = 16, R = kSR;
-  static_assert(CH == 2 * kSU && R <= kSU && CH % G == 0 && CH % BW == 0 &&
-                    FW <= 32 && BW <= 64,
+  static_assert(CH == 2 * kSU && R <= kSU && CH % G == 0 && CH % BW == 0 && BW <= 64,
                 "sweep geometry");
   const int npad = nch * CH, nu = 2 * nch;
-
-  // ---- forward sweep
-  {
-    const int lf = lane & (FW - 1);
-    constexpr int NL = stage_loads<T, FW>();
-    static_assert(NL >= 1 && kSU * FW * (int)sizeof(T) % 1024 == 0, "staging unit geometry");
-    u32x4 r0[NL], r1[NL];  // units in flight (even / odd)
-    stage_load<T, FW>(r0, Lp, 0, lane);
-    stage_load<T, FW>(r1, Lp, 1, lane);
-    stage_store(r0, st, lane);
-    if (nu > 2) stage_load<T, FW>(r0, Lp, 2, lane);
-    T ring[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) ring[k] = st[k * FW + lf];
-    // slot bytes of a chunk: lane i holds word i mod 16 (columns 4i .. 4i + 3);
-    // vector loads, one chunk ahead, so that no scalar load shares the LDS
-    // wait counter with the ring reads
-    uint32_t swv = sw[lane & 15];
-    T w = lane < FW ? b[lane] : (T)0;
-    for (int c = 0; c < nch; ++c) {
-      const int j0 = c * CH;
-      const uint32_t swc = swv;
-      if (c + 1 < nch) swv = sw[(j0 + CH) / 4 + (lane & 15)];
-      T* yo = b + j0;
-      T nv[2][G];
-#pragma unroll
-      for (int k = 0; k < G; ++k) nv[0][k] = yo[k + FW];
-#pragma unroll
-      for (int k = 0; k < G; ++k) pin(nv[0][k]);
-      uint32_t word = 0;
-      T yacc = (T)0;  // lane t: y of column j0 + t
-      static_for<0, CH / G>([&](auto gc) {
-        constexpr int g = decltype(gc)::value;
-        if (g + 1 < CH / G) {
-#pragma unroll
-          for (int k = 0; k < G; ++k) nv[(g + 1) & 1][k] = yo[(g + 1) * G + k + FW];
-        }
-        static_for<0, G>([&](auto kc) {
-          constexpr int k = decltype(kc)::value;
-          constexpr int t = g * G + k;
-          if constexpr (t % kSU == 0) {
-            // start of unit v = 2c + t / kSU: unit v + 1 to LDS, unit v + 3 requested
-            constexpr int h = (t / kSU + 1) & 1;
-            const int v3 = 2 * c + t / kSU + 3;
-            if constexpr (h == 1) {
-              stage_store(r1, st + kSU * FW, lane);
-              if (v3 < nu) stage_load<T, FW>(r1, Lp, v3, lane);
-            } else {
-              stage_store(r0, st, lane);
-              if (v3 < nu) stage_load<T, FW>(r0, Lp, v3, lane);
-            }
-          }
-          if ((t & 3) == 0) word = __builtin_amdgcn_readlane(swc, t >> 2);
-          const int s = (word >> (8 * (t & 3))) & 0xff;
-          const T y = readlane_t(w, s);
-          put_lane<t>(yacc, y);
-          const T l = ring[t % R];
-          constexpr int tn = t + R;  // column read ahead, buffer by its unit's parity
-          ring[t % R] = st[((tn / kSU) & 1) * kSU * FW + (tn % kSU) * FW + lf];
-          w = __builtin_amdgcn_inverse_ballot_w64(1ull << s) ? nv[g & 1][k] : fma(-l, y, w);
-        });
-        if (g + 1 < CH / G) {
-#pragma unroll
-          for (int k = 0; k < G; ++k) pin(nv[(g + 1) & 1][k]);
-        }
-      });
-      yo[lane] = yacc;
-    }
-  }
-
   // ---- backward sweep (columns descending; processing index v of unit nu - 1 - v)
   {
     const int lb = lane & (BW - 1);
@@ -531,7 +472,14 @@ __device__ __forceinline__ void sweeps_staged(T* b, const T* __restrict__ Lp,
       });
       xo[lane] = xacc;
     }
-  }
+  }}
+
+template <typename T, int FW, int BW>
+__device__ __forceinline__ void sweeps_staged(T* b, const T* __restrict__ Lp,
+                                              const uint32_t* __restrict__ sw,
+                                              const T* __restrict__ Up, int nch, int lane, T* st) {
+  sweep_forward<T, FW>(b, Lp, sw, nch, lane);
+  sweep_backward_staged<T, BW>(b, Up, nch, lane, st);
 }
 
 // Right-hand side of the real-scaled system for one pencil, one real part
