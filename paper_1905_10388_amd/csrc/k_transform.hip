@@ -72,64 +72,101 @@ __device__ __forceinline__ bool active(const XformArgs& a, int p) {
 }
 
 // ---------------------------------------------------------------------------
+// z transforms: TP pencils of M points per block of 256 threads, TP * M =
+// kZPts (z_tile), so every thread owns exactly kZPts / 256 points of the
+// block.  The FFT and DCT twiddle tables (M entries each) are staged in LDS
+// behind the data, and each thread issues all of its global loads before it
+// uses any, so that their latencies overlap instead of adding up.
+// ---------------------------------------------------------------------------
+constexpr int kZPts = 3072;
+constexpr int kZThreads = 256;
+constexpr int kZEpt = kZPts / kZThreads;
+
+template <typename T>
+__device__ __forceinline__ void stage_z_tables(const XformArgs& a, cpx<T>* twl, cpx<T>* dcl, int M,
+                                               int tid) {
+  for (int i = tid; i < M; i += kZThreads) {
+    twl[i] = tw_of<T>(a, a.twz, a.twz32, i);
+    dcl[i] = tw_of<T>(a, a.dctz, a.dctz32, i);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Backward z (DCT-III with padding N -> M): g_j = sum_{n<N} c_n T_n(z_j)
 // for every field of `fl` and TP pencils per block.
 // ---------------------------------------------------------------------------
 template <int MAXBF, typename T>
-__global__ void __launch_bounds__(256) zb_kernel(XformArgs a, FieldList fl,
-                                                 const double2* __restrict__ X,
-                                                 typename V2<T>::type* __restrict__ G, int TP) {
+__global__ void __launch_bounds__(kZThreads) zb_kernel(XformArgs a, FieldList fl,
+                                                       const double2* __restrict__ X,
+                                                       typename V2<T>::type* __restrict__ G, int TP) {
   extern __shared__ double2 smem[];
   using cT = cpx<T>;
+  const int M = a.M, N = a.N, S = fl.src_S ? fl.src_S : a.S;
   cT* buf = (cT*)smem;
+  cT* twl = buf + kZPts;  // FFT twiddles
+  cT* dcl = twl + M;      // DCT twiddles
   const int f = blockIdx.y;
   const int p0 = blockIdx.x * TP;
-  const int M = a.M, N = a.N, S = fl.src_S ? fl.src_S : a.S;
   const int var = fl.var[f], der = fl.deriv[f];
   const double wfac = fl.wmode ? 2.0 / (double)M : 1.0;  // (2 - delta_n0) / M, n > 0
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int idx = tid; idx < TP * M; idx += nt) {
+  const int tid = threadIdx.x;
+  stage_z_tables<T>(a, twl, dcl, M, tid);
+  // c_n and c_{M-n} of each owned point (zero outside the stored modes)
+  double2 ya[kZEpt], yb[kZEpt];
+#pragma unroll
+  for (int it = 0; it < kZEpt; ++it) {
+    const int idx = tid + it * kZThreads;
+    const int s = idx / M, nn = idx - s * M;
+    const int p = p0 + s;
+    ya[it] = make_double2(0.0, 0.0);
+    yb[it] = make_double2(0.0, 0.0);
+    if (active(a, p)) {
+      const double2* col = X + ((size_t)p * S + var) * N;
+      if (nn < N) ya[it] = col[nn];
+      if (nn > 0 && M - nn < N) yb[it] = col[M - nn];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kZEpt; ++it) {
+    const int idx = tid + it * kZThreads;
     const int s = idx / M, nn = idx - s * M;
     const int p = p0 + s;
     cT z = mk<T>(0, 0);
     if (active(a, p)) {
-      const double2* col = X + ((size_t)p * S + var) * N;
       double kk = 0.0;
       if (der == 1) kk = kx_of(a, p);
       if (der == 2) kk = ky_of(a, p);
-      auto Yp = [&](int m) -> cd {
-        if (m >= N || m >= M) return mk(0.0, 0.0);
-        cd c = ld2(col + m);
+      auto Yp = [&](double2 v, int m) -> cd {
+        cd c = mk(v.x, v.y);
         if (der) c = mk(-kk * c.y, kk * c.x);  // i k c
         double s1 = (m & 1) ? -1.0 : 1.0;      // T_n on the ascending grid
         if (m > 0) s1 *= 0.5 * wfac;
         else if (fl.wmode) s1 = 1.0 / (double)M;
         return scale(c, s1);
       };
-      cd yn = Yp(nn);
-      cd ym = nn == 0 ? mk(0.0, 0.0) : Yp(M - nn);
-      cd t = mk(yn.x + ym.y, yn.y - ym.x);  // Y_n - i Y_{M-n}
+      const cd yn = Yp(ya[it], nn);
+      const cd ym = nn == 0 ? mk(0.0, 0.0) : Yp(yb[it], M - nn);
+      const cd t = mk(yn.x + ym.y, yn.y - ym.x);  // Y_n - i Y_{M-n}
       if constexpr (sizeof(T) == 8) {
-        cd zz = cmul(ld2(a.dctz + nn), t);
-        z = mk<T>(zz.x, zz.y);
+        z = cmul(dcl[nn], t);
       } else {
-        cT tt = mk<T>((T)t.x, (T)t.y);
-        z = cmul(tw_of<T>(a, a.dctz, a.dctz32, nn), tt);
+        z = cmul(dcl[nn], mk<T>((T)t.x, (T)t.y));
       }
     }
     buf[idx] = z;
   }
   __syncthreads();
-  if constexpr (sizeof(T) == 8)
-    fft_lds<+1, MAXBF>(buf, M, TP, (const cT*)a.twz, tid, nt);
-  else
-    fft_lds<+1, MAXBF>(buf, M, TP, (const cT*)a.twz32, tid, nt);
-  for (int idx = tid; idx < TP * M; idx += nt) {
+  fft_lds<+1, MAXBF>(buf, M, TP, (const cT*)twl, tid, kZThreads);
+#pragma unroll
+  for (int it = 0; it < kZEpt; ++it) {
+    const int idx = tid + it * kZThreads;
     const int jz = idx / TP, s = idx - jz * TP;
     const int p = p0 + s;
-    if (p >= a.P) continue;
-    const int src = (jz & 1) ? (M - 1 - (jz >> 1)) : (jz >> 1);
-    stv<T>(G + ((size_t)f * M + jz) * a.P + p, buf[s * M + src]);
+    if (p < a.P) {
+      const int src = (jz & 1) ? (M - 1 - (jz >> 1)) : (jz >> 1);
+      stv<T>(G + ((size_t)f * M + jz) * a.P + p, buf[s * M + src]);
+    }
   }
 }
 
@@ -142,29 +179,50 @@ __global__ void __launch_bounds__(256) zb_kernel(XformArgs a, FieldList fl,
 //   history hist_cur[p][0][e][n] = F~_n, hist_cur[p][1][e][n] = MX_n.
 // ---------------------------------------------------------------------------
 template <int MAXBF, int MAXIT, typename T>
-__global__ void __launch_bounds__(256) zf_kernel(XformArgs a,
-                                                 const typename V2<T>::type* __restrict__ H,
-                                                 double2* __restrict__ out, RhsArgs r, int TP) {
+__global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
+                                                       const typename V2<T>::type* __restrict__ H,
+                                                       double2* __restrict__ out, RhsArgs r, int TP) {
   extern __shared__ double2 smem[];
   using cT = cpx<T>;
+  const int M = a.M, N = a.N, ne = a.ne;
   cT* buf = (cT*)smem;
+  cT* twl = buf + kZPts;
+  cT* dcl = twl + M;
   const int e = blockIdx.y;
   const int p0 = blockIdx.x * TP;
-  const int M = a.M, N = a.N, ne = a.ne;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int idx = tid; idx < TP * M; idx += nt) {
-    const int jz = idx / TP, s = idx - jz * TP;
-    const int p = p0 + s;
-    cT y = mk<T>(0, 0);
-    if (p < a.P) y = ldv<T>(H + ((size_t)e * M + jz) * a.P + p);
-    const int dst = (jz & 1) ? (M - 1 - (jz >> 1)) : (jz >> 1);
-    buf[s * M + dst] = y;
+  const int tid = threadIdx.x, nt = kZThreads;
+  if (r.mode == 1 && a.dim == 2 && blockIdx.x == 0) {
+    // pencils beyond the grid (2-D, p >= Pa): inactive, zero right-hand side and history
+    for (int p = a.Pa; p < a.P; ++p)
+      for (int nn = tid; nn < N; nn += nt) {
+        const size_t o = ((size_t)p * ne + e) * N + nn;
+        const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
+        out[o] = make_double2(0.0, 0.0);
+        r.hist_cur[ho] = make_double2(0.0, 0.0);
+        r.hist_cur[ho + (size_t)ne * N] = make_double2(0.0, 0.0);
+      }
+  }
+  stage_z_tables<T>(a, twl, dcl, M, tid);
+  {
+    cT hv[kZEpt];
+#pragma unroll
+    for (int it = 0; it < kZEpt; ++it) {
+      const int idx = tid + it * nt;
+      const int jz = idx / TP, s = idx - jz * TP;
+      const int p = p0 + s;
+      hv[it] = mk<T>(0, 0);
+      if (p < a.P) hv[it] = ldv<T>(H + ((size_t)e * M + jz) * a.P + p);
+    }
+#pragma unroll
+    for (int it = 0; it < kZEpt; ++it) {
+      const int idx = tid + it * nt;
+      const int jz = idx / TP, s = idx - jz * TP;
+      const int dst = (jz & 1) ? (M - 1 - (jz >> 1)) : (jz >> 1);
+      buf[s * M + dst] = hv[it];
+    }
   }
   __syncthreads();
-  if constexpr (sizeof(T) == 8)
-    fft_lds<-1, MAXBF>(buf, M, TP, (const cT*)a.twz, tid, nt);
-  else
-    fft_lds<-1, MAXBF>(buf, M, TP, (const cT*)a.twz32, tid, nt);
+  fft_lds<-1, MAXBF>(buf, M, TP, (const cT*)twl, tid, nt);
   cT c[MAXIT];
   const T invM = (T)1 / (T)M;
 #pragma unroll
@@ -174,7 +232,7 @@ __global__ void __launch_bounds__(256) zf_kernel(XformArgs a,
       const int s = idx / N, nn = idx - s * N;
       cT V = buf[s * M + nn];
       cT Vm = buf[s * M + (nn == 0 ? 0 : M - nn)];
-      cT w = conj(tw_of<T>(a, a.dctz, a.dctz32, nn));
+      cT w = conj(dcl[nn]);
       cT P = cmul(w, V), Q = cmul(w, conj(Vm));
       cT Y = mk<T>((T)0.5 * (P.x + Q.x), (T)0.5 * (P.y - Q.y));
       T sc = (nn == 0 ? (T)1 : (T)2) * invM;
@@ -192,39 +250,61 @@ __global__ void __launch_bounds__(256) zf_kernel(XformArgs a,
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < TP * N; idx += nt) {
-    const int s = idx / N, nn = idx - s * N;
-    const int p = p0 + s;
-    if (p >= a.P) continue;
-    const size_t o = ((size_t)p * ne + e) * N + nn;
-    auto cget = [&](int m) -> cd {
-      const cT v = buf[s * M + m];
-      return mk((double)v.x, (double)v.y);
-    };
-    if (r.mode == 0) {
-      st2(out + o, cget(nn));
-      continue;
-    }
-    cd Ft = mk(0.0, 0.0), MX = mk(0.0, 0.0), B = mk(0.0, 0.0);
-    if (active(a, p) && nn <= N - 2) {
-      const double cnn = nn == 0 ? 1.0 : 0.5;
-      Ft = scale(cget(nn), cnn);
-      if (nn + 2 < N) Ft = Ft - scale(cget(nn + 2), 0.5);
-      const double2* xc = r.Xprev + ((size_t)p * a.S + (e + 1)) * N;
-      MX = scale(ld2(xc + nn), cnn);
-      if (nn + 2 < N) MX = MX - scale(ld2(xc + nn + 2), 0.5);
-      B = scale(Ft, r.c1) - scale(MX, r.a1);
-      if (r.has_hist) {
-        const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
-        cd Fo = ld2(r.hist_old + ho);
-        cd Mo = ld2(r.hist_old + ho + (size_t)ne * N);
-        B = B + scale(Fo, r.c2) - scale(Mo, r.a2);
+  // epilogue in groups of four points per thread: the group's loads first
+  constexpr int GE = 4;
+  static_assert(MAXIT % GE == 0, "epilogue groups");
+#pragma unroll
+  for (int g0 = 0; g0 < MAXIT; g0 += GE) {
+    double2 x0[GE], x2[GE], fo[GE], mo[GE];
+#pragma unroll
+    for (int u = 0; u < GE; ++u) {
+      const int idx = tid + (g0 + u) * nt;
+      x0[u] = x2[u] = fo[u] = mo[u] = make_double2(0.0, 0.0);
+      if (r.mode == 1 && idx < TP * N) {
+        const int s = idx / N, nn = idx - s * N;
+        const int p = p0 + s;
+        if (active(a, p) && nn <= N - 2) {
+          const double2* xc = r.Xprev + ((size_t)p * a.S + (e + 1)) * N;
+          x0[u] = xc[nn];
+          if (nn + 2 < N) x2[u] = xc[nn + 2];
+          if (r.has_hist) {
+            const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
+            fo[u] = r.hist_old[ho];
+            mo[u] = r.hist_old[ho + (size_t)ne * N];
+          }
+        }
       }
     }
-    const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
-    st2(r.hist_cur + ho, Ft);
-    st2(r.hist_cur + ho + (size_t)ne * N, MX);
-    st2(out + o, B);
+#pragma unroll
+    for (int u = 0; u < GE; ++u) {
+      const int idx = tid + (g0 + u) * nt;
+      if (idx >= TP * N) continue;
+      const int s = idx / N, nn = idx - s * N;
+      const int p = p0 + s;
+      if (p >= a.P) continue;
+      const size_t o = ((size_t)p * ne + e) * N + nn;
+      auto cget = [&](int m) -> cd {
+        const cT v = buf[s * M + m];
+        return mk((double)v.x, (double)v.y);
+      };
+      if (r.mode == 0) {
+        st2(out + o, cget(nn));
+        continue;
+      }
+      cd Ft = mk(0.0, 0.0), MX = mk(0.0, 0.0), B = mk(0.0, 0.0);
+      if (active(a, p) && nn <= N - 2) {
+        const double cnn = nn == 0 ? 1.0 : 0.5;
+        Ft = scale(cget(nn), cnn);
+        if (nn + 2 < N) Ft = Ft - scale(cget(nn + 2), 0.5);
+        MX = scale(mk(x0[u].x, x0[u].y), cnn) - scale(mk(x2[u].x, x2[u].y), 0.5);
+        B = scale(Ft, r.c1) - scale(MX, r.a1);
+        if (r.has_hist) B = B + scale(mk(fo[u].x, fo[u].y), r.c2) - scale(mk(mo[u].x, mo[u].y), r.a2);
+      }
+      const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
+      st2(r.hist_cur + ho, Ft);
+      st2(r.hist_cur + ho + (size_t)ne * N, MX);
+      st2(out + o, B);
+    }
   }
 }
 
@@ -890,6 +970,10 @@ __global__ void __launch_bounds__(256) ic_adj_x_kernel(XformArgs a, const double
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+static void allow_lds(const void* fn, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 static int z_tile(int M) { return M >= 3072 ? 1 : 3072 / M; }
 static int x_threads(int L) {
   int nt = (L + 5) / 6;
@@ -900,15 +984,19 @@ static int x_threads(int L) {
 }
 
 hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, void* G,
-                     hipStream_t st, bool fp32) {
+                     hipStream_t st, bool fp32, bool active_only) {
   const int TP = z_tile(a.M);
-  dim3 grid((a.P + TP - 1) / TP, fl.nf);
+  if (TP * a.M != kZPts) return hipErrorInvalidValue;
+  const int plaunch = active_only && a.dim == 2 ? a.Pa : a.P;
+  dim3 grid((plaunch + TP - 1) / TP, fl.nf);
   if (fp32) {
-    size_t lds = (size_t)TP * a.M * sizeof(float2);
+    size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(float2);
+    allow_lds((const void*)zb_kernel<3, float>, lds);
     hipLaunchKernelGGL((zb_kernel<3, float>), grid, dim3(256), lds, st, a, fl, (const double2*)X,
                        (float2*)G, TP);
   } else {
-    size_t lds = (size_t)TP * a.M * sizeof(double2);
+    size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(double2);
+    allow_lds((const void*)zb_kernel<3, double>, lds);
     hipLaunchKernelGGL((zb_kernel<3, double>), grid, dim3(256), lds, st, a, fl, (const double2*)X,
                        (double2*)G, TP);
   }
@@ -918,22 +1006,23 @@ hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, voi
 hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
                      hipStream_t st, bool fp32) {
   const int TP = z_tile(a.M);
-  dim3 grid((a.P + TP - 1) / TP, a.ne);
+  if (TP * a.M != kZPts || TP * a.N > 12 * kZThreads) return hipErrorInvalidValue;
+  const int plaunch = (a.dim == 2 && r.mode == 1) ? a.Pa : a.P;
+  dim3 grid((plaunch + TP - 1) / TP, a.ne);
   if (fp32) {
-    size_t lds = (size_t)TP * a.M * sizeof(float2);
+    size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(float2);
+    allow_lds((const void*)zf_kernel<3, 12, float>, lds);
     hipLaunchKernelGGL((zf_kernel<3, 12, float>), grid, dim3(256), lds, st, a, (const float2*)H,
                        (double2*)out, r, TP);
   } else {
-    size_t lds = (size_t)TP * a.M * sizeof(double2);
+    size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(double2);
+    allow_lds((const void*)zf_kernel<3, 12, double>, lds);
     hipLaunchKernelGGL((zf_kernel<3, 12, double>), grid, dim3(256), lds, st, a, (const double2*)H,
                        (double2*)out, r, TP);
   }
   return hipGetLastError();
 }
 
-static void allow_lds(const void* fn, size_t bytes) {
-  if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
 
 hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, void* Out,
                         hipStream_t st, bool fp32) {

@@ -87,8 +87,10 @@ hipError_t launch_xpass3(const XformArgs& a, const void* G2, void* H2, hipStream
                          bool fp32 = false);
 
 // transforms (2-D)
+// active_only (2-D): transform only the leading Pa pencils; G of the others
+// is left unwritten (for consumers that read p < Pa only, as the x pass does)
 hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, void* G,
-                     hipStream_t st, bool fp32 = false);
+                     hipStream_t st, bool fp32 = false, bool active_only = false);
 hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st,
                         bool fp32 = false);
 // forward z; mode 0 writes F[P][ne][N]; mode 1 assembles the SBDF right-hand

@@ -800,7 +800,7 @@ static hipError_t explicit_term(stau_pencils* pen, const void* X, hipStream_t st
   hipError_t e = timed(pen, K_ZB, st, [&] {
     if (mm) return launch_zb_mm(pen->xa, pen->fl, X, pen->G, pen->dom->Bzfrag, st);
     if (mm16) return launch_zb_bf16(pen->xa, pen->fl, X, pen->G, pen->dom->Bz3, st);
-    return launch_zb(pen->xa, pen->fl, X, pen->G, st, mixed);
+    return launch_zb(pen->xa, pen->fl, X, pen->G, st, mixed, true);
   });
   if (e != hipSuccess) return e;
   if (pen->dom->d.dim == 2)
