@@ -52,12 +52,15 @@ def algorithmic_bytes(info):
 
 ADJ_WORKLOAD = dict(Nx=512, Nz=128, Lx=4.0, Ra=1e6, Pr=1.0, dt=1e-4, steps=200, checkpoint=20,
                     seed_workload=3)
+# mixed-precision adjoint workload: 4096x64, checkpoint every 50
+ADJ_WORKLOAD_MIXED = dict(Nx=4096, Nz=64, Lx=16.0, Ra=1e7, Pr=7.0, dt=2e-5, steps=200, checkpoint=50,
+                          seed_workload=4)
 
 
-def adjoint_ratio(reps=3):
-    """Adjoint workload (512x128, Ra=1e6, 200 SBDF2 steps, checkpoint every 20):
-    time of the forward run vs the full gradient (forward with checkpoints +
-    recomputation + reverse steps + initial-condition adjoint)."""
+def adjoint_ratio(reps=3, a=None, precision="fp64", keep_grad=False):
+    """Adjoint workload (default 512x128, Ra=1e6, 200 SBDF2 steps, checkpoint
+    every 20): time of the forward run vs the full gradient (forward with
+    checkpoints + recomputation + reverse steps + initial-condition adjoint)."""
     import numpy as np
     import torch
 
@@ -65,8 +68,8 @@ def adjoint_ratio(reps=3):
     from paper_1905_10388_amd import RBSolver
     from paper_1905_10388_amd.adjoint import kinetic_energy_and_gradient
 
-    a = ADJ_WORKLOAD
-    g = RBSolver(a["Nx"], a["Nz"], a["Lx"], a["Ra"], a["Pr"])
+    a = a or ADJ_WORKLOAD
+    g = RBSolver(a["Nx"], a["Nz"], a["Lx"], a["Ra"], a["Pr"], precision=precision)
     b = torch.from_numpy(b_grid(a["Nx"], a["Nz"], si.workload_noise((a["Nx"], a["Nz"]), a["seed_workload"]))).cuda()
 
     def fwd():
@@ -91,10 +94,32 @@ def adjoint_ratio(reps=3):
         tg.append(t2 - t1)
     f, gr = float(np.median(tf)), float(np.median(tg))
     dof = 7 * a["Nx"] * a["Nz"] * a["steps"]
-    return {"workload": "rb2d_512x128_Ra1e6_dt1e-4_200steps_ckpt20", "forward_ms": f * 1e3,
-            "gradient_ms": gr * 1e3, "adjoint_over_forward": gr / f,
-            "forward_dof_updates_per_s": dof / f, "adjoint_dof_updates_per_s": dof / (gr - f) if gr > f else None,
-            "dtype": "f64"}
+    name = (f"rb2d_{a['Nx']}x{a['Nz']}_Ra{a['Ra']:.0e}_dt{a['dt']:.0e}_{a['steps']}steps"
+            f"_ckpt{a['checkpoint']}").replace("e+0", "e").replace("e-0", "e-")
+    out = {"workload": name, "forward_ms": f * 1e3,
+           "gradient_ms": gr * 1e3, "adjoint_over_forward": gr / f,
+           "forward_dof_updates_per_s": dof / f, "adjoint_dof_updates_per_s": dof / (gr - f) if gr > f else None,
+           "dtype": "f64" if precision == "fp64" else "f32+f64"}
+    if keep_grad:
+        J, gg = kinetic_energy_and_gradient(g, b, a["dt"], a["steps"], a["checkpoint"])
+        out["_J"], out["_grad"] = J, gg.detach().cpu().numpy()
+    g.close()
+    return out
+
+
+def adjoint_mixed():
+    """The 4096x64 adjoint workload in FP64 and in mixed precision, with the
+    mixed gradient's relative L2 error against the FP64 gradient."""
+    import numpy as np
+
+    r64 = adjoint_ratio(a=ADJ_WORKLOAD_MIXED, keep_grad=True)
+    rmx = adjoint_ratio(a=ADJ_WORKLOAD_MIXED, precision="mixed", keep_grad=True)
+    g64, gmx = r64.pop("_grad"), rmx.pop("_grad")
+    J64, Jmx = r64.pop("_J"), rmx.pop("_J")
+    rmx["grad_err_vs_fp64"] = float(np.linalg.norm(gmx - g64) / np.linalg.norm(g64))
+    rmx["J_err_vs_fp64"] = abs(Jmx - J64) / abs(J64)
+    rmx["speedup_vs_fp64"] = r64["gradient_ms"] / rmx["gradient_ms"]
+    return {"fp64": r64, "mixed": rmx}
 
 
 def measured_traffic(kernel):
@@ -400,6 +425,7 @@ def main():
         out["mixed"]["speedup_vs_fp64"] = out["mixed"]["value"] / value
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio()
+        out["adjoint_mixed"] = adjoint_mixed()
     if not args.no_extra:
         out["workloads"] = extra_workloads()
     if not args.no_cpu_baseline:

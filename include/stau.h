@@ -71,13 +71,15 @@ typedef struct stau_pencils stau_pencils;
  * Nz       Chebyshev modes: a power of two in [4, 512] (3Nz/2 grid points).
  * Lx, Ly   periods of x, y (> 0).
  * dealias  transform scale; must be 1.5 (the 3/2 rule, Sec. IV).
- * precision STAU_FP64 (everything FP64) or STAU_MIXED (stau_step only: FP32
- *          transforms and products; FP64 factorisation rounded to FP32 for the
- *          sweeps; FP32 solve, FP64 residual of the full system (boundary rows
- *          included) from the operator templates, one FP32 correction sweep,
- *          FP64 accumulation; state, history and right-hand side FP64).  The
- *          component calls (stau_nonlinear, stau_solve) and the adjoint run in
- *          FP64 in either mode.
+ * precision STAU_FP64 (everything FP64) or STAU_MIXED (stau_step and
+ *          stau_adjoint_step: FP32 transforms and products; FP64
+ *          factorisation rounded to FP32 for the sweeps; FP32 solve, FP64
+ *          residual of the full system (boundary rows included) from the
+ *          operator templates, one FP32 correction sweep, FP64 accumulation;
+ *          state, history, right-hand side and their adjoints FP64).  The
+ *          component calls (stau_nonlinear, stau_solve) and the
+ *          kinetic-energy and initial-state adjoints run in FP64 in either
+ *          mode.
  * device   HIP device ordinal.
  * dct_method  Chebyshev z transforms of the step: STAU_DCT_AUTO (matrix
  *          products for Nz <= 64, FFT otherwise), STAU_DCT_FFT (DCT through
@@ -227,7 +229,9 @@ typedef struct stau_adjstate {
  *   X_bar^{n-1} = M^H M~X_bar + N'(X^{n-1})^H (P^L)^H F~_bar
  * where N' is the linearised explicit term (adjoint transforms and products on
  * the 3/2 grid).  Uses cached factors of (a0, b0), refactoring synchronously
- * if neither stored factorisation matches.  Sec. IX (IVP, multistep IMEX) is
+ * if neither stored factorisation matches.  In a STAU_MIXED domain the
+ * transposed solve runs FP32 sweeps with one FP64-residual correction and the
+ * adjoint transforms and products run in FP32.  Sec. IX (IVP, multistep IMEX) is
  * the forward operation; the adjoint is not part of the paper. */
 int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, double dt,
                       double dt_prev, stau_adjstate* adj, void* stream);

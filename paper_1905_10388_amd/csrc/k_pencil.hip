@@ -611,37 +611,15 @@ __global__ void __launch_bounds__(4 * kWave) solve_kernel(PencilArgs a, int plau
 //   hM <- -a2 B_bar,  F_bar = (P^L)^T F~_bar,  X_bar_out = (P^L)^T MX_bar on
 //   the evolved variables, zero elsewhere.
 // ---------------------------------------------------------------------------
-template <int FW, int BW>
-__global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
-                                                           const double2* __restrict__ Xin,
-                                                           const double* __restrict__ Lf,
-                                                           const uint8_t* __restrict__ sl,
-                                                           const double* __restrict__ Uf,
-                                                           double2* Xout, AdjRhsArgs r) {
-  extern __shared__ double lds[];
-  const int p = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int n = a.n, N = a.desc.N, S = a.desc.S, kb = a.desc.kb, ne = a.desc.ne;
+// Right-hand side of the transposed solve for one real part:
+// x~_bar = S_R^H (P^R)^T X_bar in system column order, written to b[-BW ..
+// npad + FW) (and to b64[0 .. n) when given).
+template <typename T>
+__device__ __forceinline__ void solveT_rhs(const PencilArgs& a, const double2* __restrict__ Xp,
+                                           int part, T* b, double* b64, int BW, int FW, int npad,
+                                           int lane) {
   const SysDesc& d = a.desc;
-  const double2* Xp = Xin + (size_t)p * S * N;
-  double2* Xo = Xout + (size_t)p * S * N;
-  double2* Fb = r.Fbar + (size_t)p * ne * N;
-  double2* hb = r.hbar + (size_t)p * 2 * ne * N;
-  if (!pencil_active(a, p)) {
-    __syncthreads();
-    for (int i = tid; i < S * N; i += 2 * kWave) Xo[i] = make_double2(0.0, 0.0);
-    for (int i = tid; i < ne * N; i += 2 * kWave) Fb[i] = make_double2(0.0, 0.0);
-    for (int i = tid; i < 2 * ne * N; i += 2 * kWave) hb[i] = make_double2(0.0, 0.0);
-    return;
-  }
-  const int npad = a.nst, nch = npad / kCH;
-  const int span = BW + npad + FW;
-  double* bre = lds + BW;
-  double* bim = lds + span + BW;
-  double* b = wv == 0 ? bre : bim;
-  // x~_bar = S_R^H (P^R)^T X_bar in system column order (this wave's part)
+  const int n = a.n, N = d.N, S = d.S;
   for (int c = lane - BW; c < npad + FW; c += kWave) {
     double vr = 0.0, vi = 0.0;
     if (c >= 0 && c < n) {
@@ -662,13 +640,21 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
         vi = v.y;
       }
     }
-    b[c] = wv == 0 ? vr : vi;
+    const double v = part == 0 ? vr : vi;
+    b[c] = (T)v;
+    if (b64 && c >= 0 && c < n) b64[c] = v;
   }
-  sweeps<double, FW, BW>(b, Lf + (size_t)p * npad * FW, (const uint32_t*)(sl + (size_t)p * npad),
-                         Uf + (size_t)p * npad * BW, nch, lane);
-  __syncthreads();
+}
 
-  // ---- epilogue: history adjoints, (P^L)^T, state-layout outputs --------------
+// Epilogue of the transposed solve (per pencil, all threads of the block):
+// history adjoints, (P^L)^T, state-layout outputs, from the solution's real
+// and imaginary parts bre / bim (system order).
+__device__ __forceinline__ void solveT_epilogue(const PencilArgs& a, const AdjRhsArgs& r,
+                                                const double* bre, const double* bim,
+                                                double2* __restrict__ Xo, double2* __restrict__ Fb,
+                                                double2* __restrict__ hb, int tid, int nt) {
+  const SysDesc& d = a.desc;
+  const int N = d.N, S = d.S, kb = d.kb, ne = d.ne;
   auto bbar = [&](int e, int m) -> double2 {
     if (m < 0 || m > N - 2) return make_double2(0.0, 0.0);
     const int eq = e == 0 ? EB : (e == ne - 1 ? EW : (e == 1 ? EU : EV));
@@ -677,7 +663,7 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
     if (eq == EU || eq == EV) return make_double2(vi, -vr);  // -i v
     return make_double2(vr, vi);
   };
-  for (int i = tid; i < ne * N; i += 2 * kWave) {
+  for (int i = tid; i < ne * N; i += nt) {
     const int e = i / N, m = i - e * N;
     const size_t hF = ((size_t)0 * ne + e) * N, hM = ((size_t)1 * ne + e) * N;
     auto ft = [&](int q) -> double2 {  // F~_bar_q
@@ -695,17 +681,115 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
     Fb[(size_t)e * N + m] = make_double2(cm * f0.x - 0.5 * f2.x, cm * f0.y - 0.5 * f2.y);
     Xo[(size_t)(e + 1) * N + m] = make_double2(cm * x0.x - 0.5 * x2.x, cm * x0.y - 0.5 * x2.y);
   }
-  for (int i = tid; i < S * N; i += 2 * kWave) {
+  for (int i = tid; i < S * N; i += nt) {
     const int v = i / N;
     if (v == 0 || v > ne) Xo[i] = make_double2(0.0, 0.0);
   }
   __syncthreads();
-  for (int i = tid; i < ne * N; i += 2 * kWave) {
+  for (int i = tid; i < ne * N; i += nt) {
     const int e = i / N, m = i - e * N;
     const double2 bb = bbar(e, m);
     hb[((size_t)0 * ne + e) * N + m] = make_double2(r.c2 * bb.x, r.c2 * bb.y);
     hb[((size_t)1 * ne + e) * N + m] = make_double2(-r.a2 * bb.x, -r.a2 * bb.y);
   }
+}
+
+// zero outputs of an inactive pencil in the transposed solve
+__device__ __forceinline__ void solveT_zero(const PencilArgs& a, double2* __restrict__ Xo,
+                                            double2* __restrict__ Fb, double2* __restrict__ hb,
+                                            int tid, int nt) {
+  const int N = a.desc.N, S = a.desc.S, ne = a.desc.ne;
+  for (int i = tid; i < S * N; i += nt) Xo[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < ne * N; i += nt) Fb[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < 2 * ne * N; i += nt) hb[i] = make_double2(0.0, 0.0);
+}
+
+template <int FW, int BW>
+__global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
+                                                           const double2* __restrict__ Xin,
+                                                           const double* __restrict__ Lf,
+                                                           const uint8_t* __restrict__ sl,
+                                                           const double* __restrict__ Uf,
+                                                           double2* Xout, AdjRhsArgs r) {
+  extern __shared__ double lds[];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int N = a.desc.N, S = a.desc.S, ne = a.desc.ne;
+  const double2* Xp = Xin + (size_t)p * S * N;
+  double2* Xo = Xout + (size_t)p * S * N;
+  double2* Fb = r.Fbar + (size_t)p * ne * N;
+  double2* hb = r.hbar + (size_t)p * 2 * ne * N;
+  if (!pencil_active(a, p)) {
+    __syncthreads();
+    solveT_zero(a, Xo, Fb, hb, tid, 2 * kWave);
+    return;
+  }
+  const int npad = a.nst, nch = npad / kCH;
+  const int span = BW + npad + FW;
+  double* bre = lds + BW;
+  double* bim = lds + span + BW;
+  double* b = wv == 0 ? bre : bim;
+  solveT_rhs<double>(a, Xp, wv, b, nullptr, BW, FW, npad, lane);
+  sweeps<double, FW, BW>(b, Lf + (size_t)p * npad * FW, (const uint32_t*)(sl + (size_t)p * npad),
+                         Uf + (size_t)p * npad * BW, nch, lane);
+  __syncthreads();
+  solveT_epilogue(a, r, bre, bim, Xo, Fb, hb, tid, 2 * kWave);
+}
+
+// Mixed-precision transposed solve: FP32 sweeps on FP32 copies of the
+// transposed factors, the FP64 residual r = b - A~^T x^ formed row by row
+// from the operator templates (apply_col: a column of A~), one FP32
+// correction sweep, x = x^ + d in FP64, then the FP64 epilogue.
+template <int FW, int BW>
+__global__ void __launch_bounds__(2 * kWave) solveT_mixed_kernel(
+    PencilArgs a, double a0, double b0, const double2* __restrict__ Xin,
+    const float* __restrict__ Lf, const uint8_t* __restrict__ sl, const float* __restrict__ Uf,
+    double2* Xout, AdjRhsArgs r) {
+  extern __shared__ double lds[];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = a.n, N = a.desc.N, S = a.desc.S, ne = a.desc.ne;
+  const SysDesc& d = a.desc;
+  const double2* Xp = Xin + (size_t)p * S * N;
+  double2* Xo = Xout + (size_t)p * S * N;
+  double2* Fb = r.Fbar + (size_t)p * ne * N;
+  double2* hb = r.hbar + (size_t)p * 2 * ne * N;
+  if (!pencil_active(a, p)) {
+    __syncthreads();
+    solveT_zero(a, Xo, Fb, hb, tid, 2 * kWave);
+    return;
+  }
+  const PencilCoef pc = pencil_coef(a, p, a0, b0);
+  const int npad = a.nst, nch = npad / kCH;
+  const int span = BW + npad + FW;
+  double* b64r = lds;
+  double* b64i = lds + n;
+  double* b64 = wv == 0 ? b64r : b64i;
+  float* f0 = (float*)(lds + 2 * n) + (size_t)wv * (span + n);
+  float* w = f0 + BW;
+  float* xh = f0 + span;
+  solveT_rhs<float>(a, Xp, wv, w, b64, BW, FW, npad, lane);
+  const float* Lp = Lf + (size_t)p * npad * FW;
+  const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
+  const float* Up = Uf + (size_t)p * npad * BW;
+  sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
+  for (int c = lane; c < n; c += kWave) xh[c] = w[c];
+  for (int c = lane; c < npad + FW; c += kWave) {
+    if (c < n) {
+      const double ax = apply_col(d, pc, c, [&](int j) { return (double)xh[j]; });
+      w[c] = (float)(b64[c] - ax);
+    } else {
+      w[c] = 0.0f;
+    }
+  }
+  sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
+  for (int c = lane; c < n; c += kWave) b64[c] = (double)xh[c] + (double)w[c];
+  __syncthreads();
+  solveT_epilogue(a, r, b64r, b64i, Xo, Fb, hb, tid, 2 * kWave);
 }
 
 // LDS of one pencil in the mixed solve, in doubles (16-byte multiple):
@@ -915,6 +999,29 @@ static hipError_t launch_solveT_t(const PencilArgs& a, const void* Xin, const do
   hipLaunchKernelGGL((solveT_kernel<FW, BW>), dim3(a.P), dim3(2 * kWave), lds, st, a,
                      (const double2*)Xin, Lf, sl, Uf, (double2*)Xout, r);
   return hipGetLastError();
+}
+
+template <int FW, int BW>
+static hipError_t launch_solveT_mixed_t(const PencilArgs& a, double a0, double b0, const void* Xin,
+                                        const float* Lf, const uint8_t* sl, const float* Uf,
+                                        void* Xout, const AdjRhsArgs& r, hipStream_t st) {
+  const int span = BW + a.nst + FW;
+  size_t lds = (size_t)2 * a.n * sizeof(double) + (size_t)2 * (span + a.n) * sizeof(float);
+  allow_lds((const void*)solveT_mixed_kernel<FW, BW>, lds);
+  hipLaunchKernelGGL((solveT_mixed_kernel<FW, BW>), dim3(a.P), dim3(2 * kWave), lds, st, a, a0, b0,
+                     (const double2*)Xin, Lf, sl, Uf, (double2*)Xout, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_solveT_mixed(const PencilArgs& a, double a0, double b0, const void* Xin,
+                               const float* Lf, const uint8_t* sl, const float* Uf, void* Xout,
+                               const AdjRhsArgs& r, hipStream_t st) {
+#define STAU_CASE(F, B) \
+  if (a.FW == F && a.BW == B)   \
+    return launch_solveT_mixed_t<F, B>(a, a0, b0, Xin, Lf, sl, Uf, Xout, r, st);
+  STAU_SWEEP_VARIANTS(STAU_CASE)
+#undef STAU_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_solveT(const PencilArgs& a, const void* Xin, const double* Lf, const uint8_t* sl,

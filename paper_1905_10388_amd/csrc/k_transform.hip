@@ -658,42 +658,56 @@ __global__ void ke_sum_kernel(const double2* __restrict__ c, int N, double* out)
 // c optionally multiplied by i k): c_bar_n += conj(i k) sum_j T_n(z_j) g_bar_j,
 // i.e. an unweighted DCT-II per source field, summed per target variable and
 // accumulated into Xbar[p][var][n].
-template <int MAXBF, int MAXIT>
-__global__ void __launch_bounds__(256) zadj_kernel(XformArgs a, AccList al,
-                                                   const double2* __restrict__ Gb,
-                                                   double2* __restrict__ Xb, int TP) {
+template <int MAXBF, int MAXIT, typename T>
+__global__ void __launch_bounds__(kZThreads) zadj_kernel(XformArgs a, AccList al,
+                                                         const typename V2<T>::type* __restrict__ Gb,
+                                                         double2* __restrict__ Xb, int TP) {
   extern __shared__ double2 smem[];
-  cd* buf = (cd*)smem;
+  using cT = cpx<T>;
+  const int M = a.M, N = a.N, S = a.S;
+  cT* buf = (cT*)smem;
+  cT* twl = buf + kZPts;
+  cT* dcl = twl + M;
   const int ti = blockIdx.y;
   const int p0 = blockIdx.x * TP;
-  const int M = a.M, N = a.N, S = a.S;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = kZThreads;
+  stage_z_tables<T>(a, twl, dcl, M, tid);
   cd acc[MAXIT];
 #pragma unroll
   for (int it = 0; it < MAXIT; ++it) acc[it] = mk(0.0, 0.0);
   for (int q = 0; q < al.nsrc[ti]; ++q) {
     const int f = al.src[ti][q], der = al.deriv[ti][q];
-    for (int idx = tid; idx < TP * M; idx += nt) {
-      const int jz = idx / TP, s = idx - jz * TP;
-      const int p = p0 + s;
-      cd y = mk(0.0, 0.0);
-      if (p < a.P) y = ld2(Gb + ((size_t)f * M + jz) * a.P + p);
-      const int dst = (jz & 1) ? (M - 1 - (jz >> 1)) : (jz >> 1);
-      buf[s * M + dst] = y;
+    {
+      cT hv[kZEpt];
+#pragma unroll
+      for (int it = 0; it < kZEpt; ++it) {
+        const int idx = tid + it * nt;
+        const int jz = idx / TP, s = idx - jz * TP;
+        const int p = p0 + s;
+        hv[it] = mk<T>(0, 0);
+        if (p < a.P) hv[it] = ldv<T>(Gb + ((size_t)f * M + jz) * a.P + p);
+      }
+#pragma unroll
+      for (int it = 0; it < kZEpt; ++it) {
+        const int idx = tid + it * nt;
+        const int jz = idx / TP, s = idx - jz * TP;
+        const int dst = (jz & 1) ? (M - 1 - (jz >> 1)) : (jz >> 1);
+        buf[s * M + dst] = hv[it];
+      }
     }
     __syncthreads();
-    fft_lds<-1, MAXBF>(buf, M, TP, (const cd*)a.twz, tid, nt);
+    fft_lds<-1, MAXBF>(buf, M, TP, (const cT*)twl, tid, nt);
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
       const int idx = tid + it * nt;
       if (idx < TP * N) {
         const int s = idx / N, nn = idx - s * N;
         const int p = p0 + s;
-        cd V = buf[s * M + nn];
-        cd Vm = buf[s * M + (nn == 0 ? 0 : M - nn)];
-        cd w = conj(ld2(a.dctz + nn));
-        cd P = cmul(w, V), Q = cmul(w, conj(Vm));
-        cd Y = mk(0.5 * (P.x + Q.x), 0.5 * (P.y - Q.y));
+        const cT V = buf[s * M + nn];
+        const cT Vm = buf[s * M + (nn == 0 ? 0 : M - nn)];
+        const cT w = conj(dcl[nn]);
+        const cT P = cmul(w, V), Q = cmul(w, conj(Vm));
+        cd Y = mk((double)((T)0.5 * (P.x + Q.x)), (double)((T)0.5 * (P.y - Q.y)));
         if (nn & 1) Y = mk(-Y.x, -Y.y);
         if (der && p < a.P) {
           const double kk = der == 1 ? kx_of(a, p) : ky_of(a, p);
@@ -727,87 +741,113 @@ __global__ void __launch_bounds__(256) zadj_kernel(XformArgs a, AccList al,
 // product rule, and maps the eight grid adjoints back to spectra (adjoint of
 // the complex-to-real synthesis: c_bar_k = w_k sum_i g_bar_i e^{-2 pi i k i/L},
 // w_0 = 1, w_k = 2).
-template <int MAXBF, int PTS, int NT>
-__global__ void __launch_bounds__(NT) xpass_adj_kernel(XformArgs a, const double2* __restrict__ G,
-                                                       const double2* __restrict__ Hb,
-                                                       double2* __restrict__ Gb) {
+template <int MAXBF, int PTS, int NT, bool TWL, typename T>
+__global__ void __launch_bounds__(NT) xpass_adj_kernel(XformArgs a,
+                                                       const typename V2<T>::type* __restrict__ G,
+                                                       const typename V2<T>::type* __restrict__ Hb,
+                                                       typename V2<T>::type* __restrict__ Gb) {
   extern __shared__ double2 smem[];
-  cd* buf = (cd*)smem;
+  using cT = cpx<T>;
+  using S2 = typename V2<T>::type;
+  constexpr int KPT = (PTS + 2) / 3;  // half-spectrum entries per thread (Pa = L / 3)
+  cT* buf = (cT*)smem;
   const int jz = blockIdx.x;
   const int M = a.M, L = a.L, Pa = a.Pa, P = a.P;
   const int tid = threadIdx.x;
-  constexpr int nt = NT;
-  const cd* tw = (const cd*)a.twx;
-  // complex-to-real of a packed pair; hs scales k >= 1 (1 for synthesis, 0.5
-  // for the adjoint of the truncated forward transform)
-  auto c2r_pair = [&](const double2* A, const double2* B, double hs, double* ra, double* rb) {
-    for (int k = tid; k < L; k += nt) {
-      cd z = mk(0.0, 0.0);
-      if (k < Pa) {
-        cd Ak = A ? ld2(A + k) : mk(0.0, 0.0), Bk = B ? ld2(B + k) : mk(0.0, 0.0);
-        if (k == 0) {
-          Ak.y = 0.0;
-          Bk.y = 0.0;
+  const cT* twg = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
+  cT* twl = buf + L;
+  if constexpr (TWL) {
+    for (int i = tid; i < L; i += NT) twl[i] = twg[i];
+  }
+  const cT* tw = TWL ? (const cT*)twl : twg;
+  auto row = [&](const S2* base, int f) { return base + ((size_t)f * M + jz) * P; };
+  // complex-to-real pairs: 0..3 the forward fields (G 0..7), 4 (Hb 0, Hb 1)
+  // and 5 (Hb 2, -); hs scales k >= 1 (1 for synthesis, 0.5 for the adjoint
+  // of the truncated forward transform)
+  cT sa[KPT], sb[KPT];
+  auto fetch = [&](int k) {
+    const S2* A = k < 4 ? row(G, 2 * k) : row(Hb, 2 * (k - 4));
+    const S2* B = k < 4 ? row(G, 2 * k + 1) : (k == 4 ? row(Hb, 1) : nullptr);
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int kk = tid + q * NT;
+      sa[q] = mk<T>(0, 0);
+      sb[q] = mk<T>(0, 0);
+      if (kk < Pa) {
+        sa[q] = ldv<T>(A + kk);
+        if (B) sb[q] = ldv<T>(B + kk);
+      }
+    }
+  };
+  auto scatter = [&](T hs) {
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int kk = tid + q * NT;
+      if (kk < Pa) {
+        cT Ak = sa[q], Bk = sb[q];
+        if (kk == 0) {
+          Ak.y = 0;
+          Bk.y = 0;
         } else {
           Ak = scale(Ak, hs);
           Bk = scale(Bk, hs);
         }
-        z = mk(Ak.x - Bk.y, Ak.y + Bk.x);
-      } else if (k > L - Pa) {
-        cd Ak = A ? ld2(A + (L - k)) : mk(0.0, 0.0), Bk = B ? ld2(B + (L - k)) : mk(0.0, 0.0);
-        Ak = scale(Ak, hs);
-        Bk = scale(Bk, hs);
-        z = mk(Ak.x + Bk.y, -Ak.y + Bk.x);
-      }
-      buf[k] = z;
-    }
-    __syncthreads();
-    fft_lds<+1, MAXBF>(buf, L, 1, tw, tid, nt);
-#pragma unroll
-    for (int q = 0; q < PTS; ++q) {
-      const int i = tid + q * nt;
-      if (i < L) {
-        ra[q] = buf[i].x;
-        rb[q] = buf[i].y;
+        buf[kk] = mk<T>(Ak.x - Bk.y, Ak.y + Bk.x);
+        if (kk > 0) buf[L - kk] = mk<T>(Ak.x + Bk.y, -Ak.y + Bk.x);
       }
     }
-    __syncthreads();
+    for (int k = Pa + tid; k <= L - Pa; k += NT) buf[k] = mk<T>(0, 0);
   };
   // adjoint of a synthesis pair: spectra of two real grid rows, weights w_k
-  auto r2c_adj_pair = [&](const double* ga, const double* gb, int fa, int fb) {
+  auto r2c_adj_pair = [&](const T* ga, const T* gb, int fa, int fb) {
 #pragma unroll
     for (int q = 0; q < PTS; ++q) {
-      const int i = tid + q * nt;
-      if (i < L) buf[i] = mk(ga[q], gb[q]);
+      const int i = tid + q * NT;
+      if (i < L) buf[i] = mk<T>(ga[q], gb[q]);
     }
     __syncthreads();
-    fft_lds<-1, MAXBF>(buf, L, 1, tw, tid, nt);
-    double2* Oa = Gb + ((size_t)fa * M + jz) * P;
-    double2* Ob = Gb + ((size_t)fb * M + jz) * P;
-    for (int k = tid; k < P; k += nt) {
-      cd A = mk(0.0, 0.0), Bv = mk(0.0, 0.0);
+    fft_lds<-1, MAXBF, T, true>(buf, L, 1, tw, tid, NT);
+    S2* Oa = Gb + ((size_t)fa * M + jz) * P;
+    S2* Ob = Gb + ((size_t)fb * M + jz) * P;
+    for (int k = tid; k < P; k += NT) {
+      cT A = mk<T>(0, 0), Bv = mk<T>(0, 0);
       if (k < Pa) {
-        cd Zk = buf[k], Zm = buf[k == 0 ? 0 : L - k];
-        const double wk = k == 0 ? 1.0 : 2.0;
-        A = mk(0.5 * (Zk.x + Zm.x) * wk, 0.5 * (Zk.y - Zm.y) * wk);
-        Bv = mk(0.5 * (Zk.y + Zm.y) * wk, -0.5 * (Zk.x - Zm.x) * wk);
+        const cT Zk = buf[k], Zm = buf[k == 0 ? 0 : L - k];
+        const T wk = k == 0 ? (T)1 : (T)2;
+        A = mk<T>((T)0.5 * (Zk.x + Zm.x) * wk, (T)0.5 * (Zk.y - Zm.y) * wk);
+        Bv = mk<T>((T)0.5 * (Zk.y + Zm.y) * wk, (T)-0.5 * (Zk.x - Zm.x) * wk);
       }
-      st2(Oa + k, A);
-      st2(Ob + k, Bv);
+      stv<T>(Oa + k, A);
+      stv<T>(Ob + k, Bv);
     }
     __syncthreads();
   };
-  auto row = [&](const double2* base, int f) { return base + ((size_t)f * M + jz) * P; };
 
-  double u[PTS], w[PTS], bx[PTS], bz[PTS], ux[PTS], uz[PTS], wx[PTS], wz[PTS];
-  double nb[PTS], nu[PTS], nw[PTS], t1[PTS], t2[PTS];
-  c2r_pair(row(G, 0), row(G, 1), 1.0, u, w);
-  c2r_pair(row(G, 2), row(G, 3), 1.0, bx, bz);
-  c2r_pair(row(G, 4), row(G, 5), 1.0, ux, uz);
-  c2r_pair(row(G, 6), row(G, 7), 1.0, wx, wz);
-  c2r_pair(row(Hb, 0), row(Hb, 1), 0.5, nb, nu);
-  c2r_pair(row(Hb, 2), nullptr, 0.5, nw, t1);
-  const double invL = 1.0 / (double)L;
+  T u[PTS], w[PTS], bx[PTS], bz[PTS], ux[PTS], uz[PTS], wx[PTS], wz[PTS];
+  T nb[PTS], nu[PTS], nw[PTS], t1[PTS], t2[PTS];
+  fetch(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    scatter(k < 4 ? (T)1 : (T)0.5);
+    if (k + 1 < 6) fetch(k + 1);
+    __syncthreads();
+    fft_lds<+1, MAXBF, T, true>(buf, L, 1, tw, tid, NT);
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) {
+      const int i = tid + q * NT;
+      if (i < L) {
+        const T x = buf[i].x, y = buf[i].y;
+        if (k == 0) { u[q] = x; w[q] = y; }
+        if (k == 1) { bx[q] = x; bz[q] = y; }
+        if (k == 2) { ux[q] = x; uz[q] = y; }
+        if (k == 3) { wx[q] = x; wz[q] = y; }
+        if (k == 4) { nb[q] = x; nu[q] = y; }
+        if (k == 5) { nw[q] = x; }
+      }
+    }
+    __syncthreads();
+  }
+  const T invL = (T)1 / (T)L;
 #pragma unroll
   for (int q = 0; q < PTS; ++q) {
     nb[q] *= invL;
@@ -1092,35 +1132,61 @@ hipError_t launch_xpass3(const XformArgs& a, const void* G2, void* H2, hipStream
 }
 
 hipError_t launch_zadj(const XformArgs& a, const AccList& al, const void* Gbar, void* Xbar,
-                       hipStream_t st) {
+                       hipStream_t st, bool fp32) {
   const int TP = z_tile(a.M);
+  if (TP * a.M != kZPts || TP * a.N > 12 * kZThreads) return hipErrorInvalidValue;
   dim3 grid((a.P + TP - 1) / TP, al.nt);
-  size_t lds = (size_t)TP * a.M * sizeof(double2);
-  hipLaunchKernelGGL((zadj_kernel<3, 12>), grid, dim3(256), lds, st, a, al, (const double2*)Gbar,
-                     (double2*)Xbar, TP);
+  if (fp32) {
+    const size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(float2);
+    allow_lds((const void*)zadj_kernel<3, 12, float>, lds);
+    hipLaunchKernelGGL((zadj_kernel<3, 12, float>), grid, dim3(kZThreads), lds, st, a, al,
+                       (const float2*)Gbar, (double2*)Xbar, TP);
+  } else {
+    const size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(double2);
+    allow_lds((const void*)zadj_kernel<3, 12, double>, lds);
+    hipLaunchKernelGGL((zadj_kernel<3, 12, double>), grid, dim3(kZThreads), lds, st, a, al,
+                       (const double2*)Gbar, (double2*)Xbar, TP);
+  }
   return hipGetLastError();
 }
 
-template <int NT>
+template <int NT, int PTS, int MAXBF, typename T>
 static hipError_t launch_xpass_adj_t(const XformArgs& a, const void* G, const void* Hb, void* Gb,
                                      hipStream_t st) {
-  size_t lds = (size_t)a.L * sizeof(double2);
-  allow_lds((const void*)xpass_adj_kernel<2, 6, NT>, lds);
-  hipLaunchKernelGGL((xpass_adj_kernel<2, 6, NT>), dim3(a.M), dim3(NT), lds, st, a,
-                     (const double2*)G, (const double2*)Hb, (double2*)Gb);
+  using S2 = typename V2<T>::type;
+  const bool twl = (size_t)a.L * sizeof(S2) <= 32768;
+  const size_t lds = (size_t)a.L * sizeof(S2) * (twl ? 2 : 1);
+  if (twl) {
+    auto fn = xpass_adj_kernel<MAXBF, PTS, NT, true, T>;
+    allow_lds((const void*)fn, lds);
+    hipLaunchKernelGGL(fn, dim3(a.M), dim3(NT), lds, st, a, (const S2*)G, (const S2*)Hb, (S2*)Gb);
+  } else {
+    auto fn = xpass_adj_kernel<MAXBF, PTS, NT, false, T>;
+    allow_lds((const void*)fn, lds);
+    hipLaunchKernelGGL(fn, dim3(a.M), dim3(NT), lds, st, a, (const S2*)G, (const S2*)Hb, (S2*)Gb);
+  }
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_xpass_adj_T(const XformArgs& a, const void* G, const void* Hb, void* Gb,
+                                     hipStream_t st) {
+  const int L = a.L;
+  if (L <= 64) return launch_xpass_adj_t<64, 1, 1, T>(a, G, Hb, Gb, st);
+  if (L <= 128) return launch_xpass_adj_t<64, 2, 1, T>(a, G, Hb, Gb, st);
+  if (L <= 192) return launch_xpass_adj_t<64, 3, 1, T>(a, G, Hb, Gb, st);
+  if (L <= 384) return launch_xpass_adj_t<128, 3, 1, T>(a, G, Hb, Gb, st);
+  if (L <= 768) return launch_xpass_adj_t<256, 3, 1, T>(a, G, Hb, Gb, st);
+  if (L <= 1536) return launch_xpass_adj_t<512, 3, 1, T>(a, G, Hb, Gb, st);
+  if (L <= 3072) return launch_xpass_adj_t<1024, 3, 1, T>(a, G, Hb, Gb, st);
+  if (L <= 6144) return launch_xpass_adj_t<1024, 6, 2, T>(a, G, Hb, Gb, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_xpass_adj(const XformArgs& a, const void* G, const void* Hbar, void* Gbar,
-                            hipStream_t st) {
-  switch (x_threads(a.L)) {
-    case 64: return launch_xpass_adj_t<64>(a, G, Hbar, Gbar, st);
-    case 128: return launch_xpass_adj_t<128>(a, G, Hbar, Gbar, st);
-    case 256: return launch_xpass_adj_t<256>(a, G, Hbar, Gbar, st);
-    case 512: return launch_xpass_adj_t<512>(a, G, Hbar, Gbar, st);
-    case 1024: return launch_xpass_adj_t<1024>(a, G, Hbar, Gbar, st);
-  }
-  return hipErrorInvalidValue;
+                            hipStream_t st, bool fp32) {
+  return fp32 ? launch_xpass_adj_T<float>(a, G, Hbar, Gbar, st)
+              : launch_xpass_adj_T<double>(a, G, Hbar, Gbar, st);
 }
 
 template <int NT>

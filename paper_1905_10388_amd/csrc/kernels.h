@@ -122,10 +122,12 @@ hipError_t launch_zf_bf16(const XformArgs& a, const void* H, void* out, const Rh
 
 
 // adjoint path
+// fp32: Gbar (and in the x pass G, Hbar, Gbar) hold complex64, the
+// transforms run in FP32; Xbar accumulates in FP64 either way
 hipError_t launch_zadj(const XformArgs& a, const AccList& al, const void* Gbar, void* Xbar,
-                       hipStream_t st);
+                       hipStream_t st, bool fp32 = false);
 hipError_t launch_xpass_adj(const XformArgs& a, const void* G, const void* Hbar, void* Gbar,
-                            hipStream_t st);
+                            hipStream_t st, bool fp32 = false);
 struct AdjRhsArgs {
   double c1, c2, a1, a2;
   double2* hbar;  // [P][2][ne][N] pending adjoints (read, then overwritten)
@@ -134,6 +136,11 @@ struct AdjRhsArgs {
 hipError_t launch_solveT(const PencilArgs& a, const void* Xbar_in, const double* Lf,
                          const uint8_t* sl, const double* Uf, void* Xbar_out,
                          const AdjRhsArgs& r, hipStream_t st);
+// mixed precision: FP32 sweeps on FP32 copies of the transposed factors, one
+// FP64-residual correction (a0, b0 of the factored operator)
+hipError_t launch_solveT_mixed(const PencilArgs& a, double a0, double b0, const void* Xin,
+                               const float* Lf, const uint8_t* sl, const float* Uf, void* Xout,
+                               const AdjRhsArgs& r, hipStream_t st);
 hipError_t launch_ke_adjoint(const XformArgs& a, const void* X, void* G, void* Gbar,
                              const void* wvec, void* ebar, void* Xbar, hipStream_t st);
 hipError_t launch_initial_state_adjoint(const XformArgs& a1, const void* Xbar, double* gbar,

@@ -745,7 +745,7 @@ static int factors_for(stau_pencils* pen, double a0, double b0, hipStream_t st,
   else if (!set[1].valid) k = 1;
   if (!set[k].Lraw) {
     size_t bytes = 0;
-    hipError_t e = alloc_slot(set[k], pa, false, &bytes);
+    hipError_t e = alloc_slot(set[k], pa, pen->dom->d.precision == STAU_MIXED, &bytes);
     if (e != hipSuccess) return fail(STAU_ENOMEM, "factor allocation failed: %s", hipGetErrorString(e));
     pen->ws_bytes += (int64_t)bytes;
   }
@@ -911,21 +911,28 @@ int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, 
   r.a2 = a2;
   r.hbar = (double2*)adj->hbar;
   r.Fbar = pen->Bev;
+  // mixed precision: FP32 transposed sweeps with one FP64-residual
+  // correction, FP32 adjoint transforms; X_bar, F_bar and the history stay FP64
+  const bool mixed = pen->dom->d.precision == STAU_MIXED;
   // 1. transposed pencil solve + multistep history adjoints
-  HIP_TRY(launch_solveT(pen->paT, adj->Xbar, fs->Lf, fs->sl, fs->Uf, adj->Xbar, r, st));
+  if (mixed)
+    HIP_TRY(launch_solveT_mixed(pen->paT, a0, b0, adj->Xbar, fs->Lf32, fs->sl, fs->Uf32, adj->Xbar, r,
+                                st));
+  else
+    HIP_TRY(launch_solveT(pen->paT, adj->Xbar, fs->Lf, fs->sl, fs->Uf, adj->Xbar, r, st));
   // 2. adjoint of the forward z transform: H_bar = W^T F_bar
   FieldList fe{};
   fe.nf = pen->pa.desc.ne;
   for (int e = 0; e < fe.nf; ++e) fe.var[e] = e;
   fe.src_S = pen->pa.desc.ne;
   fe.wmode = 1;
-  HIP_TRY(launch_zb(pen->xa, fe, pen->Bev, pen->H, st));
+  HIP_TRY(launch_zb(pen->xa, fe, pen->Bev, pen->H, st, mixed));
   // 3. forward grid fields at X^{n-1}
-  HIP_TRY(launch_zb(pen->xa, pen->fl, X_prev, pen->G, st));
+  HIP_TRY(launch_zb(pen->xa, pen->fl, X_prev, pen->G, st, mixed));
   // 4. adjoint x pass
-  HIP_TRY(launch_xpass_adj(pen->xa, pen->G, pen->H, pen->Gb, st));
+  HIP_TRY(launch_xpass_adj(pen->xa, pen->G, pen->H, pen->Gb, st, mixed));
   // 5. adjoint of the backward z transform, accumulated into X_bar
-  HIP_TRY(launch_zadj(pen->xa, pen->acc, pen->Gb, adj->Xbar, st));
+  HIP_TRY(launch_zadj(pen->xa, pen->acc, pen->Gb, adj->Xbar, st, mixed));
   return STAU_OK;
 }
 

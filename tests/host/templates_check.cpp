@@ -1,0 +1,94 @@
+// Host check of the structured operator applications used by the mixed
+// solves: apply_row (rows of A~) and apply_col (rows of A~^T) against the
+// entry-by-entry matrix sys_entry, on random vectors, for 2-D and 3-D system
+// descriptions, several N, mean and non-mean pencils.  Prints the worst
+// relative error (scaled by the sum of |terms|) and exits 1 above 1e-14.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "common.h"
+
+using namespace stau;
+
+static void build(int dim, int N, SysDesc& d) {
+  std::memset(&d, 0, sizeof(d));
+  d.dim = dim;
+  d.N = N;
+  for (int i = 0; i < 9; ++i) {
+    d.var_pos[i] = -1;
+    d.eq_pos[i] = -1;
+  }
+  if (dim == 2) {
+    const int va[7] = {VW, VB, VU, VP, VBZ, VUZ, VWZ}, ea[7] = {EW, EB, EU, EC, EUZ, EBZ, EWZ};
+    d.S = 7;
+    d.ne = 3;
+    d.kb = 6;
+    for (int i = 0; i < 7; ++i) {
+      d.var_at[i] = va[i];
+      d.eq_at[i] = ea[i];
+    }
+    const int bv[6] = {VB, VU, VW, VB, VU, VW};
+    for (int i = 0; i < 6; ++i) {
+      d.bc_var[i] = bv[i];
+      d.bc_side[i] = i < 3 ? 0 : 1;
+    }
+  } else {
+    const int va[9] = {VW, VB, VU, VV, VP, VBZ, VUZ, VVZ, VWZ};
+    const int ea[9] = {EW, EB, EU, EV, EC, EUZ, EVZ, EBZ, EWZ};
+    d.S = 9;
+    d.ne = 4;
+    d.kb = 8;
+    for (int i = 0; i < 9; ++i) {
+      d.var_at[i] = va[i];
+      d.eq_at[i] = ea[i];
+    }
+    const int bv[8] = {VB, VU, VV, VW, VB, VU, VV, VW};
+    for (int i = 0; i < 8; ++i) {
+      d.bc_var[i] = bv[i];
+      d.bc_side[i] = i < 4 ? 0 : 1;
+    }
+  }
+  for (int i = 0; i < d.S; ++i) {
+    d.var_pos[d.var_at[i]] = i;
+    d.eq_pos[d.eq_at[i]] = i;
+  }
+}
+
+int main() {
+  std::mt19937_64 gen(7);
+  std::normal_distribution<double> nd;
+  double worst_row = 0, worst_col = 0;
+  for (int dim = 2; dim <= 3; ++dim)
+    for (int N : {4, 5, 16, 33})
+      for (int mean = 0; mean < 2; ++mean) {
+        SysDesc d;
+        build(dim, N, d);
+        const PencilCoef pc{1.7e3, 1.0, 3e-4, 2e-4, 1.0, mean ? 0.0 : 3.3,
+                            (mean || dim == 2) ? 0.0 : 1.9, mean};
+        const int n = d.S * N;  // kb + (N - 1) S + 1 with kb = S - 1
+        std::vector<double> x(n), y(n);
+        for (auto& v : x) v = nd(gen);
+        for (auto& v : y) v = nd(gen);
+        for (int i = 0; i < n; ++i) {
+          double rr = 0, rs = 0, cr = 0, cs = 0;
+          for (int j = 0; j < n; ++j) {
+            const double a = sys_entry(d, pc, i, j);  // A~(i, j)
+            rr += a * x[j];
+            rs += std::fabs(a * x[j]);
+            const double t = sys_entry(d, pc, j, i);  // A~^T(i, j)
+            cr += t * y[j];
+            cs += std::fabs(t * y[j]);
+          }
+          const double vr = apply_row(d, pc, i, [&](int m, int var) { return x[m * d.S + d.var_pos[var]]; });
+          const double vc = apply_col(d, pc, i, [&](int r) { return y[r]; });
+          const double er = std::fabs(vr - rr) / (rs + 1e-300), ec = std::fabs(vc - cr) / (cs + 1e-300);
+          if (er > worst_row) worst_row = er;
+          if (ec > worst_col) worst_col = ec;
+        }
+      }
+  std::printf("apply_row %.3e apply_col %.3e\n", worst_row, worst_col);
+  return (worst_row > 1e-14 || worst_col > 1e-14) ? 1 : 0;
+}

@@ -1,0 +1,117 @@
+"""Mixed-precision discrete adjoint (FP32 transposed sweeps with one
+FP64-residual correction, FP32 adjoint transforms and products) against the
+oracle's FP64 discrete adjoint, and at the 4096x64 workload against the
+GPU's FP64 gradient (itself checked against the oracle and finite
+differences in test_gpu_adjoint.py).
+
+Stated bounds: relative L2 error at most 1e-5 for one adjoint step and for
+the 12-step gradient against the oracle; at most 5e-5 for the gradient over
+a long reverse sweep against the FP64 gradient (the rounding of the FP32
+adjoint transforms and products, about 1e-7 relative per transform, adds up
+over the steps: 5.3e-6 after 100 steps and 1.1e-5 after 200 at 4096x64).
+"""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import RBOracle, RBParams
+from oracle import adjoint as ADJ
+from gpu_helpers import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1905_10388_amd import RBSolver  # noqa: E402
+from paper_1905_10388_amd.adjoint import kinetic_energy_and_gradient  # noqa: E402
+
+MIXED_BOUND = 1e-5
+GRADIENT_BOUND = 5e-5
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rand_state(o, seed, amp=1.0):
+    X = si.complex_noise(o.state_shape, seed) * amp
+    X[0] = X[0].real
+    X[o.Px - 1] = 0
+    return X * np.exp(-np.arange(o.Nz) / (o.Nz / 5.0))
+
+
+@pytest.mark.parametrize("iteration", [0, 3])
+def test_mixed_adjoint_step_matches_oracle(iteration):
+    Nx, Nz, Lx, Ra, Pr, dt = 32, 16, 4.0, 1e5, 1.0, 2e-3
+    g = RBSolver(Nx, Nz, Lx, Ra, Pr, precision="mixed")
+    o = RBOracle(Nx, Nz, Lx, RBParams(Ra, Pr))
+    Xp = _rand_state(o, 33, 0.2)
+    Xbar = _rand_state(o, 34)
+    hbar = si.complex_noise((o.Px, 2, o.ne, Nz), 35) if iteration else np.zeros((o.Px, 2, o.ne, Nz), complex)
+    hbar[o.Px - 1] = 0
+    hbar[..., Nz - 1] = 0
+    hbar[0] = hbar[0].real
+    from oracle.rb import sbdf_coefficients
+    o.reset()
+    coeffs = sbdf_coefficients(iteration, dt, dt)
+    pF = {(k,): np.concatenate([np.r_[hbar[k, 0, e], 0.0][:Nz] for e in range(o.ne)] + [np.zeros((o.S - o.ne) * Nz)])
+          for k in range(o.Px - 1)}
+    pM = {(k,): np.concatenate([hbar[k, 1, e] for e in range(o.ne)] + [np.zeros((o.S - o.ne) * Nz)])
+          for k in range(o.Px - 1)}
+    for k in pF:
+        for e in range(o.ne):
+            pF[k][e * Nz + Nz - 1] = 0
+            pM[k][e * Nz + Nz - 1] = 0
+    Xo, nF, nM = ADJ.step_adjoint(o, ADJ.StepRecord(Xp, coeffs), Xbar, pF, pM)
+    Xb = torch.from_numpy(Xbar.copy()).cuda()
+    hb = torch.from_numpy(hbar.copy()).cuda()
+    g.adjoint_step(torch.from_numpy(Xp).cuda(), iteration, dt, dt, Xb, hb)
+    err = rel_err(_np(Xb), Xo)
+    print("mixed adjoint step error", iteration, f"{err:.2e}")
+    assert err < MIXED_BOUND
+    assert err > 1e-15  # the reduced precision is visible
+    hbg = _np(hb)
+    hF = np.array([[hbg[k, 0, e, :Nz - 1] for e in range(o.ne)] for k in range(o.Px - 1)])
+    oF = np.array([[nF[(k,)][e * Nz:e * Nz + Nz - 1] for e in range(o.ne)] for k in range(o.Px - 1)])
+    hM = np.array([[hbg[k, 1, e, :Nz - 1] for e in range(o.ne)] for k in range(o.Px - 1)])
+    oM = np.array([[nM[(k,)][e * Nz:e * Nz + Nz - 1] for e in range(o.ne)] for k in range(o.Px - 1)])
+    assert rel_err(hF, oF) < MIXED_BOUND
+    assert rel_err(hM, oM) < MIXED_BOUND
+
+
+def test_mixed_gradient_matches_oracle_small():
+    Nx, Nz, Lx, Ra, Pr, dt, steps = 32, 16, 4.0, 2e4, 1.0, 5e-3, 12
+    g = RBSolver(Nx, Nz, Lx, Ra, Pr, precision="mixed")
+    o = RBOracle(Nx, Nz, Lx, RBParams(Ra, Pr))
+    xi = si.workload_noise((Nx, Nz), 3)
+    b0 = o.initial_b_grid(xi, amp=0.05)
+    Jo, go = ADJ.gradient(o, b0, dt, steps)
+    Jg, gg = kinetic_energy_and_gradient(g, torch.from_numpy(b0).cuda(), dt, steps, checkpoint=5)
+    err = rel_err(_np(gg), go)
+    print("mixed gradient error (32x16, 12 steps)", f"J {abs(Jg - Jo) / abs(Jo):.2e}", f"grad {err:.2e}")
+    assert abs(Jg - Jo) <= MIXED_BOUND * abs(Jo)
+    assert err < MIXED_BOUND
+
+
+def test_mixed_gradient_small_nz_workload_against_fp64():
+    """4096x64, Lx=16, Ra=1e7, Pr=7, dt=2e-5: 100 SBDF2 steps, checkpoint
+    every 50; the mixed gradient of the final kinetic energy against the FP64
+    one."""
+    Nx, Nz, Lx, Ra, Pr, dt, steps = 4096, 64, 16.0, 1e7, 7.0, 2e-5, 100
+    j = np.arange(Nz)
+    z = 0.5 * (1 - np.cos(np.pi * (j + 0.5) / Nz))
+    xi = si.workload_noise((Nx, Nz), 4)
+    b0 = torch.from_numpy((1 - z)[None, :] + 1e-3 * (z * (1 - z))[None, :] * xi).cuda()
+    out = {}
+    for prec in ("fp64", "mixed"):
+        g = RBSolver(Nx, Nz, Lx, Ra, Pr, precision=prec)
+        J, gr = kinetic_energy_and_gradient(g, b0, dt, steps, checkpoint=50)
+        out[prec] = (J, _np(gr))
+        g.close()
+    eJ = abs(out["mixed"][0] - out["fp64"][0]) / abs(out["fp64"][0])
+    eg = rel_err(out["mixed"][1], out["fp64"][1])
+    print("mixed vs fp64 gradient (4096x64, 100 steps)", f"J {eJ:.2e}", f"grad {eg:.2e}")
+    assert eJ < MIXED_BOUND
+    assert eg < GRADIENT_BOUND
