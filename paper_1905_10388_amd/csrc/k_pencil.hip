@@ -103,11 +103,26 @@ __device__ __forceinline__ bool pencil_active(const PencilArgs& a, int p) {
 // transposed matrix is factored (kl and ku of `a` are then those of the
 // transpose), for the adjoint's transposed solves.
 // ---------------------------------------------------------------------------
+// Entry (r, c) of the factored operator (A~ or A~^T) in the coordinates of
+// the block a.blk (reversed order for the trailing block).
+__device__ __forceinline__ double block_entry(const PencilArgs& a, const PencilCoef& pc, int r, int c) {
+  int R = r, C = c;
+  if (a.blk == 2) {
+    R = a.nfull - 1 - r;
+    C = a.nfull - 1 - c;
+  }
+  return a.trans ? sys_entry(a.desc, pc, C, R) : sys_entry(a.desc, pc, R, C);
+}
+
+// With tailL (two-block solve), the last Q columns' pivot offsets (tailP) and
+// multipliers (tailL, kl per column) are also written in elimination order.
 __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, double b0,
                                                        double* __restrict__ Lf,
                                                        uint8_t* __restrict__ sl,
                                                        double* __restrict__ Uf,
-                                                       int* __restrict__ sing) {
+                                                       int* __restrict__ sing,
+                                                       double* __restrict__ tailL,
+                                                       uint8_t* __restrict__ tailP) {
   extern __shared__ double lds[];
   const int p = blockIdx.x;
   const int lane = threadIdx.x;
@@ -125,7 +140,7 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     for (int q = lane; q < ld; q += kWave) {
       const int r = c - kv + q;
       double v = 0.0;
-      if (r >= 0 && r < n && r >= c - ku) v = a.trans ? sys_entry(d, pc, c, r) : sys_entry(d, pc, r, c);
+      if (r >= 0 && r < n && r >= c - ku) v = block_entry(a, pc, r, c);
       col[q] = v;
     }
   };
@@ -193,6 +208,11 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
       else if (r >= 0 && j - r <= kv)
         v = cj[kv + r - j];
       Up[(size_t)j * BW + l] = v;
+    }
+    if (tailL && j >= n - a.Q) {
+      const int q = j - (n - a.Q);
+      if (lane < kl) tailL[((size_t)p * a.Q + q) * kl + lane] = (lane + 1 <= hi - j) ? cj[kv + lane + 1] : 0.0;
+      if (lane == 0) tailP[(size_t)p * a.Q + q] = (uint8_t)(pr - j);
     }
     // --- emit column j: multipliers routed to physical forward slots
     if (lane == 0) spiv = pr;
@@ -353,133 +373,203 @@ __device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uin
 }
 
 // ---------------------------------------------------------------------------
-// Backward sweep with the U columns staged through LDS, for launches of at
-// most one block per compute unit (one sweeping wavefront per SIMD).  A
-// 64-lane global load costs the load unit of a compute unit about 16 cycles
-// whatever the number of distinct addresses, and the backward sweep needs
-// BW values per column; here the columns move in units of kSU columns with
-// 16-byte loads of 64 distinct addresses (1 KB per instruction), two units
+// Sweeps with the factor columns staged through LDS.  A 64-lane global load
+// costs the load unit of a compute unit about 16 cycles whatever the number
+// of distinct addresses, so one load per column and wavefront limits a
+// sweep once four or more wavefronts share a compute unit.  Here the columns
+// move in units of SU columns with loads of 64 distinct addresses (16 bytes
+// per lane, 1 KB per instruction; 8 bytes for a 512-byte unit), two units
 // ahead of their use, through two LDS buffers per wavefront, and each column
 // is then one LDS read into a ring of kSR registers.  At the start of
 // processing unit v the data of unit v + 1 is written to LDS buffer
 // (v + 1) mod 2 and unit v + 3 is loaded into the freed registers; reads of
-// unit v + 1 begin kSR columns before it.  (The forward sweep keeps its
-// register ring of global loads: its FW-wide columns gain nothing from
-// staging, and the scalar loads of its slot bytes would share the LDS wait
-// counter.)
+// unit v + 1 begin kSR columns before it.  The forward sweep reads its slot
+// bytes with vector loads (one chunk ahead, a lane read per four columns),
+// so that no scalar load shares the LDS wait counter with the ring reads.
 // ---------------------------------------------------------------------------
-constexpr int kSU = 32;  // columns per staging unit
-constexpr int kSR = 8;   // LDS-read look-ahead (columns)
+constexpr int kSR = 8;  // LDS-read look-ahead (columns)
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-// 16-byte loads per lane that move one staging unit of W-wide columns
-template <typename T, int W>
-constexpr int stage_loads() {
-  return kSU * W * (int)sizeof(T) / 1024;
-}
-
-template <typename T, int W, int NL>
-__device__ __forceinline__ void stage_load(u32x4 (&r)[NL], const T* __restrict__ A, int unit,
-                                           int lane) {
-  const u32x4* src = (const u32x4*)(A + (size_t)unit * kSU * W);
+// registers of one staging unit of BYTES bytes
+template <int BYTES>
+struct UnitRegs {
+  using V = typename std::conditional<BYTES % 1024 == 0, u32x4, u32x2>::type;
+  static constexpr int NL = BYTES / (64 * (int)sizeof(V));
+  static_assert(NL >= 1 && NL * 64 * (int)sizeof(V) == BYTES, "staging unit size");
+  V r[NL];
+  __device__ __forceinline__ void load(const void* __restrict__ src, int lane) {
 #pragma unroll
-  for (int i = 0; i < NL; ++i) r[i] = src[i * 64 + lane];
-}
-
-template <int NL, typename T>
-__device__ __forceinline__ void stage_store(const u32x4 (&r)[NL], T* dst, int lane) {
+    for (int i = 0; i < NL; ++i) r[i] = ((const V*)src)[i * 64 + lane];
+  }
+  __device__ __forceinline__ void store(void* dst, int lane) const {
 #pragma unroll
-  for (int i = 0; i < NL; ++i) ((u32x4*)dst)[i * 64 + lane] = r[i];
-}
+    for (int i = 0; i < NL; ++i) ((V*)dst)[i * 64 + lane] = r[i];
+  }
+};
 
-// LDS bytes of the factor stage of one wavefront
-template <typename T, int FW, int BW>
+// LDS bytes of the factor stage of one wavefront (forward and backward reuse it)
+template <typename T, int FW, int BW, int SU>
 constexpr int stage_bytes() {
-  return 2 * kSU * BW * (int)sizeof(T);
+  return 2 * SU * (FW > BW ? FW : BW) * (int)sizeof(T);
 }
 
-template <typename T, int BW>
+template <typename T, int FW, int SU>
+__device__ __forceinline__ void sweep_forward_staged(T* b, const T* __restrict__ Lp,
+                                                     const uint32_t* __restrict__ sw, int nch,
+                                                     int lane, T* st) {
+  constexpr int CH = kCH, G = 16, R = kSR, UPC = CH / SU;
+  static_assert(CH % SU == 0 && UPC % 2 == 0 && R <= SU && CH % G == 0 && FW <= 32,
+                "sweep geometry");
+  constexpr int FB = SU * FW * (int)sizeof(T);
+  const int nu = nch * UPC;
+  const int lf = lane & (FW - 1);
+  UnitRegs<FB> r0, r1;  // units in flight (even / odd)
+  r0.load(Lp, lane);
+  r1.load(Lp + (size_t)SU * FW, lane);
+  r0.store(st, lane);
+  if (nu > 2) r0.load(Lp + (size_t)2 * SU * FW, lane);
+  T ring[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) ring[k] = st[k * FW + lf];
+  // slot bytes of a chunk: lane i holds word i mod 16 (columns 4i .. 4i + 3)
+  uint32_t swv = sw[lane & 15];
+  T w = lane < FW ? b[lane] : (T)0;
+  for (int c = 0; c < nch; ++c) {
+    const int j0 = c * CH;
+    const uint32_t swc = swv;
+    if (c + 1 < nch) swv = sw[(j0 + CH) / 4 + (lane & 15)];
+    T* yo = b + j0;
+    T nv[2][G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) nv[0][k] = yo[k + FW];
+#pragma unroll
+    for (int k = 0; k < G; ++k) pin(nv[0][k]);
+    uint32_t word = 0;
+    T yacc = (T)0;  // lane t: y of column j0 + t
+    static_for<0, CH / G>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
+      if (g + 1 < CH / G) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) nv[(g + 1) & 1][k] = yo[(g + 1) * G + k + FW];
+      }
+      static_for<0, G>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int t = g * G + k;
+        if constexpr (t % SU == 0) {
+          // start of unit v = c UPC + t / SU: unit v + 1 to LDS, unit v + 3 requested
+          const int v3 = c * UPC + t / SU + 3;
+          if constexpr ((t / SU + 1) & 1) {
+            r1.store(st + SU * FW, lane);
+            if (v3 < nu) r1.load(Lp + (size_t)v3 * SU * FW, lane);
+          } else {
+            r0.store(st, lane);
+            if (v3 < nu) r0.load(Lp + (size_t)v3 * SU * FW, lane);
+          }
+        }
+        if constexpr ((t & 3) == 0) word = (uint32_t)__builtin_amdgcn_readlane(swc, t >> 2);
+        const int s = (word >> (8 * (t & 3))) & 0xff;
+        const T y = readlane_t(w, s);
+        put_lane<t>(yacc, y);
+        const T l = ring[t % R];
+        constexpr int tn = t + R;  // column read ahead, buffer by its unit's parity
+        ring[t % R] = st[((tn / SU) & 1) * SU * FW + (tn % SU) * FW + lf];
+        w = __builtin_amdgcn_inverse_ballot_w64(1ull << s) ? nv[g & 1][k] : fma(-l, y, w);
+      });
+      if (g + 1 < CH / G) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) pin(nv[(g + 1) & 1][k]);
+      }
+    });
+    yo[lane] = yacc;
+  }
+}
+
+template <typename T, int BW, int SU>
 __device__ __forceinline__ void sweep_backward_staged(T* b, const T* __restrict__ Up, int nch,
                                                       int lane, T* st) {
-  constexpr int CH = kCH, G = 16, R = kSR;
-  static_assert(CH == 2 * kSU && R <= kSU && CH % G == 0 && CH % BW == 0 && BW <= 64,
+  constexpr int CH = kCH, G = 16, R = kSR, UPC = CH / SU;
+  static_assert(CH % SU == 0 && UPC % 2 == 0 && R <= SU && CH % G == 0 && CH % BW == 0 &&
+                    BW <= 64,
                 "sweep geometry");
-  const int npad = nch * CH, nu = 2 * nch;
-  // ---- backward sweep (columns descending; processing index v of unit nu - 1 - v)
-  {
-    const int lb = lane & (BW - 1);
-    constexpr int NL = stage_loads<T, BW>();
-    static_assert(NL >= 1 && kSU * BW * (int)sizeof(T) % 1024 == 0, "staging unit geometry");
-    u32x4 r0[NL], r1[NL];
-    stage_load<T, BW>(r0, Up, nu - 1, lane);
-    stage_load<T, BW>(r1, Up, nu - 2, lane);
-    stage_store(r0, st, lane);
-    if (nu > 2) stage_load<T, BW>(r0, Up, nu - 3, lane);
-    // processing unit v sits in LDS buffer v mod 2; column kSU - 1 - k of unit
-    // nu - 1 is ring entry k
-    T ring[R];
+  constexpr int UB = SU * BW * (int)sizeof(T);
+  const int npad = nch * CH, nu = nch * UPC;
+  // processing index v covers unit nu - 1 - v (columns descending)
+  const int lb = lane & (BW - 1);
+  UnitRegs<UB> r0, r1;
+  r0.load(Up + (size_t)(nu - 1) * SU * BW, lane);
+  r1.load(Up + (size_t)(nu - 2) * SU * BW, lane);
+  r0.store(st, lane);
+  if (nu > 2) r0.load(Up + (size_t)(nu - 3) * SU * BW, lane);
+  // processing unit v sits in LDS buffer v mod 2; column SU - 1 - k of unit
+  // nu - 1 is ring entry k
+  T ring[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) ring[k] = st[(kSU - 1 - k) * BW + lb];
-    // rows npad-BW .. npad-1 (rows >= n hold finite padding; their U
-    // coefficients are zero)
-    T w = b[npad - BW + lb];
-    for (int c = nch - 1; c >= 0; --c) {
-      const int j0 = c * CH;
-      T* xo = b + j0;
-      constexpr int NG = CH / G;
-      T nv[2][G];
+  for (int k = 0; k < R; ++k) ring[k] = st[(SU - 1 - k) * BW + lb];
+  // rows npad-BW .. npad-1 (rows >= n hold finite padding; their U
+  // coefficients are zero)
+  T w = b[npad - BW + lb];
+  for (int c = nch - 1; c >= 0; --c) {
+    const int j0 = c * CH;
+    T* xo = b + j0;
+    constexpr int NG = CH / G;
+    T nv[2][G];
 #pragma unroll
-      for (int k = 0; k < G; ++k) nv[(NG - 1) & 1][k] = xo[(NG - 1) * G + k - BW];
+    for (int k = 0; k < G; ++k) nv[(NG - 1) & 1][k] = xo[(NG - 1) * G + k - BW];
 #pragma unroll
-      for (int k = 0; k < G; ++k) pin(nv[(NG - 1) & 1][k]);
-      T xacc = (T)0;  // lane t: x of column j0 + t
-      static_for<0, NG>([&](auto gc) {
-        constexpr int g = NG - 1 - decltype(gc)::value;
-        if (g > 0) {
+    for (int k = 0; k < G; ++k) pin(nv[(NG - 1) & 1][k]);
+    T xacc = (T)0;  // lane t: x of column j0 + t
+    static_for<0, NG>([&](auto gc) {
+      constexpr int g = NG - 1 - decltype(gc)::value;
+      if (g > 0) {
 #pragma unroll
-          for (int k = 0; k < G; ++k) nv[(g - 1) & 1][k] = xo[(g - 1) * G + k - BW];
-        }
-        static_for<0, G>([&](auto kc) {
-          constexpr int k = G - 1 - decltype(kc)::value;
-          constexpr int t = g * G + k;
-          constexpr int q = CH - 1 - t;  // position in processing order within the chunk
-          if constexpr (q % kSU == 0) {
-            // unit of processing index v = 2 (nch - 1 - c) + q / kSU starts
-            constexpr int h = (q / kSU + 1) & 1;
-            const int v3 = 2 * (nch - 1 - c) + q / kSU + 3;
-            if constexpr (h == 1) {
-              stage_store(r1, st + kSU * BW, lane);
-              if (v3 < nu) stage_load<T, BW>(r1, Up, nu - 1 - v3, lane);
-            } else {
-              stage_store(r0, st, lane);
-              if (v3 < nu) stage_load<T, BW>(r0, Up, nu - 1 - v3, lane);
-            }
+        for (int k = 0; k < G; ++k) nv[(g - 1) & 1][k] = xo[(g - 1) * G + k - BW];
+      }
+      static_for<0, G>([&](auto kc) {
+        constexpr int k = G - 1 - decltype(kc)::value;
+        constexpr int t = g * G + k;
+        constexpr int q = CH - 1 - t;  // position in processing order within the chunk
+        if constexpr (q % SU == 0) {
+          // unit of processing index v = UPC (nch - 1 - c) + q / SU starts
+          const int v3 = UPC * (nch - 1 - c) + q / SU + 3;
+          if constexpr ((q / SU + 1) & 1) {
+            r1.store(st + SU * BW, lane);
+            if (v3 < nu) r1.load(Up + (size_t)(nu - 1 - v3) * SU * BW, lane);
+          } else {
+            r0.store(st, lane);
+            if (v3 < nu) r0.load(Up + (size_t)(nu - 1 - v3) * SU * BW, lane);
           }
-          constexpr int sj = t % BW;
-          constexpr uint64_t msj = BW == 32 ? ((1ull << sj) | (1ull << (sj + 32))) : (1ull << sj);
-          const T u = ring[q % R];
-          constexpr int qn = q + R;  // processing position read ahead
-          ring[q % R] = st[((qn / kSU) & 1) * kSU * BW + (kSU - 1 - qn % kSU) * BW + lb];
-          const T x = readlane_t(w * u, sj);
-          put_lane<t>(xacc, x);
-          w = __builtin_amdgcn_inverse_ballot_w64(msj) ? nv[g & 1][k] : fma(-u, x, w);
-        });
-        if (g > 0) {
-#pragma unroll
-          for (int k = 0; k < G; ++k) pin(nv[(g - 1) & 1][k]);
         }
+        constexpr int sj = t % BW;
+        constexpr uint64_t msj = BW == 32 ? ((1ull << sj) | (1ull << (sj + 32))) : (1ull << sj);
+        const T u = ring[q % R];
+        constexpr int qn = q + R;  // processing position read ahead
+        ring[q % R] = st[((qn / SU) & 1) * SU * BW + (SU - 1 - qn % SU) * BW + lb];
+        const T x = readlane_t(w * u, sj);
+        put_lane<t>(xacc, x);
+        w = __builtin_amdgcn_inverse_ballot_w64(msj) ? nv[g & 1][k] : fma(-u, x, w);
       });
-      xo[lane] = xacc;
-    }
-  }}
+      if (g > 0) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) pin(nv[(g - 1) & 1][k]);
+      }
+    });
+    xo[lane] = xacc;
+  }
+}
+
+// Staged sweeps of the single-block solve: the forward sweep keeps its
+// register ring of global loads (faster at one wavefront per SIMD), the
+// backward sweep stages its BW-wide columns in units of 32.
+constexpr int kSU = 32;
 
 template <typename T, int FW, int BW>
 __device__ __forceinline__ void sweeps_staged(T* b, const T* __restrict__ Lp,
                                               const uint32_t* __restrict__ sw,
                                               const T* __restrict__ Up, int nch, int lane, T* st) {
   sweep_forward<T, FW>(b, Lp, sw, nch, lane);
-  sweep_backward_staged<T, BW>(b, Up, nch, lane, st);
+  sweep_backward_staged<T, BW, kSU>(b, Up, nch, lane, st);
 }
 
 // Right-hand side of the real-scaled system for one pencil, one real part
@@ -586,7 +676,7 @@ __global__ void __launch_bounds__(4 * kWave) solve_kernel(PencilArgs a, int plau
     const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
     const double* Up = Uf + (size_t)p * npad * BW;
     if constexpr (STG) {
-      double* stg = lds + (size_t)4 * span + (size_t)wv * (stage_bytes<double, FW, BW>() / 8);
+      double* stg = lds + (size_t)4 * span + (size_t)wv * (stage_bytes<double, 1, BW, kSU>() / 8);
       sweeps_staged<double, FW, BW>(b, Lp, swp, Up, nch, lane, stg);
     } else {
       sweeps<double, FW, BW>(b, Lp, swp, Up, nch, lane);
@@ -597,6 +687,286 @@ __global__ void __launch_bounds__(4 * kWave) solve_kernel(PencilArgs a, int plau
     write_state(a, bre, bim, X + (size_t)p * S * N, tid & (2 * kWave - 1), 2 * kWave);
   else if (live)
     zero_pencils(X, p, p + 1, S * N, tid & (2 * kWave - 1), 2 * kWave);
+}
+
+// ---------------------------------------------------------------------------
+// Two-block solve (layout in kernels.h, launch_coupling / launch_solve2).
+// ---------------------------------------------------------------------------
+// U(r, c), r <= c, from the rotated column storage (1 / U(c, c) on lane c mod BW)
+__device__ __forceinline__ double u_entry(const double* __restrict__ Up, int BW, int r, int c) {
+  if (r > c || c - r >= BW) return 0.0;
+  if (r == c) return 1.0 / Up[(size_t)c * BW + (c % BW)];
+  return Up[(size_t)c * BW + (r % BW)];
+}
+
+__global__ void __launch_bounds__(kWave) coupling_kernel(
+    PencilArgs t, PencilArgs bt, double a0, double b0, const double* __restrict__ tailLt,
+    const uint8_t* __restrict__ tailPt, const double* __restrict__ tailLb,
+    const uint8_t* __restrict__ tailPb, const double* __restrict__ Uft, const double* __restrict__ Ufb,
+    double* __restrict__ Rinv, double* __restrict__ E1o, double* __restrict__ E2o,
+    int* __restrict__ sing) {
+  extern __shared__ double lds[];
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (!pencil_active(t, p)) return;
+  const PencilCoef pc = pencil_coef(t, p, a0, b0);
+  const int kl = t.kl, ku = t.ku, Q = t.Q, K = kl + ku, m = t.n, n = t.nfull, nb = n - m;
+  double* E1 = lds;          // [Q][ku]
+  double* E2 = E1 + Q * ku;  // [Q][kl]
+  double* R = E2 + Q * kl;   // [K][2K]: [R | I] for Gauss-Jordan
+  __shared__ int piv_s;
+  __shared__ double mult[64];
+  auto opA = [&](int r, int c) -> double {  // entry of the factored operator, whole-system indices
+    if (r < 0 || c < 0 || r >= n || c >= n || c - r > ku || r - c > kl) return 0.0;
+    return t.trans ? sys_entry(t.desc, pc, c, r) : sys_entry(t.desc, pc, r, c);
+  };
+  for (int idx = lane; idx < Q * ku; idx += kWave) {
+    const int i = idx / ku, k = idx - i * ku;
+    E1[idx] = opA(m - Q + i, m + k);
+  }
+  for (int idx = lane; idx < Q * kl; idx += kWave) {
+    const int i = idx / kl, k = idx - i * kl;
+    E2[idx] = opA(n - 1 - (nb - Q + i), m - kl + k);
+  }
+  __syncthreads();
+  // replay the last Q elimination steps of a block on its coupling columns
+  // (one column per lane)
+  auto eliminate = [&](double* E, int ncol, const double* tl, const uint8_t* tp, int klb) {
+    for (int q = 0; q < Q; ++q) {
+      const int off = tp[(size_t)p * Q + q];
+      if (lane < ncol) {
+        if (off) {
+          const double x = E[q * ncol + lane];
+          E[q * ncol + lane] = E[(q + off) * ncol + lane];
+          E[(q + off) * ncol + lane] = x;
+        }
+        const double piv = E[q * ncol + lane];
+        for (int i = 1; i <= klb && q + i < Q; ++i)
+          E[(q + i) * ncol + lane] -= tl[((size_t)p * Q + q) * klb + i - 1] * piv;
+      }
+    }
+  };
+  eliminate(E1, ku, tailLt, tailPt, t.kl);
+  eliminate(E2, kl, tailLb, tailPb, bt.kl);
+  __syncthreads();
+  // interface system [R | I]; unknowns [x1b (kl); yb (ku)], x2t[k] = yb[ku - 1 - k]
+  const double* Ut = Uft + (size_t)p * t.nst * t.BW;
+  const double* Ub = Ufb + (size_t)p * bt.nst * bt.BW;
+  for (int idx = lane; idx < K * 2 * K; idx += kWave) {
+    const int i = idx / (2 * K), c = idx - i * 2 * K;
+    double v = 0.0;
+    if (c >= K) {
+      v = (c - K == i) ? 1.0 : 0.0;
+    } else if (i < kl) {
+      if (c < kl) v = u_entry(Ut, t.BW, m - kl + i, m - kl + c);
+      else v = E1[(Q - kl + i) * ku + (ku - 1 - (c - kl))];
+    } else {
+      const int ib = i - kl;
+      if (c < kl) v = E2[(Q - ku + ib) * kl + c];
+      else v = u_entry(Ub, bt.BW, nb - ku + ib, nb - ku + (c - kl));
+    }
+    R[idx] = v;
+  }
+  __syncthreads();
+  // Gauss-Jordan with partial pivoting
+  for (int c = 0; c < K; ++c) {
+    double mag = -1.0;
+    int idx = c;
+    if (lane < K - c) {
+      mag = fabs(R[(c + lane) * 2 * K + c]);
+      idx = c + lane;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double om = __shfl_xor(mag, off);
+      const int oi = __shfl_xor(idx, off);
+      if (om > mag || (om == mag && oi < idx)) {
+        mag = om;
+        idx = oi;
+      }
+    }
+    if (lane == 0) piv_s = idx;
+    __syncthreads();
+    const int pr = piv_s;
+    if (pr != c)
+      for (int q = lane; q < 2 * K; q += kWave) {
+        const double x = R[c * 2 * K + q];
+        R[c * 2 * K + q] = R[pr * 2 * K + q];
+        R[pr * 2 * K + q] = x;
+      }
+    __syncthreads();
+    double pv = R[c * 2 * K + c];
+    if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
+      if (lane == 0) atomicMin(sing, p);
+      pv = 1.0;
+    }
+    const double rp = 1.0 / pv;
+    __syncthreads();
+    for (int q = lane; q < 2 * K; q += kWave) R[c * 2 * K + q] *= rp;
+    __syncthreads();
+    if (lane < K) mult[lane] = lane == c ? 0.0 : R[lane * 2 * K + c];
+    __syncthreads();
+    for (int i2 = lane; i2 < K * 2 * K; i2 += kWave) {
+      const int i = i2 / (2 * K), q = i2 - i * 2 * K;
+      R[i2] -= mult[i] * R[c * 2 * K + q];
+    }
+    __syncthreads();
+  }
+  for (int idx = lane; idx < K * K; idx += kWave) {
+    const int i = idx / K, c = idx - i * K;
+    Rinv[(size_t)p * K * K + idx] = R[i * 2 * K + K + c];
+  }
+  for (int idx = lane; idx < Q * ku; idx += kWave) E1o[(size_t)p * Q * ku + idx] = E1[idx];
+  for (int idx = lane; idx < Q * kl; idx += kWave) E2o[(size_t)p * Q * kl + idx] = E2[idx];
+}
+
+constexpr int kSU2 = 16;  // staging unit of the two-block solve (two blocks per compute unit)
+
+// LDS doubles of a pencil's coupling data (Rinv, E1, E2), rounded to 16 bytes
+__host__ __device__ inline int solve2_coupling_doubles(int K, int Q) { return (K * K + Q * K + 1) / 2 * 2; }
+
+// Two-block solve: one pencil per block of four wavefronts, wave 2 half + part
+// (half 0: leading block, 1: trailing block; part: real / imaginary).
+template <int FWT, int BWT, int FWB, int BWB>
+__global__ void __launch_bounds__(4 * kWave) solve2_kernel(
+    PencilArgs t, PencilArgs bt, int plaunch, const double2* __restrict__ Bev,
+    const double* __restrict__ Lft, const uint8_t* __restrict__ slt, const double* __restrict__ Uft,
+    const double* __restrict__ Lfb, const uint8_t* __restrict__ slb, const double* __restrict__ Ufb,
+    const double* __restrict__ Rinv, const double* __restrict__ E1, const double* __restrict__ E2,
+    double2* __restrict__ X) {
+  extern __shared__ double lds[];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int part = wv & 1, half = wv >> 1;
+  const SysDesc& d = t.desc;
+  const int N = d.N, S = d.S, ne = d.ne, kb = d.kb;
+  const int n = t.nfull, m = t.n, nb = bt.n, kl = t.kl, ku = t.ku, Q = t.Q, K = kl + ku;
+  if (blockIdx.x == 0 && plaunch < t.P) zero_pencils(X, plaunch, t.P, S * N, tid, 4 * kWave);
+  double2* Xp = X + (size_t)p * S * N;
+  if (!pencil_active(t, p)) {
+    zero_pencils(X, p, p + 1, S * N, tid, 4 * kWave);
+    return;
+  }
+  const PencilCoef pc = pencil_coef(t, p, 0.0, 0.0);
+  const int spanT = BWT + t.nst + FWT, spanB = BWB + bt.nst + FWB;
+  double* vt0 = lds + BWT;
+  double* vt1 = vt0 + spanT;
+  double* vb0 = lds + 2 * spanT + BWB;
+  double* vb1 = vb0 + spanB;
+  double* z = lds + 2 * spanT + 2 * spanB;  // [2][K]
+  double* cR = z + 2 * 64;                  // coupling data: Rinv [K][K], E1 [Q][ku], E2 [Q][kl]
+  double* cE1 = cR + K * K;
+  double* cE2 = cE1 + Q * ku;
+  constexpr int SB = stage_bytes<double, (FWT > FWB ? FWT : FWB), (BWT > BWB ? BWT : BWB), kSU2>() / 8;
+  double* stg = cR + solve2_coupling_doubles(K, Q) + (size_t)wv * SB;
+  double* v = half == 0 ? (part == 0 ? vt0 : vt1) : (part == 0 ? vb0 : vb1);
+  // the pencil's coupling data, loaded now and stored to LDS after the
+  // right-hand side (needed after the forward sweeps)
+  constexpr int kCpl = 8;  // coupling doubles per thread (K K + Q (kl + ku) <= 8 * 256)
+  double cpl[kCpl];
+  {
+    const int nR = K * K, nE1 = Q * ku, nE2 = Q * kl;
+#pragma unroll
+    for (int u = 0; u < kCpl; ++u) {
+      const int i = tid + u * 4 * kWave;
+      cpl[u] = 0.0;
+      if (i < nR) cpl[u] = Rinv[(size_t)p * nR + i];
+      else if (i < nR + nE1) cpl[u] = E1[(size_t)p * nE1 + i - nR];
+      else if (i < nR + nE1 + nE2) cpl[u] = E2[(size_t)p * nE2 + i - nR - nE1];
+    }
+  }
+  // right-hand side: zero fill (boundary values in the leading block), then
+  // the evolved entries scattered to their rows (whole row R: leading block R,
+  // trailing block n - 1 - R)
+  {
+    const int BWx = half == 0 ? BWT : BWB, FWx = half == 0 ? FWT : FWB;
+    const int npad = half == 0 ? t.nst : bt.nst;
+    for (int r = lane - BWx; r < npad + FWx; r += kWave) {
+      double val = 0.0;
+      if (half == 0 && part == 0 && r >= 0 && r < kb && pc.mean && d.bc_var[r] == VB)
+        val = d.bc_side[r] == 0 ? t.b_bottom : t.b_top;
+      v[r] = val;
+    }
+    const double2* Bp = Bev + (size_t)p * ne * N;
+    // modes whose rows can fall in this half (row kb + mo S + pos, pos < S)
+    const int mcut = (m - kb) / S;
+    const int mlo = half == 0 ? 0 : (mcut > 0 ? mcut - 1 : 0);
+    const int mhi = half == 0 ? (mcut + 1 < N - 1 ? mcut + 1 : N - 1) : N - 1;
+    const int Nm = mhi - mlo;
+    for (int i = lane; i < ne * Nm; i += kWave) {
+      const int e = i / Nm, mo = mlo + (i - e * Nm);
+      const int eq = e == 0 ? EB : (e == ne - 1 ? EW : (e == 1 ? EU : EV));
+      const int Rw = kb + mo * S + d.eq_pos[eq];
+      if ((half == 0) != (Rw < m)) continue;
+      const double2 b2 = Bp[e * N + mo];
+      const bool scaled = eq == EU || eq == EV;  // row scaled by i
+      v[half == 0 ? Rw : n - 1 - Rw] = part == 0 ? (scaled ? -b2.y : b2.x) : (scaled ? b2.x : b2.y);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kCpl; ++u) {
+    const int i = tid + u * 4 * kWave;
+    if (i < solve2_coupling_doubles(K, Q)) cR[i] = cpl[u];
+  }
+  if (half == 0)
+    sweep_forward_staged<double, FWT, kSU2>(v, Lft + (size_t)p * t.nst * FWT,
+                                            (const uint32_t*)(slt + (size_t)p * t.nst), t.nst / kCH,
+                                            lane, stg);
+  else
+    sweep_forward_staged<double, FWB, kSU2>(v, Lfb + (size_t)p * bt.nst * FWB,
+                                            (const uint32_t*)(slb + (size_t)p * bt.nst), bt.nst / kCH,
+                                            lane, stg);
+  __syncthreads();
+  if (half == 0 && lane < K) {
+    // interface system of this part: z = Rinv [g1b; g2b]
+    const double* Rp = cR + lane * K;
+    const double* g1 = part == 0 ? vt0 : vt1;
+    const double* g2 = part == 0 ? vb0 : vb1;
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) acc = fma(Rp[k], k < kl ? g1[m - kl + k] : g2[nb - ku + (k - kl)], acc);
+    z[part * 64 + lane] = acc;
+  }
+  __syncthreads();
+  if (lane < Q) {
+    if (half == 0) {
+      // g1[m - Q + i] -= sum_k E1[i][k] x2t[k],  x2t[k] = yb[ku - 1 - k]
+      const double* Ep = cE1 + lane * ku;
+      double acc = 0.0;
+      for (int k = 0; k < ku; ++k) acc = fma(Ep[k], z[part * 64 + kl + ku - 1 - k], acc);
+      v[m - Q + lane] -= acc;
+    } else {
+      const double* Ep = cE2 + lane * kl;
+      double acc = 0.0;
+      for (int k = 0; k < kl; ++k) acc = fma(Ep[k], z[part * 64 + k], acc);
+      v[nb - Q + lane] -= acc;
+    }
+  }
+  if (half == 0)
+    sweep_backward_staged<double, BWT, kSU2>(v, Uft + (size_t)p * t.nst * BWT, t.nst / kCH, lane, stg);
+  else
+    sweep_backward_staged<double, BWB, kSU2>(v, Ufb + (size_t)p * bt.nst * BWB, bt.nst / kCH, lane, stg);
+  __syncthreads();
+  // X = P^R x~ (x~ row c: leading block for c < m, else the reversed trailing block)
+  for (int i = tid; i < S * N; i += 4 * kWave) {
+    const int vabi = i / N, mo = i - vabi * N;
+    const int var = t.var_of_abi[vabi];
+    const int pos = d.var_pos[var];
+    auto xt = [&](int pp, int c) -> double {
+      return c < m ? (pp == 0 ? vt0 : vt1)[c] : (pp == 0 ? vb0 : vb1)[n - 1 - c];
+    };
+    const int c0 = mo * S + pos;
+    double xr = xt(0, c0), xi = xt(1, c0);
+    if (mo + 2 < N) {
+      xr -= xt(0, c0 + 2 * S);
+      xi -= xt(1, c0 + 2 * S);
+    }
+    if (var == VU || var == VUZ || var == VV || var == VVZ)
+      Xp[i] = make_double2(xi, -xr);  // u = -i u~
+    else
+      Xp[i] = make_double2(xr, xi);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -838,7 +1208,7 @@ __global__ void __launch_bounds__(4 * kWave) solve_mixed_kernel(
     const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
     const float* Up = Uf + (size_t)p * npad * BW;
     float* stg = (float*)(lds + 2 * mixed_pencil_doubles(n, span)) +
-                 (size_t)wv * (stage_bytes<float, FW, BW>() / 4);
+                 (size_t)wv * (stage_bytes<float, 1, BW, kSU>() / 4);
     auto sweep = [&]() {
       if constexpr (STG)
         sweeps_staged<float, FW, BW>(w, Lp, swp, Up, nch, lane, stg);
@@ -880,10 +1250,11 @@ int factor_stride(int n) { return (n + kCH - 1) / kCH * kCH; }
 int factor_slack() { return kRing; }
 
 hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, uint8_t* sl,
-                         double* Uf, int* sing, hipStream_t st) {
+                         double* Uf, int* sing, hipStream_t st, double* tailL, uint8_t* tailP) {
   const int kv = a.kl + a.ku, ld = kv + a.kl + 1;
   size_t lds = (size_t)kCW * ld * sizeof(double);
-  hipLaunchKernelGGL(factor_kernel, dim3(a.P), dim3(kWave), lds, st, a, a0, b0, Lf, sl, Uf, sing);
+  hipLaunchKernelGGL(factor_kernel, dim3(a.P), dim3(kWave), lds, st, a, a0, b0, Lf, sl, Uf, sing,
+                     tailL, tailP);
   return hipGetLastError();
 }
 
@@ -934,7 +1305,7 @@ template <int FW, int BW>
 static hipError_t launch_solve_t(const PencilArgs& a, const void* Bev, const double* Lf,
                                  const uint8_t* sl, const double* Uf, void* X, hipStream_t st) {
   const PencilGrid g = pencil_grid(a, (size_t)2 * (BW + a.nst + FW) * sizeof(double),
-                                   (size_t)4 * stage_bytes<double, FW, BW>());
+                                   (size_t)4 * stage_bytes<double, 1, BW, kSU>());
   if (g.staged) {
     allow_lds((const void*)solve_kernel<FW, BW, true>, g.lds);
     hipLaunchKernelGGL((solve_kernel<FW, BW, true>), dim3(g.blocks), dim3(4 * kWave), g.lds, st, a,
@@ -956,13 +1327,69 @@ hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, 
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_coupling(const PencilArgs& t, const PencilArgs& bt, double a0, double b0,
+                           const double* tailLt, const uint8_t* tailPt, const double* tailLb,
+                           const uint8_t* tailPb, const double* Uft, const double* Ufb,
+                           double* Rinv, double* E1, double* E2, int* sing, hipStream_t st) {
+  const int K = t.kl + t.ku;
+  if (K > 64 || t.Q != K) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(t.Q * (t.kl + t.ku) + K * 2 * K) * sizeof(double);
+  allow_lds((const void*)coupling_kernel, lds);
+  hipLaunchKernelGGL(coupling_kernel, dim3(t.P), dim3(kWave), lds, st, t, bt, a0, b0, tailLt, tailPt,
+                     tailLb, tailPb, Uft, Ufb, Rinv, E1, E2, sing);
+  return hipGetLastError();
+}
+
+template <int FWT, int BWT, int FWB, int BWB>
+static hipError_t launch_solve2_t(const PencilArgs& t, const PencilArgs& bt, const void* Bev,
+                                  const double* Lft, const uint8_t* slt, const double* Uft,
+                                  const double* Lfb, const uint8_t* slb, const double* Ufb,
+                                  const double* Rinv, const double* E1, const double* E2, void* X,
+                                  hipStream_t st) {
+  const int plaunch = t.desc.dim == 2 ? t.Px - 1 : t.P;
+  constexpr int SB = stage_bytes<double, (FWT > FWB ? FWT : FWB), (BWT > BWB ? BWT : BWB), kSU2>();
+  const int K = t.kl + t.ku;
+  if (K * K + t.Q * K > 8 * 4 * kWave) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(2 * (BWT + t.nst + FWT) + 2 * (BWB + bt.nst + FWB) + 2 * 64 +
+                              solve2_coupling_doubles(K, t.Q)) * sizeof(double) + (size_t)4 * SB;
+  auto fn = solve2_kernel<FWT, BWT, FWB, BWB>;
+  allow_lds((const void*)fn, lds);
+  hipLaunchKernelGGL(fn, dim3(plaunch), dim3(4 * kWave), lds, st, t, bt, plaunch, (const double2*)Bev,
+                     Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, E2, (double2*)X);
+  return hipGetLastError();
+}
+
+#define STAU_SOLVE2_VARIANTS(X) X(8, 32, 32, 32) X(16, 32, 32, 32)
+
+bool solve2_supported(const PencilArgs& t, const PencilArgs& bt) {
+#define STAU_CASE2(FT, BT, FB, BB) \
+  if (t.FW == FT && t.BW == BT && bt.FW == FB && bt.BW == BB) return true;
+  STAU_SOLVE2_VARIANTS(STAU_CASE2)
+#undef STAU_CASE2
+  return false;
+}
+
+hipError_t launch_solve2(const PencilArgs& t, const PencilArgs& bt, const void* Bev,
+                         const double* Lft, const uint8_t* slt, const double* Uft,
+                         const double* Lfb, const uint8_t* slb, const double* Ufb,
+                         const double* Rinv, const double* E1, const double* E2, void* X,
+                         hipStream_t st) {
+#define STAU_CASE2(FT, BT, FB, BB)                                                             \
+  if (t.FW == FT && t.BW == BT && bt.FW == FB && bt.BW == BB)                                  \
+    return launch_solve2_t<FT, BT, FB, BB>(t, bt, Bev, Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, \
+                                           E2, X, st);
+  STAU_SOLVE2_VARIANTS(STAU_CASE2)
+#undef STAU_CASE2
+  return hipErrorInvalidValue;
+}
+
 template <int FW, int BW>
 static hipError_t launch_solve_mixed_t(const PencilArgs& a, double a0, double b0, const void* Bev,
                                        const float* Lf, const uint8_t* sl, const float* Uf,
                                        void* X, hipStream_t st) {
   const int span = BW + a.nst + FW;
   const PencilGrid g = pencil_grid(a, mixed_pencil_doubles(a.n, span) * sizeof(double),
-                                   (size_t)4 * stage_bytes<float, FW, BW>());
+                                   (size_t)4 * stage_bytes<float, 1, BW, kSU>());
   if (g.staged) {
     allow_lds((const void*)solve_mixed_kernel<FW, BW, true>, g.lds);
     hipLaunchKernelGGL((solve_mixed_kernel<FW, BW, true>), dim3(g.blocks), dim3(4 * kWave), g.lds,

@@ -389,9 +389,12 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
 //               w_y, w_z                                     -> N_b, N_u, N_v, N_w
 // Each pair's half spectrum is loaded into registers one pair ahead of its
 // transform; with TWL the twiddle table is staged in LDS once per block.
-// Thread t owns grid points t + q NT, q < PTS.
+// Thread t owns grid points t + q NT, q < PTS.  SPLIT (2-D, for launches with
+// fewer rows than compute units): two blocks per row, blockIdx.y = 0 forms
+// N_b and N_u from the pairs (u, w), (b_x, b_z), (u_x, u_z), blockIdx.y = 1
+// forms N_w from (u, w), (w_x, w_z).
 // ---------------------------------------------------------------------------
-template <int DIM, int NT, int PTS, int MAXBF, bool TWL, typename T>
+template <int DIM, int NT, int PTS, int MAXBF, bool TWL, typename T, bool SPLIT = false>
 __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
                                                   const typename V2<T>::type* __restrict__ G,
                                                   typename V2<T>::type* __restrict__ H) {
@@ -454,11 +457,17 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
   };
 
   T u[PTS], v[PTS], w[PTS], nb[PTS], nu[PTS], nv[PTS], nw[PTS];
+  // pairs of this block: all NP, or for SPLIT (0, 1, 2) / (0, 3)
+  const int part = SPLIT ? (int)blockIdx.y : 0;
+  const int npr = SPLIT ? (part == 0 ? 3 : 2) : NP;
+  auto pair_of = [&](int k) { return SPLIT && part == 1 && k == 1 ? 3 : k; };
   fetch(0);
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
+    if (k >= npr) break;
+    const int pk = pair_of(k);
     scatter();
-    if (k + 1 < NP) fetch(k + 1);
+    if (k + 1 < npr) fetch(pair_of(k + 1));
     __syncthreads();
     fft_lds<+1, MAXBF, T, DIM == 2>(buf, L, 1, tw, tid, NT);
 #pragma unroll
@@ -467,10 +476,10 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
       if (i < L) {
         const T x = buf[i].x, y = buf[i].y;  // the pair's two real fields at point i
         if constexpr (DIM == 2) {
-          if (k == 0) { u[q] = x; w[q] = y; }
-          if (k == 1) nb[q] = -(u[q] * x + w[q] * y);
-          if (k == 2) nu[q] = -(u[q] * x + w[q] * y);
-          if (k == 3) nw[q] = -(u[q] * x + w[q] * y);
+          if (pk == 0) { u[q] = x; w[q] = y; }
+          if (pk == 1) nb[q] = -(u[q] * x + w[q] * y);
+          if (pk == 2) nu[q] = -(u[q] * x + w[q] * y);
+          if (pk == 3) nw[q] = -(u[q] * x + w[q] * y);
         } else {
           if (k == 0) { u[q] = x; v[q] = y; }
           if (k == 1) { w[q] = x; nb[q] = -(u[q] * y); }
@@ -516,11 +525,13 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
     }
     __syncthreads();
   };
-  r2c(nb, nu, 0, 1);
-  if constexpr (DIM == 2)
-    r2c(nw, nullptr, 2, -1);
-  else
+  if constexpr (DIM == 2) {
+    if (!SPLIT || part == 0) r2c(nb, nu, 0, 1);
+    if (!SPLIT || part == 1) r2c(nw, nullptr, 2, -1);
+  } else {
+    r2c(nb, nu, 0, 1);
     r2c(nv, nw, 2, 3);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1097,14 +1108,20 @@ static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipS
   const int rows = a.M * (DIM == 2 ? 1 : a.Ngy);
   const bool twl = (size_t)a.L * sizeof(S2) <= 32768;
   const size_t lds = (size_t)a.L * sizeof(S2) * (twl ? 2 : 1);
+  // 2-D rows fewer than compute units: two blocks per row
+  int dev = 0, cus = 0;
+  const bool split = DIM == 2 && hipGetDevice(&dev) == hipSuccess &&
+                     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                     rows < cus;
+  const dim3 grid(rows, split ? 2 : 1);
   if (twl) {
-    auto fn = xrow_kernel<DIM, NT, PTS, MAXBF, true, T>;
+    auto fn = split ? xrow_kernel<DIM, NT, PTS, MAXBF, true, T, true> : xrow_kernel<DIM, NT, PTS, MAXBF, true, T, false>;
     allow_lds((const void*)fn, lds);
-    hipLaunchKernelGGL(fn, dim3(rows), dim3(NT), lds, st, a, (const S2*)G, (S2*)H);
+    hipLaunchKernelGGL(fn, grid, dim3(NT), lds, st, a, (const S2*)G, (S2*)H);
   } else {
-    auto fn = xrow_kernel<DIM, NT, PTS, MAXBF, false, T>;
+    auto fn = split ? xrow_kernel<DIM, NT, PTS, MAXBF, false, T, true> : xrow_kernel<DIM, NT, PTS, MAXBF, false, T, false>;
     allow_lds((const void*)fn, lds);
-    hipLaunchKernelGGL(fn, dim3(rows), dim3(NT), lds, st, a, (const S2*)G, (S2*)H);
+    hipLaunchKernelGGL(fn, grid, dim3(NT), lds, st, a, (const S2*)G, (S2*)H);
   }
   return hipGetLastError();
 }

@@ -15,6 +15,11 @@ struct PencilArgs {
   int n, kl, ku, FW, BW;
   int nst;    // factor columns stored per pencil (n rounded up to the sweep chunk; zero beyond n)
   int trans;  // 1: the factors are those of the transposed matrix
+  // two-block solve: blk 0 = the whole system; 1 = the leading block (rows
+  // and columns 0 .. n-1 of the whole system of size nfull); 2 = the trailing
+  // block in reversed order (block index i <-> whole index nfull - 1 - i).
+  // Q = kl + ku of the whole operator.
+  int blk, nfull, Q;
 
   int P, Px, Ny;
   double kappa, nu, buoyancy, b_bottom, b_top;
@@ -71,7 +76,30 @@ struct AccList {
 int factor_stride(int n);
 int factor_slack();
 hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, uint8_t* sl,
-                         double* Uf, int* sing, hipStream_t st);
+                         double* Uf, int* sing, hipStream_t st, double* tailL = nullptr,
+                         uint8_t* tailP = nullptr);
+// Two-block solve (2-D): the whole operator A (band kl, ku) split at m into the
+// leading block T and the trailing block B (factored in reversed order), each
+// with its own banded LU; with A12 = A[0:m, m:m+ku] and A21 = A[m:n, m-kl:m],
+//   E1 = L_T^{-1} P_T A12 (last Q rows),  E2 = L_B^{-1} P_B J A21 (last Q rows),
+// and Rinv the inverse of the (kl + ku) x (kl + ku) interface system
+//   [U_T(last kl)  E1 J; E2  U_B(last ku)].
+// launch_coupling forms E1 [P][Q][ku], E2 [P][Q][kl] and Rinv [P][K][K] from
+// the replayed last-Q elimination steps of both factorizations (tailL / tailP
+// of launch_factor) and the stored U factors.  t / bt are the block
+// descriptions (blk 1 / 2).
+hipError_t launch_coupling(const PencilArgs& t, const PencilArgs& bt, double a0, double b0,
+                           const double* tailLt, const uint8_t* tailPt, const double* tailLb,
+                           const uint8_t* tailPb, const double* Uft, const double* Ufb,
+                           double* Rinv, double* E1, double* E2, int* sing, hipStream_t st);
+// Whole-system solve from the two blocks: forward sweeps of both blocks in
+// parallel, the interface system, the corrections, backward sweeps.
+hipError_t launch_solve2(const PencilArgs& t, const PencilArgs& bt, const void* Bev,
+                         const double* Lft, const uint8_t* slt, const double* Uft,
+                         const double* Lfb, const uint8_t* slb, const double* Ufb,
+                         const double* Rinv, const double* E1, const double* E2, void* X,
+                         hipStream_t st);
+bool solve2_supported(const PencilArgs& t, const PencilArgs& bt);
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
                         const double* Uf, void* X, hipStream_t st);
 

@@ -170,15 +170,25 @@ struct stau_pencils {
     double* Uf = nullptr;
     float* Lf32 = nullptr;  // mixed precision: FP32 copies of the FP64 factors
     float* Uf32 = nullptr;
+    // two-block solve: factors of the leading (T) and trailing (B) blocks,
+    // their last-Q elimination steps and the coupling data
+    double *LTraw = nullptr, *UTraw = nullptr, *LBraw = nullptr, *UBraw = nullptr;
+    uint8_t *sTraw = nullptr, *sBraw = nullptr;
+    double *LfT = nullptr, *UfT = nullptr, *LfB = nullptr, *UfB = nullptr;
+    uint8_t *slT = nullptr, *slB = nullptr;
+    double *tLt = nullptr, *tLb = nullptr, *Rinv = nullptr, *E1 = nullptr, *E2 = nullptr;
+    uint8_t *tPt = nullptr, *tPb = nullptr;
     bool valid = false;
     double a0 = 0.0, b0 = 0.0;
     int64_t stamp = 0;
   } slot[2], slotT[2];    // slotT: factors of the transposed matrices (adjoint)
   PencilArgs paT{};       // band description of the transposed system
+  // two-block solve of the forward system (FP64, 2-D, at most two blocks per
+  // compute unit): leading / trailing block descriptions
+  bool two = false;
+  PencilArgs pt{}, pb{};
   int64_t clock = 0;
-  double* Lf = nullptr;     // factors of the most recent stau_factor (aliases a slot)
-  uint8_t* sl = nullptr;
-  double* Uf = nullptr;
+  FactorSlot* last = nullptr;  // factors of the most recent stau_factor
   int* sing = nullptr;     // device: first singular pencil (INT_MAX if none)
   int* flag = nullptr;     // device: non-finite flag
   double* scratch = nullptr;
@@ -469,6 +479,10 @@ static void free_pencils(stau_pencils* p) {
       hipFree(f.Uraw);
       hipFree(f.L32raw);
       hipFree(f.U32raw);
+      for (void* q : {(void*)f.LTraw, (void*)f.UTraw, (void*)f.LBraw, (void*)f.UBraw, (void*)f.sTraw,
+                      (void*)f.sBraw, (void*)f.tLt, (void*)f.tLb, (void*)f.Rinv, (void*)f.E1,
+                      (void*)f.E2, (void*)f.tPt, (void*)f.tPb})
+        (void)hipFree(q);
       f = stau_pencils::FactorSlot{};
     }
   hipFree(p->sing);
@@ -506,6 +520,42 @@ static hipError_t alloc_slot(stau_pencils::FactorSlot& f, const PencilArgs& pa, 
 }
 
 // Solve window widths for a band: FW >= kl + 1 (8, 16, 32), BW >= kl + ku + 1 (32, 64).
+// Allocate (zeroed) two-block factor storage: both blocks' factors (with
+// slack), their last-Q steps and the coupling data.
+static hipError_t alloc_slot2(stau_pencils::FactorSlot& f, const PencilArgs& pt, const PencilArgs& pb,
+                              size_t* bytes) {
+  const size_t sk = (size_t)factor_slack();
+  const size_t P = (size_t)pt.P, Q = (size_t)pt.Q, K = (size_t)(pt.kl + pt.ku);
+  const size_t cT = P * pt.nst + 2 * sk, cB = P * pb.nst + 2 * sk;
+  hipError_t e = hipSuccess;
+  auto get = [&](void** ptr, size_t nb) {
+    if (e == hipSuccess) e = hipMalloc(ptr, nb);
+    if (e == hipSuccess) e = hipMemset(*ptr, 0, nb);
+    *bytes += nb;
+  };
+  get((void**)&f.LTraw, cT * pt.FW * sizeof(double));
+  get((void**)&f.UTraw, cT * pt.BW * sizeof(double));
+  get((void**)&f.sTraw, cT);
+  get((void**)&f.LBraw, cB * pb.FW * sizeof(double));
+  get((void**)&f.UBraw, cB * pb.BW * sizeof(double));
+  get((void**)&f.sBraw, cB);
+  get((void**)&f.tLt, P * Q * pt.kl * sizeof(double));
+  get((void**)&f.tLb, P * Q * pb.kl * sizeof(double));
+  get((void**)&f.tPt, P * Q);
+  get((void**)&f.tPb, P * Q);
+  get((void**)&f.Rinv, P * K * K * sizeof(double));
+  get((void**)&f.E1, P * Q * pt.ku * sizeof(double));
+  get((void**)&f.E2, P * Q * pt.kl * sizeof(double));
+  if (e != hipSuccess) return e;
+  f.LfT = f.LTraw + sk * pt.FW;
+  f.UfT = f.UTraw + sk * pt.BW;
+  f.slT = f.sTraw + sk;
+  f.LfB = f.LBraw + sk * pb.FW;
+  f.UfB = f.UBraw + sk * pb.BW;
+  f.slB = f.sBraw + sk;
+  return hipSuccess;
+}
+
 static bool window_widths(PencilArgs& pa) {
   pa.FW = pa.kl + 1 <= 8 ? 8 : (pa.kl + 1 <= 16 ? 16 : 32);
   pa.BW = (pa.kl + pa.ku + 1 <= 32) ? 32 : 64;
@@ -552,6 +602,45 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   if (!window_widths(paT)) {
     delete pen;
     return fail(STAU_EUNSUPPORTED, "transposed band too wide (kl=%d, ku=%d)", paT.kl, paT.ku);
+  }
+  // Two-block solve for FP64 2-D domains with at most two pencils per compute
+  // unit: the system splits at m = kb + S k near n / 2 (a leading block that
+  // ends inside a mode is singular) into two halves swept in parallel.
+  if (d.dim == 2 && d.precision == STAU_FP64) {
+    const int Q = pa.kl + pa.ku, S = pa.desc.S, kb = pa.desc.kb;
+    // the trailing block's forward sweep (FW = 32) runs slower per column:
+    // its share of the rows is about 48 %
+    const int m = kb + S * (int)((0.52 * pa.n - kb) / S), nb = pa.n - m;
+    int dev = 0, cus = 0, lds_cu = 0;
+    if (m >= Q + 64 && nb >= Q + 64 && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+            hipSuccess) {
+      PencilArgs& t = pen->pt;
+      PencilArgs& b = pen->pb;
+      t = pa;
+      t.blk = 1;
+      t.nfull = pa.n;
+      t.n = m;
+      t.Q = Q;
+      t.nst = factor_stride(m);
+      b = pa;
+      b.blk = 2;
+      b.nfull = pa.n;
+      b.n = nb;
+      b.Q = Q;
+      b.kl = pa.ku;
+      b.ku = pa.kl;
+      b.nst = factor_stride(nb);
+      const bool ok = window_widths(t) && window_widths(b) && solve2_supported(t, b);
+      // LDS of one two-block solve block (as launch_solve2 sizes it): two
+      // blocks must fit a compute unit
+      const int FWm = t.FW > b.FW ? t.FW : b.FW, BWm = t.BW > b.BW ? t.BW : b.BW;
+      const size_t lds = (size_t)(2 * (t.BW + t.nst + t.FW) + 2 * (b.BW + b.nst + b.FW) + 128 +
+                                  (Q * Q + Q * Q + 1) / 2 * 2) * 8 +
+                         (size_t)4 * 2 * 16 * (FWm > BWm ? FWm : BWm) * 8;
+      pen->two = ok && dom->Pa <= 2 * cus && 2 * lds <= (size_t)lds_cu;
+    }
   }
 
   XformArgs& xa = pen->xa;
@@ -640,7 +729,7 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   const bool mixed = d.precision == STAU_MIXED;
   size_t szF = 0;
   for (auto& f : pen->slot)
-    if (e == hipSuccess) e = alloc_slot(f, pa, mixed, &szF);
+    if (e == hipSuccess) e = pen->two ? alloc_slot2(f, pen->pt, pen->pb, &szF) : alloc_slot(f, pa, mixed, &szF);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->sing, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->flag, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->scratch, szScratch);
@@ -704,8 +793,16 @@ static int factor_into(stau_pencils* pen, stau_pencils::FactorSlot* set, const P
   f.valid = false;
   const int big = 0x7fffffff;
   HIP_TRY(hipMemcpyAsync(pen->sing, &big, sizeof(int), hipMemcpyHostToDevice, st));
+  const bool two = pen->two && set == pen->slot;
   HIP_TRY(timed(pen, K_FACTOR, st, [&] {
-    return launch_factor(pa, a0, b0, f.Lf, f.sl, f.Uf, pen->sing, st);
+    if (!two) return launch_factor(pa, a0, b0, f.Lf, f.sl, f.Uf, pen->sing, st);
+    hipError_t e = launch_factor(pen->pt, a0, b0, f.LfT, f.slT, f.UfT, pen->sing, st, f.tLt, f.tPt);
+    if (e == hipSuccess)
+      e = launch_factor(pen->pb, a0, b0, f.LfB, f.slB, f.UfB, pen->sing, st, f.tLb, f.tPb);
+    if (e == hipSuccess)
+      e = launch_coupling(pen->pt, pen->pb, a0, b0, f.tLt, f.tPt, f.tLb, f.tPb, f.UfT, f.UfB, f.Rinv,
+                          f.E1, f.E2, pen->sing, st);
+    return e;
   }));
   int h = big;
   HIP_TRY(hipMemcpyAsync(&h, pen->sing, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -764,9 +861,7 @@ int stau_factor(stau_pencils* pen, double a0, double b0, void* stream) {
   for (int q = 0; q < 2; ++q)
     if (pen->slot[q].valid && pen->slot[q].a0 == a0 && pen->slot[q].b0 == b0) k = q;
   int rc = factor_into(pen, pen->slot, pen->pa, k, a0, b0, st);
-  pen->Lf = rc ? nullptr : pen->slot[k].Lf;
-  pen->sl = rc ? nullptr : pen->slot[k].sl;
-  pen->Uf = rc ? nullptr : pen->slot[k].Uf;
+  pen->last = rc ? nullptr : &pen->slot[k];
   return rc;
 }
 
@@ -851,6 +946,9 @@ int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
   HIP_TRY(timed(pen, K_SOLVE, st, [&] {
     if (mixed)
       return launch_solve_mixed(pen->pa, a0, b0, pen->Bev, fs->Lf32, fs->sl, fs->Uf32, s->X, st);
+    if (pen->two)
+      return launch_solve2(pen->pt, pen->pb, pen->Bev, fs->LfT, fs->slT, fs->UfT, fs->LfB, fs->slB,
+                           fs->UfB, fs->Rinv, fs->E1, fs->E2, s->X, st);
     return launch_solve(pen->pa, pen->Bev, fs->Lf, fs->sl, fs->Uf, s->X, st);
   }));
   s->head = cur;
@@ -882,9 +980,14 @@ int stau_nonlinear(stau_pencils* pen, const void* X, void* F, void* stream) {
 
 int stau_solve(stau_pencils* pen, const void* B_ev, void* X, void* stream) {
   if (!pen || !B_ev || !X) return fail(STAU_EINVAL, "null argument");
-  if (!pen->Lf) return fail(STAU_ESTATE, "stau_solve before a successful stau_factor");
+  if (!pen->last) return fail(STAU_ESTATE, "stau_solve before a successful stau_factor");
   HIP_TRY(hipSetDevice(pen->dom->d.device));
-  HIP_TRY(launch_solve(pen->pa, B_ev, pen->Lf, pen->sl, pen->Uf, X, (hipStream_t)stream));
+  const stau_pencils::FactorSlot* f = pen->last;
+  if (pen->two)
+    HIP_TRY(launch_solve2(pen->pt, pen->pb, B_ev, f->LfT, f->slT, f->UfT, f->LfB, f->slB, f->UfB, f->Rinv,
+                          f->E1, f->E2, X, (hipStream_t)stream));
+  else
+    HIP_TRY(launch_solve(pen->pa, B_ev, f->Lf, f->sl, f->Uf, X, (hipStream_t)stream));
   return STAU_OK;
 }
 
