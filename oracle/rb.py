@@ -15,6 +15,8 @@ fusion or fast transforms:
   variable-major (Kronecker block) ordering;
 * the multistep IMEX update of Sec. IX "Multistep IMEX integrators" with the
   semi-implicit BDF coefficients (first order on the first step);
+* the IMEX Runge-Kutta stages of Sec. IX "Runge-Kutta IMEX integrators"
+  (`step_rk`, stage right-hand sides with L~X applied directly);
 * each pencil is solved by a direct LU factorisation (dense LAPACK getrf for
   small pencils, SuperLU for large ones) reused while (a0, b0) are unchanged.
 
@@ -58,6 +60,42 @@ def sbdf_coefficients(iteration: int, dt: float, dt_prev: float | None):
     a1 = -(1.0 + w) / dt
     a2 = w * w / ((1.0 + w) * dt)
     return a0, a1, a2, 1.0, 1.0 + w, -w
+
+
+def rk_tableau(scheme: str):
+    """(H, A, c) of an IMEX Runge-Kutta scheme with stages 0..s (Sec. IX
+    "Runge-Kutta IMEX integrators"): H implicit (first row and column zero),
+    A explicit (strictly lower triangular), c the stage times; the last stage
+    is the new state.
+
+    reading: the paper names the family (Ascher, Ruuth & Spiteri 1997) but
+    prints no tableau; RK111, RK222 and RK443 are that reference's (1,1,1),
+    (2,2,2) and (4,4,3) schemes, orders 1, 2 and 3."""
+    if scheme == "RK111":
+        c = [0.0, 1.0]
+        A = [[0.0, 0.0], [1.0, 0.0]]
+        H = [[0.0, 0.0], [0.0, 1.0]]
+    elif scheme == "RK222":
+        g = (2.0 - math.sqrt(2.0)) / 2.0
+        d = 1.0 - 1.0 / (2.0 * g)
+        c = [0.0, g, 1.0]
+        A = [[0.0, 0.0, 0.0], [g, 0.0, 0.0], [d, 1.0 - d, 0.0]]
+        H = [[0.0, 0.0, 0.0], [0.0, g, 0.0], [0.0, 1.0 - g, g]]
+    elif scheme == "RK443":
+        c = [0.0, 1 / 2, 2 / 3, 1 / 2, 1.0]
+        A = [[0.0] * 5,
+             [1 / 2, 0.0, 0.0, 0.0, 0.0],
+             [11 / 18, 1 / 18, 0.0, 0.0, 0.0],
+             [5 / 6, -5 / 6, 1 / 2, 0.0, 0.0],
+             [1 / 4, 7 / 4, 3 / 4, -7 / 4, 0.0]]
+        H = [[0.0] * 5,
+             [0.0, 1 / 2, 0.0, 0.0, 0.0],
+             [0.0, 1 / 6, 1 / 2, 0.0, 0.0],
+             [0.0, -1 / 2, 1 / 2, 1 / 2, 0.0],
+             [0.0, 3 / 2, -3 / 2, 1 / 2, 1 / 2]]
+    else:
+        raise ValueError(f"unknown scheme {scheme!r}")
+    return np.array(H), np.array(A), np.array(c)
 
 
 @dataclass
@@ -371,6 +409,50 @@ class RBOracle:
         for _ in range(steps):
             X = self.step(X, dt)
         return X
+
+    # ------------------------------------------------------------------
+    # time stepping (Sec. IX "Runge-Kutta IMEX integrators")
+    # ------------------------------------------------------------------
+    def step_rk(self, X: np.ndarray, dt: float, scheme: str = "RK222") -> np.ndarray:
+        """One IMEX Runge-Kutta step X^n -> X^{n+1} (returns a new array).
+
+        Stages i = 1..s solve, per pencil,
+          (M~ + dt H_ii L~) X^{n,i} = M~ X^{n,0} + dt sum_{j<i} A_ij F~^{n,j}
+                                     - dt sum_{j<i} H_ij L~ X^{n,j},
+        with F~^{n,j} = P^L F(X^{n,j}) (boundary rows carrying their values)
+        and L~ X^{n,j} applied directly; the last stage is X^{n+1} (globally
+        stiffly accurate).  The multistep history is not touched."""
+        H, A, c = rk_tableau(scheme)
+        s = len(c) - 1
+        Xs = [X]
+        MX0: dict = {}
+        Ft: list = []   # Ft[j][key] = F~^{n,j}
+        LX: list = []   # LX[j][key] = L~ X^{n,j}
+        for i in range(1, s + 1):
+            Fnl = self.nonlinear(Xs[i - 1])
+            Ft_j, LX_j = {}, {}
+            for key, kx, ky, is_mean, active in self.pencils():
+                if not active:
+                    continue
+                M, L = self._ML_cached(key, kx, ky, is_mean)
+                xv = Xs[i - 1][key].reshape(-1)
+                if i == 1:
+                    MX0[key] = M @ xv
+                Ft_j[key] = self.precondition_rhs(Fnl[key], is_mean)
+                LX_j[key] = L @ xv
+            Ft.append(Ft_j)
+            LX.append(LX_j)
+            Xn = np.zeros_like(X)
+            for key, kx, ky, is_mean, active in self.pencils():
+                if not active:
+                    continue
+                B = MX0[key].copy()
+                for j in range(i):
+                    B += dt * A[i][j] * Ft[j][key] - dt * H[i][j] * LX[j][key]
+                solve = self.solver_for(key, kx, ky, is_mean, 1.0, dt * H[i][i])
+                Xn[key] = solve(B).reshape(self.S, self.Nz)
+            Xs.append(Xn)
+        return Xs[s]
 
     # ------------------------------------------------------------------
     # initial condition and functionals
