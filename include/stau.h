@@ -61,6 +61,13 @@ extern "C" {
 #define STAU_DCT_FFT 1
 #define STAU_DCT_MATMUL 2
 
+/* IMEX Runge-Kutta schemes of stau_step_rk: the (1,1,1), (2,2,2) and (4,4,3)
+ * schemes of Ascher, Ruuth & Spiteri (1997), orders 1, 2, 3, with 1, 2, 4
+ * implicit stages. */
+#define STAU_RK111 1
+#define STAU_RK222 2
+#define STAU_RK443 3
+
 typedef struct stau_domain stau_domain;
 typedef struct stau_pencils stau_pencils;
 
@@ -173,6 +180,23 @@ int64_t stau_last_singular_pencil(const stau_pencils* pen);
  * differ from the stored factorisation.  Updates st->X, st->hist and the
  * host fields iteration, dt_prev, head.  Asynchronous otherwise. */
 int stau_step(stau_pencils* pen, stau_state* st, double dt, void* stream);
+
+/* One IMEX Runge-Kutta step X^n -> X^{n+1} (Sec. IX "Runge-Kutta IMEX
+ * integrators"), in place on X (device, state layout).  For the stages
+ * i = 1..s of `scheme` (STAU_RK111, STAU_RK222, STAU_RK443; else
+ * STAU_EINVAL) it evaluates the explicit term of X^{n,i-1} on the dealiased
+ * grid and solves, per pencil,
+ *   (M~ + dt H_ii L~) X~^{n,i} = M~X^{n,0} + dt sum_{j<i} A_ij F~^{n,j}
+ *                                 - dt sum_{j<i} H_ij L~X^{n,j},
+ * recovering X^{n,i} = P^R X~^{n,i}; the last stage is X^{n+1}.  The stage
+ * operator is factored as M~ / (dt H_ii) + L~ (one factorisation per dt, the
+ * schemes' H_ii are equal; refactored synchronously when no stored
+ * factorisation matches).  The stage values F~ and L~X live in a workspace of
+ * the pencils object (allocated on the first call with a larger scheme:
+ * max(1, 2s - 2) arrays of P ne Nz complex entries).  Needs no history: every step is full order, dt may change from
+ * step to step.  In a STAU_MIXED domain the transforms, products and sweeps
+ * run as in stau_step.  Asynchronous otherwise. */
+int stau_step_rk(stau_pencils* pen, int scheme, double dt, void* X, void* stream);
 
 /* Initial state from real scale-1 grid values of b (2-D b[ix][jz], 3-D
  * b[ix][ly][jz]; device, float64; Chebyshev Gauss grid in z ascending,

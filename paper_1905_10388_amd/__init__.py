@@ -121,6 +121,14 @@ class RBSolver:
         self._st.hist = self.hist.data_ptr()
         _lib.check(self.lib.stau_step(self._pen, C.byref(self._st), float(dt), _stream_ptr()))
 
+    def step_rk(self, dt: float, scheme: str = "RK222"):
+        """One IMEX Runge-Kutta step of the state in place (RK111, RK222 or
+        RK443); independent of the multistep history."""
+        code = _lib.RK_SCHEMES.get(scheme)
+        if code is None:
+            raise ValueError(f"unknown Runge-Kutta scheme {scheme!r}")
+        _lib.check(self.lib.stau_step_rk(self._pen, code, float(dt), _ptr(self.X), _stream_ptr()))
+
     def factor(self, a0: float, b0: float = 1.0):
         _lib.check(self.lib.stau_factor(self._pen, float(a0), float(b0), _stream_ptr()))
 

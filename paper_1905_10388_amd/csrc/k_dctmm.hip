@@ -104,7 +104,8 @@ __global__ void __launch_bounds__(256) zb_mm_kernel(XformArgs a, FieldList fl,
 // ---------------------------------------------------------------------------
 // Forward z transform of the ne explicit-term fields H[e][j][p] with the
 // epilogue of zf_kernel: mode 0 writes c (Ffrag = Fz), mode 1 assembles the
-// SBDF right-hand side from F~ (Ffrag = P^L Fz) and writes the history.
+// SBDF right-hand side from F~ (Ffrag = P^L Fz) and writes the history, mode 2
+// the right-hand side of a Runge-Kutta stage.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) zf_mm_kernel(XformArgs a, const double2* __restrict__ H,
                                                     double2* __restrict__ out, RhsArgs r,
@@ -168,6 +169,10 @@ __global__ void __launch_bounds__(256) zf_mm_kernel(XformArgs a, const double2* 
         MX.x -= 0.5 * x2.x;
         MX.y -= 0.5 * x2.y;
       }
+      if (r.mode == 2) {
+        rk_rhs(r.rk, o, Ft, MX, out);
+        continue;
+      }
       B = make_double2(r.c1 * Ft.x - r.a1 * MX.x, r.c1 * Ft.y - r.a1 * MX.y);
       if (r.has_hist) {
         const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
@@ -175,6 +180,10 @@ __global__ void __launch_bounds__(256) zf_mm_kernel(XformArgs a, const double2* 
         B.x += r.c2 * Fo.x - r.a2 * Mo.x;
         B.y += r.c2 * Fo.y - r.a2 * Mo.y;
       }
+    }
+    if (r.mode == 2) {  // inactive pencil or row N - 1
+      out[o] = B;
+      continue;
     }
     const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
     r.hist_cur[ho] = Ft;
@@ -308,8 +317,9 @@ __global__ void __launch_bounds__(256) zb_bf16_kernel(XformArgs a, FieldList fl,
 }
 
 // Forward z transform, mixed path, from H[e][j][p] (FP32 complex), with the
-// FP64 epilogue of zf_kernel (mode 0: c with the Fz table; mode 1: the SBDF
-// right-hand side from F~ with the P^L Fz table) for the block's rows.
+// FP64 epilogue of zf_kernel (mode 0: c with the Fz table; modes 1 and 2: the
+// SBDF or Runge-Kutta stage right-hand side from F~ with the P^L Fz table) for
+// the block's rows.
 __global__ void __launch_bounds__(256) zf_bf16_kernel(XformArgs a, const float2* __restrict__ H,
                                                       double2* __restrict__ out, RhsArgs r,
                                                       const bf16x8* __restrict__ F3) {
@@ -385,6 +395,10 @@ __global__ void __launch_bounds__(256) zf_bf16_kernel(XformArgs a, const float2*
         MX.x -= 0.5 * x2.x;
         MX.y -= 0.5 * x2.y;
       }
+      if (r.mode == 2) {
+        rk_rhs(r.rk, o, Ft, MX, out);
+        continue;
+      }
       B = make_double2(r.c1 * Ft.x - r.a1 * MX.x, r.c1 * Ft.y - r.a1 * MX.y);
       if (r.has_hist) {
         const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
@@ -392,6 +406,10 @@ __global__ void __launch_bounds__(256) zf_bf16_kernel(XformArgs a, const float2*
         B.x += r.c2 * Fo.x - r.a2 * Mo.x;
         B.y += r.c2 * Fo.y - r.a2 * Mo.y;
       }
+    }
+    if (r.mode == 2) {  // inactive pencil or row N - 1
+      out[o] = B;
+      continue;
     }
     const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
     r.hist_cur[ho] = Ft;

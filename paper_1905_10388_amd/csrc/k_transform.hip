@@ -177,6 +177,7 @@ __global__ void __launch_bounds__(kZThreads) zb_kernel(XformArgs a, FieldList fl
 //   F~_n = P^L c (n <= N-2), MX_n = P^L X^{n-1}_e,
 //   B_n = c1 F~_n - a1 MX_n + [c2 F~old_n - a2 MXold_n],
 //   history hist_cur[p][0][e][n] = F~_n, hist_cur[p][1][e][n] = MX_n.
+// mode 2: right-hand side of a Runge-Kutta stage from F~_n and MX_n (rk_rhs).
 // ---------------------------------------------------------------------------
 template <int MAXBF, int MAXIT, typename T>
 __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
@@ -191,15 +192,18 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
   const int e = blockIdx.y;
   const int p0 = blockIdx.x * TP;
   const int tid = threadIdx.x, nt = kZThreads;
-  if (r.mode == 1 && a.dim == 2 && blockIdx.x == 0) {
-    // pencils beyond the grid (2-D, p >= Pa): inactive, zero right-hand side and history
+  if (r.mode >= 1 && a.dim == 2 && blockIdx.x == 0) {
+    // pencils beyond the grid (2-D, p >= Pa): inactive, zero right-hand side
+    // (and history)
     for (int p = a.Pa; p < a.P; ++p)
       for (int nn = tid; nn < N; nn += nt) {
         const size_t o = ((size_t)p * ne + e) * N + nn;
-        const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
         out[o] = make_double2(0.0, 0.0);
-        r.hist_cur[ho] = make_double2(0.0, 0.0);
-        r.hist_cur[ho + (size_t)ne * N] = make_double2(0.0, 0.0);
+        if (r.mode == 1) {
+          const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
+          r.hist_cur[ho] = make_double2(0.0, 0.0);
+          r.hist_cur[ho + (size_t)ne * N] = make_double2(0.0, 0.0);
+        }
       }
   }
   stage_z_tables<T>(a, twl, dcl, M, tid);
@@ -260,14 +264,14 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
     for (int u = 0; u < GE; ++u) {
       const int idx = tid + (g0 + u) * nt;
       x0[u] = x2[u] = fo[u] = mo[u] = make_double2(0.0, 0.0);
-      if (r.mode == 1 && idx < TP * N) {
+      if (r.mode >= 1 && idx < TP * N) {
         const int s = idx / N, nn = idx - s * N;
         const int p = p0 + s;
         if (active(a, p) && nn <= N - 2) {
           const double2* xc = r.Xprev + ((size_t)p * a.S + (e + 1)) * N;
           x0[u] = xc[nn];
           if (nn + 2 < N) x2[u] = xc[nn + 2];
-          if (r.has_hist) {
+          if (r.mode == 1 && r.has_hist) {
             const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
             fo[u] = r.hist_old[ho];
             mo[u] = r.hist_old[ho + (size_t)ne * N];
@@ -297,8 +301,16 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
         Ft = scale(cget(nn), cnn);
         if (nn + 2 < N) Ft = Ft - scale(cget(nn + 2), 0.5);
         MX = scale(mk(x0[u].x, x0[u].y), cnn) - scale(mk(x2[u].x, x2[u].y), 0.5);
+        if (r.mode == 2) {
+          rk_rhs(r.rk, o, make_double2(Ft.x, Ft.y), make_double2(MX.x, MX.y), out);
+          continue;
+        }
         B = scale(Ft, r.c1) - scale(MX, r.a1);
         if (r.has_hist) B = B + scale(mk(fo[u].x, fo[u].y), r.c2) - scale(mk(mo[u].x, mo[u].y), r.a2);
+      }
+      if (r.mode == 2) {  // inactive pencil or row N - 1
+        st2(out + o, B);
+        continue;
       }
       const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
       st2(r.hist_cur + ho, Ft);
@@ -1058,7 +1070,7 @@ hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs
                      hipStream_t st, bool fp32) {
   const int TP = z_tile(a.M);
   if (TP * a.M != kZPts || TP * a.N > 12 * kZThreads) return hipErrorInvalidValue;
-  const int plaunch = (a.dim == 2 && r.mode == 1) ? a.Pa : a.P;
+  const int plaunch = (a.dim == 2 && r.mode >= 1) ? a.Pa : a.P;
   dim3 grid((plaunch + TP - 1) / TP, a.ne);
   if (fp32) {
     size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(float2);

@@ -122,15 +122,69 @@ hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, voi
 hipError_t launch_xpass(const XformArgs& a, const void* G, void* H, hipStream_t st,
                         bool fp32 = false);
 // forward z; mode 0 writes F[P][ne][N]; mode 1 assembles the SBDF right-hand
-// side and the history (see k_transform.hip)
+// side and the history (see k_transform.hip); mode 2 the right-hand side of a
+// Runge-Kutta stage (rk_rhs below)
+constexpr int kMaxRkStages = 4;
+struct RkArgs {
+  int stage;      // i, 1 <= i <= s
+  int last;       // i == s: F~^{n,i-1} and dt L~X^{n,i-1} are not needed later
+  double dt;
+  double scale;   // 1 / (dt H_ii): the stage system is factored as (M~ / (dt H_ii) + L~)
+  double hprev;   // 1 / H_{i-1,i-1} (i >= 2)
+  double A[kMaxRkStages], H[kMaxRkStages];  // A_ij, H_ij for j < i
+  double2* F[kMaxRkStages];  // F~^{n,j} [P][ne][N], written by stage j + 1
+  double2* K[kMaxRkStages];  // dt L~X^{n,j} (j >= 1) [P][ne][N], written by stage j + 1
+  double2* MX0;              // M~X^{n,0} [P][ne][N], written by stage 1
+};
 struct RhsArgs {
   int mode;
   double c1, c2, a1, a2;
   int has_hist;
-  const double2* Xprev;  // state X^{n-1}
+  const double2* Xprev;  // state X^{n-1} (mode 2: the stage state X^{n,i-1})
   double2* hist_cur;     // [P][2][ne][N]
   const double2* hist_old;
+  RkArgs rk;
 };
+
+// Right-hand side of Runge-Kutta stage i at one evolved-equation U-row
+// (index o of the [P][ne][N] arrays) of an active pencil (Sec. IX
+// "Runge-Kutta IMEX integrators"):
+//   B~ = M~X^{n,0} + dt sum_{j<i} A_ij F~^{n,j} - dt sum_{j<i} H_ij L~X^{n,j},
+// written to out as B~ / (dt H_ii).  H_i0 = 0 for the schemes built here.
+// dt L~X^{n,i-1} is not applied from the operator: stage i - 1 solved
+// (M~ / (dt H) + L~) X^{n,i-1} = out, so dt L~X^{n,i-1} = dt out - M~X^{n,i-1} / H
+// row by row (H = H_{i-1,i-1}), read from out before it is overwritten.
+// Ft = F~^{n,i-1} and MX = M~X^{n,i-1} at the row.
+__device__ __forceinline__ void rk_rhs(const RkArgs& k, size_t o, double2 Ft, double2 MX,
+                                       double2* __restrict__ out) {
+  const int i = k.stage;
+  if (!k.last) k.F[i - 1][o] = Ft;
+  double2 B;
+  if (i == 1) {
+    k.MX0[o] = MX;
+    B = MX;
+  } else {
+    const double2 bp = out[o];
+    const double2 Kp = make_double2(k.dt * bp.x - k.hprev * MX.x, k.dt * bp.y - k.hprev * MX.y);
+    if (!k.last) k.K[i - 1][o] = Kp;
+    B = k.MX0[o];
+    B.x -= k.H[i - 1] * Kp.x;
+    B.y -= k.H[i - 1] * Kp.y;
+    for (int j = 1; j < i - 1; ++j) {
+      const double2 Kj = k.K[j][o];
+      B.x -= k.H[j] * Kj.x;
+      B.y -= k.H[j] * Kj.y;
+    }
+  }
+  for (int j = 0; j < i - 1; ++j) {
+    const double2 Fj = k.F[j][o];
+    B.x += k.dt * k.A[j] * Fj.x;
+    B.y += k.dt * k.A[j] * Fj.y;
+  }
+  B.x += k.dt * k.A[i - 1] * Ft.x;
+  B.y += k.dt * k.A[i - 1] * Ft.y;
+  out[o] = make_double2(B.x * k.scale, B.y * k.scale);
+}
 hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
                      hipStream_t st, bool fp32 = false);
 

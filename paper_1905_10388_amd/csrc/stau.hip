@@ -158,6 +158,10 @@ struct stau_pencils {
   double2* H = nullptr;    // [ne][M][P]
   double2* Bev = nullptr;  // [P][ne][N]
   double2* Gb = nullptr;   // [NF][M][P] adjoint workspace
+  // Runge-Kutta stage values (allocated on the first stau_step_rk):
+  // F~^{n,j} (j < s - 1), dt L~X^{n,j} (1 <= j < s - 1), M~X^{n,0}; [P][ne][N] each
+  double2* rkbuf = nullptr;
+  int rk_slots = 0;
   double2* wvec = nullptr; // [N] Chebyshev integration weights of the KE functional
   // Factor storage of one (a0, b0): factor_stride(n) columns per pencil plus
   // factor_slack() zero columns before and after (raw pointers own the memory).
@@ -471,6 +475,7 @@ static void free_pencils(stau_pencils* p) {
   hipFree(p->Bev);
   hipFree(p->Gb);
   hipFree(p->wvec);
+  hipFree(p->rkbuf);
   for (auto* set : {p->slot, p->slotT})
     for (int k = 0; k < 2; ++k) {
       auto& f = set[k];
@@ -909,6 +914,18 @@ static hipError_t explicit_term(stau_pencils* pen, const void* X, hipStream_t st
                [&] { return launch_ypass(pen->xa, -1, pen->pa.desc.ne, pen->G, pen->H, st, mixed); });
 }
 
+// Pencil solve of the step with the factors fs of (a0, b0): FP32 sweeps with
+// an FP64 residual in a mixed domain, else the two-block or the single-block
+// FP64 solve.
+static hipError_t solve_launch(stau_pencils* pen, const stau_pencils::FactorSlot* fs, double a0,
+                               double b0, const double2* B, void* X, hipStream_t st, bool mixed) {
+  if (mixed) return launch_solve_mixed(pen->pa, a0, b0, B, fs->Lf32, fs->sl, fs->Uf32, X, st);
+  if (pen->two)
+    return launch_solve2(pen->pt, pen->pb, B, fs->LfT, fs->slT, fs->UfT, fs->LfB, fs->slB, fs->UfB,
+                         fs->Rinv, fs->E1, fs->E2, X, st);
+  return launch_solve(pen->pa, B, fs->Lf, fs->sl, fs->Uf, X, st);
+}
+
 int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
   if (!pen || !s || !s->X || !s->hist) return fail(STAU_EINVAL, "null argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(STAU_EINVAL, "dt must be positive");
@@ -943,17 +960,115 @@ int stau_step(stau_pencils* pen, stau_state* s, double dt, void* stream) {
     if (pen->dom->mm16 && mixed) return launch_zf_bf16(pen->xa, pen->H, pen->Bev, r, pen->dom->PLFz3, st);
     return launch_zf(pen->xa, pen->H, pen->Bev, r, st, mixed);
   }));
-  HIP_TRY(timed(pen, K_SOLVE, st, [&] {
-    if (mixed)
-      return launch_solve_mixed(pen->pa, a0, b0, pen->Bev, fs->Lf32, fs->sl, fs->Uf32, s->X, st);
-    if (pen->two)
-      return launch_solve2(pen->pt, pen->pb, pen->Bev, fs->LfT, fs->slT, fs->UfT, fs->LfB, fs->slB,
-                           fs->UfB, fs->Rinv, fs->E1, fs->E2, s->X, st);
-    return launch_solve(pen->pa, pen->Bev, fs->Lf, fs->sl, fs->Uf, s->X, st);
-  }));
+  HIP_TRY(timed(pen, K_SOLVE, st, [&] { return solve_launch(pen, fs, a0, b0, pen->Bev, s->X, st, mixed); }));
   s->head = cur;
   s->iteration += 1;
   s->dt_prev = dt;
+  return STAU_OK;
+}
+
+namespace {
+// IMEX Runge-Kutta tableaus with stages 0..s: H implicit (first row and
+// column zero), A explicit (strictly lower triangular); the last stage is the
+// step.  The (1,1,1), (2,2,2) and (4,4,3) schemes of Ascher, Ruuth & Spiteri.
+struct RkTab {
+  int s = 0;
+  double A[5][5] = {}, H[5][5] = {};
+};
+
+bool rk_tableau(int scheme, RkTab* t) {
+  *t = RkTab{};
+  if (scheme == STAU_RK111) {
+    t->s = 1;
+    t->A[1][0] = 1.0;
+    t->H[1][1] = 1.0;
+  } else if (scheme == STAU_RK222) {
+    const double g = 1.0 - 1.0 / std::sqrt(2.0), d = 1.0 - 1.0 / (2.0 * g);
+    t->s = 2;
+    t->A[1][0] = g;
+    t->A[2][0] = d;
+    t->A[2][1] = 1.0 - d;
+    t->H[1][1] = g;
+    t->H[2][1] = 1.0 - g;
+    t->H[2][2] = g;
+  } else if (scheme == STAU_RK443) {
+    t->s = 4;
+    const double A[5][5] = {{0, 0, 0, 0, 0},
+                            {1.0 / 2, 0, 0, 0, 0},
+                            {11.0 / 18, 1.0 / 18, 0, 0, 0},
+                            {5.0 / 6, -5.0 / 6, 1.0 / 2, 0, 0},
+                            {1.0 / 4, 7.0 / 4, 3.0 / 4, -7.0 / 4, 0}};
+    const double H[5][5] = {{0, 0, 0, 0, 0},
+                            {0, 1.0 / 2, 0, 0, 0},
+                            {0, 1.0 / 6, 1.0 / 2, 0, 0},
+                            {0, -1.0 / 2, 1.0 / 2, 1.0 / 2, 0},
+                            {0, 3.0 / 2, -3.0 / 2, 1.0 / 2, 1.0 / 2}};
+    std::memcpy(t->A, A, sizeof(A));
+    std::memcpy(t->H, H, sizeof(H));
+  } else {
+    return false;
+  }
+  return true;
+}
+}  // namespace
+
+int stau_step_rk(stau_pencils* pen, int scheme, double dt, void* X, void* stream) {
+  if (!pen || !X) return fail(STAU_EINVAL, "null argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(STAU_EINVAL, "dt must be positive");
+  RkTab tb;
+  if (!rk_tableau(scheme, &tb)) return fail(STAU_EINVAL, "unknown Runge-Kutta scheme %d", scheme);
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  const int s = tb.s;
+  const size_t field = (size_t)pen->dom->P * pen->pa.desc.ne * pen->dom->d.Nz;
+  // F~ of stages 0..s-2, dt L~X of stages 1..s-2, M~X^{n,0}
+  const int slots = (s - 1) + (s > 2 ? s - 2 : 0) + 1;
+  if (pen->rk_slots < slots) {
+    if (pen->rkbuf) {
+      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(hipFree(pen->rkbuf));
+      pen->ws_bytes -= (int64_t)(pen->rk_slots * field * sizeof(double2));
+      pen->rkbuf = nullptr;
+      pen->rk_slots = 0;
+    }
+    if (hipMalloc(&pen->rkbuf, slots * field * sizeof(double2)) != hipSuccess)
+      return fail(STAU_ENOMEM, "Runge-Kutta workspace allocation failed");
+    pen->rk_slots = slots;
+    pen->ws_bytes += (int64_t)(slots * field * sizeof(double2));
+  }
+  RhsArgs r{};
+  r.mode = 2;
+  r.Xprev = (const double2*)X;
+  RkArgs& k = r.rk;
+  k.dt = dt;
+  int q = 0;
+  for (int j = 0; j + 1 < s; ++j) k.F[j] = pen->rkbuf + (size_t)(q++) * field;
+  for (int j = 1; j + 1 < s; ++j) k.K[j] = pen->rkbuf + (size_t)(q++) * field;
+  k.MX0 = pen->rkbuf + (size_t)(q++) * field;
+  const bool mixed = pen->dom->d.precision == STAU_MIXED;
+  for (int i = 1; i <= s; ++i) {
+    const double a0 = 1.0 / (dt * tb.H[i][i]), b0 = 1.0;
+    stau_pencils::FactorSlot* fs = nullptr;
+    {
+      int rc = factors_for(pen, a0, b0, st, &fs);
+      if (rc) return rc;
+    }
+    k.stage = i;
+    k.last = i == s;
+    k.scale = a0;
+    k.hprev = i > 1 ? 1.0 / tb.H[i - 1][i - 1] : 0.0;
+    for (int j = 0; j < kMaxRkStages; ++j) {
+      k.A[j] = j < i ? tb.A[i][j] : 0.0;
+      k.H[j] = j < i ? tb.H[i][j] : 0.0;
+    }
+    HIP_TRY(explicit_term(pen, X, st, mixed));
+    HIP_TRY(timed(pen, K_ZF, st, [&] {
+      if (pen->dom->mm && !mixed) return launch_zf_mm(pen->xa, pen->H, pen->Bev, r, pen->dom->PLFzfrag, st);
+      if (pen->dom->mm16 && mixed) return launch_zf_bf16(pen->xa, pen->H, pen->Bev, r, pen->dom->PLFz3, st);
+      return launch_zf(pen->xa, pen->H, pen->Bev, r, st, mixed);
+    }));
+    HIP_TRY(timed(pen, K_SOLVE, st, [&] { return solve_launch(pen, fs, a0, b0, pen->Bev, X, st, mixed); }));
+  }
   return STAU_OK;
 }
 
