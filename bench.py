@@ -184,6 +184,43 @@ def mixed_run(w, steps, warmup, X_fp64):
             "steps_compared": steps + warmup}
 
 
+def rk_run(w, X_start, steps=100, warmup=3):
+    """IMEX Runge-Kutta steps (RK222, RK443; FP64) on the headline workload
+    from the state the SBDF2 run reached: ms per step and per stage (one
+    explicit term and one pencil solve each), per-kernel averages."""
+    import torch
+
+    from paper_1905_10388_amd import RBSolver
+
+    Nx, Nz, dt = w["Nx"], w["Nz"], w["dt"]
+    out = {}
+    for scheme, stages in (("RK222", 2), ("RK443", 4)):
+        g = RBSolver(Nx, Nz, w["Lx"], w["Ra"], w["Pr"])
+        g.set_state(X_start)
+        for _ in range(warmup):
+            g.step_rk(dt, scheme)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(steps):
+            g.step_rk(dt, scheme)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = max((time.perf_counter() - t0) * 1e3 / steps, ev0.elapsed_time(ev1) / steps)
+        g.check()
+        g.set_kernel_timing(True)
+        for _ in range(10):
+            g.step_rk(dt, scheme)
+        kt = {k: round(v * 1e3 / c, 3) for k, (v, c) in g.read_kernel_timing().items() if c}
+        g.close()
+        out[scheme] = {"value": 7 * Nx * Nz / (ms * 1e-3), "unit": "DOF-updates/s", "ms_per_step": ms,
+                       "stages": stages, "ms_per_stage": ms / stages, "steps": steps,
+                       "kernels_avg_us": kt, "dtype": "f64"}
+    return out
+
+
 EXTRA_WORKLOADS = {
     # 3-D Fourier x, y x Chebyshev z: 33,024 pencil slots per launch
     "rb3d_256x256x128_Ra1e7_dt5e-5": dict(dim=3, Nx=256, Ny=256, Nz=128, Lx=4.0, Ly=4.0, Ra=1e7,
@@ -328,6 +365,7 @@ def main():
                     help="steps of the per-kernel HIP-event pass after the timed region")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-rk", action="store_true", help="skip the Runge-Kutta steps")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 3-D and small-Nz workloads")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -423,6 +461,8 @@ def main():
     if not args.no_mixed:
         out["mixed"] = mixed_run(w, args.steps, n_steps_end - args.steps, X_end)
         out["mixed"]["speedup_vs_fp64"] = out["mixed"]["value"] / value
+    if not args.no_rk:
+        out["runge_kutta"] = rk_run(w, X_end)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio()
         out["adjoint_mixed"] = adjoint_mixed()

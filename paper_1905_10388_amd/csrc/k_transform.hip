@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kZThreads) zb_kernel(XformArgs a, FieldList fl
 //   history hist_cur[p][0][e][n] = F~_n, hist_cur[p][1][e][n] = MX_n.
 // mode 2: right-hand side of a Runge-Kutta stage from F~_n and MX_n (rk_rhs).
 // ---------------------------------------------------------------------------
-template <int MAXBF, int MAXIT, typename T>
+template <int MAXBF, int MAXIT, typename T, bool RK = false>
 __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
                                                        const typename V2<T>::type* __restrict__ H,
                                                        double2* __restrict__ out, RhsArgs r, int TP) {
@@ -260,6 +260,7 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
 #pragma unroll
   for (int g0 = 0; g0 < MAXIT; g0 += GE) {
     double2 x0[GE], x2[GE], fo[GE], mo[GE];
+    RkRow rv[RK ? GE : 1];
 #pragma unroll
     for (int u = 0; u < GE; ++u) {
       const int idx = tid + (g0 + u) * nt;
@@ -271,6 +272,7 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
           const double2* xc = r.Xprev + ((size_t)p * a.S + (e + 1)) * N;
           x0[u] = xc[nn];
           if (nn + 2 < N) x2[u] = xc[nn + 2];
+          if constexpr (RK) rk_load(r.rk, ((size_t)p * ne + e) * N + nn, rv[u]);
           if (r.mode == 1 && r.has_hist) {
             const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
             fo[u] = r.hist_old[ho];
@@ -301,14 +303,14 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
         Ft = scale(cget(nn), cnn);
         if (nn + 2 < N) Ft = Ft - scale(cget(nn + 2), 0.5);
         MX = scale(mk(x0[u].x, x0[u].y), cnn) - scale(mk(x2[u].x, x2[u].y), 0.5);
-        if (r.mode == 2) {
-          rk_rhs(r.rk, o, make_double2(Ft.x, Ft.y), make_double2(MX.x, MX.y), out);
+        if constexpr (RK) {
+          rk_finish(r.rk, o, rv[u], make_double2(Ft.x, Ft.y), make_double2(MX.x, MX.y), out);
           continue;
         }
         B = scale(Ft, r.c1) - scale(MX, r.a1);
         if (r.has_hist) B = B + scale(mk(fo[u].x, fo[u].y), r.c2) - scale(mk(mo[u].x, mo[u].y), r.a2);
       }
-      if (r.mode == 2) {  // inactive pencil or row N - 1
+      if constexpr (RK) {  // inactive pencil or row N - 1
         st2(out + o, B);
         continue;
       }
@@ -1072,16 +1074,21 @@ hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs
   if (TP * a.M != kZPts || TP * a.N > 12 * kZThreads) return hipErrorInvalidValue;
   const int plaunch = (a.dim == 2 && r.mode >= 1) ? a.Pa : a.P;
   dim3 grid((plaunch + TP - 1) / TP, a.ne);
+  // the Runge-Kutta stage epilogue is a separate instantiation, so the SBDF
+  // kernel carries none of its code
+  auto go = [&](auto kern, auto h) {
+    const size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(*h);
+    allow_lds((const void*)kern, lds);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a, h, (double2*)out, r, TP);
+  };
+  const float2* h32 = (const float2*)H;
+  const double2* h64 = (const double2*)H;
   if (fp32) {
-    size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(float2);
-    allow_lds((const void*)zf_kernel<3, 12, float>, lds);
-    hipLaunchKernelGGL((zf_kernel<3, 12, float>), grid, dim3(256), lds, st, a, (const float2*)H,
-                       (double2*)out, r, TP);
+    if (r.mode == 2) go(zf_kernel<3, 12, float, true>, h32);
+    else go(zf_kernel<3, 12, float>, h32);
   } else {
-    size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(double2);
-    allow_lds((const void*)zf_kernel<3, 12, double>, lds);
-    hipLaunchKernelGGL((zf_kernel<3, 12, double>), grid, dim3(256), lds, st, a, (const double2*)H,
-                       (double2*)out, r, TP);
+    if (r.mode == 2) go(zf_kernel<3, 12, double, true>, h64);
+    else go(zf_kernel<3, 12, double>, h64);
   }
   return hipGetLastError();
 }

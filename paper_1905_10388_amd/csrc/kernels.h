@@ -135,6 +135,7 @@ struct RkArgs {
   double2* F[kMaxRkStages];  // F~^{n,j} [P][ne][N], written by stage j + 1
   double2* K[kMaxRkStages];  // dt L~X^{n,j} (j >= 1) [P][ne][N], written by stage j + 1
   double2* MX0;              // M~X^{n,0} [P][ne][N], written by stage 1
+  const double2* Bprev;      // the right-hand side of stage i - 1 (the buffer out is written to)
 };
 struct RhsArgs {
   int mode;
@@ -154,36 +155,65 @@ struct RhsArgs {
 // dt L~X^{n,i-1} is not applied from the operator: stage i - 1 solved
 // (M~ / (dt H) + L~) X^{n,i-1} = out, so dt L~X^{n,i-1} = dt out - M~X^{n,i-1} / H
 // row by row (H = H_{i-1,i-1}), read from out before it is overwritten.
-// Ft = F~^{n,i-1} and MX = M~X^{n,i-1} at the row.
-__device__ __forceinline__ void rk_rhs(const RkArgs& k, size_t o, double2 Ft, double2 MX,
-                                       double2* __restrict__ out) {
+// rk_load issues the row's loads (so that a caller can batch several rows),
+// rk_finish takes Ft = F~^{n,i-1} and MX = M~X^{n,i-1} and stores.
+struct RkRow {
+  double2 bp, mx0;                  // out (stage i - 1), M~X^{n,0}
+  double2 F[kMaxRkStages - 1];      // F~^{n,j}, j < i - 1
+  double2 K[kMaxRkStages - 2];      // dt L~X^{n,j}, 1 <= j < i - 1 (slot j - 1)
+};
+
+__device__ __forceinline__ void rk_load(const RkArgs& k, size_t o, RkRow& v) {
   const int i = k.stage;
-  if (!k.last) k.F[i - 1][o] = Ft;
+  if (i > 1) {
+    v.bp = k.Bprev[o];
+    v.mx0 = k.MX0[o];
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxRkStages - 1; ++j)
+    if (j < i - 1) v.F[j] = k.F[j][o];
+#pragma unroll
+  for (int j = 1; j < kMaxRkStages - 1; ++j)
+    if (j < i - 1) v.K[j - 1] = k.K[j][o];
+}
+
+__device__ __forceinline__ void rk_finish(const RkArgs& k, size_t o, const RkRow& v, double2 Ft,
+                                          double2 MX, double2* __restrict__ out) {
+  const int i = k.stage;
   double2 B;
   if (i == 1) {
     k.MX0[o] = MX;
     B = MX;
   } else {
-    const double2 bp = out[o];
-    const double2 Kp = make_double2(k.dt * bp.x - k.hprev * MX.x, k.dt * bp.y - k.hprev * MX.y);
+    const double2 Kp = make_double2(k.dt * v.bp.x - k.hprev * MX.x, k.dt * v.bp.y - k.hprev * MX.y);
     if (!k.last) k.K[i - 1][o] = Kp;
-    B = k.MX0[o];
+    B = v.mx0;
     B.x -= k.H[i - 1] * Kp.x;
     B.y -= k.H[i - 1] * Kp.y;
-    for (int j = 1; j < i - 1; ++j) {
-      const double2 Kj = k.K[j][o];
-      B.x -= k.H[j] * Kj.x;
-      B.y -= k.H[j] * Kj.y;
+#pragma unroll
+    for (int j = 1; j < kMaxRkStages - 1; ++j)
+      if (j < i - 1) {
+        B.x -= k.H[j] * v.K[j - 1].x;
+        B.y -= k.H[j] * v.K[j - 1].y;
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxRkStages - 1; ++j)
+    if (j < i - 1) {
+      B.x += k.dt * k.A[j] * v.F[j].x;
+      B.y += k.dt * k.A[j] * v.F[j].y;
     }
-  }
-  for (int j = 0; j < i - 1; ++j) {
-    const double2 Fj = k.F[j][o];
-    B.x += k.dt * k.A[j] * Fj.x;
-    B.y += k.dt * k.A[j] * Fj.y;
-  }
   B.x += k.dt * k.A[i - 1] * Ft.x;
   B.y += k.dt * k.A[i - 1] * Ft.y;
+  if (!k.last) k.F[i - 1][o] = Ft;
   out[o] = make_double2(B.x * k.scale, B.y * k.scale);
+}
+
+__device__ __forceinline__ void rk_rhs(const RkArgs& k, size_t o, double2 Ft, double2 MX,
+                                       double2* __restrict__ out) {
+  RkRow v;
+  rk_load(k, o, v);
+  rk_finish(k, o, v, Ft, MX, out);
 }
 hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs& r,
                      hipStream_t st, bool fp32 = false);

@@ -1045,6 +1045,7 @@ int stau_step_rk(stau_pencils* pen, int scheme, double dt, void* X, void* stream
   for (int j = 0; j + 1 < s; ++j) k.F[j] = pen->rkbuf + (size_t)(q++) * field;
   for (int j = 1; j + 1 < s; ++j) k.K[j] = pen->rkbuf + (size_t)(q++) * field;
   k.MX0 = pen->rkbuf + (size_t)(q++) * field;
+  k.Bprev = pen->Bev;
   const bool mixed = pen->dom->d.precision == STAU_MIXED;
   for (int i = 1; i <= s; ++i) {
     const double a0 = 1.0 / (dt * tb.H[i][i]), b0 = 1.0;
