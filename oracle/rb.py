@@ -15,6 +15,8 @@ fusion or fast transforms:
   variable-major (Kronecker block) ordering;
 * the multistep IMEX update of Sec. IX "Multistep IMEX integrators" with the
   semi-implicit BDF coefficients (first order on the first step);
+* the linear boundary value solve of Sec. IX "Linear boundary value
+  solver" (`lbvp`);
 * the IMEX Runge-Kutta stages of Sec. IX "Runge-Kutta IMEX integrators"
   (`step_rk`, stage right-hand sides with L~X applied directly);
 * each pencil is solved by a direct LU factorisation (dense LAPACK getrf for
@@ -408,6 +410,25 @@ class RBOracle:
     def run(self, X: np.ndarray, dt: float, steps: int) -> np.ndarray:
         for _ in range(steps):
             X = self.step(X, dt)
+        return X
+
+    # ------------------------------------------------------------------
+    # linear boundary value problem (Sec. IX "Linear boundary value solver")
+    # ------------------------------------------------------------------
+    def lbvp(self, F: np.ndarray) -> np.ndarray:
+        """Solve L X = F per pencil: the left-preconditioned system
+        P^L L P^R (P^R)^{-1} X = P^L F (here without P^R, which does not change
+        X), with F given as T coefficients of the right side of each evolved
+        equation (evolved-field axis of size ne in place of the variable
+        axis), the boundary rows carrying their Dirichlet values and the
+        first-order and continuity rows zero.  Returns X in the state layout."""
+        X = np.zeros(self.state_shape, dtype=np.complex128)
+        for key, kx, ky, is_mean, active in self.pencils():
+            if not active:
+                continue
+            M, L = self._ML_cached(key, kx, ky, is_mean)
+            solve = self.solver_for(key, kx, ky, is_mean, 0.0, 1.0)
+            X[key] = solve(self.precondition_rhs(F[key], is_mean)).reshape(self.S, self.Nz)
         return X
 
     # ------------------------------------------------------------------
