@@ -198,6 +198,18 @@ int stau_step(stau_pencils* pen, stau_state* st, double dt, void* stream);
  * run as in stau_step.  Asynchronous otherwise. */
 int stau_step_rk(stau_pencils* pen, int scheme, double dt, void* X, void* stream);
 
+/* Linear boundary value solve (Sec. IX "Linear boundary value solver"): per
+ * pencil, L~ X~ = P^L F with the boundary rows taking the problem's Dirichlet
+ * values and the z-derivative and continuity rows zero, then X = P^R X~.
+ * F is device complex128 [P][ne][Nz] (2-D) / [Ny][Px][ne][Nz] (3-D): the T
+ * coefficients of the right side of each evolved equation (b, u, [v], w;
+ * -kappa lap b = F_b, -nu lap u + grad p - b e_z = F_u), read only for
+ * active pencils.  X (device, state layout) is written entirely.  Factors
+ * L~ (a0 = 0, b0 = 1) into the factorisation cache (synchronously when no
+ * stored factorisation matches); the solve is FP64 in either precision
+ * mode.  Asynchronous otherwise. */
+int stau_lbvp(stau_pencils* pen, const void* F, void* X, void* stream);
+
 /* Initial state from real scale-1 grid values of b (2-D b[ix][jz], 3-D
  * b[ix][ly][jz]; device, float64; Chebyshev Gauss grid in z ascending,
  * x_i = Lx i / Nx): forward transforms, bz = d_z b by the Chebyshev derivative

@@ -129,6 +129,18 @@ class RBSolver:
             raise ValueError(f"unknown Runge-Kutta scheme {scheme!r}")
         _lib.check(self.lib.stau_step_rk(self._pen, code, float(dt), _ptr(self.X), _stream_ptr()))
 
+    def lbvp(self, F, out=None):
+        """Linear boundary value solve L X = F per pencil (F: complex128 T
+        coefficients [.., ne, Nz] of the evolved equations' right sides).
+        Returns X in the state layout (a new tensor unless `out` is given)."""
+        t = self._torch
+        F = F.to(device=self.device, dtype=t.complex128).contiguous()
+        if tuple(F.shape) != tuple(self.ev_shape):
+            raise ValueError(f"F must have shape {self.ev_shape}")
+        X = out if out is not None else t.empty(self.state_shape, dtype=t.complex128, device=self.device)
+        _lib.check(self.lib.stau_lbvp(self._pen, _ptr(F), _ptr(X), _stream_ptr()))
+        return X
+
     def factor(self, a0: float, b0: float = 1.0):
         _lib.check(self.lib.stau_factor(self._pen, float(a0), float(b0), _stream_ptr()))
 

@@ -570,6 +570,40 @@ __global__ void __launch_bounds__(256) ic_x_kernel(XformArgs a, const double* __
   for (int k = tid; k < a.Px; k += nt) st2(out + k, k < a.Pa ? scale(buf[k], inv) : mk(0.0, 0.0));
 }
 
+// Right-hand side of the linear boundary value solve on the evolved-equation
+// U-rows: Bev[p][e][n] = (P^L F)_n = c_n F_n - F_{n+2} / 2 (c_0 = 1, else 1/2)
+// for n <= N - 2 of an active pencil, zero otherwise (T-to-U conversion,
+// Appendix A).
+__global__ void lbvp_rhs_kernel(XformArgs a, const double2* __restrict__ F, double2* __restrict__ Bev) {
+  const int N = a.N, ne = a.ne;
+  const size_t total = (size_t)a.P * ne * N;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int nn = (int)(i % N);
+    const int p = (int)(i / ((size_t)ne * N));
+    double2 v = make_double2(0.0, 0.0);
+    if (active(a, p) && nn <= N - 2) {
+      const double c = nn == 0 ? 1.0 : 0.5;
+      const double2 f0 = F[i];
+      v = make_double2(c * f0.x, c * f0.y);
+      if (nn + 2 < N) {
+        const double2 f2 = F[i + 2];
+        v.x -= 0.5 * f2.x;
+        v.y -= 0.5 * f2.y;
+      }
+    }
+    Bev[i] = v;
+  }
+}
+
+hipError_t launch_lbvp_rhs(const XformArgs& a, const void* F, void* Bev, hipStream_t st) {
+  const size_t total = (size_t)a.P * a.ne * a.N;
+  const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+  hipLaunchKernelGGL(lbvp_rhs_kernel, dim3(blocks), dim3(256), 0, st, a, (const double2*)F,
+                     (double2*)Bev);
+  return hipGetLastError();
+}
+
 // X[p][b] = c, X[p][bz] = d_z c (Chebyshev derivative recursion on [0, 1]),
 // all other variables zero.
 __global__ void ic_fill_kernel(XformArgs a, const double2* __restrict__ C, double2* __restrict__ X,
@@ -1127,11 +1161,13 @@ static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipS
   const int rows = a.M * (DIM == 2 ? 1 : a.Ngy);
   const bool twl = (size_t)a.L * sizeof(S2) <= 32768;
   const size_t lds = (size_t)a.L * sizeof(S2) * (twl ? 2 : 1);
-  // 2-D rows fewer than compute units: two blocks per row
+  // 2-D rows fewer than compute units (FP32: fewer than twice as many): two
+  // blocks per row.  (Measured at 1536 x 384 points: FP32 27.8 -> 21.6 us
+  // split; FP64 37.8 -> 41.3 us, so FP64 keeps one block per row there.)
   int dev = 0, cus = 0;
   const bool split = DIM == 2 && hipGetDevice(&dev) == hipSuccess &&
                      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-                     rows < cus;
+                     rows < (sizeof(T) == 4 ? 2 * cus : cus);
   const dim3 grid(rows, split ? 2 : 1);
   if (twl) {
     auto fn = split ? xrow_kernel<DIM, NT, PTS, MAXBF, true, T, true> : xrow_kernel<DIM, NT, PTS, MAXBF, true, T, false>;

@@ -259,6 +259,8 @@ hipError_t launch_initial_state_adjoint(const XformArgs& a1, const void* Xbar, d
                                         void* work, hipStream_t st);
 
 // initial state from scale-1 grid values of b
+// P^L F on the evolved U-rows for the linear boundary value solve
+hipError_t launch_lbvp_rhs(const XformArgs& a, const void* F, void* Bev, hipStream_t st);
 hipError_t launch_initial_state(const XformArgs& a1, const double* bgrid, void* X, void* work,
                                 hipStream_t st);
 

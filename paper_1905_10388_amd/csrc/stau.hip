@@ -1073,6 +1073,20 @@ int stau_step_rk(stau_pencils* pen, int scheme, double dt, void* X, void* stream
   return STAU_OK;
 }
 
+int stau_lbvp(stau_pencils* pen, const void* F, void* X, void* stream) {
+  if (!pen || !F || !X) return fail(STAU_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  stau_pencils::FactorSlot* fs = nullptr;
+  {
+    int rc = factors_for(pen, 0.0, 1.0, st, &fs);
+    if (rc) return rc;
+  }
+  HIP_TRY(launch_lbvp_rhs(pen->xa, F, pen->Bev, st));
+  HIP_TRY(timed(pen, K_SOLVE, st, [&] { return solve_launch(pen, fs, 0.0, 1.0, pen->Bev, X, st, false); }));
+  return STAU_OK;
+}
+
 int stau_initial_state(stau_pencils* pen, const double* b_grid, void* X, void* stream) {
   if (!pen || !b_grid || !X) return fail(STAU_EINVAL, "null argument");
   HIP_TRY(hipSetDevice(pen->dom->d.device));
