@@ -551,12 +551,12 @@ class RBOracle:
     # ------------------------------------------------------------------
     # linear eigenproblem sigma M X + L X = 0 (Sec. IX "Eigenvalue solver")
     # ------------------------------------------------------------------
-    def linearized_matrices(self, kx: float, ky: float = 0.0):
+    def linearized_matrices(self, kx: float, ky: float = 0.0, is_mean: bool = False):
         """(M, L + L') for the problem linearised about the conduction state
         b0 = b_bottom + (b_top - b_bottom) z.  L' is the linearisation of the
         explicit term -(u.grad) b about b0, i.e. -w d_z b0 in the b equation,
         moved to the left-hand side as (b_top - b_bottom) P^L w on its U-rows."""
-        M, L = self.pencil_matrices(kx, ky, False)
+        M, L = self.pencil_matrices(kx, ky, is_mean)
         N = self.Nz
         Lp = sp.lil_matrix(L.shape, dtype=np.complex128)
         w0 = self.vi["w"] * N
@@ -572,6 +572,29 @@ class RBOracle:
         w = w[np.isfinite(w)]
         w = w[np.abs(w) < 1e8]
         return float(np.max(w.real))
+
+
+    def stability_eigenvalue(self, kx: float, ky: float = 0.0, tau: float = 0.0,
+                             is_mean: bool = False, method: str = "auto") -> float:
+        """The eigenvalue sigma of sigma M X + (L + L') X = 0 (linearised about
+        conduction, Sec. IX "Eigenvalue solver") nearest the real shift tau:
+        the dense generalized eigenvalues for small pencils, else ARPACK on the
+        shift-inverted operator (L + L' + tau M)^{-1} M, whose dominant
+        eigenvalue is 1 / (tau - sigma) (the paper's sparse shift-invert
+        route).  The spectrum of this problem is real; the real part is
+        returned.  is_mean selects the mean pencil's rows (gauge p(1) = 0);
+        method "dense" or "arpack" forces a route."""
+        M, A = self.linearized_matrices(kx, ky, is_mean)
+        n = M.shape[0]
+        if method == "dense" or (method == "auto" and n <= 1200):
+            w = sla.eigvals(A.toarray(), -M.toarray())
+            w = w[np.isfinite(w)]
+            w = w[np.abs(w) < 1e8]
+            return float(np.real(w[np.argmin(np.abs(w - tau))]))
+        lu = spla.splu((A + tau * M).tocsc())
+        T = spla.LinearOperator(A.shape, matvec=lambda x: lu.solve(M @ x), dtype=np.complex128)
+        mu = spla.eigs(T, k=1, which="LM", return_eigenvectors=False, tol=1e-14)[0]
+        return float(np.real(tau - 1.0 / mu))
 
 
 def tau_poisson_bvp(N: int, f_coeffs: np.ndarray) -> np.ndarray:
