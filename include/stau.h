@@ -210,6 +210,26 @@ int stau_step_rk(stau_pencils* pen, int scheme, double dt, void* X, void* stream
  * mode.  Asynchronous otherwise. */
 int stau_lbvp(stau_pencils* pen, const void* F, void* X, void* stream);
 
+/* Linear stability of the conduction state b0(z) = b_bottom + (b_top - b_bottom) z
+ * (Sec. IX "Eigenvalue solver"): for every active pencil, the eigenvalue sigma
+ * of  sigma M~ X + (L~ + L~') X = 0  nearest the real shift tau, where L~' is
+ * the explicit term -w d_z b linearised about b0 and moved to the left
+ * ((b_top - b_bottom) P^L w on the b rows).  `iters` steps of shift-invert
+ * iteration x <- A^{-1} M~ x / |A^{-1} M~ x| with the banded LU of
+ * A = tau M~ + L~ + L~' (factored by this call when tau changed, synchronously;
+ * whole-band layout, kept apart from the step's factors); the iteration
+ * converges like |tau - sigma_1| / |tau - sigma_2| per step.  The spectrum of
+ * this problem is real.
+ * sigma, resid  device float64 [P] (one entry per pencil slot, 0 for inactive
+ *          slots): the eigenvalue, and the relative residual
+ *          |A^{-1} M~ x - mu x| / |A^{-1} M~ x| of the last step, mu = 1 / (tau - sigma).
+ * X        device, state layout, or NULL: the eigenvectors (unit 2-norm of the
+ *          recombined real-scaled vector; real, u-type variables imaginary).
+ * iters in [1, 100000], else STAU_EINVAL; STAU_ESINGULAR when tau is an
+ * eigenvalue of a pencil.  Asynchronous after the factorisation. */
+int stau_evp(stau_pencils* pen, double tau, int iters, double* sigma, double* resid, void* X,
+             void* stream);
+
 /* Initial state from real scale-1 grid values of b (2-D b[ix][jz], 3-D
  * b[ix][ly][jz]; device, float64; Chebyshev Gauss grid in z ascending,
  * x_i = Lx i / Nx): forward transforms, bz = d_z b by the Chebyshev derivative

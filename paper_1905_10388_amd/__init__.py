@@ -141,6 +141,18 @@ class RBSolver:
         _lib.check(self.lib.stau_lbvp(self._pen, _ptr(F), _ptr(X), _stream_ptr()))
         return X
 
+    def evp(self, tau: float, iters: int = 100, vectors: bool = False):
+        """Linear-stability eigenvalue nearest tau for every pencil slot:
+        (sigma [P], resid [P], X or None) as device tensors."""
+        t = self._torch
+        P = self.info["P"]
+        sigma = t.empty(P, dtype=t.float64, device=self.device)
+        resid = t.empty(P, dtype=t.float64, device=self.device)
+        X = t.empty(self.state_shape, dtype=t.complex128, device=self.device) if vectors else None
+        _lib.check(self.lib.stau_evp(self._pen, float(tau), int(iters), _ptr(sigma), _ptr(resid),
+                                     _ptr(X) if X is not None else None, _stream_ptr()))
+        return sigma, resid, X
+
     def factor(self, a0: float, b0: float = 1.0):
         _lib.check(self.lib.stau_factor(self._pen, float(a0), float(b0), _stream_ptr()))
 

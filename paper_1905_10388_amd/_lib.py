@@ -32,7 +32,7 @@ EXPORTS = (
     "stau_query", "stau_factor", "stau_last_singular_pencil", "stau_step", "stau_initial_state",
     "stau_nonlinear", "stau_solve", "stau_check", "stau_kinetic_energy", "stau_last_error",
     "stau_set_kernel_timing", "stau_read_kernel_timing", "stau_adjoint_step",
-    "stau_kinetic_energy_adjoint", "stau_initial_state_adjoint", "stau_step_rk", "stau_lbvp",
+    "stau_kinetic_energy_adjoint", "stau_initial_state_adjoint", "stau_step_rk", "stau_lbvp", "stau_evp",
 )
 KERNEL_KINDS = ("z_backward", "x_pass", "z_forward_rhs", "pencil_solve", "pencil_factor", "y_pass")
 
@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH):
         "stau_step": (i32, [vp, C.POINTER(StateC), dbl, vp]),
         "stau_step_rk": (i32, [vp, i32, dbl, vp, vp]),
         "stau_lbvp": (i32, [vp, vp, vp, vp]),
+        "stau_evp": (i32, [vp, dbl, i32, vp, vp, vp, vp]),
         "stau_initial_state": (i32, [vp, vp, vp, vp]),
         "stau_nonlinear": (i32, [vp, vp, vp, vp]),
         "stau_solve": (i32, [vp, vp, vp, vp]),

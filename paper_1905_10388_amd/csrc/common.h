@@ -232,6 +232,10 @@ struct SysDesc {
 struct PencilCoef {
   double a0, b0, kappa, nu, buoy, kx, ky;
   int mean;
+  // linearisation of the explicit term -w d_z b about the conduction profile
+  // b0(z) = b_bottom + (b_top - b_bottom) z: lin = b_top - b_bottom times
+  // P^L w on the b rows (linear-stability problems only; 0 for the step)
+  double lin;
 };
 
 // Entry (r, c) of a0 M~ + b0 L~ in the interleaved, Dirichlet-recombined,
@@ -267,6 +271,7 @@ __host__ __device__ inline double entry_T(const SysDesc& d, const PencilCoef& pc
     case EB:
       if (var == VB) return (pc.a0 + pc.b0 * pc.kappa * k2) * cheb_C(n, m);
       if (var == VBZ) return -pc.b0 * pc.kappa * cheb_D(n, m);
+      if (var == VW) return pc.b0 * pc.lin * cheb_C(n, m);
       return 0.0;
     case EU:
       if (var == VU) return (pc.a0 + pc.b0 * pc.nu * k2) * cheb_C(n, m);
@@ -361,7 +366,7 @@ __host__ __device__ inline double apply_row(const SysDesc& d, const PencilCoef& 
   const double k2 = pc.kx * pc.kx + pc.ky * pc.ky;
   const double ak = pc.a0 + pc.b0 * pc.kappa * k2, an = pc.a0 + pc.b0 * pc.nu * k2;
   switch (eq) {
-    case EB: return ak * Cv(VB, n) - pc.b0 * pc.kappa * Dv(VBZ, n);
+    case EB: return ak * Cv(VB, n) - pc.b0 * pc.kappa * Dv(VBZ, n) + pc.b0 * pc.lin * Cv(VW, n);
     case EU: return an * Cv(VU, n) - pc.b0 * pc.nu * Dv(VUZ, n) - pc.b0 * pc.kx * Cv(VP, n);
     case EV: return an * Cv(VV, n) - pc.b0 * pc.nu * Dv(VVZ, n) - pc.b0 * pc.ky * Cv(VP, n);
     case EW:
@@ -414,7 +419,7 @@ __host__ __device__ inline double apply_col(const SysDesc& d, const PencilCoef& 
       case VUZ: return -b0 * pc.nu * DT(EU, q) + b0 * CT(EUZ, q);
       case VV: return an * CT(EV, q) - b0 * DT(EVZ, q) + b0 * pc.ky * yrow(q, EC);
       case VVZ: return -b0 * pc.nu * DT(EV, q) + b0 * CT(EVZ, q);
-      case VW: return an * CT(EW, q) - b0 * DT(EWZ, q);
+      case VW: return an * CT(EW, q) - b0 * DT(EWZ, q) + b0 * pc.lin * CT(EB, q);
       case VWZ: return -b0 * pc.nu * DT(EW, q) + b0 * CT(EWZ, q) + b0 * yrow(q, EC);
       case VP: return -b0 * pc.kx * CT(EU, q) - b0 * pc.ky * CT(EV, q) + b0 * DT(EW, q);
     }

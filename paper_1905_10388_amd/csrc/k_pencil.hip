@@ -87,6 +87,7 @@ __device__ __forceinline__ PencilCoef pencil_coef(const PencilArgs& a, int p, do
   }
   pc.kx = a.two_pi_over_Lx * (double)ix;
   pc.mean = (ix == 0 && iy == 0);
+  pc.lin = a.lin;
   return pc;
 }
 
@@ -687,6 +688,109 @@ __global__ void __launch_bounds__(4 * kWave) solve_kernel(PencilArgs a, int plau
     write_state(a, bre, bim, X + (size_t)p * S * N, tid & (2 * kWave - 1), 2 * kWave);
   else if (live)
     zero_pencils(X, p, p + 1, S * N, tid & (2 * kWave - 1), 2 * kWave);
+}
+
+// ---------------------------------------------------------------------------
+// Linear stability (Sec. IX "Eigenvalue solver"): sigma M~ x + (L~ + L~') x = 0
+// about the conduction state, per pencil.  With the factors of
+// A = tau M~ + L~ + L~', the iteration x <- A^{-1} M~ x / |A^{-1} M~ x|
+// converges to the eigenvector whose eigenvalue mu = 1 / (tau - sigma) of
+// A^{-1} M~ is largest in modulus, i.e. sigma nearest tau (the spectrum of
+// this problem is real); mu = x . A^{-1} M~ x.  One wavefront per pencil: M~ x
+// from the operator templates (a0 = 1, b0 = 0), the two sweeps of the solve,
+// then the normalisation.  Writes sigma = tau - 1 / mu, the relative residual
+// |A^{-1} M~ x - mu x| / |A^{-1} M~ x| of the last iteration and, with X, the
+// eigenvector X = P^R x (state layout, unit 2-norm over x).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int FW, int BW>
+__global__ void __launch_bounds__(kWave) evp_kernel(PencilArgs a, double tau, int iters,
+                                                    const double* __restrict__ Lf,
+                                                    const uint8_t* __restrict__ sl,
+                                                    const double* __restrict__ Uf,
+                                                    double* __restrict__ sigma,
+                                                    double* __restrict__ resid,
+                                                    double2* __restrict__ X) {
+  extern __shared__ double lds[];
+  const int p = blockIdx.x, lane = threadIdx.x;
+  const SysDesc& d = a.desc;
+  const int n = a.n, N = d.N, S = d.S, npad = a.nst, nch = npad / kCH;
+  const int span = BW + npad + FW;
+  double* b = lds + BW;     // solve vector, rows [-BW, npad + FW)
+  double* x = lds + span;   // iterate, rows [0, n)
+  if (!pencil_active(a, p)) {
+    if (lane == 0) {
+      sigma[p] = 0.0;
+      resid[p] = 0.0;
+    }
+    if (X) zero_pencils(X, p, p + 1, S * N, lane, kWave);
+    return;
+  }
+  const PencilCoef pm = pencil_coef(a, p, 1.0, 0.0);  // M~
+  // deterministic start vector (no symmetry of the problem), unit norm
+  double ss = 0.0;
+  for (int r = lane; r < n; r += kWave) {
+    const double q = 0.6180339887498949 * (double)(r + 1);  // golden-ratio sequence in [0.5, 1.5)
+    const double v = 0.5 + (q - floor(q));
+    x[r] = v;
+    ss += v * v;
+  }
+  ss = wave_sum(ss);
+  {
+    const double inv = 1.0 / __builtin_sqrt(ss);
+    for (int r = lane; r < n; r += kWave) x[r] *= inv;
+  }
+  const double* Lp = Lf + (size_t)p * npad * FW;
+  const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
+  const double* Up = Uf + (size_t)p * npad * BW;
+  double mu = 0.0, res = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    __syncthreads();
+    for (int r = lane - BW; r < npad + FW; r += kWave)
+      b[r] = (r >= 0 && r < n) ? apply_row(d, pm, r, [&](int m, int var) { return x[m * S + d.var_pos[var]]; })
+                               : 0.0;
+    __syncthreads();
+    sweeps<double, FW, BW>(b, Lp, swp, Up, nch, lane);
+    __syncthreads();
+    double xz = 0.0, zz = 0.0;
+    for (int r = lane; r < n; r += kWave) {
+      xz += x[r] * b[r];
+      zz += b[r] * b[r];
+    }
+    mu = wave_sum(xz);
+    zz = wave_sum(zz);
+    double rr = 0.0;
+    for (int r = lane; r < n; r += kWave) {
+      const double e = b[r] - mu * x[r];
+      rr += e * e;
+    }
+    rr = wave_sum(rr);
+    res = __builtin_sqrt(rr / zz);
+    const double inv = 1.0 / __builtin_sqrt(zz);
+    for (int r = lane; r < n; r += kWave) x[r] = b[r] * inv;
+  }
+  if (lane == 0) {
+    sigma[p] = tau - 1.0 / mu;
+    resid[p] = res;
+  }
+  if (X) {
+    __syncthreads();
+    double2* Xp = X + (size_t)p * S * N;
+    for (int i = lane; i < S * N; i += kWave) {
+      const int vabi = i / N, m = i - vabi * N;
+      const int var = a.var_of_abi[vabi];
+      const int pos = d.var_pos[var];
+      double v = x[m * S + pos];
+      if (m + 2 < N) v -= x[(m + 2) * S + pos];
+      Xp[i] = (var == VU || var == VUZ || var == VV || var == VVZ) ? make_double2(0.0, -v)  // u = -i u~
+                                                                   : make_double2(v, 0.0);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1322,6 +1426,26 @@ hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, 
                         const double* Uf, void* X, hipStream_t st) {
 #define STAU_CASE(F, B) \
   if (a.FW == F && a.BW == B) return launch_solve_t<F, B>(a, Bev, Lf, sl, Uf, X, st);
+  STAU_SWEEP_VARIANTS(STAU_CASE)
+#undef STAU_CASE
+  return hipErrorInvalidValue;
+}
+
+template <int FW, int BW>
+static hipError_t launch_evp_t(const PencilArgs& a, double tau, int iters, const double* Lf,
+                               const uint8_t* sl, const double* Uf, double* sigma, double* resid,
+                               void* X, hipStream_t st) {
+  const size_t lds = (size_t)(BW + a.nst + FW + a.n) * sizeof(double);
+  allow_lds((const void*)evp_kernel<FW, BW>, lds);
+  hipLaunchKernelGGL((evp_kernel<FW, BW>), dim3(a.P), dim3(kWave), lds, st, a, tau, iters, Lf, sl, Uf,
+                     sigma, resid, (double2*)X);
+  return hipGetLastError();
+}
+
+hipError_t launch_evp(const PencilArgs& a, double tau, int iters, const double* Lf, const uint8_t* sl,
+                      const double* Uf, double* sigma, double* resid, void* X, hipStream_t st) {
+#define STAU_CASE(F, B) \
+  if (a.FW == F && a.BW == B) return launch_evp_t<F, B>(a, tau, iters, Lf, sl, Uf, sigma, resid, X, st);
   STAU_SWEEP_VARIANTS(STAU_CASE)
 #undef STAU_CASE
   return hipErrorInvalidValue;

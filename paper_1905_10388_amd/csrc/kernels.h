@@ -23,6 +23,7 @@ struct PencilArgs {
 
   int P, Px, Ny;
   double kappa, nu, buoyancy, b_bottom, b_top;
+  double lin;  // PencilCoef::lin of every pencil (0 for the step's operators)
   double two_pi_over_Lx, two_pi_over_Ly;
   int var_of_abi[9];
 };
@@ -100,6 +101,11 @@ hipError_t launch_solve2(const PencilArgs& t, const PencilArgs& bt, const void* 
                          const double* Rinv, const double* E1, const double* E2, void* X,
                          hipStream_t st);
 bool solve2_supported(const PencilArgs& t, const PencilArgs& bt);
+// shift-invert iteration for the linear-stability eigenvalue nearest tau, one
+// wavefront per pencil, on the factors of tau M~ + L~ + L~' (k_pencil.hip)
+hipError_t launch_evp(const PencilArgs& a, double tau, int iters, const double* Lf,
+                      const uint8_t* sl, const double* Uf, double* sigma, double* resid, void* X,
+                      hipStream_t st);
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
                         const double* Uf, void* X, hipStream_t st);
 

@@ -186,6 +186,7 @@ struct stau_pencils {
     double a0 = 0.0, b0 = 0.0;
     int64_t stamp = 0;
   } slot[2], slotT[2];    // slotT: factors of the transposed matrices (adjoint)
+  FactorSlot evp;         // factors of tau M~ + L~ + L~' (linear stability), whole-band layout
   PencilArgs paT{};       // band description of the transposed system
   // two-block solve of the forward system (FP64, 2-D, at most two blocks per
   // compute unit): leading / trailing block descriptions
@@ -292,7 +293,7 @@ void band_widths(const SysDesc& d, int64_t n, int* kl, int* ku) {
   int l = 0, u = 0;
   for (int mean = 0; mean < 2; ++mean) {
     PencilCoef pc{1.7, 1.3, 0.31, 0.67, 1.1, mean ? 0.0 : 0.93, (mean || d.dim == 2) ? 0.0 : 0.61,
-                  mean};
+                  mean, -0.83};  // the linear-stability term inside the band too
     for (int64_t r = 0; r < n; ++r) {
       const int64_t c0 = r - 6 * d.S < 0 ? 0 : r - 6 * d.S;
       const int64_t c1 = r + 7 * d.S > n ? n : r + 7 * d.S;
@@ -476,8 +477,8 @@ static void free_pencils(stau_pencils* p) {
   hipFree(p->Gb);
   hipFree(p->wvec);
   hipFree(p->rkbuf);
-  for (auto* set : {p->slot, p->slotT})
-    for (int k = 0; k < 2; ++k) {
+  for (auto* set : {p->slot, p->slotT, &p->evp})
+    for (int k = 0; k < (set == &p->evp ? 1 : 2); ++k) {
       auto& f = set[k];
       hipFree(f.Lraw);
       hipFree(f.sraw);
@@ -1084,6 +1085,42 @@ int stau_lbvp(stau_pencils* pen, const void* F, void* X, void* stream) {
   }
   HIP_TRY(launch_lbvp_rhs(pen->xa, F, pen->Bev, st));
   HIP_TRY(timed(pen, K_SOLVE, st, [&] { return solve_launch(pen, fs, 0.0, 1.0, pen->Bev, X, st, false); }));
+  return STAU_OK;
+}
+
+int stau_evp(stau_pencils* pen, double tau, int iters, double* sigma, double* resid, void* X,
+             void* stream) {
+  if (!pen || !sigma || !resid) return fail(STAU_EINVAL, "null argument");
+  if (!std::isfinite(tau)) return fail(STAU_EINVAL, "non-finite shift");
+  if (iters < 1 || iters > 100000) return fail(STAU_EINVAL, "iters must be in [1, 100000]");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  PencilArgs pe = pen->pa;
+  pe.lin = pen->par.b_top - pen->par.b_bottom;
+  auto& f = pen->evp;
+  if (!f.Lraw) {
+    size_t bytes = 0;
+    hipError_t e = alloc_slot(f, pe, false, &bytes);
+    if (e != hipSuccess) return fail(STAU_ENOMEM, "factor allocation failed: %s", hipGetErrorString(e));
+    pen->ws_bytes += (int64_t)bytes;
+  }
+  if (!f.valid || f.a0 != tau) {
+    f.valid = false;
+    const int big = 0x7fffffff;
+    HIP_TRY(hipMemcpyAsync(pen->sing, &big, sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(timed(pen, K_FACTOR, st, [&] { return launch_factor(pe, tau, 1.0, f.Lf, f.sl, f.Uf, pen->sing, st); }));
+    int h = big;
+    HIP_TRY(hipMemcpyAsync(&h, pen->sing, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h != big) {
+      pen->last_sing = h;
+      return fail(STAU_ESINGULAR, "zero or non-finite pivot in pencil %d (tau an eigenvalue?)", h);
+    }
+    f.valid = true;
+    f.a0 = tau;
+    f.b0 = 1.0;
+  }
+  HIP_TRY(timed(pen, K_SOLVE, st, [&] { return launch_evp(pe, tau, iters, f.Lf, f.sl, f.Uf, sigma, resid, X, st); }));
   return STAU_OK;
 }
 

@@ -63,11 +63,12 @@ int main() {
   double worst_row = 0, worst_col = 0;
   for (int dim = 2; dim <= 3; ++dim)
     for (int N : {4, 5, 16, 33})
-      for (int mean = 0; mean < 2; ++mean) {
+      for (int mean = 0; mean < 2; ++mean)
+      for (double lin : {0.0, -1.0}) {
         SysDesc d;
         build(dim, N, d);
         const PencilCoef pc{1.7e3, 1.0, 3e-4, 2e-4, 1.0, mean ? 0.0 : 3.3,
-                            (mean || dim == 2) ? 0.0 : 1.9, mean};
+                            (mean || dim == 2) ? 0.0 : 1.9, mean, lin};
         const int n = d.S * N;  // kb + (N - 1) S + 1 with kb = S - 1
         std::vector<double> x(n), y(n);
         for (auto& v : x) v = nd(gen);
