@@ -221,6 +221,40 @@ def rk_run(w, X_start, steps=100, warmup=3):
     return out
 
 
+def lbvp_evp_run(w, reps=50, evp_iters=200):
+    """The linear boundary value solve (factors cached) and the shift-invert
+    linear-stability iteration on the headline workload's pencils."""
+    import torch
+
+    import seeded_inputs as si
+    from paper_1905_10388_amd import RBSolver
+
+    Nx, Nz = w["Nx"], w["Nz"]
+    g = RBSolver(Nx, Nz, w["Lx"], w["Ra"], w["Pr"])
+    F = torch.from_numpy(si.complex_noise(g.ev_shape, 24)).cuda()
+    X = g.lbvp(F)  # factors L~
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        g.lbvp(F, out=X)
+    ev1.record()
+    torch.cuda.synchronize()
+    lbvp_ms = ev0.elapsed_time(ev1) / reps
+    g.evp(1.0, iters=1)  # factors 1 M~ + L~ + L~'
+    torch.cuda.synchronize()
+    ev0.record()
+    sig, res, _ = g.evp(1.0, iters=evp_iters)
+    ev1.record()
+    torch.cuda.synchronize()
+    evp_ms = ev0.elapsed_time(ev1)
+    g.close()
+    return {"lbvp_ms": lbvp_ms, "lbvp_pencils": Nx // 2,
+            "evp_iterations": evp_iters, "evp_ms": evp_ms, "evp_us_per_iteration": evp_ms * 1e3 / evp_iters,
+            "evp_tau": 1.0, "evp_top_sigma": float(sig.max())}
+
+
 EXTRA_WORKLOADS = {
     # 3-D Fourier x, y x Chebyshev z: 33,024 pencil slots per launch
     "rb3d_256x256x128_Ra1e7_dt5e-5": dict(dim=3, Nx=256, Ny=256, Nz=128, Lx=4.0, Ly=4.0, Ra=1e7,
@@ -463,6 +497,7 @@ def main():
         out["mixed"]["speedup_vs_fp64"] = out["mixed"]["value"] / value
     if not args.no_rk:
         out["runge_kutta"] = rk_run(w, X_end)
+        out["lbvp_evp"] = lbvp_evp_run(w)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio()
         out["adjoint_mixed"] = adjoint_mixed()
