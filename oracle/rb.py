@@ -15,6 +15,9 @@ fusion or fast transforms:
   variable-major (Kronecker block) ordering;
 * the multistep IMEX update of Sec. IX "Multistep IMEX integrators" with the
   semi-implicit BDF coefficients (first order on the first step);
+* an optional non-constant coefficient Gamma(z) w in the b equation
+  (Sec. II, non-constant coefficients: the product matrix of numpy's
+  Chebyshev multiplication, truncated to N modes);
 * the linear boundary value solve of Sec. IX "Linear boundary value
   solver" (`lbvp`);
 * the IMEX Runge-Kutta stages of Sec. IX "Runge-Kutta IMEX integrators"
@@ -37,6 +40,7 @@ import math
 from dataclasses import dataclass
 
 import numpy as np
+import numpy.polynomial.chebyshev as npc
 import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
@@ -62,6 +66,21 @@ def sbdf_coefficients(iteration: int, dt: float, dt_prev: float | None):
     a1 = -(1.0 + w) / dt
     a2 = w * w / ((1.0 + w) * dt)
     return a0, a1, a2, 1.0, 1.0 + w, -w
+
+
+def ncc_matrix(coeffs, N: int) -> np.ndarray:
+    """Multiplication by g = sum_k coeffs_k T_k as an N x N matrix on T
+    coefficients, the product truncated to the first N modes (Sec. II
+    "non-constant coefficients"): column j holds the T expansion of g T_j,
+    formed with numpy's Chebyshev product."""
+    G = np.zeros((N, N))
+    for j in range(N):
+        ej = np.zeros(j + 1)
+        ej[j] = 1.0
+        prod = npc.chebmul(np.asarray(coeffs, dtype=np.float64), ej)
+        m = min(N, prod.size)
+        G[:m, j] = prod[:m]
+    return G
 
 
 def rk_tableau(scheme: str):
@@ -107,6 +126,10 @@ class RBParams:
     buoyancy: float = 1.0   # coefficient of the -b term in the w equation
     b_bottom: float = 1.0   # b(z=0)
     b_top: float = 0.0      # b(z=1)
+    # non-constant coefficient Gamma(z) = sum_k gamma_k T_k(2 z - 1) multiplying
+    # w in the b equation (a background stratification: d_t b + Gamma w - ...);
+    # empty: none
+    gamma: tuple = ()
 
     @property
     def kappa(self) -> float:
@@ -229,6 +252,8 @@ class RBOracle:
             add(Mb, r, q, trunc @ C)
             add(Lb, r, q, trunc @ (diff * k2 * C))
             add(Lb, r, q + "z", trunc @ (-diff * D))
+            if q == "b" and len(self.par.gamma):
+                add(Lb, r, "w", trunc @ (C @ sp.csr_matrix(ncc_matrix(self.par.gamma, N))))
             if q == "u":
                 add(Lb, r, "p", trunc @ (1j * kx * C))
             elif q == "v":
