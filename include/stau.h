@@ -111,9 +111,20 @@ typedef struct stau_domain_desc {
 /* Rayleigh-Benard parameters in free-fall units: kappa = (Ra Pr)^(-1/2),
  * nu = (Ra / Pr)^(-1/2).  buoyancy multiplies the -b term of the w equation
  * (1 for convection, 0 for pure diffusion checks).  b_bottom / b_top are the
- * Dirichlet values of b at z = 0 / z = 1; u = (v =) w = 0 on both walls. */
+ * Dirichlet values of b at z = 0 / z = 1; u = (v =) w = 0 on both walls.
+ * n_gamma, gamma: an optional non-constant coefficient (Sec. II, NCCs)
+ * Gamma(z) = sum_{k < n_gamma} gamma[k] T_k(2 z - 1) multiplying w in the b
+ * equation (a background stratification: d_t b + Gamma w - kappa lap b = ...),
+ * entered on the left-hand side as its truncated Chebyshev product matrix.
+ * n_gamma in [0, 4] (0: none); it widens the pencil band by S per term, and
+ * stau_build_pencils returns STAU_EUNSUPPORTED when the band exceeds the
+ * sweep windows (kl < 32, kl + ku < 64: n_gamma <= 3).  The adjoint calls need
+ * the transposed band to fit too (n_gamma <= 1), else STAU_EUNSUPPORTED. */
 typedef struct stau_rb_params {
   double Ra, Pr, buoyancy, b_bottom, b_top;
+  int32_t n_gamma;
+  int32_t reserved;
+  double gamma[4];
 } stau_rb_params;
 
 /* Multistep state, caller owned.

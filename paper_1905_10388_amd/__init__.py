@@ -37,7 +37,8 @@ class RBSolver:
 
     def __init__(self, Nx: int, Nz: int, Lx: float, Ra: float, Pr: float, *, dim: int = 2,
                  Ny: int = 1, Ly: float = 1.0, precision: str = "fp64", buoyancy: float = 1.0,
-                 b_bottom: float = 1.0, b_top: float = 0.0, device: int = 0, dct: str = "auto"):
+                 b_bottom: float = 1.0, b_top: float = 0.0, device: int = 0, dct: str = "auto",
+                 gamma=()):
         import torch
 
         self._torch = torch
@@ -47,13 +48,19 @@ class RBSolver:
                                Nx=Nx, Ny=Ny, Nz=Nz, Lx=Lx, Ly=Ly, dealias=1.5, device=device,
                                dct_method={"auto": _lib.STAU_DCT_AUTO, "fft": _lib.STAU_DCT_FFT,
                                            "matmul": _lib.STAU_DCT_MATMUL}[dct])
+        gamma = tuple(float(g) for g in gamma)
+        if len(gamma) > 4:
+            raise ValueError("at most 4 Chebyshev terms of Gamma(z)")
         self._dom = C.c_void_p()
         _lib.check(lib.stau_create_domain(C.byref(desc), C.byref(self._dom)))
-        par = _lib.RBParamsC(Ra=Ra, Pr=Pr, buoyancy=buoyancy, b_bottom=b_bottom, b_top=b_top)
+        par = _lib.RBParamsC(Ra=Ra, Pr=Pr, buoyancy=buoyancy, b_bottom=b_bottom, b_top=b_top,
+                             n_gamma=len(gamma), gamma=(C.c_double * 4)(*(gamma + (0.0,) * (4 - len(gamma)))))
         self._pen = C.c_void_p()
         rc = lib.stau_build_pencils(self._dom, C.byref(par), C.byref(self._pen))
         if rc:
             lib.stau_destroy_domain(self._dom)
+            self._dom = None  # destroyed: close() must not free it again
+            self._pen = None
             _lib.check(rc)
         info = _lib.InfoC()
         _lib.check(lib.stau_query(self._pen, C.byref(info)))

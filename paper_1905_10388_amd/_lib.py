@@ -45,7 +45,8 @@ class DomainDesc(C.Structure):
 
 class RBParamsC(C.Structure):
     _fields_ = [("Ra", C.c_double), ("Pr", C.c_double), ("buoyancy", C.c_double),
-                ("b_bottom", C.c_double), ("b_top", C.c_double)]
+                ("b_bottom", C.c_double), ("b_top", C.c_double), ("n_gamma", C.c_int32),
+                ("reserved", C.c_int32), ("gamma", C.c_double * 4)]
 
 
 class StateC(C.Structure):

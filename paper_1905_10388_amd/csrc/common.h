@@ -229,6 +229,8 @@ struct SysDesc {
   int evolved[4];     // evolved Var in ABI evolved order (b, u, [v], w)
 };
 
+constexpr int kMaxNcc = 4;  // Chebyshev terms of the non-constant coefficient
+
 struct PencilCoef {
   double a0, b0, kappa, nu, buoy, kx, ky;
   int mean;
@@ -236,7 +238,24 @@ struct PencilCoef {
   // b0(z) = b_bottom + (b_top - b_bottom) z: lin = b_top - b_bottom times
   // P^L w on the b rows (linear-stability problems only; 0 for the step)
   double lin;
+  // non-constant coefficient Gamma(z) = sum_{k < nncc} ncc[k] T_k multiplying
+  // w in the b equation (P^L G w on the b rows, G the truncated product matrix)
+  int nncc;
+  double ncc[kMaxNcc];
 };
+
+// G(i, j) of the product matrix of Gamma: <T_i | Gamma T_j> from
+// T_k T_j = (T_{k+j} + T_{|k-j|}) / 2 (Sec. II, non-constant coefficients)
+__host__ __device__ inline double ncc_G(const PencilCoef& pc, int i, int j) {
+  double v = 0.0;
+  for (int k = 0; k < pc.nncc; ++k) {
+    double t = 0.0;
+    if (i == j + k) t += 1.0;
+    if (i == (j >= k ? j - k : k - j)) t += 1.0;
+    v += 0.5 * pc.ncc[k] * t;
+  }
+  return v;
+}
 
 // Entry (r, c) of a0 M~ + b0 L~ in the interleaved, Dirichlet-recombined,
 // real-scaled system of one pencil.  Rows: kb boundary rows, then modes
@@ -271,7 +290,15 @@ __host__ __device__ inline double entry_T(const SysDesc& d, const PencilCoef& pc
     case EB:
       if (var == VB) return (pc.a0 + pc.b0 * pc.kappa * k2) * cheb_C(n, m);
       if (var == VBZ) return -pc.b0 * pc.kappa * cheb_D(n, m);
-      if (var == VW) return pc.b0 * pc.lin * cheb_C(n, m);
+      if (var == VW) {
+        // (P^L (lin + G))(n, m) with P^L = C: rows n and n + 2 of G (truncated at N)
+        double v = pc.lin * cheb_C(n, m);
+        if (pc.nncc) {
+          v += (n == 0 ? 1.0 : 0.5) * ncc_G(pc, n, m);
+          if (n + 2 < d.N) v -= 0.5 * ncc_G(pc, n + 2, m);
+        }
+        return pc.b0 * v;
+      }
       return 0.0;
     case EU:
       if (var == VU) return (pc.a0 + pc.b0 * pc.nu * k2) * cheb_C(n, m);
@@ -366,7 +393,28 @@ __host__ __device__ inline double apply_row(const SysDesc& d, const PencilCoef& 
   const double k2 = pc.kx * pc.kx + pc.ky * pc.ky;
   const double ak = pc.a0 + pc.b0 * pc.kappa * k2, an = pc.a0 + pc.b0 * pc.nu * k2;
   switch (eq) {
-    case EB: return ak * Cv(VB, n) - pc.b0 * pc.kappa * Dv(VBZ, n) + pc.b0 * pc.lin * Cv(VW, n);
+    case EB: {
+      double v = ak * Cv(VB, n) - pc.b0 * pc.kappa * Dv(VBZ, n) + pc.b0 * pc.lin * Cv(VW, n);
+      if (pc.nncc) {
+        // C (G w_T): (G y)_i = sum_j G(i, j) y_j, the j with i = j + k or
+        // i = |j - k|: (G y)_i = sum_k g_k ([i >= k] y_{i-k} + y_{i+k}
+        // + [0 < i <= k] y_{k-i}) / 2 over stored modes
+        auto Gw = [&](int i) {
+          double a = 0.0;
+          for (int k = 0; k < pc.nncc; ++k) {
+            double t = xT(VW, i + k);
+            if (i >= k) t += xT(VW, i - k);
+            if (i > 0 && k >= i) t += xT(VW, k - i);
+            a += 0.5 * pc.ncc[k] * t;
+          }
+          return a;
+        };
+        double g = (n == 0 ? 1.0 : 0.5) * Gw(n);
+        if (n + 2 < N) g -= 0.5 * Gw(n + 2);
+        v += pc.b0 * g;
+      }
+      return v;
+    }
     case EU: return an * Cv(VU, n) - pc.b0 * pc.nu * Dv(VUZ, n) - pc.b0 * pc.kx * Cv(VP, n);
     case EV: return an * Cv(VV, n) - pc.b0 * pc.nu * Dv(VVZ, n) - pc.b0 * pc.ky * Cv(VP, n);
     case EW:
@@ -419,7 +467,15 @@ __host__ __device__ inline double apply_col(const SysDesc& d, const PencilCoef& 
       case VUZ: return -b0 * pc.nu * DT(EU, q) + b0 * CT(EUZ, q);
       case VV: return an * CT(EV, q) - b0 * DT(EVZ, q) + b0 * pc.ky * yrow(q, EC);
       case VVZ: return -b0 * pc.nu * DT(EV, q) + b0 * CT(EVZ, q);
-      case VW: return an * CT(EW, q) - b0 * DT(EWZ, q) + b0 * pc.lin * CT(EB, q);
+      case VW: {
+        double v = an * CT(EW, q) - b0 * DT(EWZ, q) + b0 * pc.lin * CT(EB, q);
+        // G^T C^T y: (G^T z)(q) = sum_k g_k (z(q + k) + z(|q - k|)) / 2, z = C^T y over rows < N
+        for (int k = 0; k < pc.nncc; ++k) {
+          const int i1 = q + k, i2 = q >= k ? q - k : k - q;
+          v += 0.5 * b0 * pc.ncc[k] * ((i1 < N ? CT(EB, i1) : 0.0) + CT(EB, i2));
+        }
+        return v;
+      }
       case VWZ: return -b0 * pc.nu * DT(EW, q) + b0 * CT(EWZ, q) + b0 * yrow(q, EC);
       case VP: return -b0 * pc.kx * CT(EU, q) - b0 * pc.ky * CT(EV, q) + b0 * DT(EW, q);
     }

@@ -88,6 +88,9 @@ __device__ __forceinline__ PencilCoef pencil_coef(const PencilArgs& a, int p, do
   pc.kx = a.two_pi_over_Lx * (double)ix;
   pc.mean = (ix == 0 && iy == 0);
   pc.lin = a.lin;
+  pc.nncc = a.nncc;
+#pragma unroll
+  for (int k = 0; k < kMaxNcc; ++k) pc.ncc[k] = a.ncc[k];
   return pc;
 }
 

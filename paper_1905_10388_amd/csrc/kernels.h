@@ -24,6 +24,8 @@ struct PencilArgs {
   int P, Px, Ny;
   double kappa, nu, buoyancy, b_bottom, b_top;
   double lin;  // PencilCoef::lin of every pencil (0 for the step's operators)
+  int nncc;    // non-constant coefficient Gamma(z): Chebyshev terms (0: none)
+  double ncc[kMaxNcc];
   double two_pi_over_Lx, two_pi_over_Ly;
   int var_of_abi[9];
 };

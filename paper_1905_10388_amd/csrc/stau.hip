@@ -192,6 +192,7 @@ struct stau_pencils {
   // compute unit): leading / trailing block descriptions
   bool two = false;
   PencilArgs pt{}, pb{};
+  bool adj_ok = true;  // the transposed band fits the sweep windows
   int64_t clock = 0;
   FactorSlot* last = nullptr;  // factors of the most recent stau_factor
   int* sing = nullptr;     // device: first singular pencil (INT_MAX if none)
@@ -289,11 +290,12 @@ void build_sysdesc(int dim, int N, SysDesc& d, int* var_of_abi) {
 
 // Band widths of the interleaved system from its structure (generic
 // coefficients, plus the mean pencil for the gauge row).
-void band_widths(const SysDesc& d, int64_t n, int* kl, int* ku) {
+void band_widths(const SysDesc& d, int64_t n, int nncc, int* kl, int* ku) {
   int l = 0, u = 0;
   for (int mean = 0; mean < 2; ++mean) {
+    // the linear-stability term and the non-constant coefficient inside the band too
     PencilCoef pc{1.7, 1.3, 0.31, 0.67, 1.1, mean ? 0.0 : 0.93, (mean || d.dim == 2) ? 0.0 : 0.61,
-                  mean, -0.83};  // the linear-stability term inside the band too
+                  mean, -0.83, nncc, {0.7, -0.4, 0.25, 0.1}};
     for (int64_t r = 0; r < n; ++r) {
       const int64_t c0 = r - 6 * d.S < 0 ? 0 : r - 6 * d.S;
       const int64_t c1 = r + 7 * d.S > n ? n : r + 7 * d.S;
@@ -583,13 +585,19 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   build_sysdesc(d.dim, N, pa.desc, pa.var_of_abi);
   pen->n = (int64_t)pa.desc.S * N;
   pa.n = (int)pen->n;
-  band_widths(pa.desc, pen->n, &pa.kl, &pa.ku);
+  if (par->n_gamma < 0 || par->n_gamma > kMaxNcc) {
+    delete pen;
+    return fail(STAU_EINVAL, "n_gamma must be in [0, %d]", kMaxNcc);
+  }
+  pa.nncc = par->n_gamma;
+  for (int k = 0; k < kMaxNcc; ++k) pa.ncc[k] = k < pa.nncc ? par->gamma[k] : 0.0;
+  band_widths(pa.desc, pen->n, pa.nncc, &pa.kl, &pa.ku);
   pa.nst = factor_stride(pa.n);
   pa.trans = 0;
   PencilArgs& paT = pen->paT;  // filled below from pa
   if (!window_widths(pa)) {
     delete pen;
-    return fail(STAU_EUNSUPPORTED, "band too wide (kl=%d, ku=%d)", pa.kl, pa.ku);
+    return fail(STAU_EUNSUPPORTED, "band too wide (kl=%d, ku=%d; n_gamma=%d)", pa.kl, pa.ku, pa.nncc);
   }
   pa.P = (int)dom->P;
   pa.Px = (int)dom->Px;
@@ -605,10 +613,9 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   paT.kl = pa.ku;
   paT.ku = pa.kl;
   paT.trans = 1;
-  if (!window_widths(paT)) {
-    delete pen;
-    return fail(STAU_EUNSUPPORTED, "transposed band too wide (kl=%d, ku=%d)", paT.kl, paT.ku);
-  }
+  // the transposed operator (adjoint) swaps kl and ku; when it does not fit the
+  // sweep windows the adjoint calls are refused for this pencils object
+  pen->adj_ok = window_widths(paT);
   // Two-block solve for FP64 2-D domains with at most two pencils per compute
   // unit: the system splits at m = kb + S k near n / 2 (a leading block that
   // ends inside a mode is singular) into two halves swept in parallel.
@@ -1162,6 +1169,7 @@ int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, 
                       double dt_prev, stau_adjstate* adj, void* stream) {
   if (!pen || !X_prev || !adj || !adj->Xbar || !adj->hbar) return fail(STAU_EINVAL, "null argument");
   if (pen->dom->d.dim != 2) return fail(STAU_EUNSUPPORTED, "the adjoint is built for 2-D domains");
+  if (!pen->adj_ok) return fail(STAU_EUNSUPPORTED, "transposed band too wide for the adjoint (n_gamma)");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(STAU_EINVAL, "dt must be positive");
   if (iteration < 0 || (iteration > 0 && !(dt_prev > 0.0)))
     return fail(STAU_EINVAL, "iteration / dt_prev inconsistent");

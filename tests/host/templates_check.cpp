@@ -64,11 +64,14 @@ int main() {
   for (int dim = 2; dim <= 3; ++dim)
     for (int N : {4, 5, 16, 33})
       for (int mean = 0; mean < 2; ++mean)
+      for (int nn = 0; nn <= kMaxNcc; nn += 2)
       for (double lin : {0.0, -1.0}) {
         SysDesc d;
         build(dim, N, d);
-        const PencilCoef pc{1.7e3, 1.0, 3e-4, 2e-4, 1.0, mean ? 0.0 : 3.3,
-                            (mean || dim == 2) ? 0.0 : 1.9, mean, lin};
+        PencilCoef pc{1.7e3, 1.0, 3e-4, 2e-4, 1.0, mean ? 0.0 : 3.3,
+                      (mean || dim == 2) ? 0.0 : 1.9, mean, lin, nn, {0.7, -0.4, 0.25, 0.1}};
+        if (nn == 0) pc.nncc = 0;
+        if (nn == 2) pc.nncc = 3;
         const int n = d.S * N;  // kb + (N - 1) S + 1 with kb = S - 1
         std::vector<double> x(n), y(n);
         for (auto& v : x) v = nd(gen);
