@@ -255,6 +255,41 @@ def lbvp_evp_run(w, reps=50, evp_iters=200):
             "evp_tau": 1.0, "evp_top_sigma": float(sig.max())}
 
 
+def ncc_run(w, X_start, steps=100, warmup=5):
+    """SBDF2 steps of the headline workload with a non-constant coefficient
+    Gamma(z) w in the b equation: one Chebyshev term (same band, two-block
+    solve) and three terms (band kl = 21, ku = 35: whole-band solve)."""
+    import torch
+
+    from paper_1905_10388_amd import RBSolver
+
+    Nx, Nz, dt = w["Nx"], w["Nz"], w["dt"]
+    out = {}
+    for name, gamma in (("gamma_1term", (0.5,)), ("gamma_3term", (0.2, 0.15, -0.1))):
+        g = RBSolver(Nx, Nz, w["Lx"], w["Ra"], w["Pr"], gamma=gamma)
+        g.set_state(X_start)
+        for _ in range(warmup):
+            g.step(dt)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            g.step(dt)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        g.check()
+        g.set_kernel_timing(True)
+        for _ in range(10):
+            g.step(dt)
+        kt = {k: round(v * 1e3 / c, 3) for k, (v, c) in g.read_kernel_timing().items() if c}
+        out[name] = {"gamma": list(gamma), "kl": g.info["kl"], "ku": g.info["ku"], "ms_per_step": ms,
+                     "value": 7 * Nx * Nz / (ms * 1e-3), "kernels_avg_us": kt}
+        g.close()
+    return out
+
+
 EXTRA_WORKLOADS = {
     # 3-D Fourier x, y x Chebyshev z: 33,024 pencil slots per launch
     "rb3d_256x256x128_Ra1e7_dt5e-5": dict(dim=3, Nx=256, Ny=256, Nz=128, Lx=4.0, Ly=4.0, Ra=1e7,
@@ -498,6 +533,7 @@ def main():
     if not args.no_rk:
         out["runge_kutta"] = rk_run(w, X_end)
         out["lbvp_evp"] = lbvp_evp_run(w)
+        out["ncc"] = ncc_run(w, X_end)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio()
         out["adjoint_mixed"] = adjoint_mixed()

@@ -116,10 +116,11 @@ typedef struct stau_domain_desc {
  * Gamma(z) = sum_{k < n_gamma} gamma[k] T_k(2 z - 1) multiplying w in the b
  * equation (a background stratification: d_t b + Gamma w - kappa lap b = ...),
  * entered on the left-hand side as its truncated Chebyshev product matrix.
- * n_gamma in [0, 4] (0: none); it widens the pencil band by S per term, and
- * stau_build_pencils returns STAU_EUNSUPPORTED when the band exceeds the
- * sweep windows (kl < 32, kl + ku < 64: n_gamma <= 3).  The adjoint calls need
- * the transposed band to fit too (n_gamma <= 1), else STAU_EUNSUPPORTED. */
+ * n_gamma in [0, 4] (0: none, else STAU_EINVAL); it widens the pencil band
+ * by about S per term, and stau_build_pencils returns STAU_EUNSUPPORTED when
+ * the band exceeds the sweep windows (kl < 32, kl + ku < 64: n_gamma <= 3 in
+ * 2-D, <= 2 in 3-D).  The adjoint calls need the transposed band to fit too
+ * (2-D: n_gamma <= 2), else they return STAU_EUNSUPPORTED. */
 typedef struct stau_rb_params {
   double Ra, Pr, buoyancy, b_bottom, b_top;
   int32_t n_gamma;
