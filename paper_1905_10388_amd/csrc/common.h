@@ -246,9 +246,12 @@ struct PencilCoef {
 
 // G(i, j) of the product matrix of Gamma: <T_i | Gamma T_j> from
 // T_k T_j = (T_{k+j} + T_{|k-j|}) / 2 (Sec. II, non-constant coefficients)
-__host__ __device__ inline double ncc_G(const PencilCoef& pc, int i, int j) {
+__host__ __device__ __forceinline__ double ncc_G(const PencilCoef& pc, int i, int j) {
   double v = 0.0;
-  for (int k = 0; k < pc.nncc; ++k) {
+  // fixed trip count: the coefficients stay in registers (no scratch array)
+#pragma unroll
+  for (int k = 0; k < kMaxNcc; ++k) {
+    if (k >= pc.nncc) break;
     double t = 0.0;
     if (i == j + k) t += 1.0;
     if (i == (j >= k ? j - k : k - j)) t += 1.0;
@@ -283,7 +286,7 @@ __host__ __device__ inline double cheb_D(int n, int m) {  // d/dz (z in [0,1]) T
 }
 
 // T-basis entry (row (n, eq), column (m, var)); real-scaled.
-__host__ __device__ inline double entry_T(const SysDesc& d, const PencilCoef& pc, int n, int eq,
+__host__ __device__ __forceinline__ double entry_T(const SysDesc& d, const PencilCoef& pc, int n, int eq,
                                           int m, int var) {
   const double k2 = pc.kx * pc.kx + pc.ky * pc.ky;
   switch (eq) {
@@ -342,7 +345,7 @@ __host__ __device__ inline double entry_T(const SysDesc& d, const PencilCoef& pc
   return 0.0;
 }
 
-__host__ __device__ inline double sys_entry(const SysDesc& d, const PencilCoef& pc, int r, int c) {
+__host__ __device__ __forceinline__ double sys_entry(const SysDesc& d, const PencilCoef& pc, int r, int c) {
   const int m = c / d.S;
   const int var = d.var_at[c - m * d.S];
   if (r < d.kb) {
@@ -394,14 +397,17 @@ __host__ __device__ inline double apply_row(const SysDesc& d, const PencilCoef& 
   const double ak = pc.a0 + pc.b0 * pc.kappa * k2, an = pc.a0 + pc.b0 * pc.nu * k2;
   switch (eq) {
     case EB: {
-      double v = ak * Cv(VB, n) - pc.b0 * pc.kappa * Dv(VBZ, n) + pc.b0 * pc.lin * Cv(VW, n);
+      double v = ak * Cv(VB, n) - pc.b0 * pc.kappa * Dv(VBZ, n);
+      if (pc.lin != 0.0) v += pc.b0 * pc.lin * Cv(VW, n);  // uniform branch: no reads when absent
       if (pc.nncc) {
         // C (G w_T): (G y)_i = sum_j G(i, j) y_j, the j with i = j + k or
         // i = |j - k|: (G y)_i = sum_k g_k ([i >= k] y_{i-k} + y_{i+k}
         // + [0 < i <= k] y_{k-i}) / 2 over stored modes
         auto Gw = [&](int i) {
           double a = 0.0;
-          for (int k = 0; k < pc.nncc; ++k) {
+#pragma unroll
+          for (int k = 0; k < kMaxNcc; ++k) {
+            if (k >= pc.nncc) break;
             double t = xT(VW, i + k);
             if (i >= k) t += xT(VW, i - k);
             if (i > 0 && k >= i) t += xT(VW, k - i);
@@ -468,9 +474,12 @@ __host__ __device__ inline double apply_col(const SysDesc& d, const PencilCoef& 
       case VV: return an * CT(EV, q) - b0 * DT(EVZ, q) + b0 * pc.ky * yrow(q, EC);
       case VVZ: return -b0 * pc.nu * DT(EV, q) + b0 * CT(EVZ, q);
       case VW: {
-        double v = an * CT(EW, q) - b0 * DT(EWZ, q) + b0 * pc.lin * CT(EB, q);
+        double v = an * CT(EW, q) - b0 * DT(EWZ, q);
+        if (pc.lin != 0.0) v += b0 * pc.lin * CT(EB, q);
         // G^T C^T y: (G^T z)(q) = sum_k g_k (z(q + k) + z(|q - k|)) / 2, z = C^T y over rows < N
-        for (int k = 0; k < pc.nncc; ++k) {
+#pragma unroll
+        for (int k = 0; k < kMaxNcc; ++k) {
+          if (k >= pc.nncc) break;
           const int i1 = q + k, i2 = q >= k ? q - k : k - q;
           v += 0.5 * b0 * pc.ncc[k] * ((i1 < N ? CT(EB, i1) : 0.0) + CT(EB, i2));
         }
