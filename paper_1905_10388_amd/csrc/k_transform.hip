@@ -549,6 +549,151 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
 }
 
 // ---------------------------------------------------------------------------
+// 2-D x pass with the field pairs transformed two at a time: the backward
+// transforms of pairs (0, 1) and (2, 3), and the forward ones of (N_b, N_u)
+// and N_w, each run as one batch of two sequences, so a row takes half the
+// radix passes and barriers of one pair at a time (the passes are latency
+// bound: a radix-8 pass of one 1536-point sequence keeps 192 of 512 threads
+// busy).  Data [2][L] and twiddles [L] in LDS.  Same products and outputs as
+// xrow_kernel<2>; SPLIT as there (part 0: pairs (0, 1), (2) and N_b, N_u;
+// part 1: pairs (0, 3) and N_w).
+// ---------------------------------------------------------------------------
+template <int NT, int PTS, int MAXBF, typename T, bool SPLIT>
+__global__ void __launch_bounds__(NT) xrow2_kernel(XformArgs a,
+                                                   const typename V2<T>::type* __restrict__ G,
+                                                   typename V2<T>::type* __restrict__ H) {
+  extern __shared__ double2 smem[];
+  using cT = cpx<T>;
+  using S2 = typename V2<T>::type;
+  constexpr int KPT = (PTS + 2) / 3;  // half-spectrum entries per thread (Pa = L / 3)
+  cT* buf = (cT*)smem;                // two sequences of L points
+  const int r = blockIdx.x;
+  const int L = a.L, Pa = a.Pa, Px = a.Px;
+  const size_t R = (size_t)a.M;
+  const int tid = threadIdx.x;
+  const cT* twg = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
+  cT* twl = buf + 2 * L;
+  for (int i = tid; i < L; i += NT) twl[i] = twg[i];
+  const int part = SPLIT ? (int)blockIdx.y : 0;
+  // the block's batches of pairs (-1: none): (0, 1), (2, 3); SPLIT part 0
+  // (0, 1), (2); part 1 (0, 3)
+  const bool p1 = SPLIT && part == 1;
+  const int b01 = p1 ? 3 : 1, b10 = p1 ? -1 : 2, b11 = SPLIT ? -1 : 3;
+  const int nbatch = p1 ? 1 : 2;
+  cT sa[2][KPT], sb[2][KPT];
+  auto fetch = [&](int slot, int k) {
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      sa[slot][q] = mk<T>(0, 0);
+      sb[slot][q] = mk<T>(0, 0);
+    }
+    if (k < 0) return;
+    const S2* A = G + ((size_t)(2 * k) * R + r) * Px;
+    const S2* B = G + ((size_t)(2 * k + 1) * R + r) * Px;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int kk = tid + q * NT;
+      if (kk < Pa) {
+        sa[slot][q] = ldv<T>(A + kk);
+        sb[slot][q] = ldv<T>(B + kk);
+      }
+    }
+  };
+  // Hermitian extension of the packed pair A + i B onto sequence `slot`
+  auto scatter = [&](int slot) {
+    cT* bb = buf + slot * L;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int kk = tid + q * NT;
+      if (kk < Pa) {
+        cT Ak = sa[slot][q], Bk = sb[slot][q];
+        if (kk == 0) {
+          Ak.y = 0;
+          Bk.y = 0;
+        }
+        bb[kk] = mk<T>(Ak.x - Bk.y, Ak.y + Bk.x);
+        if (kk > 0) bb[L - kk] = mk<T>(Ak.x + Bk.y, -Ak.y + Bk.x);
+      }
+    }
+    for (int k = Pa + tid; k <= L - Pa; k += NT) bb[k] = mk<T>(0, 0);
+  };
+
+  T u[PTS], w[PTS], nb[PTS], nu[PTS], nw[PTS];
+  auto take = [&](int pk, int q, T x, T y) {  // the pair's two real fields at point q
+    if (pk == 0) {
+      u[q] = x;
+      w[q] = y;
+    }
+    if (pk == 1) nb[q] = -(u[q] * x + w[q] * y);
+    if (pk == 2) nu[q] = -(u[q] * x + w[q] * y);
+    if (pk == 3) nw[q] = -(u[q] * x + w[q] * y);
+  };
+  fetch(0, 0);
+  fetch(1, b01);
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi) {
+    if (bi >= nbatch) break;
+    const int k0 = bi == 0 ? 0 : b10, k1 = bi == 0 ? b01 : b11;
+    scatter(0);
+    if (k1 >= 0) scatter(1);
+    if (bi == 0 && nbatch == 2) {
+      fetch(0, b10);
+      fetch(1, b11);
+    }
+    __syncthreads();
+    fft_lds<+1, MAXBF, T, true>(buf, L, k1 >= 0 ? 2 : 1, twl, tid, NT);
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) {
+      const int i = tid + q * NT;
+      if (i < L) {
+        const cT x0 = buf[i];
+        take(k0, q, x0.x, x0.y);
+        if (k1 >= 0) {
+          const cT x1 = buf[L + i];
+          take(k1, q, x1.x, x1.y);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // forward: sequence 0 = N_b + i N_u (part 0), sequence 1 (or 0) = N_w
+  const bool f0 = !SPLIT || part == 0, f1 = !SPLIT || part == 1;
+  const int s1 = f0 ? 1 : 0;
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    const int i = tid + q * NT;
+    if (i < L) {
+      if (f0) buf[i] = mk<T>(nb[q], nu[q]);
+      if (f1) buf[s1 * L + i] = mk<T>(nw[q], (T)0);
+    }
+  }
+  __syncthreads();
+  fft_lds<-1, MAXBF, T, true>(buf, L, (f0 && f1) ? 2 : 1, twl, tid, NT);
+  const T invL = (T)1 / (T)L;
+  const T hf = (T)0.5;
+  S2* H0 = H + (size_t)r * Px;
+  S2* H1 = H + (R + r) * Px;
+  S2* H2 = H + (2 * R + r) * Px;
+  for (int k = tid; k < Px; k += NT) {
+    cT A = mk<T>(0, 0), Bv = mk<T>(0, 0), Wv = mk<T>(0, 0);
+    if (k < Pa) {
+      if (f0) {
+        const cT Zk = buf[k], Zm = buf[k == 0 ? 0 : L - k];
+        A = mk<T>(hf * (Zk.x + Zm.x) * invL, hf * (Zk.y - Zm.y) * invL);
+        Bv = mk<T>(hf * (Zk.y + Zm.y) * invL, -hf * (Zk.x - Zm.x) * invL);
+      }
+      if (f1) Wv = scale(buf[s1 * L + k], invL);
+    }
+    if (f0) {
+      stv<T>(H0 + k, A);
+      stv<T>(H1 + k, Bv);
+    }
+    if (f1) stv<T>(H2 + k, Wv);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Initial state: scale-1 forward x transform of the b grid (one z level per
 // block), then the z forward transform (zf_kernel, mode 0) and the fill below.
 // ---------------------------------------------------------------------------
@@ -1169,6 +1314,16 @@ static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipS
                      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
                      rows < (sizeof(T) == 4 ? 2 * cus : cus);
   const dim3 grid(rows, split ? 2 : 1);
+  // 2-D: pairs two at a time when two sequences and the twiddles fit 80 KB
+  if constexpr (DIM == 2) {
+    const size_t lds2 = (size_t)3 * a.L * sizeof(S2);
+    if (lds2 <= 80 * 1024) {
+      auto fn = split ? xrow2_kernel<NT, PTS, 2 * MAXBF, T, true> : xrow2_kernel<NT, PTS, 2 * MAXBF, T, false>;
+      allow_lds((const void*)fn, lds2);
+      hipLaunchKernelGGL(fn, grid, dim3(NT), lds2, st, a, (const S2*)G, (S2*)H);
+      return hipGetLastError();
+    }
+  }
   if (twl) {
     auto fn = split ? xrow_kernel<DIM, NT, PTS, MAXBF, true, T, true> : xrow_kernel<DIM, NT, PTS, MAXBF, true, T, false>;
     allow_lds((const void*)fn, lds);
