@@ -307,8 +307,11 @@ __device__ __forceinline__ void sweep_forward(T* b, const T* __restrict__ Lp,
         const T l = ring[t % D];
         ring[t % D] = Ln[t * FW];
         if ((t & 3) == 3) sring[(t >> 2) % (D / 4)] = Sn[t >> 2];
-        // lane s takes the next row; the lane mask is formed on the scalar unit
-        w = __builtin_amdgcn_inverse_ballot_w64(1ull << s) ? nv[g & 1][k] : fma(-l, y, w);
+        // lane s takes the next row (the lane mask is formed on the scalar
+        // unit); its multiplier is 0, so the select is made before the
+        // update, beside the lane read instead of after the FMA
+        const T ws = __builtin_amdgcn_inverse_ballot_w64(1ull << s) ? nv[g & 1][k] : w;
+        w = fma(-l, y, ws);
       });
       if (g + 1 < CH / G) {
 #pragma unroll
@@ -479,7 +482,8 @@ __device__ __forceinline__ void sweep_forward_staged(T* b, const T* __restrict__
         const T l = ring[t % R];
         constexpr int tn = t + R;  // column read ahead, buffer by its unit's parity
         ring[t % R] = st[((tn / SU) & 1) * SU * FW + (tn % SU) * FW + lf];
-        w = __builtin_amdgcn_inverse_ballot_w64(1ull << s) ? nv[g & 1][k] : fma(-l, y, w);
+        const T ws = __builtin_amdgcn_inverse_ballot_w64(1ull << s) ? nv[g & 1][k] : w;
+        w = fma(-l, y, ws);  // multiplier 0 at the pivot slot: the select precedes the update
       });
       if (g + 1 < CH / G) {
 #pragma unroll
