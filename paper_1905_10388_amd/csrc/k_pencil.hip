@@ -974,7 +974,7 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
   double* stg = cR + solve2_coupling_doubles(K, Q) + (size_t)wv * SB;
   double* v = half == 0 ? (part == 0 ? vt0 : vt1) : (part == 0 ? vb0 : vb1);
   // the pencil's coupling data, loaded now and stored to LDS after the
-  // right-hand side (needed after the forward sweeps)
+  // forward sweeps (needed only then)
   constexpr int kCpl = 8;  // coupling doubles per thread (K K + Q (kl + ku) <= 8 * 256)
   double cpl[kCpl];
   {
@@ -1006,20 +1006,34 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
     const int mlo = half == 0 ? 0 : (mcut > 0 ? mcut - 1 : 0);
     const int mhi = half == 0 ? (mcut + 1 < N - 1 ? mcut + 1 : N - 1) : N - 1;
     const int Nm = mhi - mlo;
-    for (int i = lane; i < ne * Nm; i += kWave) {
-      const int e = i / Nm, mo = mlo + (i - e * Nm);
-      const int eq = e == 0 ? EB : (e == ne - 1 ? EW : (e == 1 ? EU : EV));
-      const int Rw = kb + mo * S + d.eq_pos[eq];
-      if ((half == 0) != (Rw < m)) continue;
-      const double2 b2 = Bp[e * N + mo];
-      const bool scaled = eq == EU || eq == EV;  // row scaled by i
-      v[half == 0 ? Rw : n - 1 - Rw] = part == 0 ? (scaled ? -b2.y : b2.x) : (scaled ? b2.x : b2.y);
-    }
-  }
+    // groups of kRG entries per lane: all loads of a group in flight together
+    constexpr int kRG = 8;
+    for (int i0 = lane; i0 < ne * Nm; i0 += kRG * kWave) {
+      double2 b2[kRG];
+      int dst[kRG];
 #pragma unroll
-  for (int u = 0; u < kCpl; ++u) {
-    const int i = tid + u * 4 * kWave;
-    if (i < solve2_coupling_doubles(K, Q)) cR[i] = cpl[u];
+      for (int u = 0; u < kRG; ++u) {
+        const int i = i0 + u * kWave;
+        dst[u] = -1;
+        b2[u] = make_double2(0.0, 0.0);
+        if (i < ne * Nm) {
+          const int e = i / Nm, mo = mlo + (i - e * Nm);
+          const int eq = e == 0 ? EB : (e == ne - 1 ? EW : (e == 1 ? EU : EV));
+          const int Rw = kb + mo * S + d.eq_pos[eq];
+          if ((half == 0) == (Rw < m)) {
+            b2[u] = Bp[e * N + mo];
+            // rows scaled by i (u, v equations) take (-Im, Re)
+            dst[u] = (half == 0 ? Rw : n - 1 - Rw) * 2 + ((eq == EU || eq == EV) ? 1 : 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kRG; ++u) {
+        if (dst[u] < 0) continue;
+        const bool scaled = dst[u] & 1;
+        v[dst[u] >> 1] = part == 0 ? (scaled ? -b2[u].y : b2[u].x) : (scaled ? b2[u].x : b2[u].y);
+      }
+    }
   }
   if (half == 0)
     sweep_forward_staged<double, FWT, kSU2>(v, Lft + (size_t)p * t.nst * FWT,
@@ -1029,6 +1043,13 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
     sweep_forward_staged<double, FWB, kSU2>(v, Lfb + (size_t)p * bt.nst * FWB,
                                             (const uint32_t*)(slb + (size_t)p * bt.nst), bt.nst / kCH,
                                             lane, stg);
+  // the coupling data, loaded at the start, reach LDS only now (their loads
+  // completed during the sweep instead of delaying it)
+#pragma unroll
+  for (int u = 0; u < kCpl; ++u) {
+    const int i = tid + u * 4 * kWave;
+    if (i < solve2_coupling_doubles(K, Q)) cR[i] = cpl[u];
+  }
   __syncthreads();
   if (half == 0 && lane < K) {
     // interface system of this part: z = Rinv [g1b; g2b]
