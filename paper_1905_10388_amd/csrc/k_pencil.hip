@@ -422,10 +422,25 @@ constexpr int stage_bytes() {
   return 2 * SU * (FW > BW ? FW : BW) * (int)sizeof(T);
 }
 
+// Two sweeping wavefronts share each SIMD in the two-block solve, and the
+// instruction arbiter prefers the older one, so the second block on a compute
+// unit ran its sweeps about 1.5x slower than the first.  Taking turns at a
+// raised wave priority in the forward sweeps, chunk by chunk (psel = 0 or 1
+// for the two blocks that share a unit), evens their progress (forward 93k /
+// 137k cycles -> 101k / 115k); the slowest wavefront sets the kernel time.
+// Turns every 16 columns, or also in the backward sweeps (whose skew is
+// small), measured slower.
+__device__ __forceinline__ void prio_turn(int chunk, int psel) {
+  if ((chunk + psel) & 1)
+    __builtin_amdgcn_s_setprio(1);
+  else
+    __builtin_amdgcn_s_setprio(0);
+}
+
 template <typename T, int FW, int SU>
 __device__ __forceinline__ void sweep_forward_staged(T* b, const T* __restrict__ Lp,
                                                      const uint32_t* __restrict__ sw, int nch,
-                                                     int lane, T* st) {
+                                                     int lane, T* st, int psel = -1) {
   constexpr int CH = kCH, G = 16, R = kSR, UPC = CH / SU;
   static_assert(CH % SU == 0 && UPC % 2 == 0 && R <= SU && CH % G == 0 && FW <= 32,
                 "sweep geometry");
@@ -444,6 +459,7 @@ __device__ __forceinline__ void sweep_forward_staged(T* b, const T* __restrict__
   uint32_t swv = sw[lane & 15];
   T w = lane < FW ? b[lane] : (T)0;
   for (int c = 0; c < nch; ++c) {
+    if (psel >= 0) prio_turn(c, psel);
     const int j0 = c * CH;
     const uint32_t swc = swv;
     if (c + 1 < nch) swv = sw[(j0 + CH) / 4 + (lane & 15)];
@@ -1035,14 +1051,17 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
       }
     }
   }
+  // blocks p and p + gridDim / 2 share a compute unit (two per unit)
+  const int psel = p >= (int)(gridDim.x / 2) ? 1 : 0;
   if (half == 0)
     sweep_forward_staged<double, FWT, kSU2>(v, Lft + (size_t)p * t.nst * FWT,
                                             (const uint32_t*)(slt + (size_t)p * t.nst), t.nst / kCH,
-                                            lane, stg);
+                                            lane, stg, psel);
   else
     sweep_forward_staged<double, FWB, kSU2>(v, Lfb + (size_t)p * bt.nst * FWB,
                                             (const uint32_t*)(slb + (size_t)p * bt.nst), bt.nst / kCH,
-                                            lane, stg);
+                                            lane, stg, psel);
+  __builtin_amdgcn_s_setprio(0);
   // the coupling data, loaded at the start, reach LDS only now (their loads
   // completed during the sweep instead of delaying it)
 #pragma unroll
