@@ -83,7 +83,10 @@ typedef struct stau_pencils stau_pencils;
  *          factorisation rounded to FP32 for the sweeps; FP32 solve, FP64
  *          residual of the full system (boundary rows included) from the
  *          operator templates, one FP32 correction sweep, FP64 accumulation;
- *          state, history, right-hand side and their adjoints FP64).  The
+ *          state, history, right-hand side and their adjoints FP64).  2-D
+ *          launches of at most two pencils per compute unit are latency
+ *          bound; there the step's solve runs as the FP64 two-block solve,
+ *          which is faster than the FP32 sweeps and residual.  The
  *          component calls (stau_nonlinear, stau_solve) and the
  *          kinetic-energy and initial-state adjoints run in FP64 in either
  *          mode.
@@ -96,7 +99,7 @@ typedef struct stau_pencils stau_pencils;
  *          run as split-BF16 matrix-core products with FP32 accumulation
  *          (each operand split into three BF16 terms): STAU_DCT_MATMUL needs
  *          Nz = 64, 128 or 256 there (else STAU_EUNSUPPORTED) and
- *          STAU_DCT_AUTO takes them for those Nz; otherwise the mixed step
+ *          STAU_DCT_AUTO takes them for Nz = 64; otherwise the mixed step
  *          uses the FP32 FFT. */
 typedef struct stau_domain_desc {
   int32_t dim;

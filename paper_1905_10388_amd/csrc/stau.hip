@@ -403,8 +403,12 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
   if ((rc = upload(t, &dom->twx1))) goto bad;
   dom->mm = mm_supported((int)d.Nz) &&
             (d.dct_method == STAU_DCT_MATMUL || (d.dct_method == STAU_DCT_AUTO && d.Nz <= 64));
+  // split-BF16 products for the mixed step: auto takes them for Nz = 64 only
+  // (4096x64: 13.8 / 14.4 us against 27.8 / 27.3 for the FP32 FFT); at
+  // Nz = 128, 256 the FP32 FFT with half-size tiles is faster (1024x256:
+  // 22.5 / 25.3 us against 30.2 / 39.5)
   dom->mm16 = d.precision == STAU_MIXED && mm_bf16_supported((int)d.Nz) &&
-              (d.dct_method == STAU_DCT_MATMUL || d.dct_method == STAU_DCT_AUTO);
+              (d.dct_method == STAU_DCT_MATMUL || (d.dct_method == STAU_DCT_AUTO && d.Nz <= 64));
   if (dom->mm || dom->mm16) {
     const int N = (int)d.Nz, M = (int)dom->Ngz;
     std::vector<double> Bz((size_t)M * N), Fz((size_t)N * M), PLFz((size_t)N * M);
@@ -616,10 +620,12 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   // the transposed operator (adjoint) swaps kl and ku; when it does not fit the
   // sweep windows the adjoint calls are refused for this pencils object
   pen->adj_ok = window_widths(paT);
-  // Two-block solve for FP64 2-D domains with at most two pencils per compute
+  // Two-block solve for 2-D domains with at most two pencils per compute
   // unit: the system splits at m = kb + S k near n / 2 (a leading block that
-  // ends inside a mode is singular) into two halves swept in parallel.
-  if (d.dim == 2 && d.precision == STAU_FP64) {
+  // ends inside a mode is singular) into two halves swept in parallel.  In
+  // that latency-bound regime the FP64 two-block sweeps beat the mixed
+  // solve's two FP32 sweeps and residual, so mixed domains use them too.
+  if (d.dim == 2) {
     const int Q = pa.kl + pa.ku, S = pa.desc.S, kb = pa.desc.kb;
     // the trailing block's forward sweep (FW = 32) runs slower per column:
     // its share of the rows is about 48 %
@@ -853,7 +859,7 @@ static int factors_for(stau_pencils* pen, double a0, double b0, hipStream_t st,
   int k = set[0].stamp <= set[1].stamp ? 0 : 1;
   if (!set[0].valid) k = 0;
   else if (!set[1].valid) k = 1;
-  if (!set[k].Lraw) {
+  if (!set[k].Lraw && !set[k].LTraw) {  // (two-block slots are allocated with the pencils)
     size_t bytes = 0;
     hipError_t e = alloc_slot(set[k], pa, pen->dom->d.precision == STAU_MIXED, &bytes);
     if (e != hipSuccess) return fail(STAU_ENOMEM, "factor allocation failed: %s", hipGetErrorString(e));
@@ -922,12 +928,12 @@ static hipError_t explicit_term(stau_pencils* pen, const void* X, hipStream_t st
                [&] { return launch_ypass(pen->xa, -1, pen->pa.desc.ne, pen->G, pen->H, st, mixed); });
 }
 
-// Pencil solve of the step with the factors fs of (a0, b0): FP32 sweeps with
-// an FP64 residual in a mixed domain, else the two-block or the single-block
-// FP64 solve.
+// Pencil solve of the step with the factors fs of (a0, b0): the two-block
+// FP64 solve where it applies (either precision), else FP32 sweeps with an
+// FP64 residual in a mixed domain, else the single-block FP64 solve.
 static hipError_t solve_launch(stau_pencils* pen, const stau_pencils::FactorSlot* fs, double a0,
                                double b0, const double2* B, void* X, hipStream_t st, bool mixed) {
-  if (mixed) return launch_solve_mixed(pen->pa, a0, b0, B, fs->Lf32, fs->sl, fs->Uf32, X, st);
+  if (mixed && !pen->two) return launch_solve_mixed(pen->pa, a0, b0, B, fs->Lf32, fs->sl, fs->Uf32, X, st);
   if (pen->two)
     return launch_solve2(pen->pt, pen->pb, B, fs->LfT, fs->slT, fs->UfT, fs->LfB, fs->slB, fs->UfB,
                          fs->Rinv, fs->E1, fs->E2, X, st);
