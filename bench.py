@@ -39,7 +39,14 @@ def b_grid(Nx, Nz, xi, amp=1e-3):
 
 
 def algorithmic_bytes(info):
-    """Minimum HBM bytes per launch of each kernel (FP64)."""
+    """Minimum HBM bytes per launch of each kernel (FP64): every input read
+    once, every output written once.  z backward: 6 state fields of N modes
+    read (b, u, w, bz, uz, wz), 8 grid fields of M points written; x pass: 8
+    fields read on the active pencils, 3 written; z forward + RHS: 3 grid
+    fields read, the previous state's evolved rows and the old history read,
+    the new history (2 arrays) and the right-hand side written; solve: the
+    whole-band factors (kl + kl + ku + 1 doubles and a pivot byte per column)
+    and the right-hand side read, the state written."""
     P, Pa, N, M, S, ne = info["P"], info["P_active"], info["Nz"], info["Ngz"], info["S"], info["ne"]
     n, kl, ku = info["n"], info["kl"], info["ku"]
     c16 = 16
