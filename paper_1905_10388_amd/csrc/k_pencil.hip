@@ -588,6 +588,25 @@ __device__ __forceinline__ void sweep_backward_staged(T* b, const T* __restrict_
 // backward sweep stages its BW-wide columns in units of 32.
 constexpr int kSU = 32;
 
+// Both sweeps staged in small units (su3 columns) for launches with many
+// blocks per compute unit: each column's factor then costs an LDS read
+// instead of a 64-lane global load, whose load-unit cost (about 16 cycles per
+// unit whatever the addresses) limits the unstaged sweeps once several
+// wavefronts share a unit; small units keep two blocks per unit.
+// (8 columns for FP64, 16 for FP32: a unit holds at least 512 bytes)
+template <typename T>
+constexpr int su3() {
+  return sizeof(T) == 8 ? 8 : 16;
+}
+
+template <typename T, int FW, int BW>
+__device__ __forceinline__ void sweeps_staged_both(T* b, const T* __restrict__ Lp,
+                                                   const uint32_t* __restrict__ sw,
+                                                   const T* __restrict__ Up, int nch, int lane, T* st) {
+  sweep_forward_staged<T, FW, su3<T>()>(b, Lp, sw, nch, lane, st);
+  sweep_backward_staged<T, BW, su3<T>()>(b, Up, nch, lane, st);
+}
+
 template <typename T, int FW, int BW>
 __device__ __forceinline__ void sweeps_staged(T* b, const T* __restrict__ Lp,
                                               const uint32_t* __restrict__ sw,
@@ -670,7 +689,8 @@ __device__ __forceinline__ void zero_pencils(double2* __restrict__ X, size_t fir
 // y = L^{-1} P b and x~ = U^{-1} y, and after one barrier the pencil's two
 // wavefronts write X = P^R x~.
 // ---------------------------------------------------------------------------
-template <int FW, int BW, bool STG>
+// STG: 0 unstaged sweeps, 1 backward sweep staged (kSU), 2 both staged (kSU3)
+template <int FW, int BW, int STG>
 __global__ void __launch_bounds__(4 * kWave) solve_kernel(PencilArgs a, int plaunch,
                                                           const double2* __restrict__ Bev,
                                                           const double* __restrict__ Lf,
@@ -699,7 +719,10 @@ __global__ void __launch_bounds__(4 * kWave) solve_kernel(PencilArgs a, int plau
     const double* Lp = Lf + (size_t)p * npad * FW;
     const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
     const double* Up = Uf + (size_t)p * npad * BW;
-    if constexpr (STG) {
+    if constexpr (STG == 2) {
+      double* stg = lds + (size_t)4 * span + (size_t)wv * (stage_bytes<double, FW, BW, su3<double>()>() / 8);
+      sweeps_staged_both<double, FW, BW>(b, Lp, swp, Up, nch, lane, stg);
+    } else if constexpr (STG == 1) {
       double* stg = lds + (size_t)4 * span + (size_t)wv * (stage_bytes<double, 1, BW, kSU>() / 8);
       sweeps_staged<double, FW, BW>(b, Lp, swp, Up, nch, lane, stg);
     } else {
@@ -1327,7 +1350,8 @@ __host__ __device__ inline size_t mixed_pencil_doubles(int n, int span) {
 // Per wavefront (one real part) in LDS: b64[n] (FP64 right-hand side, then
 // the solution), w32 (padded FP32 sweep vector), xh[n] (FP32 first solution).
 // ---------------------------------------------------------------------------
-template <int FW, int BW, bool STG>
+// STG: 0 unstaged sweeps, 1 backward sweep staged (kSU)
+template <int FW, int BW, int STG>
 __global__ void __launch_bounds__(4 * kWave) solve_mixed_kernel(
     PencilArgs a, int plaunch, double a0, double b0, const double2* __restrict__ Bev,
     const float* __restrict__ Lf, const uint8_t* __restrict__ sl, const float* __restrict__ Uf,
@@ -1361,7 +1385,7 @@ __global__ void __launch_bounds__(4 * kWave) solve_mixed_kernel(
     float* stg = (float*)(lds + 2 * mixed_pencil_doubles(n, span)) +
                  (size_t)wv * (stage_bytes<float, 1, BW, kSU>() / 4);
     auto sweep = [&]() {
-      if constexpr (STG)
+      if constexpr (STG == 1)
         sweeps_staged<float, FW, BW>(w, Lp, swp, Up, nch, lane, stg);
       else
         sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
@@ -1455,17 +1479,32 @@ static PencilGrid pencil_grid(const PencilArgs& a, size_t lds_per_pencil, size_t
 template <int FW, int BW>
 static hipError_t launch_solve_t(const PencilArgs& a, const void* Bev, const double* Lf,
                                  const uint8_t* sl, const double* Uf, void* X, hipStream_t st) {
-  const PencilGrid g = pencil_grid(a, (size_t)2 * (BW + a.nst + FW) * sizeof(double),
-                                   (size_t)4 * stage_bytes<double, 1, BW, kSU>());
+  const size_t per_pencil = (size_t)2 * (BW + a.nst + FW) * sizeof(double);
+  const PencilGrid g = pencil_grid(a, per_pencil, (size_t)4 * stage_bytes<double, 1, BW, kSU>());
+  auto go = [&](auto kern, size_t lds) {
+    allow_lds((const void*)kern, lds);
+    hipLaunchKernelGGL(kern, dim3(g.blocks), dim3(4 * kWave), lds, st, a, g.plaunch, (const double2*)Bev,
+                       Lf, sl, Uf, (double2*)X);
+  };
   if (g.staged) {
-    allow_lds((const void*)solve_kernel<FW, BW, true>, g.lds);
-    hipLaunchKernelGGL((solve_kernel<FW, BW, true>), dim3(g.blocks), dim3(4 * kWave), g.lds, st, a,
-                       g.plaunch, (const double2*)Bev, Lf, sl, Uf, (double2*)X);
-  } else {
-    allow_lds((const void*)solve_kernel<FW, BW, false>, g.lds);
-    hipLaunchKernelGGL((solve_kernel<FW, BW, false>), dim3(g.blocks), dim3(4 * kWave), g.lds, st, a,
-                       g.plaunch, (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+    go(solve_kernel<FW, BW, 1>, g.lds);
+    return hipGetLastError();
   }
+  // more blocks than compute units: both sweeps staged in small units when two
+  // blocks still fit a unit's LDS
+  int dev = 0, cus = 0, lds_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess &&
+      g.blocks > cus) {
+    const size_t lds2 = 2 * per_pencil + (size_t)4 * stage_bytes<double, FW, BW, su3<double>()>();
+    if (2 * lds2 <= (size_t)lds_cu) {
+      go(solve_kernel<FW, BW, 2>, lds2);
+      return hipGetLastError();
+    }
+  }
+  go(solve_kernel<FW, BW, 0>, g.lds);
   return hipGetLastError();
 }
 
@@ -1559,17 +1598,20 @@ static hipError_t launch_solve_mixed_t(const PencilArgs& a, double a0, double b0
                                        const float* Lf, const uint8_t* sl, const float* Uf,
                                        void* X, hipStream_t st) {
   const int span = BW + a.nst + FW;
-  const PencilGrid g = pencil_grid(a, mixed_pencil_doubles(a.n, span) * sizeof(double),
-                                   (size_t)4 * stage_bytes<float, 1, BW, kSU>());
+  const size_t per_pencil = mixed_pencil_doubles(a.n, span) * sizeof(double);
+  const PencilGrid g = pencil_grid(a, per_pencil, (size_t)4 * stage_bytes<float, 1, BW, kSU>());
+  auto go = [&](auto kern, size_t lds) {
+    allow_lds((const void*)kern, lds);
+    hipLaunchKernelGGL(kern, dim3(g.blocks), dim3(4 * kWave), lds, st, a, g.plaunch, a0, b0,
+                       (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+  };
   if (g.staged) {
-    allow_lds((const void*)solve_mixed_kernel<FW, BW, true>, g.lds);
-    hipLaunchKernelGGL((solve_mixed_kernel<FW, BW, true>), dim3(g.blocks), dim3(4 * kWave), g.lds,
-                       st, a, g.plaunch, a0, b0, (const double2*)Bev, Lf, sl, Uf, (double2*)X);
-  } else {
-    allow_lds((const void*)solve_mixed_kernel<FW, BW, false>, g.lds);
-    hipLaunchKernelGGL((solve_mixed_kernel<FW, BW, false>), dim3(g.blocks), dim3(4 * kWave), g.lds,
-                       st, a, g.plaunch, a0, b0, (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+    go(solve_mixed_kernel<FW, BW, 1>, g.lds);
+    return hipGetLastError();
   }
+  // (both sweeps staged, as solve_kernel does for many blocks per unit,
+  // measured slower here: 4096x64 119 -> 171 us)
+  go(solve_mixed_kernel<FW, BW, 0>, g.lds);
   return hipGetLastError();
 }
 
