@@ -78,15 +78,14 @@ typedef struct stau_pencils stau_pencils;
  * Nz       Chebyshev modes: a power of two in [4, 512] (3Nz/2 grid points).
  * Lx, Ly   periods of x, y (> 0).
  * dealias  transform scale; must be 1.5 (the 3/2 rule, Sec. IV).
- * precision STAU_FP64 (everything FP64) or STAU_MIXED (stau_step and
- *          stau_adjoint_step: FP32 transforms and products; FP64
- *          factorisation rounded to FP32 for the sweeps; FP32 solve, FP64
- *          residual of the full system (boundary rows included) from the
- *          operator templates, one FP32 correction sweep, FP64 accumulation;
- *          state, history, right-hand side and their adjoints FP64).  2-D
- *          launches of at most two pencils per compute unit are latency
- *          bound; there the step's solve runs as the FP64 two-block solve,
- *          which is faster than the FP32 sweeps and residual.  The
+ * precision STAU_FP64 (everything FP64) or STAU_MIXED (FP32 transforms and
+ *          products in stau_step, stau_step_rk and stau_adjoint_step; the
+ *          pencil factorisation, the step's pencil solve, the state,
+ *          history, right-hand side and their adjoints FP64.  The adjoint's
+ *          transposed solve runs FP32 sweeps on FP32 copies of the factors,
+ *          an FP64 residual of the full system (boundary rows included) from
+ *          the operator templates, one FP32 correction sweep and FP64
+ *          accumulation.)  The
  *          component calls (stau_nonlinear, stau_solve) and the
  *          kinetic-energy and initial-state adjoints run in FP64 in either
  *          mode.

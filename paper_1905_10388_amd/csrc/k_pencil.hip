@@ -1336,81 +1336,6 @@ __global__ void __launch_bounds__(2 * kWave) solveT_mixed_kernel(
   solveT_epilogue(a, r, b64r, b64i, Xo, Fb, hb, tid, 2 * kWave);
 }
 
-// LDS of one pencil in the mixed solve, in doubles (16-byte multiple):
-// b64[2 n] + 2 x (FP32 sweep vector [span] + FP32 first solution [n])
-__host__ __device__ inline size_t mixed_pencil_doubles(int n, int span) {
-  return ((size_t)2 * n + (size_t)(span + n) + 1) / 2 * 2;
-}
-
-// ---------------------------------------------------------------------------
-// Mixed-precision solve: FP32 sweeps with FP32 copies of the FP64 factors,
-// FP64 residual r = b - A x^ from the operator templates (boundary rows
-// included), one FP32 correction sweep, x = x^ + d accumulated in FP64.
-// The right-hand side (boundary values included) and the output stay FP64.
-// Per wavefront (one real part) in LDS: b64[n] (FP64 right-hand side, then
-// the solution), w32 (padded FP32 sweep vector), xh[n] (FP32 first solution).
-// ---------------------------------------------------------------------------
-// STG: 0 unstaged sweeps, 1 backward sweep staged (kSU)
-template <int FW, int BW, int STG>
-__global__ void __launch_bounds__(4 * kWave) solve_mixed_kernel(
-    PencilArgs a, int plaunch, double a0, double b0, const double2* __restrict__ Bev,
-    const float* __restrict__ Lf, const uint8_t* __restrict__ sl, const float* __restrict__ Uf,
-    double2* __restrict__ X) {
-  extern __shared__ double lds[];
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int q = wv >> 1, part = wv & 1;
-  const int p = blockIdx.x * 2 + q;
-  const int n = a.n, N = a.desc.N, S = a.desc.S, ne = a.desc.ne;
-  const SysDesc& d = a.desc;
-  if (blockIdx.x == 0 && plaunch < a.P) zero_pencils(X, plaunch, a.P, S * N, tid, 4 * kWave);
-  const bool live = p < plaunch;
-  const bool act = live && pencil_active(a, p);
-  const int npad = a.nst, nch = npad / kCH;
-  const int span = BW + npad + FW;
-  // per pencil: b64 for both parts, then per part the FP32 sweep vector and x^
-  double* b64r = lds + (size_t)q * mixed_pencil_doubles(n, span);
-  double* b64i = b64r + n;
-  if (act) {
-    const PencilCoef pc = pencil_coef(a, p, a0, b0);
-    double* b64 = part == 0 ? b64r : b64i;
-    float* f0 = (float*)(b64r + 2 * n) + (size_t)part * (span + n);
-    float* w = f0 + BW;
-    float* xh = f0 + span;
-    build_rhs<float>(a, pc, Bev + (size_t)p * ne * N, part, w, b64, BW, FW, npad, lane);
-    const float* Lp = Lf + (size_t)p * npad * FW;
-    const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
-    const float* Up = Uf + (size_t)p * npad * BW;
-    float* stg = (float*)(lds + 2 * mixed_pencil_doubles(n, span)) +
-                 (size_t)wv * (stage_bytes<float, 1, BW, kSU>() / 4);
-    auto sweep = [&]() {
-      if constexpr (STG == 1)
-        sweeps_staged<float, FW, BW>(w, Lp, swp, Up, nch, lane, stg);
-      else
-        sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
-    };
-    sweep();
-    for (int r = lane; r < n; r += kWave) xh[r] = w[r];
-    for (int r = lane; r < npad + FW; r += kWave) {
-      if (r < n) {
-        const double ax =
-            apply_row(d, pc, r, [&](int m, int var) { return (double)xh[m * S + d.var_pos[var]]; });
-        w[r] = (float)(b64[r] - ax);
-      } else {
-        w[r] = 0.0f;
-      }
-    }
-    sweep();
-    for (int r = lane; r < n; r += kWave) b64[r] = (double)xh[r] + (double)w[r];
-  }
-  __syncthreads();
-  if (act)
-    write_state(a, b64r, b64i, X + (size_t)p * S * N, tid & (2 * kWave - 1), 2 * kWave);
-  else if (live)
-    zero_pencils(X, p, p + 1, S * N, tid & (2 * kWave - 1), 2 * kWave);
-}
-
 __global__ void round_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
                                     size_t count) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
@@ -1590,38 +1515,6 @@ hipError_t launch_solve2(const PencilArgs& t, const PencilArgs& bt, const void* 
                                            E2, X, st);
   STAU_SOLVE2_VARIANTS(STAU_CASE2)
 #undef STAU_CASE2
-  return hipErrorInvalidValue;
-}
-
-template <int FW, int BW>
-static hipError_t launch_solve_mixed_t(const PencilArgs& a, double a0, double b0, const void* Bev,
-                                       const float* Lf, const uint8_t* sl, const float* Uf,
-                                       void* X, hipStream_t st) {
-  const int span = BW + a.nst + FW;
-  const size_t per_pencil = mixed_pencil_doubles(a.n, span) * sizeof(double);
-  const PencilGrid g = pencil_grid(a, per_pencil, (size_t)4 * stage_bytes<float, 1, BW, kSU>());
-  auto go = [&](auto kern, size_t lds) {
-    allow_lds((const void*)kern, lds);
-    hipLaunchKernelGGL(kern, dim3(g.blocks), dim3(4 * kWave), lds, st, a, g.plaunch, a0, b0,
-                       (const double2*)Bev, Lf, sl, Uf, (double2*)X);
-  };
-  if (g.staged) {
-    go(solve_mixed_kernel<FW, BW, 1>, g.lds);
-    return hipGetLastError();
-  }
-  // (both sweeps staged, as solve_kernel does for many blocks per unit,
-  // measured slower here: 4096x64 119 -> 171 us)
-  go(solve_mixed_kernel<FW, BW, 0>, g.lds);
-  return hipGetLastError();
-}
-
-hipError_t launch_solve_mixed(const PencilArgs& a, double a0, double b0, const void* Bev,
-                              const float* Lf, const uint8_t* sl, const float* Uf, void* X,
-                              hipStream_t st) {
-#define STAU_CASE(F, B) \
-  if (a.FW == F && a.BW == B) return launch_solve_mixed_t<F, B>(a, a0, b0, Bev, Lf, sl, Uf, X, st);
-  STAU_SWEEP_VARIANTS(STAU_CASE)
-#undef STAU_CASE
   return hipErrorInvalidValue;
 }
 

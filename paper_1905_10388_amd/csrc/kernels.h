@@ -111,9 +111,6 @@ hipError_t launch_evp(const PencilArgs& a, double tau, int iters, const double* 
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
                         const double* Uf, void* X, hipStream_t st);
 
-hipError_t launch_solve_mixed(const PencilArgs& a, double a0, double b0, const void* Bev,
-                              const float* Lf, const uint8_t* sl, const float* Uf, void* X,
-                              hipStream_t st);
 hipError_t launch_round_f32(const double* src, float* dst, size_t count, hipStream_t st);
 
 // transforms along y and the 3-D x pass
