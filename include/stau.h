@@ -80,12 +80,9 @@ typedef struct stau_pencils stau_pencils;
  * dealias  transform scale; must be 1.5 (the 3/2 rule, Sec. IV).
  * precision STAU_FP64 (everything FP64) or STAU_MIXED (FP32 transforms and
  *          products in stau_step, stau_step_rk and stau_adjoint_step; the
- *          pencil factorisation, the step's pencil solve, the state,
- *          history, right-hand side and their adjoints FP64.  The adjoint's
- *          transposed solve runs FP32 sweeps on FP32 copies of the factors,
- *          an FP64 residual of the full system (boundary rows included) from
- *          the operator templates, one FP32 correction sweep and FP64
- *          accumulation.)  The
+ *          pencil factorisation, the pencil solves (the step's and the
+ *          adjoint's transposed one), the state, history, right-hand side
+ *          and their adjoints FP64.)  The
  *          component calls (stau_nonlinear, stau_solve) and the
  *          kinetic-energy and initial-state adjoints run in FP64 in either
  *          mode.
@@ -208,8 +205,8 @@ int stau_step(stau_pencils* pen, stau_state* st, double dt, void* stream);
  * factorisation matches).  The stage values F~ and L~X live in a workspace of
  * the pencils object (allocated on the first call with a larger scheme:
  * max(1, 2s - 2) arrays of P ne Nz complex entries).  Needs no history: every step is full order, dt may change from
- * step to step.  In a STAU_MIXED domain the transforms, products and sweeps
- * run as in stau_step.  Asynchronous otherwise. */
+ * step to step.  In a STAU_MIXED domain the transforms and products run as in
+ * stau_step (FP32; the solve FP64).  Asynchronous otherwise. */
 int stau_step_rk(stau_pencils* pen, int scheme, double dt, void* X, void* stream);
 
 /* Linear boundary value solve (Sec. IX "Linear boundary value solver"): per
@@ -300,8 +297,7 @@ typedef struct stau_adjstate {
  * where N' is the linearised explicit term (adjoint transforms and products on
  * the 3/2 grid).  Uses cached factors of (a0, b0), refactoring synchronously
  * if neither stored factorisation matches.  In a STAU_MIXED domain the
- * transposed solve runs FP32 sweeps with one FP64-residual correction and the
- * adjoint transforms and products run in FP32.  Sec. IX (IVP, multistep IMEX) is
+ * adjoint transforms and products run in FP32 (the transposed solve in FP64).  Sec. IX (IVP, multistep IMEX) is
  * the forward operation; the adjoint is not part of the paper. */
 int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, double dt,
                       double dt_prev, stau_adjstate* adj, void* stream);

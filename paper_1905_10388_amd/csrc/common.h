@@ -436,71 +436,4 @@ __host__ __device__ inline double apply_row(const SysDesc& d, const PencilCoef& 
 }
 
 
-// ---------------------------------------------------------------------------
-// Row c of the transpose, (A~^T y)_c = sum_r A~(r, c) y_r, from the same
-// templates: column c = (m, var) of A~ is the T-basis column E(., m) minus
-// E(., m-2) (P^R), and E(., q) collects, over the equations that contain var,
-// the transposed conversion C^T y (q) = (q ? 1/2 : 1) y_q - 1/2 y_{q-2}, the
-// transposed derivative D^T y (q) = 2 q y_{q-1} and, for continuity, y_q; the
-// boundary rows add their values at modes 0 and 1.  gety(r) returns y at
-// system row r; rows that do not exist (mode N-1 holds only continuity) are
-// zero.
-// ---------------------------------------------------------------------------
-template <typename GY>
-__host__ __device__ inline double apply_col(const SysDesc& d, const PencilCoef& pc, int c, GY gety) {
-  const int N = d.N, S = d.S, kb = d.kb;
-  const int m = c / S;
-  const int var = d.var_at[c - m * S];
-  auto yrow = [&](int n, int eq) -> double {
-    if (n < 0 || n >= N || d.eq_pos[eq] < 0) return 0.0;
-    if (n == N - 1) return eq == EC ? gety(kb + n * S) : 0.0;
-    return gety(kb + n * S + d.eq_pos[eq]);
-  };
-  auto CT = [&](int eq, int q) {
-    double v = (q == 0 ? 1.0 : 0.5) * yrow(q, eq);
-    if (q >= 2) v -= 0.5 * yrow(q - 2, eq);
-    return v;
-  };
-  auto DT = [&](int eq, int q) { return q >= 1 ? 2.0 * q * yrow(q - 1, eq) : 0.0; };
-  const double k2 = pc.kx * pc.kx + pc.ky * pc.ky;
-  const double ak = pc.a0 + pc.b0 * pc.kappa * k2, an = pc.a0 + pc.b0 * pc.nu * k2;
-  const double b0 = pc.b0;
-  auto g = [&](int q) -> double {
-    switch (var) {
-      case VB: return ak * CT(EB, q) - b0 * pc.buoy * CT(EW, q) - b0 * DT(EBZ, q);
-      case VBZ: return -b0 * pc.kappa * DT(EB, q) + b0 * CT(EBZ, q);
-      case VU: return an * CT(EU, q) - b0 * DT(EUZ, q) + b0 * pc.kx * yrow(q, EC);
-      case VUZ: return -b0 * pc.nu * DT(EU, q) + b0 * CT(EUZ, q);
-      case VV: return an * CT(EV, q) - b0 * DT(EVZ, q) + b0 * pc.ky * yrow(q, EC);
-      case VVZ: return -b0 * pc.nu * DT(EV, q) + b0 * CT(EVZ, q);
-      case VW: {
-        double v = an * CT(EW, q) - b0 * DT(EWZ, q);
-        if (pc.lin != 0.0) v += b0 * pc.lin * CT(EB, q);
-        // G^T C^T y: (G^T z)(q) = sum_k g_k (z(q + k) + z(|q - k|)) / 2, z = C^T y over rows < N
-#pragma unroll
-        for (int k = 0; k < kMaxNcc; ++k) {
-          if (k >= pc.nncc) break;
-          const int i1 = q + k, i2 = q >= k ? q - k : k - q;
-          v += 0.5 * b0 * pc.ncc[k] * ((i1 < N ? CT(EB, i1) : 0.0) + CT(EB, i2));
-        }
-        return v;
-      }
-      case VWZ: return -b0 * pc.nu * DT(EW, q) + b0 * CT(EWZ, q) + b0 * yrow(q, EC);
-      case VP: return -b0 * pc.kx * CT(EU, q) - b0 * pc.ky * CT(EV, q) + b0 * DT(EW, q);
-    }
-    return 0.0;
-  };
-  double v = g(m);
-  if (m >= 2) v -= g(m - 2);
-  if (m <= 1) {
-    for (int r = 0; r < kb; ++r) {
-      int bv = d.bc_var[r];
-      if (pc.mean && bv == VW && d.bc_side[r] == 1) bv = VP;  // gauge p(z=1) = 0
-      if (bv == var) v += b0 * ((d.bc_side[r] == 0 && m == 1) ? -1.0 : 1.0) * gety(r);
-    }
-  }
-  return v;
-}
-
-
 }  // namespace stau

@@ -1157,11 +1157,9 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
 // ---------------------------------------------------------------------------
 // Right-hand side of the transposed solve for one real part:
 // x~_bar = S_R^H (P^R)^T X_bar in system column order, written to b[-BW ..
-// npad + FW) (and to b64[0 .. n) when given).
-template <typename T>
+// npad + FW).
 __device__ __forceinline__ void solveT_rhs(const PencilArgs& a, const double2* __restrict__ Xp,
-                                           int part, T* b, double* b64, int BW, int FW, int npad,
-                                           int lane) {
+                                           int part, double* b, int BW, int FW, int npad, int lane) {
   const SysDesc& d = a.desc;
   const int n = a.n, N = d.N, S = d.S;
   for (int c = lane - BW; c < npad + FW; c += kWave) {
@@ -1184,9 +1182,7 @@ __device__ __forceinline__ void solveT_rhs(const PencilArgs& a, const double2* _
         vi = v.y;
       }
     }
-    const double v = part == 0 ? vr : vi;
-    b[c] = (T)v;
-    if (b64 && c >= 0 && c < n) b64[c] = v;
+    b[c] = part == 0 ? vr : vi;
   }
 }
 
@@ -1248,8 +1244,12 @@ __device__ __forceinline__ void solveT_zero(const PencilArgs& a, double2* __rest
   for (int i = tid; i < 2 * ne * N; i += nt) hb[i] = make_double2(0.0, 0.0);
 }
 
-template <int FW, int BW>
-__global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
+// STAGED: both sweeps staged in su3-column units.  Blocks cover pencils
+// [0, plaunch); block 0 also zeroes the outputs of the inactive pencils
+// [plaunch, P) (in 2-D the Nyquist pencil), so that a launch of plaunch <= #CU
+// blocks places at most one block per compute unit.
+template <int FW, int BW, bool STAGED>
+__global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a, int plaunch,
                                                            const double2* __restrict__ Xin,
                                                            const double* __restrict__ Lf,
                                                            const uint8_t* __restrict__ sl,
@@ -1261,6 +1261,10 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
   const int lane = tid & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int N = a.desc.N, S = a.desc.S, ne = a.desc.ne;
+  if (blockIdx.x == 0)
+    for (int q = plaunch; q < a.P; ++q)
+      solveT_zero(a, Xout + (size_t)q * S * N, r.Fbar + (size_t)q * ne * N,
+                  r.hbar + (size_t)q * 2 * ne * N, tid, 2 * kWave);
   const double2* Xp = Xin + (size_t)p * S * N;
   double2* Xo = Xout + (size_t)p * S * N;
   double2* Fb = r.Fbar + (size_t)p * ne * N;
@@ -1275,72 +1279,18 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a,
   double* bre = lds + BW;
   double* bim = lds + span + BW;
   double* b = wv == 0 ? bre : bim;
-  solveT_rhs<double>(a, Xp, wv, b, nullptr, BW, FW, npad, lane);
-  sweeps<double, FW, BW>(b, Lf + (size_t)p * npad * FW, (const uint32_t*)(sl + (size_t)p * npad),
-                         Uf + (size_t)p * npad * BW, nch, lane);
+  solveT_rhs(a, Xp, wv, b, BW, FW, npad, lane);
+  const double* Lp = Lf + (size_t)p * npad * FW;
+  const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
+  const double* Up = Uf + (size_t)p * npad * BW;
+  if constexpr (STAGED) {
+    double* stg = lds + (size_t)2 * span + (size_t)wv * (stage_bytes<double, FW, BW, su3<double>()>() / 8);
+    sweeps_staged_both<double, FW, BW>(b, Lp, swp, Up, nch, lane, stg);
+  } else {
+    sweeps<double, FW, BW>(b, Lp, swp, Up, nch, lane);
+  }
   __syncthreads();
   solveT_epilogue(a, r, bre, bim, Xo, Fb, hb, tid, 2 * kWave);
-}
-
-// Mixed-precision transposed solve: FP32 sweeps on FP32 copies of the
-// transposed factors, the FP64 residual r = b - A~^T x^ formed row by row
-// from the operator templates (apply_col: a column of A~), one FP32
-// correction sweep, x = x^ + d in FP64, then the FP64 epilogue.
-template <int FW, int BW>
-__global__ void __launch_bounds__(2 * kWave) solveT_mixed_kernel(
-    PencilArgs a, double a0, double b0, const double2* __restrict__ Xin,
-    const float* __restrict__ Lf, const uint8_t* __restrict__ sl, const float* __restrict__ Uf,
-    double2* Xout, AdjRhsArgs r) {
-  extern __shared__ double lds[];
-  const int p = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int n = a.n, N = a.desc.N, S = a.desc.S, ne = a.desc.ne;
-  const SysDesc& d = a.desc;
-  const double2* Xp = Xin + (size_t)p * S * N;
-  double2* Xo = Xout + (size_t)p * S * N;
-  double2* Fb = r.Fbar + (size_t)p * ne * N;
-  double2* hb = r.hbar + (size_t)p * 2 * ne * N;
-  if (!pencil_active(a, p)) {
-    __syncthreads();
-    solveT_zero(a, Xo, Fb, hb, tid, 2 * kWave);
-    return;
-  }
-  const PencilCoef pc = pencil_coef(a, p, a0, b0);
-  const int npad = a.nst, nch = npad / kCH;
-  const int span = BW + npad + FW;
-  double* b64r = lds;
-  double* b64i = lds + n;
-  double* b64 = wv == 0 ? b64r : b64i;
-  float* f0 = (float*)(lds + 2 * n) + (size_t)wv * (span + n);
-  float* w = f0 + BW;
-  float* xh = f0 + span;
-  solveT_rhs<float>(a, Xp, wv, w, b64, BW, FW, npad, lane);
-  const float* Lp = Lf + (size_t)p * npad * FW;
-  const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
-  const float* Up = Uf + (size_t)p * npad * BW;
-  sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
-  for (int c = lane; c < n; c += kWave) xh[c] = w[c];
-  for (int c = lane; c < npad + FW; c += kWave) {
-    if (c < n) {
-      const double ax = apply_col(d, pc, c, [&](int j) { return (double)xh[j]; });
-      w[c] = (float)(b64[c] - ax);
-    } else {
-      w[c] = 0.0f;
-    }
-  }
-  sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
-  for (int c = lane; c < n; c += kWave) b64[c] = (double)xh[c] + (double)w[c];
-  __syncthreads();
-  solveT_epilogue(a, r, b64r, b64i, Xo, Fb, hb, tid, 2 * kWave);
-}
-
-__global__ void round_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
-                                    size_t count) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
-       i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = (float)src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1518,43 +1468,34 @@ hipError_t launch_solve2(const PencilArgs& t, const PencilArgs& bt, const void* 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_round_f32(const double* src, float* dst, size_t count, hipStream_t st) {
-  hipLaunchKernelGGL(round_to_f32_kernel, dim3(1024), dim3(256), 0, st, src, dst, count);
-  return hipGetLastError();
-}
-
+// One pencil per block of two wavefronts.  More blocks than compute units:
+// both sweeps staged (su3 columns) when two blocks fit a unit's LDS (512
+// blocks and more share units; 4096x64 adjoint step 432 -> 342 us); up to one
+// block per unit: unstaged (staging the backward sweep, or both, measured
+// 3-14 us slower at 512x128).
 template <int FW, int BW>
 static hipError_t launch_solveT_t(const PencilArgs& a, const void* Xin, const double* Lf,
                                   const uint8_t* sl, const double* Uf, void* Xout,
                                   const AdjRhsArgs& r, hipStream_t st) {
-  size_t lds = (size_t)2 * (BW + a.nst + FW) * sizeof(double);
-  allow_lds((const void*)solveT_kernel<FW, BW>, lds);
-  hipLaunchKernelGGL((solveT_kernel<FW, BW>), dim3(a.P), dim3(2 * kWave), lds, st, a,
-                     (const double2*)Xin, Lf, sl, Uf, (double2*)Xout, r);
+  const size_t vec = (size_t)2 * (BW + a.nst + FW) * sizeof(double);
+  const int plaunch = a.desc.dim == 2 ? a.Px - 1 : a.P;
+  auto go = [&](auto kern, size_t lds) {
+    allow_lds((const void*)kern, lds);
+    hipLaunchKernelGGL(kern, dim3(plaunch), dim3(2 * kWave), lds, st, a, plaunch,
+                       (const double2*)Xin, Lf, sl, Uf, (double2*)Xout, r);
+  };
+  int dev = 0, cus = 0, lds_cu = 0;
+  const size_t lds2 = vec + (size_t)2 * stage_bytes<double, FW, BW, su3<double>()>();
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess &&
+      plaunch > cus && 2 * lds2 <= (size_t)lds_cu) {
+    go(solveT_kernel<FW, BW, true>, lds2);
+    return hipGetLastError();
+  }
+  go(solveT_kernel<FW, BW, false>, vec);
   return hipGetLastError();
-}
-
-template <int FW, int BW>
-static hipError_t launch_solveT_mixed_t(const PencilArgs& a, double a0, double b0, const void* Xin,
-                                        const float* Lf, const uint8_t* sl, const float* Uf,
-                                        void* Xout, const AdjRhsArgs& r, hipStream_t st) {
-  const int span = BW + a.nst + FW;
-  size_t lds = (size_t)2 * a.n * sizeof(double) + (size_t)2 * (span + a.n) * sizeof(float);
-  allow_lds((const void*)solveT_mixed_kernel<FW, BW>, lds);
-  hipLaunchKernelGGL((solveT_mixed_kernel<FW, BW>), dim3(a.P), dim3(2 * kWave), lds, st, a, a0, b0,
-                     (const double2*)Xin, Lf, sl, Uf, (double2*)Xout, r);
-  return hipGetLastError();
-}
-
-hipError_t launch_solveT_mixed(const PencilArgs& a, double a0, double b0, const void* Xin,
-                               const float* Lf, const uint8_t* sl, const float* Uf, void* Xout,
-                               const AdjRhsArgs& r, hipStream_t st) {
-#define STAU_CASE(F, B) \
-  if (a.FW == F && a.BW == B)   \
-    return launch_solveT_mixed_t<F, B>(a, a0, b0, Xin, Lf, sl, Uf, Xout, r, st);
-  STAU_SWEEP_VARIANTS(STAU_CASE)
-#undef STAU_CASE
-  return hipErrorInvalidValue;
 }
 
 hipError_t launch_solveT(const PencilArgs& a, const void* Xin, const double* Lf, const uint8_t* sl,

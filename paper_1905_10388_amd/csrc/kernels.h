@@ -111,8 +111,6 @@ hipError_t launch_evp(const PencilArgs& a, double tau, int iters, const double* 
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
                         const double* Uf, void* X, hipStream_t st);
 
-hipError_t launch_round_f32(const double* src, float* dst, size_t count, hipStream_t st);
-
 // transforms along y and the 3-D x pass
 hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, void* Out,
                         hipStream_t st, bool fp32 = false);
@@ -253,11 +251,6 @@ struct AdjRhsArgs {
 hipError_t launch_solveT(const PencilArgs& a, const void* Xbar_in, const double* Lf,
                          const uint8_t* sl, const double* Uf, void* Xbar_out,
                          const AdjRhsArgs& r, hipStream_t st);
-// mixed precision: FP32 sweeps on FP32 copies of the transposed factors, one
-// FP64-residual correction (a0, b0 of the factored operator)
-hipError_t launch_solveT_mixed(const PencilArgs& a, double a0, double b0, const void* Xin,
-                               const float* Lf, const uint8_t* sl, const float* Uf, void* Xout,
-                               const AdjRhsArgs& r, hipStream_t st);
 hipError_t launch_ke_adjoint(const XformArgs& a, const void* X, void* G, void* Gbar,
                              const void* wvec, void* ebar, void* Xbar, hipStream_t st);
 hipError_t launch_initial_state_adjoint(const XformArgs& a1, const void* Xbar, double* gbar,

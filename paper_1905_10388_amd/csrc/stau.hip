@@ -168,12 +168,9 @@ struct stau_pencils {
   struct FactorSlot {
     double *Lraw = nullptr, *Uraw = nullptr;
     uint8_t* sraw = nullptr;
-    float *L32raw = nullptr, *U32raw = nullptr;
     double* Lf = nullptr;
     uint8_t* sl = nullptr;
     double* Uf = nullptr;
-    float* Lf32 = nullptr;  // mixed precision: FP32 copies of the FP64 factors
-    float* Uf32 = nullptr;
     // two-block solve: factors of the leading (T) and trailing (B) blocks,
     // their last-Q elimination steps and the coupling data
     double *LTraw = nullptr, *UTraw = nullptr, *LBraw = nullptr, *UBraw = nullptr;
@@ -489,8 +486,6 @@ static void free_pencils(stau_pencils* p) {
       hipFree(f.Lraw);
       hipFree(f.sraw);
       hipFree(f.Uraw);
-      hipFree(f.L32raw);
-      hipFree(f.U32raw);
       for (void* q : {(void*)f.LTraw, (void*)f.UTraw, (void*)f.LBraw, (void*)f.UBraw, (void*)f.sTraw,
                       (void*)f.sBraw, (void*)f.tLt, (void*)f.tLb, (void*)f.Rinv, (void*)f.E1,
                       (void*)f.E2, (void*)f.tPt, (void*)f.tPb})
@@ -503,8 +498,7 @@ static void free_pencils(stau_pencils* p) {
 }
 
 // Allocate (zeroed) factor storage for one slot of the band description pa.
-static hipError_t alloc_slot(stau_pencils::FactorSlot& f, const PencilArgs& pa, bool mixed,
-                             size_t* bytes) {
+static hipError_t alloc_slot(stau_pencils::FactorSlot& f, const PencilArgs& pa, size_t* bytes) {
   const size_t sk = (size_t)factor_slack();
   const size_t cols = (size_t)pa.P * pa.nst + 2 * sk;
   hipError_t e = hipSuccess;
@@ -516,18 +510,10 @@ static hipError_t alloc_slot(stau_pencils::FactorSlot& f, const PencilArgs& pa, 
   get((void**)&f.Lraw, cols * pa.FW * sizeof(double));
   get((void**)&f.Uraw, cols * pa.BW * sizeof(double));
   get((void**)&f.sraw, cols);
-  if (mixed) {
-    get((void**)&f.L32raw, cols * pa.FW * sizeof(float));
-    get((void**)&f.U32raw, cols * pa.BW * sizeof(float));
-  }
   if (e != hipSuccess) return e;
   f.Lf = f.Lraw + sk * pa.FW;
   f.Uf = f.Uraw + sk * pa.BW;
   f.sl = f.sraw + sk;
-  if (mixed) {
-    f.Lf32 = f.L32raw + sk * pa.FW;
-    f.Uf32 = f.U32raw + sk * pa.BW;
-  }
   return hipSuccess;
 }
 
@@ -747,7 +733,7 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   if (e == hipSuccess) e = hipMalloc((void**)&pen->wvec, (size_t)N * sizeof(double2));
   size_t szF = 0;
   for (auto& f : pen->slot)
-    if (e == hipSuccess) e = pen->two ? alloc_slot2(f, pen->pt, pen->pb, &szF) : alloc_slot(f, pa, false, &szF);
+    if (e == hipSuccess) e = pen->two ? alloc_slot2(f, pen->pt, pen->pb, &szF) : alloc_slot(f, pa, &szF);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->sing, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->flag, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->scratch, szScratch);
@@ -829,11 +815,6 @@ static int factor_into(stau_pencils* pen, stau_pencils::FactorSlot* set, const P
     pen->last_sing = h;
     return fail(STAU_ESINGULAR, "zero or non-finite pivot in pencil %d", h);
   }
-  if (f.Lf32) {
-    const size_t cols = (size_t)pa.P * pa.nst;
-    HIP_TRY(launch_round_f32(f.Lf, f.Lf32, cols * pa.FW, st));
-    HIP_TRY(launch_round_f32(f.Uf, f.Uf32, cols * pa.BW, st));
-  }
   f.valid = true;
   f.a0 = a0;
   f.b0 = b0;
@@ -860,9 +841,7 @@ static int factors_for(stau_pencils* pen, double a0, double b0, hipStream_t st,
   else if (!set[1].valid) k = 1;
   if (!set[k].Lraw && !set[k].LTraw) {  // (two-block slots are allocated with the pencils)
     size_t bytes = 0;
-    // FP32 copies only for the transposed factors of a mixed domain (the
-    // adjoint's FP32 sweeps)
-    hipError_t e = alloc_slot(set[k], pa, trans && pen->dom->d.precision == STAU_MIXED, &bytes);
+    hipError_t e = alloc_slot(set[k], pa, &bytes);
     if (e != hipSuccess) return fail(STAU_ENOMEM, "factor allocation failed: %s", hipGetErrorString(e));
     pen->ws_bytes += (int64_t)bytes;
   }
@@ -1118,7 +1097,7 @@ int stau_evp(stau_pencils* pen, double tau, int iters, double* sigma, double* re
   auto& f = pen->evp;
   if (!f.Lraw) {
     size_t bytes = 0;
-    hipError_t e = alloc_slot(f, pe, false, &bytes);
+    hipError_t e = alloc_slot(f, pe, &bytes);
     if (e != hipSuccess) return fail(STAU_ENOMEM, "factor allocation failed: %s", hipGetErrorString(e));
     pen->ws_bytes += (int64_t)bytes;
   }
@@ -1200,15 +1179,13 @@ int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, 
   r.a2 = a2;
   r.hbar = (double2*)adj->hbar;
   r.Fbar = pen->Bev;
-  // mixed precision: FP32 transposed sweeps with one FP64-residual
-  // correction, FP32 adjoint transforms; X_bar, F_bar and the history stay FP64
+  // mixed precision: FP32 adjoint transforms; the transposed solve is FP64
+  // (FP32 sweeps with an FP64 residual and a correction sweep measured slower:
+  // 512x128 adjoint step 260 -> 150 us, 4096x64 303 -> 273 us), and X_bar,
+  // F_bar and the history stay FP64
   const bool mixed = pen->dom->d.precision == STAU_MIXED;
   // 1. transposed pencil solve + multistep history adjoints
-  if (mixed)
-    HIP_TRY(launch_solveT_mixed(pen->paT, a0, b0, adj->Xbar, fs->Lf32, fs->sl, fs->Uf32, adj->Xbar, r,
-                                st));
-  else
-    HIP_TRY(launch_solveT(pen->paT, adj->Xbar, fs->Lf, fs->sl, fs->Uf, adj->Xbar, r, st));
+  HIP_TRY(launch_solveT(pen->paT, adj->Xbar, fs->Lf, fs->sl, fs->Uf, adj->Xbar, r, st));
   // 2. adjoint of the forward z transform: H_bar = W^T F_bar
   FieldList fe{};
   fe.nf = pen->pa.desc.ne;

@@ -1,5 +1,5 @@
-// Host check of the structured operator applications used by the mixed
-// solves: apply_row (rows of A~) and apply_col (rows of A~^T) against the
+// Host check of the structured operator application used by the stability
+// iteration (M~ x): apply_row (rows of a0 M~ + b0 L~) against the
 // entry-by-entry matrix sys_entry, on random vectors, for 2-D and 3-D system
 // descriptions, several N, mean and non-mean pencils.  Prints the worst
 // relative error (scaled by the sum of |terms|) and exits 1 above 1e-14.
@@ -60,7 +60,7 @@ static void build(int dim, int N, SysDesc& d) {
 int main() {
   std::mt19937_64 gen(7);
   std::normal_distribution<double> nd;
-  double worst_row = 0, worst_col = 0;
+  double worst_row = 0;
   for (int dim = 2; dim <= 3; ++dim)
     for (int N : {4, 5, 16, 33})
       for (int mean = 0; mean < 2; ++mean)
@@ -73,26 +73,20 @@ int main() {
         if (nn == 0) pc.nncc = 0;
         if (nn == 2) pc.nncc = 3;
         const int n = d.S * N;  // kb + (N - 1) S + 1 with kb = S - 1
-        std::vector<double> x(n), y(n);
+        std::vector<double> x(n);
         for (auto& v : x) v = nd(gen);
-        for (auto& v : y) v = nd(gen);
         for (int i = 0; i < n; ++i) {
-          double rr = 0, rs = 0, cr = 0, cs = 0;
+          double rr = 0, rs = 0;
           for (int j = 0; j < n; ++j) {
             const double a = sys_entry(d, pc, i, j);  // A~(i, j)
             rr += a * x[j];
             rs += std::fabs(a * x[j]);
-            const double t = sys_entry(d, pc, j, i);  // A~^T(i, j)
-            cr += t * y[j];
-            cs += std::fabs(t * y[j]);
           }
           const double vr = apply_row(d, pc, i, [&](int m, int var) { return x[m * d.S + d.var_pos[var]]; });
-          const double vc = apply_col(d, pc, i, [&](int r) { return y[r]; });
-          const double er = std::fabs(vr - rr) / (rs + 1e-300), ec = std::fabs(vc - cr) / (cs + 1e-300);
+          const double er = std::fabs(vr - rr) / (rs + 1e-300);
           if (er > worst_row) worst_row = er;
-          if (ec > worst_col) worst_col = ec;
         }
       }
-  std::printf("apply_row %.3e apply_col %.3e\n", worst_row, worst_col);
-  return (worst_row > 1e-14 || worst_col > 1e-14) ? 1 : 0;
+  std::printf("apply_row %.3e\n", worst_row);
+  return worst_row > 1e-14 ? 1 : 0;
 }

@@ -1,5 +1,5 @@
-"""Mixed-precision step (FP32 transforms and products, FP32 sweeps with one
-FP64-residual correction, FP64 factorisation and boundary rows) against the
+"""Mixed-precision step (FP32 transforms and products; FP64 factorisation,
+pencil solve and boundary rows) against the
 FP64 oracle, per field.  The Chebyshev transforms run either as FP32 FFTs or
 as split-BF16 matrix-core products with FP32 accumulation; both are checked.
 

@@ -1,6 +1,6 @@
-"""The structured operator applications of the mixed solves (apply_row for
-A~ x, apply_col for A~^T y) against the entry-by-entry system matrix
-(sys_entry), compiled and run on the host."""
+"""The structured operator application of the stability iteration (apply_row
+for (a0 M~ + b0 L~) x) against the entry-by-entry system matrix (sys_entry),
+compiled and run on the host."""
 import os
 import shutil
 import subprocess
@@ -12,7 +12,7 @@ HIPCC = shutil.which("hipcc") or ("/opt/rocm/bin/hipcc" if os.path.exists("/opt/
 
 
 @pytest.mark.skipif(HIPCC is None, reason="hipcc not available")
-def test_apply_row_and_apply_col_match_sys_entry(tmp_path):
+def test_apply_row_matches_sys_entry(tmp_path):
     exe = tmp_path / "templates_check"
     src = os.path.join(ROOT, "tests", "host", "templates_check.cpp")
     inc = os.path.join(ROOT, "paper_1905_10388_amd", "csrc")
