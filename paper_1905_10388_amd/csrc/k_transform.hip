@@ -945,8 +945,10 @@ __global__ void __launch_bounds__(kZThreads) zadj_kernel(XformArgs a, AccList al
 // g_bar_i = (1/L) [Re c_0 + Re sum_{k>=1} c_k e^{2 pi i k i / L}]), applies the
 // product rule, and maps the eight grid adjoints back to spectra (adjoint of
 // the complex-to-real synthesis: c_bar_k = w_k sum_i g_bar_i e^{-2 pi i k i/L},
-// w_0 = 1, w_k = 2).
-template <int MAXBF, int PTS, int NT, bool TWL, typename T>
+// w_0 = 1, w_k = 2).  SPLIT: two blocks per row (blockIdx.y 0: the (u, w)
+// outputs, 1: the derivative outputs), for launches with fewer rows than
+// compute units; each block synthesises the fields its outputs need.
+template <int MAXBF, int PTS, int NT, bool TWL, typename T, bool SPLIT>
 __global__ void __launch_bounds__(NT) xpass_adj_kernel(XformArgs a,
                                                        const typename V2<T>::type* __restrict__ G,
                                                        const typename V2<T>::type* __restrict__ Hb,
@@ -1028,62 +1030,81 @@ __global__ void __launch_bounds__(NT) xpass_adj_kernel(XformArgs a,
     __syncthreads();
   };
 
-  T u[PTS], w[PTS], bx[PTS], bz[PTS], ux[PTS], uz[PTS], wx[PTS], wz[PTS];
-  T nb[PTS], nu[PTS], nw[PTS], t1[PTS], t2[PTS];
-  fetch(0);
+  // The grid fields are consumed as they are synthesised: the explicit-term
+  // adjoints first (n_b, n_u, n_w), then the derivative pairs accumulate the
+  // (u, w) adjoints t1 = -(n . grad_x), t2 = -(n . grad_z), and (u, w) feeds
+  // the derivative adjoints -n_q (u, w).  Part 1 computes the (u, w) outputs,
+  // part 2 the six derivative outputs (blocks of a split launch), part 0 both.
+  auto body = [&](auto part_c) {
+    constexpr int PART = decltype(part_c)::value;
+    constexpr int NS = PART == 1 ? 5 : PART == 2 ? 3 : 6;
+    // synthesis order: 4, 5 (H_bar), then part 1: 1, 2, 3; part 2: 0; part 0: 1, 2, 3, 0
+    auto seq = [](int i) { return i == 0 ? 4 : i == 1 ? 5 : PART == 2 ? 0 : i < 5 ? i - 1 : 0; };
+    T u[PTS], w[PTS], nb[PTS], nu[PTS], nw[PTS], t1[PTS], t2[PTS];
+    const T invL = (T)1 / (T)L;
+    fetch(seq(0));
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    scatter(k < 4 ? (T)1 : (T)0.5);
-    if (k + 1 < 6) fetch(k + 1);
-    __syncthreads();
-    fft_lds<+1, MAXBF, T, true>(buf, L, 1, tw, tid, NT);
+    for (int i = 0; i < NS; ++i) {
+      const int k = seq(i);
+      scatter(k < 4 ? (T)1 : (T)0.5);
+      if (i + 1 < NS) fetch(seq(i + 1));
+      __syncthreads();
+      fft_lds<+1, MAXBF, T, true>(buf, L, 1, tw, tid, NT);
 #pragma unroll
-    for (int q = 0; q < PTS; ++q) {
-      const int i = tid + q * NT;
-      if (i < L) {
-        const T x = buf[i].x, y = buf[i].y;
-        if (k == 0) { u[q] = x; w[q] = y; }
-        if (k == 1) { bx[q] = x; bz[q] = y; }
-        if (k == 2) { ux[q] = x; uz[q] = y; }
-        if (k == 3) { wx[q] = x; wz[q] = y; }
-        if (k == 4) { nb[q] = x; nu[q] = y; }
-        if (k == 5) { nw[q] = x; }
+      for (int q = 0; q < PTS; ++q) {
+        const int ii = tid + q * NT;
+        if (ii < L) {
+          const T x = buf[ii].x, y = buf[ii].y;
+          if (k == 4) {
+            nb[q] = x * invL;
+            nu[q] = y * invL;
+          } else if (k == 5) {
+            nw[q] = x * invL;
+          } else if (k == 0) {
+            u[q] = x;
+            w[q] = y;
+          } else if (k == 1) {
+            t1[q] = -(nb[q] * x);
+            t2[q] = -(nb[q] * y);
+          } else {
+            const T n = k == 2 ? nu[q] : nw[q];
+            t1[q] -= n * x;
+            t2[q] -= n * y;
+          }
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  const T invL = (T)1 / (T)L;
+    if constexpr (PART != 2) r2c_adj_pair(t1, t2, 0, 1);
+    if constexpr (PART != 1) {
 #pragma unroll
-  for (int q = 0; q < PTS; ++q) {
-    nb[q] *= invL;
-    nu[q] *= invL;
-    nw[q] *= invL;
-  }
-  // (u, w)
+      for (int q = 0; q < PTS; ++q) {
+        t1[q] = -nb[q] * u[q];
+        t2[q] = -nb[q] * w[q];
+      }
+      r2c_adj_pair(t1, t2, 2, 3);
 #pragma unroll
-  for (int q = 0; q < PTS; ++q) {
-    t1[q] = -(nb[q] * bx[q] + nu[q] * ux[q] + nw[q] * wx[q]);
-    t2[q] = -(nb[q] * bz[q] + nu[q] * uz[q] + nw[q] * wz[q]);
-  }
-  r2c_adj_pair(t1, t2, 0, 1);
+      for (int q = 0; q < PTS; ++q) {
+        t1[q] = -nu[q] * u[q];
+        t2[q] = -nu[q] * w[q];
+      }
+      r2c_adj_pair(t1, t2, 4, 5);
 #pragma unroll
-  for (int q = 0; q < PTS; ++q) {
-    t1[q] = -nb[q] * u[q];
-    t2[q] = -nb[q] * w[q];
+      for (int q = 0; q < PTS; ++q) {
+        t1[q] = -nw[q] * u[q];
+        t2[q] = -nw[q] * w[q];
+      }
+      r2c_adj_pair(t1, t2, 6, 7);
+    }
+  };
+  if constexpr (SPLIT) {
+    if (blockIdx.y == 0)
+      body(std::integral_constant<int, 1>{});
+    else
+      body(std::integral_constant<int, 2>{});
+  } else {
+    body(std::integral_constant<int, 0>{});
   }
-  r2c_adj_pair(t1, t2, 2, 3);
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) {
-    t1[q] = -nu[q] * u[q];
-    t2[q] = -nu[q] * w[q];
-  }
-  r2c_adj_pair(t1, t2, 4, 5);
-#pragma unroll
-  for (int q = 0; q < PTS; ++q) {
-    t1[q] = -nw[q] * u[q];
-    t2[q] = -nw[q] * w[q];
-  }
-  r2c_adj_pair(t1, t2, 6, 7);
 }
 
 // Kinetic-energy adjoint for one row: u_bar = e_bar_j u, w_bar = e_bar_j w with
@@ -1413,14 +1434,25 @@ static hipError_t launch_xpass_adj_t(const XformArgs& a, const void* G, const vo
   using S2 = typename V2<T>::type;
   const bool twl = (size_t)a.L * sizeof(S2) <= 32768;
   const size_t lds = (size_t)a.L * sizeof(S2) * (twl ? 2 : 1);
+  int dev = 0, cus = 0;
+  const bool split = hipGetDevice(&dev) == hipSuccess &&
+                     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                     a.M < cus;
+  auto go = [&](auto fn) {
+    allow_lds((const void*)fn, lds);
+    hipLaunchKernelGGL(fn, dim3(a.M, split ? 2 : 1), dim3(NT), lds, st, a, (const S2*)G,
+                       (const S2*)Hb, (S2*)Gb);
+  };
   if (twl) {
-    auto fn = xpass_adj_kernel<MAXBF, PTS, NT, true, T>;
-    allow_lds((const void*)fn, lds);
-    hipLaunchKernelGGL(fn, dim3(a.M), dim3(NT), lds, st, a, (const S2*)G, (const S2*)Hb, (S2*)Gb);
+    if (split)
+      go(xpass_adj_kernel<MAXBF, PTS, NT, true, T, true>);
+    else
+      go(xpass_adj_kernel<MAXBF, PTS, NT, true, T, false>);
   } else {
-    auto fn = xpass_adj_kernel<MAXBF, PTS, NT, false, T>;
-    allow_lds((const void*)fn, lds);
-    hipLaunchKernelGGL(fn, dim3(a.M), dim3(NT), lds, st, a, (const S2*)G, (const S2*)Hb, (S2*)Gb);
+    if (split)
+      go(xpass_adj_kernel<MAXBF, PTS, NT, false, T, true>);
+    else
+      go(xpass_adj_kernel<MAXBF, PTS, NT, false, T, false>);
   }
   return hipGetLastError();
 }

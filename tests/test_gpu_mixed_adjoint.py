@@ -42,9 +42,12 @@ def _rand_state(o, seed, amp=1.0):
     return X * np.exp(-np.arange(o.Nz) / (o.Nz / 5.0))
 
 
+# 32x16: 24 dealiased z rows (the x pass splits each row over two blocks);
+# 16x256: 384 rows, more than compute units (one block per row)
+@pytest.mark.parametrize("Nx,Nz", [(32, 16), (16, 256)])
 @pytest.mark.parametrize("iteration", [0, 3])
-def test_mixed_adjoint_step_matches_oracle(iteration):
-    Nx, Nz, Lx, Ra, Pr, dt = 32, 16, 4.0, 1e5, 1.0, 2e-3
+def test_mixed_adjoint_step_matches_oracle(iteration, Nx, Nz):
+    Lx, Ra, Pr, dt = 4.0, 1e5, 1.0, 2e-3
     g = RBSolver(Nx, Nz, Lx, Ra, Pr, precision="mixed")
     o = RBOracle(Nx, Nz, Lx, RBParams(Ra, Pr))
     Xp = _rand_state(o, 33, 0.2)
