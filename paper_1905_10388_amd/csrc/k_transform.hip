@@ -863,7 +863,7 @@ __global__ void ke_sum_kernel(const double2* __restrict__ c, int N, double* out)
 // c optionally multiplied by i k): c_bar_n += conj(i k) sum_j T_n(z_j) g_bar_j,
 // i.e. an unweighted DCT-II per source field, summed per target variable and
 // accumulated into Xbar[p][var][n].
-template <int MAXBF, int MAXIT, typename T>
+template <int MAXBF, int MAXIT, typename T, int EPT = kZEpt>
 __global__ void __launch_bounds__(kZThreads) zadj_kernel(XformArgs a, AccList al,
                                                          const typename V2<T>::type* __restrict__ Gb,
                                                          double2* __restrict__ Xb, int TP) {
@@ -871,7 +871,7 @@ __global__ void __launch_bounds__(kZThreads) zadj_kernel(XformArgs a, AccList al
   using cT = cpx<T>;
   const int M = a.M, N = a.N, S = a.S;
   cT* buf = (cT*)smem;
-  cT* twl = buf + kZPts;
+  cT* twl = buf + EPT * kZThreads;  // FFT twiddles after the EPT * kZThreads tile points
   cT* dcl = twl + M;
   const int ti = blockIdx.y;
   const int p0 = blockIdx.x * TP;
@@ -883,9 +883,9 @@ __global__ void __launch_bounds__(kZThreads) zadj_kernel(XformArgs a, AccList al
   for (int q = 0; q < al.nsrc[ti]; ++q) {
     const int f = al.src[ti][q], der = al.deriv[ti][q];
     {
-      cT hv[kZEpt];
+      cT hv[EPT];
 #pragma unroll
-      for (int it = 0; it < kZEpt; ++it) {
+      for (int it = 0; it < EPT; ++it) {
         const int idx = tid + it * nt;
         const int jz = idx / TP, s = idx - jz * TP;
         const int p = p0 + s;
@@ -893,7 +893,7 @@ __global__ void __launch_bounds__(kZThreads) zadj_kernel(XformArgs a, AccList al
         if (p < a.P) hv[it] = ldv<T>(Gb + ((size_t)f * M + jz) * a.P + p);
       }
 #pragma unroll
-      for (int it = 0; it < kZEpt; ++it) {
+      for (int it = 0; it < EPT; ++it) {
         const int idx = tid + it * nt;
         const int jz = idx / TP, s = idx - jz * TP;
         const int dst = (jz & 1) ? (M - 1 - (jz >> 1)) : (jz >> 1);
@@ -1253,13 +1253,13 @@ static int x_threads(int L) {
 // has fewer than kZBlocksPerCU blocks per compute unit: more, smaller blocks
 // keep every unit busy (1024x256: z backward 28.2 -> 24.9 us, z forward 30.8 ->
 // 25.7 us; quarter tiles measured no better).  Returns the divisor (1 or 2).
-static int z_split(int blocks, int M) {
+static int z_split(int blocks, int M, int per_cu = kZBlocksPerCU) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 1;
   int d = 1;
-  if (M <= kZPts / 2 && blocks < kZBlocksPerCU * cus) d = 2;
+  if (M <= kZPts / 2 && blocks < per_cu * cus) d = 2;
   return d;
 }
 
@@ -1411,19 +1411,26 @@ hipError_t launch_xpass3(const XformArgs& a, const void* G2, void* H2, hipStream
 
 hipError_t launch_zadj(const XformArgs& a, const AccList& al, const void* Gbar, void* Xbar,
                        hipStream_t st, bool fp32) {
-  const int TP = z_tile(a.M);
+  int TP = z_tile(a.M);
   if (TP * a.M != kZPts || TP * a.N > 12 * kZThreads) return hipErrorInvalidValue;
+  // half-size tiles when the full-size grid has fewer blocks than compute
+  // units (512x128: 102 -> 198 blocks, adjoint step 146 -> 139 us; at 4096x64,
+  // 390 -> 774 blocks, half tiles measured 7 us slower)
+  const int dv = z_split((a.P + TP - 1) / TP * al.nt, a.M, 1);
+  TP /= dv;
+  const int pts = kZPts / dv;
   dim3 grid((a.P + TP - 1) / TP, al.nt);
+  auto go = [&](auto kern, auto g) {
+    const size_t lds = (size_t)(pts + 2 * a.M) * sizeof(*g);
+    allow_lds((const void*)kern, lds);
+    hipLaunchKernelGGL(kern, grid, dim3(kZThreads), lds, st, a, al, g, (double2*)Xbar, TP);
+  };
   if (fp32) {
-    const size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(float2);
-    allow_lds((const void*)zadj_kernel<3, 12, float>, lds);
-    hipLaunchKernelGGL((zadj_kernel<3, 12, float>), grid, dim3(kZThreads), lds, st, a, al,
-                       (const float2*)Gbar, (double2*)Xbar, TP);
+    if (dv == 2) go(zadj_kernel<3, 12, float, kZEpt / 2>, (const float2*)Gbar);
+    else go(zadj_kernel<3, 12, float>, (const float2*)Gbar);
   } else {
-    const size_t lds = (size_t)(kZPts + 2 * a.M) * sizeof(double2);
-    allow_lds((const void*)zadj_kernel<3, 12, double>, lds);
-    hipLaunchKernelGGL((zadj_kernel<3, 12, double>), grid, dim3(kZThreads), lds, st, a, al,
-                       (const double2*)Gbar, (double2*)Xbar, TP);
+    if (dv == 2) go(zadj_kernel<3, 12, double, kZEpt / 2>, (const double2*)Gbar);
+    else go(zadj_kernel<3, 12, double>, (const double2*)Gbar);
   }
   return hipGetLastError();
 }
