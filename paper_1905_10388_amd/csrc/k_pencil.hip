@@ -970,6 +970,113 @@ __global__ void __launch_bounds__(kWave) coupling_kernel(
   for (int idx = lane; idx < Q * kl; idx += kWave) E2o[(size_t)p * Q * kl + idx] = E2[idx];
 }
 
+// ---------------------------------------------------------------------------
+// Transposed solve (adjoint of solve_kernel): B_bar = S_L^H A~^{-T} S_R^H
+// (P^R)^T X_bar, where A~ is the real-scaled recombined matrix, S_R the
+// column scaling (u = -i u~) and S_L the row scaling (u rows times i).  A~^T
+// has its own banded LU with partial pivoting (factor_kernel with a.trans),
+// so A~^{-T} is the same pair of sweeps as the forward solve, on the
+// transposed factors.
+// Epilogue (per pencil): the multistep history adjoints,
+//   F~_bar = c1 B_bar + hF,  MX_bar = -a1 B_bar + hM,  hF <- c2 B_bar,
+//   hM <- -a2 B_bar,  F_bar = (P^L)^T F~_bar,  X_bar_out = (P^L)^T MX_bar on
+//   the evolved variables, zero elsewhere.
+// ---------------------------------------------------------------------------
+// Entry c (system column order, 0 <= c < n) of the transposed solve's
+// right-hand side x~_bar = S_R^H (P^R)^T X_bar, real part (part 0) or
+// imaginary part (part 1).
+__device__ __forceinline__ double solveT_col(const SysDesc& d, const double2* __restrict__ Xp, int c,
+                                            int part) {
+  const int N = d.N, S = d.S;
+  const int m = c / S, pos = c - m * S;
+  const int var = d.var_at[pos];
+  const int vabi = d.abi_index[var];
+  double2 v = Xp[(size_t)vabi * N + m];
+  if (m >= 2) {
+    const double2 w2 = Xp[(size_t)vabi * N + m - 2];
+    v.x -= w2.x;
+    v.y -= w2.y;
+  }
+  if (var == VU || var == VUZ || var == VV || var == VVZ) return part == 0 ? -v.y : v.x;  // i v
+  return part == 0 ? v.x : v.y;
+}
+
+// Right-hand side of the transposed solve for one real part, written to
+// b[-BW .. npad + FW) (zero outside the n columns).
+__device__ __forceinline__ void solveT_rhs(const PencilArgs& a, const double2* __restrict__ Xp,
+                                           int part, double* b, int BW, int FW, int npad, int lane) {
+  for (int c = lane - BW; c < npad + FW; c += kWave)
+    b[c] = (c >= 0 && c < a.n) ? solveT_col(a.desc, Xp, c, part) : 0.0;
+}
+
+// Epilogue of the transposed solve (per pencil, all threads of the block):
+// history adjoints, (P^L)^T, state-layout outputs, from the solution's real
+// and imaginary parts bre / bim (system order).
+// sol(row) returns the solution's (real, imaginary) parts at system row `row`.
+template <typename SOL>
+__device__ __forceinline__ void solveT_epilogue_g(const PencilArgs& a, const AdjRhsArgs& r, SOL sol,
+                                                  double2* Xo, double2* Fb, double2* hb, int tid,
+                                                  int nt) {
+  const SysDesc& d = a.desc;
+  const int N = d.N, S = d.S, kb = d.kb, ne = d.ne;
+  auto bbar = [&](int e, int m) -> double2 {
+    if (m < 0 || m > N - 2) return make_double2(0.0, 0.0);
+    const int eq = e == 0 ? EB : (e == ne - 1 ? EW : (e == 1 ? EU : EV));
+    const int row = kb + m * S + d.eq_pos[eq];
+    const double2 rv = sol(row);
+    const double vr = rv.x, vi = rv.y;
+    if (eq == EU || eq == EV) return make_double2(vi, -vr);  // -i v
+    return make_double2(vr, vi);
+  };
+  for (int i = tid; i < ne * N; i += nt) {
+    const int e = i / N, m = i - e * N;
+    const size_t hF = ((size_t)0 * ne + e) * N, hM = ((size_t)1 * ne + e) * N;
+    auto ft = [&](int q) -> double2 {  // F~_bar_q
+      if (q < 0 || q > N - 2) return make_double2(0.0, 0.0);
+      const double2 bb = bbar(e, q), h = hb[hF + q];
+      return make_double2(r.c1 * bb.x + h.x, r.c1 * bb.y + h.y);
+    };
+    auto mx = [&](int q) -> double2 {  // MX_bar_q
+      if (q < 0 || q > N - 2) return make_double2(0.0, 0.0);
+      const double2 bb = bbar(e, q), h = hb[hM + q];
+      return make_double2(-r.a1 * bb.x + h.x, -r.a1 * bb.y + h.y);
+    };
+    const double cm = m == 0 ? 1.0 : 0.5;
+    const double2 f0 = ft(m), f2 = ft(m - 2), x0 = mx(m), x2 = mx(m - 2);
+    Fb[(size_t)e * N + m] = make_double2(cm * f0.x - 0.5 * f2.x, cm * f0.y - 0.5 * f2.y);
+    Xo[(size_t)(e + 1) * N + m] = make_double2(cm * x0.x - 0.5 * x2.x, cm * x0.y - 0.5 * x2.y);
+  }
+  for (int i = tid; i < S * N; i += nt) {
+    const int v = i / N;
+    if (v == 0 || v > ne) Xo[i] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int i = tid; i < ne * N; i += nt) {
+    const int e = i / N, m = i - e * N;
+    const double2 bb = bbar(e, m);
+    hb[((size_t)0 * ne + e) * N + m] = make_double2(r.c2 * bb.x, r.c2 * bb.y);
+    hb[((size_t)1 * ne + e) * N + m] = make_double2(-r.a2 * bb.x, -r.a2 * bb.y);
+  }
+}
+
+__device__ __forceinline__ void solveT_epilogue(const PencilArgs& a, const AdjRhsArgs& r,
+                                                const double* bre, const double* bim,
+                                                double2* __restrict__ Xo, double2* __restrict__ Fb,
+                                                double2* __restrict__ hb, int tid, int nt) {
+  solveT_epilogue_g(a, r, [&](int row) { return make_double2(bre[row], bim[row]); }, Xo, Fb, hb, tid,
+                    nt);
+}
+
+// zero outputs of an inactive pencil in the transposed solve
+__device__ __forceinline__ void solveT_zero(const PencilArgs& a, double2* __restrict__ Xo,
+                                            double2* __restrict__ Fb, double2* __restrict__ hb,
+                                            int tid, int nt) {
+  const int N = a.desc.N, S = a.desc.S, ne = a.desc.ne;
+  for (int i = tid; i < S * N; i += nt) Xo[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < ne * N; i += nt) Fb[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < 2 * ne * N; i += nt) hb[i] = make_double2(0.0, 0.0);
+}
+
 constexpr int kSU2 = 16;  // staging unit of the two-block solve (two blocks per compute unit)
 
 // LDS doubles of a pencil's coupling data (Rinv, E1, E2), rounded to 16 bytes
@@ -977,13 +1084,16 @@ __host__ __device__ inline int solve2_coupling_doubles(int K, int Q) { return (K
 
 // Two-block solve: one pencil per block of four wavefronts, wave 2 half + part
 // (half 0: leading block, 1: trailing block; part: real / imaginary).
-template <int FWT, int BWT, int FWB, int BWB>
+// TRANS: the adjoint's transposed solve on the two-block factors of A~^T
+// (t, bt with trans set): right-hand side from X_bar (Bev), the transposed
+// solve's epilogue with r, X_bar written in place (X).
+template <int FWT, int BWT, int FWB, int BWB, bool TRANS>
 __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
     PencilArgs t, PencilArgs bt, int plaunch, const double2* __restrict__ Bev,
     const double* __restrict__ Lft, const uint8_t* __restrict__ slt, const double* __restrict__ Uft,
     const double* __restrict__ Lfb, const uint8_t* __restrict__ slb, const double* __restrict__ Ufb,
     const double* __restrict__ Rinv, const double* __restrict__ E1, const double* __restrict__ E2,
-    double2* __restrict__ X) {
+    double2* __restrict__ X, AdjRhsArgs r) {
   extern __shared__ double lds[];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
@@ -993,10 +1103,20 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
   const SysDesc& d = t.desc;
   const int N = d.N, S = d.S, ne = d.ne, kb = d.kb;
   const int n = t.nfull, m = t.n, nb = bt.n, kl = t.kl, ku = t.ku, Q = t.Q, K = kl + ku;
-  if (blockIdx.x == 0 && plaunch < t.P) zero_pencils(X, plaunch, t.P, S * N, tid, 4 * kWave);
+  if constexpr (TRANS) {
+    if (blockIdx.x == 0)
+      for (int q = plaunch; q < t.P; ++q)
+        solveT_zero(t, X + (size_t)q * S * N, r.Fbar + (size_t)q * ne * N,
+                    r.hbar + (size_t)q * 2 * ne * N, tid, 4 * kWave);
+  } else {
+    if (blockIdx.x == 0 && plaunch < t.P) zero_pencils(X, plaunch, t.P, S * N, tid, 4 * kWave);
+  }
   double2* Xp = X + (size_t)p * S * N;
   if (!pencil_active(t, p)) {
-    zero_pencils(X, p, p + 1, S * N, tid, 4 * kWave);
+    if constexpr (TRANS)
+      solveT_zero(t, Xp, r.Fbar + (size_t)p * ne * N, r.hbar + (size_t)p * 2 * ne * N, tid, 4 * kWave);
+    else
+      zero_pencils(X, p, p + 1, S * N, tid, 4 * kWave);
     return;
   }
   const PencilCoef pc = pencil_coef(t, p, 0.0, 0.0);
@@ -1029,8 +1149,15 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
   }
   // right-hand side: zero fill (boundary values in the leading block), then
   // the evolved entries scattered to their rows (whole row R: leading block R,
-  // trailing block n - 1 - R)
-  {
+  // trailing block n - 1 - R).  TRANS: x~_bar by whole column (leading block
+  // c, trailing block n - 1 - c).
+  if constexpr (TRANS) {
+    const int BWx = half == 0 ? BWT : BWB, FWx = half == 0 ? FWT : FWB;
+    const int npad = half == 0 ? t.nst : bt.nst, nloc = half == 0 ? m : nb;
+    const double2* Xs = Bev + (size_t)p * S * N;
+    for (int c = lane - BWx; c < npad + FWx; c += kWave)
+      v[c] = (c >= 0 && c < nloc) ? solveT_col(d, Xs, half == 0 ? c : n - 1 - c, part) : 0.0;
+  } else {
     const int BWx = half == 0 ? BWT : BWB, FWx = half == 0 ? FWT : FWB;
     const int npad = half == 0 ? t.nst : bt.nst;
     for (int r = lane - BWx; r < npad + FWx; r += kWave) {
@@ -1122,6 +1249,16 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
   else
     sweep_backward_staged<double, BWB, kSU2>(v, Ufb + (size_t)p * bt.nst * BWB, bt.nst / kCH, lane, stg);
   __syncthreads();
+  if constexpr (TRANS) {
+    // solution row c: leading block for c < m, else the reversed trailing block
+    solveT_epilogue_g(
+        t, r,
+        [&](int c) {
+          return c < m ? make_double2(vt0[c], vt1[c]) : make_double2(vb0[n - 1 - c], vb1[n - 1 - c]);
+        },
+        Xp, r.Fbar + (size_t)p * ne * N, r.hbar + (size_t)p * 2 * ne * N, tid, 4 * kWave);
+    return;
+  }
   // X = P^R x~ (x~ row c: leading block for c < m, else the reversed trailing block)
   for (int i = tid; i < S * N; i += 4 * kWave) {
     const int vabi = i / N, mo = i - vabi * N;
@@ -1141,107 +1278,6 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
     else
       Xp[i] = make_double2(xr, xi);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Transposed solve (adjoint of solve_kernel): B_bar = S_L^H A~^{-T} S_R^H
-// (P^R)^T X_bar, where A~ is the real-scaled recombined matrix, S_R the
-// column scaling (u = -i u~) and S_L the row scaling (u rows times i).  A~^T
-// has its own banded LU with partial pivoting (factor_kernel with a.trans),
-// so A~^{-T} is the same pair of sweeps as the forward solve, on the
-// transposed factors.
-// Epilogue (per pencil): the multistep history adjoints,
-//   F~_bar = c1 B_bar + hF,  MX_bar = -a1 B_bar + hM,  hF <- c2 B_bar,
-//   hM <- -a2 B_bar,  F_bar = (P^L)^T F~_bar,  X_bar_out = (P^L)^T MX_bar on
-//   the evolved variables, zero elsewhere.
-// ---------------------------------------------------------------------------
-// Right-hand side of the transposed solve for one real part:
-// x~_bar = S_R^H (P^R)^T X_bar in system column order, written to b[-BW ..
-// npad + FW).
-__device__ __forceinline__ void solveT_rhs(const PencilArgs& a, const double2* __restrict__ Xp,
-                                           int part, double* b, int BW, int FW, int npad, int lane) {
-  const SysDesc& d = a.desc;
-  const int n = a.n, N = d.N, S = d.S;
-  for (int c = lane - BW; c < npad + FW; c += kWave) {
-    double vr = 0.0, vi = 0.0;
-    if (c >= 0 && c < n) {
-      const int m = c / S, pos = c - m * S;
-      const int var = d.var_at[pos];
-      const int vabi = d.abi_index[var];
-      double2 v = Xp[(size_t)vabi * N + m];
-      if (m >= 2) {
-        const double2 w2 = Xp[(size_t)vabi * N + m - 2];
-        v.x -= w2.x;
-        v.y -= w2.y;
-      }
-      if (var == VU || var == VUZ || var == VV || var == VVZ) {
-        vr = -v.y;  // i v
-        vi = v.x;
-      } else {
-        vr = v.x;
-        vi = v.y;
-      }
-    }
-    b[c] = part == 0 ? vr : vi;
-  }
-}
-
-// Epilogue of the transposed solve (per pencil, all threads of the block):
-// history adjoints, (P^L)^T, state-layout outputs, from the solution's real
-// and imaginary parts bre / bim (system order).
-__device__ __forceinline__ void solveT_epilogue(const PencilArgs& a, const AdjRhsArgs& r,
-                                                const double* bre, const double* bim,
-                                                double2* __restrict__ Xo, double2* __restrict__ Fb,
-                                                double2* __restrict__ hb, int tid, int nt) {
-  const SysDesc& d = a.desc;
-  const int N = d.N, S = d.S, kb = d.kb, ne = d.ne;
-  auto bbar = [&](int e, int m) -> double2 {
-    if (m < 0 || m > N - 2) return make_double2(0.0, 0.0);
-    const int eq = e == 0 ? EB : (e == ne - 1 ? EW : (e == 1 ? EU : EV));
-    const int row = kb + m * S + d.eq_pos[eq];
-    const double vr = bre[row], vi = bim[row];
-    if (eq == EU || eq == EV) return make_double2(vi, -vr);  // -i v
-    return make_double2(vr, vi);
-  };
-  for (int i = tid; i < ne * N; i += nt) {
-    const int e = i / N, m = i - e * N;
-    const size_t hF = ((size_t)0 * ne + e) * N, hM = ((size_t)1 * ne + e) * N;
-    auto ft = [&](int q) -> double2 {  // F~_bar_q
-      if (q < 0 || q > N - 2) return make_double2(0.0, 0.0);
-      const double2 bb = bbar(e, q), h = hb[hF + q];
-      return make_double2(r.c1 * bb.x + h.x, r.c1 * bb.y + h.y);
-    };
-    auto mx = [&](int q) -> double2 {  // MX_bar_q
-      if (q < 0 || q > N - 2) return make_double2(0.0, 0.0);
-      const double2 bb = bbar(e, q), h = hb[hM + q];
-      return make_double2(-r.a1 * bb.x + h.x, -r.a1 * bb.y + h.y);
-    };
-    const double cm = m == 0 ? 1.0 : 0.5;
-    const double2 f0 = ft(m), f2 = ft(m - 2), x0 = mx(m), x2 = mx(m - 2);
-    Fb[(size_t)e * N + m] = make_double2(cm * f0.x - 0.5 * f2.x, cm * f0.y - 0.5 * f2.y);
-    Xo[(size_t)(e + 1) * N + m] = make_double2(cm * x0.x - 0.5 * x2.x, cm * x0.y - 0.5 * x2.y);
-  }
-  for (int i = tid; i < S * N; i += nt) {
-    const int v = i / N;
-    if (v == 0 || v > ne) Xo[i] = make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int i = tid; i < ne * N; i += nt) {
-    const int e = i / N, m = i - e * N;
-    const double2 bb = bbar(e, m);
-    hb[((size_t)0 * ne + e) * N + m] = make_double2(r.c2 * bb.x, r.c2 * bb.y);
-    hb[((size_t)1 * ne + e) * N + m] = make_double2(-r.a2 * bb.x, -r.a2 * bb.y);
-  }
-}
-
-// zero outputs of an inactive pencil in the transposed solve
-__device__ __forceinline__ void solveT_zero(const PencilArgs& a, double2* __restrict__ Xo,
-                                            double2* __restrict__ Fb, double2* __restrict__ hb,
-                                            int tid, int nt) {
-  const int N = a.desc.N, S = a.desc.S, ne = a.desc.ne;
-  for (int i = tid; i < S * N; i += nt) Xo[i] = make_double2(0.0, 0.0);
-  for (int i = tid; i < ne * N; i += nt) Fb[i] = make_double2(0.0, 0.0);
-  for (int i = tid; i < 2 * ne * N; i += nt) hb[i] = make_double2(0.0, 0.0);
 }
 
 // STAGED: both sweeps staged in su3-column units.  Blocks cover pencils
@@ -1425,26 +1461,27 @@ hipError_t launch_coupling(const PencilArgs& t, const PencilArgs& bt, double a0,
   return hipGetLastError();
 }
 
-template <int FWT, int BWT, int FWB, int BWB>
+template <int FWT, int BWT, int FWB, int BWB, bool TRANS>
 static hipError_t launch_solve2_t(const PencilArgs& t, const PencilArgs& bt, const void* Bev,
                                   const double* Lft, const uint8_t* slt, const double* Uft,
                                   const double* Lfb, const uint8_t* slb, const double* Ufb,
                                   const double* Rinv, const double* E1, const double* E2, void* X,
-                                  hipStream_t st) {
+                                  const AdjRhsArgs& r, hipStream_t st) {
   const int plaunch = t.desc.dim == 2 ? t.Px - 1 : t.P;
   constexpr int SB = stage_bytes<double, (FWT > FWB ? FWT : FWB), (BWT > BWB ? BWT : BWB), kSU2>();
   const int K = t.kl + t.ku;
   if (K * K + t.Q * K > 8 * 4 * kWave) return hipErrorInvalidValue;
   const size_t lds = (size_t)(2 * (BWT + t.nst + FWT) + 2 * (BWB + bt.nst + FWB) + 2 * 64 +
                               solve2_coupling_doubles(K, t.Q)) * sizeof(double) + (size_t)4 * SB;
-  auto fn = solve2_kernel<FWT, BWT, FWB, BWB>;
+  auto fn = solve2_kernel<FWT, BWT, FWB, BWB, TRANS>;
   allow_lds((const void*)fn, lds);
   hipLaunchKernelGGL(fn, dim3(plaunch), dim3(4 * kWave), lds, st, t, bt, plaunch, (const double2*)Bev,
-                     Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, E2, (double2*)X);
+                     Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, E2, (double2*)X, r);
   return hipGetLastError();
 }
 
-#define STAU_SOLVE2_VARIANTS(X) X(8, 32, 32, 32) X(16, 32, 32, 32)
+// forward (leading FW 8 or 16) and transposed (leading FW 32, trailing 8) block widths
+#define STAU_SOLVE2_VARIANTS(X) X(8, 32, 32, 32) X(16, 32, 32, 32) X(32, 32, 8, 32)
 
 bool solve2_supported(const PencilArgs& t, const PencilArgs& bt) {
 #define STAU_CASE2(FT, BT, FB, BB) \
@@ -1459,12 +1496,25 @@ hipError_t launch_solve2(const PencilArgs& t, const PencilArgs& bt, const void* 
                          const double* Lfb, const uint8_t* slb, const double* Ufb,
                          const double* Rinv, const double* E1, const double* E2, void* X,
                          hipStream_t st) {
-#define STAU_CASE2(FT, BT, FB, BB)                                                             \
-  if (t.FW == FT && t.BW == BT && bt.FW == FB && bt.BW == BB)                                  \
-    return launch_solve2_t<FT, BT, FB, BB>(t, bt, Bev, Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, \
-                                           E2, X, st);
+  const AdjRhsArgs none{};
+#define STAU_CASE2(FT, BT, FB, BB)                                                                    \
+  if (t.FW == FT && t.BW == BT && bt.FW == FB && bt.BW == BB)                                         \
+    return launch_solve2_t<FT, BT, FB, BB, false>(t, bt, Bev, Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, \
+                                                  E2, X, none, st);
   STAU_SOLVE2_VARIANTS(STAU_CASE2)
 #undef STAU_CASE2
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_solve2T(const PencilArgs& t, const PencilArgs& bt, const void* Xin,
+                          const double* Lft, const uint8_t* slt, const double* Uft,
+                          const double* Lfb, const uint8_t* slb, const double* Ufb,
+                          const double* Rinv, const double* E1, const double* E2, void* Xout,
+                          const AdjRhsArgs& r, hipStream_t st) {
+  if (!t.trans || !bt.trans) return hipErrorInvalidValue;
+  if (t.FW == 32 && t.BW == 32 && bt.FW == 8 && bt.BW == 32)
+    return launch_solve2_t<32, 32, 8, 32, true>(t, bt, Xin, Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, E2,
+                                                Xout, r, st);
   return hipErrorInvalidValue;
 }
 

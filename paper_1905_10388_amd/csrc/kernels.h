@@ -251,6 +251,15 @@ struct AdjRhsArgs {
 hipError_t launch_solveT(const PencilArgs& a, const void* Xbar_in, const double* Lf,
                          const uint8_t* sl, const double* Uf, void* Xbar_out,
                          const AdjRhsArgs& r, hipStream_t st);
+// The same on the two-block factors of A~^T (t, bt: block descriptions with
+// trans set; leading block FW 32, trailing block FW 8): the two-block solve's
+// sweeps and interface system with the transposed solve's right-hand side and
+// epilogue.
+hipError_t launch_solve2T(const PencilArgs& t, const PencilArgs& bt, const void* Xbar_in,
+                          const double* Lft, const uint8_t* slt, const double* Uft,
+                          const double* Lfb, const uint8_t* slb, const double* Ufb,
+                          const double* Rinv, const double* E1, const double* E2, void* Xbar_out,
+                          const AdjRhsArgs& r, hipStream_t st);
 hipError_t launch_ke_adjoint(const XformArgs& a, const void* X, void* G, void* Gbar,
                              const void* wvec, void* ebar, void* Xbar, hipStream_t st);
 hipError_t launch_initial_state_adjoint(const XformArgs& a1, const void* Xbar, double* gbar,

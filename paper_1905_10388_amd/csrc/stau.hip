@@ -189,6 +189,9 @@ struct stau_pencils {
   // compute unit): leading / trailing block descriptions
   bool two = false;
   PencilArgs pt{}, pb{};
+  // the same for the transposed system (the adjoint's solves): blocks of A~^T
+  bool twoT = false;
+  PencilArgs ptT{}, pbT{};
   bool adj_ok = true;  // the transposed band fits the sweep windows
   int64_t clock = 0;
   FactorSlot* last = nullptr;  // factors of the most recent stau_factor
@@ -645,6 +648,32 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
                                   (Q * Q + Q * Q + 1) / 2 * 2) * 8 +
                          (size_t)4 * 2 * 16 * (FWm > BWm ? FWm : BWm) * 8;
       pen->two = ok && dom->Pa <= 2 * cus && 2 * lds <= (size_t)lds_cu;
+      // transposed blocks: the leading block of A~^T is the transpose of a
+      // leading block of A~ (split at a mode boundary), kl and ku swap (the
+      // reversed trailing block swaps them back).  Here the leading block has
+      // the wide forward window, so it takes the smaller share of the rows.
+      const int mT = kb + S * (int)((0.48 * pa.n - kb) / S);
+      PencilArgs& tT = pen->ptT;
+      PencilArgs& bT = pen->pbT;
+      tT = t;
+      tT.trans = 1;
+      tT.kl = pa.ku;
+      tT.ku = pa.kl;
+      tT.n = mT;
+      tT.nst = factor_stride(mT);
+      bT = b;
+      bT.trans = 1;
+      bT.kl = pa.kl;
+      bT.ku = pa.ku;
+      bT.n = pa.n - mT;
+      bT.nst = factor_stride(pa.n - mT);
+      const bool okT = pen->adj_ok && mT >= Q + 64 && pa.n - mT >= Q + 64 && window_widths(tT) &&
+                       window_widths(bT) && solve2_supported(tT, bT);
+      const int FWmT = tT.FW > bT.FW ? tT.FW : bT.FW, BWmT = tT.BW > bT.BW ? tT.BW : bT.BW;
+      const size_t ldsT = (size_t)(2 * (tT.BW + tT.nst + tT.FW) + 2 * (bT.BW + bT.nst + bT.FW) + 128 +
+                                   (Q * Q + Q * Q + 1) / 2 * 2) * 8 +
+                          (size_t)4 * 2 * 16 * (FWmT > BWmT ? FWmT : BWmT) * 8;
+      pen->twoT = okT && dom->Pa <= 2 * cus && 2 * ldsT <= (size_t)lds_cu;
     }
   }
 
@@ -797,15 +826,17 @@ static int factor_into(stau_pencils* pen, stau_pencils::FactorSlot* set, const P
   f.valid = false;
   const int big = 0x7fffffff;
   HIP_TRY(hipMemcpyAsync(pen->sing, &big, sizeof(int), hipMemcpyHostToDevice, st));
-  const bool two = pen->two && set == pen->slot;
+  const bool trans = set == pen->slotT;
+  const bool two = trans ? pen->twoT : (pen->two && set == pen->slot);
+  const PencilArgs& bt = trans ? pen->ptT : pen->pt;
+  const PencilArgs& bb = trans ? pen->pbT : pen->pb;
   HIP_TRY(timed(pen, K_FACTOR, st, [&] {
     if (!two) return launch_factor(pa, a0, b0, f.Lf, f.sl, f.Uf, pen->sing, st);
-    hipError_t e = launch_factor(pen->pt, a0, b0, f.LfT, f.slT, f.UfT, pen->sing, st, f.tLt, f.tPt);
+    hipError_t e = launch_factor(bt, a0, b0, f.LfT, f.slT, f.UfT, pen->sing, st, f.tLt, f.tPt);
+    if (e == hipSuccess) e = launch_factor(bb, a0, b0, f.LfB, f.slB, f.UfB, pen->sing, st, f.tLb, f.tPb);
     if (e == hipSuccess)
-      e = launch_factor(pen->pb, a0, b0, f.LfB, f.slB, f.UfB, pen->sing, st, f.tLb, f.tPb);
-    if (e == hipSuccess)
-      e = launch_coupling(pen->pt, pen->pb, a0, b0, f.tLt, f.tPt, f.tLb, f.tPb, f.UfT, f.UfB, f.Rinv,
-                          f.E1, f.E2, pen->sing, st);
+      e = launch_coupling(bt, bb, a0, b0, f.tLt, f.tPt, f.tLb, f.tPb, f.UfT, f.UfB, f.Rinv, f.E1, f.E2,
+                          pen->sing, st);
     return e;
   }));
   int h = big;
@@ -841,7 +872,8 @@ static int factors_for(stau_pencils* pen, double a0, double b0, hipStream_t st,
   else if (!set[1].valid) k = 1;
   if (!set[k].Lraw && !set[k].LTraw) {  // (two-block slots are allocated with the pencils)
     size_t bytes = 0;
-    hipError_t e = alloc_slot(set[k], pa, &bytes);
+    hipError_t e = (trans && pen->twoT) ? alloc_slot2(set[k], pen->ptT, pen->pbT, &bytes)
+                                        : alloc_slot(set[k], pa, &bytes);
     if (e != hipSuccess) return fail(STAU_ENOMEM, "factor allocation failed: %s", hipGetErrorString(e));
     pen->ws_bytes += (int64_t)bytes;
   }
@@ -1185,7 +1217,11 @@ int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, 
   // F_bar and the history stay FP64
   const bool mixed = pen->dom->d.precision == STAU_MIXED;
   // 1. transposed pencil solve + multistep history adjoints
-  HIP_TRY(launch_solveT(pen->paT, adj->Xbar, fs->Lf, fs->sl, fs->Uf, adj->Xbar, r, st));
+  if (pen->twoT)
+    HIP_TRY(launch_solve2T(pen->ptT, pen->pbT, adj->Xbar, fs->LfT, fs->slT, fs->UfT, fs->LfB, fs->slB,
+                           fs->UfB, fs->Rinv, fs->E1, fs->E2, adj->Xbar, r, st));
+  else
+    HIP_TRY(launch_solveT(pen->paT, adj->Xbar, fs->Lf, fs->sl, fs->Uf, adj->Xbar, r, st));
   // 2. adjoint of the forward z transform: H_bar = W^T F_bar
   FieldList fe{};
   fe.nf = pen->pa.desc.ne;
