@@ -297,7 +297,10 @@ typedef struct stau_adjstate {
  * where N' is the linearised explicit term (adjoint transforms and products on
  * the 3/2 grid).  Uses cached factors of (a0, b0), refactoring synchronously
  * if neither stored factorisation matches.  In a STAU_MIXED domain the
- * adjoint transforms and products run in FP32 (the transposed solve in FP64).  Sec. IX (IVP, multistep IMEX) is
+ * adjoint transforms and products run in FP32 (the transposed solve in FP64).
+ * The forward grid fields at X_prev are transformed on an internal
+ * non-blocking stream of the pencils object, forked from and joined back to
+ * `stream` with events, so the call stays ordered on `stream` alone.  Sec. IX (IVP, multistep IMEX) is
  * the forward operation; the adjoint is not part of the paper. */
 int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, double dt,
                       double dt_prev, stau_adjstate* adj, void* stream);

@@ -193,6 +193,10 @@ struct stau_pencils {
   bool twoT = false;
   PencilArgs ptT{}, pbT{};
   bool adj_ok = true;  // the transposed band fits the sweep windows
+  // adjoint step: a non-blocking side stream (default priority) and the
+  // fork / join events of the work it overlaps (created on first use)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int64_t clock = 0;
   FactorSlot* last = nullptr;  // factors of the most recent stau_factor
   int* sing = nullptr;     // device: first singular pencil (INT_MAX if none)
@@ -471,6 +475,11 @@ int stau_destroy_domain(stau_domain* dom) {
 }
 
 static void free_pencils(stau_pencils* p) {
+  if (p->side) (void)hipStreamDestroy(p->side);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  p->side = nullptr;
+  p->ev_fork = p->ev_join = nullptr;
   for (auto& ev : p->events) {
     hipEventDestroy(ev.a);
     hipEventDestroy(ev.b);
@@ -1216,6 +1225,17 @@ int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, 
   // 512x128 adjoint step 260 -> 150 us, 4096x64 303 -> 273 us), and X_bar,
   // F_bar and the history stay FP64
   const bool mixed = pen->dom->d.precision == STAU_MIXED;
+  // 3. (forward grid fields at X^{n-1}) needs only X_prev: it runs on the side
+  // stream, overlapping steps 1 and 2, which leave pen->G alone
+  if (!pen->side) {
+    HIP_TRY(hipStreamCreateWithFlags(&pen->side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&pen->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&pen->ev_join, hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventRecord(pen->ev_fork, st));
+  HIP_TRY(hipStreamWaitEvent(pen->side, pen->ev_fork, 0));
+  HIP_TRY(launch_zb(pen->xa, pen->fl, X_prev, pen->G, pen->side, mixed));
+  HIP_TRY(hipEventRecord(pen->ev_join, pen->side));
   // 1. transposed pencil solve + multistep history adjoints
   if (pen->twoT)
     HIP_TRY(launch_solve2T(pen->ptT, pen->pbT, adj->Xbar, fs->LfT, fs->slT, fs->UfT, fs->LfB, fs->slB,
@@ -1229,8 +1249,8 @@ int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, 
   fe.src_S = pen->pa.desc.ne;
   fe.wmode = 1;
   HIP_TRY(launch_zb(pen->xa, fe, pen->Bev, pen->H, st, mixed));
-  // 3. forward grid fields at X^{n-1}
-  HIP_TRY(launch_zb(pen->xa, pen->fl, X_prev, pen->G, st, mixed));
+  // (join step 3)
+  HIP_TRY(hipStreamWaitEvent(st, pen->ev_join, 0));
   // 4. adjoint x pass
   HIP_TRY(launch_xpass_adj(pen->xa, pen->G, pen->H, pen->Gb, st, mixed));
   // 5. adjoint of the backward z transform, accumulated into X_bar
