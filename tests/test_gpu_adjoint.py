@@ -84,6 +84,34 @@ def test_adjoint_step_matches_oracle(iteration, Nx, Nz):
             np.testing.assert_allclose(hbg[k, 1, e, :Nz - 1], nM[(k,)][e * Nz:e * Nz + Nz - 1], atol=1e-10 * np.abs(Xbar).max() / dt)
 
 
+@pytest.mark.parametrize("Nx,Nz", [(32, 64), (16, 256)])
+def test_adjoint_step_on_a_caller_stream_matches_default_stream(Nx, Nz):
+    """The adjoint step transforms the forward fields on an internal stream,
+    forked from and joined back to the caller's stream; on a caller stream
+    other than the default one the result must be the same, bit for bit."""
+    g = RBSolver(Nx, Nz, 4.0, 1e5, 1.0)
+    o = RBOracle(Nx, Nz, 4.0, RBParams(1e5, 1.0))
+    Xp = torch.from_numpy(_rand_state(o, 41, 0.2)).cuda()
+    Xbar0 = torch.from_numpy(_rand_state(o, 42)).cuda()
+    hbar0 = torch.from_numpy(si.complex_noise((o.Px, 2, o.ne, Nz), 43)).cuda()
+    out = []
+    for use_side in (False, True):
+        Xb, hb = Xbar0.clone(), hbar0.clone()
+        torch.cuda.synchronize()
+        if use_side:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    g.adjoint_step(Xp, 3, 2e-3, 2e-3, Xb, hb)
+            s.synchronize()
+        else:
+            for _ in range(3):
+                g.adjoint_step(Xp, 3, 2e-3, 2e-3, Xb, hb)
+        out.append((_np(Xb), _np(hb)))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_gradient_matches_oracle_small():
     Nx, Nz, Lx, Ra, Pr, dt, steps = 32, 16, 4.0, 2e4, 1.0, 5e-3, 12
     g = RBSolver(Nx, Nz, Lx, Ra, Pr)
