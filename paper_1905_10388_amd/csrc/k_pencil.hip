@@ -985,7 +985,7 @@ __global__ void __launch_bounds__(kWave) coupling_kernel(
 // Entry c (system column order, 0 <= c < n) of the transposed solve's
 // right-hand side x~_bar = S_R^H (P^R)^T X_bar, real part (part 0) or
 // imaginary part (part 1).
-__device__ __forceinline__ double solveT_col(const SysDesc& d, const double2* __restrict__ Xp, int c,
+__device__ __forceinline__ double solveT_col(const SysDesc& d, const double2* Xp, int c,
                                             int part) {
   const int N = d.N, S = d.S;
   const int m = c / S, pos = c - m * S;
@@ -1003,7 +1003,7 @@ __device__ __forceinline__ double solveT_col(const SysDesc& d, const double2* __
 
 // Right-hand side of the transposed solve for one real part, written to
 // b[-BW .. npad + FW) (zero outside the n columns).
-__device__ __forceinline__ void solveT_rhs(const PencilArgs& a, const double2* __restrict__ Xp,
+__device__ __forceinline__ void solveT_rhs(const PencilArgs& a, const double2* Xp,
                                            int part, double* b, int BW, int FW, int npad, int lane) {
   for (int c = lane - BW; c < npad + FW; c += kWave)
     b[c] = (c >= 0 && c < a.n) ? solveT_col(a.desc, Xp, c, part) : 0.0;
@@ -1085,15 +1085,16 @@ __host__ __device__ inline int solve2_coupling_doubles(int K, int Q) { return (K
 // Two-block solve: one pencil per block of four wavefronts, wave 2 half + part
 // (half 0: leading block, 1: trailing block; part: real / imaginary).
 // TRANS: the adjoint's transposed solve on the two-block factors of A~^T
-// (t, bt with trans set): right-hand side from X_bar (Bev), the transposed
-// solve's epilogue with r, X_bar written in place (X).
+// (t, bt with trans set): right-hand side from X_bar (XinT), the transposed
+// solve's epilogue with r, X_bar written to XoutT (the same array: these two
+// are not restrict-qualified; Bev and X are unused).
 template <int FWT, int BWT, int FWB, int BWB, bool TRANS>
 __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
     PencilArgs t, PencilArgs bt, int plaunch, const double2* __restrict__ Bev,
     const double* __restrict__ Lft, const uint8_t* __restrict__ slt, const double* __restrict__ Uft,
     const double* __restrict__ Lfb, const uint8_t* __restrict__ slb, const double* __restrict__ Ufb,
     const double* __restrict__ Rinv, const double* __restrict__ E1, const double* __restrict__ E2,
-    double2* __restrict__ X, AdjRhsArgs r) {
+    double2* __restrict__ X, const double2* XinT, double2* XoutT, AdjRhsArgs r) {
   extern __shared__ double lds[];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
@@ -1106,12 +1107,12 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
   if constexpr (TRANS) {
     if (blockIdx.x == 0)
       for (int q = plaunch; q < t.P; ++q)
-        solveT_zero(t, X + (size_t)q * S * N, r.Fbar + (size_t)q * ne * N,
+        solveT_zero(t, XoutT + (size_t)q * S * N, r.Fbar + (size_t)q * ne * N,
                     r.hbar + (size_t)q * 2 * ne * N, tid, 4 * kWave);
   } else {
     if (blockIdx.x == 0 && plaunch < t.P) zero_pencils(X, plaunch, t.P, S * N, tid, 4 * kWave);
   }
-  double2* Xp = X + (size_t)p * S * N;
+  double2* Xp = (TRANS ? XoutT : X) + (size_t)p * S * N;
   if (!pencil_active(t, p)) {
     if constexpr (TRANS)
       solveT_zero(t, Xp, r.Fbar + (size_t)p * ne * N, r.hbar + (size_t)p * 2 * ne * N, tid, 4 * kWave);
@@ -1154,7 +1155,7 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
   if constexpr (TRANS) {
     const int BWx = half == 0 ? BWT : BWB, FWx = half == 0 ? FWT : FWB;
     const int npad = half == 0 ? t.nst : bt.nst, nloc = half == 0 ? m : nb;
-    const double2* Xs = Bev + (size_t)p * S * N;
+    const double2* Xs = XinT + (size_t)p * S * N;
     for (int c = lane - BWx; c < npad + FWx; c += kWave)
       v[c] = (c >= 0 && c < nloc) ? solveT_col(d, Xs, half == 0 ? c : n - 1 - c, part) : 0.0;
   } else {
@@ -1286,7 +1287,7 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
 // blocks places at most one block per compute unit.
 template <int FW, int BW, bool STAGED>
 __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a, int plaunch,
-                                                           const double2* __restrict__ Xin,
+                                                           const double2* Xin,
                                                            const double* __restrict__ Lf,
                                                            const uint8_t* __restrict__ sl,
                                                            const double* __restrict__ Uf,
@@ -1475,8 +1476,12 @@ static hipError_t launch_solve2_t(const PencilArgs& t, const PencilArgs& bt, con
                               solve2_coupling_doubles(K, t.Q)) * sizeof(double) + (size_t)4 * SB;
   auto fn = solve2_kernel<FWT, BWT, FWB, BWB, TRANS>;
   allow_lds((const void*)fn, lds);
-  hipLaunchKernelGGL(fn, dim3(plaunch), dim3(4 * kWave), lds, st, t, bt, plaunch, (const double2*)Bev,
-                     Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, E2, (double2*)X, r);
+  if constexpr (TRANS)
+    hipLaunchKernelGGL(fn, dim3(plaunch), dim3(4 * kWave), lds, st, t, bt, plaunch, nullptr, Lft, slt,
+                       Uft, Lfb, slb, Ufb, Rinv, E1, E2, nullptr, (const double2*)Bev, (double2*)X, r);
+  else
+    hipLaunchKernelGGL(fn, dim3(plaunch), dim3(4 * kWave), lds, st, t, bt, plaunch, (const double2*)Bev,
+                       Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, E2, (double2*)X, nullptr, nullptr, r);
   return hipGetLastError();
 }
 
