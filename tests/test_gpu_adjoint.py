@@ -46,8 +46,10 @@ def test_initial_state_adjoint_matches_oracle():
 
 
 # 32x16: 24 dealiased z rows (the x pass splits each row over two blocks);
-# 16x256: 384 rows, more than compute units (one block per row)
-@pytest.mark.parametrize("Nx,Nz", [(32, 16), (16, 256)])
+# 16x256: 384 rows, more than compute units (one block per row), and the
+# two-block transposed solve; 1024x16: 512 pencils, more than compute units
+# (the transposed solve with both sweeps staged)
+@pytest.mark.parametrize("Nx,Nz", [(32, 16), (16, 256), (1024, 16)])
 @pytest.mark.parametrize("iteration", [0, 3])
 def test_adjoint_step_matches_oracle(iteration, Nx, Nz):
     Lx, Ra, Pr, dt = 4.0, 1e5, 1.0, 2e-3
