@@ -43,8 +43,9 @@ def _rand_state(o, seed, amp=1.0):
 
 
 # 32x16: 24 dealiased z rows (the x pass splits each row over two blocks);
-# 16x256: 384 rows, more than compute units (one block per row)
-@pytest.mark.parametrize("Nx,Nz", [(32, 16), (16, 256)])
+# 16x256: 384 rows, more than compute units (one block per row), and the
+# two-block transposed solve; 1024x16: 512 pencils (the staged transposed solve)
+@pytest.mark.parametrize("Nx,Nz", [(32, 16), (16, 256), (1024, 16)])
 @pytest.mark.parametrize("iteration", [0, 3])
 def test_mixed_adjoint_step_matches_oracle(iteration, Nx, Nz):
     Lx, Ra, Pr, dt = 4.0, 1e5, 1.0, 2e-3
