@@ -43,7 +43,7 @@ def to_grid_adjoint(o: RBOracle, gbar: np.ndarray) -> np.ndarray:
         Gbar = np.zeros((o.Px, o.Ngz), dtype=np.complex128)
         Gbar[: o.kx_active] = o.Ex.conj().T @ gbar        # g = Re(Ex G)
         return Gbar @ o.Bz                                 # G = c Bz^T, Bz real
-    Gy = np.einsum("ik,yiz->ykz", o.Ex.conj(), gbar)       # (Ngy, kx_active, Ngz)
+    Gy = np.matmul(o.Ex.conj().T, gbar)                    # (Ngy, kx_active, Ngz)
     Gfull = np.zeros((o.Ngy, o.Px, o.Ngz), dtype=np.complex128)
     Gfull[:, : o.kx_active] = Gy
     G = np.tensordot(o.Ey.conj().T, Gfull, axes=(1, 0))    # y backward adjoint
@@ -57,7 +57,7 @@ def from_grid_adjoint(o: RBOracle, cbar: np.ndarray) -> np.ndarray:
         return np.real(o.Fx.conj().T @ Hbar)               # H = Fx g
     Hbar = cbar[:, : o.kx_active] @ o.Fz                   # (Ny, kx_active, Ngz)
     Hy = np.tensordot(o.Fy.conj().T, Hbar, axes=(1, 0))    # (Ngy, kx_active, Ngz)
-    return np.real(np.einsum("ki,ykz->yiz", o.Fx.conj(), Hy))
+    return np.real(np.matmul(o.Fx.conj().T, Hy))
 
 
 def nonlinear_adjoint(o: RBOracle, X: np.ndarray, Fbar: np.ndarray) -> np.ndarray:
@@ -117,7 +117,7 @@ def initial_state_adjoint(o: RBOracle, Xbar: np.ndarray) -> np.ndarray:
     Fy1 = S.fourier_complex_forward_matrix(o.Ny, o.Ny)
     H = cbar[:, : o.kx_active] @ Fz1                       # (Ny, kx, Nz)
     H = np.tensordot(Fy1.conj().T, H, axes=(1, 0))         # (Ny grid, kx, Nz)
-    return np.real(np.einsum("ki,lkz->ilz", Fx1.conj(), H))
+    return np.real(np.matmul(Fx1.conj().T, H)).transpose(1, 0, 2)
 
 
 # ----------------------------------------------------------------------------

@@ -327,7 +327,7 @@ class RBOracle:
             return np.real(self.Ex @ G[: self.kx_active])    # x backward
         G = np.tensordot(self.Ey, G, axes=(1, 0))           # y backward
         G = G[:, : self.kx_active, :]
-        return np.real(np.einsum("ik,ykz->yiz", self.Ex, G))
+        return np.real(np.matmul(self.Ex, G))               # x backward, per y level
 
     def from_grid(self, g: np.ndarray) -> np.ndarray:
         """Real values on the dealiased grid -> truncated coefficients."""
@@ -336,7 +336,7 @@ class RBOracle:
             out = np.zeros((self.Px, self.Nz), dtype=np.complex128)
             out[: self.kx_active] = H @ self.Fz.T            # z forward
             return out
-        H = np.einsum("ki,yiz->ykz", self.Fx, g)             # x forward
+        H = np.matmul(self.Fx, g)                            # x forward, per y level
         H = np.tensordot(self.Fy, H, axes=(1, 0))            # y forward
         out = np.zeros((self.Ny, self.Px, self.Nz), dtype=np.complex128)
         out[:, : self.kx_active] = H @ self.Fz.T             # z forward
@@ -522,7 +522,7 @@ class RBOracle:
             out[: self.kx_active] = (Fx1 @ g) @ Fz1.T
             return out
         Fy1 = S.fourier_complex_forward_matrix(self.Ny, self.Ny)
-        H = np.einsum("ki,ilz->lkz", Fx1, g)                 # (Ny, Nx/2, Nz)
+        H = np.matmul(Fx1, g.transpose(1, 0, 2))             # (Ny, Nx/2, Nz)
         H = np.tensordot(Fy1, H, axes=(1, 0))
         out = np.zeros((self.Ny, self.Px, self.Nz), dtype=np.complex128)
         out[:, : self.kx_active] = H @ Fz1.T
@@ -536,7 +536,7 @@ class RBOracle:
             return np.real(Ex1 @ G[: self.kx_active])
         Ey1 = S.fourier_complex_backward_matrix(self.Ny, self.Ny)
         G = np.tensordot(Ey1, G, axes=(1, 0))[:, : self.kx_active, :]
-        return np.real(np.einsum("ik,lkz->ilz", Ex1, G))
+        return np.real(np.matmul(Ex1, G)).transpose(1, 0, 2)
 
     def initial_b_grid(self, xi: np.ndarray, amp: float = 1e-3) -> np.ndarray:
         """reading: b = 1 - z + amp z (1 - z) xi on the scale-1 grid."""

@@ -191,14 +191,3 @@ def cheb_integ_row(N: int) -> np.ndarray:
     ev = (np.arange(N) % 2) == 0
     out[ev] = 2.0 / (1.0 - n[ev] ** 2)
     return out
-
-
-def cheb_product_matrix(N: int, n: int) -> np.ndarray:
-    """Single-mode product <T_i|T_n T_j> = (delta_{i,j+n} + delta_{i,|j-n|}) / 2,
-    truncated to i, j < N."""
-    G = np.zeros((N, N))
-    for j in range(N):
-        if j + n < N:
-            G[j + n, j] += 0.5
-        G[abs(j - n), j] += 0.5
-    return G
