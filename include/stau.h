@@ -253,7 +253,10 @@ int stau_initial_state(stau_pencils* pen, const double* b_grid, void* X, void* s
  * written as zero. */
 int stau_nonlinear(stau_pencils* pen, const void* X, void* F, void* stream);
 
-/* Pencil solve alone with the stored factors: B_ev is device complex128
+/* Pencil solve alone with the factors of the operator (a0, b0) of the last
+ * successful stau_factor (refactored synchronously when later steps or
+ * boundary value solves have evicted them from the two-slot cache; STAU_ESTATE
+ * before any successful stau_factor).  B_ev is device complex128
  * [P][ne][Nz] holding the right-hand sides of the evolved-equation U-rows
  * n = 0..Nz-2 (entry Nz-1 ignored); the z-derivative and continuity rows are
  * zero and the boundary rows take the problem's Dirichlet values.  Writes X

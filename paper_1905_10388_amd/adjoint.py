@@ -23,8 +23,8 @@ def _forward(solver, b_grid, dt, steps, checkpoint):
     return solver.kinetic_energy(), ckpts
 
 
-def _reverse(solver, dt, steps, checkpoint, ckpts):
-    Xbar = solver.kinetic_energy_adjoint(solver.X)
+def _reverse(solver, dt, steps, checkpoint, ckpts, X_final):
+    Xbar = solver.kinetic_energy_adjoint(X_final)
     _, hbar = solver.new_adjoint_state()
     for start in sorted(ckpts, reverse=True):
         end = min(start + checkpoint, steps)
@@ -41,7 +41,7 @@ def _reverse(solver, dt, steps, checkpoint, ckpts):
 def kinetic_energy_and_gradient(solver, b_grid, dt: float, steps: int, checkpoint: int = 20):
     """(J, dJ/d b_grid) without autograd bookkeeping."""
     J, ckpts = _forward(solver, b_grid, dt, steps, checkpoint)
-    return J, _reverse(solver, dt, steps, checkpoint, ckpts)
+    return J, _reverse(solver, dt, steps, checkpoint, ckpts, solver.X.clone())
 
 
 class FinalKineticEnergy(torch.autograd.Function):
@@ -50,13 +50,18 @@ class FinalKineticEnergy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, b_grid, solver, dt, steps, checkpoint):
         J, ckpts = _forward(solver, b_grid, dt, steps, checkpoint)
+        # the final state of this forward pass seeds the reverse sweep, so
+        # stepping the solver between forward and backward does not change it
         ctx.solver, ctx.dt, ctx.steps, ctx.checkpoint, ctx.ckpts = solver, dt, steps, checkpoint, ckpts
+        ctx.X_final = solver.X.clone()
+        ctx.b_dtype, ctx.b_device = b_grid.dtype, b_grid.device
         return torch.tensor(J, dtype=torch.float64, device=b_grid.device)
 
     @staticmethod
     def backward(ctx, gJ):
-        g = _reverse(ctx.solver, ctx.dt, ctx.steps, ctx.checkpoint, ctx.ckpts)
-        return gJ * g, None, None, None, None
+        g = _reverse(ctx.solver, ctx.dt, ctx.steps, ctx.checkpoint, ctx.ckpts, ctx.X_final)
+        g = g.to(device=ctx.b_device, dtype=ctx.b_dtype)
+        return gJ.to(device=ctx.b_device, dtype=ctx.b_dtype) * g, None, None, None, None
 
 
 def final_kinetic_energy(b_grid, solver, dt: float, steps: int, checkpoint: int = 20):

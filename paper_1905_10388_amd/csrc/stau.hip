@@ -198,7 +198,11 @@ struct stau_pencils {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int64_t clock = 0;
-  FactorSlot* last = nullptr;  // factors of the most recent stau_factor
+  // (a0, b0) of the most recent successful stau_factor: stau_solve solves with
+  // the factors of this operator (looked up in the cache, refactored if the
+  // steps evicted them since)
+  bool has_last = false;
+  double last_a0 = 0.0, last_b0 = 0.0;
   int* sing = nullptr;     // device: first singular pencil (INT_MAX if none)
   int* flag = nullptr;     // device: non-finite flag
   double* scratch = nullptr;
@@ -901,7 +905,9 @@ int stau_factor(stau_pencils* pen, double a0, double b0, void* stream) {
   for (int q = 0; q < 2; ++q)
     if (pen->slot[q].valid && pen->slot[q].a0 == a0 && pen->slot[q].b0 == b0) k = q;
   int rc = factor_into(pen, pen->slot, pen->pa, k, a0, b0, st);
-  pen->last = rc ? nullptr : &pen->slot[k];
+  pen->has_last = rc == STAU_OK;
+  pen->last_a0 = a0;
+  pen->last_b0 = b0;
   return rc;
 }
 
@@ -1185,9 +1191,15 @@ int stau_nonlinear(stau_pencils* pen, const void* X, void* F, void* stream) {
 
 int stau_solve(stau_pencils* pen, const void* B_ev, void* X, void* stream) {
   if (!pen || !B_ev || !X) return fail(STAU_EINVAL, "null argument");
-  if (!pen->last) return fail(STAU_ESTATE, "stau_solve before a successful stau_factor");
+  if (!pen->has_last) return fail(STAU_ESTATE, "stau_solve before a successful stau_factor");
   HIP_TRY(hipSetDevice(pen->dom->d.device));
-  const stau_pencils::FactorSlot* f = pen->last;
+  // the slot stau_factor filled may have been refactored since for another
+  // operator (the step's and the boundary value solve's cache is shared)
+  stau_pencils::FactorSlot* f = nullptr;
+  {
+    int rc = factors_for(pen, pen->last_a0, pen->last_b0, (hipStream_t)stream, &f);
+    if (rc) return rc;
+  }
   if (pen->two)
     HIP_TRY(launch_solve2(pen->pt, pen->pb, B_ev, f->LfT, f->slT, f->UfT, f->LfB, f->slB, f->UfB, f->Rinv,
                           f->E1, f->E2, X, (hipStream_t)stream));
