@@ -241,11 +241,52 @@ int stau_lbvp(stau_pencils* pen, const void* F, void* X, void* stream);
 int stau_evp(stau_pencils* pen, double tau, int iters, double* sigma, double* resid, void* X,
              void* stream);
 
-/* Initial state from real scale-1 grid values of b (2-D b[ix][jz], 3-D
- * b[ix][ly][jz]; device, float64; Chebyshev Gauss grid in z ascending,
- * x_i = Lx i / Nx): forward transforms, bz = d_z b by the Chebyshev derivative
- * recursion, every other variable zero.  X is written entirely. */
+/* Initial state from real scale-1 grid values of b (Sec. IX "Initial
+ * conditions": the state is set in grid space and must satisfy the problem's
+ * constraints; Sec. VI "Data manipulation").  b_grid is device float64,
+ * 2-D b[ix][jz], 3-D b[ix][ly][jz], on the Chebyshev Gauss grid in z
+ * (ascending) and x_i = Lx i / Nx, y_l = Ly l / Ny.  Forward transforms, then
+ * bz = d_z b by the Chebyshev derivative recursion (so the first-order
+ * constraint bz - d_z b = 0 holds), every other variable zero.  X (device,
+ * state layout) is written entirely.  Asynchronous. */
 int stau_initial_state(stau_pencils* pen, const double* b_grid, void* X, void* stream);
+
+/* Grid <-> coefficient transforms of selected state variables (Sec. VI "Data
+ * manipulation": the grid and coefficient data of a field; Sec. IV "Scaled
+ * transforms & dealiasing": the transforms evaluated at a chosen scale).
+ * vars     bit mask of the variables of the state layout (bit v: variable v in
+ *          ABI order; non-empty, no bit at or above S, else STAU_EINVAL); the
+ *          grid holds the selected variables in increasing order.
+ * scale    1 (Nx x [Ny x] Nz grid points) or 1.5 (the dealiased 3/2 grid),
+ *          else STAU_EINVAL.
+ * grid     device float64 [nvars][Lg][Mg] (2-D) / [nvars][Lg][Lgy][Mg] (3-D),
+ *          Lg = scale Nx, Lgy = scale Ny, Mg = scale Nz: x_i = Lx i / Lg,
+ *          y_l = Ly l / Lgy, z_j = (1 - cos(pi (j + 1/2) / Mg)) / 2 ascending.
+ * X        device complex128, state layout.
+ * stau_coeff_to_grid: grid = sum over the stored modes (Nyquist modes
+ *          excluded) of c e^{i k.x} T_n(2 z - 1), real.  X is only read.
+ * stau_grid_to_coeff: the truncating forward transform (discrete
+ *          orthogonality on the grid): coefficients of the selected variables
+ *          for every pencil slot (Nyquist and unused slots zero); the other
+ *          variables of X are left unchanged.  At scale 1 this inverts
+ *          stau_coeff_to_grid on band-limited data.
+ * The two adjoint calls are the exact transposes under the real inner
+ * products (a complex coefficient is a pair of reals, so the adjoint of z is
+ * dJ/dRe z + i dJ/dIm z):
+ * stau_coeff_to_grid_adjoint: X_bar (selected variables overwritten, the
+ *          others unchanged) = adjoint of stau_coeff_to_grid applied to grid_bar;
+ * stau_grid_to_coeff_adjoint: grid_bar (written entirely) = adjoint of
+ *          stau_grid_to_coeff applied to the selected variables of X_bar.
+ * All four use the pencils object's transform workspaces (calls on one
+ * pencils object are ordered on their streams) and are asynchronous. */
+int stau_coeff_to_grid(stau_pencils* pen, const void* X, uint32_t vars, double scale, double* grid,
+                       void* stream);
+int stau_grid_to_coeff(stau_pencils* pen, const double* grid, uint32_t vars, double scale, void* X,
+                       void* stream);
+int stau_coeff_to_grid_adjoint(stau_pencils* pen, const double* grid_bar, uint32_t vars, double scale,
+                               void* X_bar, void* stream);
+int stau_grid_to_coeff_adjoint(stau_pencils* pen, const void* X_bar, uint32_t vars, double scale,
+                               double* grid_bar, void* stream);
 
 /* Explicit term alone: F = coefficients of -(u.grad) q for q in the evolved
  * fields, evaluated on the 3/2 grid (Sec. IV) from the state X.  F is device

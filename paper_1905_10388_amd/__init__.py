@@ -166,6 +166,65 @@ class RBSolver:
     def last_singular_pencil(self) -> int:
         return int(self.lib.stau_last_singular_pencil(self._pen))
 
+    # -- grid <-> coefficient transforms ------------------------------------
+    def vars_mask(self, names) -> int:
+        """Bit mask of state variables given by name ("b", "u", ...) or index."""
+        order = ("p", "b", "u", "w", "bz", "uz", "wz") if self.dim == 2 else \
+            ("p", "b", "u", "v", "w", "bz", "uz", "vz", "wz")
+        m = 0
+        for v in ([names] if isinstance(names, (str, int)) else names):
+            m |= 1 << (order.index(v) if isinstance(v, str) else int(v))
+        return m
+
+    def grid_shape(self, nvars: int, scale: float):
+        i = self.info
+        Lg, Mg = int(round(scale * i["Nx"])), int(round(scale * i["Nz"]))
+        if self.dim == 2:
+            return (nvars, Lg, Mg)
+        return (nvars, Lg, int(round(scale * i["Ny"])), Mg)
+
+    def coeff_to_grid(self, names, scale: float = 1.0, X=None):
+        """Grid values (float64 [nvars][x][(y)][z]) of the selected variables."""
+        t = self._torch
+        m = self.vars_mask(names)
+        Xs = (self.X if X is None else X).contiguous()
+        g = t.empty(self.grid_shape(bin(m).count("1"), scale), dtype=t.float64, device=self.device)
+        _lib.check(self.lib.stau_coeff_to_grid(self._pen, _ptr(Xs), m, float(scale), _ptr(g),
+                                               _stream_ptr()))
+        return g
+
+    def grid_to_coeff(self, names, grid, scale: float = 1.0, X=None):
+        """Coefficients of the selected variables from their grid values,
+        written into X (default: the solver's state); other variables kept."""
+        t = self._torch
+        m = self.vars_mask(names)
+        g = grid.to(device=self.device, dtype=t.float64).contiguous()
+        if tuple(g.shape) != self.grid_shape(bin(m).count("1"), scale):
+            raise ValueError(f"grid must have shape {self.grid_shape(bin(m).count('1'), scale)}")
+        Xo = self.X if X is None else X
+        _lib.check(self.lib.stau_grid_to_coeff(self._pen, _ptr(g), m, float(scale), _ptr(Xo),
+                                               _stream_ptr()))
+        return Xo
+
+    def coeff_to_grid_adjoint(self, names, grid_bar, scale: float = 1.0, X_bar=None):
+        t = self._torch
+        m = self.vars_mask(names)
+        g = grid_bar.to(device=self.device, dtype=t.float64).contiguous()
+        Xb = X_bar if X_bar is not None else t.zeros(self.state_shape, dtype=t.complex128,
+                                                     device=self.device)
+        _lib.check(self.lib.stau_coeff_to_grid_adjoint(self._pen, _ptr(g), m, float(scale), _ptr(Xb),
+                                                       _stream_ptr()))
+        return Xb
+
+    def grid_to_coeff_adjoint(self, names, X_bar, scale: float = 1.0):
+        t = self._torch
+        m = self.vars_mask(names)
+        Xb = X_bar.to(device=self.device, dtype=t.complex128).contiguous()
+        g = t.empty(self.grid_shape(bin(m).count("1"), scale), dtype=t.float64, device=self.device)
+        _lib.check(self.lib.stau_grid_to_coeff_adjoint(self._pen, _ptr(Xb), m, float(scale), _ptr(g),
+                                                       _stream_ptr()))
+        return g
+
     # -- components -------------------------------------------------------
     def nonlinear(self, X=None):
         t = self._torch

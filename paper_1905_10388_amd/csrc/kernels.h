@@ -112,8 +112,9 @@ hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, 
                         const double* Uf, void* X, hipStream_t st);
 
 // transforms along y and the 3-D x pass
+// ys: output scale in place of the default (0: 1 backward, 1 / Ngy forward)
 hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, void* Out,
-                        hipStream_t st, bool fp32 = false);
+                        hipStream_t st, bool fp32 = false, double ys = 0.0);
 hipError_t launch_xpass3(const XformArgs& a, const void* G2, void* H2, hipStream_t st,
                          bool fp32 = false);
 
@@ -270,6 +271,20 @@ hipError_t launch_initial_state_adjoint(const XformArgs& a1, const void* Xbar, d
 hipError_t launch_lbvp_rhs(const XformArgs& a, const void* F, void* Bev, hipStream_t st);
 hipError_t launch_initial_state(const XformArgs& a1, const double* bgrid, void* X, void* work,
                                 hipStream_t st);
+
+// grid <-> coefficient transforms (k_grid.hip): the x stage between spectral
+// rows s[f][jz][l][kx] and the grid g[f][ix][l][jz] (Lg x points, Ngy y levels,
+// Mg z levels; tw the Lg-point FFT table), dir +1 synthesis
+//   g = s0 Re c_0 + 2 s1 Re sum_{1 <= k < Pa} c_k e^{2 pi i k ix / Lg},
+// dir -1 analysis c_0 = s0 sum g, c_k = s1 sum g e^{-2 pi i k ix / Lg} (k < Pa,
+// zero up to Px); the variable gather / scatter of the state layout
+bool xgrid_supported(int Lg, int Mg);
+hipError_t launch_xgrid(const XformArgs& a, int dir, int nf, int Lg, int Ngy, int Mg,
+                        const double2* tw, const void* in, void* out, double s0, double s1,
+                        hipStream_t st);
+hipError_t launch_put_vars(int P, int S, int N, const FieldList& fl, const void* F, void* X,
+                           hipStream_t st);
+hipError_t launch_zero_vars(int P, int S, int N, const FieldList& fl, void* X, hipStream_t st);
 
 // kinetic energy: mean over x of |u|^2/2 per z row, then Chebyshev integral
 hipError_t launch_ke(const XformArgs& a, const void* X, void* G, void* G2, double* rowmean, double* out,

@@ -38,6 +38,7 @@ int fail(int code, const char* fmt, ...) {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+
 // exp(-2 pi i t / n) with t reduced modulo n in integers and the angle formed
 // in long double.
 void fft_table(int64_t n, std::vector<double2>& out) {
@@ -1172,6 +1173,140 @@ int stau_initial_state(stau_pencils* pen, const double* b_grid, void* X, void* s
   if (!pen || !b_grid || !X) return fail(STAU_EINVAL, "null argument");
   HIP_TRY(hipSetDevice(pen->dom->d.device));
   HIP_TRY(launch_initial_state(pen->xa1, b_grid, X, pen->scratch, (hipStream_t)stream));
+  return STAU_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Fields of a variable mask (bit v: variable v of the state layout).
+int vars_list(const stau_pencils* pen, uint32_t vars, FieldList* fl) {
+  const int S = pen->pa.desc.S;
+  if (vars == 0 || (vars >> S) != 0)
+    return fail(STAU_EINVAL, "vars 0x%x must be a non-empty mask of the %d state variables", vars, S);
+  *fl = FieldList{};
+  for (int v = 0; v < S; ++v)
+    if (vars & (1u << v)) {
+      fl->var[fl->nf] = v;
+      fl->deriv[fl->nf] = 0;
+      ++fl->nf;
+    }
+  return STAU_OK;
+}
+
+// Transform description and grid sizes of a grid scale (1 or 3/2).
+int grid_args(const stau_pencils* pen, double scale, XformArgs* xa, int* Lg, int* Ngy, int* Mg) {
+  if (scale == 1.0)
+    *xa = pen->xa1;
+  else if (scale == 1.5)
+    *xa = pen->xa;
+  else
+    return fail(STAU_EINVAL, "scale must be 1 or 1.5");
+  *Lg = xa->L;
+  *Ngy = xa->dim == 3 ? xa->Ngy : 1;
+  *Mg = xa->M;
+  if (!xgrid_supported(*Lg, *Mg)) return fail(STAU_EUNSUPPORTED, "grid of %d x points unsupported", *Lg);
+  return STAU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stau_coeff_to_grid(stau_pencils* pen, const void* X, uint32_t vars, double scale, double* grid,
+                       void* stream) {
+  if (!pen || !X || !grid) return fail(STAU_EINVAL, "null argument");
+  FieldList fl;
+  XformArgs xa;
+  int Lg, Ngy, Mg, rc;
+  if ((rc = vars_list(pen, vars, &fl)) || (rc = grid_args(pen, scale, &xa, &Lg, &Ngy, &Mg))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  HIP_TRY(launch_zb(xa, fl, X, pen->G, st));
+  const void* rows = pen->G;
+  if (xa.dim == 3) {
+    HIP_TRY(launch_ypass(xa, +1, fl.nf, pen->G, pen->G2, st));
+    rows = pen->G2;
+  }
+  HIP_TRY(launch_xgrid(xa, +1, fl.nf, Lg, Ngy, Mg, xa.twx, rows, grid, 1.0, 1.0, st));
+  return STAU_OK;
+}
+
+int stau_grid_to_coeff(stau_pencils* pen, const double* grid, uint32_t vars, double scale, void* X,
+                       void* stream) {
+  if (!pen || !X || !grid) return fail(STAU_EINVAL, "null argument");
+  FieldList fl;
+  XformArgs xa;
+  int Lg, Ngy, Mg, rc;
+  if ((rc = vars_list(pen, vars, &fl)) || (rc = grid_args(pen, scale, &xa, &Lg, &Ngy, &Mg))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  const bool d3 = xa.dim == 3;
+  // x analysis to spectral rows, (y analysis,) z analysis to F[P][nf][N]
+  double2* rows = d3 ? pen->G2 : pen->G;
+  HIP_TRY(launch_xgrid(xa, -1, fl.nf, Lg, Ngy, Mg, xa.twx, grid, rows, 1.0 / Lg, 1.0 / Lg, st));
+  if (d3) HIP_TRY(launch_ypass(xa, -1, fl.nf, pen->G2, pen->G, st));
+  double2* F = d3 ? pen->G2 : pen->Gb;
+  XformArgs az = xa;
+  az.ne = fl.nf;
+  RhsArgs r{};
+  r.mode = 0;
+  HIP_TRY(launch_zf(az, pen->G, F, r, st));
+  HIP_TRY(launch_put_vars(xa.P, xa.S, xa.N, fl, F, X, st));
+  return STAU_OK;
+}
+
+int stau_coeff_to_grid_adjoint(stau_pencils* pen, const double* grid_bar, uint32_t vars, double scale,
+                               void* X_bar, void* stream) {
+  if (!pen || !X_bar || !grid_bar) return fail(STAU_EINVAL, "null argument");
+  FieldList fl;
+  XformArgs xa;
+  int Lg, Ngy, Mg, rc;
+  if ((rc = vars_list(pen, vars, &fl)) || (rc = grid_args(pen, scale, &xa, &Lg, &Ngy, &Mg))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  const bool d3 = xa.dim == 3;
+  HIP_TRY(launch_zero_vars(xa.P, xa.S, xa.N, fl, X_bar, st));
+  // adjoint of the x synthesis: analysis with weights 1 (k = 0) and 2
+  double2* rows = d3 ? pen->G2 : pen->G;
+  HIP_TRY(launch_xgrid(xa, -1, fl.nf, Lg, Ngy, Mg, xa.twx, grid_bar, rows, 1.0, 2.0, st));
+  // adjoint of the y synthesis: the analysis without the 1 / Ngy
+  if (d3) HIP_TRY(launch_ypass(xa, -1, fl.nf, pen->G2, pen->G, st, false, 1.0));
+  // adjoint of the z synthesis, accumulated into the zeroed variables
+  AccList al{};
+  al.nt = fl.nf;
+  for (int f = 0; f < fl.nf; ++f) {
+    al.target[f] = fl.var[f];
+    al.nsrc[f] = 1;
+    al.src[f][0] = f;
+    al.src[f][1] = -1;
+  }
+  HIP_TRY(launch_zadj(xa, al, pen->G, X_bar, st));
+  return STAU_OK;
+}
+
+int stau_grid_to_coeff_adjoint(stau_pencils* pen, const void* X_bar, uint32_t vars, double scale,
+                               double* grid_bar, void* stream) {
+  if (!pen || !X_bar || !grid_bar) return fail(STAU_EINVAL, "null argument");
+  FieldList fl;
+  XformArgs xa;
+  int Lg, Ngy, Mg, rc;
+  if ((rc = vars_list(pen, vars, &fl)) || (rc = grid_args(pen, scale, &xa, &Lg, &Ngy, &Mg))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(pen->dom->d.device));
+  // adjoint of the z analysis: synthesis of the coefficients weighted by
+  // (2 - delta_n0) / Mg
+  fl.wmode = 1;
+  HIP_TRY(launch_zb(xa, fl, X_bar, pen->G, st));
+  const void* rows = pen->G;
+  if (xa.dim == 3) {
+    // adjoint of the y analysis: the synthesis scaled by 1 / Ngy
+    HIP_TRY(launch_ypass(xa, +1, fl.nf, pen->G, pen->G2, st, false, 1.0 / Ngy));
+    rows = pen->G2;
+  }
+  // adjoint of the x analysis: synthesis with weights 1 / Lg (k = 0) and 1 / (2 Lg)
+  HIP_TRY(launch_xgrid(xa, +1, fl.nf, Lg, Ngy, Mg, xa.twx, rows, grid_bar, 1.0 / Lg, 0.5 / Lg, st));
   return STAU_OK;
 }
 
