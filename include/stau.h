@@ -61,6 +61,10 @@ extern "C" {
 #define STAU_DCT_FFT 1
 #define STAU_DCT_MATMUL 2
 
+#define STAU_SOLVE_AUTO 0
+#define STAU_SOLVE_FP64 1
+#define STAU_SOLVE_REFINED 2
+
 /* IMEX Runge-Kutta schemes of stau_step_rk: the (1,1,1), (2,2,2) and (4,4,3)
  * schemes of Ascher, Ruuth & Spiteri (1997), orders 1, 2, 3, with 1, 2, 4
  * implicit stages. */
@@ -80,9 +84,9 @@ typedef struct stau_pencils stau_pencils;
  * dealias  transform scale; must be 1.5 (the 3/2 rule, Sec. IV).
  * precision STAU_FP64 (everything FP64) or STAU_MIXED (FP32 transforms and
  *          products in stau_step, stau_step_rk and stau_adjoint_step; the
- *          pencil factorisation, the pencil solves (the step's and the
- *          adjoint's transposed one), the state, history, right-hand side
- *          and their adjoints FP64.)  The
+ *          pencil factorisation, the adjoint's transposed solve, the state,
+ *          history, right-hand side and their adjoints FP64; the step's
+ *          solve as mixed_solve selects.)  The
  *          component calls (stau_nonlinear, stau_solve) and the
  *          kinetic-energy and initial-state adjoints run in FP64 in either
  *          mode.
@@ -96,7 +100,15 @@ typedef struct stau_pencils stau_pencils;
  *          (each operand split into three BF16 terms): STAU_DCT_MATMUL needs
  *          Nz = 64, 128 or 256 there (else STAU_EUNSUPPORTED) and
  *          STAU_DCT_AUTO takes them for Nz = 64; otherwise the mixed step
- *          uses the FP32 FFT. */
+ *          uses the FP32 FFT.
+ * mixed_solve  the pencil solve of the mixed-precision steps (ignored in
+ *          FP64 domains): STAU_SOLVE_FP64 (FP64 sweeps on the FP64 factors),
+ *          STAU_SOLVE_REFINED (FP32 sweeps on FP32 copies of the FP64
+ *          factors, the residual of the first solution in FP64 from the
+ *          operator templates, one FP32 correction sweep, the sum in FP64;
+ *          single-block sweep layout), STAU_SOLVE_AUTO (FP64, the faster of
+ *          the two at every size measured).  Else STAU_EINVAL.
+ * reserved must be 0. */
 typedef struct stau_domain_desc {
   int32_t dim;
   int32_t precision;
@@ -105,6 +117,8 @@ typedef struct stau_domain_desc {
   double dealias;
   int32_t device;
   int32_t dct_method;
+  int32_t mixed_solve;
+  int32_t reserved;
 } stau_domain_desc;
 
 /* Rayleigh-Benard parameters in free-fall units: kappa = (Ra Pr)^(-1/2),

@@ -38,7 +38,7 @@ class RBSolver:
     def __init__(self, Nx: int, Nz: int, Lx: float, Ra: float, Pr: float, *, dim: int = 2,
                  Ny: int = 1, Ly: float = 1.0, precision: str = "fp64", buoyancy: float = 1.0,
                  b_bottom: float = 1.0, b_top: float = 0.0, device: int = 0, dct: str = "auto",
-                 gamma=()):
+                 gamma=(), mixed_solve: str = "auto"):
         import torch
 
         self._torch = torch
@@ -47,7 +47,9 @@ class RBSolver:
         desc = _lib.DomainDesc(dim=dim, precision={"fp64": _lib.STAU_FP64, "mixed": _lib.STAU_MIXED}[precision],
                                Nx=Nx, Ny=Ny, Nz=Nz, Lx=Lx, Ly=Ly, dealias=1.5, device=device,
                                dct_method={"auto": _lib.STAU_DCT_AUTO, "fft": _lib.STAU_DCT_FFT,
-                                           "matmul": _lib.STAU_DCT_MATMUL}[dct])
+                                           "matmul": _lib.STAU_DCT_MATMUL}[dct],
+                               mixed_solve={"auto": _lib.STAU_SOLVE_AUTO, "fp64": _lib.STAU_SOLVE_FP64,
+                                            "refined": _lib.STAU_SOLVE_REFINED}[mixed_solve])
         gamma = tuple(float(g) for g in gamma)
         if len(gamma) > 4:
             raise ValueError("at most 4 Chebyshev terms of Gamma(z)")

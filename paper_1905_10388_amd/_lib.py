@@ -20,6 +20,9 @@ STAU_MIXED = 1
 STAU_DCT_AUTO = 0
 STAU_DCT_FFT = 1
 STAU_DCT_MATMUL = 2
+STAU_SOLVE_AUTO = 0
+STAU_SOLVE_FP64 = 1
+STAU_SOLVE_REFINED = 2
 
 RK_SCHEMES = {"RK111": 1, "RK222": 2, "RK443": 3}
 
@@ -41,7 +44,8 @@ KERNEL_KINDS = ("z_backward", "x_pass", "z_forward_rhs", "pencil_solve", "pencil
 class DomainDesc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("Nx", C.c_int64),
                 ("Ny", C.c_int64), ("Nz", C.c_int64), ("Lx", C.c_double), ("Ly", C.c_double),
-                ("dealias", C.c_double), ("device", C.c_int32), ("dct_method", C.c_int32)]
+                ("dealias", C.c_double), ("device", C.c_int32), ("dct_method", C.c_int32),
+                ("mixed_solve", C.c_int32), ("reserved", C.c_int32)]
 
 
 class RBParamsC(C.Structure):

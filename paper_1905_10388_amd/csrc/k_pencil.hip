@@ -23,7 +23,6 @@
 namespace stau {
 
 constexpr int kWave = 64;
-constexpr int kCW = 64;  // factor column window (>= kv + 1)
 constexpr int kCH = 64;  // sweep chunk: columns per unrolled loop body
 constexpr int kRing = 32;  // look-ahead of the factor loads in the sweeps (columns)
 
@@ -102,8 +101,20 @@ __device__ __forceinline__ bool pencil_active(const PencilArgs& a, int p) {
 }
 
 // ---------------------------------------------------------------------------
-// Factor: one wavefront per pencil.  Band held in an LDS window of kCW
-// columns, LAPACK layout (row i of column c at kv + i - c).  With a.trans the
+// Factor: banded LU with partial pivoting, one wavefront per pencil, the
+// active part of the band in registers.  Before step j, lane l holds one
+// column c of the window j..j+63 (c = l mod 64) and rows j..j+kl of it in
+// av[0..kl] (av[i] zero for i > kl).  Step j: the pivot row (first largest
+// |a_ij|) is found in the lane of column j, rows j and j+d are interchanged in
+// every lane (a wave-uniform register swap), the multipliers of column j are
+// formed there and read by every lane, and each lane holding a column of
+// j+1..j+kv applies the rank-1 update to its rows.  Then the rows move up by
+// one and each lane appends row j+kl+1 of its column from the operator
+// templates; the lane of column j moves on to column j+64, whose rows
+// j+1..j+kl lie outside the band (kl + ku <= 63).  Row j of U goes to an LDS
+// staging area (kv + 1 entries per column, entry k = c - r) and column j's
+// BW-lane solve record is written when it completes (step j).  The
+// multipliers go straight to their forward-window slots.  With a.trans the
 // transposed matrix is factored (kl and ku of `a` are then those of the
 // transpose), for the adjoint's transposed solves.
 // ---------------------------------------------------------------------------
@@ -120,6 +131,7 @@ __device__ __forceinline__ double block_entry(const PencilArgs& a, const PencilC
 
 // With tailL (two-block solve), the last Q columns' pivot offsets (tailP) and
 // multipliers (tailL, kl per column) are also written in elimination order.
+template <int FW>
 __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, double b0,
                                                        double* __restrict__ Lf,
                                                        uint8_t* __restrict__ sl,
@@ -127,126 +139,118 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
                                                        int* __restrict__ sing,
                                                        double* __restrict__ tailL,
                                                        uint8_t* __restrict__ tailP) {
-  extern __shared__ double lds[];
+  extern __shared__ double ustage[];  // [64][kv + 2]: U(r, c) at (c mod 64, c - r)
   const int p = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int n = a.n, kl = a.kl, ku = a.ku, kv = kl + ku, ld = kv + kl + 1;
-  const int FW = a.FW, BW = a.BW;
-  double* win = lds;                                  // kCW * ld
-  __shared__ int phys[64];
-  __shared__ int spiv;
   if (!pencil_active(a, p)) return;
+  const int lane = threadIdx.x;
+  const int n = a.n, kl = a.kl, ku = a.ku, kv = kl + ku, BW = a.BW, us = kv + 2;
   const PencilCoef pc = pencil_coef(a, p, a0, b0);
-  const SysDesc d = a.desc;
-
-  auto assemble = [&](int c) {
-    double* col = win + (c % kCW) * ld;
-    for (int q = lane; q < ld; q += kWave) {
-      const int r = c - kv + q;
-      double v = 0.0;
-      if (r >= 0 && r < n && r >= c - ku) v = block_entry(a, pc, r, c);
-      col[q] = v;
-    }
-  };
-  for (int c = 0; c <= kv && c < n; ++c) assemble(c);
-  if (lane < FW) phys[lane] = lane;
-  __syncthreads();
-
   double* Lp = Lf + (size_t)p * a.nst * FW;
   double* Up = Uf + (size_t)p * a.nst * BW;
   uint8_t* sp = sl + (size_t)p * a.nst;
-
-  for (int j = 0; j < n; ++j) {
-    double* cj = win + (j % kCW) * ld;
-    const int hi = min(n - 1, j + kl);
-    // --- pivot search: first index of the largest |a_ij|, i = j..hi
-    double mag = -1.0;
-    int idx = j;
-    if (lane <= hi - j) {
-      mag = fabs(cj[kv + lane]);
-      idx = j + lane;
-    }
+  auto entry = [&](int r, int c) -> double {
+    if (r >= n || c >= n || c - r > ku || r - c > kl) return 0.0;
+    return block_entry(a, pc, r, c);
+  };
+  int c = lane;  // this lane's column
+  double av[FW];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      double om = __shfl_xor(mag, off);
-      int oi = __shfl_xor(idx, off);
-      if (om > mag || (om == mag && oi < idx)) {
-        mag = om;
-        idx = oi;
+  for (int i = 0; i < FW; ++i) av[i] = i <= kl ? entry(i, c) : 0.0;
+  int ph = lane;  // lane s < FW: the physical slot of forward-window position s
+  for (int j = 0; j < n; ++j) {
+    const int pl = j & (kWave - 1);
+    const int hi = min(n - 1, j + kl) - j;  // rows j..j+hi exist
+    // pivot search (used from lane pl): first index of the largest |a|
+    double mag = fabs(av[0]);
+    int idx = 0;
+#pragma unroll
+    for (int i = 1; i < FW; ++i) {
+      const double m = fabs(av[i]);
+      if (i <= hi && m > mag) {
+        mag = m;
+        idx = i;
       }
     }
-    const int pr = idx;
-    // --- swap rows j and pr over columns j..j+kv
-    const int cmax = min(n - 1, j + kv);
-    if (pr != j) {
-      for (int c = j + lane; c <= cmax; c += kWave) {
-        double* cc = win + (c % kCW) * ld;
-        double t = cc[kv + j - c];
-        cc[kv + j - c] = cc[kv + pr - c];
-        cc[kv + pr - c] = t;
-      }
+    const int d = __builtin_amdgcn_readlane(idx, pl);
+    // interchange rows j and j + d in every column
+    if (d != 0) {
+#pragma unroll
+      for (int i = 1; i < FW; ++i)
+        if (i == d) {
+          const double t = av[0];
+          av[0] = av[i];
+          av[i] = t;
+        }
     }
-    __syncthreads();
-    double piv = cj[kv];
+    double piv = readlane_d(av[0], pl);
     if (!(fabs(piv) > 0.0) || !isfinite(piv)) {
       if (lane == 0) atomicMin(sing, p);
       piv = 1.0;
     }
     const double rinv = 1.0 / piv;
-    // --- multipliers
-    if (lane >= 1 && lane <= hi - j) cj[kv + lane] *= rinv;
-    __syncthreads();
-    // --- rank-1 update of rows j+1..hi, columns j+1..cmax
-    const int nr = hi - j, nc = cmax - j;
-    for (int t = lane; t < nr * nc; t += kWave) {
-      const int i = 1 + t / nc, cc = 1 + t % nc;
-      double* col = win + ((j + cc) % kCW) * ld;
-      col[kv + (j + i) - (j + cc)] -= cj[kv + i] * col[kv + j - (j + cc)];
+    // multipliers of column j, read by every lane (zero beyond row j + hi)
+    double lm[FW];
+    lm[0] = 0.0;
+#pragma unroll
+    for (int i = 1; i < FW; ++i) lm[i] = i <= hi ? readlane_d(av[i], pl) * rinv : 0.0;
+    // rank-1 update of columns j+1..j+kv
+    if (lane != pl && c <= j + kv) {
+#pragma unroll
+      for (int i = 1; i < FW; ++i) av[i] -= lm[i] * av[0];
     }
-    // --- emit column j: U rotated into the backward window
-    for (int l = lane; l < BW; l += kWave) {
-      const int r = j - ((j - l) % BW + BW) % BW;
+    // row j of U (columns j..j+kv; the pivot as its reciprocal), then the solve
+    // record of column j: lane l carries row r = j - ((j - l) mod BW)
+    if (c <= j + kv) ustage[(c & (kWave - 1)) * us + (c - j)] = c == j ? rinv : av[0];
+    __builtin_amdgcn_wave_barrier();
+    if (lane < BW) {
+      const int k = (j - lane) & (BW - 1);
       double v = 0.0;
-      if (r == j)
-        v = rinv;
-      else if (r >= 0 && j - r <= kv)
-        v = cj[kv + r - j];
-      Up[(size_t)j * BW + l] = v;
+      if (k <= kv && k <= j) v = ustage[pl * us + k];
+      Up[(size_t)j * BW + lane] = v;
+    }
+    // multipliers routed to the physical slots of the forward window: swap
+    // the slots of positions 0 and d, the pivot's slot gets 0, then the
+    // window advances (the pivot's slot is refilled by the incoming row)
+    const int spv = __shfl(ph, d);
+    const int t0 = __shfl(ph, 0);
+    if (d != 0) {
+      if (lane == 0) ph = spv;
+      if (lane == d) ph = t0;
+    }
+    if (lane == 0) sp[j] = (uint8_t)spv;
+    if (lane < FW) {
+      double lv = 0.0;
+#pragma unroll
+      for (int i = 1; i < FW; ++i)
+        if (lane == i) lv = lm[i];
+      Lp[(size_t)j * FW + ph] = lv;
     }
     if (tailL && j >= n - a.Q) {
       const int q = j - (n - a.Q);
-      if (lane < kl) tailL[((size_t)p * a.Q + q) * kl + lane] = (lane + 1 <= hi - j) ? cj[kv + lane + 1] : 0.0;
-      if (lane == 0) tailP[(size_t)p * a.Q + q] = (uint8_t)(pr - j);
+      if (lane < kl) {
+        double tv = 0.0;
+#pragma unroll
+        for (int i = 1; i < FW; ++i)
+          if (lane + 1 == i) tv = lm[i];
+        tailL[((size_t)p * a.Q + q) * kl + lane] = tv;
+      }
+      if (lane == 0) tailP[(size_t)p * a.Q + q] = (uint8_t)d;
     }
-    // --- emit column j: multipliers routed to physical forward slots
-    if (lane == 0) spiv = pr;
-    __syncthreads();
     {
-      const int dd = spiv - j;
-      const int s = phys[dd];
-      const int t0 = phys[0];
-      __syncthreads();
-      if (lane == 0) {
-        phys[dd] = t0;
-        phys[0] = s;
-        sp[j] = (uint8_t)s;
-      }
-      __syncthreads();
-      double lv = 0.0;
-      int slot = -1;
-      if (lane >= 1 && lane < FW) {
-        slot = phys[lane];
-        lv = (lane <= hi - j) ? cj[kv + lane] : 0.0;
-      }
-      if (lane < FW) Lp[(size_t)j * FW + (lane == 0 ? s : slot)] = (lane == 0 ? 0.0 : lv);
-      __syncthreads();
-      int nxt = (lane < FW - 1) ? phys[lane + 1] : s;
-      __syncthreads();
-      if (lane < FW) phys[lane] = nxt;
+      int nxt = __shfl_down(ph, 1);
+      if (lane == FW - 1) nxt = spv;
+      if (lane < FW) ph = nxt;
     }
-    __syncthreads();
-    if (j + kv + 1 < n) assemble(j + kv + 1);
-    __syncthreads();
+    // rows j+1..j+1+kl for the next step
+    const bool fresh = lane == pl;
+    if (fresh) c += kWave;
+    const double nv = entry(j + 1 + kl, c);
+#pragma unroll
+    for (int i = 0; i < FW; ++i) {
+      double v = (i + 1 < FW && !fresh) ? av[i + 1] : 0.0;
+      if (i >= kl) v = i == kl ? nv : 0.0;
+      av[i] = v;
+    }
   }
 }
 
@@ -734,6 +738,125 @@ __global__ void __launch_bounds__(4 * kWave) solve_kernel(PencilArgs a, int plau
     write_state(a, bre, bim, X + (size_t)p * S * N, tid & (2 * kWave - 1), 2 * kWave);
   else if (live)
     zero_pencils(X, p, p + 1, S * N, tid & (2 * kWave - 1), 2 * kWave);
+}
+
+// ---------------------------------------------------------------------------
+// Refined mixed-precision solve: FP32 sweeps on FP32 copies of the FP64
+// factors, the FP64 residual r = b - A x^ of the first solution (A applied
+// from the operator templates, every row including the boundary rows; b
+// re-read from Bev in FP64), one FP32 correction sweep, and x = x^ + d summed
+// in FP64 when the state is written.  Per wavefront (one real part) in LDS:
+// the FP32 sweep vector w (padded, span) and x^ (n).  STG: 0 unstaged sweeps,
+// 2 both sweeps staged in su3<float>() column units (launches with more
+// blocks than compute units).
+// ---------------------------------------------------------------------------
+// Entry of the real-scaled right-hand side at row r (as build_rhs writes it)
+__device__ __forceinline__ double rhs_entry(const PencilArgs& a, const PencilCoef& pc,
+                                            const double2* __restrict__ Bp, int part, int r) {
+  const SysDesc& d = a.desc;
+  if (r < d.kb) {
+    if (part == 0 && pc.mean && d.bc_var[r] == VB) return d.bc_side[r] == 0 ? a.b_bottom : a.b_top;
+    return 0.0;
+  }
+  const int q = r - d.kb, mo = q / d.S;
+  const int eq = d.eq_at[q - mo * d.S];
+  if (mo >= d.N - 1) return 0.0;
+  int e = -1;
+  if (eq == EB) e = 0;
+  else if (eq == EU) e = 1;
+  else if (eq == EV) e = 2;
+  else if (eq == EW) e = d.ne - 1;
+  if (e < 0) return 0.0;
+  const double2 v = Bp[e * d.N + mo];
+  const bool scaled = eq == EU || eq == EV;  // rows scaled by i
+  return part == 0 ? (scaled ? -v.y : v.x) : (scaled ? v.x : v.y);
+}
+
+template <int FW, int BW, int STG>
+__global__ void __launch_bounds__(4 * kWave) solve_refined_kernel(PencilArgs a, int plaunch,
+                                                                  const double2* __restrict__ Bev,
+                                                                  const float* __restrict__ Lf,
+                                                                  const uint8_t* __restrict__ sl,
+                                                                  const float* __restrict__ Uf,
+                                                                  double2* __restrict__ X) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = wv >> 1, part = wv & 1;
+  const int p = blockIdx.x * 2 + q;
+  const SysDesc& d = a.desc;
+  const int n = a.n, N = d.N, S = d.S, ne = d.ne;
+  if (blockIdx.x == 0 && plaunch < a.P) zero_pencils(X, plaunch, a.P, S * N, tid, 4 * kWave);
+  const bool live = p < plaunch;
+  const bool act = live && pencil_active(a, p);
+  const int npad = a.nst, nch = npad / kCH;
+  const int span = BW + npad + FW;
+  const int per = (span + n + 3) / 4 * 4;  // floats per wavefront, 16-byte multiple
+  float* base = (float*)lds + (size_t)wv * per;
+  float* w = base + BW;          // sweep vector, rows -BW .. npad + FW
+  float* xh = base + span;       // first solution x^
+  float* stg = (float*)lds + (size_t)4 * per + (size_t)wv * (stage_bytes<float, FW, BW, su3<float>()>() / 4);
+  if (act) {
+    const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
+    const double2* Bp = Bev + (size_t)p * ne * N;
+    const float* Lp = Lf + (size_t)p * npad * FW;
+    const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
+    const float* Up = Uf + (size_t)p * npad * BW;
+    auto sweep = [&]() {
+      if constexpr (STG == 2)
+        sweeps_staged_both<float, FW, BW>(w, Lp, swp, Up, nch, lane, stg);
+      else
+        sweeps<float, FW, BW>(w, Lp, swp, Up, nch, lane);
+    };
+    build_rhs<float>(a, pc, Bp, part, w, nullptr, BW, FW, npad, lane);
+    sweep();
+    for (int r = lane; r < n; r += kWave) xh[r] = w[r];
+    // FP64 residual of x^ (every row of the system), rounded to FP32
+    const PencilCoef pa = pencil_coef(a, p, a.refine_a0, a.refine_b0);
+    for (int r = lane - BW; r < npad + FW; r += kWave) {
+      float v = 0.0f;
+      if (r >= 0 && r < n) {
+        const double ax =
+            apply_row(d, pa, r, [&](int m, int var) { return (double)xh[m * S + d.var_pos[var]]; });
+        v = (float)(rhs_entry(a, pc, Bp, part, r) - ax);
+      }
+      w[r] = v;
+    }
+    sweep();
+  }
+  __syncthreads();
+  if (act) {
+    // X = P^R (x^ + d) with the real scaling undone, summed in FP64
+    const float* hr = (const float*)lds + (size_t)(2 * q) * per + span;
+    const float* hi = (const float*)lds + (size_t)(2 * q + 1) * per + span;
+    const float* dr = (const float*)lds + (size_t)(2 * q) * per + BW;
+    const float* di = (const float*)lds + (size_t)(2 * q + 1) * per + BW;
+    double2* Xp = X + (size_t)p * S * N;
+    for (int i = tid & (2 * kWave - 1); i < S * N; i += 2 * kWave) {
+      const int vabi = i / N, m = i - vabi * N;
+      const int var = a.var_of_abi[vabi];
+      const int c = m * S + d.var_pos[var];
+      double xr = (double)hr[c] + (double)dr[c], xi = (double)hi[c] + (double)di[c];
+      if (m + 2 < N) {
+        xr -= (double)hr[c + 2 * S] + (double)dr[c + 2 * S];
+        xi -= (double)hi[c + 2 * S] + (double)di[c + 2 * S];
+      }
+      if (var == VU || var == VUZ || var == VV || var == VVZ)
+        Xp[i] = make_double2(xi, -xr);  // u = -i u~
+      else
+        Xp[i] = make_double2(xr, xi);
+    }
+  } else if (live) {
+    zero_pencils(X, p, p + 1, S * N, tid & (2 * kWave - 1), 2 * kWave);
+  }
+}
+
+__global__ void round_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
+                                    size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1338,10 +1461,16 @@ int factor_slack() { return kRing; }
 
 hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, uint8_t* sl,
                          double* Uf, int* sing, hipStream_t st, double* tailL, uint8_t* tailP) {
-  const int kv = a.kl + a.ku, ld = kv + a.kl + 1;
-  size_t lds = (size_t)kCW * ld * sizeof(double);
-  hipLaunchKernelGGL(factor_kernel, dim3(a.P), dim3(kWave), lds, st, a, a0, b0, Lf, sl, Uf, sing,
-                     tailL, tailP);
+  const int kv = a.kl + a.ku;
+  if (a.kl + 1 > a.FW || kv + 1 > a.BW || kv > kWave - 1) return hipErrorInvalidValue;
+  const size_t lds = (size_t)kWave * (kv + 2) * sizeof(double);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(a.P), dim3(kWave), lds, st, a, a0, b0, Lf, sl, Uf, sing, tailL, tailP);
+  };
+  if (a.FW == 8) go(factor_kernel<8>);
+  else if (a.FW == 16) go(factor_kernel<16>);
+  else if (a.FW == 32) go(factor_kernel<32>);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -1427,6 +1556,43 @@ hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, 
   STAU_SWEEP_VARIANTS(STAU_CASE)
 #undef STAU_CASE
   return hipErrorInvalidValue;
+}
+
+template <int FW, int BW>
+static hipError_t launch_solve_refined_t(const PencilArgs& a, const void* Bev, const float* Lf,
+                                         const uint8_t* sl, const float* Uf, void* X, hipStream_t st) {
+  const int span = BW + a.nst + FW;
+  const size_t per = (size_t)(span + a.n + 3) / 4 * 4 * sizeof(float);
+  const int plaunch = a.desc.dim == 2 ? a.Px - 1 : a.P;
+  const int blocks = (plaunch + 1) / 2;
+  int dev = 0, cus = 0;
+  const bool many = hipGetDevice(&dev) == hipSuccess &&
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                    blocks > cus;
+  auto go = [&](auto kern, size_t lds) {
+    allow_lds((const void*)kern, lds);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(4 * kWave), lds, st, a, plaunch, (const double2*)Bev,
+                       Lf, sl, Uf, (double2*)X);
+  };
+  if (many)
+    go(solve_refined_kernel<FW, BW, 2>, 4 * per + (size_t)4 * stage_bytes<float, FW, BW, su3<float>()>());
+  else
+    go(solve_refined_kernel<FW, BW, 0>, 4 * per);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_refined(const PencilArgs& a, const void* Bev, const float* Lf, const uint8_t* sl,
+                                const float* Uf, void* X, hipStream_t st) {
+#define STAU_CASE(F, B) \
+  if (a.FW == F && a.BW == B) return launch_solve_refined_t<F, B>(a, Bev, Lf, sl, Uf, X, st);
+  STAU_SWEEP_VARIANTS(STAU_CASE)
+#undef STAU_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_round_f32(const double* src, float* dst, size_t count, hipStream_t st) {
+  hipLaunchKernelGGL(round_to_f32_kernel, dim3(1024), dim3(256), 0, st, src, dst, count);
+  return hipGetLastError();
 }
 
 template <int FW, int BW>

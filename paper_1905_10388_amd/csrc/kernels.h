@@ -24,6 +24,7 @@ struct PencilArgs {
   int P, Px, Ny;
   double kappa, nu, buoyancy, b_bottom, b_top;
   double lin;  // PencilCoef::lin of every pencil (0 for the step's operators)
+  double refine_a0, refine_b0;  // operator of the refined mixed solve's residual
   int nncc;    // non-constant coefficient Gamma(z): Chebyshev terms (0: none)
   double ncc[kMaxNcc];
   double two_pi_over_Lx, two_pi_over_Ly;
@@ -110,6 +111,12 @@ hipError_t launch_evp(const PencilArgs& a, double tau, int iters, const double* 
                       hipStream_t st);
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
                         const double* Uf, void* X, hipStream_t st);
+// Mixed-precision solve with one FP64 refinement: FP32 sweeps on the FP32
+// factor copies, the FP64 residual of (a.refine_a0 M~ + a.refine_b0 L~) from
+// the templates, an FP32 correction sweep, the sum in FP64
+hipError_t launch_solve_refined(const PencilArgs& a, const void* Bev, const float* Lf, const uint8_t* sl,
+                                const float* Uf, void* X, hipStream_t st);
+hipError_t launch_round_f32(const double* src, float* dst, size_t count, hipStream_t st);
 
 // transforms along y and the 3-D x pass
 // ys: output scale in place of the default (0: 1 backward, 1 / Ngy forward)

@@ -180,6 +180,8 @@ struct stau_pencils {
     uint8_t *slT = nullptr, *slB = nullptr;
     double *tLt = nullptr, *tLb = nullptr, *Rinv = nullptr, *E1 = nullptr, *E2 = nullptr;
     uint8_t *tPt = nullptr, *tPb = nullptr;
+    // refined mixed solve: FP32 copies of Lf / Uf (with the same slack)
+    float *L32raw = nullptr, *U32raw = nullptr, *Lf32 = nullptr, *Uf32 = nullptr;
     bool valid = false;
     double a0 = 0.0, b0 = 0.0;
     int64_t stamp = 0;
@@ -194,6 +196,9 @@ struct stau_pencils {
   bool twoT = false;
   PencilArgs ptT{}, pbT{};
   bool adj_ok = true;  // the transposed band fits the sweep windows
+  // mixed domains: the step's solve as FP32 sweeps with one FP64 refinement
+  // (single-block layout) instead of the FP64 sweeps
+  bool refined = false;
   // adjoint step: a non-blocking side stream (default priority) and the
   // fork / join events of the work it overlaps (created on first use)
   hipStream_t side = nullptr;
@@ -368,6 +373,8 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
     return fail(STAU_EINVAL, "precision %d unknown", d.precision);
   if (d.dct_method < STAU_DCT_AUTO || d.dct_method > STAU_DCT_MATMUL)
     return fail(STAU_EINVAL, "dct_method %d unknown", d.dct_method);
+  if (d.mixed_solve < STAU_SOLVE_AUTO || d.mixed_solve > STAU_SOLVE_REFINED)
+    return fail(STAU_EINVAL, "mixed_solve %d unknown", d.mixed_solve);
   if (d.dct_method == STAU_DCT_MATMUL && !mm_supported((int)d.Nz))
     return fail(STAU_EUNSUPPORTED, "matrix-product z transforms need Nz a multiple of 32 in [32, 256]");
   if (d.dct_method == STAU_DCT_MATMUL && d.precision == STAU_MIXED && !mm_bf16_supported((int)d.Nz))
@@ -505,7 +512,7 @@ static void free_pencils(stau_pencils* p) {
       hipFree(f.Uraw);
       for (void* q : {(void*)f.LTraw, (void*)f.UTraw, (void*)f.LBraw, (void*)f.UBraw, (void*)f.sTraw,
                       (void*)f.sBraw, (void*)f.tLt, (void*)f.tLb, (void*)f.Rinv, (void*)f.E1,
-                      (void*)f.E2, (void*)f.tPt, (void*)f.tPb})
+                      (void*)f.E2, (void*)f.tPt, (void*)f.tPb, (void*)f.L32raw, (void*)f.U32raw})
         (void)hipFree(q);
       f = stau_pencils::FactorSlot{};
     }
@@ -515,7 +522,8 @@ static void free_pencils(stau_pencils* p) {
 }
 
 // Allocate (zeroed) factor storage for one slot of the band description pa.
-static hipError_t alloc_slot(stau_pencils::FactorSlot& f, const PencilArgs& pa, size_t* bytes) {
+static hipError_t alloc_slot(stau_pencils::FactorSlot& f, const PencilArgs& pa, size_t* bytes,
+                             bool fp32 = false) {
   const size_t sk = (size_t)factor_slack();
   const size_t cols = (size_t)pa.P * pa.nst + 2 * sk;
   hipError_t e = hipSuccess;
@@ -527,10 +535,18 @@ static hipError_t alloc_slot(stau_pencils::FactorSlot& f, const PencilArgs& pa, 
   get((void**)&f.Lraw, cols * pa.FW * sizeof(double));
   get((void**)&f.Uraw, cols * pa.BW * sizeof(double));
   get((void**)&f.sraw, cols);
+  if (fp32) {
+    get((void**)&f.L32raw, cols * pa.FW * sizeof(float));
+    get((void**)&f.U32raw, cols * pa.BW * sizeof(float));
+  }
   if (e != hipSuccess) return e;
   f.Lf = f.Lraw + sk * pa.FW;
   f.Uf = f.Uraw + sk * pa.BW;
   f.sl = f.sraw + sk;
+  if (fp32) {
+    f.Lf32 = f.L32raw + sk * pa.FW;
+    f.Uf32 = f.U32raw + sk * pa.BW;
+  }
   return hipSuccess;
 }
 
@@ -623,6 +639,7 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   // the transposed operator (adjoint) swaps kl and ku; when it does not fit the
   // sweep windows the adjoint calls are refused for this pencils object
   pen->adj_ok = window_widths(paT);
+  pen->refined = d.precision == STAU_MIXED && d.mixed_solve == STAU_SOLVE_REFINED;
   // Two-block solve for 2-D domains with at most two pencils per compute
   // unit: the system splits at m = kb + S k near n / 2 (a leading block that
   // ends inside a mode is singular) into two halves swept in parallel.  In
@@ -661,7 +678,8 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
       const size_t lds = (size_t)(2 * (t.BW + t.nst + t.FW) + 2 * (b.BW + b.nst + b.FW) + 128 +
                                   (Q * Q + Q * Q + 1) / 2 * 2) * 8 +
                          (size_t)4 * 2 * 16 * (FWm > BWm ? FWm : BWm) * 8;
-      pen->two = ok && dom->Pa <= 2 * cus && 2 * lds <= (size_t)lds_cu;
+      // (the refined mixed solve has the single-block layout only)
+      pen->two = ok && dom->Pa <= 2 * cus && 2 * lds <= (size_t)lds_cu && !pen->refined;
       // transposed blocks: the leading block of A~^T is the transpose of a
       // leading block of A~ (split at a mode boundary), kl and ku swap (the
       // reversed trailing block swaps them back).  Here the leading block has
@@ -845,7 +863,15 @@ static int factor_into(stau_pencils* pen, stau_pencils::FactorSlot* set, const P
   const PencilArgs& bt = trans ? pen->ptT : pen->pt;
   const PencilArgs& bb = trans ? pen->pbT : pen->pb;
   HIP_TRY(timed(pen, K_FACTOR, st, [&] {
-    if (!two) return launch_factor(pa, a0, b0, f.Lf, f.sl, f.Uf, pen->sing, st);
+    if (!two) {
+      hipError_t e = launch_factor(pa, a0, b0, f.Lf, f.sl, f.Uf, pen->sing, st);
+      if (e == hipSuccess && f.L32raw) {  // FP32 copies for the refined mixed solve
+        const size_t cols = (size_t)pa.P * pa.nst + 2 * (size_t)factor_slack();
+        e = launch_round_f32(f.Lraw, f.L32raw, cols * pa.FW, st);
+        if (e == hipSuccess) e = launch_round_f32(f.Uraw, f.U32raw, cols * pa.BW, st);
+      }
+      return e;
+    }
     hipError_t e = launch_factor(bt, a0, b0, f.LfT, f.slT, f.UfT, pen->sing, st, f.tLt, f.tPt);
     if (e == hipSuccess) e = launch_factor(bb, a0, b0, f.LfB, f.slB, f.UfB, pen->sing, st, f.tLb, f.tPb);
     if (e == hipSuccess)
@@ -887,7 +913,7 @@ static int factors_for(stau_pencils* pen, double a0, double b0, hipStream_t st,
   if (!set[k].Lraw && !set[k].LTraw) {  // (two-block slots are allocated with the pencils)
     size_t bytes = 0;
     hipError_t e = (trans && pen->twoT) ? alloc_slot2(set[k], pen->ptT, pen->pbT, &bytes)
-                                        : alloc_slot(set[k], pa, &bytes);
+                                        : alloc_slot(set[k], pa, &bytes, !trans && pen->refined);
     if (e != hipSuccess) return fail(STAU_ENOMEM, "factor allocation failed: %s", hipGetErrorString(e));
     pen->ws_bytes += (int64_t)bytes;
   }
@@ -956,16 +982,17 @@ static hipError_t explicit_term(stau_pencils* pen, const void* X, hipStream_t st
                [&] { return launch_ypass(pen->xa, -1, pen->pa.desc.ne, pen->G, pen->H, st, mixed); });
 }
 
-// Pencil solve of the step with the factors fs of (a0, b0), FP64 in either
-// precision mode: the two-block solve where it applies, else the single-block
-// solve.  (FP32 sweeps with an FP64 residual and a correction sweep measured
-// slower than one FP64 sweep at every size here: 1024x256 298 against 121 us,
-// 4096x64 117 against 101 us, 256x256x128 7.7 against 5.8 ms.)
+// Pencil solve of the step with the factors fs of (a0, b0): in mixed domains
+// with the refined solve, FP32 sweeps and one FP64 refinement; otherwise FP64,
+// the two-block solve where it applies, else the single-block solve.
 static hipError_t solve_launch(stau_pencils* pen, const stau_pencils::FactorSlot* fs, double a0,
                                double b0, const double2* B, void* X, hipStream_t st, bool mixed) {
-  (void)a0;
-  (void)b0;
-  (void)mixed;
+  if (mixed && pen->refined && fs->Lf32) {
+    PencilArgs pr = pen->pa;
+    pr.refine_a0 = a0;
+    pr.refine_b0 = b0;
+    return launch_solve_refined(pr, B, fs->Lf32, fs->sl, fs->Uf32, X, st);
+  }
   if (pen->two)
     return launch_solve2(pen->pt, pen->pb, B, fs->LfT, fs->slT, fs->UfT, fs->LfB, fs->slB, fs->UfB,
                          fs->Rinv, fs->E1, fs->E2, X, st);

@@ -40,7 +40,7 @@ def test_struct_layouts_match_header():
     from paper_1905_10388_amd import _lib
 
     # field order and sizes of the C structs (natural alignment, LP64)
-    assert ctypes.sizeof(_lib.DomainDesc) == 4 + 4 + 8 * 3 + 8 * 3 + 4 + 4
+    assert ctypes.sizeof(_lib.DomainDesc) == 4 + 4 + 8 * 3 + 8 * 3 + 4 + 4 + 4 + 4
     assert ctypes.sizeof(_lib.RBParamsC) == 5 * 8 + 8 + 4 * 8
     assert ctypes.sizeof(_lib.StateC) == 8 + 8 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(_lib.InfoC) == 17 * 8

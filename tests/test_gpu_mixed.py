@@ -103,3 +103,56 @@ def test_mixed_matmul_rejects_unsupported_nz():
     with pytest.raises(RuntimeError, match="Nz = 64, 128 or 256"):
         RBSolver(64, 32, 4.0, 1e4, 1.0, precision="mixed", dct="matmul")
     RBSolver(64, 32, 4.0, 1e4, 1.0, precision="fp64", dct="matmul")
+
+
+@pytest.mark.parametrize("cfg,steps,dct", [(C1, 100, "fft"), ((128, 64, 4.0, 1e6, 1.0, 1e-4), 20, "matmul"),
+                                           ((32, 128, 2.0, 1e7, 7.0, 2e-5), 10, "fft")],
+                         ids=["C1-fft", "128x64-bf16", "32x128-fft"])
+def test_refined_solve_trajectory_within_bound(cfg, steps, dct):
+    """Mixed steps whose pencil solve is FP32 sweeps with one FP64 refinement
+    (mixed_solve='refined'), against the FP64 oracle; the FP64 residual makes
+    the solve's own error negligible next to the FP32 transforms'."""
+    Nx, Nz, Lx, Ra, Pr, dt = cfg
+    g = RBSolver(Nx, Nz, Lx, Ra, Pr, precision="mixed", dct=dct, mixed_solve="refined")
+    o = RBOracle(Nx, Nz, Lx, RBParams(Ra, Pr))
+    xi = si.workload_noise((Nx, Nz), 0)
+    Xo = o.initial_state(xi)
+    g.initial_state(torch.from_numpy(o.initial_b_grid(xi)))
+    for _ in range(steps):
+        Xo = o.step(Xo, dt)
+        g.step(dt)
+    errs = field_errors(o, _to_np(g.X), Xo)
+    print("refined mixed per-field error", cfg, {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) < MIXED_BOUND, errs
+
+
+def test_refined_solve_3d_and_rk():
+    """3-D mixed steps and a mixed RK443 step with the refined solve."""
+    Nx, Ny, Nz, Lx, Ly, Ra, Pr, dt = 16, 8, 16, 4.0, 4.0, 1e5, 1.0, 5e-4
+    o = RBOracle(Nx, Nz, Lx, RBParams(Ra, Pr), dim=3, Ny=Ny, Ly=Ly)
+    g = RBSolver(Nx, Nz, Lx, Ra, Pr, dim=3, Ny=Ny, Ly=Ly, precision="mixed", mixed_solve="refined")
+    xi = si.workload_noise((Nx, Ny, Nz), 0)
+    Xo = o.initial_state(xi, amp=1e-2)
+    g.initial_state(torch.from_numpy(o.initial_b_grid(xi, amp=1e-2)))
+    for _ in range(10):
+        Xo = o.step(Xo, dt)
+        g.step(dt)
+    errs = field_errors(o, _to_np(g.X), Xo)
+    assert max(errs.values()) < MIXED_BOUND, errs
+    Xr = o.step_rk(Xo, dt, "RK443")
+    g.set_state(torch.from_numpy(Xo).cuda())
+    g.step_rk(dt, "RK443")
+    errs = field_errors(o, _to_np(g.X), Xr)
+    assert max(errs.values()) < MIXED_BOUND, errs
+
+
+def test_mixed_solve_option_is_checked():
+    from paper_1905_10388_amd import StauError, _lib
+    import ctypes as C
+
+    desc = _lib.DomainDesc(dim=2, precision=_lib.STAU_MIXED, Nx=64, Ny=1, Nz=32, Lx=4.0, Ly=1.0,
+                           dealias=1.5, device=0, dct_method=0, mixed_solve=7)
+    dom = C.c_void_p()
+    lib = _lib.load()
+    with pytest.raises(StauError, match="EINVAL"):
+        _lib.check(lib.stau_create_domain(C.byref(desc), C.byref(dom)))
