@@ -327,6 +327,19 @@ int stau_check(stau_pencils* pen, const void* X, void* stream);
  * (Sec. VII "Integration"); result written to *out (host) after a sync. */
 int stau_kinetic_energy(stau_pencils* pen, const void* X, double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the kinetic-energy
+ * functional of stau_kinetic_energy, with the same kernels and result, that
+ * allocates nothing and does not synchronise.  `out` is a device double
+ * written asynchronously on `stream`.  Every intermediate lives in a
+ * library-owned device array of 64 MiB per GPU (held until the process
+ * ends); domains whose intermediates exceed it (2-D: 2 fields x 3Nz/2 x
+ * (Nx/2 + 1) complex entries, 3-D: 3 fields on the z and y grids) return
+ * STAU_EUNSUPPORTED.  Calls on one GPU share that array: calls that overlap
+ * in time on one GPU (concurrent streams, several host threads) race and
+ * must be ordered by the caller. */
+int stau_kinetic_energy_noalloc(stau_pencils* pen, const void* X, double* out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Discrete adjoint (2-D domains; the three calls below return
  * STAU_EUNSUPPORTED for dim = 3).  The adjoint of a complex coefficient z is

@@ -300,6 +300,15 @@ class RBSolver:
         Xs = self.X if X is None else X
         _lib.check(self.lib.stau_check(self._pen, _ptr(Xs), _stream_ptr()))
 
+    def kinetic_energy_noalloc(self, X=None, out=None):
+        """The kinetic energy into a device float64 tensor of one element,
+        asynchronously, through the entry point that allocates nothing."""
+        t = self._torch
+        Xs = (self.X if X is None else X).contiguous()
+        o = out if out is not None else t.empty(1, dtype=t.float64, device=self.device)
+        _lib.check(self.lib.stau_kinetic_energy_noalloc(self._pen, _ptr(Xs), _ptr(o), _stream_ptr()))
+        return o
+
     def kinetic_energy(self, X=None) -> float:
         Xs = (self.X if X is None else X).contiguous()
         out = C.c_double()

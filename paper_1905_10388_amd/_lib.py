@@ -37,6 +37,7 @@ EXPORTS = (
     "stau_set_kernel_timing", "stau_read_kernel_timing", "stau_adjoint_step",
     "stau_kinetic_energy_adjoint", "stau_initial_state_adjoint", "stau_step_rk", "stau_lbvp", "stau_evp",
     "stau_coeff_to_grid", "stau_grid_to_coeff", "stau_coeff_to_grid_adjoint", "stau_grid_to_coeff_adjoint",
+    "stau_kinetic_energy_noalloc",
 )
 KERNEL_KINDS = ("z_backward", "x_pass", "z_forward_rhs", "pencil_solve", "pencil_factor", "y_pass")
 
@@ -111,6 +112,7 @@ def load(path: str = LIB_PATH):
         "stau_kinetic_energy_adjoint": (i32, [vp, vp, vp, vp]),
         "stau_initial_state_adjoint": (i32, [vp, vp, vp, vp]),
         "stau_read_kernel_timing": (i32, [vp, C.POINTER(dbl), C.POINTER(i64), i32]),
+        "stau_kinetic_energy_noalloc": (i32, [vp, vp, vp, vp]),
         "stau_coeff_to_grid": (i32, [vp, vp, C.c_uint32, dbl, vp, vp]),
         "stau_grid_to_coeff": (i32, [vp, vp, C.c_uint32, dbl, vp, vp]),
         "stau_coeff_to_grid_adjoint": (i32, [vp, vp, C.c_uint32, dbl, vp, vp]),

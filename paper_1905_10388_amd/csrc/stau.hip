@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -38,6 +39,31 @@ int fail(int code, const char* fmt, ...) {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Device scratch of stau_kinetic_energy_noalloc: one array per GPU, held for
+// the life of the process.  Host code never uses the array's name as an
+// address: each device's address comes from hipGetSymbolAddress, taken once
+// per device with that device current (scratch_address).
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+__device__ __align__(256) double2 scratch[kNoAllocBytes / sizeof(double2)];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on device `dev`, which must be the current device.
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(STAU_EINVAL, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(STAU_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return STAU_OK;
+}
 
 // exp(-2 pi i t / n) with t reduced modulo n in integers and the angle formed
 // in long double.
@@ -391,6 +417,11 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
     if (!(d.Ly > 0.0)) return fail(STAU_EINVAL, "Ly must be positive");
   }
   HIP_TRY(hipSetDevice(d.device));
+  {
+    void* sp = nullptr;  // the no-allocation scratch of this device, looked up once
+    const int rc0 = scratch_address(d.device, &sp);
+    if (rc0) return rc0;
+  }
   stau_domain* dom = new (std::nothrow) stau_domain();
   if (!dom) return fail(STAU_ENOMEM, "host allocation failed");
   dom->d = d;
@@ -1475,6 +1506,36 @@ int stau_check(stau_pencils* pen, const void* X, void* stream) {
   HIP_TRY(hipMemcpyAsync(&h, pen->flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (h) return fail(STAU_ENONFINITE, "state holds non-finite values");
+  return STAU_OK;
+}
+
+int stau_kinetic_energy_noalloc(stau_pencils* pen, const void* X, double* out, void* stream) {
+  if (!pen || !X || !out) return fail(STAU_EINVAL, "null argument");
+  const int dev = pen->dom->d.device;
+  HIP_TRY(hipSetDevice(dev));
+  void* sp = nullptr;
+  {
+    const int rc = scratch_address(dev, &sp);
+    if (rc) return rc;
+  }
+  // the same kernels as stau_kinetic_energy, with every intermediate in the
+  // device's scratch array: G [nf][M][P], G2 [nf][M][Ngy][Px] (3-D), rowmean
+  // [M Ngy]; the result goes to the caller's device double.  Every entry is
+  // written before it is read, so nothing needs clearing between calls.
+  const XformArgs& a = pen->xa;
+  const size_t nf = a.dim == 2 ? 2 : 3, R = (size_t)a.M * (a.dim == 3 ? a.Ngy : 1);
+  const size_t bG = nf * a.M * a.P * sizeof(double2);
+  const size_t bG2 = a.dim == 3 ? nf * R * a.Px * sizeof(double2) : 0;
+  const size_t bR = (R * sizeof(double) + 255) / 256 * 256;
+  const size_t need = bG + bG2 + bR;
+  if (need > kNoAllocBytes)
+    return fail(STAU_EUNSUPPORTED, "no-allocation kinetic energy needs %zu bytes of scratch (limit %zu)",
+                need, kNoAllocBytes);
+  char* base = (char*)sp;
+  void* G = base;
+  void* G2 = a.dim == 3 ? base + bG : nullptr;
+  double* rowmean = (double*)(base + bG + bG2);
+  HIP_TRY(launch_ke(a, X, G, G2, rowmean, out, (hipStream_t)stream));
   return STAU_OK;
 }
 
