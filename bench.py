@@ -79,11 +79,11 @@ def dof(w):
     return S * w["Nx"] * w["Ny"] * w["Nz"]
 
 
-def solver(w, precision="fp64", dct="auto", **kw):
+def solver(w, precision="fp64", dct="auto", solve="auto", **kw):
     from paper_1905_10388_amd import RBSolver
 
     return RBSolver(w["Nx"], w["Nz"], w["Lx"], w["Ra"], w["Pr"], dim=w["dim"], Ny=w["Ny"],
-                    Ly=w["Ly"], precision=precision, dct=dct, **kw)
+                    Ly=w["Ly"], precision=precision, dct=dct, mixed_solve=solve, **kw)
 
 
 def algorithmic_bytes(info, dim):
@@ -181,12 +181,12 @@ def field_err(Xa, Xb, dim):
     return out
 
 
-def run(w, precision="fp64", dct="auto", steps=None, warmup=10, timing_steps=10):
+def run(w, precision="fp64", dct="auto", steps=None, warmup=10, timing_steps=10, solve="auto"):
     """Warm-up (with the two factorisations timed), timed steps, a per-kernel
     pass; returns the figures and the state after warm-up + timed steps."""
     import torch
 
-    g = solver(w, precision, dct)
+    g = solver(w, precision, dct, solve)
     g.initial_state(torch.from_numpy(b_grid(w)))
     steps = w["steps"] if steps is None else steps
     g.set_kernel_timing(True)
@@ -468,26 +468,27 @@ def adjoint_mixed(w):
     return {"fp64": r64, "mixed": rmx}
 
 
-def workload_pair(name, w, timing_steps=10, dcts=("auto",)):
+def workload_pair(name, w, timing_steps=10, forms=(("auto", "auto"),)):
     """FP64 and mixed steps of one workload over its configured step count,
     with the mixed state's per-field relative difference to the FP64 state
-    after the same steps."""
+    after the same steps; forms are (z transform, mixed solve) pairs."""
     r64 = run(w, "fp64", timing_steps=timing_steps)
     X64 = r64.pop("X")
     out = {"workload": name, "pencils": r64["info"]["P_active"],
            "unknowns_per_pencil": r64["info"]["n"], "unit": "DOF-updates/s",
            "fp64": _public(r64)}
-    for dct in dcts:
+    for dct, solve in forms:
+        key = f"mixed_{dct}" + ("" if solve == "auto" else f"_{solve}")
         try:
-            rmx = run(w, "mixed", dct, timing_steps=timing_steps)
+            rmx = run(w, "mixed", dct, timing_steps=timing_steps, solve=solve)
         except Exception as e:
-            out[f"mixed_{dct}"] = {"error": str(e)}
+            out[key] = {"error": str(e)}
             continue
         Xmx = rmx.pop("X")
         m = _public(rmx)
         m["diff_vs_fp64_per_field"] = field_err(Xmx, X64, w["dim"])
         m["speedup_vs_fp64"] = rmx["value"] / r64["value"]
-        out[f"mixed_{dct}"] = m
+        out[key] = m
     return out, X64
 
 
@@ -595,24 +596,28 @@ def main():
     if not args.no_mixed:
         # the 3-D workload names split-BF16 matrix-core z transforms for the
         # mixed form; the FP32 FFT form beside it
-        for dct in ("matmul", "fft"):
-            rmx = run(w, "mixed", dct, steps=args.steps, warmup=args.warmup, timing_steps=args.timing_steps)
+        for dct, solve in (("matmul", "auto"), ("fft", "auto"), ("matmul", "refined")):
+            rmx = run(w, "mixed", dct, steps=args.steps, warmup=args.warmup, timing_steps=args.timing_steps,
+                      solve=solve)
             Xmx = rmx.pop("X")
             m = _public(rmx)
             m["dtype"] = "f32+f64"
             m["z_transform"] = "split-BF16 matrix-core products" if dct == "matmul" else "FP32 FFT"
+            m["pencil_solve"] = ("FP32 sweeps + one FP64 refinement" if solve == "refined"
+                                 else "FP64 sweeps")
             m["diff_vs_fp64_per_field"] = field_err(Xmx, X64, 3)
             m["steps_compared"] = r["warmup"] + args.steps
             m["speedup_vs_fp64"] = rmx["value"] / r["value"]
-            out[f"mixed_{dct}"] = m
+            out[f"mixed_{dct}" + ("" if solve == "auto" else f"_{solve}")] = m
     if not args.no_extra:
         extra = {}
-        res, X2 = workload_pair(C2, WORKLOADS[C2], dcts=("auto", "matmul"))
+        res, X2 = workload_pair(C2, WORKLOADS[C2], forms=(("auto", "auto"), ("matmul", "auto"),
+                                                          ("auto", "refined")))
         extra[C2] = res
         extra[C2]["runge_kutta"] = rk_run(WORKLOADS[C2], X2)
         extra[C2]["lbvp_evp"] = lbvp_evp_run(WORKLOADS[C2])
         extra[C2]["ncc"] = ncc_run(WORKLOADS[C2], X2)
-        extra[C5], _ = workload_pair(C5, WORKLOADS[C5], dcts=("auto",))
+        extra[C5], _ = workload_pair(C5, WORKLOADS[C5], forms=(("auto", "auto"), ("auto", "refined")))
         extra[C4] = {"adjoint": adjoint_ratio(WORKLOADS[C4])}
         extra[C5]["adjoint"] = adjoint_mixed(dict(WORKLOADS[C5], adj_steps=200))
         out["workloads"] = extra
