@@ -90,11 +90,12 @@ def algorithmic_bytes(info, dim):
     """Minimum HBM bytes per launch of each kernel (FP64 complex = 16 B): every
     input read once, every output written once.
       z backward: the state fields the explicit term needs (2-D b, u, w, bz,
-        uz, wz; 3-D also v, vz) read, the grid fields (8; 3-D 15) of M points
-        written per pencil slot;
-      y passes (3-D): backward, 15 fields of Ny rows read and Ngy written per
+        uz, wz; 3-D also v, vz) read, their transforms (6; 3-D 12 with the y
+        derivatives of b, u, v, w; x derivatives are formed in the x pass) of
+        M points written per pencil slot;
+      y passes (3-D): backward, 12 fields of Ny rows read and Ngy written per
         (z level, kx); forward, 4 fields of Ngy read and Ny written;
-      x pass: the grid fields read on the active kx, 3 (3-D: 4) written;
+      x pass: the transformed fields read on the active kx, 3 (3-D: 4) written;
       z forward + RHS: the explicit term read, the previous state's evolved
         rows and the old history read, the new history (two arrays) and the
         right-hand side written;
@@ -104,7 +105,7 @@ def algorithmic_bytes(info, dim):
     n, kl, ku = info["n"], info["kl"], info["ku"]
     Px, Ny, Ngy = info["Px"], info["Ny"], info["Ngy"]
     c16 = 16
-    nin, nf = (6, 8) if dim == 2 else (8, 15)
+    nin, nf = (6, 6) if dim == 2 else (8, 12)
     zb = nin * P * N * c16 + nf * M * P * c16
     if dim == 2:
         xp = nf * M * (Px - 1) * c16 + ne * M * Px * c16

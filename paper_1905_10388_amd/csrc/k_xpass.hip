@@ -22,6 +22,39 @@ namespace stau {
 // N_b and N_u from the pairs (u, w), (b_x, b_z), (u_x, u_z), blockIdx.y = 1
 // forms N_w from (u, w), (w_x, w_z).
 // ---------------------------------------------------------------------------
+// The grid fields of pair k as (source field of G, x-derivative flag) for
+// its real and imaginary parts.  G holds the z (and y) transforms of the
+// state fields without their x derivatives (2-D: u, w, b, bz, uz, wz; 3-D: u,
+// v, w, b, b_y, bz, u_y, uz, v_y, vz, w_y, wz): q_x is i kx times q's row,
+// formed here, since the x derivative commutes with the z and y transforms.
+//   2-D pairs: (u, w), (b_x, bz), (u_x, uz), (w_x, wz)
+//   3-D pairs: (u, v), (w, b_x), (b_y, bz), (u_x, u_y), (uz, v_x), (v_y, vz),
+//              (w_x, w_y), (wz, -)
+template <int DIM>
+__device__ __forceinline__ void pair_src(int k, int& fa, int& da, int& fb, int& db) {
+  if constexpr (DIM == 2) {
+    constexpr int A[4] = {0, 2, 0, 1}, DA[4] = {0, 1, 1, 1}, B[4] = {1, 3, 4, 5};
+    fa = A[k];
+    da = DA[k];
+    fb = B[k];
+    db = 0;
+  } else {
+    constexpr int A[8] = {0, 2, 4, 0, 7, 8, 2, 11}, DA[8] = {0, 0, 0, 1, 0, 0, 1, 0};
+    constexpr int B[8] = {1, 3, 5, 6, 1, 9, 10, -1}, DB[8] = {0, 1, 0, 0, 1, 0, 0, 0};
+    fa = A[k];
+    da = DA[k];
+    fb = B[k];
+    db = DB[k];
+  }
+}
+
+// i kx c for the half-spectrum entry kk of a row (kx = 2 pi kk / Lx)
+template <typename T>
+__device__ __forceinline__ cpx<T> ikx(const XformArgs& a, int kk, cpx<T> c) {
+  const T k = (T)(a.two_pi_over_Lx * (double)kk);
+  return mk<T>(-k * c.y, k * c.x);
+}
+
 template <int DIM, int NT, int PTS, int MAXBF, bool TWL, typename T, bool SPLIT = false>
 __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
                                                   const typename V2<T>::type* __restrict__ G,
@@ -43,16 +76,10 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
   }
   const cT* tw = TWL ? (const cT*)twl : twg;
 
-  // pair k: fields (fa, fb); fb < 0 means zero
-  auto pair_fields = [](int k, int& fa, int& fb) {
-    fa = 2 * k;
-    fb = 2 * k + 1;
-    if (DIM == 3 && k == 7) fb = -1;
-  };
   cT sa[KPT], sb[KPT];
   auto fetch = [&](int k) {
-    int fa, fb;
-    pair_fields(k, fa, fb);
+    int fa, da, fb, db;
+    pair_src<DIM>(k, fa, da, fb, db);
     const S2* A = G + ((size_t)fa * R + r) * Px;
     const S2* B = G + ((size_t)(fb < 0 ? fa : fb) * R + r) * Px;
 #pragma unroll
@@ -62,7 +89,11 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
       sb[q] = mk<T>(0, 0);
       if (kk < Pa) {
         sa[q] = ldv<T>(A + kk);
-        if (fb >= 0) sb[q] = ldv<T>(B + kk);
+        if (da) sa[q] = ikx<T>(a, kk, sa[q]);
+        if (fb >= 0) {
+          sb[q] = ldv<T>(B + kk);
+          if (db) sb[q] = ikx<T>(a, kk, sb[q]);
+        }
       }
     }
   };
@@ -202,13 +233,16 @@ __global__ void __launch_bounds__(NT) xrow2_kernel(XformArgs a,
       sb[slot][q] = mk<T>(0, 0);
     }
     if (k < 0) return;
-    const S2* A = G + ((size_t)(2 * k) * R + r) * Px;
-    const S2* B = G + ((size_t)(2 * k + 1) * R + r) * Px;
+    int fa, da, fb, db;
+    pair_src<2>(k, fa, da, fb, db);
+    const S2* A = G + ((size_t)fa * R + r) * Px;
+    const S2* B = G + ((size_t)fb * R + r) * Px;
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
       const int kk = tid + q * NT;
       if (kk < Pa) {
         sa[slot][q] = ldv<T>(A + kk);
+        if (da) sa[slot][q] = ikx<T>(a, kk, sa[slot][q]);
         sb[slot][q] = ldv<T>(B + kk);
       }
     }

@@ -176,7 +176,8 @@ struct stau_pencils {
   PencilArgs pa{};
   XformArgs xa{};   // dealiased transforms
   XformArgs xa1{};  // scale-1 transforms
-  FieldList fl{};
+  FieldList fl{};      // the explicit term's fields of the step
+  FieldList fl_adj{};  // the adjoint x pass's fields (2-D)
   AccList acc{};
   int64_t n = 0;
   // workspaces
@@ -772,22 +773,35 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   pen->xa1.Ngy = d.dim == 3 ? (int)d.Ny : 1;
   pen->xa1.twy = dom->twy1;
 
+  // explicit-term fields through the z (and y) transforms; their x
+  // derivatives are formed in the x pass (i kx times the row)
   FieldList& fl = pen->fl;
-  if (d.dim == 2) {  // u, w, b_x, b_z, u_x, u_z, w_x, w_z
-    const int fv[8] = {2, 3, 1, 4, 2, 5, 3, 6};
-    const int fd[8] = {0, 0, 1, 0, 1, 0, 1, 0};
-    fl.nf = 8;
-    for (int i = 0; i < 8; ++i) {
+  if (d.dim == 2) {  // u, w, b, bz, uz, wz
+    const int fv[6] = {2, 3, 1, 4, 5, 6};
+    fl.nf = 6;
+    for (int i = 0; i < 6; ++i) {
+      fl.var[i] = fv[i];
+      fl.deriv[i] = 0;
+    }
+  } else {  // u, v, w, b, b_y, bz, u_y, uz, v_y, vz, w_y, wz (ABI order p,b,u,v,w,bz,uz,vz,wz)
+    const int fv[12] = {2, 3, 4, 1, 1, 5, 2, 6, 3, 7, 4, 8};
+    const int fd[12] = {0, 0, 0, 0, 2, 0, 2, 0, 2, 0, 2, 0};
+    fl.nf = 12;
+    for (int i = 0; i < 12; ++i) {
       fl.var[i] = fv[i];
       fl.deriv[i] = fd[i];
     }
-  } else {  // u, v, w, then q_x, q_y, q_z for q = b, u, v, w (ABI order p,b,u,v,w,bz,uz,vz,wz)
-    const int fv[15] = {2, 3, 4, 1, 1, 5, 2, 2, 6, 3, 3, 7, 4, 4, 8};
-    const int fd[15] = {0, 0, 0, 1, 2, 0, 1, 2, 0, 1, 2, 0, 1, 2, 0};
-    fl.nf = 15;
-    for (int i = 0; i < 15; ++i) {
-      fl.var[i] = fv[i];
-      fl.deriv[i] = fd[i];
+  }
+  // the adjoint x pass recomputes the eight 2-D grid fields with their x
+  // derivatives transformed: u, w, b_x, b_z, u_x, u_z, w_x, w_z
+  FieldList& fa = pen->fl_adj;
+  {
+    const int fv[8] = {2, 3, 1, 4, 2, 5, 3, 6};
+    const int fd[8] = {0, 0, 1, 0, 1, 0, 1, 0};
+    fa.nf = 8;
+    for (int i = 0; i < 8; ++i) {
+      fa.var[i] = fv[i];
+      fa.deriv[i] = fd[i];
     }
   }
   {
@@ -809,7 +823,7 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   }
 
   const size_t P = dom->P, M = dom->Ngz, ne = pa.desc.ne, n = pen->n;
-  const size_t szG = (size_t)fl.nf * M * P * sizeof(double2);
+  const size_t szG = (size_t)(fl.nf > pen->fl_adj.nf ? fl.nf : pen->fl_adj.nf) * M * P * sizeof(double2);
   const size_t szH = ne * M * P * sizeof(double2);
   const size_t szB = P * ne * N * sizeof(double2);
   const size_t Ngy = (size_t)dom->Ngy, Px = (size_t)dom->Px;
@@ -1439,7 +1453,7 @@ int stau_adjoint_step(stau_pencils* pen, const void* X_prev, int64_t iteration, 
   }
   HIP_TRY(hipEventRecord(pen->ev_fork, st));
   HIP_TRY(hipStreamWaitEvent(pen->side, pen->ev_fork, 0));
-  HIP_TRY(launch_zb(pen->xa, pen->fl, X_prev, pen->G, pen->side, mixed));
+  HIP_TRY(launch_zb(pen->xa, pen->fl_adj, X_prev, pen->G, pen->side, mixed));
   HIP_TRY(hipEventRecord(pen->ev_join, pen->side));
   // 1. transposed pencil solve + multistep history adjoints
   if (pen->twoT)
