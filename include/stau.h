@@ -105,9 +105,10 @@ typedef struct stau_pencils stau_pencils;
  *          FP64 domains): STAU_SOLVE_FP64 (FP64 sweeps on the FP64 factors),
  *          STAU_SOLVE_REFINED (FP32 sweeps on FP32 copies of the FP64
  *          factors, the residual of the first solution in FP64 from the
- *          operator templates, one FP32 correction sweep, the sum in FP64;
- *          single-block sweep layout), STAU_SOLVE_AUTO (FP64, the faster of
- *          the two at every size measured).  Else STAU_EINVAL.
+ *          operator templates, one FP32 correction sweep, the sum in FP64; in
+ *          the single-block or the two-block sweep layout, as the FP64 solve
+ *          uses), STAU_SOLVE_AUTO (FP64, the faster of the two at every size
+ *          measured).  Else STAU_EINVAL.
  * reserved must be 0. */
 typedef struct stau_domain_desc {
   int32_t dim;

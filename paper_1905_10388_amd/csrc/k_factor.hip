@@ -30,24 +30,16 @@ namespace stau {
 // j+1..j+kv applies the rank-1 update to its rows.  Then the rows move up by
 // one and each lane appends row j+kl+1 of its column from the operator
 // templates; the lane of column j moves on to column j+64, whose rows
-// j+1..j+kl lie outside the band (kl + ku <= 63).  Row j of U goes to an LDS
+// j+1..j+kl lie outside the band (kl + ku <= 63).  Entries come from band
+// templates of the operator (host-built, one row per step and lane: six
+// loads issued a step ahead and one combination with the pencil's a0, b0,
+// k^2, kx, ky and lin).  Row j of U goes to an LDS
 // staging area (kv + 1 entries per column, entry k = c - r) and column j's
 // BW-lane solve record is written when it completes (step j).  The
 // multipliers go straight to their forward-window slots.  With a.trans the
 // transposed matrix is factored (kl and ku of `a` are then those of the
 // transpose), for the adjoint's transposed solves.
 // ---------------------------------------------------------------------------
-// Entry (r, c) of the factored operator (A~ or A~^T) in the coordinates of
-// the block a.blk (reversed order for the trailing block).
-__device__ __forceinline__ double block_entry(const PencilArgs& a, const PencilCoef& pc, int r, int c) {
-  int R = r, C = c;
-  if (a.blk == 2) {
-    R = a.nfull - 1 - r;
-    C = a.nfull - 1 - c;
-  }
-  return a.trans ? sys_entry(a.desc, pc, C, R) : sys_entry(a.desc, pc, R, C);
-}
-
 // With tailL (two-block solve), the last Q columns' pivot offsets (tailP) and
 // multipliers (tailL, kl per column) are also written in elimination order.
 template <int FW>
@@ -67,9 +59,40 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
   double* Lp = Lf + (size_t)p * a.nst * FW;
   double* Up = Uf + (size_t)p * a.nst * BW;
   uint8_t* sp = sl + (size_t)p * a.nst;
+  // entry (r, c) of the block's operator from the band templates of the whole
+  // operator (row R, column C of A~; of A~^T with a.trans)
+  const double k2 = pc.kx * pc.kx + pc.ky * pc.ky;
+  const size_t ps = (size_t)a.tplane;
+  const double* tp1 = a.tpl + (pc.mean ? 2 : 1) * ps;
+  auto tpl_at = [&](int r, int c, double* t) -> bool {
+    if (r >= n || c >= n || c - r > ku || r - c > kl) return false;
+    int R = r, C = c;
+    if (a.blk == 2) {
+      R = a.nfull - 1 - r;
+      C = a.nfull - 1 - c;
+    }
+    if (a.trans) {
+      const int q = R;
+      R = C;
+      C = q;
+    }
+    const size_t o = (size_t)R * a.tw + (C - R + a.tkl);
+    t[0] = a.tpl[o];
+    t[1] = tp1[o];
+    t[2] = a.tpl[3 * ps + o];
+    t[3] = a.tpl[4 * ps + o];
+    t[4] = a.tpl[5 * ps + o];
+    t[5] = a.tpl[6 * ps + o];
+    return true;
+  };
+  auto combine = [&](bool in, const double* t) -> double {
+    if (!in) return 0.0;
+    return a0 * t[0] + b0 * (t[1] + k2 * t[2] + pc.kx * t[3] + pc.ky * t[4] + pc.lin * t[5]);
+  };
   auto entry = [&](int r, int c) -> double {
-    if (r >= n || c >= n || c - r > ku || r - c > kl) return 0.0;
-    return block_entry(a, pc, r, c);
+    double t[6];
+    const bool in = tpl_at(r, c, t);
+    return combine(in, t);
   };
   int c = lane;  // this lane's column
   double av[FW];
@@ -79,6 +102,11 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
   for (int j = 0; j < n; ++j) {
     const int pl = j & (kWave - 1);
     const int hi = min(n - 1, j + kl) - j;  // rows j..j+hi exist
+    // template entries of row j+1+kl for the end of this step (the lane of
+    // column j then holds column j+64), loaded now so that they arrive while
+    // the step runs
+    double tn[6];
+    const bool tin = tpl_at(j + 1 + kl, lane == pl ? c + kWave : c, tn);
     // pivot search (used from lane pl): first index of the largest |a|
     double mag = fabs(av[0]);
     int idx = 0;
@@ -163,7 +191,7 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     // rows j+1..j+1+kl for the next step
     const bool fresh = lane == pl;
     if (fresh) c += kWave;
-    const double nv = entry(j + 1 + kl, c);
+    const double nv = combine(tin, tn);
 #pragma unroll
     for (int i = 0; i < FW; ++i) {
       double v = (i + 1 < FW && !fresh) ? av[i + 1] : 0.0;

@@ -1028,6 +1028,169 @@ __global__ void __launch_bounds__(4 * kWave) solve2_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two-block refined mixed-precision solve: the two-block solve of
+// solve2_kernel with FP32 sweeps on FP32 copies of the block factors (the
+// interface system and the corrections in FP64 from the FP64 coupling data),
+// then the FP64 residual r = b - A x^ of the whole system from the operator
+// templates, a second FP32 two-block pass on r, and X = P^R (x^ + d) summed in
+// FP64.  LDS: the interface unknowns and coupling data (double), the four
+// FP32 block vectors, x^ in whole-system order ([2][n] FP32) and the FP32
+// staging units.
+// ---------------------------------------------------------------------------
+template <int FWT, int BWT, int FWB, int BWB>
+__global__ void __launch_bounds__(4 * kWave) solve2_refined_kernel(
+    PencilArgs t, PencilArgs bt, int plaunch, const double2* __restrict__ Bev,
+    const float* __restrict__ Lft, const uint8_t* __restrict__ slt, const float* __restrict__ Uft,
+    const float* __restrict__ Lfb, const uint8_t* __restrict__ slb, const float* __restrict__ Ufb,
+    const double* __restrict__ Rinv, const double* __restrict__ E1, const double* __restrict__ E2,
+    double2* __restrict__ X) {
+  extern __shared__ double lds[];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int part = wv & 1, half = wv >> 1;
+  const SysDesc& d = t.desc;
+  const int N = d.N, S = d.S, ne = d.ne, kb = d.kb;
+  const int n = t.nfull, m = t.n, nb = bt.n, kl = t.kl, ku = t.ku, Q = t.Q, K = kl + ku;
+  if (blockIdx.x == 0 && plaunch < t.P) zero_pencils(X, plaunch, t.P, S * N, tid, 4 * kWave);
+  double2* Xp = X + (size_t)p * S * N;
+  if (!pencil_active(t, p)) {
+    zero_pencils(X, p, p + 1, S * N, tid, 4 * kWave);
+    return;
+  }
+  const PencilCoef pc = pencil_coef(t, p, 0.0, 0.0);
+  const PencilCoef pa = pencil_coef(t, p, t.refine_a0, t.refine_b0);
+  const int spanT = BWT + t.nst + FWT, spanB = BWB + bt.nst + FWB;
+  double* z = lds;         // [2][64] interface unknowns
+  double* cR = z + 2 * 64;  // Rinv [K][K], E1 [Q][ku], E2 [Q][kl]
+  double* cE1 = cR + K * K;
+  double* cE2 = cE1 + Q * ku;
+  float* fb = (float*)(cR + solve2_coupling_doubles(K, Q));
+  float* vt0 = fb + BWT;
+  float* vt1 = vt0 + spanT;
+  float* vb0 = fb + 2 * spanT + BWB;
+  float* vb1 = vb0 + spanB;
+  float* xh = fb + 2 * spanT + 2 * spanB;  // [2][n]
+  constexpr int SB = stage_bytes<float, (FWT > FWB ? FWT : FWB), (BWT > BWB ? BWT : BWB), kSU2>() / 4;
+  float* stg = xh + (2 * n + 3) / 4 * 4 + (size_t)wv * SB;
+  float* v = half == 0 ? (part == 0 ? vt0 : vt1) : (part == 0 ? vb0 : vb1);
+  {
+    const int nR = K * K, nE1 = Q * ku, nE2 = Q * kl;
+    for (int i = tid; i < nR + nE1 + nE2; i += 4 * kWave)
+      cR[i] = i < nR ? Rinv[(size_t)p * nR + i]
+                     : (i < nR + nE1 ? E1[(size_t)p * nE1 + i - nR] : E2[(size_t)p * nE2 + i - nR - nE1]);
+  }
+  const double2* Bp = Bev + (size_t)p * ne * N;
+  {
+    // right-hand side (FP32): zero fill with the boundary values, then the
+    // evolved entries (whole row R: leading block R, trailing block n - 1 - R)
+    const int BWx = half == 0 ? BWT : BWB, FWx = half == 0 ? FWT : FWB;
+    const int npad = half == 0 ? t.nst : bt.nst;
+    for (int r = lane - BWx; r < npad + FWx; r += kWave) {
+      double val = 0.0;
+      if (half == 0 && part == 0 && r >= 0 && r < kb && pc.mean && d.bc_var[r] == VB)
+        val = d.bc_side[r] == 0 ? t.b_bottom : t.b_top;
+      v[r] = (float)val;
+    }
+    const int Nm = N - 1;
+    for (int i = lane; i < ne * Nm; i += kWave) {
+      const int e = i / Nm, mo = i - e * Nm;
+      const int eq = e == 0 ? EB : (e == ne - 1 ? EW : (e == 1 ? EU : EV));
+      const int Rw = kb + mo * S + d.eq_pos[eq];
+      if ((half == 0) != (Rw < m)) continue;
+      const double2 b2 = Bp[e * N + mo];
+      const bool scaled = eq == EU || eq == EV;
+      v[half == 0 ? Rw : n - 1 - Rw] = (float)(part == 0 ? (scaled ? -b2.y : b2.x) : (scaled ? b2.x : b2.y));
+    }
+  }
+  const int psel = p >= (int)(gridDim.x / 2) ? 1 : 0;
+  auto pass = [&]() {
+    if (half == 0)
+      sweep_forward_staged<float, FWT, kSU2>(v, Lft + (size_t)p * t.nst * FWT,
+                                             (const uint32_t*)(slt + (size_t)p * t.nst), t.nst / kCH,
+                                             lane, stg, psel);
+    else
+      sweep_forward_staged<float, FWB, kSU2>(v, Lfb + (size_t)p * bt.nst * FWB,
+                                             (const uint32_t*)(slb + (size_t)p * bt.nst), bt.nst / kCH,
+                                             lane, stg, psel);
+    __builtin_amdgcn_s_setprio(0);
+    __syncthreads();
+    if (half == 0 && lane < K) {
+      const double* Rp = cR + lane * K;
+      const float* g1 = part == 0 ? vt0 : vt1;
+      const float* g2 = part == 0 ? vb0 : vb1;
+      double acc = 0.0;
+      for (int k = 0; k < K; ++k)
+        acc = fma(Rp[k], (double)(k < kl ? g1[m - kl + k] : g2[nb - ku + (k - kl)]), acc);
+      z[part * 64 + lane] = acc;
+    }
+    __syncthreads();
+    if (lane < Q) {
+      double acc = 0.0;
+      if (half == 0) {
+        const double* Ep = cE1 + lane * ku;
+        for (int k = 0; k < ku; ++k) acc = fma(Ep[k], z[part * 64 + kl + ku - 1 - k], acc);
+        v[m - Q + lane] = (float)((double)v[m - Q + lane] - acc);
+      } else {
+        const double* Ep = cE2 + lane * kl;
+        for (int k = 0; k < kl; ++k) acc = fma(Ep[k], z[part * 64 + k], acc);
+        v[nb - Q + lane] = (float)((double)v[nb - Q + lane] - acc);
+      }
+    }
+    if (half == 0)
+      sweep_backward_staged<float, BWT, kSU2>(v, Uft + (size_t)p * t.nst * BWT, t.nst / kCH, lane, stg);
+    else
+      sweep_backward_staged<float, BWB, kSU2>(v, Ufb + (size_t)p * bt.nst * BWB, bt.nst / kCH, lane, stg);
+    __syncthreads();
+  };
+  pass();
+  // x^ in whole-system order
+  for (int c = tid; c < n; c += 4 * kWave) {
+    xh[c] = c < m ? vt0[c] : vb0[n - 1 - c];
+    xh[n + c] = c < m ? vt1[c] : vb1[n - 1 - c];
+  }
+  __syncthreads();
+  // FP64 residual of x^ into the block vectors (padding zero)
+  for (int i = tid; i < 2 * (spanT + spanB); i += 4 * kWave) {
+    const int q = i < 2 * spanT ? (i < spanT ? 0 : 1) : ((i - 2 * spanT) < spanB ? 0 : 1);
+    const bool lead = i < 2 * spanT;
+    const int pos = lead ? (i - q * spanT) - BWT : (i - 2 * spanT - q * spanB) - BWB;
+    const int loc = lead ? m : nb;
+    float val = 0.0f;
+    if (pos >= 0 && pos < loc) {
+      const int R = lead ? pos : n - 1 - pos;
+      const float* x = xh + (size_t)q * n;
+      const double ax = apply_row(d, pa, R, [&](int mo, int var) { return (double)x[mo * S + d.var_pos[var]]; });
+      val = (float)(rhs_entry(t, pc, Bp, q, R) - ax);
+    }
+    (lead ? fb : fb + 2 * spanT)[i - (lead ? 0 : 2 * spanT)] = val;
+  }
+  __syncthreads();
+  pass();
+  // X = P^R (x^ + d), real scaling undone
+  for (int i = tid; i < S * N; i += 4 * kWave) {
+    const int vabi = i / N, mo = i - vabi * N;
+    const int var = t.var_of_abi[vabi];
+    const int pos = d.var_pos[var];
+    auto xt = [&](int pp, int c) -> double {
+      const double dd = c < m ? (pp == 0 ? vt0 : vt1)[c] : (pp == 0 ? vb0 : vb1)[n - 1 - c];
+      return (double)xh[(size_t)pp * n + c] + dd;
+    };
+    const int c0 = mo * S + pos;
+    double xr = xt(0, c0), xi = xt(1, c0);
+    if (mo + 2 < N) {
+      xr -= xt(0, c0 + 2 * S);
+      xi -= xt(1, c0 + 2 * S);
+    }
+    if (var == VU || var == VUZ || var == VV || var == VVZ)
+      Xp[i] = make_double2(xi, -xr);  // u = -i u~
+    else
+      Xp[i] = make_double2(xr, xi);
+  }
+}
+
 // STAGED: both sweeps staged in su3-column units.  Blocks cover pencils
 // [0, plaunch); block 0 also zeroes the outputs of the inactive pencils
 // [plaunch, P) (in 2-D the Nyquist pencil), so that a launch of plaunch <= #CU
@@ -1270,6 +1433,38 @@ hipError_t launch_solve2(const PencilArgs& t, const PencilArgs& bt, const void* 
                                                   E2, X, none, st);
   STAU_SOLVE2_VARIANTS(STAU_CASE2)
 #undef STAU_CASE2
+  return hipErrorInvalidValue;
+}
+
+template <int FWT, int BWT, int FWB, int BWB>
+static hipError_t launch_solve2_refined_t(const PencilArgs& t, const PencilArgs& bt, const void* Bev,
+                                          const float* Lft, const uint8_t* slt, const float* Uft,
+                                          const float* Lfb, const uint8_t* slb, const float* Ufb,
+                                          const double* Rinv, const double* E1, const double* E2,
+                                          void* X, hipStream_t st) {
+  const int plaunch = t.Px - 1;
+  constexpr int SB = stage_bytes<float, (FWT > FWB ? FWT : FWB), (BWT > BWB ? BWT : BWB), kSU2>();
+  const int K = t.kl + t.ku;
+  const size_t floats = (size_t)2 * (BWT + t.nst + FWT) + 2 * (BWB + bt.nst + FWB);
+  const size_t lds = (size_t)(2 * 64 + solve2_coupling_doubles(K, t.Q)) * sizeof(double) +
+                     (floats + (size_t)(2 * t.nfull + 3) / 4 * 4) * sizeof(float) + (size_t)4 * SB;
+  auto fn = solve2_refined_kernel<FWT, BWT, FWB, BWB>;
+  allow_lds((const void*)fn, lds);
+  hipLaunchKernelGGL(fn, dim3(plaunch), dim3(4 * kWave), lds, st, t, bt, plaunch, (const double2*)Bev, Lft,
+                     slt, Uft, Lfb, slb, Ufb, Rinv, E1, E2, (double2*)X);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve2_refined(const PencilArgs& t, const PencilArgs& bt, const void* Bev,
+                                 const float* Lft, const uint8_t* slt, const float* Uft,
+                                 const float* Lfb, const uint8_t* slb, const float* Ufb,
+                                 const double* Rinv, const double* E1, const double* E2, void* X,
+                                 hipStream_t st) {
+  if (t.trans || t.desc.dim != 2) return hipErrorInvalidValue;
+  if (t.FW == 8 && t.BW == 32 && bt.FW == 32 && bt.BW == 32)
+    return launch_solve2_refined_t<8, 32, 32, 32>(t, bt, Bev, Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, E2, X, st);
+  if (t.FW == 16 && t.BW == 32 && bt.FW == 32 && bt.BW == 32)
+    return launch_solve2_refined_t<16, 32, 32, 32>(t, bt, Bev, Lft, slt, Uft, Lfb, slb, Ufb, Rinv, E1, E2, X, st);
   return hipErrorInvalidValue;
 }
 

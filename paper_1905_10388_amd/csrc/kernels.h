@@ -25,6 +25,13 @@ struct PencilArgs {
   double kappa, nu, buoyancy, b_bottom, b_top;
   double lin;  // PencilCoef::lin of every pencil (0 for the step's operators)
   double refine_a0, refine_b0;  // operator of the refined mixed solve's residual
+  // Band templates of the whole operator (row R, column C at R * tw + C - R + tkl):
+  // a0 M~ + b0 L~ = a0 T0 + b0 (T1 + k^2 T2 + kx T3 + ky T4 + lin T5), with
+  // T1 of the mean pencil (gauge row) in its own plane: planes T0, T1, T1 mean,
+  // T2, T3, T4, T5, each tplane doubles
+  const double* tpl;
+  int tkl, tw;
+  long long tplane;
   int nncc;    // non-constant coefficient Gamma(z): Chebyshev terms (0: none)
   double ncc[kMaxNcc];
   double two_pi_over_Lx, two_pi_over_Ly;
@@ -117,6 +124,13 @@ hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, 
 hipError_t launch_solve_refined(const PencilArgs& a, const void* Bev, const float* Lf, const uint8_t* sl,
                                 const float* Uf, void* X, hipStream_t st);
 hipError_t launch_round_f32(const double* src, float* dst, size_t count, hipStream_t st);
+// The same for the two-block layout: FP32 copies of both blocks' factors, the
+// FP64 coupling data; t.refine_a0 / refine_b0 name the operator (2-D)
+hipError_t launch_solve2_refined(const PencilArgs& t, const PencilArgs& bt, const void* Bev,
+                                 const float* Lft, const uint8_t* slt, const float* Uft,
+                                 const float* Lfb, const uint8_t* slb, const float* Ufb,
+                                 const double* Rinv, const double* E1, const double* E2, void* X,
+                                 hipStream_t st);
 
 // transforms along y and the 3-D x pass
 // ys: output scale in place of the default (0: 1 backward, 1 / Ngy forward)

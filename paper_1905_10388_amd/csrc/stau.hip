@@ -207,8 +207,11 @@ struct stau_pencils {
     uint8_t *slT = nullptr, *slB = nullptr;
     double *tLt = nullptr, *tLb = nullptr, *Rinv = nullptr, *E1 = nullptr, *E2 = nullptr;
     uint8_t *tPt = nullptr, *tPb = nullptr;
-    // refined mixed solve: FP32 copies of Lf / Uf (with the same slack)
+    // refined mixed solve: FP32 copies of Lf / Uf (with the same slack), and
+    // of both blocks' factors in the two-block layout
     float *L32raw = nullptr, *U32raw = nullptr, *Lf32 = nullptr, *Uf32 = nullptr;
+    float *LT32raw = nullptr, *UT32raw = nullptr, *LB32raw = nullptr, *UB32raw = nullptr;
+    float *LfT32 = nullptr, *UfT32 = nullptr, *LfB32 = nullptr, *UfB32 = nullptr;
     bool valid = false;
     double a0 = 0.0, b0 = 0.0;
     int64_t stamp = 0;
@@ -236,6 +239,7 @@ struct stau_pencils {
   // steps evicted them since)
   bool has_last = false;
   double last_a0 = 0.0, last_b0 = 0.0;
+  double* tpl = nullptr;   // device: band templates of the operator (PencilArgs::tpl)
   int* sing = nullptr;     // device: first singular pencil (INT_MAX if none)
   int* flag = nullptr;     // device: non-finite flag
   double* scratch = nullptr;
@@ -544,10 +548,12 @@ static void free_pencils(stau_pencils* p) {
       hipFree(f.Uraw);
       for (void* q : {(void*)f.LTraw, (void*)f.UTraw, (void*)f.LBraw, (void*)f.UBraw, (void*)f.sTraw,
                       (void*)f.sBraw, (void*)f.tLt, (void*)f.tLb, (void*)f.Rinv, (void*)f.E1,
-                      (void*)f.E2, (void*)f.tPt, (void*)f.tPb, (void*)f.L32raw, (void*)f.U32raw})
+                      (void*)f.E2, (void*)f.tPt, (void*)f.tPb, (void*)f.L32raw, (void*)f.U32raw,
+                      (void*)f.LT32raw, (void*)f.UT32raw, (void*)f.LB32raw, (void*)f.UB32raw})
         (void)hipFree(q);
       f = stau_pencils::FactorSlot{};
     }
+  hipFree(p->tpl);
   hipFree(p->sing);
   hipFree(p->flag);
   hipFree(p->scratch);
@@ -586,7 +592,7 @@ static hipError_t alloc_slot(stau_pencils::FactorSlot& f, const PencilArgs& pa, 
 // Allocate (zeroed) two-block factor storage: both blocks' factors (with
 // slack), their last-Q steps and the coupling data.
 static hipError_t alloc_slot2(stau_pencils::FactorSlot& f, const PencilArgs& pt, const PencilArgs& pb,
-                              size_t* bytes) {
+                              size_t* bytes, bool fp32 = false) {
   const size_t sk = (size_t)factor_slack();
   const size_t P = (size_t)pt.P, Q = (size_t)pt.Q, K = (size_t)(pt.kl + pt.ku);
   const size_t cT = P * pt.nst + 2 * sk, cB = P * pb.nst + 2 * sk;
@@ -609,7 +615,19 @@ static hipError_t alloc_slot2(stau_pencils::FactorSlot& f, const PencilArgs& pt,
   get((void**)&f.Rinv, P * K * K * sizeof(double));
   get((void**)&f.E1, P * Q * pt.ku * sizeof(double));
   get((void**)&f.E2, P * Q * pt.kl * sizeof(double));
+  if (fp32) {
+    get((void**)&f.LT32raw, cT * pt.FW * sizeof(float));
+    get((void**)&f.UT32raw, cT * pt.BW * sizeof(float));
+    get((void**)&f.LB32raw, cB * pb.FW * sizeof(float));
+    get((void**)&f.UB32raw, cB * pb.BW * sizeof(float));
+  }
   if (e != hipSuccess) return e;
+  if (fp32) {
+    f.LfT32 = f.LT32raw + sk * pt.FW;
+    f.UfT32 = f.UT32raw + sk * pt.BW;
+    f.LfB32 = f.LB32raw + sk * pb.FW;
+    f.UfB32 = f.UB32raw + sk * pb.BW;
+  }
   f.LfT = f.LTraw + sk * pt.FW;
   f.UfT = f.UTraw + sk * pt.BW;
   f.slT = f.sTraw + sk;
@@ -664,6 +682,46 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   pa.b_top = par->b_top;
   pa.two_pi_over_Lx = 2.0 * M_PI / d.Lx;
   pa.two_pi_over_Ly = d.dim == 3 ? 2.0 * M_PI / d.Ly : 0.0;
+  {
+    // band templates of the operator: entries of a0 M~ + b0 L~ separated by
+    // their pencil-dependent factors (exact differences of template entries)
+    const int n = pa.n, kl = pa.kl, tw = pa.kl + pa.ku + 1;
+    const size_t plane = (size_t)n * tw;
+    std::vector<double> T(7 * plane, 0.0);
+    auto coef = [&](double a0, double b0, double kx, double ky, int mean, double lin, int ncc) {
+      PencilCoef pc{a0, b0, pa.kappa, pa.nu, pa.buoyancy, kx, ky, mean, lin, ncc ? pa.nncc : 0, {}};
+      for (int k = 0; k < kMaxNcc; ++k) pc.ncc[k] = pa.ncc[k];
+      return pc;
+    };
+    const PencilCoef cM = coef(1, 0, 0, 0, 0, 0, 0), c1 = coef(0, 1, 0, 0, 0, 0, 1),
+                     c1m = coef(0, 1, 0, 0, 1, 0, 1), cxp = coef(0, 1, 1, 0, 0, 0, 1),
+                     cxm = coef(0, 1, -1, 0, 0, 0, 1), cyp = coef(0, 1, 0, 1, 0, 0, 1),
+                     cym = coef(0, 1, 0, -1, 0, 0, 1), cl1 = coef(0, 1, 0, 0, 0, 1, 0),
+                     cl0 = coef(0, 1, 0, 0, 0, 0, 0);
+    for (int r = 0; r < n; ++r)
+      for (int c = r - kl < 0 ? 0 : r - kl; c < n && c - r <= pa.ku; ++c) {
+        const size_t o = (size_t)r * tw + (c - r + kl);
+        const double t1 = sys_entry(pa.desc, c1, r, c);
+        const double xp = sys_entry(pa.desc, cxp, r, c), xm = sys_entry(pa.desc, cxm, r, c);
+        T[o] = sys_entry(pa.desc, cM, r, c);
+        T[plane + o] = t1;
+        T[2 * plane + o] = sys_entry(pa.desc, c1m, r, c);
+        T[3 * plane + o] = 0.5 * (xp + xm) - t1;
+        T[4 * plane + o] = 0.5 * (xp - xm);
+        if (d.dim == 3) T[5 * plane + o] = 0.5 * (sys_entry(pa.desc, cyp, r, c) - sys_entry(pa.desc, cym, r, c));
+        T[6 * plane + o] = sys_entry(pa.desc, cl1, r, c) - sys_entry(pa.desc, cl0, r, c);
+      }
+    int rc = upload(T, &pen->tpl);
+    if (rc) {
+      free_pencils(pen);
+      delete pen;
+      return rc;
+    }
+    pa.tpl = pen->tpl;
+    pa.tkl = kl;
+    pa.tw = tw;
+    pa.tplane = (long long)plane;
+  }
   paT = pa;
   paT.kl = pa.ku;
   paT.ku = pa.kl;
@@ -710,8 +768,7 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
       const size_t lds = (size_t)(2 * (t.BW + t.nst + t.FW) + 2 * (b.BW + b.nst + b.FW) + 128 +
                                   (Q * Q + Q * Q + 1) / 2 * 2) * 8 +
                          (size_t)4 * 2 * 16 * (FWm > BWm ? FWm : BWm) * 8;
-      // (the refined mixed solve has the single-block layout only)
-      pen->two = ok && dom->Pa <= 2 * cus && 2 * lds <= (size_t)lds_cu && !pen->refined;
+      pen->two = ok && dom->Pa <= 2 * cus && 2 * lds <= (size_t)lds_cu;
       // transposed blocks: the leading block of A~^T is the transpose of a
       // leading block of A~ (split at a mode boundary), kl and ku swap (the
       // reversed trailing block swaps them back).  Here the leading block has
@@ -839,7 +896,8 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   if (e == hipSuccess) e = hipMalloc((void**)&pen->wvec, (size_t)N * sizeof(double2));
   size_t szF = 0;
   for (auto& f : pen->slot)
-    if (e == hipSuccess) e = pen->two ? alloc_slot2(f, pen->pt, pen->pb, &szF) : alloc_slot(f, pa, &szF);
+    if (e == hipSuccess)
+      e = pen->two ? alloc_slot2(f, pen->pt, pen->pb, &szF, pen->refined) : alloc_slot(f, pa, &szF);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->sing, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->flag, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->scratch, szScratch);
@@ -922,6 +980,14 @@ static int factor_into(stau_pencils* pen, stau_pencils::FactorSlot* set, const P
     if (e == hipSuccess)
       e = launch_coupling(bt, bb, a0, b0, f.tLt, f.tPt, f.tLb, f.tPb, f.UfT, f.UfB, f.Rinv, f.E1, f.E2,
                           pen->sing, st);
+    if (e == hipSuccess && f.LT32raw) {  // FP32 copies for the refined mixed solve
+      const size_t sk2 = 2 * (size_t)factor_slack();
+      const size_t cT = (size_t)bt.P * bt.nst + sk2, cB = (size_t)bb.P * bb.nst + sk2;
+      e = launch_round_f32(f.LTraw, f.LT32raw, cT * bt.FW, st);
+      if (e == hipSuccess) e = launch_round_f32(f.UTraw, f.UT32raw, cT * bt.BW, st);
+      if (e == hipSuccess) e = launch_round_f32(f.LBraw, f.LB32raw, cB * bb.FW, st);
+      if (e == hipSuccess) e = launch_round_f32(f.UBraw, f.UB32raw, cB * bb.BW, st);
+    }
     return e;
   }));
   int h = big;
@@ -1032,6 +1098,13 @@ static hipError_t explicit_term(stau_pencils* pen, const void* X, hipStream_t st
 // the two-block solve where it applies, else the single-block solve.
 static hipError_t solve_launch(stau_pencils* pen, const stau_pencils::FactorSlot* fs, double a0,
                                double b0, const double2* B, void* X, hipStream_t st, bool mixed) {
+  if (mixed && pen->refined && pen->two && fs->LfT32) {
+    PencilArgs pt = pen->pt, pb = pen->pb;
+    pt.refine_a0 = pb.refine_a0 = a0;
+    pt.refine_b0 = pb.refine_b0 = b0;
+    return launch_solve2_refined(pt, pb, B, fs->LfT32, fs->slT, fs->UfT32, fs->LfB32, fs->slB, fs->UfB32,
+                                 fs->Rinv, fs->E1, fs->E2, X, st);
+  }
   if (mixed && pen->refined && fs->Lf32) {
     PencilArgs pr = pen->pa;
     pr.refine_a0 = a0;
