@@ -34,7 +34,8 @@ namespace stau {
 // templates of the operator (host-built, one row per step and lane: six
 // loads issued a step ahead and one combination with the pencil's a0, b0,
 // k^2, kx, ky and lin).  Row j of U goes to an LDS
-// staging area (kv + 1 entries per column, entry k = c - r) and column j's
+// staging ring (kv + 1 entries for each of the kv + 1 columns j..j+kv that
+// receive U rows, entry k = c - r) and column j's
 // BW-lane solve record is written when it completes (step j).  The
 // multipliers go straight to their forward-window slots.  With a.trans the
 // transposed matrix is factored (kl and ku of `a` are then those of the
@@ -50,7 +51,7 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
                                                        int* __restrict__ sing,
                                                        double* __restrict__ tailL,
                                                        uint8_t* __restrict__ tailP) {
-  extern __shared__ double ustage[];  // [64][kv + 2]: U(r, c) at (c mod 64, c - r)
+  extern __shared__ double ustage[];  // [kv + 1][kv + 2]: U(r, c) at (c mod (kv + 1), c - r)
   const int p = blockIdx.x;
   if (!pencil_active(a, p)) return;
   const int lane = threadIdx.x;
@@ -95,6 +96,10 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     return combine(in, t);
   };
   int c = lane;  // this lane's column
+  // staging ring of the kv + 1 columns j..j+kv that receive U rows: slot
+  // c mod RS of this lane's column, slot j mod RS of column j
+  const int RS = kv + 1, adv = kWave % RS;
+  int cs = lane % RS, js = 0;
   double av[FW];
 #pragma unroll
   for (int i = 0; i < FW; ++i) av[i] = i <= kl ? entry(i, c) : 0.0;
@@ -147,14 +152,15 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     }
     // row j of U (columns j..j+kv; the pivot as its reciprocal), then the solve
     // record of column j: lane l carries row r = j - ((j - l) mod BW)
-    if (c <= j + kv) ustage[(c & (kWave - 1)) * us + (c - j)] = c == j ? rinv : av[0];
+    if (c <= j + kv) ustage[cs * us + (c - j)] = c == j ? rinv : av[0];
     __builtin_amdgcn_wave_barrier();
     if (lane < BW) {
       const int k = (j - lane) & (BW - 1);
       double v = 0.0;
-      if (k <= kv && k <= j) v = ustage[pl * us + k];
+      if (k <= kv && k <= j) v = ustage[js * us + k];
       Up[(size_t)j * BW + lane] = v;
     }
+    js = js + 1 == RS ? 0 : js + 1;
     // multipliers routed to the physical slots of the forward window: swap
     // the slots of positions 0 and d, the pivot's slot gets 0, then the
     // window advances (the pivot's slot is refilled by the incoming row)
@@ -190,7 +196,11 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     }
     // rows j+1..j+1+kl for the next step
     const bool fresh = lane == pl;
-    if (fresh) c += kWave;
+    if (fresh) {
+      c += kWave;
+      cs += adv;
+      if (cs >= RS) cs -= RS;
+    }
     const double nv = combine(tin, tn);
 #pragma unroll
     for (int i = 0; i < FW; ++i) {
@@ -348,7 +358,7 @@ hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, 
                          double* Uf, int* sing, hipStream_t st, double* tailL, uint8_t* tailP) {
   const int kv = a.kl + a.ku;
   if (a.kl + 1 > a.FW || kv + 1 > a.BW || kv > kWave - 1) return hipErrorInvalidValue;
-  const size_t lds = (size_t)kWave * (kv + 2) * sizeof(double);
+  const size_t lds = (size_t)(kv + 1) * (kv + 2) * sizeof(double);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(a.P), dim3(kWave), lds, st, a, a0, b0, Lf, sl, Uf, sing, tailL, tailP);
   };
