@@ -357,9 +357,10 @@ def rk_run(w, X_start, steps=100, warmup=3):
     return out
 
 
-def lbvp_evp_run(w, reps=50, evp_iters=200):
+def lbvp_evp_run(w, reps=50, nev=4, max_ops=3000):
     """The linear boundary value solve (factors cached) and the shift-invert
-    linear-stability iteration on the workload's pencils."""
+    Krylov-Schur linear-stability solve (nev modes nearest tau = 1 on every
+    pencil, at most max_ops operator applications per pencil)."""
     import torch
 
     import seeded_inputs as si
@@ -376,17 +377,21 @@ def lbvp_evp_run(w, reps=50, evp_iters=200):
     ev1.record()
     torch.cuda.synchronize()
     lbvp_ms = ev0.elapsed_time(ev1) / reps
-    g.evp(1.0, iters=1)
+    g.evp(1.0, nev=1, max_ops=20)  # factors of tau M + L + L' and the bases
     torch.cuda.synchronize()
     ev0.record()
-    sig, res, _ = g.evp(1.0, iters=evp_iters)
+    sig, res, nconv, nops, _ = g.evp(1.0, nev=nev, max_ops=max_ops)
     ev1.record()
     torch.cuda.synchronize()
     evp_ms = ev0.elapsed_time(ev1)
+    act = w["Nx"] // 2
+    nconv, nops = nconv[:act].cpu(), nops[:act].cpu()
+    top = sig[:act, 0].real.max().item()
     g.close()
-    return {"lbvp_ms": lbvp_ms, "lbvp_pencils": w["Nx"] // 2, "evp_iterations": evp_iters,
-            "evp_ms": evp_ms, "evp_us_per_iteration": evp_ms * 1e3 / evp_iters, "evp_tau": 1.0,
-            "evp_top_sigma": float(sig.max())}
+    return {"lbvp_ms": lbvp_ms, "lbvp_pencils": act, "evp_tau": 1.0, "evp_nev": nev, "evp_max_ops": max_ops,
+            "evp_ms": evp_ms, "evp_pencils_all_converged": int((nconv == nev).sum()),
+            "evp_ops_mean": float(nops.float().mean()), "evp_ops_max": int(nops.max()),
+            "evp_top_sigma": top}
 
 
 def ncc_run(w, X_start, steps=100, warmup=5):

@@ -237,24 +237,35 @@ int stau_step_rk(stau_pencils* pen, int scheme, double dt, void* X, void* stream
 int stau_lbvp(stau_pencils* pen, const void* F, void* X, void* stream);
 
 /* Linear stability of the conduction state b0(z) = b_bottom + (b_top - b_bottom) z
- * (Sec. IX "Eigenvalue solver"): for every active pencil, the eigenvalue sigma
- * of  sigma M~ X + (L~ + L~') X = 0  nearest the real shift tau, where L~' is
- * the explicit term -w d_z b linearised about b0 and moved to the left
- * ((b_top - b_bottom) P^L w on the b rows).  `iters` steps of shift-invert
- * iteration x <- A^{-1} M~ x / |A^{-1} M~ x| with the banded LU of
- * A = tau M~ + L~ + L~' (factored by this call when tau changed, synchronously;
- * whole-band layout, kept apart from the step's factors); the iteration
- * converges like |tau - sigma_1| / |tau - sigma_2| per step.  The spectrum of
- * this problem is real.
- * sigma, resid  device float64 [P] (one entry per pencil slot, 0 for inactive
- *          slots): the eigenvalue, and the relative residual
- *          |A^{-1} M~ x - mu x| / |A^{-1} M~ x| of the last step, mu = 1 / (tau - sigma).
- * X        device, state layout, or NULL: the eigenvectors (unit 2-norm of the
- *          recombined real-scaled vector; real, u-type variables imaginary).
- * iters in [1, 100000], else STAU_EINVAL; STAU_ESINGULAR when tau is an
- * eigenvalue of a pencil.  Asynchronous after the factorisation. */
-int stau_evp(stau_pencils* pen, double tau, int iters, double* sigma, double* resid, void* X,
-             void* stream);
+ * (Sec. IX "Eigenvalue solver"): for every active pencil, the nev eigenvalues
+ * sigma of  sigma M~ X + (L~ + L~') X = 0  nearest the real shift tau, where
+ * L~' is the explicit term -w d_z b linearised about b0 and moved to the left
+ * ((b_top - b_bottom) P^L w on the b rows).  Shift-invert Krylov-Schur
+ * iteration: Arnoldi steps with T = A^{-1} M~ (the banded LU of
+ * A = tau M~ + L~ + L~', factored by this call when tau changed,
+ * synchronously; whole-band layout, kept apart from the step's factors) on a
+ * basis of at most ncv vectors, Rayleigh-Ritz on the projected matrix, and
+ * thick restarts that keep nev plus half of the remaining Ritz vectors, until
+ * the nev Ritz values theta = 1 / (tau - sigma) of largest modulus have
+ * converged or max_ops applications of T (exceeded by at most ncv) are spent.
+ * sigma    device complex128 [P][nev] (float64 pairs): sigma = tau - 1 / theta,
+ *          nearest tau first (0 for inactive slots; NaN for a value the
+ *          iteration could not determine)
+ * resid    device float64 [P][nev]: |T x - theta x| / |theta| of the Ritz
+ *          pair (the Krylov estimate |beta y_last| / |theta|; for a complex
+ *          pair that of its two-dimensional invariant subspace)
+ * nconv    device int32 [P]: how many of the nev have resid <= tol
+ * nops     device int32 [P] or NULL: applications of T spent
+ * X        device complex128 [nev][P][state] or NULL: the eigenvectors
+ *          (unit 2-norm of the real-scaled vector; X = P^R x with u-type
+ *          variables scaled by -i; zero for inactive slots)
+ * 1 <= nev <= 16, nev + 2 <= ncv <= min(32, pencil size), ncv <= max_ops <=
+ * 1e6, 0 < tol < 1, else STAU_EINVAL; STAU_ESINGULAR when tau is an
+ * eigenvalue of a pencil; STAU_ENOMEM when the bases (P (ncv + 1) n doubles,
+ * kept for later calls) cannot be allocated.  Asynchronous after the
+ * factorisation. */
+int stau_evp(stau_pencils* pen, double tau, int nev, int ncv, int max_ops, double tol, double* sigma,
+             double* resid, int32_t* nconv, int32_t* nops, void* X, void* stream);
 
 /* Initial state from real scale-1 grid values of b (Sec. IX "Initial
  * conditions": the state is set in grid space and must satisfy the problem's

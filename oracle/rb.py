@@ -622,6 +622,29 @@ class RBOracle:
         return float(np.real(tau - 1.0 / mu))
 
 
+    def stability_eigenvalues(self, kx: float, ky: float = 0.0, tau: float = 0.0, nev: int = 1,
+                              is_mean: bool = False, method: str = "auto") -> np.ndarray:
+        """The nev eigenvalues sigma of sigma M X + (L + L') X = 0 (linearised
+        about conduction, Sec. IX "Eigenvalue solver") nearest the real shift
+        tau, nearest first, as complex numbers: all finite generalized
+        eigenvalues (dense, small pencils) or ARPACK's nev dominant
+        eigenvalues mu of the shift-inverted operator (L + L' + tau M)^{-1} M,
+        sigma = tau - 1 / mu (the paper's sparse route); method "dense" or
+        "arpack" forces a route."""
+        M, A = self.linearized_matrices(kx, ky, is_mean)
+        n = M.shape[0]
+        if method == "dense" or (method == "auto" and n <= 1200):
+            w = sla.eigvals(A.toarray(), -M.toarray())
+            w = w[np.isfinite(w)]
+            w = w[np.abs(w) < 1e8]
+        else:
+            lu = spla.splu((A + tau * M).tocsc())
+            T = spla.LinearOperator(A.shape, matvec=lambda x: lu.solve(M @ x), dtype=np.complex128)
+            mu = spla.eigs(T, k=nev, ncv=max(2 * nev + 1, 20), which="LM", return_eigenvectors=False,
+                           tol=1e-14)
+            w = tau - 1.0 / mu
+        return w[np.argsort(np.abs(w - tau), kind="stable")][:nev]
+
 def tau_poisson_bvp(N: int, f_coeffs: np.ndarray) -> np.ndarray:
     """Worked example of Sec. II "Summary & example": u'' = f on [-1, 1],
     u(-1) = 0, u'(1) = 0, as the first-order system d_x ux = f,

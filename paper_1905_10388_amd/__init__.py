@@ -150,17 +150,26 @@ class RBSolver:
         _lib.check(self.lib.stau_lbvp(self._pen, _ptr(F), _ptr(X), _stream_ptr()))
         return X
 
-    def evp(self, tau: float, iters: int = 100, vectors: bool = False):
-        """Linear-stability eigenvalue nearest tau for every pencil slot:
-        (sigma [P], resid [P], X or None) as device tensors."""
+    def evp(self, tau: float, nev: int = 1, ncv: int = None, max_ops: int = 2000, tol: float = 1e-10,
+            vectors: bool = False):
+        """Linear-stability eigenvalues nearest tau for every pencil slot
+        (shift-invert Krylov-Schur, stau_evp): (sigma complex [P, nev],
+        resid [P, nev], nconv int32 [P], nops int32 [P], X [nev, *state] or
+        None) as device tensors.  ncv defaults to max(2 nev + 8, 20), at
+        most 32."""
         t = self._torch
         P = self.info["P"]
-        sigma = t.empty(P, dtype=t.float64, device=self.device)
-        resid = t.empty(P, dtype=t.float64, device=self.device)
-        X = t.empty(self.state_shape, dtype=t.complex128, device=self.device) if vectors else None
-        _lib.check(self.lib.stau_evp(self._pen, float(tau), int(iters), _ptr(sigma), _ptr(resid),
+        if ncv is None:
+            ncv = min(32, max(2 * nev + 8, 20))
+        sigma = t.empty((P, nev), dtype=t.complex128, device=self.device)
+        resid = t.empty((P, nev), dtype=t.float64, device=self.device)
+        nconv = t.empty(P, dtype=t.int32, device=self.device)
+        nops = t.empty(P, dtype=t.int32, device=self.device)
+        X = t.empty((nev,) + tuple(self.state_shape), dtype=t.complex128, device=self.device) if vectors else None
+        _lib.check(self.lib.stau_evp(self._pen, float(tau), int(nev), int(ncv), int(max_ops), float(tol),
+                                     _ptr(sigma), _ptr(resid), _ptr(nconv), _ptr(nops),
                                      _ptr(X) if X is not None else None, _stream_ptr()))
-        return sigma, resid, X
+        return sigma, resid, nconv, nops, X
 
     def factor(self, a0: float, b0: float = 1.0):
         _lib.check(self.lib.stau_factor(self._pen, float(a0), float(b0), _stream_ptr()))

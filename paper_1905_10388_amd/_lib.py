@@ -100,7 +100,7 @@ def load(path: str = LIB_PATH):
         "stau_step": (i32, [vp, C.POINTER(StateC), dbl, vp]),
         "stau_step_rk": (i32, [vp, i32, dbl, vp, vp]),
         "stau_lbvp": (i32, [vp, vp, vp, vp]),
-        "stau_evp": (i32, [vp, dbl, i32, vp, vp, vp, vp]),
+        "stau_evp": (i32, [vp, dbl, i32, i32, i32, dbl, vp, vp, vp, vp, vp, vp]),
         "stau_initial_state": (i32, [vp, vp, vp, vp]),
         "stau_nonlinear": (i32, [vp, vp, vp, vp]),
         "stau_solve": (i32, [vp, vp, vp, vp]),

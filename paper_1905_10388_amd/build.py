@@ -10,8 +10,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libstau.so")
-SOURCES = ["stau.hip", "k_pencil.hip", "k_factor.hip", "k_transform.hip", "k_xpass.hip", "k_adjoint.hip",
-           "k_dctmm.hip", "k_grid.hip"]
+SOURCES = ["stau.hip", "k_pencil.hip", "k_factor.hip", "k_evp.hip", "k_transform.hip", "k_xpass.hip",
+           "k_adjoint.hip", "k_dctmm.hip", "k_grid.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # no packed-FP32 instructions in generated code

@@ -155,7 +155,8 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     if (c <= j + kv) ustage[cs * us + (c - j)] = c == j ? rinv : av[0];
     __builtin_amdgcn_wave_barrier();
     if (lane < BW) {
-      const int k = (j - lane) & (BW - 1);
+      int k = (j - lane) % BW;  // (BW need not be a power of two)
+      if (k < 0) k += BW;
       double v = 0.0;
       if (k <= kv && k <= j) v = ustage[js * us + k];
       Up[(size_t)j * BW + lane] = v;

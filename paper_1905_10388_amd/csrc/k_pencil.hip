@@ -1,141 +1,12 @@
 // Pencil solve kernels: the batched banded solve (one wavefront per pencil
-// and real part, register windows), its two-block and transposed forms, the
-// refined mixed-precision solve and the shift-invert stability iteration.
-// The factor layout they read is described in k_factor.hip.
+// and real part, register windows), its two-block and transposed forms and
+// the refined mixed-precision solve.  The factor layout they read is
+// described in k_factor.hip.
 #include <algorithm>
 
-#include "pencil.h"
+#include "sweeps.h"
 
 namespace stau {
-
-// ---------------------------------------------------------------------------
-// Sweeps of one real right-hand side b (this wavefront's own vector in LDS,
-// padded: BW finite values before row 0, FW after row npad - 1, npad = nch *
-// kCH) through the stored factors of one pencil:
-//   forward  y = L^{-1} P b  (window of FW pending rows in physical slots:
-//            lane s holds the row in slot s; the pivot's slot is refilled
-//            with the next row, the others take the rank-1 update);
-//   backward x = U^{-1} y    (lane l carries row r = l mod BW of the window
-//            [j - BW + 1, j]; lane j mod BW holds 1 / U(j, j)).
-// Factor coefficients stream from global memory straight into a ring of
-// kRing registers per lane, kRing columns ahead of their use: no LDS staging
-// and no barrier, so each wavefront sweeps on its own.  The factor arrays
-// hold nst = npad columns per pencil (zero beyond n) with kRing columns of
-// slack before the first pencil and after the last, so the look-ahead loads
-// never leave the allocation (their values past the sweep are not used).
-// ---------------------------------------------------------------------------
-template <typename T, int FW>
-__device__ __forceinline__ void sweep_forward(T* b, const T* __restrict__ Lp,
-                                              const uint32_t* __restrict__ sw, int nch, int lane) {
-  constexpr int CH = kCH, D = kRing, G = 16;
-  static_assert(CH % D == 0 && D % 4 == 0 && CH % G == 0 && FW <= 32, "sweep geometry");
-  const int lf = lane & (FW - 1);
-  T ring[D];
-  uint32_t sring[D / 4];
-#pragma unroll
-  for (int k = 0; k < D; ++k) ring[k] = Lp[k * FW + lf];
-#pragma unroll
-  for (int k = 0; k < D / 4; ++k) sring[k] = sw[k];
-  T w = lane < FW ? b[lane] : (T)0;
-  for (int c = 0; c < nch; ++c) {
-    const int j0 = c * CH;
-    const T* Ln = Lp + (size_t)(j0 + D) * FW + lf;  // column j0 + D + t at Ln[t * FW]
-    const uint32_t* Sn = sw + (j0 + D) / 4;
-    T* yo = b + j0;
-    T nv[2][G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) nv[0][k] = yo[k + FW];
-#pragma unroll
-    for (int k = 0; k < G; ++k) pin(nv[0][k]);
-    uint32_t word = 0;
-    T yacc = (T)0;  // lane t: y of column j0 + t
-    static_for<0, CH / G>([&](auto gc) {
-      constexpr int g = decltype(gc)::value;
-      if (g + 1 < CH / G) {
-#pragma unroll
-        for (int k = 0; k < G; ++k) nv[(g + 1) & 1][k] = yo[(g + 1) * G + k + FW];
-      }
-      static_for<0, G>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        constexpr int t = g * G + k;
-        if ((t & 3) == 0) word = __builtin_amdgcn_readfirstlane(sring[(t >> 2) % (D / 4)]);
-        const int s = (word >> (8 * (t & 3))) & 0xff;
-        const T y = readlane_t(w, s);
-        put_lane<t>(yacc, y);
-        const T l = ring[t % D];
-        ring[t % D] = Ln[t * FW];
-        if ((t & 3) == 3) sring[(t >> 2) % (D / 4)] = Sn[t >> 2];
-        // lane s takes the next row (the lane mask is formed on the scalar
-        // unit); its multiplier is 0, so the select is made before the
-        // update, beside the lane read instead of after the FMA
-        const T ws = __builtin_amdgcn_inverse_ballot_w64(1ull << s) ? nv[g & 1][k] : w;
-        w = fma(-l, y, ws);
-      });
-      if (g + 1 < CH / G) {
-#pragma unroll
-        for (int k = 0; k < G; ++k) pin(nv[(g + 1) & 1][k]);
-      }
-    });
-    yo[lane] = yacc;
-  }
-
-}
-
-template <typename T, int BW>
-__device__ __forceinline__ void sweep_backward(T* b, const T* __restrict__ Up, int nch, int lane) {
-  constexpr int CH = kCH, D = kRing, G = 16;
-  static_assert(CH % D == 0 && CH % G == 0 && CH % BW == 0 && BW <= 64, "sweep geometry");
-  const int npad = nch * CH;
-  // columns descending
-  const int lb = lane & (BW - 1);
-  T ring[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) ring[k] = Up[(size_t)(npad - D + k) * BW + lb];  // slot j mod D
-  // rows npad-BW .. npad-1 (rows >= n hold finite padding; their U
-  // coefficients are zero)
-  T w = b[npad - BW + lb];
-  for (int c = nch - 1; c >= 0; --c) {
-    const int j0 = c * CH;
-    const T* Un = Up + ((ptrdiff_t)j0 - D) * BW + lb;  // column j0 - D + t at Un[t * BW]
-    T* xo = b + j0;
-    constexpr int NG = CH / G;
-    T nv[2][G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) nv[(NG - 1) & 1][k] = xo[(NG - 1) * G + k - BW];
-#pragma unroll
-    for (int k = 0; k < G; ++k) pin(nv[(NG - 1) & 1][k]);
-    T xacc = (T)0;  // lane t: x of column j0 + t
-    static_for<0, NG>([&](auto gc) {
-      constexpr int g = NG - 1 - decltype(gc)::value;
-      if (g > 0) {
-#pragma unroll
-        for (int k = 0; k < G; ++k) nv[(g - 1) & 1][k] = xo[(g - 1) * G + k - BW];
-      }
-      static_for<0, G>([&](auto kc) {
-        constexpr int k = G - 1 - decltype(kc)::value;
-        constexpr int t = g * G + k;
-        constexpr int sj = t % BW;
-        constexpr uint64_t msj = BW == 32 ? ((1ull << sj) | (1ull << (sj + 32))) : (1ull << sj);
-        const T u = ring[t % D];
-        ring[t % D] = Un[t * BW];
-        const T x = readlane_t(w * u, sj);
-        put_lane<t>(xacc, x);
-        w = __builtin_amdgcn_inverse_ballot_w64(msj) ? nv[g & 1][k] : fma(-u, x, w);  // lanes l = sj mod BW
-      });
-      if (g > 0) {
-#pragma unroll
-        for (int k = 0; k < G; ++k) pin(nv[(g - 1) & 1][k]);
-      }
-    });
-    xo[lane] = xacc;
-  }}
-
-template <typename T, int FW, int BW>
-__device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uint32_t* __restrict__ sw,
-                                       const T* __restrict__ Up, int nch, int lane) {
-  sweep_forward<T, FW>(b, Lp, sw, nch, lane);
-  sweep_backward<T, BW>(b, Up, nch, lane);
-}
 
 // ---------------------------------------------------------------------------
 // Sweeps with the factor columns staged through LDS.  A 64-lane global load
@@ -143,14 +14,22 @@ __device__ __forceinline__ void sweeps(T* b, const T* __restrict__ Lp, const uin
 // of distinct addresses, so one load per column and wavefront limits a
 // sweep once four or more wavefronts share a compute unit.  Here the columns
 // move in units of SU columns with loads of 64 distinct addresses (16 bytes
-// per lane, 1 KB per instruction; 8 bytes for a 512-byte unit), two units
+// per lane, 1 KB per instruction; 8 bytes for a 512-byte unit), K units
 // ahead of their use, through two LDS buffers per wavefront, and each column
-// is then one LDS read into a ring of kSR registers.  At the start of
-// processing unit v the data of unit v + 1 is written to LDS buffer
-// (v + 1) mod 2 and unit v + 3 is loaded into the freed registers; reads of
-// unit v + 1 begin kSR columns before it.  The forward sweep reads its slot
-// bytes with vector loads (one chunk ahead, a lane read per four columns),
-// so that no scalar load shares the LDS wait counter with the ring reads.
+// is then one LDS read into a ring of kSR registers.  K units are in flight
+// in registers (unit u in register set u mod K): at the start of processing
+// unit v the data of unit v + 1 is written to LDS buffer (v + 1) mod 2 and
+// unit v + 1 + K is loaded into the freed registers; reads of unit v + 1
+// begin kSR columns before it.  K sets how far ahead of their use the
+// global loads are issued (K SU columns), which must cover the memory
+// latency when only a few wavefronts share a SIMD.  Every load is issued
+// unconditionally (past the last unit the last one again): a load under a
+// branch makes the compiler wait for all outstanding loads (vmcnt 0) before
+// the next LDS store, which would expose the full latency once per unit.  The
+// forward sweep's slot bytes come with each unit (a vector load of its words,
+// one lane read per four columns): a separate stream of
+// them made the compiler wait for nearly all loads at each chunk, and a
+// scalar load would share the LDS wait counter with the ring reads.
 // ---------------------------------------------------------------------------
 constexpr int kSR = 8;  // LDS-read look-ahead (columns)
 
@@ -195,32 +74,45 @@ __device__ __forceinline__ void prio_turn(int chunk, int psel) {
     __builtin_amdgcn_s_setprio(0);
 }
 
-template <typename T, int FW, int SU>
+template <typename T, int FW, int SU, int K = 2>
 __device__ __forceinline__ void sweep_forward_staged(T* b, const T* __restrict__ Lp,
                                                      const uint32_t* __restrict__ sw, int nch,
                                                      int lane, T* st, int psel = -1) {
   constexpr int CH = kCH, G = 16, R = kSR, UPC = CH / SU;
-  static_assert(CH % SU == 0 && UPC % 2 == 0 && R <= SU && CH % G == 0 && FW <= 32,
+  static_assert(CH % SU == 0 && UPC % 2 == 0 && UPC % K == 0 && K >= 2 && R <= SU &&
+                    CH % G == 0 && FW <= 32,
                 "sweep geometry");
   constexpr int FB = SU * FW * (int)sizeof(T);
+  constexpr int SWU = SU / 4;  // slot words of a unit (four columns per word)
   const int nu = nch * UPC;
   const int lf = lane & (FW - 1);
-  UnitRegs<FB> r0, r1;  // units in flight (even / odd)
-  r0.load(Lp, lane);
-  r1.load(Lp + (size_t)SU * FW, lane);
-  r0.store(st, lane);
-  if (nu > 2) r0.load(Lp + (size_t)2 * SU * FW, lane);
+  // units in flight: unit u in r[u mod K], its slot words in swr[u mod K]
+  // (lane i holds word i mod SWU: a lane-dependent address keeps it a vector
+  // load); the words travel with the unit's data, so that one wait covers both
+  UnitRegs<FB> r[K];
+  uint32_t swr[K];
+  auto load_unit = [&](int k, int u) {
+    r[k].load(Lp + (size_t)u * SU * FW, lane);
+    swr[k] = sw[u * SWU + (lane & (SWU - 1))];
+  };
+  load_unit(0, 0);
+#pragma unroll
+  for (int u = 1; u < K; ++u) load_unit(u, u < nu ? u : nu - 1);
+  r[0].store(st, lane);
+  // slot words of the next and the current unit, read into scalar registers
+  // when the unit's data goes to LDS (copies of loaded vector registers
+  // across the chunk loop would wait for every load in flight)
+  uint32_t wnx[SWU], wcur[SWU];
+#pragma unroll
+  for (int i = 0; i < SWU; ++i) wnx[i] = (uint32_t)__builtin_amdgcn_readlane(swr[0], i);
+  load_unit(0, K < nu ? K : nu - 1);
   T ring[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) ring[k] = st[k * FW + lf];
-  // slot bytes of a chunk: lane i holds word i mod 16 (columns 4i .. 4i + 3)
-  uint32_t swv = sw[lane & 15];
   T w = lane < FW ? b[lane] : (T)0;
   for (int c = 0; c < nch; ++c) {
     if (psel >= 0) prio_turn(c, psel);
     const int j0 = c * CH;
-    const uint32_t swc = swv;
-    if (c + 1 < nch) swv = sw[(j0 + CH) / 4 + (lane & 15)];
     T* yo = b + j0;
     T nv[2][G];
 #pragma unroll
@@ -239,17 +131,22 @@ __device__ __forceinline__ void sweep_forward_staged(T* b, const T* __restrict__
         constexpr int k = decltype(kc)::value;
         constexpr int t = g * G + k;
         if constexpr (t % SU == 0) {
-          // start of unit v = c UPC + t / SU: unit v + 1 to LDS, unit v + 3 requested
-          const int v3 = c * UPC + t / SU + 3;
-          if constexpr ((t / SU + 1) & 1) {
-            r1.store(st + SU * FW, lane);
-            if (v3 < nu) r1.load(Lp + (size_t)v3 * SU * FW, lane);
-          } else {
-            r0.store(st, lane);
-            if (v3 < nu) r0.load(Lp + (size_t)v3 * SU * FW, lane);
+          // start of unit v = c UPC + t / SU: unit v + 1 to LDS, unit v + 1 + K
+          // requested (c UPC is a multiple of K, so the register set is fixed)
+          const int vk = c * UPC + t / SU + 1 + K;
+          constexpr int rs = (t / SU + 1) % K;
+          // (the pin keeps the lane reads here: the compiler would hoist every
+          // unit's reads to the top of the chunk, waiting for all loads)
+          asm volatile("" : "+v"(swr[rs]));
+#pragma unroll
+          for (int i = 0; i < SWU; ++i) {
+            wcur[i] = wnx[i];
+            wnx[i] = (uint32_t)__builtin_amdgcn_readlane(swr[rs], i);
           }
+          r[rs].store(st + ((t / SU + 1) & 1) * SU * FW, lane);
+          load_unit(rs, vk < nu ? vk : nu - 1);
         }
-        if constexpr ((t & 3) == 0) word = (uint32_t)__builtin_amdgcn_readlane(swc, t >> 2);
+        if constexpr ((t & 3) == 0) word = wcur[(t % SU) >> 2];
         const int s = (word >> (8 * (t & 3))) & 0xff;
         const T y = readlane_t(w, s);
         put_lane<t>(yacc, y);
@@ -268,22 +165,26 @@ __device__ __forceinline__ void sweep_forward_staged(T* b, const T* __restrict__
   }
 }
 
-template <typename T, int BW, int SU>
+template <typename T, int BW, int SU, int K = 2>
 __device__ __forceinline__ void sweep_backward_staged(T* b, const T* __restrict__ Up, int nch,
                                                       int lane, T* st) {
   constexpr int CH = kCH, G = 16, R = kSR, UPC = CH / SU;
-  static_assert(CH % SU == 0 && UPC % 2 == 0 && R <= SU && CH % G == 0 && CH % BW == 0 &&
-                    BW <= 64,
+  static_assert(CH % SU == 0 && UPC % 2 == 0 && UPC % K == 0 && K >= 2 && R <= SU &&
+                    CH % G == 0 && BW % 16 == 0 && BW <= 64,
                 "sweep geometry");
+  constexpr bool kDiv = CH % BW == 0;
   constexpr int UB = SU * BW * (int)sizeof(T);
   const int npad = nch * CH, nu = nch * UPC;
-  // processing index v covers unit nu - 1 - v (columns descending)
-  const int lb = lane & (BW - 1);
-  UnitRegs<UB> r0, r1;
-  r0.load(Up + (size_t)(nu - 1) * SU * BW, lane);
-  r1.load(Up + (size_t)(nu - 2) * SU * BW, lane);
-  r0.store(st, lane);
-  if (nu > 2) r0.load(Up + (size_t)(nu - 3) * SU * BW, lane);
+  // processing index v covers unit nu - 1 - v (columns descending); index v
+  // in flight in r[v mod K]
+  const int lb = lane % BW;
+  UnitRegs<UB> r[K];
+  r[0].load(Up + (size_t)(nu - 1) * SU * BW, lane);
+#pragma unroll
+  for (int u = 1; u < K; ++u)
+    r[u].load(Up + (size_t)(u < nu ? nu - 1 - u : 0) * SU * BW, lane);
+  r[0].store(st, lane);
+  r[0].load(Up + (size_t)(K < nu ? nu - 1 - K : 0) * SU * BW, lane);
   // processing unit v sits in LDS buffer v mod 2; column SU - 1 - k of unit
   // nu - 1 is ring entry k
   T ring[R];
@@ -291,9 +192,10 @@ __device__ __forceinline__ void sweep_backward_staged(T* b, const T* __restrict_
   for (int k = 0; k < R; ++k) ring[k] = st[(SU - 1 - k) * BW + lb];
   // rows npad-BW .. npad-1 (rows >= n hold finite padding; their U
   // coefficients are zero)
-  T w = b[npad - BW + lb];
+  T w = b[window_start_row<BW>(npad, lb)];
   for (int c = nch - 1; c >= 0; --c) {
     const int j0 = c * CH;
+    const int s0 = kDiv ? 0 : j0 % BW;
     T* xo = b + j0;
     constexpr int NG = CH / G;
     T nv[2][G];
@@ -314,17 +216,13 @@ __device__ __forceinline__ void sweep_backward_staged(T* b, const T* __restrict_
         constexpr int q = CH - 1 - t;  // position in processing order within the chunk
         if constexpr (q % SU == 0) {
           // unit of processing index v = UPC (nch - 1 - c) + q / SU starts
-          const int v3 = UPC * (nch - 1 - c) + q / SU + 3;
-          if constexpr ((q / SU + 1) & 1) {
-            r1.store(st + SU * BW, lane);
-            if (v3 < nu) r1.load(Up + (size_t)(nu - 1 - v3) * SU * BW, lane);
-          } else {
-            r0.store(st, lane);
-            if (v3 < nu) r0.load(Up + (size_t)(nu - 1 - v3) * SU * BW, lane);
-          }
+          const int vk = UPC * (nch - 1 - c) + q / SU + 1 + K;
+          constexpr int rs = (q / SU + 1) % K;
+          r[rs].store(st + ((q / SU + 1) & 1) * SU * BW, lane);
+          r[rs].load(Up + (size_t)(vk < nu ? nu - 1 - vk : 0) * SU * BW, lane);
         }
-        constexpr int sj = t % BW;
-        constexpr uint64_t msj = BW == 32 ? ((1ull << sj) | (1ull << (sj + 32))) : (1ull << sj);
+        const int sj = kDiv ? t % BW : window_lane<BW>(s0, t);
+        const uint64_t msj = window_lanes<BW>(sj);
         const T u = ring[q % R];
         constexpr int qn = q + R;  // processing position read ahead
         ring[q % R] = st[((qn / SU) & 1) * SU * BW + (SU - 1 - qn % SU) * BW + lb];
@@ -357,12 +255,12 @@ constexpr int su3() {
   return sizeof(T) == 8 ? 8 : 16;
 }
 
-template <typename T, int FW, int BW>
+template <typename T, int FW, int BW, int K = 2>
 __device__ __forceinline__ void sweeps_staged_both(T* b, const T* __restrict__ Lp,
                                                    const uint32_t* __restrict__ sw,
                                                    const T* __restrict__ Up, int nch, int lane, T* st) {
-  sweep_forward_staged<T, FW, su3<T>()>(b, Lp, sw, nch, lane, st);
-  sweep_backward_staged<T, BW, su3<T>()>(b, Up, nch, lane, st);
+  sweep_forward_staged<T, FW, su3<T>(), K>(b, Lp, sw, nch, lane, st);
+  sweep_backward_staged<T, BW, su3<T>(), K>(b, Up, nch, lane, st);
 }
 
 template <typename T, int FW, int BW>
@@ -478,8 +376,11 @@ __global__ void __launch_bounds__(4 * kWave) solve_kernel(PencilArgs a, int plau
     const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
     const double* Up = Uf + (size_t)p * npad * BW;
     if constexpr (STG == 2) {
+      // eight units (64 columns) of loads in flight: at two blocks per compute
+      // unit, two units left the sweeps waiting on memory (solve of the
+      // 256 x 256 x 128 workload 5.77 ms with two, 5.38 with four, 5.21 with eight)
       double* stg = lds + (size_t)4 * span + (size_t)wv * (stage_bytes<double, FW, BW, su3<double>()>() / 8);
-      sweeps_staged_both<double, FW, BW>(b, Lp, swp, Up, nch, lane, stg);
+      sweeps_staged_both<double, FW, BW, 8>(b, Lp, swp, Up, nch, lane, stg);
     } else if constexpr (STG == 1) {
       double* stg = lds + (size_t)4 * span + (size_t)wv * (stage_bytes<double, 1, BW, kSU>() / 8);
       sweeps_staged<double, FW, BW>(b, Lp, swp, Up, nch, lane, stg);
@@ -612,110 +513,6 @@ __global__ void round_to_f32_kernel(const double* __restrict__ src, float* __res
        i += (size_t)gridDim.x * blockDim.x)
     dst[i] = (float)src[i];
 }
-
-// ---------------------------------------------------------------------------
-// Linear stability (Sec. IX "Eigenvalue solver"): sigma M~ x + (L~ + L~') x = 0
-// about the conduction state, per pencil.  With the factors of
-// A = tau M~ + L~ + L~', the iteration x <- A^{-1} M~ x / |A^{-1} M~ x|
-// converges to the eigenvector whose eigenvalue mu = 1 / (tau - sigma) of
-// A^{-1} M~ is largest in modulus, i.e. sigma nearest tau (the spectrum of
-// this problem is real); mu = x . A^{-1} M~ x.  One wavefront per pencil: M~ x
-// from the operator templates (a0 = 1, b0 = 0), the two sweeps of the solve,
-// then the normalisation.  Writes sigma = tau - 1 / mu, the relative residual
-// |A^{-1} M~ x - mu x| / |A^{-1} M~ x| of the last iteration and, with X, the
-// eigenvector X = P^R x (state layout, unit 2-norm over x).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-template <int FW, int BW>
-__global__ void __launch_bounds__(kWave) evp_kernel(PencilArgs a, double tau, int iters,
-                                                    const double* __restrict__ Lf,
-                                                    const uint8_t* __restrict__ sl,
-                                                    const double* __restrict__ Uf,
-                                                    double* __restrict__ sigma,
-                                                    double* __restrict__ resid,
-                                                    double2* __restrict__ X) {
-  extern __shared__ double lds[];
-  const int p = blockIdx.x, lane = threadIdx.x;
-  const SysDesc& d = a.desc;
-  const int n = a.n, N = d.N, S = d.S, npad = a.nst, nch = npad / kCH;
-  const int span = BW + npad + FW;
-  double* b = lds + BW;     // solve vector, rows [-BW, npad + FW)
-  double* x = lds + span;   // iterate, rows [0, n)
-  if (!pencil_active(a, p)) {
-    if (lane == 0) {
-      sigma[p] = 0.0;
-      resid[p] = 0.0;
-    }
-    if (X) zero_pencils(X, p, p + 1, S * N, lane, kWave);
-    return;
-  }
-  const PencilCoef pm = pencil_coef(a, p, 1.0, 0.0);  // M~
-  // deterministic start vector (no symmetry of the problem), unit norm
-  double ss = 0.0;
-  for (int r = lane; r < n; r += kWave) {
-    const double q = 0.6180339887498949 * (double)(r + 1);  // golden-ratio sequence in [0.5, 1.5)
-    const double v = 0.5 + (q - floor(q));
-    x[r] = v;
-    ss += v * v;
-  }
-  ss = wave_sum(ss);
-  {
-    const double inv = 1.0 / __builtin_sqrt(ss);
-    for (int r = lane; r < n; r += kWave) x[r] *= inv;
-  }
-  const double* Lp = Lf + (size_t)p * npad * FW;
-  const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
-  const double* Up = Uf + (size_t)p * npad * BW;
-  double mu = 0.0, res = 0.0;
-  for (int it = 0; it < iters; ++it) {
-    __syncthreads();
-    for (int r = lane - BW; r < npad + FW; r += kWave)
-      b[r] = (r >= 0 && r < n) ? apply_row(d, pm, r, [&](int m, int var) { return x[m * S + d.var_pos[var]]; })
-                               : 0.0;
-    __syncthreads();
-    sweeps<double, FW, BW>(b, Lp, swp, Up, nch, lane);
-    __syncthreads();
-    double xz = 0.0, zz = 0.0;
-    for (int r = lane; r < n; r += kWave) {
-      xz += x[r] * b[r];
-      zz += b[r] * b[r];
-    }
-    mu = wave_sum(xz);
-    zz = wave_sum(zz);
-    double rr = 0.0;
-    for (int r = lane; r < n; r += kWave) {
-      const double e = b[r] - mu * x[r];
-      rr += e * e;
-    }
-    rr = wave_sum(rr);
-    res = __builtin_sqrt(rr / zz);
-    const double inv = 1.0 / __builtin_sqrt(zz);
-    for (int r = lane; r < n; r += kWave) x[r] = b[r] * inv;
-  }
-  if (lane == 0) {
-    sigma[p] = tau - 1.0 / mu;
-    resid[p] = res;
-  }
-  if (X) {
-    __syncthreads();
-    double2* Xp = X + (size_t)p * S * N;
-    for (int i = lane; i < S * N; i += kWave) {
-      const int vabi = i / N, m = i - vabi * N;
-      const int var = a.var_of_abi[vabi];
-      const int pos = d.var_pos[var];
-      double v = x[m * S + pos];
-      if (m + 2 < N) v -= x[(m + 2) * S + pos];
-      Xp[i] = (var == VU || var == VUZ || var == VV || var == VVZ) ? make_double2(0.0, -v)  // u = -i u~
-                                                                   : make_double2(v, 0.0);
-    }
-  }
-}
-
 
 // ---------------------------------------------------------------------------
 // Transposed solve (adjoint of solve_kernel): B_bar = S_L^H A~^{-T} S_R^H
@@ -1243,14 +1040,9 @@ __global__ void __launch_bounds__(2 * kWave) solveT_kernel(PencilArgs a, int pla
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
-// launchers
-// ---------------------------------------------------------------------------
 static void allow_lds(const void* fn, size_t bytes) {
   if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
-
-#define STAU_SWEEP_VARIANTS(X) X(8, 32) X(8, 64) X(16, 32) X(16, 64) X(32, 32) X(32, 64)
 
 // Launch shape of the two-pencil blocks: pencils covered (the leading active
 // pencils in 2-D, all in 3-D), block count, and the LDS request.  When the
@@ -1367,25 +1159,6 @@ hipError_t launch_round_f32(const double* src, float* dst, size_t count, hipStre
   return hipGetLastError();
 }
 
-template <int FW, int BW>
-static hipError_t launch_evp_t(const PencilArgs& a, double tau, int iters, const double* Lf,
-                               const uint8_t* sl, const double* Uf, double* sigma, double* resid,
-                               void* X, hipStream_t st) {
-  const size_t lds = (size_t)(BW + a.nst + FW + a.n) * sizeof(double);
-  allow_lds((const void*)evp_kernel<FW, BW>, lds);
-  hipLaunchKernelGGL((evp_kernel<FW, BW>), dim3(a.P), dim3(kWave), lds, st, a, tau, iters, Lf, sl, Uf,
-                     sigma, resid, (double2*)X);
-  return hipGetLastError();
-}
-
-hipError_t launch_evp(const PencilArgs& a, double tau, int iters, const double* Lf, const uint8_t* sl,
-                      const double* Uf, double* sigma, double* resid, void* X, hipStream_t st) {
-#define STAU_CASE(F, B) \
-  if (a.FW == F && a.BW == B) return launch_evp_t<F, B>(a, tau, iters, Lf, sl, Uf, sigma, resid, X, st);
-  STAU_SWEEP_VARIANTS(STAU_CASE)
-#undef STAU_CASE
-  return hipErrorInvalidValue;
-}
 
 template <int FWT, int BWT, int FWB, int BWB, bool TRANS>
 static hipError_t launch_solve2_t(const PencilArgs& t, const PencilArgs& bt, const void* Bev,

@@ -111,11 +111,19 @@ hipError_t launch_solve2(const PencilArgs& t, const PencilArgs& bt, const void* 
                          const double* Rinv, const double* E1, const double* E2, void* X,
                          hipStream_t st);
 bool solve2_supported(const PencilArgs& t, const PencilArgs& bt);
-// shift-invert iteration for the linear-stability eigenvalue nearest tau, one
-// wavefront per pencil, on the factors of tau M~ + L~ + L~' (k_pencil.hip)
-hipError_t launch_evp(const PencilArgs& a, double tau, int iters, const double* Lf,
-                      const uint8_t* sl, const double* Uf, double* sigma, double* resid, void* X,
-                      hipStream_t st);
+// Linear-stability eigenvalues nearest tau by shift-invert Krylov-Schur
+// iteration, one wavefront per pencil, on the whole-band factors of
+// tau M~ + L~ + L~' (k_evp.hip).  V: device workspace of P (ncv + 1) n doubles.
+struct EvpOut {
+  double2* sigma;  // [P][nev]
+  double* resid;   // [P][nev]
+  int* nconv;      // [P]
+  int* nops;       // [P]
+  double2* X;      // [nev][P][S N] or null
+};
+hipError_t launch_evp(const PencilArgs& a, double tau, int nev, int ncv, int max_ops, double tol,
+                      const double* Lf, const uint8_t* sl, const double* Uf, double* V,
+                      const EvpOut& o, hipStream_t st);
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
                         const double* Uf, void* X, hipStream_t st);
 // Mixed-precision solve with one FP64 refinement: FP32 sweeps on the FP32

@@ -217,6 +217,8 @@ struct stau_pencils {
     int64_t stamp = 0;
   } slot[2], slotT[2];    // slotT: factors of the transposed matrices (adjoint)
   FactorSlot evp;         // factors of tau M~ + L~ + L~' (linear stability), whole-band layout
+  double* evp_V = nullptr;  // Krylov bases of the stability solver, P (ncv + 1) n doubles
+  size_t evp_V_bytes = 0;
   PencilArgs paT{};       // band description of the transposed system
   // two-block solve of the forward system (FP64, 2-D, at most two blocks per
   // compute unit): leading / trailing block descriptions
@@ -554,6 +556,7 @@ static void free_pencils(stau_pencils* p) {
       f = stau_pencils::FactorSlot{};
     }
   hipFree(p->tpl);
+  hipFree(p->evp_V);
   hipFree(p->sing);
   hipFree(p->flag);
   hipFree(p->scratch);
@@ -639,7 +642,8 @@ static hipError_t alloc_slot2(stau_pencils::FactorSlot& f, const PencilArgs& pt,
 
 static bool window_widths(PencilArgs& pa) {
   pa.FW = pa.kl + 1 <= 8 ? 8 : (pa.kl + 1 <= 16 ? 16 : 32);
-  pa.BW = (pa.kl + pa.ku + 1 <= 32) ? 32 : 64;
+  // backward windows of 32, 48 or 64 rows: the stored U columns are BW wide
+  pa.BW = pa.kl + pa.ku + 1 <= 32 ? 32 : (pa.kl + pa.ku + 1 <= 48 ? 48 : 64);
   return pa.kl + 1 <= 32 && pa.kl + pa.ku + 1 <= 64;
 }
 
@@ -1278,11 +1282,16 @@ int stau_lbvp(stau_pencils* pen, const void* F, void* X, void* stream) {
   return STAU_OK;
 }
 
-int stau_evp(stau_pencils* pen, double tau, int iters, double* sigma, double* resid, void* X,
-             void* stream) {
-  if (!pen || !sigma || !resid) return fail(STAU_EINVAL, "null argument");
+int stau_evp(stau_pencils* pen, double tau, int nev, int ncv, int max_ops, double tol, double* sigma,
+             double* resid, int32_t* nconv, int32_t* nops, void* X, void* stream) {
+  if (!pen) return fail(STAU_EINVAL, "null argument");
+  if (nev < 1 || nev > 16) return fail(STAU_EINVAL, "nev must be in [1, 16]");
+  if (!sigma || !resid || !nconv) return fail(STAU_EINVAL, "null argument");
   if (!std::isfinite(tau)) return fail(STAU_EINVAL, "non-finite shift");
-  if (iters < 1 || iters > 100000) return fail(STAU_EINVAL, "iters must be in [1, 100000]");
+  if (ncv < nev + 2 || ncv > 32 || ncv > pen->pa.n)
+    return fail(STAU_EINVAL, "ncv must be in [nev + 2, 32] and at most the pencil size");
+  if (max_ops < ncv || max_ops > 1000000) return fail(STAU_EINVAL, "max_ops must be in [ncv, 1000000]");
+  if (!(tol > 0.0 && tol < 1.0)) return fail(STAU_EINVAL, "tol must be in (0, 1)");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(pen->dom->d.device));
   PencilArgs pe = pen->pa;
@@ -1293,6 +1302,18 @@ int stau_evp(stau_pencils* pen, double tau, int iters, double* sigma, double* re
     hipError_t e = alloc_slot(f, pe, &bytes);
     if (e != hipSuccess) return fail(STAU_ENOMEM, "factor allocation failed: %s", hipGetErrorString(e));
     pen->ws_bytes += (int64_t)bytes;
+  }
+  const size_t vbytes = (size_t)pe.P * (size_t)(ncv + 1) * (size_t)pe.n * sizeof(double);
+  if (pen->evp_V_bytes < vbytes) {
+    HIP_TRY(hipStreamSynchronize(st));
+    if (pen->evp_V) (void)hipFree(pen->evp_V);
+    pen->ws_bytes -= (int64_t)pen->evp_V_bytes;
+    pen->evp_V = nullptr;
+    pen->evp_V_bytes = 0;
+    hipError_t e = hipMalloc((void**)&pen->evp_V, vbytes);
+    if (e != hipSuccess) return fail(STAU_ENOMEM, "Krylov basis allocation failed: %s", hipGetErrorString(e));
+    pen->evp_V_bytes = vbytes;
+    pen->ws_bytes += (int64_t)vbytes;
   }
   if (!f.valid || f.a0 != tau) {
     f.valid = false;
@@ -1310,7 +1331,10 @@ int stau_evp(stau_pencils* pen, double tau, int iters, double* sigma, double* re
     f.a0 = tau;
     f.b0 = 1.0;
   }
-  HIP_TRY(timed(pen, K_SOLVE, st, [&] { return launch_evp(pe, tau, iters, f.Lf, f.sl, f.Uf, sigma, resid, X, st); }));
+  const EvpOut o{(double2*)sigma, resid, (int*)nconv, (int*)nops, (double2*)X};
+  HIP_TRY(timed(pen, K_SOLVE, st, [&] {
+    return launch_evp(pe, tau, nev, ncv, max_ops, tol, f.Lf, f.sl, f.Uf, pen->evp_V, o, st);
+  }));
   return STAU_OK;
 }
 
