@@ -341,6 +341,138 @@ __global__ void __launch_bounds__(NT) xrow2_kernel(XformArgs a,
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3-D x pass with the eight field pairs transformed four at a time (two
+// batches of four sequences) and the two forward pairs as one batch: three
+// batched transforms per row instead of ten one-sequence transforms, a
+// quarter of the radix passes and barriers, with twice the threads per row.
+// Batch A holds (u, v), (w, b_x), (b_y, bz), (u_x, u_y): N_b completes and
+// N_u starts; batch B holds (uz, v_x), (v_y, vz), (w_x, w_y), (wz, -): N_u,
+// N_v and N_w complete.  Data [4][L] and twiddles [L] in LDS; the spectra of
+// batch B are loaded while batch A is transformed.  Same products and
+// outputs as xrow_kernel<3>.
+// ---------------------------------------------------------------------------
+template <int NT, int PTS, int MAXBF, typename T>
+__global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
+                                                   const typename V2<T>::type* __restrict__ G,
+                                                   typename V2<T>::type* __restrict__ H) {
+  extern __shared__ double2 smem[];
+  using cT = cpx<T>;
+  using S2 = typename V2<T>::type;
+  constexpr int KPT = (PTS + 2) / 3;  // half-spectrum entries per thread (Pa = L / 3)
+  cT* buf = (cT*)smem;                // four sequences of L points
+  const int r = blockIdx.x;
+  const int L = a.L, Pa = a.Pa, Px = a.Px;
+  const size_t R = (size_t)a.M * a.Ngy;
+  const int tid = threadIdx.x;
+  const cT* twg = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
+  cT* twl = buf + 4 * L;
+  for (int i = tid; i < L; i += NT) twl[i] = twg[i];
+  cT sa[4][KPT], sb[4][KPT];
+  auto fetch = [&](int slot, int k) {
+    int fa, da, fb, db;
+    pair_src<3>(k, fa, da, fb, db);
+    const S2* A = G + ((size_t)fa * R + r) * Px;
+    const S2* B = G + ((size_t)(fb < 0 ? fa : fb) * R + r) * Px;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int kk = tid + q * NT;
+      sa[slot][q] = mk<T>(0, 0);
+      sb[slot][q] = mk<T>(0, 0);
+      if (kk < Pa) {
+        sa[slot][q] = ldv<T>(A + kk);
+        if (da) sa[slot][q] = ikx<T>(a, kk, sa[slot][q]);
+        if (fb >= 0) {
+          sb[slot][q] = ldv<T>(B + kk);
+          if (db) sb[slot][q] = ikx<T>(a, kk, sb[slot][q]);
+        }
+      }
+    }
+  };
+  // Hermitian extension of the packed pair A + i B onto sequence `slot`
+  auto scatter = [&](int slot) {
+    cT* bb = buf + slot * L;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int kk = tid + q * NT;
+      if (kk < Pa) {
+        cT Ak = sa[slot][q], Bk = sb[slot][q];
+        if (kk == 0) {
+          Ak.y = 0;
+          Bk.y = 0;
+        }
+        bb[kk] = mk<T>(Ak.x - Bk.y, Ak.y + Bk.x);
+        if (kk > 0) bb[L - kk] = mk<T>(Ak.x + Bk.y, -Ak.y + Bk.x);
+      }
+    }
+    for (int k = Pa + tid; k <= L - Pa; k += NT) bb[k] = mk<T>(0, 0);
+  };
+
+  T u[PTS], v[PTS], w[PTS], nb[PTS], nu[PTS], nv[PTS], nw[PTS];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) fetch(s, s);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) scatter(s);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) fetch(s, 4 + s);
+  __syncthreads();
+  fft_lds<+1, MAXBF, T, false>(buf, L, 4, twl, tid, NT);
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    const int i = tid + q * NT;
+    if (i < L) {
+      const cT p0 = buf[i], p1 = buf[L + i], p2 = buf[2 * L + i], p3 = buf[3 * L + i];
+      u[q] = p0.x;
+      v[q] = p0.y;
+      w[q] = p1.x;
+      nb[q] = -(u[q] * p1.y + v[q] * p2.x + w[q] * p2.y);
+      nu[q] = -(u[q] * p3.x + v[q] * p3.y);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) scatter(s);
+  __syncthreads();
+  fft_lds<+1, MAXBF, T, false>(buf, L, 4, twl, tid, NT);
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    const int i = tid + q * NT;
+    if (i < L) {
+      const cT p4 = buf[i], p5 = buf[L + i], p6 = buf[2 * L + i], p7 = buf[3 * L + i];
+      nu[q] -= w[q] * p4.x;
+      nv[q] = -(u[q] * p4.y + v[q] * p5.x + w[q] * p5.y);
+      nw[q] = -(u[q] * p6.x + v[q] * p6.y + w[q] * p7.x);
+    }
+  }
+  __syncthreads();
+  // forward: sequence 0 = N_b + i N_u, sequence 1 = N_v + i N_w
+#pragma unroll
+  for (int q = 0; q < PTS; ++q) {
+    const int i = tid + q * NT;
+    if (i < L) {
+      buf[i] = mk<T>(nb[q], nu[q]);
+      buf[L + i] = mk<T>(nv[q], nw[q]);
+    }
+  }
+  __syncthreads();
+  fft_lds<-1, MAXBF, T, false>(buf, L, 2, twl, tid, NT);
+  const T invL = (T)1 / (T)L;
+  const T hf = (T)0.5;
+  for (int k = tid; k < Px; k += NT) {
+#pragma unroll
+    for (int sq = 0; sq < 2; ++sq) {
+      cT A = mk<T>(0, 0), Bv = mk<T>(0, 0);
+      if (k < Pa) {
+        const cT Zk = buf[sq * L + k], Zm = buf[sq * L + (k == 0 ? 0 : L - k)];
+        A = mk<T>(hf * (Zk.x + Zm.x) * invL, hf * (Zk.y - Zm.y) * invL);
+        Bv = mk<T>(hf * (Zk.y + Zm.y) * invL, -hf * (Zk.x - Zm.x) * invL);
+      }
+      stv<T>(H + ((size_t)(2 * sq) * R + r) * Px + k, A);
+      stv<T>(H + ((size_t)(2 * sq + 1) * R + r) * Px + k, Bv);
+    }
+  }
+}
+
 template <int DIM, int NT, int PTS, int MAXBF, typename T>
 static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipStream_t st) {
   using S2 = typename V2<T>::type;
@@ -362,6 +494,18 @@ static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipS
       auto fn = split ? xrow2_kernel<NT, PTS, 2 * MAXBF, T, true> : xrow2_kernel<NT, PTS, 2 * MAXBF, T, false>;
       allow_lds((const void*)fn, lds2);
       hipLaunchKernelGGL(fn, grid, dim3(NT), lds2, st, a, (const S2*)G, (S2*)H);
+      return hipGetLastError();
+    }
+  }
+  // 3-D: pairs four at a time, with twice the threads (each thread half the
+  // points), when four sequences and the twiddles fit 64 KB
+  if constexpr (DIM == 3 && NT <= 512) {
+    constexpr int PTS3 = (PTS + 1) / 2;
+    const size_t lds3 = (size_t)5 * a.L * sizeof(S2);
+    if (lds3 <= 64 * 1024 && a.L <= 2 * NT * PTS3) {
+      auto fn = xrow3_kernel<2 * NT, PTS3, 2 * MAXBF, T>;
+      allow_lds((const void*)fn, lds3);
+      hipLaunchKernelGGL(fn, grid, dim3(2 * NT), lds3, st, a, (const S2*)G, (S2*)H);
       return hipGetLastError();
     }
   }
