@@ -204,6 +204,88 @@ __device__ __forceinline__ void fft_lds(cpx<T>* buf, int M, int batch, const cpx
 }
 
 // ---------------------------------------------------------------------------
+// The same transform for a length M known at compile time: the radix plan is
+// resolved by the templates and every pass's butterfly indices divide by
+// constants (shifts and multiply-highs instead of the integer division
+// sequences the runtime version issues per butterfly).  MC = 0 selects the
+// runtime version.
+// ---------------------------------------------------------------------------
+template <int R, int DIR, int MAXBF, int M, int NS, typename T>
+__device__ __forceinline__ void stockham_pass_c(cpx<T>* buf, int batch, const cpx<T>* __restrict__ tw,
+                                                int tid, int nt) {
+  constexpr int MR = M / R, TSTR = M / (NS * R);
+  const int nbf = batch * MR;
+  cpx<T> v[MAXBF][R];
+#pragma unroll
+  for (int b = 0; b < MAXBF; ++b) {
+    const int bf = tid + b * nt;
+    if (bf < nbf) {
+      const int s = bf / MR, j = bf - s * MR;
+      const cpx<T>* src = buf + s * M + j;
+      const int jm = j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = src[r * MR];
+      cpx<T> w[R];
+      w[1] = tw[jm * TSTR];
+      if constexpr (R >= 3) w[2] = cmul(w[1], w[1]);
+      if constexpr (R >= 4) w[3] = cmul(w[1], w[2]);
+      if constexpr (R == 8) {
+        w[4] = cmul(w[2], w[2]);
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+      }
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[b][r] = DIR < 0 ? cmul(v[b][r], w[r]) : cmulc(v[b][r], w[r]);
+      dftR<R, DIR>(v[b]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXBF; ++b) {
+    const int bf = tid + b * nt;
+    if (bf < nbf) {
+      const int s = bf / MR, j = bf - s * MR;
+      const int jm = j % NS;
+      cpx<T>* dst = buf + s * M + (j / NS) * NS * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * NS] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
+// passes for the part M / NS not yet transformed, in the order of fft_lds
+template <int M, int NS, int DIR, int MAXBF, typename T, bool R8>
+__device__ __forceinline__ void fft_passes_c(cpx<T>* buf, int batch, const cpx<T>* __restrict__ tw, int tid,
+                                             int nt) {
+  constexpr int rem = M / NS;
+  if constexpr (rem > 1) {
+    constexpr int lg = ilog2c(rem);
+    constexpr int R = rem % 3 == 0 ? 3
+                      : R8         ? (lg >= 3 ? 8 : (lg == 2 ? 4 : 2))
+                      : (lg & 1)   ? (lg >= 3 ? 8 : 2)
+                                   : 4;
+    constexpr int BF = R == 3 ? (MAXBF * 4 + 2) / 3 : R == 8 ? (MAXBF + 1) / 2 : R == 4 ? MAXBF : MAXBF * 2;
+    stockham_pass_c<R, DIR, BF, M, NS, T>(buf, batch, tw, tid, nt);
+    fft_passes_c<M, NS * R, DIR, MAXBF, T, R8>(buf, batch, tw, tid, nt);
+  }
+}
+
+template <int MC, int DIR, int MAXBF, typename T, bool R8 = true>
+__device__ __forceinline__ void fft_lds_c(cpx<T>* buf, int M, int batch, const cpx<T>* __restrict__ tw, int tid,
+                                          int nt) {
+  if constexpr (MC > 0) {
+    static_assert(MC % 9 != 0, "at most one factor 3");
+    fft_passes_c<MC, 1, DIR, MAXBF, T, R8>(buf, batch, tw, tid, nt);
+  } else {
+    fft_lds<DIR, MAXBF, T, R8>(buf, M, batch, tw, tid, nt);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Pencil system layout (2-D: S = 7, 3-D: S = 9).
 //  variables per mode (column order):  2-D (w, b, u, p, bz, uz, wz)
 //                                      3-D (w, b, u, v, p, bz, uz, vz, wz)

@@ -239,6 +239,195 @@ __device__ __forceinline__ void sweep_backward_staged(T* b, const T* __restrict_
   }
 }
 
+// Both real parts of one pencil in one wavefront: the right-hand sides b0
+// (real part) and b1 (imaginary part) share the stored factors, so each
+// staged unit, slot word and LDS read of a column serves two independent
+// update chains, whose instructions interleave: the latency of one chain's
+// lane read and fused multiply-add is covered by the other's.  Staging as in
+// the one-vector sweeps (K units in flight); the incoming rows are read
+// from LDS G = 8 columns ahead.
+template <typename T, int FW, int SU, int K>
+__device__ __forceinline__ void sweep_forward_pair(T* b0, T* b1, const T* __restrict__ Lp,
+                                                   const uint32_t* __restrict__ sw, int nch, int lane,
+                                                   T* st) {
+  constexpr int CH = kCH, G = 8, R = kSR, UPC = CH / SU;
+  static_assert(CH % SU == 0 && UPC % 2 == 0 && UPC % K == 0 && K >= 2 && R <= SU &&
+                    CH % G == 0 && FW <= 32,
+                "sweep geometry");
+  constexpr int FB = SU * FW * (int)sizeof(T);
+  constexpr int SWU = SU / 4;
+  const int nu = nch * UPC;
+  const int lf = lane & (FW - 1);
+  UnitRegs<FB> r[K];
+  uint32_t swr[K];
+  auto load_unit = [&](int k, int u) {
+    r[k].load(Lp + (size_t)u * SU * FW, lane);
+    swr[k] = sw[u * SWU + (lane & (SWU - 1))];
+  };
+  load_unit(0, 0);
+#pragma unroll
+  for (int u = 1; u < K; ++u) load_unit(u, u < nu ? u : nu - 1);
+  r[0].store(st, lane);
+  uint32_t wnx[SWU], wcur[SWU];
+#pragma unroll
+  for (int i = 0; i < SWU; ++i) wnx[i] = (uint32_t)__builtin_amdgcn_readlane(swr[0], i);
+  load_unit(0, K < nu ? K : nu - 1);
+  T ring[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) ring[k] = st[k * FW + lf];
+  T w0 = lane < FW ? b0[lane] : (T)0, w1 = lane < FW ? b1[lane] : (T)0;
+  for (int c = 0; c < nch; ++c) {
+    const int j0 = c * CH;
+    T* yo0 = b0 + j0;
+    T* yo1 = b1 + j0;
+    T n0[2][G], n1[2][G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      n0[0][k] = yo0[k + FW];
+      n1[0][k] = yo1[k + FW];
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      pin(n0[0][k]);
+      pin(n1[0][k]);
+    }
+    uint32_t word = 0;
+    T ya0 = (T)0, ya1 = (T)0;  // lane t: y of column j0 + t
+    static_for<0, CH / G>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
+      if (g + 1 < CH / G) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          n0[(g + 1) & 1][k] = yo0[(g + 1) * G + k + FW];
+          n1[(g + 1) & 1][k] = yo1[(g + 1) * G + k + FW];
+        }
+      }
+      static_for<0, G>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int t = g * G + k;
+        if constexpr (t % SU == 0) {
+          const int vk = c * UPC + t / SU + 1 + K;
+          constexpr int rs = (t / SU + 1) % K;
+          asm volatile("" : "+v"(swr[rs]));
+#pragma unroll
+          for (int i = 0; i < SWU; ++i) {
+            wcur[i] = wnx[i];
+            wnx[i] = (uint32_t)__builtin_amdgcn_readlane(swr[rs], i);
+          }
+          r[rs].store(st + ((t / SU + 1) & 1) * SU * FW, lane);
+          load_unit(rs, vk < nu ? vk : nu - 1);
+        }
+        if constexpr ((t & 3) == 0) word = wcur[(t % SU) >> 2];
+        const int s = (word >> (8 * (t & 3))) & 0xff;
+        const T y0 = readlane_t(w0, s), y1 = readlane_t(w1, s);
+        put_lane<t>(ya0, y0);
+        put_lane<t>(ya1, y1);
+        const T l = ring[t % R];
+        constexpr int tn = t + R;
+        ring[t % R] = st[((tn / SU) & 1) * SU * FW + (tn % SU) * FW + lf];
+        const bool in = __builtin_amdgcn_inverse_ballot_w64(1ull << s);
+        const T ws0 = in ? n0[g & 1][k] : w0;
+        const T ws1 = in ? n1[g & 1][k] : w1;
+        w0 = fma(-l, y0, ws0);
+        w1 = fma(-l, y1, ws1);
+      });
+      if (g + 1 < CH / G) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          pin(n0[(g + 1) & 1][k]);
+          pin(n1[(g + 1) & 1][k]);
+        }
+      }
+    });
+    yo0[lane] = ya0;
+    yo1[lane] = ya1;
+  }
+}
+
+template <typename T, int BW, int SU, int K>
+__device__ __forceinline__ void sweep_backward_pair(T* b0, T* b1, const T* __restrict__ Up, int nch,
+                                                    int lane, T* st) {
+  constexpr int CH = kCH, G = 8, R = kSR, UPC = CH / SU;
+  static_assert(CH % SU == 0 && UPC % 2 == 0 && UPC % K == 0 && K >= 2 && R <= SU &&
+                    CH % G == 0 && BW % 16 == 0 && BW <= 64,
+                "sweep geometry");
+  constexpr bool kDiv = CH % BW == 0;
+  constexpr int UB = SU * BW * (int)sizeof(T);
+  const int npad = nch * CH, nu = nch * UPC;
+  const int lb = lane % BW;
+  UnitRegs<UB> r[K];
+  r[0].load(Up + (size_t)(nu - 1) * SU * BW, lane);
+#pragma unroll
+  for (int u = 1; u < K; ++u) r[u].load(Up + (size_t)(u < nu ? nu - 1 - u : 0) * SU * BW, lane);
+  r[0].store(st, lane);
+  r[0].load(Up + (size_t)(K < nu ? nu - 1 - K : 0) * SU * BW, lane);
+  T ring[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) ring[k] = st[(SU - 1 - k) * BW + lb];
+  const int r0 = window_start_row<BW>(npad, lb);
+  T w0 = b0[r0], w1 = b1[r0];
+  for (int c = nch - 1; c >= 0; --c) {
+    const int j0 = c * CH;
+    const int s0 = kDiv ? 0 : j0 % BW;
+    T* xo0 = b0 + j0;
+    T* xo1 = b1 + j0;
+    constexpr int NG = CH / G;
+    T n0[2][G], n1[2][G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      n0[(NG - 1) & 1][k] = xo0[(NG - 1) * G + k - BW];
+      n1[(NG - 1) & 1][k] = xo1[(NG - 1) * G + k - BW];
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      pin(n0[(NG - 1) & 1][k]);
+      pin(n1[(NG - 1) & 1][k]);
+    }
+    T xa0 = (T)0, xa1 = (T)0;  // lane t: x of column j0 + t
+    static_for<0, NG>([&](auto gc) {
+      constexpr int g = NG - 1 - decltype(gc)::value;
+      if (g > 0) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          n0[(g - 1) & 1][k] = xo0[(g - 1) * G + k - BW];
+          n1[(g - 1) & 1][k] = xo1[(g - 1) * G + k - BW];
+        }
+      }
+      static_for<0, G>([&](auto kc) {
+        constexpr int k = G - 1 - decltype(kc)::value;
+        constexpr int t = g * G + k;
+        constexpr int q = CH - 1 - t;
+        if constexpr (q % SU == 0) {
+          const int vk = UPC * (nch - 1 - c) + q / SU + 1 + K;
+          constexpr int rs = (q / SU + 1) % K;
+          r[rs].store(st + ((q / SU + 1) & 1) * SU * BW, lane);
+          r[rs].load(Up + (size_t)(vk < nu ? nu - 1 - vk : 0) * SU * BW, lane);
+        }
+        const int sj = kDiv ? t % BW : window_lane<BW>(s0, t);
+        const uint64_t msj = window_lanes<BW>(sj);
+        const T u = ring[q % R];
+        constexpr int qn = q + R;
+        ring[q % R] = st[((qn / SU) & 1) * SU * BW + (SU - 1 - qn % SU) * BW + lb];
+        const T x0 = readlane_t(w0 * u, sj), x1 = readlane_t(w1 * u, sj);
+        put_lane<t>(xa0, x0);
+        put_lane<t>(xa1, x1);
+        const bool in = __builtin_amdgcn_inverse_ballot_w64(msj);
+        w0 = in ? n0[g & 1][k] : fma(-u, x0, w0);
+        w1 = in ? n1[g & 1][k] : fma(-u, x1, w1);
+      });
+      if (g > 0) {
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          pin(n0[(g - 1) & 1][k]);
+          pin(n1[(g - 1) & 1][k]);
+        }
+      }
+    });
+    xo0[lane] = xa0;
+    xo1[lane] = xa1;
+  }
+}
+
 // Staged sweeps of the single-block solve: the forward sweep keeps its
 // register ring of global loads (faster at one wavefront per SIMD), the
 // backward sweep stages its BW-wide columns in units of 32.
@@ -393,6 +582,52 @@ __global__ void __launch_bounds__(4 * kWave) solve_kernel(PencilArgs a, int plau
     write_state(a, bre, bim, X + (size_t)p * S * N, tid & (2 * kWave - 1), 2 * kWave);
   else if (live)
     zero_pencils(X, p, p + 1, S * N, tid & (2 * kWave - 1), 2 * kWave);
+}
+
+// ---------------------------------------------------------------------------
+// Solve with both real parts of a pencil in one wavefront (sweep_*_pair):
+// two pencils per block of two wavefronts, wave q for pencil 2 blockIdx.x + q.
+// For launches with many blocks per compute unit: half the waves of
+// solve_kernel, each with two update chains, and one factor stage per pencil.
+// ---------------------------------------------------------------------------
+template <int FW, int BW>
+__global__ void __launch_bounds__(2 * kWave) solve_pair_kernel(PencilArgs a, int plaunch,
+                                                               const double2* __restrict__ Bev,
+                                                               const double* __restrict__ Lf,
+                                                               const uint8_t* __restrict__ sl,
+                                                               const double* __restrict__ Uf,
+                                                               double2* __restrict__ X) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int q = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int p = blockIdx.x * 2 + q;
+  const SysDesc& d = a.desc;
+  const int N = d.N, S = d.S, ne = d.ne;
+  if (blockIdx.x == 0 && plaunch < a.P) zero_pencils(X, plaunch, a.P, S * N, tid, 2 * kWave);
+  const bool live = p < plaunch;
+  const bool act = live && pencil_active(a, p);
+  const int npad = a.nst, nch = npad / kCH;
+  const int span = BW + npad + FW;
+  double* bre = lds + (size_t)q * 2 * span + BW;
+  double* bim = bre + span;
+  if (act) {
+    const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
+    const double2* Bp = Bev + (size_t)p * ne * N;
+    build_rhs<double>(a, pc, Bp, 0, bre, nullptr, BW, FW, npad, lane);
+    build_rhs<double>(a, pc, Bp, 1, bim, nullptr, BW, FW, npad, lane);
+    const double* Lp = Lf + (size_t)p * npad * FW;
+    const uint32_t* swp = (const uint32_t*)(sl + (size_t)p * npad);
+    const double* Up = Uf + (size_t)p * npad * BW;
+    double* stg = lds + (size_t)4 * span + (size_t)q * (stage_bytes<double, FW, BW, su3<double>()>() / 8);
+    sweep_forward_pair<double, FW, su3<double>(), 8>(bre, bim, Lp, swp, nch, lane, stg);
+    sweep_backward_pair<double, BW, su3<double>(), 8>(bre, bim, Up, nch, lane, stg);
+  }
+  __syncthreads();
+  if (act)
+    write_state(a, bre, bim, X + (size_t)p * S * N, lane, kWave);
+  else if (live)
+    zero_pencils(X, p, p + 1, S * N, lane, kWave);
 }
 
 // ---------------------------------------------------------------------------
@@ -1104,6 +1339,15 @@ static hipError_t launch_solve_t(const PencilArgs& a, const void* Bev, const dou
           hipSuccess &&
       g.blocks > cus) {
     const size_t lds2 = 2 * per_pencil + (size_t)4 * stage_bytes<double, FW, BW, su3<double>()>();
+    const size_t ldsp = 2 * per_pencil + (size_t)2 * stage_bytes<double, FW, BW, su3<double>()>();
+    // both real parts per wavefront where three blocks of two pencils fit a
+    // unit (256 x 256 x 128: 5.06 -> 4.91 ms; 4096 x 64: 97.5 -> 93.1 us)
+    if (2 * ldsp <= (size_t)lds_cu) {
+      allow_lds((const void*)solve_pair_kernel<FW, BW>, ldsp);
+      hipLaunchKernelGGL((solve_pair_kernel<FW, BW>), dim3(g.blocks), dim3(2 * kWave), ldsp, st, a,
+                         g.plaunch, (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+      return hipGetLastError();
+    }
     if (2 * lds2 <= (size_t)lds_cu) {
       go(solve_kernel<FW, BW, 2>, lds2);
       return hipGetLastError();

@@ -19,13 +19,15 @@ namespace stau {
 // Backward z (DCT-III with padding N -> M): g_j = sum_{n<N} c_n T_n(z_j)
 // for every field of `fl` and TP pencils per block.
 // ---------------------------------------------------------------------------
-template <int MAXBF, typename T, int EPT = kZEpt>
+// MC > 0: M = MC fixed at compile time (constant divisors in the index math).
+template <int MAXBF, typename T, int EPT = kZEpt, int MC = 0>
 __global__ void __launch_bounds__(kZThreads) zb_kernel(XformArgs a, FieldList fl,
                                                        const double2* __restrict__ X,
-                                                       typename V2<T>::type* __restrict__ G, int TP) {
+                                                       typename V2<T>::type* __restrict__ G, int TPr) {
   extern __shared__ double2 smem[];
   using cT = cpx<T>;
-  const int M = a.M, N = a.N, S = fl.src_S ? fl.src_S : a.S;
+  const int M = MC > 0 ? MC : a.M, N = a.N, S = fl.src_S ? fl.src_S : a.S;
+  const int TP = MC > 0 ? EPT * kZThreads / MC : TPr;
   cT* buf = (cT*)smem;
   cT* twl = buf + EPT * kZThreads;  // FFT twiddles
   cT* dcl = twl + M;      // DCT twiddles
@@ -34,6 +36,7 @@ __global__ void __launch_bounds__(kZThreads) zb_kernel(XformArgs a, FieldList fl
   const int var = fl.var[f], der = fl.deriv[f];
   const double wfac = fl.wmode ? 2.0 / (double)M : 1.0;  // (2 - delta_n0) / M, n > 0
   const int tid = threadIdx.x;
+  const PencilBase pb = pencil_base(a, p0);
   stage_z_tables<T>(a, twl, dcl, M, tid);
   // c_n and c_{M-n} of each owned point (zero outside the stored modes)
   double2 ya[EPT], yb[EPT];
@@ -44,7 +47,7 @@ __global__ void __launch_bounds__(kZThreads) zb_kernel(XformArgs a, FieldList fl
     const int p = p0 + s;
     ya[it] = make_double2(0.0, 0.0);
     yb[it] = make_double2(0.0, 0.0);
-    if (active(a, p)) {
+    if (active_at(a, pb, s)) {
       const double2* col = X + ((size_t)p * S + var) * N;
       if (nn < N) ya[it] = col[nn];
       if (nn > 0 && M - nn < N) yb[it] = col[M - nn];
@@ -55,12 +58,11 @@ __global__ void __launch_bounds__(kZThreads) zb_kernel(XformArgs a, FieldList fl
   for (int it = 0; it < EPT; ++it) {
     const int idx = tid + it * kZThreads;
     const int s = idx / M, nn = idx - s * M;
-    const int p = p0 + s;
     cT z = mk<T>(0, 0);
-    if (active(a, p)) {
+    if (active_at(a, pb, s)) {
       double kk = 0.0;
-      if (der == 1) kk = kx_of(a, p);
-      if (der == 2) kk = ky_of(a, p);
+      if (der == 1) kk = kx_at(a, pb, s);
+      if (der == 2) kk = ky_at(a, pb, s);
       auto Yp = [&](double2 v, int m) -> cd {
         cd c = mk(v.x, v.y);
         if (der) c = mk(-kk * c.y, kk * c.x);  // i k c
@@ -81,7 +83,7 @@ __global__ void __launch_bounds__(kZThreads) zb_kernel(XformArgs a, FieldList fl
     buf[idx] = z;
   }
   __syncthreads();
-  fft_lds<+1, MAXBF>(buf, M, TP, (const cT*)twl, tid, kZThreads);
+  fft_lds_c<MC, +1, MAXBF>(buf, M, TP, (const cT*)twl, tid, kZThreads);
 #pragma unroll
   for (int it = 0; it < EPT; ++it) {
     const int idx = tid + it * kZThreads;
@@ -103,19 +105,22 @@ __global__ void __launch_bounds__(kZThreads) zb_kernel(XformArgs a, FieldList fl
 //   history hist_cur[p][0][e][n] = F~_n, hist_cur[p][1][e][n] = MX_n.
 // mode 2: right-hand side of a Runge-Kutta stage from F~_n and MX_n (rk_rhs).
 // ---------------------------------------------------------------------------
-template <int MAXBF, int MAXIT, typename T, bool RK = false, int EPT = kZEpt>
+// MC, NC > 0: M and N fixed at compile time (constant divisors).
+template <int MAXBF, int MAXIT, typename T, bool RK = false, int EPT = kZEpt, int MC = 0, int NC = 0>
 __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
                                                        const typename V2<T>::type* __restrict__ H,
-                                                       double2* __restrict__ out, RhsArgs r, int TP) {
+                                                       double2* __restrict__ out, RhsArgs r, int TPr) {
   extern __shared__ double2 smem[];
   using cT = cpx<T>;
-  const int M = a.M, N = a.N, ne = a.ne;
+  const int M = MC > 0 ? MC : a.M, N = NC > 0 ? NC : a.N, ne = a.ne;
+  const int TP = MC > 0 ? EPT * kZThreads / MC : TPr;
   cT* buf = (cT*)smem;
   cT* twl = buf + EPT * kZThreads;
   cT* dcl = twl + M;
   const int e = blockIdx.y;
   const int p0 = blockIdx.x * TP;
   const int tid = threadIdx.x, nt = kZThreads;
+  const PencilBase pb = pencil_base(a, p0);
   if (r.mode >= 1 && a.dim == 2 && blockIdx.x == 0) {
     // pencils beyond the grid (2-D, p >= Pa): inactive, zero right-hand side
     // (and history)
@@ -150,7 +155,7 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
     }
   }
   __syncthreads();
-  fft_lds<-1, MAXBF>(buf, M, TP, (const cT*)twl, tid, nt);
+  fft_lds_c<MC, -1, MAXBF>(buf, M, TP, (const cT*)twl, tid, nt);
   cT c[MAXIT];
   const T invM = (T)1 / (T)M;
 #pragma unroll
@@ -192,7 +197,7 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
       if (r.mode >= 1 && idx < TP * N) {
         const int s = idx / N, nn = idx - s * N;
         const int p = p0 + s;
-        if (active(a, p) && nn <= N - 2) {
+        if (active_at(a, pb, s) && nn <= N - 2) {
           const double2* xc = r.Xprev + ((size_t)p * a.S + (e + 1)) * N;
           x0[u] = xc[nn];
           if (nn + 2 < N) x2[u] = xc[nn + 2];
@@ -222,7 +227,7 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
         continue;
       }
       cd Ft = mk(0.0, 0.0), MX = mk(0.0, 0.0), B = mk(0.0, 0.0);
-      if (active(a, p) && nn <= N - 2) {
+      if (active_at(a, pb, s) && nn <= N - 2) {
         const double cnn = nn == 0 ? 1.0 : 0.5;
         Ft = scale(cget(nn), cnn);
         if (nn + 2 < N) Ft = Ft - scale(cget(nn + 2), 0.5);
@@ -259,16 +264,18 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
 // ys (0: the default above) replaces the output scale: 1 / Ngy of the forward
 // transform, 1 of the backward one (the adjoint grid transforms use the
 // other's).
-template <int DIR, int MAXBF, typename T>
+// NGC > 0: Ngy = NGC fixed at compile time, TK = 3072 / NGC.
+template <int DIR, int MAXBF, typename T, int NGC = 0>
 __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
                                                     const typename V2<T>::type* __restrict__ In,
-                                                    typename V2<T>::type* __restrict__ Out, int TK,
+                                                    typename V2<T>::type* __restrict__ Out, int TKr,
                                                     double ys) {
   extern __shared__ double2 smem[];
   using cT = cpx<T>;
   cT* buf = (cT*)smem;
+  const int TK = NGC > 0 ? 3072 / NGC : TKr;
   const int f = blockIdx.z, jz = blockIdx.y, k0 = blockIdx.x * TK;
-  const int Ny = a.Ny, Ng = a.Ngy, Px = a.Px, M = a.M, half = Ny / 2;
+  const int Ny = a.Ny, Ng = NGC > 0 ? NGC : a.Ngy, Px = a.Px, M = a.M, half = Ny / 2;
   const int tid = threadIdx.x, nt = blockDim.x;
   const size_t inRows = DIR > 0 ? Ny : Ng, outRows = DIR > 0 ? Ng : Ny;
   const typename V2<T>::type* src = In + ((size_t)f * M + jz) * inRows * Px;
@@ -295,9 +302,9 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
   }
   __syncthreads();
   if constexpr (sizeof(T) == 8)
-    fft_lds<DIR, MAXBF>(buf, Ng, TK, (const cT*)a.twy, tid, nt);
+    fft_lds_c<NGC, DIR, MAXBF>(buf, Ng, TK, (const cT*)a.twy, tid, nt);
   else
-    fft_lds<DIR, MAXBF>(buf, Ng, TK, (const cT*)a.twy32, tid, nt);
+    fft_lds_c<NGC, DIR, MAXBF>(buf, Ng, TK, (const cT*)a.twy32, tid, nt);
   if (DIR > 0) {
     for (int idx = tid; idx < TK * Ng; idx += nt) {
       const int l = idx / TK, s = idx - l * TK;
@@ -494,13 +501,22 @@ hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, voi
     allow_lds((const void*)kern, lds);
     hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a, fl, (const double2*)X, g, TP);
   };
-  if (fp32) {
-    if (dv == 2) go(zb_kernel<3, float, kZEpt / 2>, (float2*)G);
-    else go(zb_kernel<3, float>, (float2*)G);
-  } else {
-    if (dv == 2) go(zb_kernel<3, double, kZEpt / 2>, (double2*)G);
-    else go(zb_kernel<3, double>, (double2*)G);
-  }
+  // the workloads' dealiased lengths (Nz = 128, 256) with M fixed at compile time
+  auto pick = [&](auto tc, auto g) {
+    using TT = typename decltype(tc)::type;
+    if (a.M == 192) {
+      if (dv == 2) go(zb_kernel<3, TT, kZEpt / 2, 192>, g);
+      else go(zb_kernel<3, TT, kZEpt, 192>, g);
+    } else if (a.M == 384) {
+      if (dv == 2) go(zb_kernel<3, TT, kZEpt / 2, 384>, g);
+      else go(zb_kernel<3, TT, kZEpt, 384>, g);
+    } else {
+      if (dv == 2) go(zb_kernel<3, TT, kZEpt / 2>, g);
+      else go(zb_kernel<3, TT>, g);
+    }
+  };
+  if (fp32) pick(std::common_type<float>(), (float2*)G);
+  else pick(std::common_type<double>(), (double2*)G);
   return hipGetLastError();
 }
 
@@ -522,11 +538,20 @@ hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs
   };
   const float2* h32 = (const float2*)H;
   const double2* h64 = (const double2*)H;
+  // the workloads' (M, N) = (192, 128), (384, 256) with both fixed at compile time
   auto pick = [&](auto tc, auto rk, auto h) {
     using TT = typename decltype(tc)::type;
     constexpr bool RKv = decltype(rk)::value;
-    if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2>, h);
-    else go(zf_kernel<3, 12, TT, RKv>, h);
+    if (a.M == 192 && a.N == 128) {
+      if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2, 192, 128>, h);
+      else go(zf_kernel<3, 12, TT, RKv, kZEpt, 192, 128>, h);
+    } else if (a.M == 384 && a.N == 256) {
+      if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2, 384, 256>, h);
+      else go(zf_kernel<3, 12, TT, RKv, kZEpt, 384, 256>, h);
+    } else {
+      if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2>, h);
+      else go(zf_kernel<3, 12, TT, RKv>, h);
+    }
   };
   using tf = std::common_type<float>;
   using td = std::common_type<double>;
@@ -546,21 +571,25 @@ hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, voi
   const int TK = a.Ngy >= 3072 ? 1 : 3072 / a.Ngy;
   dim3 grid((a.Px + TK - 1) / TK, a.M, nf);
   const size_t lds = (size_t)TK * a.Ngy * (fp32 ? sizeof(float2) : sizeof(double2));
-  if (fp32) {
-    if (dir > 0)
-      hipLaunchKernelGGL((ypass_kernel<+1, 3, float>), grid, dim3(256), lds, st, a,
-                         (const float2*)In, (float2*)Out, TK, ys);
-    else
-      hipLaunchKernelGGL((ypass_kernel<-1, 3, float>), grid, dim3(256), lds, st, a,
-                         (const float2*)In, (float2*)Out, TK, ys);
-  } else {
-    if (dir > 0)
-      hipLaunchKernelGGL((ypass_kernel<+1, 3, double>), grid, dim3(256), lds, st, a,
-                         (const double2*)In, (double2*)Out, TK, ys);
-    else
-      hipLaunchKernelGGL((ypass_kernel<-1, 3, double>), grid, dim3(256), lds, st, a,
-                         (const double2*)In, (double2*)Out, TK, ys);
-  }
+  // Ny = 256 (384 padded points) with the length fixed at compile time
+  auto go = [&](auto kern, auto in, auto out) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a, in, out, TK, ys);
+  };
+  auto pick = [&](auto tc) {
+    using TT = typename decltype(tc)::type;
+    using S2 = typename V2<TT>::type;
+    const S2* in = (const S2*)In;
+    S2* out = (S2*)Out;
+    if (a.Ngy == 384) {
+      if (dir > 0) go(ypass_kernel<+1, 3, TT, 384>, in, out);
+      else go(ypass_kernel<-1, 3, TT, 384>, in, out);
+    } else {
+      if (dir > 0) go(ypass_kernel<+1, 3, TT>, in, out);
+      else go(ypass_kernel<-1, 3, TT>, in, out);
+    }
+  };
+  if (fp32) pick(std::common_type<float>());
+  else pick(std::common_type<double>());
   return hipGetLastError();
 }
 

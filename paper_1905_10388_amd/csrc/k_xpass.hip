@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(NT) xrow2_kernel(XformArgs a,
 // batch B are loaded while batch A is transformed.  Same products and
 // outputs as xrow_kernel<3>.
 // ---------------------------------------------------------------------------
-template <int NT, int PTS, int MAXBF, typename T>
+template <int NT, int PTS, int MAXBF, typename T, int LC>
 __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
                                                    const typename V2<T>::type* __restrict__ G,
                                                    typename V2<T>::type* __restrict__ H) {
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
   constexpr int KPT = (PTS + 2) / 3;  // half-spectrum entries per thread (Pa = L / 3)
   cT* buf = (cT*)smem;                // four sequences of L points
   const int r = blockIdx.x;
-  const int L = a.L, Pa = a.Pa, Px = a.Px;
+  const int L = LC > 0 ? LC : a.L, Pa = a.Pa, Px = a.Px;
   const size_t R = (size_t)a.M * a.Ngy;
   const int tid = threadIdx.x;
   const cT* twg = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
 #pragma unroll
   for (int s = 0; s < 4; ++s) fetch(s, 4 + s);
   __syncthreads();
-  fft_lds<+1, MAXBF, T, false>(buf, L, 4, twl, tid, NT);
+  fft_lds_c<LC, +1, MAXBF, T, false>(buf, L, 4, twl, tid, NT);
 #pragma unroll
   for (int q = 0; q < PTS; ++q) {
     const int i = tid + q * NT;
@@ -433,7 +433,7 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
 #pragma unroll
   for (int s = 0; s < 4; ++s) scatter(s);
   __syncthreads();
-  fft_lds<+1, MAXBF, T, false>(buf, L, 4, twl, tid, NT);
+  fft_lds_c<LC, +1, MAXBF, T, false>(buf, L, 4, twl, tid, NT);
 #pragma unroll
   for (int q = 0; q < PTS; ++q) {
     const int i = tid + q * NT;
@@ -455,7 +455,7 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
     }
   }
   __syncthreads();
-  fft_lds<-1, MAXBF, T, false>(buf, L, 2, twl, tid, NT);
+  fft_lds_c<LC, -1, MAXBF, T, false>(buf, L, 2, twl, tid, NT);
   const T invL = (T)1 / (T)L;
   const T hf = (T)0.5;
   for (int k = tid; k < Px; k += NT) {
@@ -503,7 +503,9 @@ static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipS
     constexpr int PTS3 = (PTS + 1) / 2;
     const size_t lds3 = (size_t)5 * a.L * sizeof(S2);
     if (lds3 <= 64 * 1024 && a.L <= 2 * NT * PTS3) {
-      auto fn = xrow3_kernel<2 * NT, PTS3, 2 * MAXBF, T>;
+      // the 256 x 256 workload's 384-point rows with their length fixed
+      auto fn = a.L == 384 && 2 * NT * PTS3 >= 384 ? xrow3_kernel<2 * NT, PTS3, 2 * MAXBF, T, 384>
+                                                   : xrow3_kernel<2 * NT, PTS3, 2 * MAXBF, T, 0>;
       allow_lds((const void*)fn, lds3);
       hipLaunchKernelGGL(fn, grid, dim3(2 * NT), lds3, st, a, (const S2*)G, (S2*)H);
       return hipGetLastError();

@@ -65,6 +65,49 @@ __device__ __forceinline__ bool active(const XformArgs& a, int p) {
   return ix < a.Pa && iy != a.Ny / 2;
 }
 
+// Pencil p0 + s of a block whose first pencil is p0, without an integer
+// division per element: (iy0, ix0) of p0 from one division, then s added to
+// ix0 with carries into iy.
+struct PencilBase {
+  int p0, iy0, ix0;
+};
+__device__ __forceinline__ PencilBase pencil_base(const XformArgs& a, int p0) {
+  PencilBase b{p0, 0, p0};
+  if (a.dim == 3) {
+    b.iy0 = p0 / a.Px;
+    b.ix0 = p0 - b.iy0 * a.Px;
+  }
+  return b;
+}
+__device__ __forceinline__ void pencil_xy(const XformArgs& a, const PencilBase& b, int s, int& ix, int& iy) {
+  ix = b.ix0 + s;
+  iy = b.iy0;
+  if (a.dim == 3)
+    while (ix >= a.Px) {
+      ix -= a.Px;
+      ++iy;
+    }
+}
+__device__ __forceinline__ bool active_at(const XformArgs& a, const PencilBase& b, int s) {
+  if (b.p0 + s >= a.P) return false;
+  if (a.dim == 2) return b.p0 + s < a.Pa;
+  int ix, iy;
+  pencil_xy(a, b, s, ix, iy);
+  return ix < a.Pa && iy != a.Ny / 2;
+}
+__device__ __forceinline__ double kx_at(const XformArgs& a, const PencilBase& b, int s) {
+  int ix, iy;
+  pencil_xy(a, b, s, ix, iy);
+  return a.two_pi_over_Lx * (double)ix;
+}
+__device__ __forceinline__ double ky_at(const XformArgs& a, const PencilBase& b, int s) {
+  if (a.dim == 2) return 0.0;
+  int ix, iy;
+  pencil_xy(a, b, s, ix, iy);
+  const int kyi = iy < (a.Ny + 1) / 2 ? iy : iy - a.Ny;
+  return a.two_pi_over_Ly * (double)kyi;
+}
+
 // ---------------------------------------------------------------------------
 // z transforms: TP pencils of M points per block of 256 threads, TP * M =
 // kZPts (z_tile), so every thread owns exactly kZPts / 256 points of the
