@@ -501,7 +501,7 @@ hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, voi
     allow_lds((const void*)kern, lds);
     hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a, fl, (const double2*)X, g, TP);
   };
-  // the workloads' dealiased lengths (Nz = 128, 256) with M fixed at compile time
+  // the workloads' dealiased lengths (Nz = 64, 128, 256) with M fixed at compile time
   auto pick = [&](auto tc, auto g) {
     using TT = typename decltype(tc)::type;
     if (a.M == 192) {
@@ -510,6 +510,9 @@ hipError_t launch_zb(const XformArgs& a, const FieldList& fl, const void* X, voi
     } else if (a.M == 384) {
       if (dv == 2) go(zb_kernel<3, TT, kZEpt / 2, 384>, g);
       else go(zb_kernel<3, TT, kZEpt, 384>, g);
+    } else if (a.M == 96) {
+      if (dv == 2) go(zb_kernel<3, TT, kZEpt / 2, 96>, g);
+      else go(zb_kernel<3, TT, kZEpt, 96>, g);
     } else {
       if (dv == 2) go(zb_kernel<3, TT, kZEpt / 2>, g);
       else go(zb_kernel<3, TT>, g);
@@ -538,7 +541,7 @@ hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs
   };
   const float2* h32 = (const float2*)H;
   const double2* h64 = (const double2*)H;
-  // the workloads' (M, N) = (192, 128), (384, 256) with both fixed at compile time
+  // the workloads' (M, N) = (96, 64), (192, 128), (384, 256) fixed at compile time
   auto pick = [&](auto tc, auto rk, auto h) {
     using TT = typename decltype(tc)::type;
     constexpr bool RKv = decltype(rk)::value;
@@ -548,6 +551,9 @@ hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs
     } else if (a.M == 384 && a.N == 256) {
       if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2, 384, 256>, h);
       else go(zf_kernel<3, 12, TT, RKv, kZEpt, 384, 256>, h);
+    } else if (a.M == 96 && a.N == 64) {
+      if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2, 96, 64>, h);
+      else go(zf_kernel<3, 12, TT, RKv, kZEpt, 96, 64>, h);
     } else {
       if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2>, h);
       else go(zf_kernel<3, 12, TT, RKv>, h);

@@ -55,7 +55,7 @@ __device__ __forceinline__ cpx<T> ikx(const XformArgs& a, int kk, cpx<T> c) {
   return mk<T>(-k * c.y, k * c.x);
 }
 
-template <int DIM, int NT, int PTS, int MAXBF, bool TWL, typename T, bool SPLIT = false>
+template <int DIM, int NT, int PTS, int MAXBF, bool TWL, typename T, bool SPLIT = false, int LC = 0>
 __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
                                                   const typename V2<T>::type* __restrict__ G,
                                                   typename V2<T>::type* __restrict__ H) {
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
   constexpr int NP = DIM == 2 ? 4 : 8;
   cT* buf = (cT*)smem;
   const int r = blockIdx.x;
-  const int L = a.L, Pa = a.Pa, Px = a.Px;
+  const int L = LC > 0 ? LC : a.L, Pa = a.Pa, Px = a.Px;
   const size_t R = (size_t)a.M * a.Ngy;
   const int tid = threadIdx.x;
   const cT* twg = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
     scatter();
     if (k + 1 < npr) fetch(pair_of(k + 1));
     __syncthreads();
-    fft_lds<+1, MAXBF, T, DIM == 2>(buf, L, 1, tw, tid, NT);
+    fft_lds_c<LC, +1, MAXBF, T, DIM == 2>(buf, L, 1, tw, tid, NT);
 #pragma unroll
     for (int q = 0; q < PTS; ++q) {
       const int i = tid + q * NT;
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
       if (i < L) buf[i] = mk<T>(ra[q], rb ? rb[q] : (T)0);
     }
     __syncthreads();
-    fft_lds<-1, MAXBF, T, DIM == 2>(buf, L, 1, tw, tid, NT);
+    fft_lds_c<LC, -1, MAXBF, T, DIM == 2>(buf, L, 1, tw, tid, NT);
     S2* Ha = H + ((size_t)ea * R + r) * Px;
     S2* Hb = H + ((size_t)(eb < 0 ? ea : eb) * R + r) * Px;
     for (int k = tid; k < Px; k += NT) {
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(NT) xrow_kernel(XformArgs a,
 // xrow_kernel<2>; SPLIT as there (part 0: pairs (0, 1), (2) and N_b, N_u;
 // part 1: pairs (0, 3) and N_w).
 // ---------------------------------------------------------------------------
-template <int NT, int PTS, int MAXBF, typename T, bool SPLIT>
+template <int NT, int PTS, int MAXBF, typename T, bool SPLIT, int LC = 0>
 __global__ void __launch_bounds__(NT) xrow2_kernel(XformArgs a,
                                                    const typename V2<T>::type* __restrict__ G,
                                                    typename V2<T>::type* __restrict__ H) {
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(NT) xrow2_kernel(XformArgs a,
   constexpr int KPT = (PTS + 2) / 3;  // half-spectrum entries per thread (Pa = L / 3)
   cT* buf = (cT*)smem;                // two sequences of L points
   const int r = blockIdx.x;
-  const int L = a.L, Pa = a.Pa, Px = a.Px;
+  const int L = LC > 0 ? LC : a.L, Pa = a.Pa, Px = a.Px;
   const size_t R = (size_t)a.M;
   const int tid = threadIdx.x;
   const cT* twg = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(NT) xrow2_kernel(XformArgs a,
       fetch(1, b11);
     }
     __syncthreads();
-    fft_lds<+1, MAXBF, T, true>(buf, L, k1 >= 0 ? 2 : 1, twl, tid, NT);
+    fft_lds_c<LC, +1, MAXBF, T, true>(buf, L, k1 >= 0 ? 2 : 1, twl, tid, NT);
 #pragma unroll
     for (int q = 0; q < PTS; ++q) {
       const int i = tid + q * NT;
@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(NT) xrow2_kernel(XformArgs a,
     }
   }
   __syncthreads();
-  fft_lds<-1, MAXBF, T, true>(buf, L, (f0 && f1) ? 2 : 1, twl, tid, NT);
+  fft_lds_c<LC, -1, MAXBF, T, true>(buf, L, (f0 && f1) ? 2 : 1, twl, tid, NT);
   const T invL = (T)1 / (T)L;
   const T hf = (T)0.5;
   S2* H0 = H + (size_t)r * Px;
@@ -491,7 +491,13 @@ static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipS
   if constexpr (DIM == 2) {
     const size_t lds2 = (size_t)3 * a.L * sizeof(S2);
     if (lds2 <= 80 * 1024) {
+      // 1536-point rows (Nx = 1024) with the length fixed at compile time
+      constexpr bool k1536 = NT * PTS >= 1536 && NT * PTS < 3072;
       auto fn = split ? xrow2_kernel<NT, PTS, 2 * MAXBF, T, true> : xrow2_kernel<NT, PTS, 2 * MAXBF, T, false>;
+      if constexpr (k1536) {
+        if (a.L == 1536)
+          fn = split ? xrow2_kernel<NT, PTS, 2 * MAXBF, T, true, 1536> : xrow2_kernel<NT, PTS, 2 * MAXBF, T, false, 1536>;
+      }
       allow_lds((const void*)fn, lds2);
       hipLaunchKernelGGL(fn, grid, dim3(NT), lds2, st, a, (const S2*)G, (S2*)H);
       return hipGetLastError();
@@ -508,6 +514,23 @@ static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipS
                                                    : xrow3_kernel<2 * NT, PTS3, 2 * MAXBF, T, 0>;
       allow_lds((const void*)fn, lds3);
       hipLaunchKernelGGL(fn, grid, dim3(2 * NT), lds3, st, a, (const S2*)G, (S2*)H);
+      return hipGetLastError();
+    }
+  }
+  // 2-D 6144-point rows (Nx = 4096) with the length fixed at compile time
+  if constexpr (DIM == 2 && NT * PTS >= 6144) {
+    if (a.L == 6144 && !twl) {
+      auto fn = split ? xrow_kernel<DIM, NT, PTS, MAXBF, false, T, true, 6144>
+                      : xrow_kernel<DIM, NT, PTS, MAXBF, false, T, false, 6144>;
+      allow_lds((const void*)fn, lds);
+      hipLaunchKernelGGL(fn, grid, dim3(NT), lds, st, a, (const S2*)G, (S2*)H);
+      return hipGetLastError();
+    }
+    if (a.L == 6144 && twl) {
+      auto fn = split ? xrow_kernel<DIM, NT, PTS, MAXBF, true, T, true, 6144>
+                      : xrow_kernel<DIM, NT, PTS, MAXBF, true, T, false, 6144>;
+      allow_lds((const void*)fn, lds);
+      hipLaunchKernelGGL(fn, grid, dim3(NT), lds, st, a, (const S2*)G, (S2*)H);
       return hipGetLastError();
     }
   }
