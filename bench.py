@@ -17,7 +17,7 @@ stream), the mixed-precision forms with their errors, the other workloads as
 extra keys, and the CPU-oracle baseline on a bounded sample.
 
     python3 bench.py [--steps K] [--warmup W]
-    python3 bench.py --probe fp64|mixed WORKLOAD [--probe-steps K]   (counters)
+    python3 bench.py --probe fp64|mixed WORKLOAD [--probe-steps K] [--probe-dct auto|fft|matmul]   (counters)
 """
 from __future__ import annotations
 
@@ -504,12 +504,12 @@ def _public(r):
             "factor_ms": r["factor_ms"], "kernels_avg_us": k}
 
 
-def probe(precision, name, steps, copy_bytes):
+def probe(precision, name, steps, copy_bytes, dct="auto"):
     """A few steps of one workload (for counter collection under a profiler)."""
     import torch
 
     w = WORKLOADS[name]
-    g = solver(w, precision)
+    g = solver(w, precision, dct=dct)
     g.initial_state(torch.from_numpy(b_grid(w)))
     for _ in range(steps):
         g.step(w["dt"])
@@ -520,7 +520,7 @@ def probe(precision, name, steps, copy_bytes):
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-    print("probe done", precision, name, steps, flush=True)
+    print("probe done", precision, dct, name, steps, flush=True)
 
 
 def main():
@@ -538,6 +538,7 @@ def main():
     ap.add_argument("--probe", nargs=2, metavar=("PRECISION", "WORKLOAD"),
                     help="run --probe-steps steps of one workload and exit (for profilers)")
     ap.add_argument("--probe-steps", type=int, default=12)
+    ap.add_argument("--probe-dct", default="auto", choices=("auto", "fft", "matmul"))
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="with --probe: one device-to-device copy of this many bytes after the "
                          "steps (counter calibration)")
@@ -551,7 +552,7 @@ def main():
         prec, name = args.probe
         if name not in WORKLOADS:
             sys.exit(f"unknown workload {name}; one of {', '.join(WORKLOADS)}")
-        probe(prec, name, args.probe_steps, args.copy_bytes)
+        probe(prec, name, args.probe_steps, args.copy_bytes, args.probe_dct)
         return
 
     w = WORKLOADS[HEADLINE]
