@@ -274,7 +274,23 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
   using cT = cpx<T>;
   cT* buf = (cT*)smem;
   const int TK = NGC > 0 ? 3072 / NGC : TKr;
-  const int f = blockIdx.z, jz = blockIdx.y, k0 = blockIdx.x * TK;
+  // Blocks go to the eight XCDs (each with its own L2) in turn by linear
+  // index; the neighbouring kx tiles of a row share the cache lines at their
+  // ends (rows of Px values are not line-aligned), so the linear index is
+  // remapped to give each XCD a contiguous range of tiles.
+  int bx = blockIdx.x, jz = blockIdx.y, f = blockIdx.z;
+  {
+    const int nbx = gridDim.x, nby = gridDim.y, total = nbx * nby * gridDim.z;
+    if (total % 8 == 0) {
+      int lin = bx + nbx * (jz + nby * f);
+      lin = (lin & 7) * (total >> 3) + (lin >> 3);
+      bx = lin % nbx;
+      lin /= nbx;
+      jz = lin % nby;
+      f = lin / nby;
+    }
+  }
+  const int k0 = bx * TK;
   const int Ny = a.Ny, Ng = NGC > 0 ? NGC : a.Ngy, Px = a.Px, M = a.M, half = Ny / 2;
   const int tid = threadIdx.x, nt = blockDim.x;
   const size_t inRows = DIR > 0 ? Ny : Ng, outRows = DIR > 0 ? Ng : Ny;
@@ -286,7 +302,7 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
     if (pos > Ng - half) return Ny + (pos - Ng);
     return -1;
   };
-  for (int idx = tid; idx < TK * Ng; idx += nt) {
+  auto load = [&](int idx) -> cT {
     const int pos = idx / TK, s = idx - pos * TK;  // consecutive threads: consecutive kx
     const int kx = k0 + s;
     cT v = mk<T>(0, 0);
@@ -298,7 +314,25 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
         v = ldv<T>(src + (size_t)pos * Px + kx);
       }
     }
-    buf[s * Ng + pos] = v;
+    return v;
+  };
+  if constexpr (NGC > 0) {
+    // TK * Ng = 3072 points, 12 per thread: every load issued before the
+    // first LDS store, so that their latencies overlap
+    constexpr int EPT = 3072 / 256;
+    cT v[EPT];
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) v[it] = load(tid + it * 256);
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+      const int idx = tid + it * 256, pos = idx / TK, s = idx - pos * TK;
+      buf[s * Ng + pos] = v[it];
+    }
+  } else {
+    for (int idx = tid; idx < TK * Ng; idx += nt) {
+      const int pos = idx / TK, s = idx - pos * TK;
+      buf[s * Ng + pos] = load(idx);
+    }
   }
   __syncthreads();
   if constexpr (sizeof(T) == 8)
