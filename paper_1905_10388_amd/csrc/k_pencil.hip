@@ -631,6 +631,278 @@ __global__ void __launch_bounds__(2 * kWave) solve_pair_kernel(PencilArgs a, int
 }
 
 // ---------------------------------------------------------------------------
+// Streamed solve: the pair sweeps with the pencil's vectors outside LDS, so
+// that a compute unit holds about three times the pencils (LDS per
+// wavefront: the factor stage and two 64-row rings of incoming rows).
+//   * forward: the incoming rows j0 + FW + t of each chunk are formed from
+//     Bev (and the boundary values) one chunk ahead, into an LDS ring; the
+//     results y of each chunk go to the workspace a.ysp [p][part][nst];
+//   * backward: the incoming rows j0 - BW + t come back from the workspace
+//     one chunk ahead, into the same ring; each chunk's x~ is recombined at
+//     once, X_m = x~_m - x~_{m+2} (the partner 2S columns on, in this chunk
+//     or the one before it), and written to the state.
+// One wavefront per pencil (both real parts), one pencil per block.
+// ---------------------------------------------------------------------------
+// right-hand side row r of pencil p, both parts (rows outside [0, n): 0)
+__device__ __forceinline__ void rhs_row(const PencilArgs& a, const double2* __restrict__ Bp, bool mean,
+                                        int r, double& v0, double& v1) {
+  const SysDesc& d = a.desc;
+  v0 = v1 = 0.0;
+  if (r < 0 || r >= a.n) return;
+  if (r < d.kb) {
+    if (mean && d.bc_var[r] == VB) v0 = d.bc_side[r] == 0 ? a.b_bottom : a.b_top;
+    return;
+  }
+  const int m = (r - d.kb) / d.S, q = r - d.kb - m * d.S;
+  if (m > d.N - 2) return;
+  const int eq = d.eq_at[q];
+  int e;
+  if (eq == EB) e = 0;
+  else if (eq == EU) e = 1;
+  else if (eq == EV) e = 2;
+  else if (eq == EW) e = d.ne - 1;
+  else return;
+  const double2 v = Bp[e * d.N + m];
+  const bool scaled = eq == EU || eq == EV;  // row scaled by i
+  v0 = scaled ? -v.y : v.x;
+  v1 = scaled ? v.x : v.y;
+}
+
+template <int FW, int BW, int K>
+__global__ void __launch_bounds__(kWave) solve_stream_kernel(PencilArgs a, int plaunch,
+                                                             const double2* __restrict__ Bev,
+                                                             const double* __restrict__ Lf,
+                                                             const uint8_t* __restrict__ sl,
+                                                             const double* __restrict__ Uf,
+                                                             double2* __restrict__ X) {
+  using T = double;
+  extern __shared__ double lds[];
+  constexpr int CH = kCH, G = 4, R = kSR, SU = su3<double>(), UPC = CH / SU;
+  const int lane = threadIdx.x;
+  const int p = blockIdx.x;
+  const SysDesc& d = a.desc;
+  const int N = d.N, S = d.S, ne = d.ne;
+  if (blockIdx.x == 0 && plaunch < a.P) zero_pencils(X, plaunch, a.P, S * N, lane, kWave);
+  if (p >= plaunch) return;
+  if (!pencil_active(a, p)) {
+    zero_pencils(X, p, p + 1, S * N, lane, kWave);
+    return;
+  }
+  const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
+  const double2* Bp = Bev + (size_t)p * ne * N;
+  const int npad = a.nst, nch = npad / CH, n = a.n;
+  double* ring = lds;                       // [2 buffers][2 parts][64]
+  double* st = lds + 4 * kWave;             // factor stage
+  double* Y0 = a.ysp + (size_t)p * 2 * npad;
+  double* Y1 = Y0 + npad;
+  const double* Lp = Lf + (size_t)p * npad * FW;
+  const uint32_t* sw = (const uint32_t*)(sl + (size_t)p * npad);
+  const double* Up = Uf + (size_t)p * npad * BW;
+
+  // ---- forward ----
+  {
+    constexpr int FB = SU * FW * (int)sizeof(T);
+    constexpr int SWU = SU / 4;
+    const int nu = nch * UPC;
+    const int lf = lane & (FW - 1);
+    UnitRegs<FB> r[K];
+    uint32_t swr[K];
+    auto load_unit = [&](int k, int u) {
+      r[k].load(Lp + (size_t)u * SU * FW, lane);
+      swr[k] = sw[u * SWU + (lane & (SWU - 1))];
+    };
+    load_unit(0, 0);
+#pragma unroll
+    for (int u = 1; u < K; ++u) load_unit(u, u < nu ? u : nu - 1);
+    r[0].store(st, lane);
+    uint32_t wnx[SWU], wcur[SWU];
+#pragma unroll
+    for (int i = 0; i < SWU; ++i) wnx[i] = (uint32_t)__builtin_amdgcn_readlane(swr[0], i);
+    load_unit(0, K < nu ? K : nu - 1);
+    T rg[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) rg[k] = st[k * FW + lf];
+    T w0, w1;
+    rhs_row(a, Bp, pc.mean, lane < FW ? lane : -1, w0, w1);
+    {
+      double i0, i1;
+      rhs_row(a, Bp, pc.mean, FW + lane, i0, i1);
+      ring[lane] = i0;
+      ring[kWave + lane] = i1;
+    }
+    for (int c = 0; c < nch; ++c) {
+      const int j0 = c * CH;
+      const double* in0 = ring + (c & 1) * 2 * kWave;
+      const double* in1 = in0 + kWave;
+      // the next chunk's incoming rows, requested now, stored at the end
+      double q0, q1;
+      rhs_row(a, Bp, pc.mean, j0 + CH + FW + lane, q0, q1);
+      T n0[2][G], n1[2][G];
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        n0[0][k] = in0[k];
+        n1[0][k] = in1[k];
+      }
+      uint32_t word = 0;
+      T ya0 = (T)0, ya1 = (T)0;
+      static_for<0, CH / G>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (g + 1 < CH / G) {
+#pragma unroll
+          for (int k = 0; k < G; ++k) {
+            n0[(g + 1) & 1][k] = in0[(g + 1) * G + k];
+            n1[(g + 1) & 1][k] = in1[(g + 1) * G + k];
+          }
+        }
+        static_for<0, G>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          constexpr int t = g * G + k;
+          if constexpr (t % SU == 0) {
+            const int vk = c * UPC + t / SU + 1 + K;
+            constexpr int rs = (t / SU + 1) % K;
+            asm volatile("" : "+v"(swr[rs]));
+#pragma unroll
+            for (int i = 0; i < SWU; ++i) {
+              wcur[i] = wnx[i];
+              wnx[i] = (uint32_t)__builtin_amdgcn_readlane(swr[rs], i);
+            }
+            r[rs].store(st + ((t / SU + 1) & 1) * SU * FW, lane);
+            load_unit(rs, vk < nu ? vk : nu - 1);
+          }
+          if constexpr ((t & 3) == 0) word = wcur[(t % SU) >> 2];
+          const int s = (word >> (8 * (t & 3))) & 0xff;
+          const T y0 = readlane_t(w0, s), y1 = readlane_t(w1, s);
+          put_lane<t>(ya0, y0);
+          put_lane<t>(ya1, y1);
+          const T l = rg[t % R];
+          constexpr int tn = t + R;
+          rg[t % R] = st[((tn / SU) & 1) * SU * FW + (tn % SU) * FW + lf];
+          const bool inw = __builtin_amdgcn_inverse_ballot_w64(1ull << s);
+          const T ws0 = inw ? n0[g & 1][k] : w0;
+          const T ws1 = inw ? n1[g & 1][k] : w1;
+          w0 = fma(-l, y0, ws0);
+          w1 = fma(-l, y1, ws1);
+        });
+      });
+      Y0[j0 + lane] = ya0;
+      Y1[j0 + lane] = ya1;
+      double* nx = ring + ((c + 1) & 1) * 2 * kWave;
+      nx[lane] = q0;
+      nx[kWave + lane] = q1;
+    }
+  }
+  // the workspace rows written above are read back below by this wavefront
+  __threadfence_block();
+
+  // ---- backward ----
+  {
+    constexpr bool kDiv = CH % BW == 0;
+    constexpr int UB = SU * BW * (int)sizeof(T);
+    const int nu = nch * UPC;
+    const int lb = lane % BW;
+    UnitRegs<UB> r[K];
+    r[0].load(Up + (size_t)(nu - 1) * SU * BW, lane);
+#pragma unroll
+    for (int u = 1; u < K; ++u) r[u].load(Up + (size_t)(u < nu ? nu - 1 - u : 0) * SU * BW, lane);
+    r[0].store(st, lane);
+    r[0].load(Up + (size_t)(K < nu ? nu - 1 - K : 0) * SU * BW, lane);
+    T rg[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) rg[k] = st[(SU - 1 - k) * BW + lb];
+    const int r0 = window_start_row<BW>(npad, lb);
+    T w0 = Y0[r0], w1 = Y1[r0];
+    {
+      const int rr = (nch - 1) * CH - BW + lane;  // incoming rows of the last chunk
+      ring[lane] = rr >= 0 ? Y0[rr] : 0.0;
+      ring[kWave + lane] = rr >= 0 ? Y1[rr] : 0.0;
+    }
+    // recombination partner: column c + 2S, in this chunk or the one after it
+    const int S2 = 2 * S;
+    T xp0 = (T)0, xp1 = (T)0;  // x~ of the chunk above
+    for (int c = nch - 1; c >= 0; --c) {
+      const int j0 = c * CH;
+      const int s0 = kDiv ? 0 : j0 % BW;
+      const int bsel = (nch - 1 - c) & 1;
+      const double* in0 = ring + bsel * 2 * kWave;
+      const double* in1 = in0 + kWave;
+      double q0 = 0.0, q1 = 0.0;
+      {
+        const int rr = j0 - CH - BW + lane;  // the next (lower) chunk's incoming rows
+        if (c > 0 && rr >= 0) {
+          q0 = Y0[rr];
+          q1 = Y1[rr];
+        }
+      }
+      constexpr int NG = CH / G;
+      T n0[2][G], n1[2][G];
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        n0[(NG - 1) & 1][k] = in0[(NG - 1) * G + k];
+        n1[(NG - 1) & 1][k] = in1[(NG - 1) * G + k];
+      }
+      T xa0 = (T)0, xa1 = (T)0;
+      static_for<0, NG>([&](auto gc) {
+        constexpr int g = NG - 1 - decltype(gc)::value;
+        if (g > 0) {
+#pragma unroll
+          for (int k = 0; k < G; ++k) {
+            n0[(g - 1) & 1][k] = in0[(g - 1) * G + k];
+            n1[(g - 1) & 1][k] = in1[(g - 1) * G + k];
+          }
+        }
+        static_for<0, G>([&](auto kc) {
+          constexpr int k = G - 1 - decltype(kc)::value;
+          constexpr int t = g * G + k;
+          constexpr int q = CH - 1 - t;
+          if constexpr (q % SU == 0) {
+            const int vk = UPC * (nch - 1 - c) + q / SU + 1 + K;
+            constexpr int rs = (q / SU + 1) % K;
+            r[rs].store(st + ((q / SU + 1) & 1) * SU * BW, lane);
+            r[rs].load(Up + (size_t)(vk < nu ? nu - 1 - vk : 0) * SU * BW, lane);
+          }
+          const int sj = kDiv ? t % BW : window_lane<BW>(s0, t);
+          const uint64_t msj = window_lanes<BW>(sj);
+          const T u = rg[q % R];
+          constexpr int qn = q + R;
+          rg[q % R] = st[((qn / SU) & 1) * SU * BW + (SU - 1 - qn % SU) * BW + lb];
+          const T x0 = readlane_t(w0 * u, sj), x1 = readlane_t(w1 * u, sj);
+          put_lane<t>(xa0, x0);
+          put_lane<t>(xa1, x1);
+          const bool inw = __builtin_amdgcn_inverse_ballot_w64(msj);
+          w0 = inw ? n0[g & 1][k] : fma(-u, x0, w0);
+          w1 = inw ? n1[g & 1][k] : fma(-u, x1, w1);
+        });
+      });
+      // X = P^R x~ for the chunk's columns j0 + lane
+      {
+        const int sl2 = (lane + S2) & (kWave - 1);
+        const bool here = lane + S2 < kWave;
+        const T a0 = __shfl(xa0, sl2), b0 = __shfl(xp0, sl2);
+        const T a1 = __shfl(xa1, sl2), b1 = __shfl(xp1, sl2);
+        const int col = j0 + lane;
+        if (col < n) {
+          const int m = col / S, pos = col - m * S;
+          double v0 = xa0, v1 = xa1;
+          if (m + 2 < N) {
+            v0 -= here ? a0 : b0;
+            v1 -= here ? a1 : b1;
+          }
+          const int var = d.var_at[pos];
+          const double2 xv = (var == VU || var == VUZ || var == VV || var == VVZ) ? make_double2(v1, -v0)
+                                                                                  : make_double2(v0, v1);
+          X[((size_t)p * S + d.abi_index[var]) * N + m] = xv;
+        }
+      }
+      xp0 = xa0;
+      xp1 = xa1;
+      double* nx = ring + (bsel ^ 1) * 2 * kWave;
+      nx[lane] = q0;
+      nx[kWave + lane] = q1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Refined mixed-precision solve: FP32 sweeps on FP32 copies of the FP64
 // factors, the FP64 residual r = b - A x^ of the first solution (A applied
 // from the operator templates, every row including the boundary rows; b
@@ -1342,6 +1614,17 @@ static hipError_t launch_solve_t(const PencilArgs& a, const void* Bev, const dou
     const size_t ldsp = 2 * per_pencil + (size_t)2 * stage_bytes<double, FW, BW, su3<double>()>();
     // both real parts per wavefront where three blocks of two pencils fit a
     // unit (256 x 256 x 128: 5.06 -> 4.91 ms; 4096 x 64: 97.5 -> 93.1 us)
+    // many pencils per compute unit: vectors streamed through HBM, one pencil
+    // per wavefront and about twice the pencils resident (256 x 256 x 128:
+    // 4.92 -> 4.44 ms; at 4096 x 64, eight pencils per unit, the pair form
+    // is faster: 91.9 against 100.1 us).  Four units of factor loads in
+    // flight (eight, or four waves per SIMD with two, measured no faster).
+    if (a.ysp && g.plaunch >= 32 * cus) {
+      const size_t ldss = (size_t)4 * kWave * sizeof(double) + stage_bytes<double, FW, BW, su3<double>()>();
+      hipLaunchKernelGGL((solve_stream_kernel<FW, BW, 4>), dim3(g.plaunch), dim3(kWave), ldss, st, a,
+                         g.plaunch, (const double2*)Bev, Lf, sl, Uf, (double2*)X);
+      return hipGetLastError();
+    }
     if (2 * ldsp <= (size_t)lds_cu) {
       allow_lds((const void*)solve_pair_kernel<FW, BW>, ldsp);
       hipLaunchKernelGGL((solve_pair_kernel<FW, BW>), dim3(g.blocks), dim3(2 * kWave), ldsp, st, a,

@@ -242,6 +242,7 @@ struct stau_pencils {
   bool has_last = false;
   double last_a0 = 0.0, last_b0 = 0.0;
   double* tpl = nullptr;   // device: band templates of the operator (PencilArgs::tpl)
+  double* ysp = nullptr;   // device: streamed-solve vectors (PencilArgs::ysp)
   int* sing = nullptr;     // device: first singular pencil (INT_MAX if none)
   int* flag = nullptr;     // device: non-finite flag
   double* scratch = nullptr;
@@ -556,6 +557,7 @@ static void free_pencils(stau_pencils* p) {
       f = stau_pencils::FactorSlot{};
     }
   hipFree(p->tpl);
+  hipFree(p->ysp);
   hipFree(p->evp_V);
   hipFree(p->sing);
   hipFree(p->flag);
@@ -905,12 +907,16 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   if (e == hipSuccess) e = hipMalloc((void**)&pen->sing, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->flag, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->scratch, szScratch);
+  // the streamed single-block solve keeps each pencil's two real vectors here
+  const size_t szY = pen->two ? 0 : (size_t)pa.P * 2 * pa.nst * sizeof(double);
+  if (e == hipSuccess && szY) e = hipMalloc((void**)&pen->ysp, szY);
   if (e != hipSuccess) {
     free_pencils(pen);
     delete pen;
     return fail(STAU_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
-  pen->ws_bytes = (int64_t)(szG + szG2 + szGb + szH + szB + szF + szScratch);
+  pa.ysp = pen->ysp;
+  pen->ws_bytes = (int64_t)(szG + szG2 + szGb + szH + szB + szF + szScratch + szY);
   {
     // KE functional weights: integral over z in [0, 1] of T_m = 1 / (1 - m^2), m even
     std::vector<double2> wv(N);
