@@ -903,7 +903,8 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   size_t szF = 0;
   for (auto& f : pen->slot)
     if (e == hipSuccess)
-      e = pen->two ? alloc_slot2(f, pen->pt, pen->pb, &szF, pen->refined) : alloc_slot(f, pa, &szF);
+      e = pen->two ? alloc_slot2(f, pen->pt, pen->pb, &szF, pen->refined)
+                   : alloc_slot(f, pa, &szF, pen->refined);
   if (e == hipSuccess) e = hipMalloc((void**)&pen->sing, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->flag, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&pen->scratch, szScratch);

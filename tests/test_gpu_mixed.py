@@ -146,6 +146,29 @@ def test_refined_solve_3d_and_rk():
     assert max(errs.values()) < MIXED_BOUND, errs
 
 
+@pytest.mark.parametrize("shape", [(16, 8, 16), (2048, 1, 16)], ids=["3d-16x8x16", "2d-2048x16"])
+def test_refined_solve_is_taken_in_the_single_block_layout(shape):
+    """The refined solve must run where the pencils use the single-block
+    layout (3-D, and 2-D domains with more pencils than two per compute
+    unit): one step differs from the FP64-solve mixed step in the last bits
+    and agrees with it to the refinement's accuracy."""
+    Nx, Ny, Nz = shape
+    dim = 3 if Ny > 1 else 2
+    kw = dict(dim=3, Ny=Ny, Ly=4.0) if dim == 3 else {}
+    ga = RBSolver(Nx, Nz, 4.0, 1e5, 1.0, precision="mixed", mixed_solve="fp64", **kw)
+    gr = RBSolver(Nx, Nz, 4.0, 1e5, 1.0, precision="mixed", mixed_solve="refined", **kw)
+    xi = si.workload_noise((Nx, Ny, Nz) if dim == 3 else (Nx, Nz), 0)
+    o = RBOracle(Nx, Nz, 4.0, RBParams(1e5, 1.0), **({"dim": 3, "Ny": Ny, "Ly": 4.0} if dim == 3 else {}))
+    X0 = torch.from_numpy(o.initial_state(xi, amp=1e-2)).cuda()
+    ga.set_state(X0)
+    gr.set_state(X0)
+    ga.step(1e-4)
+    gr.step(1e-4)
+    a, r = _to_np(ga.X), _to_np(gr.X)
+    d = np.abs(a - r).max() / np.abs(a).max()
+    assert 0.0 < d < 1e-9, d
+
+
 def test_mixed_solve_option_is_checked():
     from paper_1905_10388_amd import StauError, _lib
     import ctypes as C
