@@ -96,11 +96,36 @@ __device__ __forceinline__ void dft8(cpx<T>* v) {
   v[7] = e[3] - w3o;
 }
 
+// 6 = 2 x 3: pairs (v[n], v[n + 3]) first (w^3 = -1), then a length-3 DFT of
+// the sums for the even outputs and of the differences times w^n for the odd
+// ones (w = e^{DIR 2 pi i / 6}, w^2 the length-3 root)
+template <int DIR, typename T>
+__device__ __forceinline__ void dft6(cpx<T>* v) {
+  const T h = T(0.5);
+  const T s = T(DIR) * T(0.86602540378443864676372317075294);
+  cpx<T> a[3], b[3];
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    a[n] = v[n] + v[n + 3];
+    b[n] = v[n] - v[n + 3];
+  }
+  b[1] = cmul(b[1], mk(h, s));   // w
+  b[2] = cmul(b[2], mk(-h, s));  // w^2
+  dft3<DIR>(a);
+  dft3<DIR>(b);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v[2 * k] = a[k];
+    v[2 * k + 1] = b[k];
+  }
+}
+
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dftR(cpx<T>* v) {
   if constexpr (R == 2) dft2<DIR>(v);
   if constexpr (R == 3) dft3<DIR>(v);
   if constexpr (R == 4) dft4<DIR>(v);
+  if constexpr (R == 6) dft6<DIR>(v);
   if constexpr (R == 8) dft8<DIR>(v);
 }
 
@@ -229,9 +254,11 @@ __device__ __forceinline__ void stockham_pass_c(cpx<T>* buf, int batch, const cp
       w[1] = tw[jm * TSTR];
       if constexpr (R >= 3) w[2] = cmul(w[1], w[1]);
       if constexpr (R >= 4) w[3] = cmul(w[1], w[2]);
-      if constexpr (R == 8) {
+      if constexpr (R >= 6) {
         w[4] = cmul(w[2], w[2]);
         w[5] = cmul(w[1], w[4]);
+      }
+      if constexpr (R == 8) {
         w[6] = cmul(w[2], w[4]);
         w[7] = cmul(w[3], w[4]);
       }
@@ -257,29 +284,35 @@ __device__ __forceinline__ void stockham_pass_c(cpx<T>* buf, int batch, const cp
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
-// passes for the part M / NS not yet transformed, in the order of fft_lds
-template <int M, int NS, int DIR, int MAXBF, typename T, bool R8>
+// passes for the part M / NS not yet transformed, in the order of fft_lds;
+// with R6 the factor 3 is taken with a factor 2 in one radix-6 pass (384 =
+// 6 x 8 x 8: three passes instead of four)
+template <int M, int NS, int DIR, int MAXBF, typename T, bool R8, bool R6>
 __device__ __forceinline__ void fft_passes_c(cpx<T>* buf, int batch, const cpx<T>* __restrict__ tw, int tid,
                                              int nt) {
   constexpr int rem = M / NS;
   if constexpr (rem > 1) {
     constexpr int lg = ilog2c(rem);
-    constexpr int R = rem % 3 == 0 ? 3
+    constexpr int R = rem % 3 == 0 ? (R6 && rem % 6 == 0 ? 6 : 3)
                       : R8         ? (lg >= 3 ? 8 : (lg == 2 ? 4 : 2))
                       : (lg & 1)   ? (lg >= 3 ? 8 : 2)
                                    : 4;
-    constexpr int BF = R == 3 ? (MAXBF * 4 + 2) / 3 : R == 8 ? (MAXBF + 1) / 2 : R == 4 ? MAXBF : MAXBF * 2;
+    constexpr int BF = R == 3   ? (MAXBF * 4 + 2) / 3
+                       : R == 6 ? (MAXBF * 4 + 5) / 6
+                       : R == 8 ? (MAXBF + 1) / 2
+                       : R == 4 ? MAXBF
+                                : MAXBF * 2;
     stockham_pass_c<R, DIR, BF, M, NS, T>(buf, batch, tw, tid, nt);
-    fft_passes_c<M, NS * R, DIR, MAXBF, T, R8>(buf, batch, tw, tid, nt);
+    fft_passes_c<M, NS * R, DIR, MAXBF, T, R8, R6>(buf, batch, tw, tid, nt);
   }
 }
 
-template <int MC, int DIR, int MAXBF, typename T, bool R8 = true>
+template <int MC, int DIR, int MAXBF, typename T, bool R8 = true, bool R6 = false>
 __device__ __forceinline__ void fft_lds_c(cpx<T>* buf, int M, int batch, const cpx<T>* __restrict__ tw, int tid,
                                           int nt) {
   if constexpr (MC > 0) {
     static_assert(MC % 9 != 0, "at most one factor 3");
-    fft_passes_c<MC, 1, DIR, MAXBF, T, R8>(buf, batch, tw, tid, nt);
+    fft_passes_c<MC, 1, DIR, MAXBF, T, R8, R6>(buf, batch, tw, tid, nt);
   } else {
     fft_lds<DIR, MAXBF, T, R8>(buf, M, batch, tw, tid, nt);
   }

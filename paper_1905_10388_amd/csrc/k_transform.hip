@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kZThreads) zb_kernel(XformArgs a, FieldList fl
     buf[idx] = z;
   }
   __syncthreads();
-  fft_lds_c<MC, +1, MAXBF>(buf, M, TP, (const cT*)twl, tid, kZThreads);
+  fft_lds_c<MC, +1, MAXBF, T, true, MC == 384>(buf, M, TP, (const cT*)twl, tid, kZThreads);
 #pragma unroll
   for (int it = 0; it < EPT; ++it) {
     const int idx = tid + it * kZThreads;
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
     }
   }
   __syncthreads();
-  fft_lds_c<MC, -1, MAXBF>(buf, M, TP, (const cT*)twl, tid, nt);
+  fft_lds_c<MC, -1, MAXBF, T, true, MC == 384>(buf, M, TP, (const cT*)twl, tid, nt);
   cT c[MAXIT];
   const T invM = (T)1 / (T)M;
 #pragma unroll
@@ -336,9 +336,9 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
   }
   __syncthreads();
   if constexpr (sizeof(T) == 8)
-    fft_lds_c<NGC, DIR, MAXBF>(buf, Ng, TK, (const cT*)a.twy, tid, nt);
+    fft_lds_c<NGC, DIR, MAXBF, T, true, true>(buf, Ng, TK, (const cT*)a.twy, tid, nt);
   else
-    fft_lds_c<NGC, DIR, MAXBF>(buf, Ng, TK, (const cT*)a.twy32, tid, nt);
+    fft_lds_c<NGC, DIR, MAXBF, T, true, true>(buf, Ng, TK, (const cT*)a.twy32, tid, nt);
   if (DIR > 0) {
     for (int idx = tid; idx < TK * Ng; idx += nt) {
       const int l = idx / TK, s = idx - l * TK;

@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
 #pragma unroll
   for (int s = 0; s < 4; ++s) fetch(s, 4 + s);
   __syncthreads();
-  fft_lds_c<LC, +1, MAXBF, T, false>(buf, L, 4, twl, tid, NT);
+  fft_lds_c<LC, +1, MAXBF, T, true, true>(buf, L, 4, twl, tid, NT);
 #pragma unroll
   for (int q = 0; q < PTS; ++q) {
     const int i = tid + q * NT;
@@ -433,7 +433,7 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
 #pragma unroll
   for (int s = 0; s < 4; ++s) scatter(s);
   __syncthreads();
-  fft_lds_c<LC, +1, MAXBF, T, false>(buf, L, 4, twl, tid, NT);
+  fft_lds_c<LC, +1, MAXBF, T, true, true>(buf, L, 4, twl, tid, NT);
 #pragma unroll
   for (int q = 0; q < PTS; ++q) {
     const int i = tid + q * NT;
@@ -455,7 +455,7 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
     }
   }
   __syncthreads();
-  fft_lds_c<LC, -1, MAXBF, T, false>(buf, L, 2, twl, tid, NT);
+  fft_lds_c<LC, -1, MAXBF, T, true, true>(buf, L, 2, twl, tid, NT);
   const T invL = (T)1 / (T)L;
   const T hf = (T)0.5;
   for (int k = tid; k < Px; k += NT) {

@@ -129,7 +129,9 @@ def test_gradient_matches_oracle_small():
 def test_autograd_function_and_finite_differences_adjoint_workload():
     """Adjoint workload: Nx=512, Nz=128, Ra=1e6, Pr=1, dt=1e-4, 200 SBDF2 steps,
     checkpoint every 20; gradient of the final KE w.r.t. the b grid checked by
-    central differences along 8 seeded directions."""
+    central differences along 8 seeded directions.  The central difference
+    must agree over a decade of steps (h = 1e-3 .. 1e-4: a plateau, not one
+    lucky step size), and stay close at h = 3e-5 where rounding grows."""
     Nx, Nz, Lx, Ra, Pr, dt, steps = 512, 128, 4.0, 1e6, 1.0, 1e-4, 200
     g = RBSolver(Nx, Nz, Lx, Ra, Pr)
     j = np.arange(Nz)
@@ -147,14 +149,16 @@ def test_autograd_function_and_finite_differences_adjoint_workload():
             g.step(dt)
         return g.kinetic_energy()
 
-    errs = []
+    table = []
     for r in range(1, 9):
         d = torch.from_numpy(si.direction((Nx, Nz), r)).cuda()
         ad = float((grad * d).sum())
-        best = None
-        for h in (1e-3, 3e-4, 1e-4):
+        row = []
+        for h in (1e-3, 3e-4, 1e-4, 3e-5):
             fd = (Jof(base + h * d) - Jof(base - h * d)) / (2 * h)
-            e = abs(fd - ad) / abs(ad)
-            best = e if best is None else min(best, e)
-        errs.append(best)
-    assert max(errs) < 1e-6, errs
+            row.append(abs(fd - ad) / abs(ad))
+        print("direction", r, "relative FD error at h = 1e-3, 3e-4, 1e-4, 3e-5:", " ".join(f"{e:.2e}" for e in row))
+        table.append(row)
+    table = np.array(table)
+    assert table[:, :3].max() < 1e-8, table
+    assert table[:, 3].max() < 1e-7, table
