@@ -65,6 +65,9 @@ extern "C" {
 #define STAU_SOLVE_FP64 1
 #define STAU_SOLVE_REFINED 2
 
+#define STAU_FACTORS_AUTO 0
+#define STAU_FACTORS_BAND 1
+
 /* IMEX Runge-Kutta schemes of stau_step_rk: the (1,1,1), (2,2,2) and (4,4,3)
  * schemes of Ascher, Ruuth & Spiteri (1997), orders 1, 2, 3, with 1, 2, 4
  * implicit stages. */
@@ -109,7 +112,15 @@ typedef struct stau_pencils stau_pencils;
  *          the single-block or the two-block sweep layout, as the FP64 solve
  *          uses), STAU_SOLVE_AUTO (FP64, the faster of the two at every size
  *          measured).  Else STAU_EINVAL.
- * reserved must be 0. */
+ * factor_layout  storage of the factors the FP64 pencil solve reads (Sec. IX
+ *          "Matrix solvers": the factors of the sparse banded pencil
+ *          matrices are stored and reused while dt is fixed):
+ *          STAU_FACTORS_AUTO (where the solve streams its vectors through
+ *          device memory, i.e. single-block layouts with more than 32 pencils
+ *          per compute unit, the nonzero entries are also packed into sparse
+ *          records after each factorisation and the solve reads those;
+ *          whole-band factors elsewhere), STAU_FACTORS_BAND (whole-band
+ *          factors only).  Both give the same results.  Else STAU_EINVAL. */
 typedef struct stau_domain_desc {
   int32_t dim;
   int32_t precision;
@@ -119,7 +130,7 @@ typedef struct stau_domain_desc {
   int32_t device;
   int32_t dct_method;
   int32_t mixed_solve;
-  int32_t reserved;
+  int32_t factor_layout;
 } stau_domain_desc;
 
 /* Rayleigh-Benard parameters in free-fall units: kappa = (Ra Pr)^(-1/2),

@@ -38,7 +38,7 @@ class RBSolver:
     def __init__(self, Nx: int, Nz: int, Lx: float, Ra: float, Pr: float, *, dim: int = 2,
                  Ny: int = 1, Ly: float = 1.0, precision: str = "fp64", buoyancy: float = 1.0,
                  b_bottom: float = 1.0, b_top: float = 0.0, device: int = 0, dct: str = "auto",
-                 gamma=(), mixed_solve: str = "auto"):
+                 gamma=(), mixed_solve: str = "auto", factor_layout: str = "auto"):
         import torch
 
         self._torch = torch
@@ -49,7 +49,9 @@ class RBSolver:
                                dct_method={"auto": _lib.STAU_DCT_AUTO, "fft": _lib.STAU_DCT_FFT,
                                            "matmul": _lib.STAU_DCT_MATMUL}[dct],
                                mixed_solve={"auto": _lib.STAU_SOLVE_AUTO, "fp64": _lib.STAU_SOLVE_FP64,
-                                            "refined": _lib.STAU_SOLVE_REFINED}[mixed_solve])
+                                            "refined": _lib.STAU_SOLVE_REFINED}[mixed_solve],
+                               factor_layout={"auto": _lib.STAU_FACTORS_AUTO,
+                                              "band": _lib.STAU_FACTORS_BAND}[factor_layout])
         gamma = tuple(float(g) for g in gamma)
         if len(gamma) > 4:
             raise ValueError("at most 4 Chebyshev terms of Gamma(z)")
@@ -83,6 +85,13 @@ class RBSolver:
                                dt_prev=0.0, head=0)
 
     # -- lifetime ---------------------------------------------------------
+    def query(self):
+        """Sizes of the domain as stau_query reports them now (the workspace
+        grows when factor storage is allocated on first use)."""
+        info = _lib.InfoC()
+        _lib.check(self.lib.stau_query(self._pen, C.byref(info)))
+        return {f: getattr(info, f) for f, _ in _lib.InfoC._fields_}
+
     def close(self):
         if getattr(self, "_pen", None):
             self.lib.stau_destroy_pencils(self._pen)

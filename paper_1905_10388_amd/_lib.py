@@ -23,6 +23,8 @@ STAU_DCT_MATMUL = 2
 STAU_SOLVE_AUTO = 0
 STAU_SOLVE_FP64 = 1
 STAU_SOLVE_REFINED = 2
+STAU_FACTORS_AUTO = 0
+STAU_FACTORS_BAND = 1
 
 RK_SCHEMES = {"RK111": 1, "RK222": 2, "RK443": 3}
 
@@ -46,7 +48,7 @@ class DomainDesc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("Nx", C.c_int64),
                 ("Ny", C.c_int64), ("Nz", C.c_int64), ("Lx", C.c_double), ("Ly", C.c_double),
                 ("dealias", C.c_double), ("device", C.c_int32), ("dct_method", C.c_int32),
-                ("mixed_solve", C.c_int32), ("reserved", C.c_int32)]
+                ("mixed_solve", C.c_int32), ("factor_layout", C.c_int32)]
 
 
 class RBParamsC(C.Structure):

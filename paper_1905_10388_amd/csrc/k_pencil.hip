@@ -903,6 +903,405 @@ __global__ void __launch_bounds__(kWave) solve_stream_kernel(PencilArgs a, int p
 }
 
 // ---------------------------------------------------------------------------
+// Sparse factor records for the streamed solve.  The whole-band factors are
+// mostly zeros: the pencil operators hold about six nonzeros per row, and the
+// 3-D factors about 11 nonzeros per column of U and 4 multipliers per column
+// of L against the 48 + 16 stored slots.  After each factorisation the
+// nonzeros are packed per pencil and unit of kSpU columns into records of
+// fixed stride, which the streamed solve reads with bounds-checked buffer
+// loads (bytes past a record's length are neither fetched nor used):
+//   forward record: [0, 16) per column a 16-bit mask of the forward-window
+//     slots with a nonzero multiplier, [16, 24) the pivot slot byte per
+//     column, [24, 32) zero, then the multipliers, column by column in slot
+//     order;
+//   backward record: [0, 64) per column a 64-bit mask of the rows of a
+//     64-row window (row r at bit r mod 64) with a nonzero of U (the diagonal
+//     as its reciprocal), then the entries, columns in descending order, rows
+//     in bit order;
+//   lengths: per pencil and direction kSpLen bytes, record lengths in 16-byte
+//     words.
+// A missing entry is a zero of the whole-band factors, which only adds a zero
+// product to a row, so both forms give the same results.
+// ---------------------------------------------------------------------------
+constexpr unsigned kBufWord3 = 0x00020000u;  // raw buffer descriptor word 3: 32-bit data format
+
+// Pack the records of every active pencil from the whole-band factors (one
+// wavefront per pencil, units in order).
+template <int FW, int BW>
+__global__ void __launch_bounds__(kWave) sparse_records_kernel(PencilArgs a, const double* __restrict__ Lf,
+                                                               const uint8_t* __restrict__ sl,
+                                                               const double* __restrict__ Uf, SparseFactors sf) {
+  __shared__ double col[kWave];
+  const int p = blockIdx.x, lane = threadIdx.x;
+  const int npad = a.nst, nu = npad / kSpU;
+  uint8_t* lf = sf.lenF + (size_t)p * kSpLen;
+  uint8_t* lb = sf.lenB + (size_t)p * kSpLen;
+  if (!pencil_active(a, p)) {
+    for (int u = lane; u < kSpLen; u += kWave) {
+      lf[u] = 0;
+      lb[u] = 0;
+    }
+    return;
+  }
+  const double* Lp = Lf + (size_t)p * npad * FW;
+  const double* Up = Uf + (size_t)p * npad * BW;
+  const uint8_t* sp = sl + (size_t)p * npad;
+  uint8_t* Fp = sf.F + (size_t)p * nu * sf.strideF;
+  uint8_t* Bp = sf.B + (size_t)p * nu * sf.strideB;
+  const uint64_t below = (1ull << lane) - 1;  // lanes under this one
+  // the strides hold the most entries the band allows (kl multipliers and
+  // kl + ku + 1 entries of U per column); nothing is written past them
+  const int capF = (sf.strideF - 32) / 8, capB = (sf.strideB - 64) / 8;
+  for (int u = 0; u < nu; ++u) {
+    // forward record
+    uint8_t* rf = Fp + (size_t)u * sf.strideF;
+    double* vf = (double*)(rf + 32);
+    int cnt = 0;
+    uint32_t mine = 0;  // lane t < kSpU: mask of column t
+    for (int t = 0; t < kSpU; ++t) {
+      const int j = u * kSpU + t;
+      const double v = lane < FW ? Lp[(size_t)j * FW + lane] : 0.0;
+      const uint64_t m = __ballot(v != 0.0);
+      const int idx = cnt + __popcll(m & below);
+      if (v != 0.0 && idx < capF) vf[idx] = v;
+      if (lane == t) mine = (uint32_t)m;
+      cnt += __popcll(m);
+    }
+    if (lane < kSpU) {
+      ((uint16_t*)rf)[lane] = (uint16_t)mine;
+      rf[16 + lane] = sp[u * kSpU + lane];
+      rf[24 + lane] = 0;
+    }
+    const int fb = 32 + 8 * min(cnt, capF);
+    if (lane == 0 && (fb & 15)) *(double*)(rf + fb) = 0.0;
+    if (lane == 0) lf[u] = (uint8_t)((fb + 15) >> 4);
+    // backward record: column j of U moved from the BW-row window of the
+    // whole-band form (lane l: row j - ((j - l) mod BW)) to lane r mod 64
+    uint8_t* rb = Bp + (size_t)u * sf.strideB;
+    double* vb = (double*)(rb + 64);
+    int cb = 0;
+    uint64_t mb = 0;
+    for (int q = 0; q < kSpU; ++q) {
+      const int t = kSpU - 1 - q, j = u * kSpU + t;
+      col[lane] = 0.0;
+      __syncthreads();
+      if (lane < BW) {
+        int k = (j - lane) % BW;
+        if (k < 0) k += BW;
+        if (k <= j) col[(j - k) & (kWave - 1)] = Up[(size_t)j * BW + lane];
+      }
+      __syncthreads();
+      const double v = col[lane];
+      __syncthreads();
+      const uint64_t m = __ballot(v != 0.0);
+      const int idx = cb + __popcll(m & below);
+      if (v != 0.0 && idx < capB) vb[idx] = v;
+      if (lane == t) mb = m;
+      cb += __popcll(m);
+    }
+    if (lane < kSpU) ((uint64_t*)rb)[lane] = mb;
+    const int bb = 64 + 8 * min(cb, capB);
+    if (lane == 0 && (bb & 15)) *(double*)(rb + bb) = 0.0;
+    if (lane == 0) lb[u] = (uint8_t)((bb + 15) >> 4);
+  }
+  for (int u = nu + lane; u < kSpLen; u += kWave) {
+    lf[u] = 0;
+    lb[u] = 0;
+  }
+}
+
+// registers of one record: NB loads of 16 bytes per lane from a record of
+// `bytes` bytes (lanes past the end read zeros without a memory access)
+template <int NB>
+struct RecordRegs {
+  u32x4 r[NB];
+  __device__ __forceinline__ void load(const uint8_t* rec, int bytes, int lane) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)rec, (short)0, bytes, kBufWord3);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) r[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, (i * kWave + lane) * 16, 0, 0);
+  }
+  __device__ __forceinline__ void store(void* dst, int lane) const {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) ((u32x4*)dst)[i * kWave + lane] = r[i];
+  }
+};
+
+// record length in bytes of unit u from the lane-held length bytes (lane i:
+// units 4i .. 4i + 3)
+__device__ __forceinline__ int record_bytes(uint32_t lens, int u) {
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)lens, u >> 2);
+  return (int)((w >> (8 * (u & 3))) & 0xffu) * 16;
+}
+
+// Streamed solve over the sparse records: the flow of solve_stream_kernel
+// (incoming rows through an LDS ring, forward results through the workspace,
+// recombination per chunk) with the factor columns taken from the records.
+// Each column's entry of a lane is read from the staged record at the
+// lane's rank among the column's set bits (or from a zero when its bit is
+// clear); the backward window has 64 rows, one per lane.  NBB: 16-byte loads
+// per lane of a backward record.
+template <int FW, int NBB, int K>
+__global__ void __launch_bounds__(kWave) solve_sparse_kernel(PencilArgs a, int plaunch,
+                                                             const double2* __restrict__ Bev, SparseFactors sf,
+                                                             double2* __restrict__ X) {
+  using T = double;
+  extern __shared__ double lds[];
+  constexpr int CH = kCH, G = 4, R = kSR, SU = kSpU, UPC = CH / SU, BW = kWave;
+  static_assert(R == SU && UPC % K == 0 && FW <= 16, "record geometry");
+  constexpr int SF = 1024 / 8, SB = NBB * 1024 / 8;  // doubles per stage buffer
+  const int lane = threadIdx.x;
+  const int p = blockIdx.x;
+  const SysDesc& d = a.desc;
+  const int N = d.N, S = d.S, ne = d.ne;
+  if (blockIdx.x == 0 && plaunch < a.P) zero_pencils(X, plaunch, a.P, S * N, lane, kWave);
+  if (p >= plaunch) return;
+  if (!pencil_active(a, p)) {
+    zero_pencils(X, p, p + 1, S * N, lane, kWave);
+    return;
+  }
+  const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
+  const double2* Bp = Bev + (size_t)p * ne * N;
+  const int npad = a.nst, nch = npad / CH, n = a.n, nu = npad / SU;
+  double* ring = lds;                       // [2 buffers][2 parts][64]
+  double* st = lds + 4 * kWave;             // record stage: two buffers
+  const int zoff = 2 * (SF > SB ? SF : SB); // a zero after the stage (read where a bit is clear)
+  if (lane == 0) st[zoff] = 0.0;
+  double* Y0 = a.ysp + (size_t)p * 2 * npad;
+  double* Y1 = Y0 + npad;
+  const uint8_t* Fr = sf.F + (size_t)p * nu * sf.strideF;
+  const uint8_t* Br = sf.B + (size_t)p * nu * sf.strideB;
+  const uint32_t lensF = ((const uint32_t*)(sf.lenF + (size_t)p * kSpLen))[lane];
+  const uint32_t lensB = ((const uint32_t*)(sf.lenB + (size_t)p * kSpLen))[lane];
+
+  // ---- forward ----
+  {
+    RecordRegs<1> r[K];
+    auto load_unit = [&](int k, int u) { r[k].load(Fr + (size_t)u * sf.strideF, record_bytes(lensF, u), lane); };
+#pragma unroll
+    for (int u = 0; u < K; ++u) load_unit(u, u < nu ? u : nu - 1);
+    // header of a record in registers: lane 0 holds the four mask words,
+    // lane 1 the two slot words
+    uint32_t mnx[4], wnx[2], wcur[2];
+    auto header = [&](const RecordRegs<1>& q) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mnx[i] = (uint32_t)__builtin_amdgcn_readlane((int)q.r[0][i], 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) wnx[i] = (uint32_t)__builtin_amdgcn_readlane((int)q.r[0][i], 1);
+    };
+    header(r[0]);
+    r[0].store(st, lane);
+    load_unit(0, K < nu ? K : nu - 1);
+    // entry of this lane in column c of the staged record in buffer b; la is
+    // the rank of the column's first entry in the record
+    int la = 0;
+    auto entry = [&](int b, int c) -> T {
+      const uint32_t m = (mnx[c >> 1] >> (16 * (c & 1))) & 0xffffu;
+      const int idx = la + (int)__builtin_amdgcn_mbcnt_lo(m, 0u);
+      la += __builtin_popcount(m);
+      const int off = __builtin_amdgcn_inverse_ballot_w64((uint64_t)m) ? b * SF + 4 + idx : zoff;
+      return st[off];
+    };
+    T rg[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) rg[k] = entry(0, k);
+    T w0, w1;
+    rhs_row(a, Bp, pc.mean, lane < FW ? lane : -1, w0, w1);
+    {
+      double i0, i1;
+      rhs_row(a, Bp, pc.mean, FW + lane, i0, i1);
+      ring[lane] = i0;
+      ring[kWave + lane] = i1;
+    }
+    for (int c = 0; c < nch; ++c) {
+      const int j0 = c * CH;
+      const double* in0 = ring + (c & 1) * 2 * kWave;
+      const double* in1 = in0 + kWave;
+      double q0, q1;
+      rhs_row(a, Bp, pc.mean, j0 + CH + FW + lane, q0, q1);
+      T n0[2][G], n1[2][G];
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        n0[0][k] = in0[k];
+        n1[0][k] = in1[k];
+      }
+      uint32_t word = 0;
+      T ya0 = (T)0, ya1 = (T)0;
+      static_for<0, CH / G>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (g + 1 < CH / G) {
+#pragma unroll
+          for (int k = 0; k < G; ++k) {
+            n0[(g + 1) & 1][k] = in0[(g + 1) * G + k];
+            n1[(g + 1) & 1][k] = in1[(g + 1) * G + k];
+          }
+        }
+        static_for<0, G>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          constexpr int t = g * G + k;
+          if constexpr (t % SU == 0) {
+            // unit i = c UPC + t / SU starts: unit i + 1 to the stage, its
+            // header to scalars, unit i + 1 + K requested
+            const int vk = c * UPC + t / SU + 1 + K;
+            constexpr int rs = (t / SU + 1) % K;
+            wcur[0] = wnx[0];
+            wcur[1] = wnx[1];
+            header(r[rs]);
+            r[rs].store(st + ((t / SU + 1) & 1) * SF, lane);
+            load_unit(rs, vk < nu ? vk : nu - 1);
+            la = 0;
+          }
+          if constexpr ((t & 3) == 0) word = wcur[(t % SU) >> 2];
+          const int s = (word >> (8 * (t & 3))) & 0xff;
+          const T y0 = readlane_t(w0, s), y1 = readlane_t(w1, s);
+          put_lane<t>(ya0, y0);
+          put_lane<t>(ya1, y1);
+          const T l = rg[t % R];
+          constexpr int tn = t + R;
+          rg[t % R] = entry((tn / SU) & 1, tn % SU);
+          const bool inw = __builtin_amdgcn_inverse_ballot_w64(1ull << s);
+          const T ws0 = inw ? n0[g & 1][k] : w0;
+          const T ws1 = inw ? n1[g & 1][k] : w1;
+          w0 = fma(-l, y0, ws0);
+          w1 = fma(-l, y1, ws1);
+        });
+      });
+      Y0[j0 + lane] = ya0;
+      Y1[j0 + lane] = ya1;
+      double* nx = ring + ((c + 1) & 1) * 2 * kWave;
+      nx[lane] = q0;
+      nx[kWave + lane] = q1;
+    }
+  }
+  // the workspace rows written above are read back below by this wavefront
+  __threadfence_block();
+
+  // ---- backward ----
+  {
+    RecordRegs<NBB> r[K];
+    auto load_unit = [&](int k, int v) {  // v-th unit from the top
+      const int u = v < nu ? nu - 1 - v : 0;
+      r[k].load(Br + (size_t)u * sf.strideB, record_bytes(lensB, u), lane);
+    };
+#pragma unroll
+    for (int v = 0; v < K; ++v) load_unit(v, v);
+    // header: lanes 0 .. 3 hold the eight 64-bit masks (two per lane)
+    uint64_t mb[kSpU];
+    auto header = [&](const RecordRegs<NBB>& q) {
+#pragma unroll
+      for (int i = 0; i < kSpU; ++i) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)q.r[0][2 * (i & 1)], i >> 1);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)q.r[0][2 * (i & 1) + 1], i >> 1);
+        mb[i] = ((uint64_t)hi << 32) | lo;
+      }
+    };
+    header(r[0]);
+    r[0].store(st, lane);
+    load_unit(0, K);
+    int la = 0;
+    auto entry = [&](int b, int cpos) -> T {
+      const uint64_t m = mb[cpos];
+      const int idx =
+          la + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      la += __builtin_popcountll(m);
+      const int off = __builtin_amdgcn_inverse_ballot_w64(m) ? b * SB + 8 + idx : zoff;
+      return st[off];
+    };
+    T rg[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) rg[k] = entry(0, SU - 1 - k);
+    const int r0 = window_start_row<BW>(npad, lane);
+    T w0 = Y0[r0], w1 = Y1[r0];
+    {
+      const int rr = (nch - 1) * CH - BW + lane;  // incoming rows of the last chunk
+      ring[lane] = rr >= 0 ? Y0[rr] : 0.0;
+      ring[kWave + lane] = rr >= 0 ? Y1[rr] : 0.0;
+    }
+    const int S2 = 2 * S;
+    T xp0 = (T)0, xp1 = (T)0;  // x~ of the chunk above
+    for (int c = nch - 1; c >= 0; --c) {
+      const int j0 = c * CH;
+      const int bsel = (nch - 1 - c) & 1;
+      const double* in0 = ring + bsel * 2 * kWave;
+      const double* in1 = in0 + kWave;
+      double q0 = 0.0, q1 = 0.0;
+      {
+        const int rr = j0 - CH - BW + lane;  // the next (lower) chunk's incoming rows
+        if (c > 0 && rr >= 0) {
+          q0 = Y0[rr];
+          q1 = Y1[rr];
+        }
+      }
+      constexpr int NG = CH / G;
+      T n0[2][G], n1[2][G];
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        n0[(NG - 1) & 1][k] = in0[(NG - 1) * G + k];
+        n1[(NG - 1) & 1][k] = in1[(NG - 1) * G + k];
+      }
+      T xa0 = (T)0, xa1 = (T)0;
+      static_for<0, NG>([&](auto gc) {
+        constexpr int g = NG - 1 - decltype(gc)::value;
+        if (g > 0) {
+#pragma unroll
+          for (int k = 0; k < G; ++k) {
+            n0[(g - 1) & 1][k] = in0[(g - 1) * G + k];
+            n1[(g - 1) & 1][k] = in1[(g - 1) * G + k];
+          }
+        }
+        static_for<0, G>([&](auto kc) {
+          constexpr int k = G - 1 - decltype(kc)::value;
+          constexpr int t = g * G + k;
+          constexpr int q = CH - 1 - t;
+          if constexpr (q % SU == 0) {
+            const int vk = UPC * (nch - 1 - c) + q / SU + 1 + K;
+            constexpr int rs = (q / SU + 1) % K;
+            header(r[rs]);
+            r[rs].store(st + ((q / SU + 1) & 1) * SB, lane);
+            load_unit(rs, vk);
+            la = 0;
+          }
+          constexpr uint64_t msj = 1ull << t;
+          const T u = rg[q % R];
+          constexpr int qn = q + R;
+          rg[q % R] = entry((qn / SU) & 1, SU - 1 - qn % SU);
+          const T x0 = readlane_t(w0 * u, t), x1 = readlane_t(w1 * u, t);
+          put_lane<t>(xa0, x0);
+          put_lane<t>(xa1, x1);
+          const bool inw = __builtin_amdgcn_inverse_ballot_w64(msj);
+          w0 = inw ? n0[g & 1][k] : fma(-u, x0, w0);
+          w1 = inw ? n1[g & 1][k] : fma(-u, x1, w1);
+        });
+      });
+      // X = P^R x~ for the chunk's columns j0 + lane
+      {
+        const int sl2 = (lane + S2) & (kWave - 1);
+        const bool here = lane + S2 < kWave;
+        const T a0 = __shfl(xa0, sl2), b0 = __shfl(xp0, sl2);
+        const T a1 = __shfl(xa1, sl2), b1 = __shfl(xp1, sl2);
+        const int col = j0 + lane;
+        if (col < n) {
+          const int m = col / S, pos = col - m * S;
+          double v0 = xa0, v1 = xa1;
+          if (m + 2 < N) {
+            v0 -= here ? a0 : b0;
+            v1 -= here ? a1 : b1;
+          }
+          const int var = d.var_at[pos];
+          const double2 xv = (var == VU || var == VUZ || var == VV || var == VVZ) ? make_double2(v1, -v0)
+                                                                                  : make_double2(v0, v1);
+          X[((size_t)p * S + d.abi_index[var]) * N + m] = xv;
+        }
+      }
+      xp0 = xa0;
+      xp1 = xa1;
+      double* nx = ring + (bsel ^ 1) * 2 * kWave;
+      nx[lane] = q0;
+      nx[kWave + lane] = q1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Refined mixed-precision solve: FP32 sweeps on FP32 copies of the FP64
 // factors, the FP64 residual r = b - A x^ of the first solution (A applied
 // from the operator templates, every row including the boundary rows; b
@@ -1646,6 +2045,65 @@ hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, 
   if (a.FW == F && a.BW == B) return launch_solve_t<F, B>(a, Bev, Lf, sl, Uf, X, st);
   STAU_SWEEP_VARIANTS(STAU_CASE)
 #undef STAU_CASE
+  return hipErrorInvalidValue;
+}
+
+// Sparse records where the streamed solve runs: the single-block FP64 solve
+// with more than 32 pencils per compute unit, forward windows of at most 16
+// rows, at most kSpLen units and backward records of at most three KiB.
+bool sparse_records_apply(const PencilArgs& a, SparseFactors* geom) {
+  const int nu = a.nst / kSpU, kv = a.kl + a.ku;
+  const int sf = (32 + 64 * a.kl + 15) / 16 * 16, sb = (64 + 64 * (kv + 1) + 15) / 16 * 16;
+  int dev = 0, cus = 0;
+  if (!a.ysp || a.trans || a.blk != 0 || a.FW > 16 || nu > kSpLen || sb > 3 * 1024 || sf > 1024 ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return false;
+  const int plaunch = a.desc.dim == 2 ? a.Px - 1 : a.P;
+  if (plaunch < 32 * cus) return false;
+  if (geom) {
+    geom->strideF = sf;
+    geom->strideB = sb;
+  }
+  return true;
+}
+
+hipError_t launch_sparse_records(const PencilArgs& a, const double* Lf, const uint8_t* sl, const double* Uf,
+                                 const SparseFactors& sf, hipStream_t st) {
+#define STAU_CASE(F, B)                                                                               \
+  if (a.FW == F && a.BW == B) {                                                                       \
+    hipLaunchKernelGGL((sparse_records_kernel<F, B>), dim3(a.P), dim3(kWave), 0, st, a, Lf, sl, Uf, sf); \
+    return hipGetLastError();                                                                         \
+  }
+  STAU_SWEEP_VARIANTS(STAU_CASE)
+#undef STAU_CASE
+  return hipErrorInvalidValue;
+}
+
+template <int FW, int NBB>
+static hipError_t launch_solve_sparse_t(const PencilArgs& a, const void* Bev, const SparseFactors& sf, void* X,
+                                        hipStream_t st) {
+  const int plaunch = a.desc.dim == 2 ? a.Px - 1 : a.P;
+  const size_t stage = (size_t)2 * (NBB > 1 ? NBB : 1) * 1024;
+  const size_t lds = (size_t)4 * kWave * sizeof(double) + stage + 16;
+  hipLaunchKernelGGL((solve_sparse_kernel<FW, NBB, 4>), dim3(plaunch), dim3(kWave), lds, st, a, plaunch,
+                     (const double2*)Bev, sf, (double2*)X);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_sparse(const PencilArgs& a, const void* Bev, const SparseFactors& sf, void* X,
+                               hipStream_t st) {
+  const int nbb = (sf.strideB + 1023) / 1024;
+  if (a.FW == 8) {
+    if (nbb == 1) return launch_solve_sparse_t<8, 1>(a, Bev, sf, X, st);
+    if (nbb == 2) return launch_solve_sparse_t<8, 2>(a, Bev, sf, X, st);
+    if (nbb == 3) return launch_solve_sparse_t<8, 3>(a, Bev, sf, X, st);
+  }
+  if (a.FW == 16) {
+    if (nbb == 1) return launch_solve_sparse_t<16, 1>(a, Bev, sf, X, st);
+    if (nbb == 2) return launch_solve_sparse_t<16, 2>(a, Bev, sf, X, st);
+    if (nbb == 3) return launch_solve_sparse_t<16, 3>(a, Bev, sf, X, st);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -39,6 +39,19 @@ struct PencilArgs {
   int var_of_abi[9];
 };
 
+// Sparse records of one factor slot for the streamed solve (k_pencil.hip):
+// per pencil, units of kSpU columns at fixed strides, record lengths in
+// 16-byte words (kSpLen bytes per pencil and direction).
+constexpr int kSpU = 8;
+constexpr int kSpLen = 256;
+struct SparseFactors {
+  uint8_t* F;      // forward records [P][nst / kSpU][strideF]
+  uint8_t* B;      // backward records [P][nst / kSpU][strideB]
+  uint8_t* lenF;   // [P][kSpLen]
+  uint8_t* lenB;   // [P][kSpLen]
+  int strideF, strideB;
+};
+
 struct XformArgs {
   int dim;
   int N, M;          // Chebyshev modes, dealiased z grid
@@ -127,6 +140,14 @@ hipError_t launch_evp(const PencilArgs& a, double tau, int nev, int ncv, int max
                       const EvpOut& o, hipStream_t st);
 hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, const uint8_t* sl,
                         const double* Uf, void* X, hipStream_t st);
+// Sparse factor records (k_pencil.hip): whether the streamed solve runs for
+// a (and then the record strides in geom), the packing of a slot's
+// whole-band factors after its factorisation, and the solve over them
+bool sparse_records_apply(const PencilArgs& a, SparseFactors* geom);
+hipError_t launch_sparse_records(const PencilArgs& a, const double* Lf, const uint8_t* sl, const double* Uf,
+                                 const SparseFactors& sf, hipStream_t st);
+hipError_t launch_solve_sparse(const PencilArgs& a, const void* Bev, const SparseFactors& sf, void* X,
+                               hipStream_t st);
 // Mixed-precision solve with one FP64 refinement: FP32 sweeps on the FP32
 // factor copies, the FP64 residual of (a.refine_a0 M~ + a.refine_b0 L~) from
 // the templates, an FP32 correction sweep, the sum in FP64

@@ -213,6 +213,10 @@ struct stau_pencils {
     float *L32raw = nullptr, *U32raw = nullptr, *Lf32 = nullptr, *Uf32 = nullptr;
     float *LT32raw = nullptr, *UT32raw = nullptr, *LB32raw = nullptr, *UB32raw = nullptr;
     float *LfT32 = nullptr, *UfT32 = nullptr, *LfB32 = nullptr, *UfB32 = nullptr;
+    // sparse records of the factors for the streamed solve (allocated on the
+    // first factorisation into the slot where they apply)
+    SparseFactors sf{};
+    bool sparse = false;
     bool valid = false;
     double a0 = 0.0, b0 = 0.0;
     int64_t stamp = 0;
@@ -244,6 +248,9 @@ struct stau_pencils {
   double last_a0 = 0.0, last_b0 = 0.0;
   double* tpl = nullptr;   // device: band templates of the operator (PencilArgs::tpl)
   double* ysp = nullptr;   // device: streamed-solve vectors (PencilArgs::ysp)
+  // the step's factors also as sparse records (streamed solve), with their strides
+  bool sparse_ok = false;
+  SparseFactors sgeom{};
   int* sing = nullptr;     // device: first singular pencil (INT_MAX if none)
   int* flag = nullptr;     // device: non-finite flag
   double* scratch = nullptr;
@@ -325,6 +332,8 @@ int stau_create_domain(const stau_domain_desc* desc, stau_domain** out) {
     return fail(STAU_EINVAL, "dct_method %d unknown", d.dct_method);
   if (d.mixed_solve < STAU_SOLVE_AUTO || d.mixed_solve > STAU_SOLVE_REFINED)
     return fail(STAU_EINVAL, "mixed_solve %d unknown", d.mixed_solve);
+  if (d.factor_layout != STAU_FACTORS_AUTO && d.factor_layout != STAU_FACTORS_BAND)
+    return fail(STAU_EINVAL, "factor_layout %d unknown", d.factor_layout);
   if (d.dct_method == STAU_DCT_MATMUL && !mm_supported((int)d.Nz))
     return fail(STAU_EUNSUPPORTED, "matrix-product z transforms need Nz a multiple of 32 in [32, 256]");
   if (d.dct_method == STAU_DCT_MATMUL && d.precision == STAU_MIXED && !mm_bf16_supported((int)d.Nz))
@@ -465,6 +474,7 @@ static void free_pencils(stau_pencils* p) {
       hipFree(f.Lraw);
       hipFree(f.sraw);
       hipFree(f.Uraw);
+      for (void* q : {(void*)f.sf.F, (void*)f.sf.B, (void*)f.sf.lenF, (void*)f.sf.lenB}) (void)hipFree(q);
       for (void* q : {(void*)f.LTraw, (void*)f.UTraw, (void*)f.LBraw, (void*)f.UBraw, (void*)f.sTraw,
                       (void*)f.sBraw, (void*)f.tLt, (void*)f.tLb, (void*)f.Rinv, (void*)f.E1,
                       (void*)f.E2, (void*)f.tPt, (void*)f.tPb, (void*)f.L32raw, (void*)f.U32raw,
@@ -813,6 +823,8 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
     return fail(STAU_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
   pa.ysp = pen->ysp;
+  pen->sparse_ok = d.factor_layout == STAU_FACTORS_AUTO && !pen->two && !pen->refined &&
+                   sparse_records_apply(pa, &pen->sgeom);
   pen->ws_bytes = (int64_t)(szG + szG2 + szGb + szH + szB + szF + szScratch + szY);
   {
     // KE functional weights: integral over z in [0, 1] of T_m = 1 / (1 - m^2), m even
@@ -866,6 +878,7 @@ static int factor_into(stau_pencils* pen, stau_pencils::FactorSlot* set, const P
                        int k, double a0, double b0, hipStream_t st) {
   auto& f = set[k];
   f.valid = false;
+  f.sparse = false;
   const int big = 0x7fffffff;
   HIP_TRY(hipMemcpyAsync(pen->sing, &big, sizeof(int), hipMemcpyHostToDevice, st));
   const bool trans = set == pen->slotT;
@@ -879,6 +892,20 @@ static int factor_into(stau_pencils* pen, stau_pencils::FactorSlot* set, const P
         const size_t cols = (size_t)pa.P * pa.nst + 2 * (size_t)factor_slack();
         e = launch_round_f32(f.Lraw, f.L32raw, cols * pa.FW, st);
         if (e == hipSuccess) e = launch_round_f32(f.Uraw, f.U32raw, cols * pa.BW, st);
+      }
+      if (e == hipSuccess && pen->sparse_ok && set == pen->slot) {
+        if (!f.sf.F) {
+          SparseFactors g = pen->sgeom;
+          const size_t units = (size_t)pa.P * (pa.nst / kSpU), lens = (size_t)pa.P * kSpLen;
+          e = hipMalloc((void**)&g.F, units * g.strideF);
+          if (e == hipSuccess) e = hipMalloc((void**)&g.B, units * g.strideB);
+          if (e == hipSuccess) e = hipMalloc((void**)&g.lenF, lens);
+          if (e == hipSuccess) e = hipMalloc((void**)&g.lenB, lens);
+          f.sf = g;  // (freed with the slot, also after a failed allocation)
+          if (e == hipSuccess) pen->ws_bytes += (int64_t)(units * (g.strideF + g.strideB) + 2 * lens);
+        }
+        if (e == hipSuccess) e = launch_sparse_records(pa, f.Lf, f.sl, f.Uf, f.sf, st);
+        f.sparse = e == hipSuccess;
       }
       return e;
     }
@@ -1021,6 +1048,7 @@ static hipError_t solve_launch(stau_pencils* pen, const stau_pencils::FactorSlot
   if (pen->two)
     return launch_solve2(pen->pt, pen->pb, B, fs->LfT, fs->slT, fs->UfT, fs->LfB, fs->slB, fs->UfB,
                          fs->Rinv, fs->E1, fs->E2, X, st);
+  if (fs->sparse) return launch_solve_sparse(pen->pa, B, fs->sf, X, st);
   return launch_solve(pen->pa, B, fs->Lf, fs->sl, fs->Uf, X, st);
 }
 
@@ -1411,7 +1439,10 @@ int stau_solve(stau_pencils* pen, const void* B_ev, void* X, void* stream) {
     HIP_TRY(launch_solve2(pen->pt, pen->pb, B_ev, f->LfT, f->slT, f->UfT, f->LfB, f->slB, f->UfB, f->Rinv,
                           f->E1, f->E2, X, (hipStream_t)stream));
   else
-    HIP_TRY(launch_solve(pen->pa, B_ev, f->Lf, f->sl, f->Uf, X, (hipStream_t)stream));
+    if (f->sparse)
+      HIP_TRY(launch_solve_sparse(pen->pa, B_ev, f->sf, X, (hipStream_t)stream));
+    else
+      HIP_TRY(launch_solve(pen->pa, B_ev, f->Lf, f->sl, f->Uf, X, (hipStream_t)stream));
   return STAU_OK;
 }
 
