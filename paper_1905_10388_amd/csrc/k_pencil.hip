@@ -1062,10 +1062,22 @@ __global__ void __launch_bounds__(kWave) solve_sparse_kernel(PencilArgs a, int p
   const PencilCoef pc = pencil_coef(a, p, 0.0, 0.0);
   const double2* Bp = Bev + (size_t)p * ne * N;
   const int npad = a.nst, nch = npad / CH, n = a.n, nu = npad / SU;
-  double* ring = lds;                       // [2 buffers][2 parts][64]
-  double* st = lds + 4 * kWave;             // record stage: two buffers
-  const int zoff = 2 * (SF > SB ? SF : SB); // a zero after the stage (read where a bit is clear)
+  // LDS: the ring of incoming rows [2 buffers][2 parts][64], the record stage
+  // (two buffers) and a zero read where a mask bit is clear
+  double* ring = lds;
+  double* st = lds + 4 * kWave;
+  const int zoff = 2 * (SF > SB ? SF : SB);
   if (lane == 0) st[zoff] = 0.0;
+  const uint32_t zaddr = (uint32_t)((4 * kWave + zoff) * sizeof(double));  // byte address in LDS
+  // entry of this lane in a record column with mask m: the value at the
+  // lane's rank among the set bits after the column's first rank la (a byte
+  // offset in the stage buffer, so one shift-add forms the address)
+  auto ld_entry = [&](uint64_t m, uint32_t rank, int first_byte) -> T {
+    const uint32_t addr = (rank << 3) + (uint32_t)first_byte;
+    const uint32_t sel = __builtin_amdgcn_inverse_ballot_w64(m) ? addr : zaddr;
+    // the dynamic LDS array starts at LDS address 0 (no static LDS in this kernel)
+    return *(const __attribute__((address_space(3))) T*)(size_t)sel;
+  };
   double* Y0 = a.ysp + (size_t)p * 2 * npad;
   double* Y1 = Y0 + npad;
   const uint8_t* Fr = sf.F + (size_t)p * nu * sf.strideF;
@@ -1096,10 +1108,9 @@ __global__ void __launch_bounds__(kWave) solve_sparse_kernel(PencilArgs a, int p
     int la = 0;
     auto entry = [&](int b, int c) -> T {
       const uint32_t m = (mnx[c >> 1] >> (16 * (c & 1))) & 0xffffu;
-      const int idx = la + (int)__builtin_amdgcn_mbcnt_lo(m, 0u);
+      const T v = ld_entry(m, __builtin_amdgcn_mbcnt_lo(m, 0u), (4 * kWave + b * SF + 4 + la) * 8);
       la += __builtin_popcount(m);
-      const int off = __builtin_amdgcn_inverse_ballot_w64((uint64_t)m) ? b * SF + 4 + idx : zoff;
-      return st[off];
+      return v;
     };
     T rg[R];
 #pragma unroll
@@ -1155,10 +1166,10 @@ __global__ void __launch_bounds__(kWave) solve_sparse_kernel(PencilArgs a, int p
           const T y0 = readlane_t(w0, s), y1 = readlane_t(w1, s);
           put_lane<t>(ya0, y0);
           put_lane<t>(ya1, y1);
+          const bool inw = __builtin_amdgcn_inverse_ballot_w64(1ull << s);
           const T l = rg[t % R];
           constexpr int tn = t + R;
           rg[t % R] = entry((tn / SU) & 1, tn % SU);
-          const bool inw = __builtin_amdgcn_inverse_ballot_w64(1ull << s);
           const T ws0 = inw ? n0[g & 1][k] : w0;
           const T ws1 = inw ? n1[g & 1][k] : w1;
           w0 = fma(-l, y0, ws0);
@@ -1200,11 +1211,10 @@ __global__ void __launch_bounds__(kWave) solve_sparse_kernel(PencilArgs a, int p
     int la = 0;
     auto entry = [&](int b, int cpos) -> T {
       const uint64_t m = mb[cpos];
-      const int idx =
-          la + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      const T v = ld_entry(m, rank, (4 * kWave + b * SB + 8 + la) * 8);
       la += __builtin_popcountll(m);
-      const int off = __builtin_amdgcn_inverse_ballot_w64(m) ? b * SB + 8 + idx : zoff;
-      return st[off];
+      return v;
     };
     T rg[R];
 #pragma unroll
@@ -2086,7 +2096,10 @@ static hipError_t launch_solve_sparse_t(const PencilArgs& a, const void* Bev, co
   const int plaunch = a.desc.dim == 2 ? a.Px - 1 : a.P;
   const size_t stage = (size_t)2 * (NBB > 1 ? NBB : 1) * 1024;
   const size_t lds = (size_t)4 * kWave * sizeof(double) + stage + 16;
-  hipLaunchKernelGGL((solve_sparse_kernel<FW, NBB, 4>), dim3(plaunch), dim3(kWave), lds, st, a, plaunch,
+  // two records in flight per direction: 127 VGPRs, four wavefronts per SIMD
+  // (four records, 163 VGPRs and three wavefronts, measured 5 % slower at
+  // 256 x 256 x 128)
+  hipLaunchKernelGGL((solve_sparse_kernel<FW, NBB, 2>), dim3(plaunch), dim3(kWave), lds, st, a, plaunch,
                      (const double2*)Bev, sf, (double2*)X);
   return hipGetLastError();
 }
