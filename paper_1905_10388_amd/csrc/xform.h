@@ -118,7 +118,6 @@ __device__ __forceinline__ double ky_at(const XformArgs& a, const PencilBase& b,
 constexpr int kZPts = 3072;
 constexpr int kZThreads = 256;
 constexpr int kZEpt = kZPts / kZThreads;
-constexpr int kZBlocksPerCU = 3;  // half-size tiles below this many full-size blocks per CU
 
 template <typename T>
 __device__ __forceinline__ void stage_z_tables(const XformArgs& a, cpx<T>* twl, cpx<T>* dcl, int M,
@@ -146,18 +145,23 @@ inline int x_threads(int L) {
   return nt;
 }
 
-// Half-size z tiles (kZPts / 2 points, 6 per thread) when the full-size grid
-// has fewer than kZBlocksPerCU blocks per compute unit: more, smaller blocks
-// keep every unit busy (1024x256: z backward 28.2 -> 24.9 us, z forward 30.8 ->
-// 25.7 us; quarter tiles measured no better).  Returns the divisor (1 or 2).
-inline int z_split(int blocks, int M, int per_cu = kZBlocksPerCU) {
+// Half-size z tiles (kZPts / 2 points, 6 per thread).  With few blocks per
+// compute unit, more and smaller blocks keep every unit busy (1024x256: z
+// backward 28.2 -> 24.9 us, z forward 30.8 -> 25.7 us; quarter tiles measured
+// no better); with many, the half tile's LDS (30 instead of 55 KB at M = 192)
+// holds five blocks per unit instead of two (256x256x128, about 100 blocks
+// per unit: z backward 602 -> 454 us, z forward unchanged).  So the step's
+// transforms (per_cu = 0) always take them; the adjoint's transforms
+// (per_cu > 0) take them when the full-size grid has fewer than per_cu blocks
+// per compute unit.  Returns the divisor (1 or 2).
+inline int z_split(int blocks, int M, int per_cu = 0) {
+  if (M > kZPts / 2) return 1;
+  if (per_cu == 0) return 2;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 1;
-  int d = 1;
-  if (M <= kZPts / 2 && blocks < per_cu * cus) d = 2;
-  return d;
+  return blocks < per_cu * cus ? 2 : 1;
 }
 
 
