@@ -264,8 +264,9 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
 // ys (0: the default above) replaces the output scale: 1 / Ngy of the forward
 // transform, 1 of the backward one (the adjoint grid transforms use the
 // other's).
-// NGC > 0: Ngy = NGC fixed at compile time, TK = 3072 / NGC.
-template <int DIR, int MAXBF, typename T, int NGC = 0>
+// NGC > 0: Ngy = NGC fixed at compile time, TK = PB / NGC (PB points per
+// block, PB / 256 per thread).
+template <int DIR, int MAXBF, typename T, int NGC = 0, int PB = 3072>
 __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
                                                     const typename V2<T>::type* __restrict__ In,
                                                     typename V2<T>::type* __restrict__ Out, int TKr,
@@ -273,7 +274,7 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
   extern __shared__ double2 smem[];
   using cT = cpx<T>;
   cT* buf = (cT*)smem;
-  const int TK = NGC > 0 ? 3072 / NGC : TKr;
+  const int TK = NGC > 0 ? PB / NGC : TKr;
   // Blocks go to the eight XCDs (each with its own L2) in turn by linear
   // index; the neighbouring kx tiles of a row share the cache lines at their
   // ends (rows of Px values are not line-aligned), so the linear index is
@@ -317,9 +318,9 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
     return v;
   };
   if constexpr (NGC > 0) {
-    // TK * Ng = 3072 points, 12 per thread: every load issued before the
-    // first LDS store, so that their latencies overlap
-    constexpr int EPT = 3072 / 256;
+    // TK * Ng = PB points, PB / 256 per thread: every load issued before
+    // the first LDS store, so that their latencies overlap
+    constexpr int EPT = PB / 256;
     cT v[EPT];
 #pragma unroll
     for (int it = 0; it < EPT; ++it) v[it] = load(tid + it * 256);
@@ -608,10 +609,14 @@ hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs
 
 hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, void* Out,
                         hipStream_t st, bool fp32, double ys) {
-  const int TK = a.Ngy >= 3072 ? 1 : 3072 / a.Ngy;
+  // Ny = 256 (384 padded points) with the length fixed at compile time; FP64
+  // tiles of 4 kx (1536 points, 24 KB of LDS: six blocks per compute unit
+  // instead of three with tiles of 8)
+  const bool c384 = a.Ngy == 384;
+  const int pb = c384 && !fp32 ? 1536 : 3072;
+  const int TK = a.Ngy >= pb ? 1 : pb / a.Ngy;
   dim3 grid((a.Px + TK - 1) / TK, a.M, nf);
   const size_t lds = (size_t)TK * a.Ngy * (fp32 ? sizeof(float2) : sizeof(double2));
-  // Ny = 256 (384 padded points) with the length fixed at compile time
   auto go = [&](auto kern, auto in, auto out) {
     hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a, in, out, TK, ys);
   };
@@ -620,9 +625,14 @@ hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, voi
     using S2 = typename V2<TT>::type;
     const S2* in = (const S2*)In;
     S2* out = (S2*)Out;
-    if (a.Ngy == 384) {
-      if (dir > 0) go(ypass_kernel<+1, 3, TT, 384>, in, out);
-      else go(ypass_kernel<-1, 3, TT, 384>, in, out);
+    if (c384) {
+      if constexpr (sizeof(TT) == 8) {
+        if (dir > 0) go(ypass_kernel<+1, 2, TT, 384, 1536>, in, out);
+        else go(ypass_kernel<-1, 2, TT, 384, 1536>, in, out);
+      } else {
+        if (dir > 0) go(ypass_kernel<+1, 3, TT, 384>, in, out);
+        else go(ypass_kernel<-1, 3, TT, 384>, in, out);
+      }
     } else {
       if (dir > 0) go(ypass_kernel<+1, 3, TT>, in, out);
       else go(ypass_kernel<-1, 3, TT>, in, out);
