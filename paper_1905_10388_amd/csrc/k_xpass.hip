@@ -366,8 +366,12 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
   const size_t R = (size_t)a.M * a.Ngy;
   const int tid = threadIdx.x;
   const cT* twg = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
+  // the twiddles the passes read: indices below L / R of the smallest radix
+  // (the compile-time 384-point plan is 6 x 8 x 8: the first 64 entries)
+  constexpr int TWC = LC == 384 ? 64 : 0;
+  const int tn = TWC > 0 ? TWC : L;
   cT* twl = buf + 4 * L;
-  for (int i = tid; i < L; i += NT) twl[i] = twg[i];
+  for (int i = tid; i < tn; i += NT) twl[i] = twg[i];
   cT sa[4][KPT], sb[4][KPT];
   auto fetch = [&](int slot, int k) {
     int fa, da, fb, db;
@@ -507,11 +511,13 @@ static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipS
   // points), when four sequences and the twiddles fit 64 KB
   if constexpr (DIM == 3 && NT <= 512) {
     constexpr int PTS3 = (PTS + 1) / 2;
-    const size_t lds3 = (size_t)5 * a.L * sizeof(S2);
+    const bool c384 = a.L == 384 && 2 * NT * PTS3 >= 384;
+    const size_t lds3 = ((size_t)4 * a.L + (c384 ? 64 : a.L)) * sizeof(S2);
     if (lds3 <= 64 * 1024 && a.L <= 2 * NT * PTS3) {
       // the 256 x 256 workload's 384-point rows with their length fixed
-      auto fn = a.L == 384 && 2 * NT * PTS3 >= 384 ? xrow3_kernel<2 * NT, PTS3, 2 * MAXBF, T, 384>
-                                                   : xrow3_kernel<2 * NT, PTS3, 2 * MAXBF, T, 0>;
+      // (and 64 twiddles in LDS: 25 KB per block, six blocks per unit)
+      auto fn = c384 ? xrow3_kernel<2 * NT, PTS3, 2 * MAXBF, T, 384>
+                     : xrow3_kernel<2 * NT, PTS3, 2 * MAXBF, T, 0>;
       allow_lds((const void*)fn, lds3);
       hipLaunchKernelGGL(fn, grid, dim3(2 * NT), lds3, st, a, (const S2*)G, (S2*)H);
       return hipGetLastError();
