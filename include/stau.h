@@ -53,6 +53,7 @@ extern "C" {
 #define STAU_ESTATE 5        /* call not valid in the current state */
 #define STAU_EUNSUPPORTED 6  /* size or option not supported */
 #define STAU_ENONFINITE 7    /* non-finite value detected by stau_check */
+#define STAU_EBOUNDS 8       /* index check failed (check builds only, reported by stau_check) */
 
 #define STAU_FP64 0
 #define STAU_MIXED 1
@@ -342,7 +343,13 @@ int stau_nonlinear(stau_pencils* pen, const void* X, void* F, void* stream);
 int stau_solve(stau_pencils* pen, const void* B_ev, void* X, void* stream);
 
 /* Synchronise and check the device error flag and the state for non-finite
- * values.  Returns STAU_ENONFINITE if X holds a NaN/Inf. */
+ * values.  Returns STAU_ENONFINITE if X holds a NaN/Inf.  In the check build
+ * (libstau_check.so, compiled with STAU_CHECK_BOUNDS) the kernels also record
+ * index checks (the factorisation's pivot offsets within the band, the
+ * forward sweeps' window slots, the sparse factor records' sizes and ranks)
+ * in a word per pencils object; stau_check then returns STAU_EBOUNDS if any
+ * failed since stau_build_pencils.  A failed check never traps: the kernels
+ * carry on, and the result of that call is not to be trusted. */
 int stau_check(stau_pencils* pen, const void* X, void* stream);
 
 /* Kinetic-energy functional J = (1/V) int |u|^2 / 2 evaluated on the 3/2 grid

@@ -38,11 +38,13 @@ class RBSolver:
     def __init__(self, Nx: int, Nz: int, Lx: float, Ra: float, Pr: float, *, dim: int = 2,
                  Ny: int = 1, Ly: float = 1.0, precision: str = "fp64", buoyancy: float = 1.0,
                  b_bottom: float = 1.0, b_top: float = 0.0, device: int = 0, dct: str = "auto",
-                 gamma=(), mixed_solve: str = "auto", factor_layout: str = "auto"):
+                 gamma=(), mixed_solve: str = "auto", factor_layout: str = "auto",
+                 library: str = "default"):
         import torch
 
         self._torch = torch
-        lib = _lib.load()
+        # "check": the check build (the kernels' index checks, reported by check())
+        lib = _lib.load({"default": _lib.LIB_PATH, "check": _lib.LIB_CHECK_PATH}[library])
         self.lib = lib
         desc = _lib.DomainDesc(dim=dim, precision={"fp64": _lib.STAU_FP64, "mixed": _lib.STAU_MIXED}[precision],
                                Nx=Nx, Ny=Ny, Nz=Nz, Lx=Lx, Ly=Ly, dealias=1.5, device=device,
@@ -56,7 +58,7 @@ class RBSolver:
         if len(gamma) > 4:
             raise ValueError("at most 4 Chebyshev terms of Gamma(z)")
         self._dom = C.c_void_p()
-        _lib.check(lib.stau_create_domain(C.byref(desc), C.byref(self._dom)))
+        self._ok(lib.stau_create_domain(C.byref(desc), C.byref(self._dom)))
         par = _lib.RBParamsC(Ra=Ra, Pr=Pr, buoyancy=buoyancy, b_bottom=b_bottom, b_top=b_top,
                              n_gamma=len(gamma), gamma=(C.c_double * 4)(*(gamma + (0.0,) * (4 - len(gamma)))))
         self._pen = C.c_void_p()
@@ -65,9 +67,9 @@ class RBSolver:
             lib.stau_destroy_domain(self._dom)
             self._dom = None  # destroyed: close() must not free it again
             self._pen = None
-            _lib.check(rc)
+            self._ok(rc)
         info = _lib.InfoC()
-        _lib.check(lib.stau_query(self._pen, C.byref(info)))
+        self._ok(lib.stau_query(self._pen, C.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in _lib.InfoC._fields_}
         self.dim = dim
         self.device = torch.device("cuda", device)
@@ -85,11 +87,14 @@ class RBSolver:
                                dt_prev=0.0, head=0)
 
     # -- lifetime ---------------------------------------------------------
+    def _ok(self, rc):
+        _lib.check(rc, self.lib)
+
     def query(self):
         """Sizes of the domain as stau_query reports them now (the workspace
         grows when factor storage is allocated on first use)."""
         info = _lib.InfoC()
-        _lib.check(self.lib.stau_query(self._pen, C.byref(info)))
+        self._ok(self.lib.stau_query(self._pen, C.byref(info)))
         return {f: getattr(info, f) for f, _ in _lib.InfoC._fields_}
 
     def close(self):
@@ -129,7 +134,7 @@ class RBSolver:
         """Initial state from scale-1 grid values of b (float64 device tensor)."""
         t = self._torch
         b = b_grid.to(device=self.device, dtype=t.float64).contiguous()
-        _lib.check(self.lib.stau_initial_state(self._pen, _ptr(b), _ptr(self.X), _stream_ptr()))
+        self._ok(self.lib.stau_initial_state(self._pen, _ptr(b), _ptr(self.X), _stream_ptr()))
         self.reset()
         return self.X
 
@@ -137,7 +142,7 @@ class RBSolver:
     def step(self, dt: float):
         self._st.X = self.X.data_ptr()
         self._st.hist = self.hist.data_ptr()
-        _lib.check(self.lib.stau_step(self._pen, C.byref(self._st), float(dt), _stream_ptr()))
+        self._ok(self.lib.stau_step(self._pen, C.byref(self._st), float(dt), _stream_ptr()))
 
     def step_rk(self, dt: float, scheme: str = "RK222"):
         """One IMEX Runge-Kutta step of the state in place (RK111, RK222 or
@@ -145,7 +150,7 @@ class RBSolver:
         code = _lib.RK_SCHEMES.get(scheme)
         if code is None:
             raise ValueError(f"unknown Runge-Kutta scheme {scheme!r}")
-        _lib.check(self.lib.stau_step_rk(self._pen, code, float(dt), _ptr(self.X), _stream_ptr()))
+        self._ok(self.lib.stau_step_rk(self._pen, code, float(dt), _ptr(self.X), _stream_ptr()))
 
     def lbvp(self, F, out=None):
         """Linear boundary value solve L X = F per pencil (F: complex128 T
@@ -156,7 +161,7 @@ class RBSolver:
         if tuple(F.shape) != tuple(self.ev_shape):
             raise ValueError(f"F must have shape {self.ev_shape}")
         X = out if out is not None else t.empty(self.state_shape, dtype=t.complex128, device=self.device)
-        _lib.check(self.lib.stau_lbvp(self._pen, _ptr(F), _ptr(X), _stream_ptr()))
+        self._ok(self.lib.stau_lbvp(self._pen, _ptr(F), _ptr(X), _stream_ptr()))
         return X
 
     def evp(self, tau: float, nev: int = 1, ncv: int = None, max_ops: int = 2000, tol: float = 1e-10,
@@ -175,13 +180,13 @@ class RBSolver:
         nconv = t.empty(P, dtype=t.int32, device=self.device)
         nops = t.empty(P, dtype=t.int32, device=self.device)
         X = t.empty((nev,) + tuple(self.state_shape), dtype=t.complex128, device=self.device) if vectors else None
-        _lib.check(self.lib.stau_evp(self._pen, float(tau), int(nev), int(ncv), int(max_ops), float(tol),
+        self._ok(self.lib.stau_evp(self._pen, float(tau), int(nev), int(ncv), int(max_ops), float(tol),
                                      _ptr(sigma), _ptr(resid), _ptr(nconv), _ptr(nops),
                                      _ptr(X) if X is not None else None, _stream_ptr()))
         return sigma, resid, nconv, nops, X
 
     def factor(self, a0: float, b0: float = 1.0):
-        _lib.check(self.lib.stau_factor(self._pen, float(a0), float(b0), _stream_ptr()))
+        self._ok(self.lib.stau_factor(self._pen, float(a0), float(b0), _stream_ptr()))
 
     def last_singular_pencil(self) -> int:
         return int(self.lib.stau_last_singular_pencil(self._pen))
@@ -209,7 +214,7 @@ class RBSolver:
         m = self.vars_mask(names)
         Xs = (self.X if X is None else X).contiguous()
         g = t.empty(self.grid_shape(bin(m).count("1"), scale), dtype=t.float64, device=self.device)
-        _lib.check(self.lib.stau_coeff_to_grid(self._pen, _ptr(Xs), m, float(scale), _ptr(g),
+        self._ok(self.lib.stau_coeff_to_grid(self._pen, _ptr(Xs), m, float(scale), _ptr(g),
                                                _stream_ptr()))
         return g
 
@@ -222,7 +227,7 @@ class RBSolver:
         if tuple(g.shape) != self.grid_shape(bin(m).count("1"), scale):
             raise ValueError(f"grid must have shape {self.grid_shape(bin(m).count('1'), scale)}")
         Xo = self.X if X is None else X
-        _lib.check(self.lib.stau_grid_to_coeff(self._pen, _ptr(g), m, float(scale), _ptr(Xo),
+        self._ok(self.lib.stau_grid_to_coeff(self._pen, _ptr(g), m, float(scale), _ptr(Xo),
                                                _stream_ptr()))
         return Xo
 
@@ -232,7 +237,7 @@ class RBSolver:
         g = grid_bar.to(device=self.device, dtype=t.float64).contiguous()
         Xb = X_bar if X_bar is not None else t.zeros(self.state_shape, dtype=t.complex128,
                                                      device=self.device)
-        _lib.check(self.lib.stau_coeff_to_grid_adjoint(self._pen, _ptr(g), m, float(scale), _ptr(Xb),
+        self._ok(self.lib.stau_coeff_to_grid_adjoint(self._pen, _ptr(g), m, float(scale), _ptr(Xb),
                                                        _stream_ptr()))
         return Xb
 
@@ -241,7 +246,7 @@ class RBSolver:
         m = self.vars_mask(names)
         Xb = X_bar.to(device=self.device, dtype=t.complex128).contiguous()
         g = t.empty(self.grid_shape(bin(m).count("1"), scale), dtype=t.float64, device=self.device)
-        _lib.check(self.lib.stau_grid_to_coeff_adjoint(self._pen, _ptr(Xb), m, float(scale), _ptr(g),
+        self._ok(self.lib.stau_grid_to_coeff_adjoint(self._pen, _ptr(Xb), m, float(scale), _ptr(g),
                                                        _stream_ptr()))
         return g
 
@@ -250,25 +255,25 @@ class RBSolver:
         t = self._torch
         Xs = (self.X if X is None else X).contiguous()
         F = t.empty(self.ev_shape, dtype=t.complex128, device=self.device)
-        _lib.check(self.lib.stau_nonlinear(self._pen, _ptr(Xs), _ptr(F), _stream_ptr()))
+        self._ok(self.lib.stau_nonlinear(self._pen, _ptr(Xs), _ptr(F), _stream_ptr()))
         return F
 
     def solve(self, Bev):
         t = self._torch
         B = Bev.to(device=self.device, dtype=t.complex128).contiguous()
         X = t.empty(self.state_shape, dtype=t.complex128, device=self.device)
-        _lib.check(self.lib.stau_solve(self._pen, _ptr(B), _ptr(X), _stream_ptr()))
+        self._ok(self.lib.stau_solve(self._pen, _ptr(B), _ptr(X), _stream_ptr()))
         return X
 
     def set_kernel_timing(self, enable: bool):
-        _lib.check(self.lib.stau_set_kernel_timing(self._pen, 1 if enable else 0))
+        self._ok(self.lib.stau_set_kernel_timing(self._pen, 1 if enable else 0))
 
     def read_kernel_timing(self):
         """{kernel kind: (total ms, launches)} since timing was enabled (synchronises)."""
         n = len(_lib.KERNEL_KINDS)
         ms = (C.c_double * n)()
         cnt = (C.c_int64 * n)()
-        _lib.check(self.lib.stau_read_kernel_timing(self._pen, ms, cnt, n))
+        self._ok(self.lib.stau_read_kernel_timing(self._pen, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KERNEL_KINDS)}
 
     # -- adjoint ------------------------------------------------------------
@@ -293,7 +298,7 @@ class RBSolver:
     def adjoint_step(self, X_prev, iteration: int, dt: float, dt_prev: float, Xbar, hbar):
         """Reverse one forward step in place on (Xbar, hbar)."""
         adj = _lib.AdjStateC(Xbar=Xbar.data_ptr(), hbar=hbar.data_ptr())
-        _lib.check(self.lib.stau_adjoint_step(self._pen, _ptr(X_prev.contiguous()), int(iteration),
+        self._ok(self.lib.stau_adjoint_step(self._pen, _ptr(X_prev.contiguous()), int(iteration),
                                               float(dt), float(dt_prev), C.byref(adj),
                                               _stream_ptr()))
 
@@ -301,7 +306,7 @@ class RBSolver:
         t = self._torch
         Xs = (self.X if X is None else X).contiguous()
         Xbar = t.empty(self.state_shape, dtype=t.complex128, device=self.device)
-        _lib.check(self.lib.stau_kinetic_energy_adjoint(self._pen, _ptr(Xs), _ptr(Xbar),
+        self._ok(self.lib.stau_kinetic_energy_adjoint(self._pen, _ptr(Xs), _ptr(Xbar),
                                                         _stream_ptr()))
         return Xbar
 
@@ -310,13 +315,13 @@ class RBSolver:
         i = self.info
         shape = (i["Nx"], i["Nz"]) if self.dim == 2 else (i["Nx"], i["Ny"], i["Nz"])
         g = t.empty(shape, dtype=t.float64, device=self.device)
-        _lib.check(self.lib.stau_initial_state_adjoint(self._pen, _ptr(Xbar.contiguous()), _ptr(g),
+        self._ok(self.lib.stau_initial_state_adjoint(self._pen, _ptr(Xbar.contiguous()), _ptr(g),
                                                        _stream_ptr()))
         return g
 
     def check(self, X=None):
         Xs = self.X if X is None else X
-        _lib.check(self.lib.stau_check(self._pen, _ptr(Xs), _stream_ptr()))
+        self._ok(self.lib.stau_check(self._pen, _ptr(Xs), _stream_ptr()))
 
     def kinetic_energy_noalloc(self, X=None, out=None):
         """The kinetic energy into a device float64 tensor of one element,
@@ -324,11 +329,11 @@ class RBSolver:
         t = self._torch
         Xs = (self.X if X is None else X).contiguous()
         o = out if out is not None else t.empty(1, dtype=t.float64, device=self.device)
-        _lib.check(self.lib.stau_kinetic_energy_noalloc(self._pen, _ptr(Xs), _ptr(o), _stream_ptr()))
+        self._ok(self.lib.stau_kinetic_energy_noalloc(self._pen, _ptr(Xs), _ptr(o), _stream_ptr()))
         return o
 
     def kinetic_energy(self, X=None) -> float:
         Xs = (self.X if X is None else X).contiguous()
         out = C.c_double()
-        _lib.check(self.lib.stau_kinetic_energy(self._pen, _ptr(Xs), C.byref(out), _stream_ptr()))
+        self._ok(self.lib.stau_kinetic_energy(self._pen, _ptr(Xs), C.byref(out), _stream_ptr()))
         return out.value

@@ -6,6 +6,7 @@ import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libstau.so")
+LIB_CHECK_PATH = os.path.join(_PKG, "libstau_check.so")  # the same ABI with the kernels' index checks
 
 STAU_OK = 0
 STAU_EINVAL = 1
@@ -15,6 +16,7 @@ STAU_ESINGULAR = 4
 STAU_ESTATE = 5
 STAU_EUNSUPPORTED = 6
 STAU_ENONFINITE = 7
+STAU_EBOUNDS = 8
 STAU_FP64 = 0
 STAU_MIXED = 1
 STAU_DCT_AUTO = 0
@@ -29,7 +31,7 @@ STAU_FACTORS_BAND = 1
 RK_SCHEMES = {"RK111": 1, "RK222": 2, "RK443": 3}
 
 ERRNAMES = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ESINGULAR", 5: "ESTATE",
-            6: "EUNSUPPORTED", 7: "ENONFINITE"}
+            6: "EUNSUPPORTED", 7: "ENONFINITE", 8: "EBOUNDS"}
 
 # every exported symbol of include/stau.h
 EXPORTS = (
@@ -81,11 +83,15 @@ class StauError(RuntimeError):
 _lib = None
 
 
+_loaded = {}
+
+
 def load(path: str = LIB_PATH):
-    """Load libstau.so; raises if it has not been built (no fallback)."""
+    """Load libstau.so (or the check build at LIB_CHECK_PATH); raises if it
+    has not been built (no fallback)."""
     global _lib
-    if _lib is not None:
-        return _lib
+    if path in _loaded:
+        return _loaded[path]
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_1905_10388_amd/build.py "
                            "(or __graft_entry__.build())")
@@ -124,11 +130,16 @@ def load(path: str = LIB_PATH):
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    _lib = lib
+    _loaded[path] = lib
+    if path == LIB_PATH:
+        _lib = lib
     return lib
 
 
-def check(rc: int):
+def check(rc: int, lib=None):
+    """Raise StauError for a nonzero status, with the message of the library
+    that returned it (the default one unless lib is given)."""
     if rc != STAU_OK:
-        msg = _lib.stau_last_error().decode() if _lib is not None else ""
+        src = lib if lib is not None else _lib
+        msg = src.stau_last_error().decode() if src is not None else ""
         raise StauError(rc, msg)

@@ -10,6 +10,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libstau.so")
+# the check build: the same sources with the kernels' index checks compiled in
+# (STAU_CHECK_BOUNDS, reported by stau_check)
+LIB_CHECK = os.path.join(PKG, "libstau_check.so")
 SOURCES = ["stau.hip", "k_pencil.hip", "k_factor.hip", "k_evp.hip", "k_transform.hip", "k_xpass.hip",
            "k_adjoint.hip", "k_dctmm.hip", "k_grid.hip"]
 FLAGS = [
@@ -28,14 +31,18 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    objdir = os.path.join(PKG, "_build")
+def build(verbose: bool = False, check: bool = False) -> str:
+    """Compile every source and link libstau.so (check=True: libstau_check.so
+    with the index checks)."""
+    objdir = os.path.join(PKG, "_build_check" if check else "_build")
     os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
+    flags = FLAGS + (["-DSTAU_CHECK_BOUNDS"] if check else [])
+    lib = LIB_CHECK if check else LIB
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [cc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -45,14 +52,14 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [cc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, check="--check" in sys.argv))

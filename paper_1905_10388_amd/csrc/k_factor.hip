@@ -124,6 +124,7 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
       }
     }
     const int d = __builtin_amdgcn_readlane(idx, pl);
+    STAU_BOUND(a.check, d >= 0 && d <= hi && hi < FW, kChkPivot);
     // interchange rows j and j + d in every column
     if (d != 0) {
 #pragma unroll

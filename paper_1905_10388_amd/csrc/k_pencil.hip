@@ -771,6 +771,7 @@ __global__ void __launch_bounds__(kWave) solve_stream_kernel(PencilArgs a, int p
           }
           if constexpr ((t & 3) == 0) word = wcur[(t % SU) >> 2];
           const int s = (word >> (8 * (t & 3))) & 0xff;
+          STAU_BOUND(a.check, s < FW, kChkSlot);
           const T y0 = readlane_t(w0, s), y1 = readlane_t(w1, s);
           put_lane<t>(ya0, y0);
           put_lane<t>(ya1, y1);
@@ -1000,6 +1001,7 @@ __global__ void __launch_bounds__(kWave) sparse_records_kernel(PencilArgs a, con
       cb += __popcll(m);
     }
     if (lane < kSpU) ((uint64_t*)rb)[lane] = mb;
+    STAU_BOUND(a.check, cnt <= capF && cb <= capB, kChkRecord);
     const int bb = 64 + 8 * min(cb, capB);
     if (lane == 0 && (bb & 15)) *(double*)(rb + bb) = 0.0;
     if (lane == 0) lb[u] = (uint8_t)((bb + 15) >> 4);
@@ -1157,12 +1159,21 @@ __global__ void __launch_bounds__(kWave) solve_sparse_kernel(PencilArgs a, int p
             wcur[0] = wnx[0];
             wcur[1] = wnx[1];
             header(r[rs]);
+#ifdef STAU_CHECK_BOUNDS
+            {
+              const int ui = c * UPC + t / SU + 1 < nu ? c * UPC + t / SU + 1 : nu - 1;
+              int cntf = 0;
+              for (int i = 0; i < 4; ++i) cntf += __builtin_popcount(mnx[i]);
+              STAU_BOUND(a.check, 32 + 8 * cntf <= record_bytes(lensF, ui), kChkRank);
+            }
+#endif
             r[rs].store(st + ((t / SU + 1) & 1) * SF, lane);
             load_unit(rs, vk < nu ? vk : nu - 1);
             la = 0;
           }
           if constexpr ((t & 3) == 0) word = wcur[(t % SU) >> 2];
           const int s = (word >> (8 * (t & 3))) & 0xff;
+          STAU_BOUND(a.check, s < FW, kChkSlot);
           const T y0 = readlane_t(w0, s), y1 = readlane_t(w1, s);
           put_lane<t>(ya0, y0);
           put_lane<t>(ya1, y1);
@@ -1266,6 +1277,15 @@ __global__ void __launch_bounds__(kWave) solve_sparse_kernel(PencilArgs a, int p
             const int vk = UPC * (nch - 1 - c) + q / SU + 1 + K;
             constexpr int rs = (q / SU + 1) % K;
             header(r[rs]);
+#ifdef STAU_CHECK_BOUNDS
+            {
+              const int vi = UPC * (nch - 1 - c) + q / SU + 1;
+              const int ui = vi < nu ? nu - 1 - vi : 0;
+              int cntb = 0;
+              for (int i = 0; i < kSpU; ++i) cntb += __builtin_popcountll(mb[i]);
+              STAU_BOUND(a.check, 64 + 8 * cntb <= record_bytes(lensB, ui), kChkRank);
+            }
+#endif
             r[rs].store(st + ((q / SU + 1) & 1) * SB, lane);
             load_unit(rs, vk);
             la = 0;

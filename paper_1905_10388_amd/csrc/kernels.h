@@ -26,6 +26,9 @@ struct PencilArgs {
   double lin;  // PencilCoef::lin of every pencil (0 for the step's operators)
   double refine_a0, refine_b0;  // operator of the refined mixed solve's residual
   double* ysp;  // solve workspace [P][2][nst] for the streamed solve (or null)
+  // index-check word of builds with STAU_CHECK_BOUNDS (bits of the checks
+  // that failed; null in other builds)
+  unsigned int* check;
   // Band templates of the whole operator (row R, column C at R * tw + C - R + tkl):
   // a0 M~ + b0 L~ = a0 T0 + b0 (T1 + k^2 T2 + kx T3 + ky T4 + lin T5), with
   // T1 of the mean pencil (gauge row) in its own plane: planes T0, T1, T1 mean,

@@ -11,6 +11,21 @@
 namespace stau {
 
 constexpr int kWave = 64;
+
+// Index checks of the check build (STAU_CHECK_BOUNDS): a failed check sets
+// its bit in the pencils' check word (read by stau_check); no trap, and
+// nothing at all in other builds.
+enum CheckBits : unsigned { kChkPivot = 1u, kChkRecord = 2u, kChkSlot = 4u, kChkRank = 8u };
+#ifdef STAU_CHECK_BOUNDS
+#define STAU_BOUND(word, cond, bit)              \
+  do {                                           \
+    if (!(cond) && (word)) atomicOr((word), (unsigned)(bit)); \
+  } while (0)
+#else
+#define STAU_BOUND(word, cond, bit) \
+  do {                              \
+  } while (0)
+#endif
 constexpr int kCH = 64;  // sweep chunk: columns per unrolled loop body
 constexpr int kRing = 32;  // look-ahead of the factor loads in the sweeps (columns)
 

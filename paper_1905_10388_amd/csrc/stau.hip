@@ -253,6 +253,7 @@ struct stau_pencils {
   SparseFactors sgeom{};
   int* sing = nullptr;     // device: first singular pencil (INT_MAX if none)
   int* flag = nullptr;     // device: non-finite flag
+  unsigned int* check = nullptr;  // device: index-check word (builds with STAU_CHECK_BOUNDS)
   double* scratch = nullptr;
   int64_t ws_bytes = 0;
   int64_t last_sing = -1;
@@ -487,6 +488,7 @@ static void free_pencils(stau_pencils* p) {
   hipFree(p->evp_V);
   hipFree(p->sing);
   hipFree(p->flag);
+  hipFree(p->check);
   hipFree(p->scratch);
 }
 
@@ -588,6 +590,16 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   const int N = (int)d.Nz;
   PencilArgs& pa = pen->pa;
   build_sysdesc(d.dim, N, pa.desc, pa.var_of_abi);
+  pa.check = nullptr;
+#ifdef STAU_CHECK_BOUNDS
+  if (hipMalloc((void**)&pen->check, sizeof(unsigned)) != hipSuccess ||
+      hipMemset(pen->check, 0, sizeof(unsigned)) != hipSuccess) {
+    hipFree(pen->check);
+    delete pen;
+    return fail(STAU_ENOMEM, "device allocation failed");
+  }
+  pa.check = pen->check;
+#endif
   pen->n = (int64_t)pa.desc.S * N;
   pa.n = (int)pen->n;
   if (par->n_gamma < 0 || par->n_gamma > kMaxNcc) {
@@ -1551,6 +1563,13 @@ int stau_check(stau_pencils* pen, const void* X, void* stream) {
   HIP_TRY(hipMemcpyAsync(&h, pen->flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (h) return fail(STAU_ENONFINITE, "state holds non-finite values");
+#ifdef STAU_CHECK_BOUNDS
+  unsigned bits = 0;
+  HIP_TRY(hipMemcpy(&bits, pen->check, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (bits)
+    return fail(STAU_EBOUNDS, "index check failed since the pencils were built (bits 0x%x: 1 pivot offset, "
+                "2 sparse record size, 4 forward-window slot, 8 record rank)", bits);
+#endif
   return STAU_OK;
 }
 

@@ -55,6 +55,26 @@ def test_structured_rows_templates_and_band_widths(checker):
     assert out.returncode == 0, out.stdout + out.stderr
 
 
+def test_host_code_under_sanitizers(tmp_path):
+    """The host build of the system description, band widths and templates
+    with AddressSanitizer and UndefinedBehaviorSanitizer (host code only:
+    -fno-gpu-sanitize); any report aborts the program."""
+    exe = tmp_path / "templates_check_san"
+    src = os.path.join(ROOT, "tests", "host", "templates_check.cpp")
+    inc = os.path.join(ROOT, "paper_1905_10388_amd", "csrc")
+    r = subprocess.run([HIPCC, "-O1", "-g", "-std=c++17", "-x", "hip", "--offload-arch=gfx950",
+                        "-fsanitize=address", "-fsanitize=undefined", "-fno-gpu-sanitize",
+                        "-fno-sanitize-recover=all", "-I", inc, src, "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1")
+    out = subprocess.run([str(exe)], capture_output=True, text=True, env=env)
+    assert out.returncode == 0, out.stdout + out.stderr[-4000:]
+    out = subprocess.run([str(exe), "dump", "3", "9", "1", "2.0", "1.0", "0.1", "0.2", "1.0", "0", "0", "-1",
+                          "2", "0.5", "0.25", "0", "0"], capture_output=True, text=True, env=env)
+    assert out.returncode == 0, out.stderr[-4000:]
+
+
 def _runtime_matrix(checker, dim, N, mean, a0, b0, par, kx, ky, lin):
     g = list(par.gamma) + [0.0] * (4 - len(par.gamma))
     args = [checker, "dump", dim, N, int(mean), a0, b0, par.kappa, par.nu, par.buoyancy, kx, ky, lin,
