@@ -43,7 +43,9 @@ namespace stau {
 // ---------------------------------------------------------------------------
 // With tailL (two-block solve), the last Q columns' pivot offsets (tailP) and
 // multipliers (tailL, kl per column) are also written in elimination order.
-template <int FW>
+// NR register rows per lane (NR >= kl + 1; the loops over rows run to NR,
+// the forward window of the stored multipliers has FW slots).
+template <int FW, int NR = FW>
 __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, double b0,
                                                        double* __restrict__ Lf,
                                                        uint8_t* __restrict__ sl,
@@ -100,9 +102,10 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
   // c mod RS of this lane's column, slot j mod RS of column j
   const int RS = kv + 1, adv = kWave % RS;
   int cs = lane % RS, js = 0;
-  double av[FW];
+  static_assert(NR <= FW, "register rows within the forward window");
+  double av[NR];
 #pragma unroll
-  for (int i = 0; i < FW; ++i) av[i] = i <= kl ? entry(i, c) : 0.0;
+  for (int i = 0; i < NR; ++i) av[i] = i <= kl ? entry(i, c) : 0.0;
   int ph = lane;  // lane s < FW: the physical slot of forward-window position s
   for (int j = 0; j < n; ++j) {
     const int pl = j & (kWave - 1);
@@ -116,7 +119,7 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     double mag = fabs(av[0]);
     int idx = 0;
 #pragma unroll
-    for (int i = 1; i < FW; ++i) {
+    for (int i = 1; i < NR; ++i) {
       const double m = fabs(av[i]);
       if (i <= hi && m > mag) {
         mag = m;
@@ -124,11 +127,11 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
       }
     }
     const int d = __builtin_amdgcn_readlane(idx, pl);
-    STAU_BOUND(a.check, d >= 0 && d <= hi && hi < FW, kChkPivot);
+    STAU_BOUND(a.check, d >= 0 && d <= hi && hi < NR, kChkPivot);
     // interchange rows j and j + d in every column
     if (d != 0) {
 #pragma unroll
-      for (int i = 1; i < FW; ++i)
+      for (int i = 1; i < NR; ++i)
         if (i == d) {
           const double t = av[0];
           av[0] = av[i];
@@ -142,14 +145,14 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     }
     const double rinv = 1.0 / piv;
     // multipliers of column j, read by every lane (zero beyond row j + hi)
-    double lm[FW];
+    double lm[NR];
     lm[0] = 0.0;
 #pragma unroll
-    for (int i = 1; i < FW; ++i) lm[i] = i <= hi ? readlane_d(av[i], pl) * rinv : 0.0;
+    for (int i = 1; i < NR; ++i) lm[i] = i <= hi ? readlane_d(av[i], pl) * rinv : 0.0;
     // rank-1 update of columns j+1..j+kv
     if (lane != pl && c <= j + kv) {
 #pragma unroll
-      for (int i = 1; i < FW; ++i) av[i] -= lm[i] * av[0];
+      for (int i = 1; i < NR; ++i) av[i] -= lm[i] * av[0];
     }
     // row j of U (columns j..j+kv; the pivot as its reciprocal), then the solve
     // record of column j: lane l carries row r = j - ((j - l) mod BW)
@@ -176,7 +179,7 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     if (lane < FW) {
       double lv = 0.0;
 #pragma unroll
-      for (int i = 1; i < FW; ++i)
+      for (int i = 1; i < NR; ++i)
         if (lane == i) lv = lm[i];
       Lp[(size_t)j * FW + ph] = lv;
     }
@@ -185,7 +188,7 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
       if (lane < kl) {
         double tv = 0.0;
 #pragma unroll
-        for (int i = 1; i < FW; ++i)
+        for (int i = 1; i < NR; ++i)
           if (lane + 1 == i) tv = lm[i];
         tailL[((size_t)p * a.Q + q) * kl + lane] = tv;
       }
@@ -205,8 +208,8 @@ __global__ void __launch_bounds__(kWave) factor_kernel(PencilArgs a, double a0, 
     }
     const double nv = combine(tin, tn);
 #pragma unroll
-    for (int i = 0; i < FW; ++i) {
-      double v = (i + 1 < FW && !fresh) ? av[i + 1] : 0.0;
+    for (int i = 0; i < NR; ++i) {
+      double v = (i + 1 < NR && !fresh) ? av[i + 1] : 0.0;
       if (i >= kl) v = i == kl ? nv : 0.0;
       av[i] = v;
     }
@@ -364,7 +367,10 @@ hipError_t launch_factor(const PencilArgs& a, double a0, double b0, double* Lf, 
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(a.P), dim3(kWave), lds, st, a, a0, b0, Lf, sl, Uf, sing, tailL, tailP);
   };
+  // register rows: the kl + 1 = 11 rows of the 3-D operators instead of the
+  // whole 16-slot window
   if (a.FW == 8) go(factor_kernel<8>);
+  else if (a.FW == 16 && a.kl + 1 <= 11) go(factor_kernel<16, 11>);
   else if (a.FW == 16) go(factor_kernel<16>);
   else if (a.FW == 32) go(factor_kernel<32>);
   else return hipErrorInvalidValue;
