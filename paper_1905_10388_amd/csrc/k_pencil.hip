@@ -926,23 +926,33 @@ __global__ void __launch_bounds__(kWave) solve_stream_kernel(PencilArgs a, int p
 // ---------------------------------------------------------------------------
 constexpr unsigned kBufWord3 = 0x00020000u;  // raw buffer descriptor word 3: 32-bit data format
 
-// Pack the records of every active pencil from the whole-band factors (one
-// wavefront per pencil, units in order).
+// Pack the records of every active pencil from the whole-band factors: a
+// block of kPackWaves wavefronts per pencil, wavefront w packing the units
+// w, w + kPackWaves, ... (each record at its fixed stride), the eight
+// columns' loads of a unit issued together.
+constexpr int kPackWaves = 4;
+
 template <int FW, int BW>
-__global__ void __launch_bounds__(kWave) sparse_records_kernel(PencilArgs a, const double* __restrict__ Lf,
-                                                               const uint8_t* __restrict__ sl,
-                                                               const double* __restrict__ Uf, SparseFactors sf) {
-  __shared__ double col[kWave];
-  const int p = blockIdx.x, lane = threadIdx.x;
+__global__ void __launch_bounds__(kPackWaves * kWave) sparse_records_kernel(PencilArgs a,
+                                                                            const double* __restrict__ Lf,
+                                                                            const uint8_t* __restrict__ sl,
+                                                                            const double* __restrict__ Uf,
+                                                                            SparseFactors sf) {
+  const int p = blockIdx.x, tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int npad = a.nst, nu = npad / kSpU;
   uint8_t* lf = sf.lenF + (size_t)p * kSpLen;
   uint8_t* lb = sf.lenB + (size_t)p * kSpLen;
   if (!pencil_active(a, p)) {
-    for (int u = lane; u < kSpLen; u += kWave) {
+    for (int u = tid; u < kSpLen; u += kPackWaves * kWave) {
       lf[u] = 0;
       lb[u] = 0;
     }
     return;
+  }
+  for (int u = nu + tid; u < kSpLen; u += kPackWaves * kWave) {
+    lf[u] = 0;
+    lb[u] = 0;
   }
   const double* Lp = Lf + (size_t)p * npad * FW;
   const double* Up = Uf + (size_t)p * npad * BW;
@@ -953,15 +963,18 @@ __global__ void __launch_bounds__(kWave) sparse_records_kernel(PencilArgs a, con
   // the strides hold the most entries the band allows (kl multipliers and
   // kl + ku + 1 entries of U per column); nothing is written past them
   const int capF = (sf.strideF - 32) / 8, capB = (sf.strideB - 64) / 8;
-  for (int u = 0; u < nu; ++u) {
+  for (int u = wv; u < nu; u += kPackWaves) {
     // forward record
+    double lv[kSpU];
+#pragma unroll
+    for (int t = 0; t < kSpU; ++t) lv[t] = lane < FW ? Lp[(size_t)(u * kSpU + t) * FW + lane] : 0.0;
     uint8_t* rf = Fp + (size_t)u * sf.strideF;
     double* vf = (double*)(rf + 32);
     int cnt = 0;
     uint32_t mine = 0;  // lane t < kSpU: mask of column t
+#pragma unroll
     for (int t = 0; t < kSpU; ++t) {
-      const int j = u * kSpU + t;
-      const double v = lane < FW ? Lp[(size_t)j * FW + lane] : 0.0;
+      const double v = lv[t];
       const uint64_t m = __ballot(v != 0.0);
       const int idx = cnt + __popcll(m & below);
       if (v != 0.0 && idx < capF) vf[idx] = v;
@@ -978,22 +991,23 @@ __global__ void __launch_bounds__(kWave) sparse_records_kernel(PencilArgs a, con
     if (lane == 0) lf[u] = (uint8_t)((fb + 15) >> 4);
     // backward record: column j of U moved from the BW-row window of the
     // whole-band form (lane l: row j - ((j - l) mod BW)) to lane r mod 64
+    double uv[kSpU];
+#pragma unroll
+    for (int t = 0; t < kSpU; ++t) uv[t] = lane < BW ? Up[(size_t)(u * kSpU + t) * BW + lane] : 0.0;
     uint8_t* rb = Bp + (size_t)u * sf.strideB;
     double* vb = (double*)(rb + 64);
     int cb = 0;
     uint64_t mb = 0;
+#pragma unroll
     for (int q = 0; q < kSpU; ++q) {
       const int t = kSpU - 1 - q, j = u * kSpU + t;
-      col[lane] = 0.0;
-      __syncthreads();
-      if (lane < BW) {
-        int k = (j - lane) % BW;
-        if (k < 0) k += BW;
-        if (k <= j) col[(j - k) & (kWave - 1)] = Up[(size_t)j * BW + lane];
-      }
-      __syncthreads();
-      const double v = col[lane];
-      __syncthreads();
+      // this lane's row r = j - k (k = (j - lane) mod 64) sits in the band
+      // form's lane r mod BW when k < BW and r >= 0
+      const int k = (j - lane) & (kWave - 1);
+      int src = (j - k) % BW;
+      if (src < 0) src += BW;
+      const double g = __shfl(uv[t], src);
+      const double v = (k < BW && k <= j) ? g : 0.0;
       const uint64_t m = __ballot(v != 0.0);
       const int idx = cb + __popcll(m & below);
       if (v != 0.0 && idx < capB) vb[idx] = v;
@@ -1005,10 +1019,6 @@ __global__ void __launch_bounds__(kWave) sparse_records_kernel(PencilArgs a, con
     const int bb = 64 + 8 * min(cb, capB);
     if (lane == 0 && (bb & 15)) *(double*)(rb + bb) = 0.0;
     if (lane == 0) lb[u] = (uint8_t)((bb + 15) >> 4);
-  }
-  for (int u = nu + lane; u < kSpLen; u += kWave) {
-    lf[u] = 0;
-    lb[u] = 0;
   }
 }
 
@@ -2102,7 +2112,7 @@ hipError_t launch_sparse_records(const PencilArgs& a, const double* Lf, const ui
                                  const SparseFactors& sf, hipStream_t st) {
 #define STAU_CASE(F, B)                                                                               \
   if (a.FW == F && a.BW == B) {                                                                       \
-    hipLaunchKernelGGL((sparse_records_kernel<F, B>), dim3(a.P), dim3(kWave), 0, st, a, Lf, sl, Uf, sf); \
+    hipLaunchKernelGGL((sparse_records_kernel<F, B>), dim3(a.P), dim3(kPackWaves * kWave), 0, st, a, Lf, sl, Uf, sf); \
     return hipGetLastError();                                                                         \
   }
   STAU_SWEEP_VARIANTS(STAU_CASE)
