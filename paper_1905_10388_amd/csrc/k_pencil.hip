@@ -2090,7 +2090,9 @@ hipError_t launch_solve(const PencilArgs& a, const void* Bev, const double* Lf, 
 
 // Sparse records where the streamed solve runs: the single-block FP64 solve
 // with more than 32 pencils per compute unit, forward windows of at most 16
-// rows, at most kSpLen units and backward records of at most three KiB.
+// rows, at most kSpLen units and backward records of at most three KiB.  (At
+// 4096 x 64, eight pencils per unit, the streamed solve on records took
+// 110 us against the LDS-resident pair solve's 93 us on the whole band.)
 bool sparse_records_apply(const PencilArgs& a, SparseFactors* geom) {
   const int nu = a.nst / kSpU, kv = a.kl + a.ku;
   const int sf = (32 + 64 * a.kl + 15) / 16 * 16, sb = (64 + 64 * (kv + 1) + 15) / 16 * 16;
