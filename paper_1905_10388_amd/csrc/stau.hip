@@ -907,17 +907,28 @@ static int factor_into(stau_pencils* pen, stau_pencils::FactorSlot* set, const P
       }
       if (e == hipSuccess && pen->sparse_ok && set == pen->slot) {
         if (!f.sf.F) {
+          // the records are an optimisation: if they cannot be allocated the
+          // pencils keep solving on the whole band
           SparseFactors g = pen->sgeom;
           const size_t units = (size_t)pa.P * (pa.nst / kSpU), lens = (size_t)pa.P * kSpLen;
-          e = hipMalloc((void**)&g.F, units * g.strideF);
-          if (e == hipSuccess) e = hipMalloc((void**)&g.B, units * g.strideB);
-          if (e == hipSuccess) e = hipMalloc((void**)&g.lenF, lens);
-          if (e == hipSuccess) e = hipMalloc((void**)&g.lenB, lens);
-          f.sf = g;  // (freed with the slot, also after a failed allocation)
-          if (e == hipSuccess) pen->ws_bytes += (int64_t)(units * (g.strideF + g.strideB) + 2 * lens);
+          hipError_t ea = hipMalloc((void**)&g.F, units * g.strideF);
+          if (ea == hipSuccess) ea = hipMalloc((void**)&g.B, units * g.strideB);
+          if (ea == hipSuccess) ea = hipMalloc((void**)&g.lenF, lens);
+          if (ea == hipSuccess) ea = hipMalloc((void**)&g.lenB, lens);
+          if (ea == hipSuccess) {
+            f.sf = g;
+            pen->ws_bytes += (int64_t)(units * (g.strideF + g.strideB) + 2 * lens);
+          } else {
+            for (void* q : {(void*)g.F, (void*)g.B, (void*)g.lenF, (void*)g.lenB}) (void)hipFree(q);
+            (void)hipGetLastError();  // clear the failed allocation's error
+            pen->sparse_ok = false;
+            for (auto& o : pen->slot) o.sparse = false;
+          }
         }
-        if (e == hipSuccess) e = launch_sparse_records(pa, f.Lf, f.sl, f.Uf, f.sf, st);
-        f.sparse = e == hipSuccess;
+        if (pen->sparse_ok) {
+          e = launch_sparse_records(pa, f.Lf, f.sl, f.Uf, f.sf, st);
+          f.sparse = e == hipSuccess;
+        }
       }
       return e;
     }
