@@ -90,10 +90,11 @@ def algorithmic_bytes(info, dim):
     """Minimum HBM bytes per launch of each kernel (FP64 complex = 16 B): every
     input read once, every output written once.
       z backward: the state fields the explicit term needs (2-D b, u, w, bz,
-        uz, wz; 3-D also v, vz) read, their transforms (6; 3-D 12 with the y
-        derivatives of b, u, v, w; x derivatives are formed in the x pass) of
-        M points written per pencil slot;
-      y passes (3-D): backward, 12 fields of Ny rows read and Ngy written per
+        uz, wz; 3-D also v, vz) read, their transforms (6; 3-D 8) of M points
+        written per pencil slot (the x derivatives are formed in the x pass,
+        the y derivatives in the backward y pass);
+      y passes (3-D): backward, the 8 z-transformed fields of Ny rows read
+        and 12 written on Ngy rows (with the y derivatives of b, u, v, w) per
         (z level, kx); forward, 4 fields of Ngy read and Ny written;
       x pass: the transformed fields read on the active kx, 3 (3-D: 4) written;
       z forward + RHS: the explicit term read, the previous state's evolved
@@ -108,14 +109,15 @@ def algorithmic_bytes(info, dim):
     n, kl, ku = info["n"], info["kl"], info["ku"]
     Px, Ny, Ngy = info["Px"], info["Ny"], info["Ngy"]
     c16 = 16
-    nin, nf = (6, 6) if dim == 2 else (8, 12)
-    zb = nin * P * N * c16 + nf * M * P * c16
+    # state fields read, z-transformed fields, fields of the x pass
+    nin, nz, nf = (6, 6, 6) if dim == 2 else (8, 8, 12)
+    zb = nin * P * N * c16 + nz * M * P * c16
     if dim == 2:
         xp = nf * M * (Px - 1) * c16 + ne * M * Px * c16
         yp = 0
     else:
         xp = nf * M * Ngy * (Px - 1) * c16 + ne * M * Ngy * Px * c16
-        yp = (nf * M * Ny * Px + nf * M * Ngy * Px) * c16 + (ne * M * Ngy * Px + ne * M * Ny * Px) * c16
+        yp = (nz * M * Ny * Px + nf * M * Ngy * Px) * c16 + (ne * M * Ngy * Px + ne * M * Ny * Px) * c16
     zf = ne * M * P * c16 + ne * P * N * c16 + 2 * (2 * ne * P * N * c16) + ne * P * N * c16
     solve = Pa * n * ((2 * kl + ku + 1) * 8 + 1) + Pa * ne * N * c16 + P * S * N * c16
     out = {"z_backward": zb, "x_pass": xp, "z_forward_rhs": zf, "pencil_solve": solve}

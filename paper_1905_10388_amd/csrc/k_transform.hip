@@ -266,11 +266,13 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
 // other's).
 // NGC > 0: Ngy = NGC fixed at compile time, TK = PB / NGC (PB points per
 // block, PB / 256 per thread).
+// ym (backward pass): output field f from input field ym.src[f], times i ky
+// where ym.der[f] (y derivatives formed here, after the z transform).
 template <int DIR, int MAXBF, typename T, int NGC = 0, int PB = 3072>
 __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
                                                     const typename V2<T>::type* __restrict__ In,
                                                     typename V2<T>::type* __restrict__ Out, int TKr,
-                                                    double ys) {
+                                                    double ys, YMap ym) {
   extern __shared__ double2 smem[];
   using cT = cpx<T>;
   cT* buf = (cT*)smem;
@@ -295,7 +297,9 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
   const int Ny = a.Ny, Ng = NGC > 0 ? NGC : a.Ngy, Px = a.Px, M = a.M, half = Ny / 2;
   const int tid = threadIdx.x, nt = blockDim.x;
   const size_t inRows = DIR > 0 ? Ny : Ng, outRows = DIR > 0 ? Ng : Ny;
-  const typename V2<T>::type* src = In + ((size_t)f * M + jz) * inRows * Px;
+  const int fin = ym.n ? ym.src[f] : f;
+  const bool dy = DIR > 0 && ym.n && ym.der[f];
+  const typename V2<T>::type* src = In + ((size_t)fin * M + jz) * inRows * Px;
   typename V2<T>::type* dst = Out + ((size_t)f * M + jz) * outRows * Px;
   // padded position -> stored slot (-1: padding or Nyquist)
   auto slot_of = [&](int pos) -> int {
@@ -310,7 +314,13 @@ __global__ void __launch_bounds__(256) ypass_kernel(XformArgs a,
     if (kx < Px) {
       if (DIR > 0) {
         const int iy = slot_of(pos);
-        if (iy >= 0) v = ldv<T>(src + (size_t)iy * Px + kx);
+        if (iy >= 0) {
+          v = ldv<T>(src + (size_t)iy * Px + kx);
+          if (dy) {  // i ky v
+            const T ky = (T)(a.two_pi_over_Ly * (double)(iy < half ? iy : iy - Ny));
+            v = mk<T>(-ky * v.y, ky * v.x);
+          }
+        }
       } else {
         v = ldv<T>(src + (size_t)pos * Px + kx);
       }
@@ -608,7 +618,9 @@ hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs
 
 
 hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, void* Out,
-                        hipStream_t st, bool fp32, double ys) {
+                        hipStream_t st, bool fp32, double ys, const YMap* map) {
+  YMap ym{};
+  if (map) ym = *map;
   // Ny = 256 (384 padded points) with the length fixed at compile time; FP64
   // tiles of 4 kx (1536 points, 24 KB of LDS: six blocks per compute unit
   // instead of three with tiles of 8)
@@ -618,7 +630,7 @@ hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, voi
   dim3 grid((a.Px + TK - 1) / TK, a.M, nf);
   const size_t lds = (size_t)TK * a.Ngy * (fp32 ? sizeof(float2) : sizeof(double2));
   auto go = [&](auto kern, auto in, auto out) {
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a, in, out, TK, ys);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a, in, out, TK, ys, ym);
   };
   auto pick = [&](auto tc) {
     using TT = typename decltype(tc)::type;

@@ -167,8 +167,15 @@ hipError_t launch_solve2_refined(const PencilArgs& t, const PencilArgs& bt, cons
 
 // transforms along y and the 3-D x pass
 // ys: output scale in place of the default (0: 1 backward, 1 / Ngy forward)
+// Output fields of the backward y pass from input fields: output f reads
+// input src[f], times i ky where der[f] (n = 0: output f reads input f)
+struct YMap {
+  int n;
+  int src[12];
+  int der[12];
+};
 hipError_t launch_ypass(const XformArgs& a, int dir, int nf, const void* In, void* Out,
-                        hipStream_t st, bool fp32 = false, double ys = 0.0);
+                        hipStream_t st, bool fp32 = false, double ys = 0.0, const YMap* map = nullptr);
 hipError_t launch_xpass3(const XformArgs& a, const void* G2, void* H2, hipStream_t st,
                          bool fp32 = false);
 

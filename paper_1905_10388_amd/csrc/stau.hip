@@ -177,7 +177,8 @@ struct stau_pencils {
   PencilArgs pa{};
   XformArgs xa{};   // dealiased transforms
   XformArgs xa1{};  // scale-1 transforms
-  FieldList fl{};      // the explicit term's fields of the step
+  FieldList fl{};      // the explicit term's fields of the step (z transforms)
+  YMap ymap{};         // 3-D: the x pass's 12 fields from the backward y pass
   FieldList fl_adj{};  // the adjoint x pass's fields (2-D)
   AccList acc{};
   int64_t n = 0;
@@ -764,13 +765,23 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
       fl.var[i] = fv[i];
       fl.deriv[i] = 0;
     }
-  } else {  // u, v, w, b, b_y, bz, u_y, uz, v_y, vz, w_y, wz (ABI order p,b,u,v,w,bz,uz,vz,wz)
-    const int fv[12] = {2, 3, 4, 1, 1, 5, 2, 6, 3, 7, 4, 8};
-    const int fd[12] = {0, 0, 0, 0, 2, 0, 2, 0, 2, 0, 2, 0};
-    fl.nf = 12;
-    for (int i = 0; i < 12; ++i) {
+  } else {
+    // z transforms of u, v, w, b, bz, uz, vz, wz (ABI order p,b,u,v,w,bz,uz,vz,wz);
+    // the backward y pass forms the y derivatives (i ky times the column) and
+    // hands the x pass u, v, w, b, b_y, bz, u_y, uz, v_y, vz, w_y, wz
+    const int fv[8] = {2, 3, 4, 1, 5, 6, 7, 8};
+    fl.nf = 8;
+    for (int i = 0; i < 8; ++i) {
       fl.var[i] = fv[i];
-      fl.deriv[i] = fd[i];
+      fl.deriv[i] = 0;
+    }
+    const int ys[12] = {0, 1, 2, 3, 3, 4, 0, 5, 1, 6, 2, 7};
+    const int yd[12] = {0, 0, 0, 0, 1, 0, 1, 0, 1, 0, 1, 0};
+    YMap& ym = pen->ymap;
+    ym.n = 12;
+    for (int i = 0; i < 12; ++i) {
+      ym.src[i] = ys[i];
+      ym.der[i] = yd[i];
     }
   }
   // the adjoint x pass recomputes the eight 2-D grid fields with their x
@@ -804,11 +815,14 @@ int stau_build_pencils(stau_domain* dom, const stau_rb_params* par, stau_pencils
   }
 
   const size_t P = dom->P, M = dom->Ngz, ne = pa.desc.ne, n = pen->n;
-  const size_t szG = (size_t)(fl.nf > pen->fl_adj.nf ? fl.nf : pen->fl_adj.nf) * M * P * sizeof(double2);
+  // G holds the z-transformed fields (at most 12: also the grid transforms'
+  // nine variables and the adjoint's fields), G2 the 12 fields of the 3-D y pass
+  const int nfg = d.dim == 3 ? 12 : (fl.nf > pen->fl_adj.nf ? fl.nf : pen->fl_adj.nf);
+  const size_t szG = (size_t)nfg * M * P * sizeof(double2);
   const size_t szH = ne * M * P * sizeof(double2);
   const size_t szB = P * ne * N * sizeof(double2);
   const size_t Ngy = (size_t)dom->Ngy, Px = (size_t)dom->Px;
-  const size_t szG2 = d.dim == 3 ? (size_t)fl.nf * M * Ngy * Px * sizeof(double2) : 0;
+  const size_t szG2 = d.dim == 3 ? (size_t)12 * M * Ngy * Px * sizeof(double2) : 0;
   const size_t szGb = d.dim == 2 ? szG : 0;  // the adjoint is built for 2-D
   const size_t szScratch = (size_t)(3 * N * P + 4 * M * Ngy + 64) * sizeof(double2);
   hipError_t e = hipSuccess;
@@ -1042,7 +1056,7 @@ static hipError_t explicit_term(stau_pencils* pen, const void* X, hipStream_t st
   if (pen->dom->d.dim == 2)
     return timed(pen, K_XPASS, st, [&] { return launch_xpass(pen->xa, pen->G, pen->H, st, mixed); });
   e = timed(pen, K_YPASS, st,
-            [&] { return launch_ypass(pen->xa, +1, pen->fl.nf, pen->G, pen->G2, st, mixed); });
+            [&] { return launch_ypass(pen->xa, +1, pen->ymap.n, pen->G, pen->G2, st, mixed, 0.0, &pen->ymap); });
   if (e != hipSuccess) return e;
   e = timed(pen, K_XPASS, st, [&] { return launch_xpass3(pen->xa, pen->G2, pen->G, st, mixed); });
   if (e != hipSuccess) return e;
