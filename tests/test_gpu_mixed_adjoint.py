@@ -1,7 +1,9 @@
 """Mixed-precision discrete adjoint (FP32 adjoint transforms and products,
-FP64 transposed solve) against the oracle's FP64 discrete adjoint, and at the
-4096x64 workload against the GPU's FP64 gradient (itself checked against the
-oracle and finite differences in test_gpu_adjoint.py).
+FP64 transposed solve) against the oracle's FP64 discrete adjoint (one step
+at three sizes, a 12-step gradient, and a three-step gradient at the 4096x64
+workload), and over 100 steps at 4096x64 against the GPU's FP64 gradient
+(itself checked against the oracle and finite differences in
+test_gpu_adjoint.py).
 
 Stated bounds: relative L2 error at most 1e-5 for one adjoint step and for
 the 12-step gradient against the oracle; at most 5e-5 for the gradient over
@@ -97,6 +99,29 @@ def test_mixed_gradient_matches_oracle_small():
     print("mixed gradient error (32x16, 12 steps)", f"J {abs(Jg - Jo) / abs(Jo):.2e}", f"grad {err:.2e}")
     assert abs(Jg - Jo) <= MIXED_BOUND * abs(Jo)
     assert err < MIXED_BOUND
+
+
+def test_mixed_gradient_small_nz_workload_against_oracle():
+    """4096x64, Lx=16, Ra=1e7, Pr=7, dt=2e-5 from the workload's seeded state:
+    the mixed gradient of the kinetic energy after three steps (SBDF1 and two
+    SBDF2 steps, checkpoints every two) against the oracle's FP64 discrete
+    adjoint, within the mixed bound.  (The oracle takes about two minutes
+    here: dense transform matrices of 6144 x 2049.)"""
+    Nx, Nz, Lx, Ra, Pr, dt, steps = 4096, 64, 16.0, 1e7, 7.0, 2e-5, 3
+    j = np.arange(Nz)
+    z = 0.5 * (1 - np.cos(np.pi * (j + 0.5) / Nz))
+    xi = si.workload_noise((Nx, Nz), 4)
+    b0 = (1 - z)[None, :] + 1e-3 * (z * (1 - z))[None, :] * xi
+    g = RBSolver(Nx, Nz, Lx, Ra, Pr, precision="mixed")
+    Jg, gg = kinetic_energy_and_gradient(g, torch.from_numpy(b0).cuda(), dt, steps, checkpoint=2)
+    gg = _np(gg)
+    g.close()
+    o = RBOracle(Nx, Nz, Lx, RBParams(Ra, Pr))
+    Jo, go = ADJ.gradient(o, b0, dt, steps)
+    eJ, eg = abs(Jg - Jo) / abs(Jo), rel_err(gg, go)
+    print("mixed gradient vs oracle (4096x64, 3 steps)", f"J {eJ:.2e}", f"grad {eg:.2e}")
+    assert eJ < MIXED_BOUND
+    assert eg < MIXED_BOUND
 
 
 def test_mixed_gradient_small_nz_workload_against_fp64():
