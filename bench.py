@@ -550,7 +550,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); "
+        print("bench.py: the stau library runs on exactly one GPU (it has no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.probe:
