@@ -136,6 +136,32 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
       }
   }
   stage_z_tables<T>(a, twl, dcl, M, tid);
+  // epilogue in groups of four points per thread: a group's state and
+  // history loads are issued together
+  constexpr int GE = 4;
+  static_assert(MAXIT % GE == 0, "epilogue groups");
+  auto load_group = [&](int g0, double2* x0, double2* x2, double2* fo, double2* mo, RkRow* rv) {
+#pragma unroll
+    for (int u = 0; u < GE; ++u) {
+      const int idx = tid + (g0 + u) * nt;
+      x0[u] = x2[u] = fo[u] = mo[u] = make_double2(0.0, 0.0);
+      if (r.mode >= 1 && idx < TP * N) {
+        const int s = idx / N, nn = idx - s * N;
+        const int p = p0 + s;
+        if (active_at(a, pb, s) && nn <= N - 2) {
+          const double2* xc = r.Xprev + ((size_t)p * a.S + (e + 1)) * N;
+          x0[u] = xc[nn];
+          if (nn + 2 < N) x2[u] = xc[nn + 2];
+          if constexpr (RK) rk_load(r.rk, ((size_t)p * ne + e) * N + nn, rv[u]);
+          if (r.mode == 1 && r.has_hist) {
+            const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
+            fo[u] = r.hist_old[ho];
+            mo[u] = r.hist_old[ho + (size_t)ne * N];
+          }
+        }
+      }
+    }
+  };
   {
     cT hv[EPT];
 #pragma unroll
@@ -183,33 +209,11 @@ __global__ void __launch_bounds__(kZThreads) zf_kernel(XformArgs a,
     }
   }
   __syncthreads();
-  // epilogue in groups of four points per thread: the group's loads first
-  constexpr int GE = 4;
-  static_assert(MAXIT % GE == 0, "epilogue groups");
 #pragma unroll
   for (int g0 = 0; g0 < MAXIT; g0 += GE) {
     double2 x0[GE], x2[GE], fo[GE], mo[GE];
     RkRow rv[RK ? GE : 1];
-#pragma unroll
-    for (int u = 0; u < GE; ++u) {
-      const int idx = tid + (g0 + u) * nt;
-      x0[u] = x2[u] = fo[u] = mo[u] = make_double2(0.0, 0.0);
-      if (r.mode >= 1 && idx < TP * N) {
-        const int s = idx / N, nn = idx - s * N;
-        const int p = p0 + s;
-        if (active_at(a, pb, s) && nn <= N - 2) {
-          const double2* xc = r.Xprev + ((size_t)p * a.S + (e + 1)) * N;
-          x0[u] = xc[nn];
-          if (nn + 2 < N) x2[u] = xc[nn + 2];
-          if constexpr (RK) rk_load(r.rk, ((size_t)p * ne + e) * N + nn, rv[u]);
-          if (r.mode == 1 && r.has_hist) {
-            const size_t ho = (((size_t)p * 2) * ne + e) * N + nn;
-            fo[u] = r.hist_old[ho];
-            mo[u] = r.hist_old[ho + (size_t)ne * N];
-          }
-        }
-      }
-    }
+    load_group(g0, x0, x2, fo, mo, rv);
 #pragma unroll
     for (int u = 0; u < GE; ++u) {
       const int idx = tid + (g0 + u) * nt;
@@ -586,21 +590,24 @@ hipError_t launch_zf(const XformArgs& a, const void* H, void* out, const RhsArgs
   };
   const float2* h32 = (const float2*)H;
   const double2* h64 = (const double2*)H;
-  // the workloads' (M, N) = (96, 64), (192, 128), (384, 256) fixed at compile time
+  // the workloads' (M, N) = (96, 64), (192, 128), (384, 256) fixed at compile
+  // time, with the epilogue's points per thread (TP N / threads: 8 for full
+  // tiles at M = 3N/2, 4 for half tiles); other lengths (the scale-1
+  // transforms, M = N) up to 12 and 8
   auto pick = [&](auto tc, auto rk, auto h) {
     using TT = typename decltype(tc)::type;
     constexpr bool RKv = decltype(rk)::value;
     if (a.M == 192 && a.N == 128) {
-      if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2, 192, 128>, h);
-      else go(zf_kernel<3, 12, TT, RKv, kZEpt, 192, 128>, h);
+      if (dv == 2) go(zf_kernel<3, 4, TT, RKv, kZEpt / 2, 192, 128>, h);
+      else go(zf_kernel<3, 8, TT, RKv, kZEpt, 192, 128>, h);
     } else if (a.M == 384 && a.N == 256) {
-      if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2, 384, 256>, h);
-      else go(zf_kernel<3, 12, TT, RKv, kZEpt, 384, 256>, h);
+      if (dv == 2) go(zf_kernel<3, 4, TT, RKv, kZEpt / 2, 384, 256>, h);
+      else go(zf_kernel<3, 8, TT, RKv, kZEpt, 384, 256>, h);
     } else if (a.M == 96 && a.N == 64) {
-      if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2, 96, 64>, h);
-      else go(zf_kernel<3, 12, TT, RKv, kZEpt, 96, 64>, h);
+      if (dv == 2) go(zf_kernel<3, 4, TT, RKv, kZEpt / 2, 96, 64>, h);
+      else go(zf_kernel<3, 8, TT, RKv, kZEpt, 96, 64>, h);
     } else {
-      if (dv == 2) go(zf_kernel<3, 12, TT, RKv, kZEpt / 2>, h);
+      if (dv == 2) go(zf_kernel<3, 8, TT, RKv, kZEpt / 2>, h);
       else go(zf_kernel<3, 12, TT, RKv>, h);
     }
   };
@@ -680,7 +687,8 @@ hipError_t launch_initial_state(const XformArgs& a1, const double* bgrid, void* 
   az.ne = 1;
   RhsArgs r{};
   r.mode = 0;
-  launch_zf(az, Hz, C, r, st);
+  hipError_t e = launch_zf(az, Hz, C, r, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ic_fill_kernel, dim3(a1.P), dim3(256), 0, st, a1, (const double2*)C,
                      (double2*)X, 1, a1.dim == 2 ? 4 : 5);
   return hipGetLastError();
@@ -718,7 +726,8 @@ hipError_t launch_ke(const XformArgs& a, const void* X, void* G, void* G2, doubl
                      a.dim == 2 ? 1 : a.Ngy);
   RhsArgs r{};
   r.mode = 0;
-  launch_zf(az, H, C, r, st);
+  hipError_t e = launch_zf(az, H, C, r, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ke_sum_kernel, dim3(1), dim3(256), 0, st, (const double2*)C, a.N, out);
   return hipGetLastError();
 }
