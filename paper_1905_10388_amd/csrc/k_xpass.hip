@@ -348,9 +348,12 @@ __global__ void __launch_bounds__(NT) xrow2_kernel(XformArgs a,
 // quarter of the radix passes and barriers, with twice the threads per row.
 // Batch A holds (u, v), (w, b_x), (b_y, bz), (u_x, u_y): N_b completes and
 // N_u starts; batch B holds (uz, v_x), (v_y, vz), (w_x, w_y), (wz, -): N_u,
-// N_v and N_w complete.  Data [4][L] and twiddles [L] in LDS; the spectra of
-// batch B are loaded while batch A is transformed.  Same products and
-// outputs as xrow_kernel<3>.
+// N_v and N_w complete.  Data [4][L] and twiddles [L] in LDS.  The lower
+// half of the threads loads the spectra of batch A and the upper half those
+// of batch B, both at the start (one entry per thread and sequence: the
+// launch has Pa <= NT / 2); each batch goes onto LDS from its own half while
+// the other half writes the zero padding.  Same products and outputs as
+// xrow_kernel<3>.
 // ---------------------------------------------------------------------------
 template <int NT, int PTS, int MAXBF, typename T, int LC>
 __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
@@ -359,12 +362,13 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
   extern __shared__ double2 smem[];
   using cT = cpx<T>;
   using S2 = typename V2<T>::type;
-  constexpr int KPT = (PTS + 2) / 3;  // half-spectrum entries per thread (Pa = L / 3)
+  constexpr int HT = NT / 2;          // threads per batch (whole wavefronts)
   cT* buf = (cT*)smem;                // four sequences of L points
   const int r = blockIdx.x;
   const int L = LC > 0 ? LC : a.L, Pa = a.Pa, Px = a.Px;
   const size_t R = (size_t)a.M * a.Ngy;
   const int tid = threadIdx.x;
+  const int upper = tid >= HT, j = tid - upper * HT;
   const cT* twg = (const cT*)(sizeof(T) == 8 ? (const void*)a.twx : (const void*)a.twx32);
   // the twiddles the passes read: indices below L / R of the smallest radix
   // (the compile-time 384-point plan is 6 x 8 x 8: the first 64 entries)
@@ -372,53 +376,55 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
   const int tn = TWC > 0 ? TWC : L;
   cT* twl = buf + 4 * L;
   for (int i = tid; i < tn; i += NT) twl[i] = twg[i];
-  cT sa[4][KPT], sb[4][KPT];
+  cT sa[4], sb[4];
   auto fetch = [&](int slot, int k) {
     int fa, da, fb, db;
     pair_src<3>(k, fa, da, fb, db);
     const S2* A = G + ((size_t)fa * R + r) * Px;
     const S2* B = G + ((size_t)(fb < 0 ? fa : fb) * R + r) * Px;
-#pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-      const int kk = tid + q * NT;
-      sa[slot][q] = mk<T>(0, 0);
-      sb[slot][q] = mk<T>(0, 0);
-      if (kk < Pa) {
-        sa[slot][q] = ldv<T>(A + kk);
-        if (da) sa[slot][q] = ikx<T>(a, kk, sa[slot][q]);
-        if (fb >= 0) {
-          sb[slot][q] = ldv<T>(B + kk);
-          if (db) sb[slot][q] = ikx<T>(a, kk, sb[slot][q]);
-        }
+    sa[slot] = mk<T>(0, 0);
+    sb[slot] = mk<T>(0, 0);
+    if (j < Pa) {
+      sa[slot] = ldv<T>(A + j);
+      if (da) sa[slot] = ikx<T>(a, j, sa[slot]);
+      if (fb >= 0) {
+        sb[slot] = ldv<T>(B + j);
+        if (db) sb[slot] = ikx<T>(a, j, sb[slot]);
       }
     }
   };
-  // Hermitian extension of the packed pair A + i B onto sequence `slot`
-  auto scatter = [&](int slot) {
-    cT* bb = buf + slot * L;
+  // Hermitian extension of the packed pairs A + i B onto the four sequences
+  // (the half holding the batch), or the zero padding between the two ends
+  // of the spectrum (the other half)
+  auto scatter = [&](bool mine) {
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-      const int kk = tid + q * NT;
-      if (kk < Pa) {
-        cT Ak = sa[slot][q], Bk = sb[slot][q];
-        if (kk == 0) {
-          Ak.y = 0;
-          Bk.y = 0;
+    for (int slot = 0; slot < 4; ++slot) {
+      cT* bb = buf + slot * L;
+      if (mine) {
+        if (j < Pa) {
+          cT Ak = sa[slot], Bk = sb[slot];
+          if (j == 0) {
+            Ak.y = 0;
+            Bk.y = 0;
+          }
+          bb[j] = mk<T>(Ak.x - Bk.y, Ak.y + Bk.x);
+          if (j > 0) bb[L - j] = mk<T>(Ak.x + Bk.y, -Ak.y + Bk.x);
         }
-        bb[kk] = mk<T>(Ak.x - Bk.y, Ak.y + Bk.x);
-        if (kk > 0) bb[L - kk] = mk<T>(Ak.x + Bk.y, -Ak.y + Bk.x);
+      } else {
+        for (int k = Pa + j; k <= L - Pa; k += HT) bb[k] = mk<T>(0, 0);
       }
     }
-    for (int k = Pa + tid; k <= L - Pa; k += NT) bb[k] = mk<T>(0, 0);
   };
 
   T u[PTS], v[PTS], w[PTS], nb[PTS], nu[PTS], nv[PTS], nw[PTS];
+  if (!upper) {
 #pragma unroll
-  for (int s = 0; s < 4; ++s) fetch(s, s);
+    for (int s = 0; s < 4; ++s) fetch(s, s);
+  } else {
 #pragma unroll
-  for (int s = 0; s < 4; ++s) scatter(s);
-#pragma unroll
-  for (int s = 0; s < 4; ++s) fetch(s, 4 + s);
+    for (int s = 0; s < 4; ++s) fetch(s, 4 + s);
+  }
+  scatter(!upper);
   __syncthreads();
   fft_lds_c<LC, +1, MAXBF, T, true, true>(buf, L, 4, twl, tid, NT);
 #pragma unroll
@@ -434,8 +440,7 @@ __global__ void __launch_bounds__(NT) xrow3_kernel(XformArgs a,
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int s = 0; s < 4; ++s) scatter(s);
+  scatter(upper);
   __syncthreads();
   fft_lds_c<LC, +1, MAXBF, T, true, true>(buf, L, 4, twl, tid, NT);
 #pragma unroll
@@ -513,7 +518,7 @@ static hipError_t launch_xrow_t(const XformArgs& a, const void* G, void* H, hipS
     constexpr int PTS3 = (PTS + 1) / 2;
     const bool c384 = a.L == 384 && 2 * NT * PTS3 >= 384;
     const size_t lds3 = ((size_t)4 * a.L + (c384 ? 64 : a.L)) * sizeof(S2);
-    if (lds3 <= 64 * 1024 && a.L <= 2 * NT * PTS3) {
+    if (lds3 <= 64 * 1024 && a.L <= 2 * NT * PTS3 && a.Pa <= NT) {
       // the 256 x 256 workload's 384-point rows with their length fixed
       // (and 64 twiddles in LDS: 25 KB per block, six blocks per unit)
       auto fn = c384 ? xrow3_kernel<2 * NT, PTS3, 2 * MAXBF, T, 384>
